@@ -1,0 +1,151 @@
+"""FP64 CPU oracle for the FRG flow-diagram quadrature (test infrastructure).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It loads ``liboracle.so`` built from
+``frg_oracle.c`` (plain C, no code shared with the HIP library) and exposes
+numpy-facing wrappers.  Every function states the definition it follows; the
+definitions themselves are written out in the header comment of
+``frg_oracle.c``.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "frg_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+REG_EXP = 0
+REG_LITIM = 1
+OK, E_INVAL, E_DOMAIN = 0, -1, -2
+
+
+def build(force: bool = True) -> str:
+    """Compile ``liboracle.so`` with gcc, strict IEEE (no fast-math, no contraction)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-std=c11",
+               "-D_GNU_SOURCE", "-shared", "-fPIC", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.oracle_gauss_legendre.argtypes = [ctypes.c_int, dp, dp]
+        L.oracle_Pd.argtypes = [ctypes.c_int]
+        L.oracle_Pd.restype = ctypes.c_double
+        L.oracle_Cd.argtypes = [ctypes.c_int]
+        L.oracle_Cd.restype = ctypes.c_double
+        L.oracle_integrate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_long, dp, dp, dp, ctypes.c_int]
+        L.oracle_threshold.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_long, dp, dp]
+        L.oracle_lpa_rhs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_long,
+                                     ctypes.c_double, dp, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def gauss_legendre(n: int):
+    """Gauss-Legendre nodes (ascending) and weights on [-1, 1]."""
+    x = np.empty(n)
+    w = np.empty(n)
+    rc = lib().oracle_gauss_legendre(n, _ptr(x), _ptr(w))
+    if rc != OK:
+        raise ValueError(f"oracle_gauss_legendre rc={rc}")
+    return x, w
+
+
+def Pd(d: int) -> float:
+    """Angular-measure prefactor Omega_{d-1}/(2 pi)^d."""
+    return lib().oracle_Pd(d)
+
+
+def Cd(d: int) -> float:
+    """Radial-only prefactor Omega_d/(2 pi)^d."""
+    return lib().oracle_Cd(d)
+
+
+def integrate(d, reg, k, q_max, n_r, n_a, p, m2, threads=1, allow_domain=False):
+    """One-loop flow-diagram integral I(p, m^2) for each (p[e], m2[e]) pair.
+
+    I = P_d sum_ij w_i q_i^{d-1} d_tR(q_i^2) G(q_i^2)^2 mu_j G(|q_i+p|^2), the
+    radial x angular Gauss-Legendre discretisation of
+    int d^dq/(2pi)^d d_tR G(q)^2 G(q+p).  Returns a float64 array (NaN where
+    m^2 + k^2 <= 0)."""
+    p = _f64(p).ravel()
+    m2 = _f64(m2).ravel()
+    if p.shape != m2.shape:
+        raise ValueError("p and m2 must have the same length")
+    out = np.empty_like(p)
+    rc = lib().oracle_integrate(int(d), int(reg), float(k), float(q_max), int(n_r), int(n_a),
+                                p.size, _ptr(p), _ptr(m2), _ptr(out), int(threads))
+    if rc == E_INVAL or (rc == E_DOMAIN and not allow_domain):
+        raise ValueError(f"oracle_integrate rc={rc}")
+    return out
+
+
+def integrate_grid(d, reg, k, q_max, n_r, n_a, p, m2, threads=1):
+    """Tensor grid: out[a, b] = I(p[a], m2[b])."""
+    p = _f64(p).ravel()
+    m2 = _f64(m2).ravel()
+    P = np.repeat(p, m2.size)
+    M = np.tile(m2, p.size)
+    return integrate(d, reg, k, q_max, n_r, n_a, P, M, threads).reshape(p.size, m2.size)
+
+
+def threshold(d, reg, k, q_max, n_r, n, m2, allow_domain=False):
+    """Threshold function F_n(m^2) = C_d sum_i w_i q_i^{d-1} d_tR(q_i^2) G(q_i^2)^n."""
+    m2 = _f64(m2).ravel()
+    out = np.empty_like(m2)
+    rc = lib().oracle_threshold(int(d), int(reg), float(k), float(q_max), int(n_r), int(n),
+                                m2.size, _ptr(m2), _ptr(out))
+    if rc == E_INVAL or (rc == E_DOMAIN and not allow_domain):
+        raise ValueError(f"oracle_threshold rc={rc}")
+    return out
+
+
+def lpa_rhs(d, N, reg, n_r, q_max_over_k, k, rho_max, U, jacobian=True, allow_domain=False):
+    """LPA O(N) right-hand side d_tU = 1/2 [F_1(U'+2 rho U'') + (N-1) F_1(U')]
+    on the uniform grid rho_j = j rho_max/(n-1), with its 7-band Jacobian
+    jac[o+3, j] = d(d_tU_j)/dU_{j+o}.  Returns (dUdt, jac or None, rc)."""
+    U = _f64(U).ravel()
+    n = U.size
+    dUdt = np.empty(n)
+    jac = np.zeros((7, n)) if jacobian else None
+    rc = lib().oracle_lpa_rhs(int(d), int(N), int(reg), int(n_r), float(q_max_over_k),
+                              float(k), n, float(rho_max), _ptr(U), _ptr(dUdt),
+                              _ptr(jac) if jacobian else None)
+    if rc == E_INVAL or (rc == E_DOMAIN and not allow_domain):
+        raise ValueError(f"oracle_lpa_rhs rc={rc}")
+    return dUdt, jac, rc
+
+
+def Omega(n: int) -> float:
+    """Area of the unit sphere S^{n-1} in R^n (plain Python, for the pins)."""
+    return 2.0 * math.pi ** (n / 2) / math.gamma(n / 2)

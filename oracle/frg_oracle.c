@@ -1,0 +1,318 @@
+/*
+ * frg_oracle.c -- plain, slow FP64 CPU oracle for the FRG flow-diagram quadrature.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests/, the package's smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or constant generator with the HIP library: it builds its own
+ * Gauss-Legendre rules (Newton iteration on the Legendre three-term
+ * recurrence), evaluates every integrand term from the definition, and sums
+ * in natural order with an 80-bit accumulator.
+ *
+ * What is computed (textbook FRG; the paper's text has no FRG section, so the
+ * definitions below are the standard Wetterich-equation ones, stated here in
+ * full):
+ *
+ *   one-loop flow diagram, external momentum p, mass m^2, RG scale k,
+ *   t = ln(k/Lambda), d_t = k d/dk:
+ *     I(p, m^2) = int d^dq/(2pi)^d  d_tR_k(q^2) G(q^2)^2 G(|q+p|^2),
+ *     G(s) = 1/(s + R_k(s) + m^2).
+ *   With p along one axis and x = cos(angle(q,p)):
+ *     d^dq/(2pi)^d = P_d q^{d-1} dq (1-x^2)^{(d-3)/2} dx,
+ *     P_d = Omega_{d-1}/(2pi)^d,  Omega_n = 2 pi^{n/2}/Gamma(n/2).
+ *   Discretisation: radial Gauss-Legendre on [0, Q], angular Gauss-Legendre
+ *   in x on [-1, 1] with the weight multiplied by (1-x^2)^{(d-3)/2} at the
+ *   nodes.  The result is the discrete double sum (this sum IS the method):
+ *     I = P_d sum_i sum_j w_i q_i^{d-1} d_tR(q_i^2) G(q_i^2)^2 mu_j G(s_ij),
+ *     s_ij = |q_i + p|^2 = (q_i - p)^2 + 2 q_i p (1 + x_j).
+ *
+ *   Regulators (y = s/k^2):
+ *     exponential: R = s/(e^y - 1),  d_tR = 2 k^2 beta(y) beta(-y),
+ *                  beta(z) = z/expm1(z);
+ *     Litim:       R = (k^2 - s) theta(k^2 - s),  d_tR = 2 k^2 theta(k^2 - s).
+ *   Propagator denominator written without cancellation at the pole
+ *   m^2 -> -k^2 (delta = m^2 + k^2):
+ *     exponential: s + R + m^2 = k^2 h(y) + delta,  h(y) = beta(-y) - 1,
+ *                  h from its Bernoulli series below y = 0.1;
+ *     Litim:       s + R + m^2 = max(s - k^2, 0) + delta.
+ *   Radial domain Q = q_max (exponential), Q = min(q_max, k) (Litim: the
+ *   support of d_tR).
+ *
+ *   Threshold functions (radial only, LPA):
+ *     F_n(m^2) = C_d sum_i w_i q_i^{d-1} d_tR(q_i^2) G(q_i^2)^n,
+ *     C_d = Omega_d/(2pi)^d.
+ *   LPA O(N) flow of the effective potential U(rho), rho = phi^2/2:
+ *     d_t U = 1/2 [ F_1(U' + 2 rho U'') + (N-1) F_1(U') ],
+ *   with U', U'' from second-order finite differences on a uniform grid.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_REG_EXP 0
+#define OR_REG_LITIM 1
+
+#define OR_OK 0
+#define OR_E_INVAL (-1)
+#define OR_E_DOMAIN (-2)
+
+/* ---------------------------------------------------------------- rules -- */
+
+/* Gauss-Legendre rule on [-1,1], nodes ascending: Newton on P_n(x) with P_n
+ * and P_n' from the three-term recurrence
+ *   (j+1) P_{j+1} = (2j+1) x P_j - j P_{j-1},  P_n' = n (x P_n - P_{n-1})/(x^2-1),
+ * weights 2/((1-x^2) P_n'(x)^2).  The recurrence runs in long double. */
+int oracle_gauss_legendre(int n, double *x, double *w) {
+  if (n < 1 || !x || !w) return OR_E_INVAL;
+  const long double pi = 3.14159265358979323846264338327950288L;
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    long double z = cosl(pi * (i + 0.75L) / (n + 0.5L));
+    long double dp = 1.0L;
+    for (int it = 0; it < 100; ++it) {
+      long double p0 = 1.0L, p1 = z;
+      for (int j = 1; j < n; ++j) {
+        long double p2 = ((2.0L * j + 1.0L) * z * p1 - j * p0) / (j + 1.0L);
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p0 = 1.0L; p1 = z; }
+      dp = n * (z * p1 - p0) / (z * z - 1.0L);
+      long double dz = p1 / dp;
+      z -= dz;
+      if (fabsl(dz) < 1e-19L) break;
+    }
+    /* final derivative at the converged node */
+    {
+      long double p0 = 1.0L, p1 = z;
+      for (int j = 1; j < n; ++j) {
+        long double p2 = ((2.0L * j + 1.0L) * z * p1 - j * p0) / (j + 1.0L);
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0L);
+    }
+    long double wt = 2.0L / ((1.0L - z * z) * dp * dp);
+    x[n - 1 - i] = (double)z;
+    x[i] = (double)(-z);
+    w[i] = (double)wt;
+    w[n - 1 - i] = (double)wt;
+  }
+  if (n % 2 == 1) x[n / 2] = 0.0;
+  return OR_OK;
+}
+
+/* area of the unit sphere S^{n-1} in R^n */
+static double omega(int n) {
+  return 2.0 * pow(M_PI, 0.5 * n) / tgamma(0.5 * n);
+}
+
+/* angular measure prefactor P_d = Omega_{d-1}/(2pi)^d */
+double oracle_Pd(int d) { return omega(d - 1) / pow(2.0 * M_PI, d); }
+
+/* radial-only prefactor C_d = Omega_d/(2pi)^d */
+double oracle_Cd(int d) { return omega(d) / pow(2.0 * M_PI, d); }
+
+/* (1-x^2)^{(d-3)/2} */
+static double angular_factor(int d, double x) {
+  double z = (1.0 - x) * (1.0 + x);
+  int e = d - 3;
+  double f = 1.0;
+  for (int i = 0; i < e / 2; ++i) f *= z;
+  if (e % 2 == 1) f *= sqrt(z);
+  return f;
+}
+
+static double ipow(double q, int e) {
+  double r = 1.0;
+  for (int i = 0; i < e; ++i) r *= q;
+  return r;
+}
+
+/* ------------------------------------------------------------ regulators -- */
+
+/* h(y) = beta(-y) - 1 = y/(1 - e^{-y}) - 1 for the exponential regulator */
+static double h_exp(double y) {
+  if (y < 0.1) {
+    double y2 = y * y;
+    return y / 2.0 + y2 / 12.0 - y2 * y2 / 720.0 + y2 * y2 * y2 / 30240.0 -
+           y2 * y2 * y2 * y2 / 1209600.0 + y2 * y2 * y2 * y2 * y2 / 47900160.0;
+  }
+  return y / (-expm1(-y)) - 1.0;
+}
+
+/* beta(z) = z/expm1(z), beta(0) = 1 */
+static double beta(double z) {
+  if (z == 0.0) return 1.0;
+  return z / expm1(z);
+}
+
+/* propagator denominator s + R(s) + m^2 in the stable form */
+static double denom(int reg, double k2, double s, double delta) {
+  if (reg == OR_REG_EXP) return k2 * h_exp(s / k2) + delta;
+  return fmax(s - k2, 0.0) + delta;
+}
+
+/* d_t R(s) = k dR/dk */
+static double dtR(int reg, double k2, double s) {
+  if (reg == OR_REG_EXP) {
+    double y = s / k2;
+    return 2.0 * k2 * beta(y) * beta(-y);
+  }
+  return (s < k2) ? 2.0 * k2 : 0.0;
+}
+
+/* radial rule mapped to [0, Q] */
+static int radial_rule(int reg, double k, double q_max, int n_r, double *q, double *w) {
+  int rc = oracle_gauss_legendre(n_r, q, w);
+  if (rc) return rc;
+  double Q = (reg == OR_REG_LITIM) ? fmin(q_max, k) : q_max;
+  for (int i = 0; i < n_r; ++i) {
+    q[i] = 0.5 * Q * (1.0 + q[i]);
+    w[i] = 0.5 * Q * w[i];
+  }
+  return OR_OK;
+}
+
+static int check_common(int d, int reg, double k, double q_max, int n_r) {
+  if (d < 2 || d > 10) return OR_E_INVAL;
+  if (reg != OR_REG_EXP && reg != OR_REG_LITIM) return OR_E_INVAL;
+  if (!(k > 0.0) || !(q_max > 0.0) || n_r < 1) return OR_E_INVAL;
+  return OR_OK;
+}
+
+/* ---------------------------------------------------------- integrals -- */
+
+/* I(p_e, m2_e) for n_pts independent external points. */
+int oracle_integrate(int d, int reg, double k, double q_max, int n_r, int n_a, long n_pts,
+                     const double *p, const double *m2, double *out, int n_threads) {
+  if (check_common(d, reg, k, q_max, n_r) || d < 3 || n_a < 1 || n_pts < 0) return OR_E_INVAL;
+  if (n_pts > 0 && (!p || !m2 || !out)) return OR_E_INVAL;
+  double *q = malloc(sizeof(double) * n_r), *w = malloc(sizeof(double) * n_r);
+  double *x = malloc(sizeof(double) * n_a), *v = malloc(sizeof(double) * n_a);
+  double *mu = malloc(sizeof(double) * n_a);
+  radial_rule(reg, k, q_max, n_r, q, w);
+  oracle_gauss_legendre(n_a, x, v);
+  for (int j = 0; j < n_a; ++j) mu[j] = v[j] * angular_factor(d, x[j]);
+  const double k2 = k * k;
+  const double Pd = oracle_Pd(d);
+  int domain = 0;
+  if (n_threads < 1) n_threads = 1;
+#pragma omp parallel for schedule(dynamic, 8) num_threads(n_threads) reduction(| : domain)
+  for (long e = 0; e < n_pts; ++e) {
+    double delta = m2[e] + k2;
+    if (!(delta > 0.0) || !(p[e] >= 0.0)) {
+      out[e] = NAN;
+      domain |= 1;
+      continue;
+    }
+    long double acc = 0.0L;
+    for (int i = 0; i < n_r; ++i) {
+      double qi = q[i];
+      double Gq = 1.0 / denom(reg, k2, qi * qi, delta);
+      double A = w[i] * ipow(qi, d - 1) * dtR(reg, k2, qi * qi) * Gq * Gq;
+      for (int j = 0; j < n_a; ++j) {
+        double s = (qi - p[e]) * (qi - p[e]) + 2.0 * qi * p[e] * (1.0 + x[j]);
+        double G = 1.0 / denom(reg, k2, s, delta);
+        acc += (long double)(A * mu[j] * G);
+      }
+    }
+    out[e] = Pd * (double)acc;
+  }
+  free(q); free(w); free(x); free(v); free(mu);
+  return domain ? OR_E_DOMAIN : OR_OK;
+}
+
+/* F_n(m2_e), radial only */
+int oracle_threshold(int d, int reg, double k, double q_max, int n_r, int n, long n_pts,
+                     const double *m2, double *out) {
+  if (check_common(d, reg, k, q_max, n_r) || n < 1 || n_pts < 0) return OR_E_INVAL;
+  if (n_pts > 0 && (!m2 || !out)) return OR_E_INVAL;
+  double *q = malloc(sizeof(double) * n_r), *w = malloc(sizeof(double) * n_r);
+  radial_rule(reg, k, q_max, n_r, q, w);
+  const double k2 = k * k, Cd = oracle_Cd(d);
+  int domain = 0;
+  for (long e = 0; e < n_pts; ++e) {
+    double delta = m2[e] + k2;
+    if (!(delta > 0.0)) {
+      out[e] = NAN;
+      domain = 1;
+      continue;
+    }
+    long double acc = 0.0L;
+    for (int i = 0; i < n_r; ++i) {
+      double G = 1.0 / denom(reg, k2, q[i] * q[i], delta);
+      acc += (long double)(w[i] * ipow(q[i], d - 1) * dtR(reg, k2, q[i] * q[i]) * ipow(G, n));
+    }
+    out[e] = Cd * (double)acc;
+  }
+  free(q); free(w);
+  return domain ? OR_E_DOMAIN : OR_OK;
+}
+
+/* ------------------------------------------------------------------ LPA -- */
+
+/* Finite differences on the uniform grid rho_j = j*dr, j = 0..n-1 (n >= 4):
+ *   interior  U'  = (U[j+1] - U[j-1]) / (2 dr)
+ *             U'' = ((U[j+1] - 2U[j]) + U[j-1]) / dr^2
+ *   rho = 0   U'  = ((-3U[0] + 4U[1]) - U[2]) / (2 dr)
+ *             U'' = (((2U[0] - 5U[1]) + 4U[2]) - U[3]) / dr^2
+ *   rho_max   U'  = ((3U[n-1] - 4U[n-2]) + U[n-3]) / (2 dr)
+ *             U'' = (((2U[n-1] - 5U[n-2]) + 4U[n-3]) - U[n-4]) / dr^2
+ * and the coefficient of U[j+o] in U' (c1) and U'' (c2), o = -3..3, for the
+ * Jacobian.  Grouping as written; no fused multiply-add. */
+static void fd_stencil(const double *U, long n, long j, double dr, double *d1, double *d2,
+                       double c1[7], double c2[7]) {
+  for (int o = 0; o < 7; ++o) c1[o] = c2[o] = 0.0;
+  const double i2 = 1.0 / (2.0 * dr), i1 = 1.0 / (dr * dr);
+  if (j == 0) {
+    *d1 = ((-3.0 * U[0] + 4.0 * U[1]) - U[2]) / (2.0 * dr);
+    *d2 = (((2.0 * U[0] - 5.0 * U[1]) + 4.0 * U[2]) - U[3]) / (dr * dr);
+    c1[3] = -3.0 * i2; c1[4] = 4.0 * i2; c1[5] = -1.0 * i2;
+    c2[3] = 2.0 * i1; c2[4] = -5.0 * i1; c2[5] = 4.0 * i1; c2[6] = -1.0 * i1;
+  } else if (j == n - 1) {
+    *d1 = ((3.0 * U[n - 1] - 4.0 * U[n - 2]) + U[n - 3]) / (2.0 * dr);
+    *d2 = (((2.0 * U[n - 1] - 5.0 * U[n - 2]) + 4.0 * U[n - 3]) - U[n - 4]) / (dr * dr);
+    c1[3] = 3.0 * i2; c1[2] = -4.0 * i2; c1[1] = 1.0 * i2;
+    c2[3] = 2.0 * i1; c2[2] = -5.0 * i1; c2[1] = 4.0 * i1; c2[0] = -1.0 * i1;
+  } else {
+    *d1 = (U[j + 1] - U[j - 1]) / (2.0 * dr);
+    *d2 = ((U[j + 1] - 2.0 * U[j]) + U[j - 1]) / (dr * dr);
+    c1[4] = i2; c1[2] = -i2;
+    c2[4] = i1; c2[3] = -2.0 * i1; c2[2] = i1;
+  }
+}
+
+/* dU/dt on the grid and, if jac != NULL, the Jacobian in 7 bands:
+ * jac[(o+3)*n + j] = d(dUdt_j)/dU_{j+o}, o = -3..3, zero outside the grid.
+ * The RG scale k is passed in (k = Lambda e^t is formed by the caller). */
+int oracle_lpa_rhs(int d, int N, int reg, int n_r, double q_max_over_k, double k, long n,
+                   double rho_max, const double *U, double *dUdt, double *jac) {
+  if (check_common(d, reg, k, q_max_over_k * k, n_r) || N < 1 || n < 4 || !(rho_max > 0.0))
+    return OR_E_INVAL;
+  if (!U || !dUdt) return OR_E_INVAL;
+  const double dr = rho_max / (double)(n - 1);
+  int domain = 0;
+  for (long j = 0; j < n; ++j) {
+    double d1, d2, c1[7], c2[7];
+    fd_stencil(U, n, j, dr, &d1, &d2, c1, c2);
+    double rho = (double)j * dr;
+    double m2s = d1 + (2.0 * rho) * d2;
+    double m2p = d1;
+    /* N = 1 has no Goldstone modes: the pion mass is neither used nor checked */
+    double ms[2] = {m2s, m2p}, F1[2] = {0.0, 0.0}, F2[2] = {0.0, 0.0};
+    long nm = (N > 1) ? 2 : 1;
+    int r1 = oracle_threshold(d, reg, k, q_max_over_k * k, n_r, 1, nm, ms, F1);
+    int r2 = oracle_threshold(d, reg, k, q_max_over_k * k, n_r, 2, nm, ms, F2);
+    if (r1 == OR_E_DOMAIN || r2 == OR_E_DOMAIN) domain = 1;
+    dUdt[j] = 0.5 * (F1[0] + (double)(N - 1) * F1[1]);
+    if (jac) {
+      for (int o = 0; o < 7; ++o) {
+        double dms = c1[o] + (2.0 * rho) * c2[o];
+        double dmp = c1[o];
+        double v = -0.5 * (F2[0] * dms + (double)(N - 1) * F2[1] * dmp);
+        long col = j + (o - 3);
+        jac[(long)o * n + j] = (col >= 0 && col < n) ? v : 0.0;
+      }
+    }
+  }
+  return domain ? OR_E_DOMAIN : OR_OK;
+}

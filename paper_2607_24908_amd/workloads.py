@@ -1,0 +1,163 @@
+"""Seeded synthetic inputs for the FRG quadrature workloads.
+
+This module holds no arithmetic of the method: it only draws or lays out
+external points, quadrature orders and flow requests.  Both the HIP path and
+the CPU oracle are fed from here, so that their inputs are identical.
+
+Workloads (k = 1 throughout; radial domain [0, 6k] for the exponential
+regulator):
+
+* ``plain_d4``  -- d = 4, exponential regulator, 64 momenta p log-spaced in
+  [1e-3, 10] x 32 masses m^2 uniform in [-0.5, 5], 64 radial x 16 angular
+  Gauss-Legendre nodes: 2048 integrals.
+* ``scaleup_d3`` -- d = 3, exponential regulator, 4096 momenta log-spaced in
+  [1e-4, 20] x 512 masses uniform in [-0.9, 10], 128 radial x 32 angular
+  nodes: 2 097 152 integrals, 8.59e9 integrand evaluations.
+* ``uneven_sets`` -- 256 independent integral sets: points per set uniform in
+  [16, 1024], radial order in {32, 64, 128, 256}, angular order in {8, 16, 32},
+  d in {3, 4}, regulator in {exponential, Litim}; per point p log-uniform in
+  [1e-3, 10] and m^2 uniform in [-0.5, 5].
+* ``precision_d4`` -- the plain_d4 shape with half of the masses close to the
+  pole, m^2 = -k^2 + 10^U(-8,-1), and half uniform in [-0.9, 10].
+* ``lpa_requests`` -- a Poisson stream (rate 50/s) of LPA O(N) flow requests:
+  N in {1, 2, 4}, d = 3, exponential regulator, grid of 128..1024 points on
+  rho in [0, 0.5], initial U = lambda/8 (rho - rho0)^2 with lambda ~ U(1, 20),
+  rho0 ~ U(0, 0.2), RG time 0 -> -9, 64 radial nodes.
+
+All random draws use numpy's PCG64 with an explicit seed.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+REG_EXP = 0
+REG_LITIM = 1
+
+
+@dataclass
+class Quad:
+    d: int
+    reg: int
+    k: float
+    q_max: float
+    n_r: int
+    n_a: int
+
+
+@dataclass
+class GridWorkload:
+    """Tensor grid of external points: out[a, b] = I(p[a], m2[b])."""
+    name: str
+    quad: Quad
+    p: np.ndarray
+    m2: np.ndarray
+
+    @property
+    def n_integrals(self) -> int:
+        return self.p.size * self.m2.size
+
+    @property
+    def n_evals(self) -> int:
+        return self.n_integrals * self.quad.n_r * self.quad.n_a
+
+
+@dataclass
+class PointSet:
+    """An integral set of independent (p, m^2) points sharing one quadrature."""
+    quad: Quad
+    p: np.ndarray
+    m2: np.ndarray
+
+    @property
+    def n_evals(self) -> int:
+        return self.p.size * self.quad.n_r * self.quad.n_a
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def plain_d4() -> GridWorkload:
+    q = Quad(d=4, reg=REG_EXP, k=1.0, q_max=6.0, n_r=64, n_a=16)
+    return GridWorkload("plain_d4_exp_64x32_64r16a", q,
+                        np.logspace(-3.0, 1.0, 64), np.linspace(-0.5, 5.0, 32))
+
+
+def scaleup_d3(n_p: int = 4096, n_m: int = 512) -> GridWorkload:
+    q = Quad(d=3, reg=REG_EXP, k=1.0, q_max=6.0, n_r=128, n_a=32)
+    return GridWorkload(f"scaleup_d3_exp_{n_p}x{n_m}_128r32a", q,
+                        np.logspace(-4.0, np.log10(20.0), n_p), np.linspace(-0.9, 10.0, n_m))
+
+
+def scaleup_d3_litim_p0(n_m: int = 512) -> GridWorkload:
+    """Litim regulator at p = 0 over the scale-up masses (closed-form check)."""
+    q = Quad(d=3, reg=REG_LITIM, k=1.0, q_max=6.0, n_r=128, n_a=32)
+    return GridWorkload(f"scaleup_d3_litim_p0_{n_m}", q, np.zeros(1),
+                        np.linspace(-0.9, 10.0, n_m))
+
+
+def uneven_sets(seed: int = 0, n_sets: int = 256, max_points: int = 1024) -> list[PointSet]:
+    rng = _rng(seed)
+    sets = []
+    for _ in range(n_sets):
+        n_ext = int(rng.integers(16, max_points + 1))
+        n_r = int(rng.choice([32, 64, 128, 256]))
+        n_a = int(rng.choice([8, 16, 32]))
+        d = int(rng.choice([3, 4]))
+        reg = int(rng.choice([REG_EXP, REG_LITIM]))
+        p = 10.0 ** rng.uniform(-3.0, 1.0, n_ext)
+        m2 = rng.uniform(-0.5, 5.0, n_ext)
+        sets.append(PointSet(Quad(d, reg, 1.0, 6.0, n_r, n_a), p, m2))
+    return sets
+
+
+def precision_d4(seed: int = 0) -> GridWorkload:
+    rng = _rng(seed)
+    near = -1.0 + 10.0 ** rng.uniform(-8.0, -1.0, 16)
+    far = rng.uniform(-0.9, 10.0, 16)
+    q = Quad(d=4, reg=REG_EXP, k=1.0, q_max=6.0, n_r=64, n_a=16)
+    return GridWorkload(f"precision_d4_seed{seed}", q, np.logspace(-3.0, 1.0, 64),
+                        np.concatenate([np.sort(near), np.sort(far)]))
+
+
+@dataclass
+class FlowRequest:
+    N: int
+    d: int
+    reg: int
+    n_grid: int
+    rho_max: float
+    lam: float
+    rho0: float
+    t_end: float = -9.0
+    n_r: int = 64
+    q_max_over_k: float = 6.0
+    Lambda: float = 1.0
+    arrival_s: float = 0.0
+    rtol: float = 1e-6
+    atol: float = 1e-9
+
+    def rho(self) -> np.ndarray:
+        return np.linspace(0.0, self.rho_max, self.n_grid)
+
+    def U0(self) -> np.ndarray:
+        """Initial potential (lambda/8) (rho - rho0)^2 on the grid."""
+        r = self.rho()
+        return (self.lam / 8.0) * (r - self.rho0) ** 2
+
+
+def lpa_requests(seed: int = 0, n: int = 100, rate: float = 50.0,
+                 grid_lo: int = 128, grid_hi: int = 1024) -> list[FlowRequest]:
+    rng = _rng(seed)
+    gaps = rng.exponential(1.0 / rate, n)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    reqs = []
+    for i in range(n):
+        reqs.append(FlowRequest(
+            N=int(rng.choice([1, 2, 4])), d=3, reg=REG_EXP,
+            n_grid=int(rng.integers(grid_lo, grid_hi + 1)), rho_max=0.5,
+            lam=float(rng.uniform(1.0, 20.0)), rho0=float(rng.uniform(0.0, 0.2)),
+            arrival_s=float(arrivals[i])))
+    return reqs

@@ -1,0 +1,354 @@
+"""Pins of the FP64 oracle to facts fixed by mathematics, not by the oracle itself.
+
+Each test names the identity it checks.  Together they are chosen so that a
+plausible slip in the oracle -- a wrong measure prefactor, a wrong power of G,
+a dropped factor in d_tR, a wrong |q+p|, a bad quadrature rule, a lost digit
+near the pole -- fails at least one of them:
+
+* Gauss-Legendre rules: numpy's leggauss (a library routine) and exactness on
+  monomials up to degree 2n-1.
+* Litim regulator at p = 0: closed form C_d 2 k^{d+2}/(d delta^3) (the
+  discrete rule is exact there, every propagator equals 1/delta).
+* Exponential regulator, large m^2: m^6 I -> P_d (sum mu) k^{d+2}
+  Gamma(d/2+2) zeta(d/2+1), from int y^s e^y/(e^y-1)^2 dy = Gamma(s+1) zeta(s).
+* Continuum integral by adaptive quadrature (scipy) in a different
+  parametrisation (over s = |q+p|^2 instead of cos theta), with R and d_tR
+  written from their definitions, against the converged discrete rule.
+* The discrete rule evaluated in 40-digit arithmetic (mpmath) on tiny inputs.
+* p -> 0 behaviour (quadratic in p), positivity and monotonicity in m^2.
+* LPA: Litim threshold functions in closed form, exponential F_1(0) and its
+  large-mass limit in terms of zeta, finite-difference exactness on
+  quadratics, and the Jacobian against numerical differentiation.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+import oracle
+from oracle import REG_EXP, REG_LITIM
+
+PI = math.pi
+
+
+def closed_Pd(d):
+    return {3: 1.0 / (4 * PI ** 2), 4: 1.0 / (4 * PI ** 3)}[d]
+
+
+def closed_Cd(d):
+    return {3: 1.0 / (2 * PI ** 2), 4: 1.0 / (8 * PI ** 2)}[d]
+
+
+def mu_sum(d, n_a):
+    """sum_j v_j (1-x_j^2)^{(d-3)/2} with numpy's own Gauss-Legendre rule."""
+    x, v = np.polynomial.legendre.leggauss(n_a)
+    return float(np.sum(v * (1 - x * x) ** ((d - 3) / 2)))
+
+
+# ---------------------------------------------------------------- rules --
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 8, 16, 31, 32, 64, 128, 256])
+def test_gauss_legendre_library_and_moments(n):
+    x, w = oracle.gauss_legendre(n)
+    xr, wr = np.polynomial.legendre.leggauss(n)
+    assert np.all(np.diff(x) > 0)
+    assert np.max(np.abs(x - xr)) < 2e-15
+    assert np.max(np.abs(w - wr)) < 5e-14  # numpy's own weights carry ~1e-14 absolute
+    assert abs(w.sum() - 2.0) < 1e-14
+    for deg in range(0, min(2 * n, 48)):
+        exact = 2.0 / (deg + 1) if deg % 2 == 0 else 0.0
+        assert abs(np.dot(w, x ** deg) - exact) < 2e-14, (n, deg)
+
+
+@pytest.mark.parametrize("n", [7, 64, 128])
+def test_gauss_legendre_40_digits(n):
+    """Nodes and weights against roots of P_n found in 40-digit arithmetic."""
+    import mpmath as mp
+    mp.mp.dps = 40
+    x, w = oracle.gauss_legendre(n)
+    xs, ws = _mp_rule(n)
+    for i in range(0, n, max(1, n // 9)):
+        assert abs(x[i] - float(xs[i])) < 1e-16
+        assert abs(w[i] / float(ws[i]) - 1) < 1e-15
+    mp.mp.dps = 15
+
+
+def test_prefactors_closed_form():
+    for d in (3, 4):
+        assert oracle.Pd(d) == pytest.approx(closed_Pd(d), rel=1e-15)
+        assert oracle.Cd(d) == pytest.approx(closed_Cd(d), rel=1e-15)
+
+
+# ------------------------------------------------------- Litim at p = 0 --
+
+@pytest.mark.parametrize("d", [3, 4])
+@pytest.mark.parametrize("k", [1.0, 0.7, 2.5])
+def test_litim_p0_closed_form(d, k):
+    k2 = k * k
+    m2 = np.array([-0.9, -0.5, -1.0 + 1e-8, 0.0, 3.0]) * k2
+    delta = m2 + k2
+    n_a = 16
+    got = oracle.integrate(d, REG_LITIM, k, 6 * k, 32, n_a, np.zeros_like(m2), m2)
+    want = closed_Pd(d) * mu_sum(d, n_a) * 2 * k ** (d + 2) / (d * delta ** 3)
+    np.testing.assert_allclose(got, want, rtol=2e-14, atol=0)
+    if d == 3:  # continuum value k^5/(3 pi^2 delta^3): the d=3 angular rule is exact
+        np.testing.assert_allclose(got, k ** 5 / (3 * PI ** 2 * delta ** 3), rtol=2e-14)
+
+
+# -------------------------------------------------- exp, large mass limit --
+
+@pytest.mark.parametrize("d", [3, 4])
+def test_exp_large_mass_limit(d):
+    """m^6 I(m^2) -> P_d (sum mu) k^{d+2} Gamma(d/2+2) zeta(d/2+1), Richardson in 1/m^2."""
+    k, n_a = 1.3, 16
+    p = np.array([0.4])
+
+    def f(M):
+        return M ** 3 * oracle.integrate(d, REG_EXP, k, 8 * k, 64, n_a, p, np.array([M]))[0]
+
+    M = 1e5
+    r1 = 2 * f(2 * M) - f(M)
+    r2 = 2 * f(4 * M) - f(2 * M)
+    lim = (4 * r2 - r1) / 3
+    want = closed_Pd(d) * mu_sum(d, n_a) * k ** (d + 2) * special.gamma(d / 2 + 2) * special.zeta(d / 2 + 1)
+    assert lim == pytest.approx(want, rel=1e-11)
+    # without Richardson the leading correction is O(1/m^2) and negative
+    assert f(M) < want
+
+
+# ------------------------------------------------- continuum, scipy quad --
+
+def _continuum(d, reg, k, Q, p, m2):
+    """int d^dq/(2pi)^d d_tR G(q)^2 G(q+p) truncated at |q| <= Q, by adaptive
+    quadrature.  R, d_tR = k dR/dk and G are written from their definitions;
+    the angular integral runs over s = |q+p|^2 (d = 3) or over x with the
+    algebraic weight (1-x^2)^{1/2} handled by QUADPACK (d = 4)."""
+    k2 = k * k
+
+    def R(s):
+        if reg == REG_EXP:
+            return s / math.expm1(s / k2) if s > 0 else k2
+        return max(k2 - s, 0.0)
+
+    def dtR(s):
+        if reg == REG_EXP:
+            y = s / k2
+            # k d/dk [s/(e^{s/k^2}-1)] = 2 s^2 e^y / (k^2 (e^y - 1)^2)
+            return 2.0 * s * s * math.exp(y) / (k2 * math.expm1(y) ** 2) if y > 0 else 2 * k2
+        return 2.0 * k2 if s < k2 else 0.0
+
+    def G(s):
+        return 1.0 / (s + R(s) + m2)
+
+    kinks = [k2] if reg == REG_LITIM else []
+
+    def inner(q):
+        if d == 3:
+            lo, hi = (q - p) ** 2, (q + p) ** 2
+            pts = [s for s in kinks if lo < s < hi]
+            v = integrate.quad(G, lo, hi, points=pts or None, epsabs=0, epsrel=1e-13, limit=200)[0]
+            return v / (2 * q * p)
+        # d = 4: x-form with weight (1+x)^{1/2} (1-x)^{1/2}
+        g = lambda x: G(q * q + p * p + 2 * q * p * x)
+        return integrate.quad(g, -1.0, 1.0, weight="alg", wvar=(0.5, 0.5), epsabs=0,
+                              epsrel=1e-13, limit=200)[0]
+
+    def outer(q):
+        s = q * q
+        return q ** (d - 1) * dtR(s) * G(s) ** 2 * inner(q)
+
+    pts = []
+    if reg == REG_LITIM:
+        pts = [x for x in (abs(k - p), k + p) if 0 < x < Q]
+    val = integrate.quad(outer, 0.0, Q, points=pts or None, epsabs=0, epsrel=1e-13, limit=400)[0]
+    return oracle.Omega(d - 1) / (2 * PI) ** d * val
+
+
+@pytest.mark.parametrize("p,m2", [(0.3, -0.5), (1.0, 0.0), (3.0, 2.0), (0.05, 0.7)])
+def test_exp_d3_continuum(p, m2):
+    got = oracle.integrate(3, REG_EXP, 1.0, 6.0, 128, 64, [p], [m2])[0]
+    want = _continuum(3, REG_EXP, 1.0, 6.0, p, m2)
+    assert got == pytest.approx(want, rel=1e-11)
+
+
+@pytest.mark.parametrize("p,m2", [(0.3, -0.5), (2.0, 1.0)])
+def test_exp_d4_continuum_and_rate(p, m2):
+    """The literal d = 4 rule (GL weights times sqrt(1-x^2)) converges to the
+    continuum algebraically, ~ n_a^-3."""
+    want = _continuum(4, REG_EXP, 1.0, 6.0, p, m2)
+    errs = [abs(oracle.integrate(4, REG_EXP, 1.0, 6.0, 96, n, [p], [m2])[0] / want - 1)
+            for n in (32, 64, 128)]
+    assert errs[0] / errs[1] == pytest.approx(8.0, rel=0.15)
+    assert errs[1] / errs[2] == pytest.approx(8.0, rel=0.15)
+    big = oracle.integrate(4, REG_EXP, 1.0, 6.0, 96, 1024, [p], [m2])[0]
+    assert big == pytest.approx(want, rel=2e-9)
+
+
+@pytest.mark.parametrize("p,m2", [(0.4, -0.3), (1.7, 0.5)])
+def test_litim_d3_continuum(p, m2):
+    """Litim, p > 0: the kink at |q+p| = k limits the rule to algebraic convergence."""
+    want = _continuum(3, REG_LITIM, 1.0, 6.0, p, m2)
+    got = oracle.integrate(3, REG_LITIM, 1.0, 6.0, 256, 2048, [p], [m2])[0]
+    assert got == pytest.approx(want, rel=2e-5)
+    coarse = oracle.integrate(3, REG_LITIM, 1.0, 6.0, 32, 32, [p], [m2])[0]
+    assert abs(got / want - 1) < abs(coarse / want - 1)
+
+
+# ------------------------------------------ discrete rule, 40 digits ---
+
+def _mp_rule(n):
+    """Gauss-Legendre rule from mpmath's Legendre function (hypergeometric
+    evaluation, 100 working digits), roots polished from numpy's nodes."""
+    import mpmath as mp
+    xr, _ = np.polynomial.legendre.leggauss(n)
+    xs, ws = [], []
+    with mp.workdps(100):
+        for x0 in xr:
+            x = mp.findroot(lambda t: mp.legendre(n, t), mp.mpf(x0), tol=mp.mpf(10) ** -80)
+            dp = mp.diff(lambda t: mp.legendre(n, t), x)
+            xs.append(x)
+            ws.append(2 / ((1 - x * x) * dp * dp))
+    return xs, ws
+
+
+def _mp_discrete(d, reg, k, q_max, n_r, n_a, p, m2):
+    import mpmath as mp
+    k, p, m2 = mp.mpf(k), mp.mpf(p), mp.mpf(m2)
+    k2 = k * k
+    Q = min(mp.mpf(q_max), k) if reg == REG_LITIM else mp.mpf(q_max)
+    xi, om = _mp_rule(n_r)
+    xa, va = _mp_rule(n_a)
+
+    def R(s):
+        if reg == REG_EXP:
+            return s / mp.expm1(s / k2)
+        return max(k2 - s, mp.mpf(0))
+
+    def dtR(s):
+        if reg == REG_EXP:
+            y = s / k2
+            return 2 * s * s * mp.exp(y) / (k2 * mp.expm1(y) ** 2)
+        return 2 * k2 if s < k2 else mp.mpf(0)
+
+    G = lambda s: 1 / (s + R(s) + m2)
+    tot = mp.mpf(0)
+    for i in range(n_r):
+        q = Q * (1 + xi[i]) / 2
+        w = Q * om[i] / 2
+        A = w * q ** (d - 1) * dtR(q * q) * G(q * q) ** 2
+        for j in range(n_a):
+            mu = va[j] * (1 - xa[j] ** 2) ** (mp.mpf(d - 3) / 2)
+            tot += A * mu * G(q * q + p * p + 2 * q * p * xa[j])
+    Pd = 2 * mp.pi ** (mp.mpf(d - 1) / 2) / mp.gamma(mp.mpf(d - 1) / 2) / (2 * mp.pi) ** d
+    return Pd * tot
+
+
+@pytest.mark.parametrize("d,reg", [(3, REG_EXP), (4, REG_EXP), (3, REG_LITIM), (4, REG_LITIM)])
+def test_discrete_rule_extended_precision(d, reg):
+    import mpmath as mp
+    mp.mp.dps = 40
+    pts = [(1e-3, -0.5), (0.37, 0.0), (1.9, -0.95), (5.0, 4.0), (0.8, -1.0 + 1e-6)]
+    for p, m2 in pts:
+        want = _mp_discrete(d, reg, 1.0, 6.0, 12, 6, p, m2)
+        got = oracle.integrate(d, reg, 1.0, 6.0, 12, 6, [p], [m2])[0]
+        assert abs(got / float(want) - 1) < 3e-15, (p, m2, got, want)
+    mp.mp.dps = 15
+
+
+# ------------------------------------------------ limits and invariants --
+
+def test_p_to_zero_is_quadratic():
+    """(I(p) - I(0))/I(0) = c2 p^2 + O(p^4): the symmetric angular rule keeps odd moments at zero."""
+    p = np.array([0.0, 1e-2, 1e-3, 1e-4])
+    I = oracle.integrate(3, REG_EXP, 1.0, 6.0, 64, 16, p, np.full(4, 0.3))
+    c = (I[1:] - I[0]) / I[0] / p[1:] ** 2
+    assert c[0] == pytest.approx(c[1], rel=1e-3)
+    assert c[1] == pytest.approx(c[2], rel=1e-4)
+
+
+@pytest.mark.parametrize("d,reg", [(3, REG_EXP), (4, REG_EXP), (3, REG_LITIM), (4, REG_LITIM)])
+def test_positive_and_decreasing_in_mass(d, reg):
+    m2 = np.linspace(-0.99, 10.0, 40)
+    for p in (1e-3, 0.5, 4.0):
+        I = oracle.integrate(d, reg, 1.0, 6.0, 32, 8, np.full_like(m2, p), m2)
+        assert np.all(I > 0)
+        assert np.all(np.diff(I) < 0)
+
+
+def test_domain_violation_gives_nan():
+    out = oracle.integrate(3, REG_EXP, 1.0, 6.0, 16, 8, [0.5, 0.5, 0.5], [-1.0, -1.5, 0.0],
+                           allow_domain=True)
+    assert np.isnan(out[0]) and np.isnan(out[1]) and np.isfinite(out[2])
+    with pytest.raises(ValueError):
+        oracle.integrate(3, REG_EXP, 1.0, 6.0, 16, 8, [0.5], [-1.0])
+
+
+# ------------------------------------------------------------------- LPA --
+
+@pytest.mark.parametrize("d", [3, 4])
+@pytest.mark.parametrize("n", [1, 2])
+def test_litim_threshold_closed_form(d, n):
+    k = 0.8
+    m2 = np.array([-0.9, -0.3, 0.0, 2.0]) * k * k
+    got = oracle.threshold(d, REG_LITIM, k, 6 * k, 16, n, m2)
+    want = closed_Cd(d) * 2 * k ** (d + 2) / (d * (m2 + k * k) ** n)
+    np.testing.assert_allclose(got, want, rtol=1e-14)
+
+
+@pytest.mark.parametrize("d", [3, 4])
+def test_exp_threshold_zeta_forms(d):
+    k = 1.4
+    # F_1(0) = C_d k^d Gamma(d/2+1) zeta(d/2+1)
+    f0 = oracle.threshold(d, REG_EXP, k, 8 * k, 64, 1, [0.0])[0]
+    assert f0 == pytest.approx(closed_Cd(d) * k ** d * special.gamma(d / 2 + 1) * special.zeta(d / 2 + 1),
+                               rel=1e-13)
+    # m^2 F_1(m^2) -> C_d k^{d+2} Gamma(d/2+2) zeta(d/2+1)
+    f = lambda M: M * oracle.threshold(d, REG_EXP, k, 8 * k, 64, 1, [M])[0]
+    M = 1e5
+    r1, r2 = 2 * f(2 * M) - f(M), 2 * f(4 * M) - f(2 * M)
+    assert (4 * r2 - r1) / 3 == pytest.approx(
+        closed_Cd(d) * k ** (d + 2) * special.gamma(d / 2 + 2) * special.zeta(d / 2 + 1), rel=1e-11)
+
+
+@pytest.mark.parametrize("N", [1, 2, 4])
+def test_lpa_rhs_quadratic_potential_litim(N):
+    """U = a + b rho + c rho^2: the difference formulas are exact, so
+    m_sigma^2 = b + 6 c rho, m_pi^2 = b + 2 c rho, and with the Litim closed
+    form d_tU = C_d k^{d+2}/d [1/(m_s^2+k^2) + (N-1)/(m_p^2+k^2)]."""
+    d, k, n, rho_max = 3, 0.9, 64, 0.5
+    a, b, c = 0.1, -0.2, 1.5
+    rho = np.linspace(0, rho_max, n)
+    U = a + b * rho + c * rho ** 2
+    dUdt, _, rc = oracle.lpa_rhs(d, N, REG_LITIM, 32, 6.0, k, rho_max, U)
+    ms, mp_ = b + 6 * c * rho, b + 2 * c * rho
+    want = closed_Cd(d) * k ** (d + 2) / d * (1 / (ms + k * k) + (N - 1) / (mp_ + k * k))
+    np.testing.assert_allclose(dUdt, want, rtol=1e-11)
+
+
+@pytest.mark.parametrize("N", [1, 4])
+def test_lpa_jacobian_matches_numerical_derivative(N):
+    d, k, n, rho_max = 3, 0.6, 24, 0.5
+    rho = np.linspace(0, rho_max, n)
+    U = 5.0 / 8 * (rho - 0.1) ** 2 + 0.02 * np.sin(7 * rho)
+    _, jac, _ = oracle.lpa_rhs(d, N, REG_EXP, 64, 6.0, k, rho_max, U)
+    eps = 1e-8
+    num = np.zeros((n, n))
+    for l in range(n):
+        Up, Um = U.copy(), U.copy()
+        Up[l] += eps
+        Um[l] -= eps
+        num[:, l] = (oracle.lpa_rhs(d, N, REG_EXP, 64, 6.0, k, rho_max, Up, False)[0]
+                     - oracle.lpa_rhs(d, N, REG_EXP, 64, 6.0, k, rho_max, Um, False)[0]) / (2 * eps)
+    dense = np.zeros((n, n))
+    for o in range(-3, 4):
+        for j in range(n):
+            if 0 <= j + o < n:
+                dense[j, j + o] = jac[o + 3, j]
+    scale = np.max(np.abs(num))
+    assert np.max(np.abs(dense - num)) < 1e-6 * scale
+    # nothing outside the 7 bands
+    for j in range(n):
+        for l in range(n):
+            if abs(l - j) > 3:
+                assert abs(num[j, l]) < 1e-9 * scale
