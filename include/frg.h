@@ -1,0 +1,249 @@
+/*
+ * frg.h -- C ABI of the MI355X (gfx950) library for batched FRG flow-diagram
+ * quadrature.
+ *
+ * The operations follow the standard functional-renormalisation-group
+ * definitions (Wetterich equation, one-loop flow diagrams with a regulator
+ * R_k); the paper's text fixes none of them, so each entry point states the
+ * formula it computes.
+ *
+ * Conventions shared by every call
+ *   - RG time t = ln(k/Lambda), d_t = k d/dk.
+ *   - Regulators (y = s/k^2, s a squared momentum):
+ *       FRG_REG_EXP   R_k(s) = s/(e^y - 1)
+ *       FRG_REG_LITIM R_k(s) = (k^2 - s) theta(k^2 - s)
+ *   - Propagator G(s) = 1/(s + R_k(s) + m^2); a point is in the domain iff
+ *     delta = m^2 + k^2 > 0 (then every denominator is >= delta > 0).
+ *   - Quadrature: radial Gauss-Legendre on [0, Q] with Q = q_max (exponential)
+ *     or Q = min(q_max, k) (Litim, the support of d_tR); angular
+ *     Gauss-Legendre in x = cos(theta) on [-1, 1] with each weight multiplied
+ *     by (1 - x^2)^{(d-3)/2}.  The discrete sum is the result; no
+ *     extrapolation is applied.
+ *   - Every function returns an frg_status (int).  No exception crosses the
+ *     ABI.  On failure frg_last_error() returns a message for the calling
+ *     thread.
+ *   - Memory: the caller owns every input and output buffer.  `mem` says
+ *     where ALL pointers of a call live (FRG_MEM_HOST or FRG_MEM_DEVICE); it
+ *     is never guessed.  Device calls are asynchronous on `hip_stream` (a
+ *     hipStream_t, NULL = the null stream; from PyTorch pass
+ *     torch.cuda.current_stream().cuda_stream); host calls are synchronous.
+ *   - A context serialises its synchronous calls internally; one context may
+ *     be shared by threads.  frg_submit/frg_poll are thread-safe.
+ */
+#ifndef FRG_H
+#define FRG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes --------------------------------------------------------- */
+#define FRG_OK 0
+#define FRG_PENDING 1        /* frg_poll: the flow is not finished            */
+#define FRG_E_INVAL (-1)     /* bad argument; nothing was written             */
+#define FRG_E_DOMAIN (-2)    /* some point had m^2 + k^2 <= 0: its result is
+                                NaN, every other result is valid              */
+#define FRG_E_NOMEM (-3)     /* device memory or the HBM budget is exhausted  */
+#define FRG_E_DEVICE (-4)    /* a HIP runtime call failed                     */
+#define FRG_E_AGAIN (-5)     /* submission queue full; retry later            */
+#define FRG_E_NOTFOUND (-6)  /* unknown ticket                                */
+#define FRG_E_STEP (-7)      /* flow stepper failed (step size underflow)     */
+
+/* ---- enumerations --------------------------------------------------------- */
+#define FRG_REG_EXP 0
+#define FRG_REG_LITIM 1
+
+#define FRG_PREC_FP64 0   /* FP64 throughout                                   */
+#define FRG_PREC_FP32C 1  /* FP32 angular bulk with two-sum compensated sums;
+                             FP64 per-radial-node factors and cross-lane
+                             reduction; results whose error estimate exceeds
+                             the FP32 tolerance, and points near the pole, are
+                             recomputed in FP64                                */
+
+#define FRG_MEM_HOST 0
+#define FRG_MEM_DEVICE 1
+
+/* frg_integrate flags */
+#define FRG_PLAIN 0       /* one ordinary launch per integral set              */
+#define FRG_PERSISTENT 1  /* all sets in one persistent launch over a
+                             longest-first work list                           */
+#define FRG_GRAPH 2       /* with FRG_PERSISTENT: replay a captured HIP graph
+                             when the same batch (same pointers and shapes) is
+                             submitted again                                    */
+
+typedef struct frg_ctx frg_ctx;
+
+/* Create a context on HIP device `hip_device`.  `hbm_budget_bytes` bounds the
+ * device memory the context's flow server may hold for resident flow state
+ * (0 = 1/2 of the device's free memory at creation).  Tables, work lists and
+ * staging buffers are owned by the context and freed by frg_destroy. */
+int frg_create(frg_ctx **out, int hip_device, uint64_t hbm_budget_bytes);
+
+/* Finish or cancel all flows, free all device and host resources. */
+void frg_destroy(frg_ctx *ctx);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *frg_last_error(void);
+
+/* Library version string. */
+const char *frg_version(void);
+
+/* ---- quadrature description ---------------------------------------------- */
+typedef struct {
+  int32_t d;          /* space-time dimension, 3 <= d <= 8                     */
+  int32_t reg;        /* FRG_REG_EXP or FRG_REG_LITIM                          */
+  double k;           /* RG scale, > 0                                         */
+  double q_max;       /* radial cut-off, > 0 (usually 6k)                      */
+  int32_t n_radial;   /* radial Gauss-Legendre order, 1..1024                  */
+  int32_t n_angular;  /* angular Gauss-Legendre order, 1..256                  */
+  int32_t prec;       /* FRG_PREC_FP64 or FRG_PREC_FP32C                       */
+  int32_t reserved;   /* must be 0                                             */
+} frg_quad;
+
+/* One integral set: n_ext independent external points (p[e], m2[e]).
+ *   out[e] = P_d sum_i sum_j w_i q_i^{d-1} d_tR(q_i^2) G(q_i^2)^2 mu_j G(s_ij),
+ *   s_ij = |q_i + p_e|^2 = q_i^2 + p_e^2 + 2 q_i p_e x_j,
+ *   P_d = Omega_{d-1}/(2 pi)^d,  Omega_n = 2 pi^{n/2}/Gamma(n/2),
+ * the radial x angular Gauss-Legendre form of
+ *   int d^dq/(2 pi)^d d_tR_k(q^2) G(q^2)^2 G(|q+p|^2).
+ * p[e] >= 0.  err_est (optional, FP32C only) receives an estimate of the
+ * relative error of out[e]; used_fp64 (optional, FP32C only) receives 1 where
+ * the point was evaluated in FP64.  Arrays are contiguous float64 / uint8. */
+typedef struct {
+  frg_quad quad;
+  int64_t n_ext;
+  const double *p;
+  const double *m2;
+  double *out;
+  double *err_est;
+  uint8_t *used_fp64;
+} frg_set;
+
+/* Evaluate n_sets integral sets.  flags: FRG_PLAIN, or FRG_PERSISTENT
+ * (optionally | FRG_GRAPH).  Results are bitwise identical for every flag
+ * and every tile choice: the summation order of each result depends only on
+ * (n_radial, n_angular).  Returns FRG_E_DOMAIN if any point had
+ * m^2 + k^2 <= 0 (device calls report it only after the stream completes, so
+ * device calls return FRG_OK and leave NaN in out). */
+int frg_integrate(frg_ctx *ctx, const frg_set *sets, int32_t n_sets, int32_t mem, int32_t flags,
+                  void *hip_stream);
+
+/* Tensor grid of external points sharing one quadrature:
+ *   out[a * n_m + b] = I(p[a], m2[b])   (same formula as frg_set).
+ * The regulator part of G(|q+p|) depends on p only, so it is evaluated once
+ * per (p, node) and reused for every mass.  err_est / used_fp64 as in
+ * frg_set (n_p * n_m entries, optional). */
+int frg_integrate_grid(frg_ctx *ctx, const frg_quad *quad, int64_t n_p, const double *p,
+                       int64_t n_m, const double *m2, double *out, double *err_est,
+                       uint8_t *used_fp64, int32_t mem, void *hip_stream);
+
+/* ---- LPA O(N) flow -------------------------------------------------------- */
+/* Local potential approximation of the O(N) model, effective potential U(rho)
+ * with rho = phi^2/2 on the uniform grid rho_j = j rho_max/(n_grid-1):
+ *   d_t U = 1/2 [ F_1(m_s^2) + (N-1) F_1(m_p^2) ],
+ *   m_s^2 = U' + 2 rho U'',  m_p^2 = U',
+ *   F_n(m^2) = C_d sum_i w_i q_i^{d-1} d_tR(q_i^2) G(q_i^2)^n,  C_d = Omega_d/(2 pi)^d,
+ * radial rule on [0, q_max_over_k * k] (exponential) or [0, k] (Litim).
+ * U', U'' by second-order differences, grouped exactly as
+ *   interior  U'  = (U[j+1] - U[j-1]) / (2 dr)
+ *             U'' = ((U[j+1] - 2U[j]) + U[j-1]) / dr^2
+ *   rho = 0   U'  = ((-3U[0] + 4U[1]) - U[2]) / (2 dr)
+ *             U'' = (((2U[0] - 5U[1]) + 4U[2]) - U[3]) / dr^2
+ *   rho_max   U'  = ((3U[n-1] - 4U[n-2]) + U[n-3]) / (2 dr)
+ *             U'' = (((2U[n-1] - 5U[n-2]) + 4U[n-3]) - U[n-4]) / dr^2
+ * and m_s^2 = U' + (2 rho) U'' without fused multiply-add. */
+typedef struct {
+  int32_t d;             /* 2..8                                            */
+  int32_t N;             /* O(N) components, >= 1 (N = 1: no Goldstones)    */
+  int32_t reg;           /* FRG_REG_EXP or FRG_REG_LITIM                     */
+  int32_t n_radial;      /* radial order, 1..1024                            */
+  double q_max_over_k;   /* radial cut-off in units of k (usually 6)         */
+  double Lambda;         /* UV scale, k = Lambda e^t                         */
+  int64_t n_grid;        /* grid points, 4..65536                            */
+  double rho_max;        /* grid end, > 0                                    */
+} frg_lpa;
+
+/* Right-hand side at RG time t (k = Lambda e^t).  U and dUdt: n_grid float64.
+ * jac_bands (optional): 7*n_grid float64, jac_bands[(o+3)*n_grid + j] =
+ * d(dUdt_j)/dU_{j+o} for o = -3..3 (zero where j+o is off the grid), built
+ * from dF_1/dm^2 = -F_2.  FRG_E_DOMAIN (host memory) if some mass had
+ * m^2 + k^2 <= 0; the affected entries are NaN. */
+int frg_flow_rhs(frg_ctx *ctx, const frg_lpa *lpa, double t, const double *U, double *dUdt,
+                 double *jac_bands, int32_t mem, void *hip_stream);
+
+/* The same for n_flows independent flows in ONE launch (device memory only):
+ * flow f uses lpa[f], t[f], U[f], dUdt[f], jac_bands[f] (jac_bands may be
+ * NULL, or contain NULL entries).  Each flow's result is bitwise identical to
+ * frg_flow_rhs on that flow alone. */
+int frg_flow_rhs_batch(frg_ctx *ctx, int32_t n_flows, const frg_lpa *lpa, const double *t,
+                       const double *const *U, double *const *dUdt, double *const *jac_bands,
+                       void *hip_stream);
+
+/* ---- flow integration on the host ------------------------------------------ */
+/* One LPA flow request: U(t=0) = (lambda/8)(rho - rho0)^2, integrated from
+ * t = 0 to t_end < 0 by the implicit variable-step BDF(1,2) stepper in FP64
+ * (Newton with the banded Jacobian, local error control with rtol/atol).
+ * U_out (host, n_grid float64) receives U(t_end); it must stay valid until
+ * frg_poll reports completion. */
+typedef struct {
+  frg_lpa lpa;
+  double lambda;
+  double rho0;
+  double t_end;
+  double rtol;
+  double atol;
+  double *U_out;
+} frg_request;
+
+typedef struct {
+  int32_t status;     /* FRG_OK, FRG_PENDING, FRG_E_STEP, FRG_E_DOMAIN ...  */
+  int32_t reserved;
+  int64_t steps;      /* accepted steps                                     */
+  int64_t rejected;   /* rejected steps                                     */
+  int64_t rhs_calls;  /* right-hand-side evaluations                        */
+  double submit_s;    /* monotonic clock, seconds                           */
+  double start_s;     /* admitted and started                               */
+  double done_s;      /* finished                                           */
+} frg_result;
+
+/* Host right-hand side used by frg_flow_solve: fill dUdt[n] and, if
+ * jac_bands != NULL, the 7 bands as in frg_flow_rhs.  Return FRG_OK, or
+ * FRG_E_DOMAIN to make the stepper reject the step. */
+typedef int (*frg_rhs_fn)(void *user, double t, const double *U, int64_t n, double *dUdt,
+                          double *jac_bands);
+
+/* Integrate one request synchronously with a caller-supplied right-hand side
+ * (host only; no GPU use).  The stepper is the one the flow server runs. */
+int frg_flow_solve(const frg_request *req, frg_rhs_fn rhs, void *user, frg_result *out);
+
+/* Submit a flow to the context's server (never blocks).  The server admits
+ * a flow when a slot is free and its device footprint fits the HBM budget,
+ * keeps its state resident, and batches the right-hand-side evaluations of
+ * all running flows into shared launches (continuous batching).
+ * FRG_E_AGAIN if the queue is full. */
+int frg_submit(frg_ctx *ctx, const frg_request *req, uint64_t *ticket);
+
+/* FRG_PENDING until the flow finishes; then the result (status inside) and
+ * FRG_OK, and the ticket is released.  FRG_E_NOTFOUND for unknown tickets. */
+int frg_poll(frg_ctx *ctx, uint64_t ticket, frg_result *out);
+
+/* Server statistics: completed flows, batched launches and the mean number of
+ * flows per launch since creation. */
+int frg_server_stats(frg_ctx *ctx, int64_t *flows_done, int64_t *launches, double *mean_batch);
+
+/* ---- host-only helpers ------------------------------------------------------ */
+/* Gauss-Legendre nodes (ascending) and weights on [-1, 1], n = 1..4096, by
+ * the Golub-Welsch eigenvalue method (no GPU use). */
+int frg_gauss_legendre(int32_t n, double *x, double *w);
+
+/* Bytes of device memory one flow of this shape keeps resident while it runs
+ * (what the server's HBM admission charges). */
+int64_t frg_flow_footprint(const frg_lpa *lpa);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FRG_H */

@@ -1,0 +1,707 @@
+// C ABI of libfrg: context, table cache, descriptor staging and the launch
+// paths behind frg_integrate, frg_integrate_grid and frg_flow_rhs(_batch).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "frg_ctx.h"
+
+namespace frg {
+
+static thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(FRG_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void clear_error() { g_err.clear(); }
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ------------------------------------------------------------- DevBuf --
+DevBuf::~DevBuf() { release(); }
+void DevBuf::release() {
+  if (ptr) hipFree(ptr);
+  ptr = nullptr;
+  bytes = 0;
+}
+int DevBuf::reserve(size_t b) {
+  if (b <= bytes) return FRG_OK;
+  release();
+  size_t nb = std::max<size_t>(b, 256);
+  hipError_t e = hipMalloc(&ptr, nb);
+  if (e != hipSuccess) {
+    ptr = nullptr;
+    return fail(FRG_E_NOMEM, "hipMalloc(%zu): %s", nb, hipGetErrorString(e));
+  }
+  bytes = nb;
+  return FRG_OK;
+}
+
+// --------------------------------------------------------------- ring --
+int DescRing::init(size_t slot_bytes_, int n_slots) {
+  slot_bytes = slot_bytes_;
+  slots.resize(n_slots);
+  for (auto &s : slots) {
+    if (hipHostMalloc(&s.host, slot_bytes, hipHostMallocDefault) != hipSuccess)
+      return fail(FRG_E_NOMEM, "hipHostMalloc descriptor ring");
+    if (hipMalloc(&s.dev, slot_bytes) != hipSuccess)
+      return fail(FRG_E_NOMEM, "hipMalloc descriptor ring");
+    if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
+      return fail(FRG_E_DEVICE, "hipEventCreate");
+    s.used = false;
+  }
+  return FRG_OK;
+}
+
+void DescRing::destroy() {
+  for (auto &s : slots) {
+    if (s.used) hipEventSynchronize(s.done);
+    if (s.host) hipHostFree(s.host);
+    if (s.dev) hipFree(s.dev);
+    if (s.done) hipEventDestroy(s.done);
+    s = Slot{};
+  }
+  slots.clear();
+}
+
+// Copy `bytes` of host data into the next slot and enqueue the upload on
+// `stream`; the returned device pointer stays valid until the slot comes
+// round again, which first waits for the event recorded by release().
+int DescRing::upload(const void *src, size_t bytes, hipStream_t stream, void **dev, int *slot_id) {
+  if (bytes > slot_bytes) return fail(FRG_E_INVAL, "descriptor batch too large (%zu B)", bytes);
+  Slot &s = slots[next];
+  if (s.used) {
+    hipError_t e = hipEventSynchronize(s.done);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(ring)");
+  }
+  std::memcpy(s.host, src, bytes);
+  hipError_t e = hipMemcpyAsync(s.dev, s.host, bytes, hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(descriptors)");
+  *dev = s.dev;
+  *slot_id = next;
+  next = (next + 1) % (int)slots.size();
+  return FRG_OK;
+}
+
+int DescRing::release(int slot_id, hipStream_t stream) {
+  Slot &s = slots[slot_id];
+  hipError_t e = hipEventRecord(s.done, stream);
+  if (e != hipSuccess) return hip_fail(e, "hipEventRecord(ring)");
+  s.used = true;
+  return FRG_OK;
+}
+
+// ------------------------------------------------------------- tables --
+static uint64_t dbits(double x) {
+  uint64_t u;
+  std::memcpy(&u, &x, 8);
+  return u;
+}
+
+int Ctx::quad_table(const frg_quad &q, const double **dev, QuadTable *host_copy) {
+  auto key = std::make_tuple(q.d, q.reg, dbits(q.k), dbits(q.q_max), q.n_radial, q.n_angular);
+  auto it = qtabs.find(key);
+  if (it == qtabs.end()) {
+    QuadTable t = build_quad_table(q);
+    auto buf = std::make_unique<DevBuf>();
+    int rc = buf->reserve(t.data.size() * sizeof(double));
+    if (rc) return rc;
+    hipError_t e = hipMemcpy(buf->ptr, t.data.data(), t.data.size() * sizeof(double),
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "upload quadrature table");
+    QEntry ent;
+    ent.buf = std::move(buf);
+    ent.host = std::move(t);
+    it = qtabs.emplace(key, std::move(ent)).first;
+  }
+  *dev = (const double *)it->second.buf->ptr;
+  if (host_copy) *host_copy = it->second.host;
+  return FRG_OK;
+}
+
+int Ctx::lpa_table(int d, int reg, int n_r, double qmk, const double **dev, double *Cd) {
+  auto key = std::make_tuple(d, reg, n_r, dbits(qmk));
+  auto it = ltabs.find(key);
+  if (it == ltabs.end()) {
+    LpaTable t = build_lpa_table(d, reg, n_r, qmk);
+    auto buf = std::make_unique<DevBuf>();
+    int rc = buf->reserve(t.data.size() * sizeof(double));
+    if (rc) return rc;
+    hipError_t e = hipMemcpy(buf->ptr, t.data.data(), t.data.size() * sizeof(double),
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "upload LPA table");
+    LEntry ent;
+    ent.buf = std::move(buf);
+    ent.Cd = t.Cd;
+    it = ltabs.emplace(key, std::move(ent)).first;
+  }
+  *dev = (const double *)it->second.buf->ptr;
+  *Cd = it->second.Cd;
+  return FRG_OK;
+}
+
+// ------------------------------------------------------------ validation --
+int check_quad(const frg_quad &q) {
+  if (q.d < 3 || q.d > 8) return fail(FRG_E_INVAL, "quad.d=%d outside [3, 8]", q.d);
+  if (q.reg != FRG_REG_EXP && q.reg != FRG_REG_LITIM)
+    return fail(FRG_E_INVAL, "quad.reg=%d unknown", q.reg);
+  if (!(q.k > 0.0) || !std::isfinite(q.k)) return fail(FRG_E_INVAL, "quad.k must be > 0");
+  if (!(q.q_max > 0.0) || !std::isfinite(q.q_max))
+    return fail(FRG_E_INVAL, "quad.q_max must be > 0");
+  if (q.n_radial < 1 || q.n_radial > 1024)
+    return fail(FRG_E_INVAL, "quad.n_radial=%d outside [1, 1024]", q.n_radial);
+  if (q.n_angular < 1 || q.n_angular > 256)
+    return fail(FRG_E_INVAL, "quad.n_angular=%d outside [1, 256]", q.n_angular);
+  if (q.prec != FRG_PREC_FP64 && q.prec != FRG_PREC_FP32C)
+    return fail(FRG_E_INVAL, "quad.prec=%d unknown", q.prec);
+  if (q.reserved != 0) return fail(FRG_E_INVAL, "quad.reserved must be 0");
+  return FRG_OK;
+}
+
+int check_lpa(const frg_lpa &l) {
+  if (l.d < 2 || l.d > 8) return fail(FRG_E_INVAL, "lpa.d=%d outside [2, 8]", l.d);
+  if (l.N < 1) return fail(FRG_E_INVAL, "lpa.N must be >= 1");
+  if (l.reg != FRG_REG_EXP && l.reg != FRG_REG_LITIM) return fail(FRG_E_INVAL, "lpa.reg unknown");
+  if (l.n_radial < 1 || l.n_radial > 1024) return fail(FRG_E_INVAL, "lpa.n_radial outside [1, 1024]");
+  if (!(l.q_max_over_k > 0.0)) return fail(FRG_E_INVAL, "lpa.q_max_over_k must be > 0");
+  if (!(l.Lambda > 0.0)) return fail(FRG_E_INVAL, "lpa.Lambda must be > 0");
+  if (l.n_grid < 4 || l.n_grid > 65536) return fail(FRG_E_INVAL, "lpa.n_grid outside [4, 65536]");
+  if (!(l.rho_max > 0.0) || !std::isfinite(l.rho_max)) return fail(FRG_E_INVAL, "lpa.rho_max must be > 0");
+  return FRG_OK;
+}
+
+// ----------------------------------------------------------- integrate --
+static double set_cost(const frg_quad &q, int64_t pts) {
+  const double per = (q.reg == FRG_REG_EXP) ? 5.0 : 1.0;
+  return (double)pts * q.n_radial * q.n_angular * per;
+}
+
+int Ctx::make_setdev(const frg_set &s, SetDev *out) {
+  const double *tab;
+  int rc = quad_table(s.quad, &tab, nullptr);
+  if (rc) return rc;
+  QuadTable &h = qtabs[std::make_tuple(s.quad.d, s.quad.reg, dbits(s.quad.k), dbits(s.quad.q_max),
+                                       s.quad.n_radial, s.quad.n_angular)]
+                     .host;
+  SetDev d{};
+  d.p = s.p;
+  d.m2 = s.m2;
+  d.out = s.out;
+  d.err = s.err_est;
+  d.used64 = s.used_fp64;
+  d.tab = tab;
+  d.k2 = h.k2;
+  d.inv_k2 = h.inv_k2;
+  d.pref = h.pref;
+  d.n_ext = s.n_ext;
+  d.n_r = s.quad.n_radial;
+  d.n_a = s.quad.n_angular;
+  d.reg = s.quad.reg;
+  d.prec = s.quad.prec;
+  lane_split(d.n_r, d.n_a, &d.R, &d.J, &d.T, &d.U);
+  *out = d;
+  return FRG_OK;
+}
+
+// Device-side core: every pointer in `sets` is device memory.
+int Ctx::integrate_device(const frg_set *sets, int n_sets, int flags, hipStream_t st) {
+  std::vector<SetDev> sd(n_sets);
+  for (int i = 0; i < n_sets; ++i) {
+    int rc = make_setdev(sets[i], &sd[i]);
+    if (rc) return rc;
+  }
+  for (int i = 0; i < n_sets; ++i)
+    if (sd[i].prec == FRG_PREC_FP32C) return integrate_fp32c_sets(sd, flags, st);
+  if (!(flags & FRG_PERSISTENT)) {
+    for (int i = 0; i < n_sets; ++i) {
+      if (sd[i].n_ext == 0) continue;
+      int e = launch_points_plain(sd[i], tune.plain_tile, d_flag, st);
+      if (e) return hip_fail((hipError_t)e, "points_plain_kernel launch");
+    }
+    return FRG_OK;
+  }
+  return persistent(sd, sets, n_sets, flags, st);
+}
+
+// Work list: tiles of up to `tile` points, sorted longest-first.
+void build_tiles(const std::vector<SetDev> &sd, int tile, std::vector<Tile> *tiles) {
+  std::vector<std::pair<double, Tile>> tw;
+  for (int i = 0; i < (int)sd.size(); ++i) {
+    const double per = (sd[i].reg == FRG_REG_EXP ? 5.0 : 1.0) * sd[i].n_r * sd[i].n_a;
+    for (int64_t st = 0; st < sd[i].n_ext; st += tile) {
+      Tile t;
+      t.set = i;
+      t.start = st;
+      t.count = (int)std::min<int64_t>(tile, sd[i].n_ext - st);
+      tw.push_back({per * t.count, t});
+    }
+  }
+  std::stable_sort(tw.begin(), tw.end(),
+                   [](const auto &a, const auto &b) { return a.first > b.first; });
+  tiles->resize(tw.size());
+  for (size_t i = 0; i < tw.size(); ++i) (*tiles)[i] = tw[i].second;
+}
+
+int max_table_doubles(const std::vector<SetDev> &sd) {
+  int m = 0;
+  for (auto &s : sd) m = std::max(m, 3 * s.n_r + 2 * s.n_a);
+  return m;
+}
+
+uint64_t batch_signature(const frg_set *sets, int n_sets) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    h ^= v;
+    h *= 1099511628211ull;
+  };
+  mix((uint64_t)n_sets);
+  for (int i = 0; i < n_sets; ++i) {
+    const frg_set &s = sets[i];
+    mix((uint64_t)(uintptr_t)s.p);
+    mix((uint64_t)(uintptr_t)s.m2);
+    mix((uint64_t)(uintptr_t)s.out);
+    mix((uint64_t)(uintptr_t)s.err_est);
+    mix((uint64_t)(uintptr_t)s.used_fp64);
+    mix((uint64_t)s.n_ext);
+    mix((uint64_t)s.quad.d | ((uint64_t)s.quad.reg << 8) | ((uint64_t)s.quad.prec << 16));
+    mix(dbits(s.quad.k));
+    mix(dbits(s.quad.q_max));
+    mix((uint64_t)s.quad.n_radial << 32 | (uint64_t)s.quad.n_angular);
+  }
+  return h;
+}
+
+int Ctx::persistent(const std::vector<SetDev> &sd, const frg_set *sets, int n_sets, int flags,
+                    hipStream_t st) {
+  const bool graph = (flags & FRG_GRAPH) != 0;
+  const uint64_t sig = graph ? batch_signature(sets, n_sets) : 0;
+  if (graph) {
+    auto it = graphs.find(sig);
+    if (it != graphs.end()) {
+      hipError_t e = hipGraphLaunch(it->second->exec, st);
+      if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+      return FRG_OK;
+    }
+  }
+  std::vector<Tile> tiles;
+  build_tiles(sd, tune.persist_tile, &tiles);
+  if (tiles.empty()) return FRG_OK;
+  const int lds = max_table_doubles(sd);
+  if (lds * 8 > 64 * 1024) return fail(FRG_E_INVAL, "quadrature tables exceed 64 KiB of LDS");
+  const int n_blocks = std::max(1, std::min<int>((int)tiles.size(), n_cu * tune.persist_waves_per_cu));
+  if (graph) {
+    auto g = std::make_unique<GraphEntry>();
+    int rc = g->sets.reserve(sd.size() * sizeof(SetDev));
+    if (!rc) rc = g->tiles.reserve(tiles.size() * sizeof(Tile));
+    if (!rc) rc = g->counter.reserve(sizeof(int));
+    if (rc) return rc;
+    hipError_t e = hipMemcpy(g->sets.ptr, sd.data(), sd.size() * sizeof(SetDev), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(g->tiles.ptr, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "upload graph work list");
+    e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    int e1 = launch_reset_counter((int *)g->counter.ptr, cap_stream);
+    int e2 = launch_points_persistent((const SetDev *)g->sets.ptr, (const Tile *)g->tiles.ptr,
+                                      (int)tiles.size(), (int *)g->counter.ptr, lds, n_blocks,
+                                      d_flag, cap_stream);
+    hipGraph_t graph_h = nullptr;
+    e = hipStreamEndCapture(cap_stream, &graph_h);
+    if (e1 || e2 || e != hipSuccess) {
+      if (graph_h) hipGraphDestroy(graph_h);
+      return fail(FRG_E_DEVICE, "graph capture of the persistent launch failed");
+    }
+    e = hipGraphInstantiate(&g->exec, graph_h, nullptr, nullptr, 0);
+    hipGraphDestroy(graph_h);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    e = hipGraphLaunch(g->exec, st);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    graphs.emplace(sig, std::move(g));
+    return FRG_OK;
+  }
+  // eager persistent launch: descriptors through the ring
+  std::vector<char> blob(sd.size() * sizeof(SetDev) + tiles.size() * sizeof(Tile));
+  std::memcpy(blob.data(), sd.data(), sd.size() * sizeof(SetDev));
+  std::memcpy(blob.data() + sd.size() * sizeof(SetDev), tiles.data(), tiles.size() * sizeof(Tile));
+  void *dev;
+  int slot;
+  int rc = ring.upload(blob.data(), blob.size(), st, &dev, &slot);
+  if (rc) return rc;
+  const SetDev *d_sets = (const SetDev *)dev;
+  const Tile *d_tiles = (const Tile *)((char *)dev + sd.size() * sizeof(SetDev));
+  int e1 = launch_reset_counter(d_counter, st);
+  int e2 = launch_points_persistent(d_sets, d_tiles, (int)tiles.size(), d_counter, lds, n_blocks,
+                                    d_flag, st);
+  rc = ring.release(slot, st);
+  if (e1 || e2) return fail(FRG_E_DEVICE, "persistent launch failed");
+  return rc;
+}
+
+// Host-memory wrapper: stage inputs, run on the context stream, copy back.
+int Ctx::integrate_host(const frg_set *sets, int n_sets, int flags) {
+  size_t in_bytes = 0, out_bytes = 0, aux_bytes = 0;
+  for (int i = 0; i < n_sets; ++i) {
+    in_bytes += 2 * sets[i].n_ext * sizeof(double);
+    out_bytes += sets[i].n_ext * sizeof(double);
+    aux_bytes += sets[i].n_ext * (sizeof(double) + 1);
+  }
+  int rc = stage_in.reserve(in_bytes + 64);
+  if (!rc) rc = stage_out.reserve(out_bytes + aux_bytes + 64);
+  if (rc) return rc;
+  std::vector<frg_set> dsets(sets, sets + n_sets);
+  char *pin = (char *)stage_in.ptr;
+  char *pout = (char *)stage_out.ptr;
+  size_t oin = 0, oout = 0;
+  for (int i = 0; i < n_sets; ++i) {
+    const size_t nb = sets[i].n_ext * sizeof(double);
+    dsets[i].p = (const double *)(pin + oin);
+    hipMemcpyAsync(pin + oin, sets[i].p, nb, hipMemcpyHostToDevice, stream);
+    oin += nb;
+    dsets[i].m2 = (const double *)(pin + oin);
+    hipMemcpyAsync(pin + oin, sets[i].m2, nb, hipMemcpyHostToDevice, stream);
+    oin += nb;
+    dsets[i].out = (double *)(pout + oout);
+    oout += nb;
+    if (sets[i].err_est) {
+      dsets[i].err_est = (double *)(pout + oout);
+      oout += nb;
+    }
+    if (sets[i].used_fp64) {
+      dsets[i].used_fp64 = (uint8_t *)(pout + oout);
+      oout += sets[i].n_ext;
+      oout = (oout + 7) & ~(size_t)7;
+    }
+  }
+  hipMemsetAsync(d_flag, 0, sizeof(int), stream);
+  rc = integrate_device(dsets.data(), n_sets, flags & ~FRG_GRAPH, stream);
+  if (rc) {
+    hipStreamSynchronize(stream);
+    return rc;
+  }
+  for (int i = 0; i < n_sets; ++i) {
+    const size_t nb = sets[i].n_ext * sizeof(double);
+    hipMemcpyAsync(sets[i].out, dsets[i].out, nb, hipMemcpyDeviceToHost, stream);
+    if (sets[i].err_est) hipMemcpyAsync(sets[i].err_est, dsets[i].err_est, nb, hipMemcpyDeviceToHost, stream);
+    if (sets[i].used_fp64)
+      hipMemcpyAsync(sets[i].used_fp64, dsets[i].used_fp64, sets[i].n_ext, hipMemcpyDeviceToHost, stream);
+  }
+  int flag = 0;
+  hipMemcpyAsync(&flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, stream);
+  hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  if (flag) return fail(FRG_E_DOMAIN, "some points have m^2 + k^2 <= 0 (or p < 0); their results are NaN");
+  return FRG_OK;
+}
+
+// ---------------------------------------------------------------- grid --
+int Ctx::grid_device(const frg_quad &q, int64_t n_p, const double *p, int64_t n_m,
+                     const double *m2, double *out, double *err, uint8_t *used, hipStream_t st) {
+  if (q.prec == FRG_PREC_FP32C) return grid_fp32c(q, n_p, p, n_m, m2, out, err, used, st);
+  const double *tab;
+  QuadTable h;
+  int rc = quad_table(q, &tab, &h);
+  if (rc) return rc;
+  GridArgs g{};
+  g.p = p;
+  g.m2 = m2;
+  g.out = out;
+  g.err = err;
+  g.used64 = used;
+  g.tab = tab;
+  g.flag = d_flag;
+  g.k2 = h.k2;
+  g.inv_k2 = h.inv_k2;
+  g.pref = h.pref;
+  g.n_p = n_p;
+  g.n_m = n_m;
+  g.n_r = q.n_radial;
+  g.n_a = q.n_angular;
+  lane_split(g.n_r, g.n_a, &g.R, &g.J, &g.T, &g.U);
+  int M = tune.grid_M, W = tune.grid_W;
+  g.chunk = std::max(1, tune.grid_lds_rows);
+  if (grid_lds_bytes(g) > 64 * 1024) return fail(FRG_E_INVAL, "grid tables exceed 64 KiB of LDS");
+  g.n_mb = (int)((n_m + (int64_t)M * W - 1) / ((int64_t)M * W));
+  int e = launch_grid(g, q.reg, M, W, st);
+  if (e) return hip_fail((hipError_t)e, "grid_kernel launch");
+  return FRG_OK;
+}
+
+// ----------------------------------------------------------------- LPA --
+int Ctx::lpa_jobs(int n, const frg_lpa *lpa, const double *t, const double *const *U,
+                  double *const *dUdt, double *const *jac, int *flags_dev, hipStream_t st) {
+  std::vector<LpaJob> jobs(n);
+  std::vector<int64_t> start(n + 1);
+  int64_t total = 0;
+  for (int f = 0; f < n; ++f) {
+    const frg_lpa &l = lpa[f];
+    const double *tab;
+    double Cd;
+    int rc = lpa_table(l.d, l.reg, l.n_radial, l.q_max_over_k, &tab, &Cd);
+    if (rc) return rc;
+    const double k = l.Lambda * std::exp(t[f]);
+    LpaJob &j = jobs[f];
+    j.U = U[f];
+    j.dUdt = dUdt[f];
+    j.jac = jac ? jac[f] : nullptr;
+    j.tab = tab;
+    j.flag = flags_dev ? flags_dev + f : d_flag;
+    j.k2 = k * k;
+    j.inv_k2 = 1.0 / j.k2;
+    j.pre1 = Cd * std::pow(k, l.d);
+    j.pre2 = Cd * std::pow(k, l.d - 2);
+    j.dr = l.rho_max / (double)(l.n_grid - 1);
+    j.Nm1 = (double)(l.N - 1);
+    j.n = l.n_grid;
+    j.n_r = l.n_radial;
+    j.N = l.N;
+    start[f] = total;
+    total += l.n_grid;
+  }
+  start[n] = total;
+  const size_t jb = n * sizeof(LpaJob);
+  std::vector<char> blob(jb + (n + 1) * sizeof(int64_t));
+  std::memcpy(blob.data(), jobs.data(), jb);
+  std::memcpy(blob.data() + jb, start.data(), (n + 1) * sizeof(int64_t));
+  void *dev;
+  int slot;
+  int rc = ring.upload(blob.data(), blob.size(), st, &dev, &slot);
+  if (rc) return rc;
+  int e = launch_lpa((const LpaJob *)dev, (const int64_t *)((char *)dev + jb), n, total, st);
+  rc = ring.release(slot, st);
+  if (e) return hip_fail((hipError_t)e, "lpa_kernel launch");
+  return rc;
+}
+
+Context::~Context() {
+  if (server) stop_server();
+  if (stream) hipStreamSynchronize(stream);
+  for (auto &g : graphs)
+    if (g.second->exec) hipGraphExecDestroy(g.second->exec);
+  graphs.clear();
+  ring.destroy();
+  if (d_flag) hipFree(d_flag);
+  if (d_counter) hipFree(d_counter);
+  if (stream) hipStreamDestroy(stream);
+  if (cap_stream) hipStreamDestroy(cap_stream);
+}
+
+}  // namespace frg
+
+using namespace frg;
+
+// =================================================================== ABI ==
+extern "C" {
+
+const char *frg_last_error(void) { return g_err.c_str(); }
+
+const char *frg_version(void) { return "frg-mi355x 0.1 (gfx950)"; }
+
+int frg_create(frg_ctx **out, int hip_device, uint64_t hbm_budget_bytes) {
+  if (!out) return fail(FRG_E_INVAL, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev == 0) return fail(FRG_E_DEVICE, "no HIP device available");
+  if (hip_device < 0 || hip_device >= ndev) return fail(FRG_E_INVAL, "device %d out of range", hip_device);
+  e = hipSetDevice(hip_device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  auto c = std::make_unique<frg_ctx>();
+  c->device = hip_device;
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, hip_device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  c->n_cu = prop.multiProcessorCount;
+  c->arch = prop.gcnArchName;
+  if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return fail(FRG_E_DEVICE, "hipStreamCreate");
+  if (hipMalloc(&c->d_flag, sizeof(int)) != hipSuccess ||
+      hipMalloc(&c->d_counter, sizeof(int)) != hipSuccess)
+    return fail(FRG_E_NOMEM, "hipMalloc flags");
+  hipMemset(c->d_flag, 0, sizeof(int));
+  hipMemset(c->d_counter, 0, sizeof(int));
+  int rc = c->ring.init(1 << 20, 8);
+  if (rc) return rc;
+  size_t free_b = 0, total_b = 0;
+  hipMemGetInfo(&free_b, &total_b);
+  c->hbm_budget = hbm_budget_bytes ? hbm_budget_bytes : free_b / 2;
+  c->tune.load_env();
+  *out = c.release();
+  clear_error();
+  return FRG_OK;
+}
+
+void frg_destroy(frg_ctx *ctx) { delete ctx; }
+
+int frg_integrate(frg_ctx *ctx, const frg_set *sets, int32_t n_sets, int32_t mem, int32_t flags,
+                  void *hip_stream) {
+  if (!ctx) return fail(FRG_E_INVAL, "ctx is NULL");
+  if (n_sets < 0 || (n_sets > 0 && !sets)) return fail(FRG_E_INVAL, "bad set array");
+  if (mem != FRG_MEM_HOST && mem != FRG_MEM_DEVICE) return fail(FRG_E_INVAL, "mem must be FRG_MEM_HOST or FRG_MEM_DEVICE");
+  if (flags & ~(FRG_PERSISTENT | FRG_GRAPH)) return fail(FRG_E_INVAL, "unknown flags 0x%x", flags);
+  if ((flags & FRG_GRAPH) && !(flags & FRG_PERSISTENT)) return fail(FRG_E_INVAL, "FRG_GRAPH needs FRG_PERSISTENT");
+  for (int i = 0; i < n_sets; ++i) {
+    const frg_set &s = sets[i];
+    int rc = check_quad(s.quad);
+    if (rc) return rc;
+    if (s.n_ext < 0) return fail(FRG_E_INVAL, "set %d: n_ext < 0", i);
+    if (s.n_ext > 0 && (!s.p || !s.m2 || !s.out)) return fail(FRG_E_INVAL, "set %d: NULL array", i);
+    if (s.n_ext > ((int64_t)1 << 40)) return fail(FRG_E_INVAL, "set %d: n_ext too large", i);
+    if (mem == FRG_MEM_HOST)
+      for (int64_t e = 0; e < s.n_ext; ++e)
+        if (!(s.p[e] >= 0.0) || !std::isfinite(s.p[e]) || std::isnan(s.m2[e]))
+          return fail(FRG_E_INVAL, "set %d point %lld: p must be finite and >= 0, m2 not NaN", i,
+                      (long long)e);
+  }
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  hipSetDevice(ctx->device);
+  clear_error();
+  if (mem == FRG_MEM_HOST) return ctx->integrate_host(sets, n_sets, flags);
+  return ctx->integrate_device(sets, n_sets, flags, (hipStream_t)hip_stream);
+}
+
+int frg_integrate_grid(frg_ctx *ctx, const frg_quad *quad, int64_t n_p, const double *p,
+                       int64_t n_m, const double *m2, double *out, double *err_est,
+                       uint8_t *used_fp64, int32_t mem, void *hip_stream) {
+  if (!ctx || !quad) return fail(FRG_E_INVAL, "NULL argument");
+  int rc = check_quad(*quad);
+  if (rc) return rc;
+  if (n_p < 0 || n_m < 0) return fail(FRG_E_INVAL, "negative size");
+  if (n_p * n_m > 0 && (!p || !m2 || !out)) return fail(FRG_E_INVAL, "NULL array");
+  if (n_p > ((int64_t)1 << 30) || n_m > ((int64_t)1 << 30)) return fail(FRG_E_INVAL, "grid too large");
+  if (mem != FRG_MEM_HOST && mem != FRG_MEM_DEVICE) return fail(FRG_E_INVAL, "bad mem");
+  if (n_p == 0 || n_m == 0) return FRG_OK;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  hipSetDevice(ctx->device);
+  clear_error();
+  if (mem == FRG_MEM_DEVICE)
+    return ctx->grid_device(*quad, n_p, p, n_m, m2, out, err_est, used_fp64, (hipStream_t)hip_stream);
+  for (int64_t a = 0; a < n_p; ++a)
+    if (!(p[a] >= 0.0) || !std::isfinite(p[a])) return fail(FRG_E_INVAL, "p[%lld] must be finite and >= 0", (long long)a);
+  const size_t nout = (size_t)(n_p * n_m);
+  rc = ctx->stage_in.reserve((n_p + n_m) * sizeof(double) + 64);
+  if (!rc) rc = ctx->stage_out.reserve(nout * (2 * sizeof(double) + 1) + 64);
+  if (rc) return rc;
+  double *dp = (double *)ctx->stage_in.ptr, *dm = dp + n_p;
+  double *dout = (double *)ctx->stage_out.ptr, *derr = dout + nout;
+  uint8_t *dused = (uint8_t *)(derr + nout);
+  hipStream_t st = ctx->stream;
+  hipMemcpyAsync(dp, p, n_p * sizeof(double), hipMemcpyHostToDevice, st);
+  hipMemcpyAsync(dm, m2, n_m * sizeof(double), hipMemcpyHostToDevice, st);
+  hipMemsetAsync(ctx->d_flag, 0, sizeof(int), st);
+  rc = ctx->grid_device(*quad, n_p, dp, n_m, dm, dout, err_est ? derr : nullptr,
+                        used_fp64 ? dused : nullptr, st);
+  if (rc) {
+    hipStreamSynchronize(st);
+    return rc;
+  }
+  hipMemcpyAsync(out, dout, nout * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (err_est) hipMemcpyAsync(err_est, derr, nout * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (used_fp64) hipMemcpyAsync(used_fp64, dused, nout, hipMemcpyDeviceToHost, st);
+  int flag = 0;
+  hipMemcpyAsync(&flag, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, st);
+  hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  if (flag) return fail(FRG_E_DOMAIN, "some masses have m^2 + k^2 <= 0; their results are NaN");
+  return FRG_OK;
+}
+
+int frg_flow_rhs(frg_ctx *ctx, const frg_lpa *lpa, double t, const double *U, double *dUdt,
+                 double *jac_bands, int32_t mem, void *hip_stream) {
+  if (!ctx || !lpa || !U || !dUdt) return fail(FRG_E_INVAL, "NULL argument");
+  int rc = check_lpa(*lpa);
+  if (rc) return rc;
+  if (!std::isfinite(t)) return fail(FRG_E_INVAL, "t must be finite");
+  if (mem != FRG_MEM_HOST && mem != FRG_MEM_DEVICE) return fail(FRG_E_INVAL, "bad mem");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  hipSetDevice(ctx->device);
+  clear_error();
+  if (mem == FRG_MEM_DEVICE) {
+    const double *Up[1] = {U};
+    double *Dp[1] = {dUdt};
+    double *Jp[1] = {jac_bands};
+    return ctx->lpa_jobs(1, lpa, &t, Up, Dp, Jp, nullptr, (hipStream_t)hip_stream);
+  }
+  const int64_t n = lpa->n_grid;
+  rc = ctx->stage_in.reserve(n * sizeof(double));
+  if (!rc) rc = ctx->stage_out.reserve(8 * n * sizeof(double));
+  if (rc) return rc;
+  hipStream_t st = ctx->stream;
+  double *dU = (double *)ctx->stage_in.ptr;
+  double *dD = (double *)ctx->stage_out.ptr;
+  double *dJ = dD + n;
+  hipMemcpyAsync(dU, U, n * sizeof(double), hipMemcpyHostToDevice, st);
+  hipMemsetAsync(ctx->d_flag, 0, sizeof(int), st);
+  const double *Up[1] = {dU};
+  double *Dp[1] = {dD};
+  double *Jp[1] = {jac_bands ? dJ : nullptr};
+  rc = ctx->lpa_jobs(1, lpa, &t, Up, Dp, Jp, nullptr, st);
+  if (rc) {
+    hipStreamSynchronize(st);
+    return rc;
+  }
+  hipMemcpyAsync(dUdt, dD, n * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (jac_bands) hipMemcpyAsync(jac_bands, dJ, 7 * n * sizeof(double), hipMemcpyDeviceToHost, st);
+  int flag = 0;
+  hipMemcpyAsync(&flag, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, st);
+  hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  if (flag) return fail(FRG_E_DOMAIN, "a mass reached m^2 + k^2 <= 0");
+  return FRG_OK;
+}
+
+int frg_flow_rhs_batch(frg_ctx *ctx, int32_t n_flows, const frg_lpa *lpa, const double *t,
+                       const double *const *U, double *const *dUdt, double *const *jac_bands,
+                       void *hip_stream) {
+  if (!ctx || n_flows < 0) return fail(FRG_E_INVAL, "bad arguments");
+  if (n_flows == 0) return FRG_OK;
+  if (!lpa || !t || !U || !dUdt) return fail(FRG_E_INVAL, "NULL argument");
+  for (int f = 0; f < n_flows; ++f) {
+    int rc = check_lpa(lpa[f]);
+    if (rc) return rc;
+    if (!U[f] || !dUdt[f]) return fail(FRG_E_INVAL, "flow %d: NULL buffer", f);
+  }
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  hipSetDevice(ctx->device);
+  clear_error();
+  return ctx->lpa_jobs(n_flows, lpa, t, U, dUdt, jac_bands, nullptr, (hipStream_t)hip_stream);
+}
+
+int frg_gauss_legendre(int32_t n, double *x, double *w) {
+  int rc = gauss_legendre_gw(n, x, w);
+  if (rc) return fail(rc, "n must be in [1, 4096] and x, w non-NULL");
+  return FRG_OK;
+}
+
+int64_t frg_flow_footprint(const frg_lpa *lpa) {
+  if (!lpa || lpa->n_grid < 1) return -1;
+  // U, dUdt and 7 Jacobian bands resident per flow, plus a 4 KiB descriptor share
+  return (int64_t)(9 * lpa->n_grid * sizeof(double)) + 4096;
+}
+
+}  // extern "C"

@@ -1,0 +1,124 @@
+// The context object behind the opaque frg_ctx handle (host side only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "frg_internal.h"
+
+namespace frg {
+
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+void clear_error();
+double now_s();
+int check_quad(const frg_quad &q);
+int check_lpa(const frg_lpa &l);
+void build_tiles(const std::vector<SetDev> &sd, int tile, std::vector<Tile> *tiles);
+int max_table_doubles(const std::vector<SetDev> &sd);
+
+// Grow-only device allocation.
+struct DevBuf {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf();
+  int reserve(size_t b);
+  void release();
+};
+
+// Pinned host + device slots for per-launch descriptor uploads.
+struct DescRing {
+  struct Slot {
+    void *host = nullptr;
+    void *dev = nullptr;
+    hipEvent_t done = nullptr;
+    bool used = false;
+  };
+  std::vector<Slot> slots;
+  size_t slot_bytes = 0;
+  int next = 0;
+  int init(size_t slot_bytes, int n_slots);
+  void destroy();
+  int upload(const void *src, size_t bytes, hipStream_t stream, void **dev, int *slot_id);
+  int release(int slot_id, hipStream_t stream);
+};
+
+// Launch-shape parameters (defaults; the autotuner overwrites them).
+struct Tune {
+  int plain_tile = 8;            // points per wave, plain launches
+  int persist_tile = 8;          // points per tile, persistent launches
+  int persist_waves_per_cu = 16; // resident one-wave workgroups per CU
+  int grid_M = 16;               // masses per wave, tensor-grid kernel
+  int grid_W = 4;                // waves per workgroup, tensor-grid kernel
+  int grid_lds_rows = 64;        // (t, u) rows of 64 doubles staged per chunk
+  int fp32_M = 16;
+  void load_env();
+};
+
+struct GraphEntry {
+  DevBuf sets, tiles, counter;
+  hipGraphExec_t exec = nullptr;
+};
+
+struct Server;
+
+struct Context {
+  int device = 0;
+  int n_cu = 256;
+  std::string arch;
+  hipStream_t stream = nullptr;      // host-memory calls
+  hipStream_t cap_stream = nullptr;  // graph capture
+  std::mutex mu;
+  int *d_flag = nullptr;
+  int *d_counter = nullptr;
+  frg::DescRing ring;
+  frg::DevBuf stage_in, stage_out;
+  frg::Tune tune;
+  uint64_t hbm_budget = 0;
+
+  struct QEntry {
+    std::unique_ptr<frg::DevBuf> buf;
+    frg::QuadTable host;
+  };
+  struct LEntry {
+    std::unique_ptr<frg::DevBuf> buf;
+    double Cd = 0.0;
+  };
+  std::map<std::tuple<int, int, uint64_t, uint64_t, int, int>, QEntry> qtabs;
+  std::map<std::tuple<int, int, int, uint64_t>, LEntry> ltabs;
+  std::map<uint64_t, std::unique_ptr<frg::GraphEntry>> graphs;
+  frg::Server *server = nullptr;
+
+  virtual ~Context();
+  int quad_table(const frg_quad &q, const double **dev, frg::QuadTable *host_copy);
+  int lpa_table(int d, int reg, int n_r, double qmk, const double **dev, double *Cd);
+  int make_setdev(const frg_set &s, frg::SetDev *out);
+  int integrate_device(const frg_set *sets, int n_sets, int flags, hipStream_t st);
+  int integrate_host(const frg_set *sets, int n_sets, int flags);
+  int persistent(const std::vector<frg::SetDev> &sd, const frg_set *sets, int n_sets, int flags,
+                 hipStream_t st);
+  int integrate_fp32c_sets(const std::vector<frg::SetDev> &sd, int flags, hipStream_t st);
+  int grid_device(const frg_quad &q, int64_t n_p, const double *p, int64_t n_m, const double *m2,
+                  double *out, double *err, uint8_t *used, hipStream_t st);
+  int grid_fp32c(const frg_quad &q, int64_t n_p, const double *p, int64_t n_m, const double *m2,
+                 double *out, double *err, uint8_t *used, hipStream_t st);
+  int lpa_jobs(int n, const frg_lpa *lpa, const double *t, const double *const *U,
+               double *const *dUdt, double *const *jac, int *flags_dev, hipStream_t st);
+  void stop_server();
+};
+
+using Ctx = Context;
+
+}  // namespace frg
+
+// The opaque handle of the C ABI.
+struct frg_ctx : frg::Context {};

@@ -1,0 +1,111 @@
+// Internal declarations shared by the host and device translation units of
+// libfrg.  Nothing here is part of the public ABI (include/frg.h).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "frg.h"
+
+namespace frg {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- tables --
+// Gauss-Legendre rule on [-1, 1] (ascending nodes) by Golub-Welsch.
+int gauss_legendre_gw(int n, double *x, double *w);
+
+// Packed quadrature table of one (d, reg, k, q_max, n_r, n_a) key, float64:
+//   [0, n_r)          q_i               radial node
+//   [n_r, 2n_r)       c_i               w_i q_i^{d-1} d_tR(q_i^2)
+//   [2n_r, 3n_r)      Hq_i              k^2 h(q_i^2/k^2)   (stable denominator part)
+//   [3n_r, 3n_r+n_a)  opx_j             1 + x_j
+//   [.., +n_a)        mu_j              v_j (1 - x_j^2)^{(d-3)/2}
+struct QuadTable {
+  std::vector<double> data;
+  double k2, inv_k2, pref;  // pref = P_d
+  int n_r, n_a;
+};
+QuadTable build_quad_table(const frg_quad &q);
+
+// Scale-free radial table for the LPA threshold functions (unit k):
+//   [0, n_r)       chat_i = what_i qhat_i^{d-1} 2 beta(y) beta(-y)   (exp)
+//                          = what_i qhat_i^{d-1} 2                    (Litim)
+//   [n_r, 2n_r)    hhat_i = h(qhat_i^2)
+// so that F_n(m^2) = C_d k^{d+2-2n} sum_i chat_i / (hhat_i + delta/k^2)^n.
+struct LpaTable {
+  std::vector<double> data;
+  double Cd;
+  int n_r;
+};
+LpaTable build_lpa_table(int d, int reg, int n_r, double q_max_over_k);
+
+double omega_sphere(int n);  // area of S^{n-1}
+double h_exp_host(double y);
+double dtR_over_k2_host(int reg, double y);  // d_tR / k^2 at y = s/k^2
+
+// ---------------------------------------------------------- device structs --
+struct SetDev {
+  const double *p;
+  const double *m2;
+  double *out;
+  double *err;
+  uint8_t *used64;
+  const double *tab;  // device copy of QuadTable::data
+  double k2, inv_k2, pref;
+  int64_t n_ext;
+  int32_t n_r, n_a, reg, prec;
+  int32_t R, J;  // lanes along radial / angular nodes, R * J = 64
+  int32_t T, U;  // ceil(n_r / R), ceil(n_a / J)
+};
+
+struct Tile {
+  int32_t set;
+  int32_t count;
+  int64_t start;
+};
+
+struct GridArgs {
+  const double *p;
+  const double *m2;
+  double *out;
+  double *err;
+  uint8_t *used64;
+  const double *tab;
+  int *flag;
+  double k2, inv_k2, pref;
+  int64_t n_p, n_m;
+  int32_t n_r, n_a, R, J, T, U;
+  int32_t n_mb;   // mass blocks per momentum
+  int32_t chunk;  // (t, u) rows of the Hk table held in LDS at once
+};
+
+struct LpaJob {
+  const double *U;
+  double *dUdt;
+  double *jac;      // may be null
+  const double *tab;  // LpaTable::data on the device
+  int *flag;        // set to 1 on a domain violation (may be null)
+  double k2, inv_k2;
+  double pre1, pre2;  // C_d k^d, C_d k^{d-2}
+  double dr, Nm1;
+  int64_t n;
+  int32_t n_r, N;
+};
+
+void lane_split(int n_r, int n_a, int *R, int *J, int *T, int *U);
+
+// -------------------------------------------------------------- launchers --
+// All return hipError_t as int (0 = success).
+int launch_points_plain(const SetDev &s, int tile_points, int *d_flag, void *stream);
+int launch_points_persistent(const SetDev *d_sets, const Tile *d_tiles, int n_tiles,
+                             int *d_counter, int lds_doubles, int n_blocks, int *d_flag,
+                             void *stream);
+int launch_reset_counter(int *d_counter, void *stream);
+int launch_grid(const GridArgs &g, int reg, int M, int W, void *stream);
+int grid_lds_bytes(const GridArgs &g);
+int launch_lpa(const LpaJob *d_jobs, const int64_t *d_start, int n_jobs, int64_t total_points,
+               void *stream);
+
+}  // namespace frg

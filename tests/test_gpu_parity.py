@@ -1,0 +1,329 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+FP64 bar: 1e-12 relative, element by element.  The oracle sums in natural
+order with an 80-bit accumulator and uses glibc expm1 / IEEE division; the
+kernels use a different association (per-lane partial sums, xor butterfly),
+OCML expm1 and a Newton-refined hardware reciprocal.  Every term is positive,
+so the relative difference is bounded by a few ulp per term: ~1e-15 in
+practice, far inside 1e-12.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2607_24908_amd import frg, workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    h = frg.frg_create(0)
+    yield h
+    torch.cuda.synchronize()
+    frg.frg_destroy(h)
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+def quad_of(q, prec=frg.FRG_PREC_FP64):
+    return frg.make_quad(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a, prec)
+
+
+def relerr(got, want):
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    return np.abs(got - want) / np.abs(want)
+
+
+def run_grid(ctx, quad, p, m2):
+    P, M = dev(p), dev(m2)
+    out = torch.full((P.numel() * M.numel(),), float("nan"), dtype=torch.float64, device="cuda")
+    frg.frg_integrate_grid(ctx, quad, P, M, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def run_points(ctx, quad, p, m2, flags=frg.FRG_PLAIN):
+    P, M = dev(p), dev(m2)
+    out = torch.full((P.numel(),), float("nan"), dtype=torch.float64, device="cuda")
+    frg.frg_integrate(ctx, [dict(quad=quad, p=P, m2=M, out=out)], flags=flags)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+# ---------------------------------------------------------- plain d = 4 --
+
+def test_plain_d4_grid_all_2048(ctx):
+    w = workloads.plain_d4()
+    print(f"[case] {w.name}", flush=True)
+    got = run_grid(ctx, quad_of(w.quad), w.p, w.m2)
+    q = w.quad
+    want = oracle.integrate_grid(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a, w.p, w.m2).ravel()
+    err = relerr(got, want)
+    print(f"plain_d4 grid: max rel err {err.max():.3e}, median {np.median(err):.3e}")
+    assert err.max() < RTOL
+
+
+def test_plain_d4_points_all_launch_forms_bitwise(ctx):
+    """Point-list kernel (plain, persistent, graph replays) gives the same
+    bits as the tensor-grid kernel: one summation order per (n_r, n_a)."""
+    w = workloads.plain_d4()
+    quad = quad_of(w.quad)
+    grid = run_grid(ctx, quad, w.p, w.m2)
+    P = np.repeat(w.p, w.m2.size)
+    M = np.tile(w.m2, w.p.size)
+    plain = run_points(ctx, quad, P, M, frg.FRG_PLAIN)
+    pers = run_points(ctx, quad, P, M, frg.FRG_PERSISTENT)
+    assert np.array_equal(plain, grid)
+    assert np.array_equal(pers, grid)
+    # graph: same buffers, replayed with eager work in between
+    Pd, Md = dev(P), dev(M)
+    out = torch.zeros(P.size, dtype=torch.float64, device="cuda")
+    sets = [dict(quad=quad, p=Pd, m2=Md, out=out)]
+    for rep in range(4):
+        out.zero_()
+        frg.frg_integrate(ctx, sets, flags=frg.FRG_PERSISTENT | frg.FRG_GRAPH)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), grid), f"graph replay {rep}"
+        _ = run_points(ctx, quad, P[:100], M[:100])
+
+
+# --------------------------------------------------------- ragged shapes --
+
+SHAPES = [(100, 12, 3, frg.FRG_REG_EXP), (7, 3, 4, frg.FRG_REG_LITIM), (33, 5, 5, frg.FRG_REG_EXP),
+          (256, 32, 3, frg.FRG_REG_LITIM), (1, 1, 3, frg.FRG_REG_EXP), (64, 1, 4, frg.FRG_REG_EXP),
+          (129, 17, 4, frg.FRG_REG_EXP), (32, 256, 3, frg.FRG_REG_EXP)]
+
+
+@pytest.mark.parametrize("n_r,n_a,d,reg", SHAPES)
+def test_ragged_shapes_grid_and_points(ctx, n_r, n_a, d, reg):
+    print(f"[case] ragged n_r={n_r} n_a={n_a} d={d} reg={reg}", flush=True)
+    rng = np.random.Generator(np.random.PCG64(n_r * 1000 + n_a))
+    k = 0.8
+    p = np.concatenate([[0.0, 1e-9], 10 ** rng.uniform(-3, 1.3, 35)])
+    m2 = np.concatenate([[-k * k + 1e-7, -k * k + 1e-3, 0.0],
+                         rng.uniform(-0.95 * k * k, 8.0, 50)])
+    quad = frg.make_quad(d, reg, k, 6 * k, n_r, n_a)
+    got = run_grid(ctx, quad, p, m2)
+    want = oracle.integrate_grid(d, reg, k, 6 * k, n_r, n_a, p, m2).ravel()
+    err = relerr(got, want)
+    assert err.max() < RTOL, err.max()
+    P = np.repeat(p, m2.size)
+    M = np.tile(m2, p.size)
+    pts = run_points(ctx, quad, P, M)
+    assert np.array_equal(pts, got)
+
+
+# ------------------------------------------------------- scale-up d = 3 --
+
+@pytest.fixture(scope="module")
+def scaleup(ctx):
+    w = workloads.scaleup_d3()
+    print(f"[case] {w.name}", flush=True)
+    got = run_grid(ctx, quad_of(w.quad), w.p, w.m2).reshape(w.p.size, w.m2.size)
+    return w, got
+
+
+def test_scaleup_d3_sampled_outputs(scaleup):
+    w, got = scaleup
+    q = w.quad
+    rng = np.random.Generator(np.random.PCG64(7))
+    ia = rng.integers(0, w.p.size, 3000)
+    ib = rng.integers(0, w.m2.size, 3000)
+    # always include the corners and the extreme masses
+    ia = np.concatenate([ia, [0, 0, w.p.size - 1, w.p.size - 1]])
+    ib = np.concatenate([ib, [0, w.m2.size - 1, 0, w.m2.size - 1]])
+    want = oracle.integrate(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a, w.p[ia], w.m2[ib], threads=8)
+    err = relerr(got[ia, ib], want)
+    print(f"scaleup sampled: max rel err {err.max():.3e}")
+    assert err.max() < RTOL
+
+
+def test_scaleup_d3_properties(scaleup):
+    """At any size: every result finite and positive, strictly decreasing in m^2."""
+    w, got = scaleup
+    assert np.all(np.isfinite(got)) and np.all(got > 0)
+    assert np.all(np.diff(got, axis=1) < 0)
+
+
+def test_scaleup_litim_p0_closed_form(ctx):
+    w = workloads.scaleup_d3_litim_p0()
+    got = run_grid(ctx, quad_of(w.quad), w.p, w.m2)
+    delta = w.m2 + 1.0
+    want = 1.0 / (3 * math.pi ** 2 * delta ** 3)
+    err = relerr(got, want)
+    print(f"Litim p=0 closed form: max rel err {err.max():.3e}")
+    assert err.max() < RTOL
+
+
+# --------------------------------------------------------- uneven sets --
+
+def _sets_on_device(sets):
+    out = []
+    for s in sets:
+        out.append(dict(quad=quad_of(s.quad), p=dev(s.p), m2=dev(s.m2),
+                        out=torch.full((s.p.size,), float("nan"), dtype=torch.float64,
+                                       device="cuda")))
+    return out
+
+
+def test_uneven_sets_all_points(ctx):
+    sets = workloads.uneven_sets(seed=0)
+    print(f"[case] uneven_sets seed=0 n_sets={len(sets)}", flush=True)
+    ds = _sets_on_device(sets)
+    frg.frg_integrate(ctx, ds, flags=frg.FRG_PERSISTENT)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for s, d in zip(sets, ds):
+        q = s.quad
+        want = oracle.integrate(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a, s.p, s.m2, threads=8)
+        worst = max(worst, relerr(d["out"].cpu().numpy(), want).max())
+    print(f"uneven sets: max rel err {worst:.3e}")
+    assert worst < RTOL
+
+
+def test_uneven_sets_batched_equals_plain_bitwise(ctx):
+    sets = workloads.uneven_sets(seed=1, n_sets=64)
+    a = _sets_on_device(sets)
+    b = _sets_on_device(sets)
+    frg.frg_integrate(ctx, a, flags=frg.FRG_PLAIN)
+    for rep in range(3):
+        for d in b:
+            d["out"].zero_()
+        frg.frg_integrate(ctx, b, flags=frg.FRG_PERSISTENT | frg.FRG_GRAPH)
+        torch.cuda.synchronize()
+        for x, y in zip(a, b):
+            assert torch.equal(x["out"], y["out"]), f"replay {rep}"
+
+
+# ------------------------------------------------------ host memory, edges --
+
+def test_host_memory_equals_device(ctx):
+    w = workloads.plain_d4()
+    quad = quad_of(w.quad)
+    P = np.repeat(w.p, w.m2.size)
+    M = np.tile(w.m2, w.p.size)
+    out = np.full(P.size, np.nan)
+    frg.frg_integrate(ctx, [dict(quad=quad, p=P, m2=M, out=out)], mem=frg.FRG_MEM_HOST)
+    assert np.array_equal(out, run_points(ctx, quad, P, M))
+    g = np.full(P.size, np.nan)
+    frg.frg_integrate_grid(ctx, quad, w.p, w.m2, g, mem=frg.FRG_MEM_HOST)
+    assert np.array_equal(g, out)
+
+
+def test_domain_violation_nan_and_status(ctx):
+    quad = frg.make_quad(3, frg.FRG_REG_EXP, 1.0, 6.0, 32, 8)
+    p = np.array([0.5, 0.5, 0.5, 0.5])
+    m2 = np.array([0.1, -1.0, -2.0, 0.3])
+    out = np.zeros(4)
+    rc = frg.frg_integrate(ctx, [dict(quad=quad, p=p, m2=m2, out=out)], mem=frg.FRG_MEM_HOST,
+                           allow_domain=True)
+    assert rc == frg.FRG_E_DOMAIN
+    assert np.isnan(out[1]) and np.isnan(out[2])
+    want = oracle.integrate(3, 0, 1.0, 6.0, 32, 8, p[[0, 3]], m2[[0, 3]])
+    assert relerr(out[[0, 3]], want).max() < RTOL
+    g = np.zeros(4)
+    rc = frg.frg_integrate_grid(ctx, quad, p[:1], m2, g, mem=frg.FRG_MEM_HOST, allow_domain=True)
+    assert rc == frg.FRG_E_DOMAIN and np.isnan(g[1]) and np.isfinite(g[0])
+
+
+def test_empty_inputs_and_bad_arguments(ctx):
+    quad = frg.make_quad(3, frg.FRG_REG_EXP, 1.0, 6.0, 32, 8)
+    e = np.zeros(0)
+    assert frg.frg_integrate(ctx, [dict(quad=quad, p=e, m2=e, out=e)], mem=frg.FRG_MEM_HOST) == 0
+    assert frg.frg_integrate(ctx, [], mem=frg.FRG_MEM_HOST) == 0
+    bad = frg.make_quad(2, frg.FRG_REG_EXP, 1.0, 6.0, 32, 8)
+    with pytest.raises(frg.FrgError) as ei:
+        frg.frg_integrate(ctx, [dict(quad=bad, p=np.ones(2), m2=np.ones(2), out=np.ones(2))],
+                          mem=frg.FRG_MEM_HOST)
+    assert ei.value.code == frg.FRG_E_INVAL
+    with pytest.raises(frg.FrgError):
+        frg.frg_integrate(ctx, [dict(quad=quad, p=-np.ones(2), m2=np.ones(2), out=np.ones(2))],
+                          mem=frg.FRG_MEM_HOST)
+
+
+def test_maximum_orders(ctx):
+    """Largest supported rule sizes: n_r = 1024 (point kernel), n_a = 256."""
+    quad = frg.make_quad(4, frg.FRG_REG_EXP, 1.0, 6.0, 1024, 8)
+    p = np.array([0.3, 2.0])
+    m2 = np.array([-0.5, 1.0])
+    got = run_points(ctx, quad, p, m2)
+    want = oracle.integrate(4, 0, 1.0, 6.0, 1024, 8, p, m2)
+    assert relerr(got, want).max() < RTOL
+    quad = frg.make_quad(3, frg.FRG_REG_EXP, 1.0, 6.0, 64, 256)
+    got = run_points(ctx, quad, p, m2)
+    want = oracle.integrate(3, 0, 1.0, 6.0, 64, 256, p, m2)
+    assert relerr(got, want).max() < RTOL
+
+
+# ------------------------------------------------------------------- LPA --
+
+def lpa_state(n, lam, rho0, wiggle, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rho = np.arange(n) * (0.5 / (n - 1))
+    return (lam / 8) * (rho - rho0) ** 2 + wiggle * np.sin(rng.uniform(3, 9) * rho)
+
+
+@pytest.mark.parametrize("n", [4, 5, 128, 1000])
+@pytest.mark.parametrize("N,reg", [(1, frg.FRG_REG_EXP), (2, frg.FRG_REG_LITIM), (4, frg.FRG_REG_EXP)])
+def test_lpa_rhs_matches_oracle(ctx, n, N, reg):
+    print(f"[case] lpa n={n} N={N} reg={reg}", flush=True)
+    for t in (0.0, -1.3):
+        k = math.exp(t)
+        U = lpa_state(n, 3.0, 0.02, 0.001, n + N)
+        lpa = frg.make_lpa(d=3, N=N, reg=reg, n_radial=64, n_grid=n)
+        dU = np.zeros(n)
+        jac = np.zeros(7 * n)
+        frg.frg_flow_rhs(ctx, lpa, t, U, dU, jac, mem=frg.FRG_MEM_HOST)
+        wdU, wjac, rc = oracle.lpa_rhs(3, N, reg, 64, 6.0, k, 0.5, U)
+        assert rc == 0
+        assert relerr(dU, wdU).max() < RTOL
+        wj = wjac.ravel()
+        scale = np.max(np.abs(wj))
+        assert np.max(np.abs(jac - wj)) < RTOL * scale
+        nz = wj != 0
+        assert relerr(jac[nz], wj[nz]).max() < 1e-10
+
+
+def test_lpa_rhs_domain(ctx):
+    n = 16
+    U = lpa_state(n, 12.0, 0.15, 0.0, 1)  # U'(0) = -0.45
+    lpa = frg.make_lpa(d=3, N=2, n_grid=n)
+    dU = np.zeros(n)
+    rc = frg.frg_flow_rhs(ctx, lpa, -0.5, U, dU, None, mem=frg.FRG_MEM_HOST, allow_domain=True)
+    assert rc == frg.FRG_E_DOMAIN  # k^2 = e^-1 < 0.45 at rho = 0
+    assert np.isnan(dU[0]) and np.all(np.isfinite(dU[-3:]))
+
+
+def test_lpa_batch_equals_single_bitwise(ctx):
+    shapes = [(128, 1, 0.0), (300, 2, -0.4), (1024, 4, -1.1), (77, 2, -2.0), (4, 1, -0.1)]
+    lpas, ts, Us, Ds, Js, singles = [], [], [], [], [], []
+    for i, (n, N, t) in enumerate(shapes):
+        U = lpa_state(n, 2.0 + i, 0.01 * i, 0.0005, i)
+        lpas.append(frg.make_lpa(d=3, N=N, n_grid=n))
+        ts.append(t)
+        Us.append(dev(U))
+        Ds.append(torch.zeros(n, dtype=torch.float64, device="cuda"))
+        Js.append(torch.zeros(7 * n, dtype=torch.float64, device="cuda"))
+        d1 = torch.zeros(n, dtype=torch.float64, device="cuda")
+        j1 = torch.zeros(7 * n, dtype=torch.float64, device="cuda")
+        frg.frg_flow_rhs(ctx, lpas[-1], t, Us[-1], d1, j1)
+        singles.append((d1, j1))
+    frg.frg_flow_rhs_batch(ctx, lpas, ts, Us, Ds, Js)
+    torch.cuda.synchronize()
+    # the (77, N=2, t=-2) flow is past the pole at small rho: NaN there in both
+    n_nan = 0
+    for (d1, j1), d, j in zip(singles, Ds, Js):
+        assert np.array_equal(d1.cpu().numpy(), d.cpu().numpy(), equal_nan=True)
+        assert np.array_equal(j1.cpu().numpy(), j.cpu().numpy(), equal_nan=True)
+        n_nan += int(torch.isnan(d).sum())
+    assert n_nan > 0

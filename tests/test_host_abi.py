@@ -1,0 +1,183 @@
+"""CPU-only checks of the C-ABI library: it loads, exports every entry point
+the header declares, and its host-side pieces (Gauss-Legendre rule, flow
+stepper, argument validation) are right.  No GPU call is made here."""
+import math
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+import oracle
+from paper_2607_24908_amd import frg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "frg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(frg_[a-z_0-9]+)\s*\(", src)) - {"frg_rhs_fn"})
+
+
+def test_library_exports_every_header_function():
+    names = header_functions()
+    assert len(names) >= 14
+    out = subprocess.run(["nm", "-D", "--defined-only", frg.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (frg_\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert hasattr(frg.lib, n)
+    assert set(frg.EXPORTS) == set(names)
+
+
+def test_version_string():
+    assert "gfx950" in frg.frg_version()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 16, 32, 64, 128, 256, 1024])
+def test_gauss_legendre_golub_welsch(n):
+    """The library's rule (Golub-Welsch) against the oracle's (Newton) and
+    against exactness on monomials."""
+    x, w = frg.frg_gauss_legendre(n)
+    xo, wo = oracle.gauss_legendre(n)
+    assert np.max(np.abs(x - xo)) < 4e-16
+    assert np.max(np.abs(w / wo - 1)) < 5e-15
+    assert abs(w.sum() - 2.0) < 1e-14
+    for deg in range(0, min(2 * n, 40), 2):
+        assert abs(np.dot(w, x ** deg) - 2.0 / (deg + 1)) < 3e-14
+
+
+def test_gauss_legendre_rejects_bad_n():
+    with pytest.raises(frg.FrgError):
+        frg.frg_gauss_legendre(0)
+
+
+def test_footprint_grows_with_grid():
+    a = frg.frg_flow_footprint(frg.make_lpa(n_grid=128))
+    b = frg.frg_flow_footprint(frg.make_lpa(n_grid=1024))
+    assert 0 < a < b
+
+
+def test_create_without_gpu_fails_cleanly():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    with pytest.raises(frg.FrgError) as ei:
+        frg.frg_create(0)
+    assert ei.value.code == frg.FRG_E_DEVICE
+
+
+# ------------------------------------------------------------- stepper --
+
+def oracle_rhs(lpa, N, reg, d=3, n_r=64):
+    def f(t, U):
+        k = lpa.Lambda * math.exp(t)
+        dU, jac, rc = oracle.lpa_rhs(d, N, reg, n_r, lpa.q_max_over_k, k, lpa.rho_max, U,
+                                     allow_domain=True)
+        return dU, jac, rc
+    return f
+
+
+@pytest.mark.parametrize("N", [1, 2, 4])
+def test_stepper_free_theory_litim_closed_form(N):
+    """lambda = 0: U' = U'' = 0 for all t, d_tU = N C_d k^d/d, so
+    U(t) - U(0) = N C_d Lambda^d (e^{dt} - 1)/d^2 on every grid point."""
+    d, t_end = 3, -3.0
+    lpa = frg.make_lpa(d=d, N=N, reg=frg.FRG_REG_LITIM, n_radial=16, n_grid=32)
+    U = np.zeros(32)
+    req = frg.make_request(lpa, 0.0, 0.1, t_end, 1e-10, 1e-13, U)
+    rc, res = frg.frg_flow_solve(req, oracle_rhs(lpa, N, frg.FRG_REG_LITIM, n_r=16))
+    assert rc == frg.FRG_OK, frg.last_error()
+    Cd = 1 / (2 * math.pi ** 2)
+    want = N * Cd * (math.exp(d * t_end) - 1) / d ** 2
+    # second order with per-step error control: global error ~ rtol^(2/3)
+    np.testing.assert_allclose(U, want, rtol=1e-6)
+    assert res.steps > 5 and res.rhs_calls >= res.steps
+
+
+def test_stepper_free_theory_exp_zeta():
+    """lambda = 0, exponential regulator: d_tU = N/2 C_d k^d Gamma(d/2+1) zeta(d/2+1)."""
+    d, N, t_end = 3, 2, -2.0
+    lpa = frg.make_lpa(d=d, N=N, reg=frg.FRG_REG_EXP, n_radial=64, n_grid=16)
+    U = np.zeros(16)
+    req = frg.make_request(lpa, 0.0, 0.05, t_end, 1e-10, 1e-13, U)
+    rc, res = frg.frg_flow_solve(req, oracle_rhs(lpa, N, frg.FRG_REG_EXP))
+    assert rc == frg.FRG_OK, frg.last_error()
+    Cd = 1 / (2 * math.pi ** 2)
+    want = 0.5 * N * Cd * special.gamma(d / 2 + 1) * special.zeta(d / 2 + 1) * \
+        (math.exp(d * t_end) - 1) / d
+    np.testing.assert_allclose(U, want, rtol=1e-6)
+
+
+@pytest.mark.parametrize("lam,rho0,N", [(6.0, 0.02, 2), (12.0, 0.15, 1)])
+def test_stepper_against_scipy_radau(lam, rho0, N):
+    """Interacting flow on a small grid against scipy's Radau IIA integrator
+    driven by the same oracle right-hand side."""
+    d, n, t_end = 3, 48, -2.5
+    lpa = frg.make_lpa(d=d, N=N, reg=frg.FRG_REG_EXP, n_radial=64, n_grid=n)
+    U = np.zeros(n)
+    req = frg.make_request(lpa, lam, rho0, t_end, 1e-10, 1e-13, U)
+    rhs = oracle_rhs(lpa, N, frg.FRG_REG_EXP)
+    rc, res = frg.frg_flow_solve(req, rhs)
+    assert rc == frg.FRG_OK, frg.last_error()
+    rho = np.arange(n) * (0.5 / (n - 1))
+    U0 = (lam / 8.0) * (rho - rho0) ** 2
+
+    def fun(t, u):
+        return rhs(t, u)[0]
+
+    def jac(t, u):
+        J = rhs(t, u)[1]
+        dense = np.zeros((n, n))
+        for o in range(-3, 4):
+            for j in range(n):
+                if 0 <= j + o < n:
+                    dense[j, j + o] = J[o + 3, j]
+        return dense
+
+    sol = integrate.solve_ivp(fun, (0.0, t_end), U0, method="Radau", jac=jac, rtol=1e-11,
+                              atol=1e-13)
+    assert sol.success
+    ref = sol.y[:, -1]
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(U - ref)) < 1e-6 * scale
+    assert res.rejected < res.steps
+
+
+def test_stepper_rejects_bad_request():
+    lpa = frg.make_lpa(n_grid=16)
+    U = np.zeros(16)
+    req = frg.make_request(lpa, 1.0, 0.1, +1.0, 1e-6, 1e-9, U)
+    rc, _ = frg.frg_flow_solve(req, lambda t, u: (np.zeros(16), None, 0))
+    assert rc == frg.FRG_E_INVAL
+    bad = frg.make_lpa(n_grid=2)
+    req = frg.make_request(bad, 1.0, 0.1, -1.0, 1e-6, 1e-9, np.zeros(2))
+    rc, _ = frg.frg_flow_solve(req, lambda t, u: (np.zeros(2), None, 0))
+    assert rc == frg.FRG_E_INVAL
+
+
+def test_stepper_reports_persistent_domain_failure():
+    """A right-hand side that always reports a pole crossing makes the
+    stepper shrink the step until it gives up with FRG_E_STEP."""
+    lpa = frg.make_lpa(n_grid=8)
+    U = np.zeros(8)
+    req = frg.make_request(lpa, 1.0, 0.1, -1.0, 1e-6, 1e-9, U)
+    calls = {"n": 0}
+
+    def rhs(t, u):
+        calls["n"] += 1
+        if calls["n"] == 1:
+            return np.zeros(8), None, frg.FRG_OK
+        return np.full(8, np.nan), np.zeros(56), frg.FRG_E_DOMAIN
+
+    rc, res = frg.frg_flow_solve(req, rhs)
+    assert rc == frg.FRG_E_STEP
+    assert res.rejected > 10
