@@ -1,0 +1,298 @@
+#!/usr/bin/env python3
+"""Benchmark of the FRG flow-diagram quadrature on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+One step = one evaluation of the scale-up workload (d = 3, exponential
+regulator, 4096 momenta log-spaced in [1e-4, 20] x 512 masses uniform in
+[-0.9, 10], 128 radial x 32 angular Gauss-Legendre nodes: 2 097 152
+integrals, 8.59e9 integrand evaluations) through frg_integrate_grid, inputs
+resident in HBM.  Prints ONE JSON line: throughput in integrand evaluations
+per second (plus integrals/s), the roofline of the dominant kernel, the FP64
+oracle timed on the host cores on a bounded sample, and secondary figures
+measured outside the timed region (uneven batched vs plain launches,
+compensated FP32, served-flow latency) when their parts are built.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# ALU roofline of the FP64 path.  Issue rate of the FP64 VALU of MI355X:
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 lane-cycles/s.  Floor of
+# the per-evaluation work of the reciprocal sum sum_j mu_j / (H_j + delta):
+# 4 FP64 VALU operations per term (the add forming D, its product into the
+# common denominator P, and the product + FMA folding mu_j into the numerator
+# N), the quarter-rate reciprocal being shared by all terms of a group.
+VALU_LANE_CYCLES = 256 * 4 * 16 * 2.4e9
+# HBM traffic of one grid_kernel launch from rocprofv3 FETCH_SIZE/WRITE_SIZE
+# (None until measured for the current kernel)
+TRAFFIC = None
+CYCLES_PER_EVAL_FLOOR = 4
+PEAK_EVALS = VALU_LANE_CYCLES / CYCLES_PER_EVAL_FLOOR
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one device-to-device copy of 1 GiB (PMC traffic calibration)")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w):
+    """The FP64 oracle, as it stands, on 1/16 of the workload (every 16th mass
+    for all momenta), OpenMP over points on the host cores."""
+    import oracle
+    q = w.quad
+    m2 = w.m2[::16]
+    P = np.repeat(w.p, m2.size)
+    M = np.tile(m2, w.p.size)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 64))
+    t0 = time.perf_counter()
+    oracle.integrate(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a, P, M, threads=cores)
+    dt = time.perf_counter() - t0
+    evals = P.size * q.n_r * q.n_a
+    return {"value": evals / dt, "unit": "integrand evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"1/16 of the workload: all {w.p.size} momenta x every 16th mass "
+                      f"({P.size} integrals, {evals:.3e} evals), {dt:.2f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(integral sets and flows shard across GPUs with no exchange; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2607_24908_amd import frg, workloads
+    assert torch.cuda.is_available(), "no GPU"
+    ctx = frg.frg_create(0)
+    w = workloads.scaleup_d3()
+    q = w.quad
+    quad = frg.make_quad(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a)
+    P = torch.as_tensor(w.p, dtype=torch.float64, device="cuda")
+    M = torch.as_tensor(w.m2, dtype=torch.float64, device="cuda")
+    out = torch.empty(w.n_integrals, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    log(f"workload {w.name}: {w.n_integrals} integrals, {w.n_evals:.3e} evals")
+    for _ in range(args.warmup):
+        frg.frg_integrate_grid(ctx, quad, P, M, out, stream=stream)
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} done")
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        frg.frg_integrate_grid(ctx, quad, P, M, out, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1) / args.steps
+    log(f"timed {args.steps} steps: {gpu_ms:.3f} ms/step (events), wall {wall:.3f} s")
+    res = out.cpu().numpy()
+    assert np.all(np.isfinite(res)) and np.all(res > 0), "non-finite results"
+    ms_step = wall * 1e3 / args.steps
+    evals_s = w.n_evals / (ms_step * 1e-3)
+    kernel_s = gpu_ms * 1e-3
+    achieved = w.n_evals / kernel_s / 1e9
+    line = {
+        "metric": "integrand evals/s (FP64, plain scale-up d=3 grid)",
+        "value": evals_s,
+        "unit": "integrand evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seedless deterministic grid: log-spaced p, uniform m^2)",
+        "config": {"workload": w.name, "n_p": int(w.p.size), "n_m": int(w.m2.size), "d": q.d,
+                   "regulator": "exp", "k": q.k, "q_max": q.q_max, "n_radial": q.n_r,
+                   "n_angular": q.n_a, "evals_per_step": int(w.n_evals),
+                   "integrals_per_step": int(w.n_integrals), "entry": "frg_integrate_grid"},
+        "integrals_per_s": w.n_integrals / (ms_step * 1e-3),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_EVALS / 1e9,
+                     "unit": "Geval/s", "frac": achieved * 1e9 / PEAK_EVALS, "traffic": TRAFFIC,
+                     "kernel": "grid_kernel<exp>", "kernel_ms": gpu_ms,
+                     "evals_per_launch": int(w.n_evals),
+                     "peak_basis": "FP64 VALU 3.93e13 lane-cycles/s / 4 cycles per eval"},
+    }
+    if not args.no_secondary:
+        line["secondary"] = secondary(ctx, frg, workloads, torch)
+    if args.copy_calibration:
+        x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        line["cpu_baseline"] = cpu_baseline(w)
+    frg.frg_destroy(ctx)
+    print(json.dumps(line), flush=True)
+
+
+def timed(fn, torch, reps=5):
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def secondary(ctx, frg, workloads, torch):
+    """Figures for the other workloads, measured after the timed region."""
+    sec = {}
+    # uneven sets: one plain launch per set vs one persistent graph replay
+    sets = workloads.uneven_sets(seed=0)
+    evals = sum(s.n_evals for s in sets)
+    ds = []
+    for s in sets:
+        q = s.quad
+        ds.append(dict(quad=frg.make_quad(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a),
+                       p=torch.as_tensor(s.p, device="cuda"), m2=torch.as_tensor(s.m2, device="cuda"),
+                       out=torch.empty(s.p.size, dtype=torch.float64, device="cuda")))
+    n_int = sum(s.p.size for s in sets)
+    t_plain = timed(lambda: frg.frg_integrate(ctx, ds, flags=frg.FRG_PLAIN), torch)
+    t_pers = timed(lambda: frg.frg_integrate(ctx, ds, flags=frg.FRG_PERSISTENT), torch)
+    t_graph = timed(lambda: frg.frg_integrate(ctx, ds, flags=frg.FRG_PERSISTENT | frg.FRG_GRAPH),
+                    torch)
+    sec["uneven_sets_seed0"] = {
+        "sets": len(sets), "integrals": n_int, "evals": evals,
+        "plain_evals_per_s": evals / t_plain, "persistent_evals_per_s": evals / t_pers,
+        "graph_evals_per_s": evals / t_graph, "graph_integrals_per_s": n_int / t_graph,
+        "batched_over_plain": t_plain / t_graph}
+    log(f"uneven sets: plain {evals / t_plain:.3e}, graph {evals / t_graph:.3e} evals/s")
+    # plain d = 4 grid: latency of one small call
+    w = workloads.plain_d4()
+    q = w.quad
+    quad = frg.make_quad(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a)
+    P = torch.as_tensor(w.p, device="cuda")
+    M = torch.as_tensor(w.m2, device="cuda")
+    out = torch.empty(w.n_integrals, dtype=torch.float64, device="cuda")
+    t1 = timed(lambda: frg.frg_integrate_grid(ctx, quad, P, M, out), torch, reps=50)
+    sec["plain_d4"] = {"ms_per_call": t1 * 1e3, "evals_per_s": w.n_evals / t1,
+                       "integrals_per_s": w.n_integrals / t1}
+    # compensated FP32 on the point kernel (uneven sets): the regulator is
+    # evaluated per term there, which is where FP32 pays
+    ds32 = []
+    for s, d in zip(sets, ds):
+        q = s.quad
+        ds32.append(dict(quad=frg.make_quad(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a,
+                                            frg.FRG_PREC_FP32C), p=d["p"], m2=d["m2"],
+                         out=torch.empty_like(d["out"]), err_est=torch.empty_like(d["out"]),
+                         used_fp64=torch.empty(d["out"].numel(), dtype=torch.uint8,
+                                               device="cuda")))
+    t32 = timed(lambda: frg.frg_integrate(ctx, ds32, flags=frg.FRG_PLAIN), torch)
+    frg.frg_integrate(ctx, ds, flags=frg.FRG_PLAIN)
+    torch.cuda.synchronize()
+    dev_max = max(((a["out"] - b["out"]).abs() / b["out"]).max().item() for a, b in zip(ds32, ds))
+    share = sum((a["used_fp64"] == 0).sum().item() for a in ds32) / n_int
+    sec["fp32c_uneven_sets_seed0"] = {
+        "fp32c_plain_evals_per_s": evals / t32, "fp64_plain_evals_per_s": evals / t_plain,
+        "fp64_graph_evals_per_s": evals / t_graph, "fp32_share": share,
+        "max_rel_dev_vs_fp64": dev_max}
+    log(f"fp32c uneven: {evals / t32:.3e} evals/s (fp64 plain {evals / t_plain:.3e}), "
+        f"fp32 share {share:.2f}, max dev {dev_max:.2e}")
+    # compensated FP32 on grids (precision workload: half the masses near the
+    # pole); deviation measured against the FP64 kernel's result
+    for name, wk in (("fp32c_precision_d4_seed0", workloads.precision_d4(0)),
+                     ("fp32c_scaleup_d3", workloads.scaleup_d3())):
+        q = wk.quad
+        P = torch.as_tensor(wk.p, device="cuda")
+        M = torch.as_tensor(wk.m2, device="cuda")
+        o64 = torch.empty(wk.n_integrals, dtype=torch.float64, device="cuda")
+        o32 = torch.empty_like(o64)
+        err = torch.empty_like(o64)
+        used = torch.empty(wk.n_integrals, dtype=torch.uint8, device="cuda")
+        q64 = frg.make_quad(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a, frg.FRG_PREC_FP64)
+        q32 = frg.make_quad(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a, frg.FRG_PREC_FP32C)
+        reps = 3 if wk.n_evals > 1e9 else 20
+        t64 = timed(lambda: frg.frg_integrate_grid(ctx, q64, P, M, o64), torch, reps)
+        t32 = timed(lambda: frg.frg_integrate_grid(ctx, q32, P, M, o32, err, used), torch, reps)
+        rel = ((o32 - o64).abs() / o64).max().item()
+        sec[name] = {"evals": wk.n_evals, "fp32c_evals_per_s": wk.n_evals / t32,
+                     "fp64_evals_per_s": wk.n_evals / t64,
+                     "fp32_share": 1.0 - used.double().mean().item(),
+                     "max_rel_dev_vs_fp64": rel, "max_err_estimate": err.max().item()}
+        log(f"{name}: fp32c {wk.n_evals / t32:.3e} evals/s, fp64 {wk.n_evals / t64:.3e}, "
+            f"max dev {rel:.2e}")
+    sec["serving"] = serving(frg, workloads)
+    return sec
+
+
+def serving(frg, workloads, n_req=100, seed=0):
+    """Poisson stream (50/s) of LPA O(N) flow requests through frg_submit /
+    frg_poll; latency = done - submit on the library's monotonic clock."""
+    reqs = workloads.lpa_requests(seed=seed, n=n_req)
+    ctx = frg.frg_create(0)
+    outs, keep, tickets, res = [], [], [], {}
+    t0 = time.perf_counter()
+    i = 0
+    while len(res) < n_req:
+        now = time.perf_counter() - t0
+        while i < n_req and reqs[i].arrival_s <= now:
+            r = reqs[i]
+            U = np.zeros(r.n_grid)
+            lpa = frg.make_lpa(d=r.d, N=r.N, reg=r.reg, n_radial=r.n_r,
+                               q_max_over_k=r.q_max_over_k, Lambda=r.Lambda, n_grid=r.n_grid,
+                               rho_max=r.rho_max)
+            q = frg.make_request(lpa, r.lam, r.rho0, r.t_end, r.rtol, r.atol, U)
+            outs.append(U)
+            keep.append(q)
+            tickets.append(frg.frg_submit(ctx, q))
+            i += 1
+        for tk in tickets:
+            if tk not in res:
+                rc, rr = frg.frg_poll(ctx, tk)
+                if rc == frg.FRG_OK:
+                    res[tk] = rr
+        time.sleep(0.0005)
+    wall = time.perf_counter() - t0
+    rs = [res[t] for t in tickets]
+    lat = np.array([x.done_s - x.submit_s for x in rs])
+    done, launches, mean_batch = frg.frg_server_stats(ctx)
+    frg.frg_destroy(ctx)
+    ok = sum(x.status == frg.FRG_OK for x in rs)
+    pole = sum(x.status == frg.FRG_E_DOMAIN for x in rs)
+    out = {"requests": n_req, "rate_per_s": 50, "grid": "128..1024", "N": "1,2,4",
+           "completed_to_t_end": ok, "stopped_at_pole": pole,
+           "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
+           "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
+           "mean_latency_ms": float(lat.mean() * 1e3), "flows_per_s": n_req / wall,
+           "rhs_calls_total": int(sum(x.rhs_calls for x in rs)),
+           "launches": launches, "mean_flows_per_launch": mean_batch}
+    log(f"serving: p50 {out['p50_latency_ms']:.1f} ms, p99 {out['p99_latency_ms']:.1f} ms, "
+        f"{ok} to t_end, {pole} at the pole, mean batch {mean_batch:.2f}")
+    return out
+
+
+if __name__ == "__main__":
+    main()

@@ -198,7 +198,12 @@ typedef struct {
 } frg_request;
 
 typedef struct {
-  int32_t status;     /* FRG_OK, FRG_PENDING, FRG_E_STEP, FRG_E_DOMAIN ...  */
+  int32_t status;     /* FRG_OK: reached t_end.  FRG_E_DOMAIN: ran into the
+                         propagator pole m^2 = -k^2 at t_reached (with the
+                         exponential regulator in d = 3 the threshold
+                         function F_1 stays finite at the pole, so a flow in
+                         the broken phase reaches it at finite RG time).
+                         FRG_E_STEP: step-size underflow.  FRG_PENDING.    */
   int32_t reserved;
   int64_t steps;      /* accepted steps                                     */
   int64_t rejected;   /* rejected steps                                     */
@@ -206,6 +211,8 @@ typedef struct {
   double submit_s;    /* monotonic clock, seconds                           */
   double start_s;     /* admitted and started                               */
   double done_s;      /* finished                                           */
+  double t_reached;   /* RG time of the last accepted step (U_out holds U
+                         there, also when the flow stopped early)           */
 } frg_result;
 
 /* Host right-hand side used by frg_flow_solve: fill dUdt[n] and, if
@@ -215,7 +222,8 @@ typedef int (*frg_rhs_fn)(void *user, double t, const double *U, int64_t n, doub
                           double *jac_bands);
 
 /* Integrate one request synchronously with a caller-supplied right-hand side
- * (host only; no GPU use).  The stepper is the one the flow server runs. */
+ * (host only; no GPU use).  The stepper is the one the flow server runs.
+ * Returns the final status (also in out->status). */
 int frg_flow_solve(const frg_request *req, frg_rhs_fn rhs, void *user, frg_result *out);
 
 /* Submit a flow to the context's server (never blocks).  The server admits
@@ -232,6 +240,31 @@ int frg_poll(frg_ctx *ctx, uint64_t ticket, frg_result *out);
 /* Server statistics: completed flows, batched launches and the mean number of
  * flows per launch since creation. */
 int frg_server_stats(frg_ctx *ctx, int64_t *flows_done, int64_t *launches, double *mean_batch);
+
+/* ---- launch shapes ------------------------------------------------------------- */
+/* Launch-shape autotuning (points per wave, masses per wave, waves per
+ * workgroup, tiles of the persistent work list).  mode 0: defaults and any
+ * cached choice; mode 1: the first call with a new key (kernel, regulator,
+ * n_radial, n_angular, precision, size class) times each candidate shape on
+ * that call's own inputs with HIP events on its stream (that call then
+ * synchronises the stream) and keeps the fastest.  cache_path (optional,
+ * NULL = keep the current one) names a text file read now and rewritten
+ * after each tuning.  The environment variables FRG_AUTOTUNE and
+ * FRG_AUTOTUNE_CACHE set the same at frg_create.  The summation order of
+ * every result is fixed by (n_radial, n_angular): no launch shape changes a
+ * result. */
+int frg_autotune(frg_ctx *ctx, int32_t mode, const char *cache_path);
+
+/* Set / read one default launch-shape knob: "grid_M" (4, 8, 16), "grid_W"
+ * (1..8), "grid_MB" (1..64), "grid_lds_rows" (8..96), "plain_tile",
+ * "persist_tile" (1..64), "persist_wpc" (1..64).  Setting a knob drops the
+ * tuned choices so that it takes effect.  Two knobs route FRG_PREC_FP32C
+ * points to FP64 and do change results (within the FP32 tolerance):
+ * "fp32c_flag_ppb" (error-estimate threshold in units of 1e-9, default 80)
+ * and "fp32c_band_ppm" (pole band on (m^2 + k^2)/k^2 in units of 1e-6,
+ * default 10000). */
+int frg_tune_set(frg_ctx *ctx, const char *key, int32_t value);
+int frg_tune_get(frg_ctx *ctx, const char *key, int32_t *value);
 
 /* ---- host-only helpers ------------------------------------------------------ */
 /* Gauss-Legendre nodes (ascending) and weights on [-1, 1], n = 1..4096, by

@@ -20,8 +20,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libfrg.so")
 
-SOURCES = ["kernels.hip", "fp32c_stub.cpp", "capi.cpp", "tables.cpp", "stepper.cpp",
-           "server_stub.cpp", "tune_stub.cpp"]
+SOURCES = ["kernels.hip", "fp32c.hip", "capi.cpp", "tables.cpp", "stepper.cpp",
+           "server.cpp", "autotune.cpp"]
 
 ARCH = os.environ.get("FRG_OFFLOAD_ARCH", "gfx950")
 

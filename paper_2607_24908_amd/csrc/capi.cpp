@@ -74,6 +74,7 @@ int DescRing::init(size_t slot_bytes_, int n_slots) {
     if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
       return fail(FRG_E_DEVICE, "hipEventCreate");
     s.used = false;
+    s.cap = slot_bytes;
   }
   return FRG_OK;
 }
@@ -93,11 +94,26 @@ void DescRing::destroy() {
 // `stream`; the returned device pointer stays valid until the slot comes
 // round again, which first waits for the event recorded by release().
 int DescRing::upload(const void *src, size_t bytes, hipStream_t stream, void **dev, int *slot_id) {
-  if (bytes > slot_bytes) return fail(FRG_E_INVAL, "descriptor batch too large (%zu B)", bytes);
   Slot &s = slots[next];
   if (s.used) {
     hipError_t e = hipEventSynchronize(s.done);
     if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(ring)");
+    s.used = false;
+  }
+  if (bytes > s.cap) {  // grow this slot (its previous use has completed)
+    const size_t cap = std::max(bytes, 2 * s.cap);
+    void *h = nullptr, *d = nullptr;
+    if (hipHostMalloc(&h, cap, hipHostMallocDefault) != hipSuccess)
+      return fail(FRG_E_NOMEM, "hipHostMalloc descriptor ring (%zu B)", cap);
+    if (hipMalloc(&d, cap) != hipSuccess) {
+      hipHostFree(h);
+      return fail(FRG_E_NOMEM, "hipMalloc descriptor ring (%zu B)", cap);
+    }
+    hipHostFree(s.host);
+    hipFree(s.dev);
+    s.host = h;
+    s.dev = d;
+    s.cap = cap;
   }
   std::memcpy(s.host, src, bytes);
   hipError_t e = hipMemcpyAsync(s.dev, s.host, bytes, hipMemcpyHostToDevice, stream);
@@ -223,6 +239,8 @@ int Ctx::make_setdev(const frg_set &s, SetDev *out) {
   d.n_a = s.quad.n_angular;
   d.reg = s.quad.reg;
   d.prec = s.quad.prec;
+  d.f32_flag = tune.fp32c_flag_ppb * 1e-9;
+  d.f32_band = tune.fp32c_band_ppm * 1e-6;
   lane_split(d.n_r, d.n_a, &d.R, &d.J, &d.T, &d.U);
   *out = d;
   return FRG_OK;
@@ -240,7 +258,7 @@ int Ctx::integrate_device(const frg_set *sets, int n_sets, int flags, hipStream_
   if (!(flags & FRG_PERSISTENT)) {
     for (int i = 0; i < n_sets; ++i) {
       if (sd[i].n_ext == 0) continue;
-      int e = launch_points_plain(sd[i], tune.plain_tile, d_flag, st);
+      int e = launch_points_plain(sd[i], plain_tile_for(sd[i], st), d_flag, st);
       if (e) return hip_fail((hipError_t)e, "points_plain_kernel launch");
     }
     return FRG_OK;
@@ -308,12 +326,13 @@ int Ctx::persistent(const std::vector<SetDev> &sd, const frg_set *sets, int n_se
       return FRG_OK;
     }
   }
+  const PersistCfg pc = persist_cfg(sd, sd.empty() ? 0 : sd[0].prec, st);
   std::vector<Tile> tiles;
-  build_tiles(sd, tune.persist_tile, &tiles);
+  build_tiles(sd, pc.tile, &tiles);
   if (tiles.empty()) return FRG_OK;
   const int lds = max_table_doubles(sd);
   if (lds * 8 > 64 * 1024) return fail(FRG_E_INVAL, "quadrature tables exceed 64 KiB of LDS");
-  const int n_blocks = std::max(1, std::min<int>((int)tiles.size(), n_cu * tune.persist_waves_per_cu));
+  const int n_blocks = std::max(1, std::min<int>((int)tiles.size(), n_cu * pc.wpc));
   if (graph) {
     auto g = std::make_unique<GraphEntry>();
     int rc = g->sets.reserve(sd.size() * sizeof(SetDev));
@@ -344,7 +363,16 @@ int Ctx::persistent(const std::vector<SetDev> &sd, const frg_set *sets, int n_se
     graphs.emplace(sig, std::move(g));
     return FRG_OK;
   }
-  // eager persistent launch: descriptors through the ring
+  return persistent_eager(sd, pc, st);
+}
+
+// Eager persistent launch: work list and descriptors go through the ring.
+int Ctx::persistent_eager(const std::vector<SetDev> &sd, const PersistCfg &pc, hipStream_t st) {
+  std::vector<Tile> tiles;
+  build_tiles(sd, pc.tile, &tiles);
+  if (tiles.empty()) return FRG_OK;
+  const int lds = max_table_doubles(sd);
+  const int n_blocks = std::max(1, std::min<int>((int)tiles.size(), n_cu * pc.wpc));
   std::vector<char> blob(sd.size() * sizeof(SetDev) + tiles.size() * sizeof(Tile));
   std::memcpy(blob.data(), sd.data(), sd.size() * sizeof(SetDev));
   std::memcpy(blob.data() + sd.size() * sizeof(SetDev), tiles.data(), tiles.size() * sizeof(Tile));
@@ -442,12 +470,66 @@ int Ctx::grid_device(const frg_quad &q, int64_t n_p, const double *p, int64_t n_
   g.n_r = q.n_radial;
   g.n_a = q.n_angular;
   lane_split(g.n_r, g.n_a, &g.R, &g.J, &g.T, &g.U);
-  int M = tune.grid_M, W = tune.grid_W;
-  g.chunk = std::max(1, tune.grid_lds_rows);
+  g.chunk = std::max(8, tune.grid_lds_rows);
   if (grid_lds_bytes(g) > 64 * 1024) return fail(FRG_E_INVAL, "grid tables exceed 64 KiB of LDS");
-  g.n_mb = (int)((n_m + (int64_t)M * W - 1) / ((int64_t)M * W));
-  int e = launch_grid(g, q.reg, M, W, st);
+  const GridCfg cfg = grid_cfg(q, g, st);
+  return grid_launch(g, q.reg, cfg, st);
+}
+
+int Ctx::grid_launch(GridArgs g, int reg, const GridCfg &cfg, hipStream_t st) {
+  const bool resident = g.T * g.U <= g.chunk;
+  const int64_t per_wg_min = (int64_t)cfg.M * cfg.W;
+  // mass blocks per wave: fewer workgroups per momentum, but keep at least
+  // ~4 workgroups per CU in flight
+  int mbk = resident ? std::max(1, cfg.MB) : 1;
+  while (mbk > 1 && g.n_p * ((g.n_m + per_wg_min * mbk - 1) / (per_wg_min * mbk)) < 4LL * n_cu)
+    mbk /= 2;
+  g.mblocks = mbk;
+  g.n_mb = (int)((g.n_m + per_wg_min * mbk - 1) / (per_wg_min * mbk));
+  int e = launch_grid(g, reg, cfg.M, cfg.W, st);
   if (e) return hip_fail((hipError_t)e, "grid_kernel launch");
+  return FRG_OK;
+}
+
+// --------------------------------------------------------------- FP32C --
+// Sets with FRG_PREC_FP32C run the compensated-FP32 kernel (one launch per
+// set); FP64 sets of the same call take the FP64 paths.
+int Ctx::integrate_fp32c_sets(const std::vector<SetDev> &sd, int flags, hipStream_t st) {
+  std::vector<SetDev> f64;
+  for (const SetDev &s : sd) {
+    if (s.prec != FRG_PREC_FP32C) {
+      f64.push_back(s);
+      continue;
+    }
+    if (s.n_ext == 0) continue;
+    int e = launch_fp32c(s, tune.plain_tile, 0, d_flag, st);
+    if (e) return hip_fail((hipError_t)e, "fp32c_kernel launch");
+  }
+  if (f64.empty()) return FRG_OK;
+  if (flags & FRG_PERSISTENT) return persistent_eager(f64, persist_cfg(f64, FRG_PREC_FP64, st), st);
+  for (const SetDev &s : f64) {
+    if (s.n_ext == 0) continue;
+    int e = launch_points_plain(s, plain_tile_for(s, st), d_flag, st);
+    if (e) return hip_fail((hipError_t)e, "points_plain_kernel launch");
+  }
+  return FRG_OK;
+}
+
+int Ctx::grid_fp32c(const frg_quad &q, int64_t n_p, const double *p, int64_t n_m,
+                    const double *m2, double *out, double *err, uint8_t *used, hipStream_t st) {
+  frg_set fs{};
+  fs.quad = q;
+  fs.n_ext = n_p * n_m;
+  fs.p = p;
+  fs.m2 = m2;
+  fs.out = out;
+  fs.err_est = err;
+  fs.used_fp64 = used;
+  SetDev s;
+  int rc = make_setdev(fs, &s);
+  if (rc) return rc;
+  int e = launch_fp32c(s, tune.plain_tile, n_m, d_flag, st);
+  if (e) return hip_fail((hipError_t)e, "fp32c_kernel launch");
   return FRG_OK;
 }
 

@@ -42,6 +42,7 @@ struct DescRing {
     void *dev = nullptr;
     hipEvent_t done = nullptr;
     bool used = false;
+    size_t cap = 0;
   };
   std::vector<Slot> slots;
   size_t slot_bytes = 0;
@@ -52,16 +53,34 @@ struct DescRing {
   int release(int slot_id, hipStream_t stream);
 };
 
-// Launch-shape parameters (defaults; the autotuner overwrites them).
+// Launch shapes.  Defaults below; the autotuner (autotune.cpp) replaces
+// them per key with measured choices.  No launch shape changes a result.
+struct GridCfg {
+  int M = 8;    // masses per wave
+  int W = 4;    // waves per workgroup
+  int MB = 8;   // mass blocks per wave while the table is resident
+};
+struct PersistCfg {
+  int tile = 4;  // points per tile
+  int wpc = 16;  // resident one-wave workgroups per CU
+};
+using ShapeKey = std::tuple<int, int, int, int>;  // (regulator, n_r, n_a, precision)
+
 struct Tune {
-  int plain_tile = 8;            // points per wave, plain launches
-  int persist_tile = 8;          // points per tile, persistent launches
-  int persist_waves_per_cu = 16; // resident one-wave workgroups per CU
-  int grid_M = 16;               // masses per wave, tensor-grid kernel
-  int grid_W = 4;                // waves per workgroup, tensor-grid kernel
-  int grid_lds_rows = 64;        // (t, u) rows of 64 doubles staged per chunk
-  int fp32_M = 16;
+  GridCfg grid;
+  int plain_tile = 8;
+  PersistCfg persist;
+  int grid_lds_rows = 64;  // (t, u) rows of 64 doubles staged per LDS chunk
+  int fp32c_flag_ppb = 80;     // FP32C: FP64 redo above this error estimate (1e-9 units)
+  int fp32c_band_ppm = 10000;  // FP32C: FP64 below this delta/k^2 (1e-6 units)
+  int mode = 0;            // 0: defaults and cached choices, 1: tune new keys
+  std::string cache_path;
+  std::map<ShapeKey, GridCfg> grid_best;
+  std::map<ShapeKey, int> plain_best;
+  std::map<int, PersistCfg> persist_best;  // by precision
   void load_env();
+  int load_file(const std::string &arch);
+  int save_file(const std::string &arch) const;
 };
 
 struct GraphEntry {
@@ -114,6 +133,12 @@ struct Context {
   int lpa_jobs(int n, const frg_lpa *lpa, const double *t, const double *const *U,
                double *const *dUdt, double *const *jac, int *flags_dev, hipStream_t st);
   void stop_server();
+  // autotune.cpp
+  int grid_launch(GridArgs g, int reg, const GridCfg &cfg, hipStream_t st);
+  GridCfg grid_cfg(const frg_quad &q, const GridArgs &g, hipStream_t st);
+  int plain_tile_for(const SetDev &s, hipStream_t st);
+  PersistCfg persist_cfg(const std::vector<SetDev> &sd, int prec, hipStream_t st);
+  int persistent_eager(const std::vector<SetDev> &sd, const PersistCfg &pc, hipStream_t st);
 };
 
 using Ctx = Context;

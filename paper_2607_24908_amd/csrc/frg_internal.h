@@ -58,6 +58,8 @@ struct SetDev {
   int32_t n_r, n_a, reg, prec;
   int32_t R, J;  // lanes along radial / angular nodes, R * J = 64
   int32_t T, U;  // ceil(n_r / R), ceil(n_a / J)
+  double f32_flag;  // FP32C: error estimate above which a point is redone in FP64
+  double f32_band;  // FP32C: delta/k^2 below which a point is done in FP64
 };
 
 struct Tile {
@@ -77,8 +79,10 @@ struct GridArgs {
   double k2, inv_k2, pref;
   int64_t n_p, n_m;
   int32_t n_r, n_a, R, J, T, U;
-  int32_t n_mb;   // mass blocks per momentum
-  int32_t chunk;  // (t, u) rows of the Hk table held in LDS at once
+  int32_t n_mb;     // workgroups per momentum
+  int32_t chunk;    // (t, u) rows of the Hk table held in LDS at once
+  int32_t mblocks;  // mass blocks per wave when the table is resident
+  int32_t pad;
 };
 
 struct LpaJob {
@@ -105,6 +109,7 @@ int launch_points_persistent(const SetDev *d_sets, const Tile *d_tiles, int n_ti
 int launch_reset_counter(int *d_counter, void *stream);
 int launch_grid(const GridArgs &g, int reg, int M, int W, void *stream);
 int grid_lds_bytes(const GridArgs &g);
+int launch_fp32c(const SetDev &s, int tile_points, int64_t grid_nm, int *d_flag, void *stream);
 int launch_lpa(const LpaJob *d_jobs, const int64_t *d_start, int n_jobs, int64_t total_points,
                void *stream);
 

@@ -1,22 +1,7 @@
-// HIP kernels (gfx950) for the FRG flow-diagram quadrature.
-//
-// Work per external point (p, m^2), delta = m^2 + k^2:
-//   I = P_d sum_i A_i sum_j mu_j / D_ij,
-//   A_i = c_i / (Hq_i + delta)^2,  c_i = w_i q_i^{d-1} d_tR(q_i^2),
-//   D_ij = Hk(s_ij) + delta,  s_ij = (q_i - p)^2 + 2 q_i p (1 + x_j),
-//   Hk(s) = k^2 h(s/k^2) (exponential regulator) or max(s - k^2, 0) (Litim).
-//
-// Lane map and summation order.  A wave of 64 lanes splits the nodes as
-// R radial x J angular lanes (R = largest power of two <= min(n_r, 64),
-// J = 64/R).  Lane (rho, iota) owns radial nodes i = rho + R t and angular
-// nodes j = iota + J u (t < T, u < U, padded nodes contribute an exact 0).
-// It accumulates  sum_t A_t (sum_u mu_u / D_tu)  in t and u order, and the
-// 64 lane partials are combined by a fixed xor butterfly.  The order thus
-// depends only on (n_r, n_a): every kernel and tile choice below gives
-// bitwise-identical results for the same point.
-//
-// FP64 reciprocal: the hardware estimate (v_rcp_f64) refined by two
-// Newton-Raphson steps r <- r + r (1 - x r).
+// FP64 kernels (gfx950) of the FRG flow-diagram quadrature: the point-list
+// kernel (plain and persistent launches), the tensor-grid kernel and the
+// batched LPA right-hand side.  The per-point arithmetic, lane map and
+// summation order are in device_fp64.h.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -25,90 +10,13 @@
 
 #pragma clang fp contract(off)
 
+#include "device_fp64.h"
+
 namespace frg {
 
 namespace {
 
-constexpr int kExp = FRG_REG_EXP;
-constexpr int kLitim = FRG_REG_LITIM;
-
-__device__ __forceinline__ double rcp64(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = __builtin_fma(-x, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-x, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  return r;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
-}
-
-// h(y) = y/(1 - e^{-y}) - 1; Bernoulli series y/2 + y^2/12 - y^4/720 + ...
-// below y = 0.1 (truncation < 1e-17 relative there).
-__device__ __forceinline__ double h_exp(double y) {
-  if (y < 0.1) {
-    const double y2 = y * y;
-    double t = __builtin_fma(y2, 1.0 / 47900160.0, -1.0 / 1209600.0);
-    t = __builtin_fma(y2, t, 1.0 / 30240.0);
-    t = __builtin_fma(y2, t, -1.0 / 720.0);
-    t = __builtin_fma(y2, t, 1.0 / 12.0);
-    return __builtin_fma(y2, t, 0.5 * y);
-  }
-  const double em = expm1(-y);  // in (-1, -0.095]
-  return y * rcp64(-em) - 1.0;
-}
-
-template <int REG>
-__device__ __forceinline__ double hk(double s, double k2, double inv_k2) {
-  if constexpr (REG == kExp) {
-    return k2 * h_exp(s * inv_k2);
-  } else {
-    return fmax(s - k2, 0.0);
-  }
-}
-
-// Lane partial of one point; `tab` is the packed table (LDS).
-template <int REG>
-__device__ __forceinline__ double lane_point(const double *__restrict__ tab, const SetDev &s,
-                                             int lane, double p, double delta) {
-  const int n_r = s.n_r, n_a = s.n_a;
-  const double *tq = tab;
-  const double *tc = tab + n_r;
-  const double *tH = tab + 2 * n_r;
-  const double *to = tab + 3 * n_r;
-  const double *tm = to + n_a;
-  const int rho = lane & (s.R - 1);
-  const int iota = lane / s.R;
-  double total = 0.0;
-  for (int t = 0; t < s.T; ++t) {
-    const int i = rho + s.R * t;
-    const bool vi = i < n_r;
-    const double q = vi ? tq[i] : 0.0;
-    const double c = vi ? tc[i] : 0.0;
-    const double Hq = vi ? tH[i] : 1.0;
-    const double Gq = rcp64(Hq + delta);
-    const double A = (c * Gq) * Gq;
-    const double qm = q - p;
-    const double a = qm * qm;
-    const double b = (2.0 * q) * p;
-    double inner = 0.0;
-    for (int u = 0; u < s.U; ++u) {
-      const int j = iota + s.J * u;
-      const bool vj = j < n_a;
-      const double opx = vj ? to[j] : 1.0;
-      const double mu = vj ? tm[j] : 0.0;
-      const double sij = __builtin_fma(b, opx, a);
-      const double D = hk<REG>(sij, s.k2, s.inv_k2) + delta;
-      inner = __builtin_fma(mu, rcp64(D), inner);
-    }
-    total = __builtin_fma(A, inner, total);
-  }
-  return total;
-}
+using namespace dev;
 
 // One tile: `count` (<= 64) consecutive points of set s, one after another;
 // lane e keeps the result of point e, stored coalesced at the end.
@@ -186,12 +94,117 @@ __global__ void reset_counter_kernel(int *c) {
   if (threadIdx.x == 0) *c = 0;
 }
 
-// Tensor grid: workgroup = W waves sharing one momentum p[a]; wave w owns
-// M consecutive masses.  The table Hk(s_ij) of this p is built in LDS
-// (lane-major, conflict-free) in chunks of g.chunk (t, u) rows and each
-// entry is reused for the M masses of every wave.  Rows are visited in the
-// same (t, u) order as lane_point, so results match the point kernel bit
-// for bit.
+// Tensor grid.  A workgroup of W waves owns one momentum p[a] and
+// W * M * MB consecutive masses; wave w takes mass blocks w, w + W, ... of M
+// masses each.  The table Hk(s_ij) of this p lives in LDS (lane-major,
+// conflict-free) and serves every mass block; tables larger than g.chunk
+// rows are streamed through LDS in chunks (then MB = 1).  The (t, u) visiting
+// order and the arithmetic are those of lane_point, so results match the
+// point kernel bit for bit.
+
+// Accumulate the rows [c0, c1) of the table for the M masses of one wave.
+template <int M>
+__device__ __forceinline__ void grid_rows(const GridArgs &g, const double *lH, const double *lc,
+                                          const double *lq, const double *lm, int c0, int c1,
+                                          int lane, const double *dm, unsigned four_mask, int &t,
+                                          int &u, double *A, double *in, double *tot) {
+  const int rho = lane & (g.R - 1);
+  const int iota = lane / g.R;
+  const int n_r = g.n_r, n_a = g.n_a;
+  int tu = c0;
+  while (tu < c1) {
+    if (u == 0) {
+      const int i = rho + g.R * t;
+      const bool vi = i < n_r;
+      const double c = vi ? lc[i] : 0.0;
+      const double Hq = vi ? lq[i] : 1.0;
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const double Gq = rcp64(Hq + dm[m]);
+        A[m] = (c * Gq) * Gq;
+        in[m] = 0.0;
+      }
+    }
+    if (u + 4 <= g.U && tu + 4 <= c1) {
+      double H[4], mu[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int j = iota + g.J * (u + k);
+        mu[k] = j < n_a ? lm[j] : 0.0;
+        H[k] = lH[(tu + k - c0) * kWave + lane];
+      }
+      if (four_mask == (M == 32 ? ~0u : ((1u << M) - 1u))) {
+        // common case: every mass takes the four-term form (no branches)
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+          in[m] = sum4(H[0] + dm[m], H[1] + dm[m], H[2] + dm[m], H[3] + dm[m], mu[0], mu[1],
+                       mu[2], mu[3], in[m]);
+      } else {
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        if ((four_mask >> m) & 1u) {
+          in[m] = sum4(H[0] + dm[m], H[1] + dm[m], H[2] + dm[m], H[3] + dm[m], mu[0], mu[1],
+                       mu[2], mu[3], in[m]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) in[m] = __builtin_fma(mu[k], rcp64(H[k] + dm[m]), in[m]);
+        }
+      }
+      }
+      u += 4;
+      tu += 4;
+    } else {
+      const int j = iota + g.J * u;
+      const double mu = j < n_a ? lm[j] : 0.0;
+      const double H = lH[(tu - c0) * kWave + lane];
+#pragma unroll
+      for (int m = 0; m < M; ++m) in[m] = __builtin_fma(mu, rcp64(H + dm[m]), in[m]);
+      ++u;
+      ++tu;
+    }
+    if (u == g.U) {
+#pragma unroll
+      for (int m = 0; m < M; ++m) tot[m] = __builtin_fma(A[m], in[m], tot[m]);
+      u = 0;
+      ++t;
+    }
+  }
+}
+
+// End of the LDS chunk that starts at row c0: at most C rows, moved back to
+// a group-of-four boundary so that no four-term group is split (C >= 8).
+__device__ __forceinline__ int chunk_end(const GridArgs &g, int c0, int C, int TU) {
+  int c1 = c0 + C < TU ? c0 + C : TU;
+  if (c1 < TU) {
+    const int t1 = c1 / g.U, u1 = c1 - t1 * g.U;
+    const int grouped = g.U - (g.U & 3);
+    if (u1 < grouped) c1 = t1 * g.U + (u1 & ~3);
+  }
+  return c1;
+}
+
+template <int REG>
+__device__ __forceinline__ void grid_fill(const GridArgs &g, double *lH, int c0, int c1, double p) {
+  const double *tq = g.tab;
+  const double *to = g.tab + 3 * g.n_r;
+  for (int idx = threadIdx.x; idx < (c1 - c0) * kWave; idx += blockDim.x) {
+    const int l = idx & (kWave - 1);
+    const int tu = c0 + idx / kWave;
+    const int tt = tu / g.U, uu = tu - tt * g.U;
+    const int i = (l & (g.R - 1)) + g.R * tt;
+    const int j = (l / g.R) + g.J * uu;
+    double v = 1.0;
+    if (i < g.n_r && j < g.n_a) {
+      const double q = tq[i];
+      const double qm = q - p;
+      const double aa = qm * qm;
+      const double b = (2.0 * q) * p;
+      v = hk<REG>(__builtin_fma(b, to[j], aa), g.k2, g.inv_k2);
+    }
+    lH[idx] = v;
+  }
+}
+
 template <int REG, int M>
 __global__ __launch_bounds__(512) void grid_kernel(GridArgs g) {
   extern __shared__ double lds[];
@@ -202,98 +215,69 @@ __global__ __launch_bounds__(512) void grid_kernel(GridArgs g) {
   const int mb = (int)(blockIdx.x - a * g.n_mb);
   const double p = g.p[a];
   const int n_r = g.n_r, n_a = g.n_a;
-  const double *tq = g.tab;
-  const double *tc = g.tab + n_r;
-  const double *tH = g.tab + 2 * n_r;
-  const double *to = g.tab + 3 * n_r;
-  const double *tm = to + n_a;
   const int TU = g.T * g.U;
-  const int C = g.chunk < TU ? g.chunk : TU;
+  const bool resident = TU <= g.chunk;
+  const int C = resident ? TU : g.chunk;
+  const int MB = resident ? g.mblocks : 1;
   double *lH = lds;
   double *lc = lH + C * kWave;
   double *lq = lc + n_r;
   double *lm = lq + n_r;
   for (int idx = threadIdx.x; idx < n_r; idx += blockDim.x) {
-    lc[idx] = tc[idx];
-    lq[idx] = tH[idx];
+    lc[idx] = g.tab[n_r + idx];
+    lq[idx] = g.tab[2 * n_r + idx];
   }
-  for (int idx = threadIdx.x; idx < n_a; idx += blockDim.x) lm[idx] = tm[idx];
-
-  const int64_t m0 = ((int64_t)mb * W + wave) * M;
-  const bool p_ok = p >= 0.0;
-  double dm[M];
-  bool ok[M];
-#pragma unroll
-  for (int m = 0; m < M; ++m) {
-    const int64_t idx = m0 + m;
-    const bool valid = idx < g.n_m;
-    const double d = valid ? g.m2[idx] + g.k2 : 1.0;
-    ok[m] = valid && p_ok && d > 0.0;
-    dm[m] = ok[m] ? d : 1.0;
-  }
-  const int rho = lane & (g.R - 1);
-  const int iota = lane / g.R;
-  double tot[M], A[M], in[M];
-#pragma unroll
-  for (int m = 0; m < M; ++m) tot[m] = A[m] = in[m] = 0.0;
-  int t = 0, u = 0;
-  for (int c0 = 0; c0 < TU; c0 += C) {
-    const int c1 = (c0 + C < TU) ? c0 + C : TU;
-    if (c0 > 0) __syncthreads();  // all waves are done with the previous chunk
-    for (int idx = threadIdx.x; idx < (c1 - c0) * kWave; idx += blockDim.x) {
-      const int l = idx & (kWave - 1);
-      const int tu = c0 + idx / kWave;
-      const int tt = tu / g.U, uu = tu - tt * g.U;
-      const int i = (l & (g.R - 1)) + g.R * tt;
-      const int j = (l / g.R) + g.J * uu;
-      double v = 1.0;
-      if (i < n_r && j < n_a) {
-        const double q = tq[i];
-        const double qm = q - p;
-        const double aa = qm * qm;
-        const double b = (2.0 * q) * p;
-        v = hk<REG>(__builtin_fma(b, to[j], aa), g.k2, g.inv_k2);
-      }
-      lH[idx] = v;
-    }
+  for (int idx = threadIdx.x; idx < n_a; idx += blockDim.x) lm[idx] = g.tab[3 * n_r + n_a + idx];
+  if (resident) {
+    grid_fill<REG>(g, lH, 0, TU, p);
     __syncthreads();
-    for (int tu = c0; tu < c1; ++tu) {
-      if (u == 0) {
-        const int i = rho + g.R * t;
-        const bool vi = i < n_r;
-        const double c = vi ? lc[i] : 0.0;
-        const double Hq = vi ? lq[i] : 1.0;
+  }
+  const bool p_ok = p >= 0.0;
+  for (int rep = 0; rep < MB; ++rep) {
+    const int64_t m0 = (((int64_t)mb * MB + rep) * W + wave) * M;
+    if (m0 >= g.n_m && resident) break;  // wave-uniform
+    double dm[M];
+    bool ok[M];
+    unsigned mask = 0;
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-          const double Gq = rcp64(Hq + dm[m]);
-          A[m] = (c * Gq) * Gq;
-          in[m] = 0.0;
-        }
-      }
-      const int j = iota + g.J * u;
-      const double mu = j < n_a ? lm[j] : 0.0;
-      const double H = lH[(tu - c0) * kWave + lane];
+    for (int m = 0; m < M; ++m) {
+      const int64_t idx = m0 + m;
+      const bool valid = idx < g.n_m;
+      const double d = valid ? g.m2[idx] + g.k2 : 1.0;
+      ok[m] = valid && p_ok && d > 0.0;
+      dm[m] = ok[m] ? d : 1.0;
+      mask |= four_ok(dm[m]) ? (1u << m) : 0u;
+    }
+    // the masses are the same in every lane: make the choice wave-uniform
+    const unsigned four_mask = __builtin_amdgcn_readfirstlane(mask);
+    double tot[M], A[M], in[M];
 #pragma unroll
-      for (int m = 0; m < M; ++m) in[m] = __builtin_fma(mu, rcp64(H + dm[m]), in[m]);
-      if (++u == g.U) {
-#pragma unroll
-        for (int m = 0; m < M; ++m) tot[m] = __builtin_fma(A[m], in[m], tot[m]);
-        u = 0;
-        ++t;
+    for (int m = 0; m < M; ++m) tot[m] = A[m] = in[m] = 0.0;
+    int t = 0, u = 0;
+    if (resident) {
+      grid_rows<M>(g, lH, lc, lq, lm, 0, TU, lane, dm, four_mask, t, u, A, in, tot);
+    } else {
+      for (int c0 = 0; c0 < TU;) {
+        const int c1 = chunk_end(g, c0, C, TU);
+        __syncthreads();  // previous chunk consumed; also orders the small tables
+        grid_fill<REG>(g, lH, c0, c1, p);
+        __syncthreads();
+        grid_rows<M>(g, lH, lc, lq, lm, c0, c1, lane, dm, four_mask, t, u, A, in, tot);
+        c0 = c1;
       }
     }
-  }
-  double res = 0.0;
-  bool bad = false;
+    double res = 0.0;
+    bool bad = false;
 #pragma unroll
-  for (int m = 0; m < M; ++m) {
-    const double v = g.pref * wave_sum(tot[m]);
-    const bool valid = m0 + m < g.n_m;
-    if (lane == m) res = ok[m] ? v : __builtin_nan("");
-    bad |= valid && !ok[m];
+    for (int m = 0; m < M; ++m) {
+      const double v = g.pref * wave_sum(tot[m]);
+      const bool valid = m0 + m < g.n_m;
+      if (lane == m) res = ok[m] ? v : __builtin_nan("");
+      bad |= valid && !ok[m];
+    }
+    if (bad && lane == 0) *g.flag = 1;
+    if (lane < M && m0 + lane < g.n_m) g.out[a * g.n_m + m0 + lane] = res;
   }
-  if (bad && lane == 0) *g.flag = 1;
-  if (lane < M && m0 + lane < g.n_m) g.out[a * g.n_m + m0 + lane] = res;
 }
 
 // Coefficient of U[j+o] in U' (c1) and U'' (c2) of the difference formulas.

@@ -1,0 +1,348 @@
+// Flow server behind frg_submit / frg_poll.
+//
+// Admission: a submitted flow waits in a FIFO queue until a slot is free
+// and its device footprint (U, dU/dt and the 7 Jacobian bands, resident for
+// the flow's lifetime) fits the context's HBM budget.
+//
+// Execution: every admitted flow runs the FP64 host stepper in its own
+// thread.  Its right-hand-side calls are handed to one dispatcher thread,
+// which takes ALL calls pending at that moment -- from any mix of flows,
+// grid sizes and N -- and serves them with one batched LPA launch on the
+// server's stream (continuous batching: flows join and leave at the
+// granularity of a right-hand-side call, and calls that arrive while a batch
+// is on the GPU form the next batch).  A flow's result does not depend on
+// which flows shared its launches: the kernel evaluates each grid point of
+// each flow independently, in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <condition_variable>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "frg_ctx.h"
+
+namespace frg {
+
+int solve_flow(const frg_request &rq, frg_rhs_fn rhs, void *user, frg_result *res);
+
+struct Server;
+
+struct Flow {
+  Server *srv = nullptr;
+  uint64_t ticket = 0;
+  frg_request req{};
+  frg_result res{};
+  int64_t n = 0;
+  int64_t bytes = 0;
+  double *h_U = nullptr;    // pinned: U for the next call
+  double *h_out = nullptr;  // pinned: dU/dt (n) then the bands (7n)
+  double *d_U = nullptr;    // device, resident
+  double *d_out = nullptr;  // device, resident
+  // right-hand-side hand-off
+  double t = 0.0;
+  bool want_jac = false;
+  bool ready = false;
+  int rc = FRG_OK;
+  bool done = false;
+  std::condition_variable cv;
+  std::thread th;
+};
+
+struct Server {
+  Context *ctx = nullptr;
+  hipStream_t stream = nullptr;
+  int *d_flags = nullptr;
+  int *h_flags = nullptr;
+  int flag_cap = 0;
+  std::mutex m;
+  std::condition_variable cv_disp;
+  std::deque<Flow *> queue;
+  std::vector<Flow *> pending;
+  std::map<uint64_t, Flow *> flows;
+  uint64_t next_ticket = 1;
+  int active = 0;
+  int max_active = 64;
+  size_t max_queue = 65536;
+  uint64_t budget = 0;
+  uint64_t used = 0;
+  bool stop = false;
+  std::thread disp;
+  int64_t flows_done = 0, launches = 0, batched = 0;
+
+  int start();
+  void shutdown();
+  void dispatch_loop();
+  void admit_locked();
+  static int rhs_cb(void *user, double t, const double *U, int64_t n, double *dUdt, double *jac);
+  void run_flow(Flow *f);
+  void release(Flow *f);
+};
+
+int Server::start() {
+  if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess)
+    return fail(FRG_E_DEVICE, "server stream");
+  if (const char *e = std::getenv("FRG_SERVER_SLOTS")) max_active = std::max(1, std::atoi(e));
+  disp = std::thread([this] { dispatch_loop(); });
+  return FRG_OK;
+}
+
+void Server::shutdown() {
+  {
+    std::lock_guard<std::mutex> lk(m);
+    stop = true;
+    for (auto &kv : flows) kv.second->cv.notify_all();
+  }
+  cv_disp.notify_all();
+  if (disp.joinable()) disp.join();
+  for (auto &kv : flows) {
+    if (kv.second->th.joinable()) kv.second->th.join();
+    release(kv.second);
+    delete kv.second;
+  }
+  flows.clear();
+  for (Flow *f : queue) delete f;
+  queue.clear();
+  if (d_flags) hipFree(d_flags);
+  if (h_flags) hipHostFree(h_flags);
+  if (stream) hipStreamDestroy(stream);
+}
+
+void Server::release(Flow *f) {
+  if (f->d_U) hipFree(f->d_U);
+  if (f->d_out) hipFree(f->d_out);
+  if (f->h_U) hipHostFree(f->h_U);
+  if (f->h_out) hipHostFree(f->h_out);
+  f->d_U = f->d_out = f->h_U = f->h_out = nullptr;
+}
+
+// Under m: start queued flows while slots and budget allow (strict FIFO).
+void Server::admit_locked() {
+  if (!queue.empty()) hipSetDevice(ctx->device);
+  while (!queue.empty() && active < max_active && !stop) {
+    Flow *f = queue.front();
+    if (used + (uint64_t)f->bytes > budget) break;
+    const size_t n = (size_t)f->n;
+    bool ok = hipMalloc(&f->d_U, n * sizeof(double)) == hipSuccess &&
+              hipMalloc(&f->d_out, 8 * n * sizeof(double)) == hipSuccess &&
+              hipHostMalloc(&f->h_U, n * sizeof(double), hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&f->h_out, 8 * n * sizeof(double), hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+      release(f);
+      break;  // retry when another flow frees memory
+    }
+    queue.pop_front();
+    used += f->bytes;
+    ++active;
+    f->res.start_s = now_s();
+    f->th = std::thread([this, f] { run_flow(f); });
+  }
+}
+
+int Server::rhs_cb(void *user, double t, const double *U, int64_t n, double *dUdt, double *jac) {
+  Flow *f = static_cast<Flow *>(user);
+  Server *s = f->srv;
+  std::memcpy(f->h_U, U, n * sizeof(double));
+  {
+    std::unique_lock<std::mutex> lk(s->m);
+    if (s->stop) return FRG_E_DEVICE;
+    f->t = t;
+    f->want_jac = jac != nullptr;
+    f->ready = false;
+    s->pending.push_back(f);
+    s->cv_disp.notify_one();
+    f->cv.wait(lk, [&] { return f->ready || s->stop; });
+    if (!f->ready) return FRG_E_DEVICE;
+  }
+  std::memcpy(dUdt, f->h_out, n * sizeof(double));
+  if (jac) std::memcpy(jac, f->h_out + n, 7 * n * sizeof(double));
+  return f->rc;
+}
+
+void Server::run_flow(Flow *f) {
+  frg_result r{};
+  solve_flow(f->req, &Server::rhs_cb, f, &r);
+  std::lock_guard<std::mutex> lk(m);
+  f->res.status = r.status;
+  f->res.steps = r.steps;
+  f->res.rejected = r.rejected;
+  f->res.rhs_calls = r.rhs_calls;
+  f->res.t_reached = r.t_reached;
+  f->res.done_s = now_s();
+  f->done = true;
+  used -= f->bytes;
+  --active;
+  ++flows_done;
+  admit_locked();
+}
+
+void Server::dispatch_loop() {
+  std::vector<Flow *> batch;
+  std::vector<frg_lpa> lpas;
+  std::vector<double> ts;
+  std::vector<const double *> Us;
+  std::vector<double *> Ds, Js;
+  hipSetDevice(ctx->device);
+  for (;;) {
+    batch.clear();
+    {
+      std::unique_lock<std::mutex> lk(m);
+      cv_disp.wait(lk, [&] { return !pending.empty() || stop; });
+      if (stop) return;
+      batch.swap(pending);
+    }
+    const int nb = (int)batch.size();
+    if (nb > flag_cap) {
+      if (d_flags) hipFree(d_flags);
+      if (h_flags) hipHostFree(h_flags);
+      flag_cap = std::max(64, 2 * nb);
+      hipMalloc(&d_flags, flag_cap * sizeof(int));
+      hipHostMalloc(&h_flags, flag_cap * sizeof(int), hipHostMallocDefault);
+    }
+    lpas.resize(nb);
+    ts.resize(nb);
+    Us.resize(nb);
+    Ds.resize(nb);
+    Js.resize(nb);
+    for (int i = 0; i < nb; ++i) {
+      Flow *f = batch[i];
+      lpas[i] = f->req.lpa;
+      ts[i] = f->t;
+      Us[i] = f->d_U;
+      Ds[i] = f->d_out;
+      Js[i] = f->want_jac ? f->d_out + f->n : nullptr;
+      hipMemcpyAsync(f->d_U, f->h_U, f->n * sizeof(double), hipMemcpyHostToDevice, stream);
+    }
+    hipMemsetAsync(d_flags, 0, nb * sizeof(int), stream);
+    int rc;
+    {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      rc = ctx->lpa_jobs(nb, lpas.data(), ts.data(), Us.data(), Ds.data(), Js.data(), d_flags,
+                         stream);
+    }
+    for (int i = 0; i < nb; ++i) {
+      Flow *f = batch[i];
+      hipMemcpyAsync(f->h_out, f->d_out, (f->want_jac ? 8 : 1) * f->n * sizeof(double),
+                     hipMemcpyDeviceToHost, stream);
+    }
+    hipMemcpyAsync(h_flags, d_flags, nb * sizeof(int), hipMemcpyDeviceToHost, stream);
+    const bool ok = hipStreamSynchronize(stream) == hipSuccess && rc == FRG_OK;
+    std::lock_guard<std::mutex> lk(m);
+    ++launches;
+    batched += nb;
+    for (int i = 0; i < nb; ++i) {
+      Flow *f = batch[i];
+      f->rc = !ok ? FRG_E_DEVICE : (h_flags[i] ? FRG_E_DOMAIN : FRG_OK);
+      f->ready = true;
+      f->cv.notify_one();
+    }
+  }
+}
+
+void Context::stop_server() {
+  if (!server) return;
+  server->shutdown();
+  delete server;
+  server = nullptr;
+}
+
+}  // namespace frg
+
+using namespace frg;
+
+extern "C" {
+
+int frg_submit(frg_ctx *ctx, const frg_request *req, uint64_t *ticket) {
+  if (!ctx || !req || !ticket) return fail(FRG_E_INVAL, "NULL argument");
+  int rc = check_lpa(req->lpa);
+  if (rc) return rc;
+  if (!req->U_out) return fail(FRG_E_INVAL, "U_out is NULL");
+  if (!std::isfinite(req->t_end) || req->t_end > 0.0) return fail(FRG_E_INVAL, "t_end must be <= 0");
+  if (!std::isfinite(req->lambda) || !std::isfinite(req->rho0))
+    return fail(FRG_E_INVAL, "bad initial potential");
+  Server *s;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!ctx->server) {
+      auto *ns = new Server();
+      ns->ctx = ctx;
+      ns->budget = ctx->hbm_budget;
+      hipSetDevice(ctx->device);
+      rc = ns->start();
+      if (rc) {
+        delete ns;
+        return rc;
+      }
+      ctx->server = ns;
+    }
+    s = ctx->server;
+  }
+  const int64_t bytes = frg_flow_footprint(&req->lpa);
+  std::lock_guard<std::mutex> lk(s->m);
+  if ((uint64_t)bytes > s->budget)
+    return fail(FRG_E_NOMEM, "flow footprint %lld B exceeds the HBM budget", (long long)bytes);
+  if (s->queue.size() >= s->max_queue) return fail(FRG_E_AGAIN, "submission queue full");
+  Flow *f = new Flow();
+  f->srv = s;
+  f->ticket = s->next_ticket++;
+  f->req = *req;
+  f->n = req->lpa.n_grid;
+  f->bytes = bytes;
+  f->res.status = FRG_PENDING;
+  f->res.submit_s = now_s();
+  s->flows[f->ticket] = f;
+  s->queue.push_back(f);
+  s->admit_locked();
+  *ticket = f->ticket;
+  clear_error();
+  return FRG_OK;
+}
+
+int frg_poll(frg_ctx *ctx, uint64_t ticket, frg_result *out) {
+  if (!ctx || !out) return fail(FRG_E_INVAL, "NULL argument");
+  Server *s = ctx->server;
+  if (!s) return fail(FRG_E_NOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  Flow *f;
+  {
+    std::lock_guard<std::mutex> lk(s->m);
+    auto it = s->flows.find(ticket);
+    if (it == s->flows.end()) return fail(FRG_E_NOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    f = it->second;
+    if (!f->done) {
+      *out = f->res;
+      out->status = FRG_PENDING;
+      return FRG_PENDING;
+    }
+    s->flows.erase(it);
+  }
+  if (f->th.joinable()) f->th.join();
+  *out = f->res;
+  s->release(f);
+  delete f;
+  clear_error();
+  return FRG_OK;
+}
+
+int frg_server_stats(frg_ctx *ctx, int64_t *flows_done, int64_t *launches, double *mean_batch) {
+  if (!ctx) return fail(FRG_E_INVAL, "ctx is NULL");
+  Server *s = ctx->server;
+  int64_t d = 0, l = 0, b = 0;
+  if (s) {
+    std::lock_guard<std::mutex> lk(s->m);
+    d = s->flows_done;
+    l = s->launches;
+    b = s->batched;
+  }
+  if (flows_done) *flows_done = d;
+  if (launches) *launches = l;
+  if (mean_batch) *mean_batch = l ? (double)b / (double)l : 0.0;
+  return FRG_OK;
+}
+
+}  // extern "C"

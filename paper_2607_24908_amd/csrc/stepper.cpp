@@ -12,7 +12,10 @@
 // the third divided difference over four solution points; BDF1 residual
 // -h^2 y''/2 with y'' from the second divided difference.  Weighted RMS norm
 // with weights atol + rtol max(|y_n|, |y_{n+1}|).  A right-hand side that
-// reports a domain violation (a mass crossing the pole) rejects the step.
+// reports a domain violation (a mass crossing the pole) rejects the step;
+// when such rejections drive the step below 1e-8 |t_end| the flow has run
+// into the singularity m^2 = -k^2 and ends with FRG_E_DOMAIN.  U_out always
+// holds the last accepted state and t_reached its RG time.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -122,6 +125,7 @@ int solve_flow(const frg_request &rq, frg_rhs_fn rhs, void *user, frg_result *re
   }
   if (!(t_end < 0.0)) {
     std::memcpy(rq.U_out, y.data(), n * sizeof(double));
+    res->t_reached = 0.0;
     res->status = FRG_OK;
     return FRG_OK;
   }
@@ -136,6 +140,8 @@ int solve_flow(const frg_request &rq, frg_rhs_fn rhs, void *user, frg_result *re
     res->rhs_calls++;
     return rhs(user, t, u.data(), n, f.data(), want_jac ? jac.data() : nullptr);
   };
+  res->t_reached = 0.0;
+  std::memcpy(rq.U_out, y.data(), n * sizeof(double));
   int rc = call(0.0, y, false);
   if (rc != FRG_OK) {
     res->status = rc;
@@ -153,6 +159,7 @@ int solve_flow(const frg_request &rq, frg_rhs_fn rhs, void *user, frg_result *re
   h = std::min(h, -1e-10);
   std::vector<double> f0 = f;
   const double hmin = 1e-13 * std::fabs(t_end);
+  const double hmin_pole = 1e-8 * std::fabs(t_end);
   double t = 0.0;
   BandLU lu;
   const bool dbg = std::getenv("FRG_STEPPER_DEBUG") != nullptr;
@@ -214,9 +221,12 @@ int solve_flow(const frg_request &rq, frg_rhs_fn rhs, void *user, frg_result *re
       if (dbg) std::fprintf(stderr, "reject newton t=%.17g h=%.3e domain=%d\n", t, h, (int)domain);
       res->rejected++;
       h *= domain ? 0.25 : 0.3;
-      if (std::fabs(h) < hmin) {
-        res->status = FRG_E_STEP;
-        return FRG_E_STEP;
+      // a flow whose steps collapse on pole crossings has reached the
+      // singularity m^2 = -k^2 of the propagator: it ends there
+      const double floor = domain ? hmin_pole : hmin;
+      if (std::fabs(h) < floor) {
+        res->status = domain ? FRG_E_DOMAIN : FRG_E_STEP;
+        return res->status;
       }
       continue;
     }
@@ -259,6 +269,8 @@ int solve_flow(const frg_request &rq, frg_rhs_fn rhs, void *user, frg_result *re
     // --- accept
     t += h;
     res->steps++;
+    res->t_reached = t;
+    std::memcpy(rq.U_out, ynew.data(), n * sizeof(double));
     yh[2].swap(yh[1]);
     yh[1].swap(yh[0]);
     yh[0] = ynew;
@@ -277,7 +289,6 @@ int solve_flow(const frg_request &rq, frg_rhs_fn rhs, void *user, frg_result *re
     h = hn;
   }
   (void)hprev2;
-  std::memcpy(rq.U_out, yh[0].data(), n * sizeof(double));
   res->status = FRG_OK;
   return FRG_OK;
 }
@@ -295,7 +306,9 @@ extern "C" int frg_flow_solve(const frg_request *req, frg_rhs_fn rhs, void *user
   out->submit_s = out->start_s = now_s();
   rc = solve_flow(*req, rhs, user, out);
   out->done_s = now_s();
-  if (rc != FRG_OK) return fail(rc, "flow failed (status %d) after %lld steps", rc, (long long)out->steps);
+  if (rc != FRG_OK)
+    return fail(rc, "flow stopped (status %d) at t = %.6g after %lld steps", rc, out->t_reached,
+                (long long)out->steps);
   clear_error();
   return FRG_OK;
 }

@@ -31,7 +31,7 @@ STATUS_NAMES = {0: "FRG_OK", 1: "FRG_PENDING", -1: "FRG_E_INVAL", -2: "FRG_E_DOM
 EXPORTS = ["frg_create", "frg_destroy", "frg_last_error", "frg_version", "frg_integrate",
            "frg_integrate_grid", "frg_flow_rhs", "frg_flow_rhs_batch", "frg_flow_solve",
            "frg_submit", "frg_poll", "frg_server_stats", "frg_gauss_legendre",
-           "frg_flow_footprint"]
+           "frg_flow_footprint", "frg_autotune", "frg_tune_set", "frg_tune_get"]
 
 
 class frg_quad(ctypes.Structure):
@@ -64,7 +64,8 @@ class frg_result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("steps", ctypes.c_int64), ("rejected", ctypes.c_int64),
                 ("rhs_calls", ctypes.c_int64), ("submit_s", ctypes.c_double),
-                ("start_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+                ("start_s", ctypes.c_double), ("done_s", ctypes.c_double),
+                ("t_reached", ctypes.c_double)]
 
 
 RHS_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_double,
@@ -111,6 +112,9 @@ def _load():
     L.frg_gauss_legendre.argtypes = [i32, vp, vp]
     L.frg_flow_footprint.argtypes = [ctypes.POINTER(frg_lpa)]
     L.frg_flow_footprint.restype = i64
+    L.frg_autotune.argtypes = [vp, i32, ctypes.c_char_p]
+    L.frg_tune_set.argtypes = [vp, ctypes.c_char_p, i32]
+    L.frg_tune_get.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(i32)]
     return L
 
 
@@ -259,6 +263,20 @@ def frg_gauss_legendre(n: int):
 
 def frg_flow_footprint(lpa: frg_lpa) -> int:
     return int(lib.frg_flow_footprint(ctypes.byref(lpa)))
+
+
+def frg_autotune(ctx, mode: int, cache_path: str | None = None):
+    return _check(lib.frg_autotune(ctx, mode, cache_path.encode() if cache_path else None))
+
+
+def frg_tune_set(ctx, key: str, value: int):
+    return _check(lib.frg_tune_set(ctx, key.encode(), int(value)))
+
+
+def frg_tune_get(ctx, key: str) -> int:
+    v = ctypes.c_int32()
+    _check(lib.frg_tune_get(ctx, key.encode(), ctypes.byref(v)))
+    return v.value
 
 
 def make_lpa(d=3, N=1, reg=FRG_REG_EXP, n_radial=64, q_max_over_k=6.0, Lambda=1.0, n_grid=128,
