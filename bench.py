@@ -28,15 +28,17 @@ sys.path.insert(0, ROOT)
 
 # ALU roofline of the FP64 path.  Issue rate of the FP64 VALU of MI355X:
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 lane-cycles/s.  Floor of
-# the per-evaluation work of the reciprocal sum sum_j mu_j / (H_j + delta):
-# 4 FP64 VALU operations per term (the add forming D, its product into the
-# common denominator P, and the product + FMA folding mu_j into the numerator
-# N), the quarter-rate reciprocal being shared by all terms of a group.
+# the per-evaluation work of the reciprocal sum sum_j 1/D'_j (mu_j folded
+# into D'_j = delta rmu_j + H'_j): 3 FP64 VALU operations per term (the FMA
+# forming D', the FMA N <- N D' + P and the product P <- P D' of the running
+# fraction), the quarter-rate reciprocal and its Newton step being shared by
+# a group of eight terms and left out of the floor.
 VALU_LANE_CYCLES = 256 * 4 * 16 * 2.4e9
-# HBM traffic of one grid_kernel launch from rocprofv3 FETCH_SIZE/WRITE_SIZE
-# (None until measured for the current kernel)
+# HBM bytes per grid_kernel launch from rocprofv3 FETCH_SIZE / WRITE_SIZE,
+# scaled by a 1 GiB device copy read the same way; None until the counters
+# have been taken on the current kernel.
 TRAFFIC = None
-CYCLES_PER_EVAL_FLOOR = 4
+CYCLES_PER_EVAL_FLOOR = 3
 PEAK_EVALS = VALU_LANE_CYCLES / CYCLES_PER_EVAL_FLOOR
 
 
@@ -49,7 +51,34 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device-to-device copy of 1 GiB (PMC traffic calibration)")
+    ap.add_argument("--only", choices=["uneven64", "uneven32"], default=None,
+                    help="profiling aid: run only --steps persistent launches of the uneven sets "
+                         "(FP64 or FP32C) and print their timing")
     return ap.parse_args()
+
+
+def only_uneven(prec_name, steps, warmup):
+    import torch
+    from paper_2607_24908_amd import frg, workloads
+    prec = frg.FRG_PREC_FP64 if prec_name == "uneven64" else frg.FRG_PREC_FP32C
+    ctx = frg.frg_create(0)
+    sets = workloads.uneven_sets(seed=0)
+    ds = [dict(quad=frg.make_quad(s.quad.d, s.quad.reg, s.quad.k, s.quad.q_max, s.quad.n_r,
+                                  s.quad.n_a, prec),
+               p=torch.as_tensor(s.p, device="cuda"), m2=torch.as_tensor(s.m2, device="cuda"),
+               out=torch.empty(s.p.size, dtype=torch.float64, device="cuda")) for s in sets]
+    evals = sum(s.n_evals for s in sets)
+    for _ in range(warmup):
+        frg.frg_integrate(ctx, ds, flags=frg.FRG_PERSISTENT)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        frg.frg_integrate(ctx, ds, flags=frg.FRG_PERSISTENT)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    frg.frg_destroy(ctx)
+    print(json.dumps({"only": prec_name, "steps": steps, "ms_per_launch": dt * 1e3,
+                      "evals_per_s": evals / dt}), flush=True)
 
 
 def log(msg):
@@ -85,6 +114,9 @@ def main():
               "(integral sets and flows shard across GPUs with no exchange; see DESIGN.md)",
               file=sys.stderr)
         sys.exit(2)
+    if args.only:
+        only_uneven(args.only, args.steps, args.warmup)
+        return
     import torch
     from paper_2607_24908_amd import frg, workloads
     assert torch.cuda.is_available(), "no GPU"
@@ -140,8 +172,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_EVALS / 1e9,
                      "unit": "Geval/s", "frac": achieved * 1e9 / PEAK_EVALS, "traffic": TRAFFIC,
                      "kernel": "grid_kernel<exp>", "kernel_ms": gpu_ms,
-                     "evals_per_launch": int(w.n_evals),
-                     "peak_basis": "FP64 VALU 3.93e13 lane-cycles/s / 4 cycles per eval"},
+                     "evals_per_launch": int(w.n_evals), "traffic_unit": "bytes per launch",
+                     "peak_basis": "FP64 VALU 3.93e13 lane-cycles/s / 3 cycles per eval"},
     }
     if not args.no_secondary:
         line["secondary"] = secondary(ctx, frg, workloads, torch)
@@ -211,15 +243,19 @@ def secondary(ctx, frg, workloads, torch):
                          used_fp64=torch.empty(d["out"].numel(), dtype=torch.uint8,
                                                device="cuda")))
     t32 = timed(lambda: frg.frg_integrate(ctx, ds32, flags=frg.FRG_PLAIN), torch)
+    t32g = timed(lambda: frg.frg_integrate(ctx, ds32, flags=frg.FRG_PERSISTENT | frg.FRG_GRAPH),
+                 torch)
     frg.frg_integrate(ctx, ds, flags=frg.FRG_PLAIN)
     torch.cuda.synchronize()
     dev_max = max(((a["out"] - b["out"]).abs() / b["out"]).max().item() for a, b in zip(ds32, ds))
     share = sum((a["used_fp64"] == 0).sum().item() for a in ds32) / n_int
     sec["fp32c_uneven_sets_seed0"] = {
-        "fp32c_plain_evals_per_s": evals / t32, "fp64_plain_evals_per_s": evals / t_plain,
+        "fp32c_plain_evals_per_s": evals / t32, "fp32c_graph_evals_per_s": evals / t32g,
+        "fp32c_graph_integrals_per_s": n_int / t32g, "fp64_plain_evals_per_s": evals / t_plain,
         "fp64_graph_evals_per_s": evals / t_graph, "fp32_share": share,
         "max_rel_dev_vs_fp64": dev_max}
-    log(f"fp32c uneven: {evals / t32:.3e} evals/s (fp64 plain {evals / t_plain:.3e}), "
+    log(f"fp32c uneven: plain {evals / t32:.3e}, graph {evals / t32g:.3e} evals/s "
+        f"(fp64 plain {evals / t_plain:.3e}, graph {evals / t_graph:.3e}), "
         f"fp32 share {share:.2f}, max dev {dev_max:.2e}")
     # compensated FP32 on grids (precision workload: half the masses near the
     # pole); deviation measured against the FP64 kernel's result

@@ -234,6 +234,8 @@ int Ctx::make_setdev(const frg_set &s, SetDev *out) {
   d.k2 = h.k2;
   d.inv_k2 = h.inv_k2;
   d.pref = h.pref;
+  d.q_top = h.q_top;
+  d.rmu_max = h.rmu_max;
   d.n_ext = s.n_ext;
   d.n_r = s.quad.n_radial;
   d.n_a = s.quad.n_angular;
@@ -253,9 +255,9 @@ int Ctx::integrate_device(const frg_set *sets, int n_sets, int flags, hipStream_
     int rc = make_setdev(sets[i], &sd[i]);
     if (rc) return rc;
   }
-  for (int i = 0; i < n_sets; ++i)
-    if (sd[i].prec == FRG_PREC_FP32C) return integrate_fp32c_sets(sd, flags, st);
   if (!(flags & FRG_PERSISTENT)) {
+    for (int i = 0; i < n_sets; ++i)
+      if (sd[i].prec == FRG_PREC_FP32C) return integrate_fp32c_sets(sd, flags, st);
     for (int i = 0; i < n_sets; ++i) {
       if (sd[i].n_ext == 0) continue;
       int e = launch_points_plain(sd[i], plain_tile_for(sd[i], st), d_flag, st);
@@ -270,7 +272,8 @@ int Ctx::integrate_device(const frg_set *sets, int n_sets, int flags, hipStream_
 void build_tiles(const std::vector<SetDev> &sd, int tile, std::vector<Tile> *tiles) {
   std::vector<std::pair<double, Tile>> tw;
   for (int i = 0; i < (int)sd.size(); ++i) {
-    const double per = (sd[i].reg == FRG_REG_EXP ? 5.0 : 1.0) * sd[i].n_r * sd[i].n_a;
+    const double w = sd[i].reg == FRG_REG_EXP ? (sd[i].prec == FRG_PREC_FP32C ? 2.0 : 5.0) : 1.0;
+    const double per = w * sd[i].n_r * sd[i].n_a;
     for (int64_t st = 0; st < sd[i].n_ext; st += tile) {
       Tile t;
       t.set = i;
@@ -285,10 +288,22 @@ void build_tiles(const std::vector<SetDev> &sd, int tile, std::vector<Tile> *til
   for (size_t i = 0; i < tw.size(); ++i) (*tiles)[i] = tw[i].second;
 }
 
-int max_table_doubles(const std::vector<SetDev> &sd) {
-  int m = 0;
-  for (auto &s : sd) m = std::max(m, 3 * s.n_r + 2 * s.n_a);
-  return m;
+bool any_fp32c(const std::vector<SetDev> &sd) {
+  for (auto &s : sd)
+    if (s.prec == FRG_PREC_FP32C) return true;
+  return false;
+}
+
+// LDS bytes the persistent kernel needs for the largest table of the batch
+// (FP32C sets add their FP32 angular tables).
+int max_table_bytes(const std::vector<SetDev> &sd) {
+  size_t m = 0;
+  for (auto &s : sd) {
+    size_t b = sizeof(double) * table_doubles(s.n_r, s.n_a);
+    if (s.prec == FRG_PREC_FP32C) b += sizeof(float) * 3 * s.n_a;
+    m = std::max(m, b);
+  }
+  return (int)m;
 }
 
 uint64_t batch_signature(const frg_set *sets, int n_sets) {
@@ -330,8 +345,8 @@ int Ctx::persistent(const std::vector<SetDev> &sd, const frg_set *sets, int n_se
   std::vector<Tile> tiles;
   build_tiles(sd, pc.tile, &tiles);
   if (tiles.empty()) return FRG_OK;
-  const int lds = max_table_doubles(sd);
-  if (lds * 8 > 64 * 1024) return fail(FRG_E_INVAL, "quadrature tables exceed 64 KiB of LDS");
+  const int lds = max_table_bytes(sd);
+  if (lds > 64 * 1024) return fail(FRG_E_INVAL, "quadrature tables exceed 64 KiB of LDS");
   const int n_blocks = std::max(1, std::min<int>((int)tiles.size(), n_cu * pc.wpc));
   if (graph) {
     auto g = std::make_unique<GraphEntry>();
@@ -348,7 +363,7 @@ int Ctx::persistent(const std::vector<SetDev> &sd, const frg_set *sets, int n_se
     int e1 = launch_reset_counter((int *)g->counter.ptr, cap_stream);
     int e2 = launch_points_persistent((const SetDev *)g->sets.ptr, (const Tile *)g->tiles.ptr,
                                       (int)tiles.size(), (int *)g->counter.ptr, lds, n_blocks,
-                                      d_flag, cap_stream);
+                                      any_fp32c(sd), d_flag, cap_stream);
     hipGraph_t graph_h = nullptr;
     e = hipStreamEndCapture(cap_stream, &graph_h);
     if (e1 || e2 || e != hipSuccess) {
@@ -371,7 +386,7 @@ int Ctx::persistent_eager(const std::vector<SetDev> &sd, const PersistCfg &pc, h
   std::vector<Tile> tiles;
   build_tiles(sd, pc.tile, &tiles);
   if (tiles.empty()) return FRG_OK;
-  const int lds = max_table_doubles(sd);
+  const int lds = max_table_bytes(sd);
   const int n_blocks = std::max(1, std::min<int>((int)tiles.size(), n_cu * pc.wpc));
   std::vector<char> blob(sd.size() * sizeof(SetDev) + tiles.size() * sizeof(Tile));
   std::memcpy(blob.data(), sd.data(), sd.size() * sizeof(SetDev));
@@ -384,7 +399,7 @@ int Ctx::persistent_eager(const std::vector<SetDev> &sd, const PersistCfg &pc, h
   const Tile *d_tiles = (const Tile *)((char *)dev + sd.size() * sizeof(SetDev));
   int e1 = launch_reset_counter(d_counter, st);
   int e2 = launch_points_persistent(d_sets, d_tiles, (int)tiles.size(), d_counter, lds, n_blocks,
-                                    d_flag, st);
+                                    any_fp32c(sd), d_flag, st);
   rc = ring.release(slot, st);
   if (e1 || e2) return fail(FRG_E_DEVICE, "persistent launch failed");
   return rc;
@@ -465,6 +480,8 @@ int Ctx::grid_device(const frg_quad &q, int64_t n_p, const double *p, int64_t n_
   g.k2 = h.k2;
   g.inv_k2 = h.inv_k2;
   g.pref = h.pref;
+  g.q_top = h.q_top;
+  g.rmu_max = h.rmu_max;
   g.n_p = n_p;
   g.n_m = n_m;
   g.n_r = q.n_radial;

@@ -16,15 +16,21 @@
 // depends only on (n_r, n_a): every kernel and tile choice below gives
 // bitwise-identical results for the same point.
 //
-// Reciprocal sums: the angular terms of one lane are taken four at a time,
-//   mu0/D0 + mu1/D1 + mu2/D2 + mu3/D3 = N/P,  P = (D0 D1)(D2 D3),
-//   N = (mu0 D1 + mu1 D0)(D2 D3) + (mu2 D3 + mu3 D2)(D0 D1),
-// so one reciprocal serves four terms (leftover u < U taken one by one).
-// Every D >= delta > 0, so N and P are sums of positive products; the form is
-// used when 1e-70 <= delta <= 1e70 (no over- or underflow of P), otherwise
-// each term gets its own reciprocal.  FP64 reciprocal: the hardware estimate
-// (v_rcp_f64, relative error < 2^-24) and one Newton-Raphson step
-// r <- r + r (1 - x r), relative error < 2.3e-15.
+// Reciprocal sums.  With mu folded into the denominators, mu_j / D_ij =
+// 1 / D'_ij,  D'_ij = fma(delta, rmu_j, H'_ij),  H'_ij = fl(Hk(s_ij) rmu_j),
+// rmu_j = 1/mu_j.  A lane takes its angular terms eight at a time by a running
+// fraction N/P of positive numbers:
+//   N <- 1, P <- D'_0;  then  N <- N D'_k + P,  P <- P D'_k  (k = 1..7),
+// so sum_k 1/D'_k = N/P costs one multiply and one FMA per term plus one
+// reciprocal per group.  The first G = 8 floor(floor(n_a/J)/8) values of u are
+// grouped (every lane holds a real node there); the rest are taken one by one
+// and padded nodes (j >= n_a) add nothing.  The grouped form is used when no
+// product can leave the normal range: delta >= 1e-30 and
+// ((q_top + p)^2 + delta) max_j rmu_j <= 1e37 (then 1e-243 < P, N < 1e297,
+// because Hk(s) <= s <= (q_top + p)^2); otherwise every term gets its own
+// reciprocal.  FP64 reciprocal: the hardware estimate (v_rcp_f64, relative
+// error < 2^-24) and one Newton-Raphson step r <- r + r (1 - x r), relative
+// error < 2.3e-15.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -47,23 +53,71 @@ __device__ __forceinline__ double rcp64(double x) {
   return __builtin_fma(r, e, r);
 }
 
-// mu/D for four terms with one reciprocal (see the header comment)
-__device__ __forceinline__ double sum4(double D0, double D1, double D2, double D3, double m0,
-                                       double m1, double m2, double m3, double acc) {
-  const double P01 = D0 * D1, P23 = D2 * D3;
-  const double N01 = __builtin_fma(m0, D1, m1 * D0);
-  const double N23 = __builtin_fma(m2, D3, m3 * D2);
-  const double P = P01 * P23;
-  const double N = __builtin_fma(N01, P23, N23 * P01);
+constexpr int kGroup = 8;
+
+// Running fraction of one group: returns acc + sum_k 1/Dp[k].
+__device__ __forceinline__ double chain_sum(const double *Dp, double acc) {
+  double N = 1.0, P = Dp[0];
+#pragma unroll
+  for (int k = 1; k < kGroup; ++k) {
+    N = __builtin_fma(N, Dp[k], P);
+    P = P * Dp[k];
+  }
   return __builtin_fma(N, rcp64(P), acc);
 }
 
-__device__ __forceinline__ bool four_ok(double delta) { return delta >= 1e-70 && delta <= 1e70; }
+// Whether the grouped form is safe for this point (same test in every kernel).
+__device__ __forceinline__ bool chain_ok(double delta, double p, double q_top, double rmu_max) {
+  const double qp = q_top + p;
+  return delta >= 1e-30 && __builtin_fma(qp, qp, delta) * rmu_max <= 1e37;
+}
+
+// Number of grouped angular steps u (a multiple of kGroup, <= U).
+__device__ __forceinline__ int grouped_u(int n_a, int J) {
+  const int umin = n_a / J;
+  return umin - umin % kGroup;
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
   return v;
+}
+
+// wave_sum of M values at once (M a power of two, 1..64).  The first log2 M
+// exchange steps halve the number of live values: at offset o a lane keeps
+// the half of its values selected by its bit o and receives the partner's
+// partial sums of that half; the remaining steps are the plain butterfly.
+// Every partial sum is the one wave_sum forms (own + partner at offsets
+// 32, 16, ..., 1), so lane l returns, bit for bit, wave_sum(v[l / (64/M)]).
+template <int M>
+__device__ __forceinline__ double wave_sum_split(const double *v, int lane) {
+  constexpr int kSteps = (M >= 64) ? 6 : (M >= 32) ? 5 : (M >= 16) ? 4 : (M >= 8) ? 3
+                                                        : (M >= 4) ? 2 : (M >= 2) ? 1 : 0;
+  static_assert((1 << kSteps) == M, "M must be a power of two <= 64");
+  double w[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) w[m] = v[m];
+#pragma unroll
+  for (int s = 0; s < kSteps; ++s) {
+    const int off = 32 >> s;
+    const int h = M >> (s + 1);
+    const bool upper = (lane & off) != 0;
+#pragma unroll
+    for (int k = 0; k < h; ++k) {
+      double lo = w[k], hi = w[h + k];
+      // pin both values in registers: a select between two loads of w would
+      // otherwise become one load at a lane-dependent index of w
+      asm("" : "+v"(lo), "+v"(hi));
+      const double keep = upper ? hi : lo;
+      const double send = upper ? lo : hi;
+      w[k] = keep + __shfl_xor(send, off, kWave);
+    }
+  }
+  double x = w[0];
+#pragma unroll
+  for (int s = kSteps; s < 6; ++s) x += __shfl_xor(x, 32 >> s, kWave);
+  return x;
 }
 
 // h(y) = y/(1 - e^{-y}) - 1; Bernoulli series y/2 + y^2/12 - y^4/720 + ...
@@ -99,10 +153,10 @@ __device__ __forceinline__ double lane_point(const double *__restrict__ tab, con
   const double *tc = tab + n_r;
   const double *tH = tab + 2 * n_r;
   const double *to = tab + 3 * n_r;
-  const double *tm = to + n_a;
+  const double *tr = to + 2 * n_a;
   const int rho = lane & (s.R - 1);
   const int iota = lane / s.R;
-  const bool four = four_ok(delta);
+  const int G = chain_ok(delta, p, s.q_top, s.rmu_max) ? grouped_u(n_a, s.J) : 0;
   double total = 0.0;
   for (int t = 0; t < s.T; ++t) {
     const int i = rho + s.R * t;
@@ -117,27 +171,24 @@ __device__ __forceinline__ double lane_point(const double *__restrict__ tab, con
     const double b = (2.0 * q) * p;
     double inner = 0.0;
     int u = 0;
-    if (four) {
-      for (; u + 4 <= s.U; u += 4) {
-        double D[4], mu[4];
+    for (; u < G; u += kGroup) {
+      double Dp[kGroup];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int j = iota + s.J * (u + k);
-          const bool vj = j < n_a;
-          mu[k] = vj ? tm[j] : 0.0;
-          D[k] = hk<REG>(__builtin_fma(b, vj ? to[j] : 1.0, a), s.k2, s.inv_k2) + delta;
-        }
-        inner = sum4(D[0], D[1], D[2], D[3], mu[0], mu[1], mu[2], mu[3], inner);
+      for (int k = 0; k < kGroup; ++k) {
+        const int j = iota + s.J * (u + k);
+        const double r = tr[j];
+        const double H = hk<REG>(__builtin_fma(b, to[j], a), s.k2, s.inv_k2) * r;
+        Dp[k] = __builtin_fma(delta, r, H);
       }
+      inner = chain_sum(Dp, inner);
     }
     for (; u < s.U; ++u) {
       const int j = iota + s.J * u;
-      const bool vj = j < n_a;
-      const double opx = vj ? to[j] : 1.0;
-      const double mu = vj ? tm[j] : 0.0;
-      const double sij = __builtin_fma(b, opx, a);
-      const double D = hk<REG>(sij, s.k2, s.inv_k2) + delta;
-      inner = __builtin_fma(mu, rcp64(D), inner);
+      if (j < n_a) {
+        const double r = tr[j];
+        const double H = hk<REG>(__builtin_fma(b, to[j], a), s.k2, s.inv_k2) * r;
+        inner = inner + rcp64(__builtin_fma(delta, r, H));
+      }
     }
     total = __builtin_fma(A, inner, total);
   }

@@ -21,7 +21,7 @@ double now_s();
 int check_quad(const frg_quad &q);
 int check_lpa(const frg_lpa &l);
 void build_tiles(const std::vector<SetDev> &sd, int tile, std::vector<Tile> *tiles);
-int max_table_doubles(const std::vector<SetDev> &sd);
+int max_table_bytes(const std::vector<SetDev> &sd);
 
 // Grow-only device allocation.
 struct DevBuf {
@@ -57,7 +57,7 @@ struct DescRing {
 // them per key with measured choices.  No launch shape changes a result.
 struct GridCfg {
   int M = 8;    // masses per wave
-  int W = 4;    // waves per workgroup
+  int W = 8;    // waves per workgroup
   int MB = 8;   // mass blocks per wave while the table is resident
 };
 struct PersistCfg {

@@ -17,14 +17,19 @@ constexpr int kWave = 64;
 int gauss_legendre_gw(int n, double *x, double *w);
 
 // Packed quadrature table of one (d, reg, k, q_max, n_r, n_a) key, float64:
-//   [0, n_r)          q_i               radial node
-//   [n_r, 2n_r)       c_i               w_i q_i^{d-1} d_tR(q_i^2)
-//   [2n_r, 3n_r)      Hq_i              k^2 h(q_i^2/k^2)   (stable denominator part)
-//   [3n_r, 3n_r+n_a)  opx_j             1 + x_j
-//   [.., +n_a)        mu_j              v_j (1 - x_j^2)^{(d-3)/2}
+//   [0, n_r)            q_i       radial node
+//   [n_r, 2n_r)         c_i       w_i q_i^{d-1} d_tR(q_i^2)
+//   [2n_r, 3n_r)        Hq_i      k^2 h(q_i^2/k^2)   (stable denominator part)
+//   [3n_r, 3n_r+n_a)    opx_j     1 + x_j
+//   [.., +n_a)          mu_j      v_j (1 - x_j^2)^{(d-3)/2}
+//   [.., +n_a)          rmu_j     1 / mu_j
+constexpr int table_doubles(int n_r, int n_a) { return 3 * n_r + 3 * n_a; }
+
 struct QuadTable {
   std::vector<double> data;
   double k2, inv_k2, pref;  // pref = P_d
+  double q_top;             // q_max: every radial node lies below it
+  double rmu_max;           // max_j rmu_j
   int n_r, n_a;
 };
 QuadTable build_quad_table(const frg_quad &q);
@@ -60,6 +65,7 @@ struct SetDev {
   int32_t T, U;  // ceil(n_r / R), ceil(n_a / J)
   double f32_flag;  // FP32C: error estimate above which a point is redone in FP64
   double f32_band;  // FP32C: delta/k^2 below which a point is done in FP64
+  double q_top, rmu_max;  // range test of the grouped reciprocal sums
 };
 
 struct Tile {
@@ -77,6 +83,7 @@ struct GridArgs {
   const double *tab;
   int *flag;
   double k2, inv_k2, pref;
+  double q_top, rmu_max;
   int64_t n_p, n_m;
   int32_t n_r, n_a, R, J, T, U;
   int32_t n_mb;     // workgroups per momentum
@@ -104,8 +111,8 @@ void lane_split(int n_r, int n_a, int *R, int *J, int *T, int *U);
 // All return hipError_t as int (0 = success).
 int launch_points_plain(const SetDev &s, int tile_points, int *d_flag, void *stream);
 int launch_points_persistent(const SetDev *d_sets, const Tile *d_tiles, int n_tiles,
-                             int *d_counter, int lds_doubles, int n_blocks, int *d_flag,
-                             void *stream);
+                             int *d_counter, int lds_bytes, int n_blocks, bool with_f32,
+                             int *d_flag, void *stream);
 int launch_reset_counter(int *d_counter, void *stream);
 int launch_grid(const GridArgs &g, int reg, int M, int W, void *stream);
 int grid_lds_bytes(const GridArgs &g);

@@ -10,6 +10,7 @@
 
 #pragma clang fp contract(off)
 
+#include "device_fp32c.h"
 #include "device_fp64.h"
 
 namespace frg {
@@ -40,7 +41,7 @@ __device__ void do_tile(const SetDev &s, const double *tab, int64_t start, int c
 }
 
 __device__ __forceinline__ void stage_table(const SetDev &s, double *lds, int tid, int nthreads) {
-  const int ntab = 3 * s.n_r + 2 * s.n_a;
+  const int ntab = table_doubles(s.n_r, s.n_a);
   for (int i = tid; i < ntab; i += nthreads) lds[i] = s.tab[i];
 }
 
@@ -61,8 +62,10 @@ __global__ __launch_bounds__(256) void points_plain_kernel(SetDev s, int tile_po
   do_tile<REG>(s, lds, start, count, lane, flag);
 }
 
-// Persistent launch over many sets: one wave per workgroup; waves pull
-// tiles (longest first) from an atomic counter until the list is drained.
+// Persistent launch over many sets (FP64 and FP32C mixed): one wave per
+// workgroup; waves pull tiles (longest first) from an atomic counter until
+// the list is drained.
+template <bool WITH_F32>
 __global__ __launch_bounds__(64) void points_persistent_kernel(const SetDev *__restrict__ sets,
                                                                const Tile *__restrict__ tiles,
                                                                int n_tiles, int *counter,
@@ -77,16 +80,29 @@ __global__ __launch_bounds__(64) void points_persistent_kernel(const SetDev *__r
     if (t >= n_tiles) break;
     const Tile tl = tiles[t];
     const SetDev s = sets[tl.set];
+    const bool f32 = WITH_F32 && s.prec == FRG_PREC_FP32C;
     if (tl.set != cur) {
       __syncthreads();
-      stage_table(s, lds, lane, kWave);
+      if (f32)
+        stage_fp32c(s, lds, lane, kWave);
+      else
+        stage_table(s, lds, lane, kWave);
       __syncthreads();
       cur = tl.set;
     }
-    if (s.reg == kExp)
+    if (f32) {
+      const float *fo = reinterpret_cast<const float *>(lds + table_doubles(s.n_r, s.n_a));
+      const float *fm = fo + s.n_a;
+      const float *fl = fm + s.n_a;
+      if (s.reg == kExp)
+        fp32c_tile<kExp>(s, lds, fo, fm, fl, tl.start, tl.count, 0, lane, flag);
+      else
+        fp32c_tile<kLitim>(s, lds, fo, fm, fl, tl.start, tl.count, 0, lane, flag);
+    } else if (s.reg == kExp) {
       do_tile<kExp>(s, lds, tl.start, tl.count, lane, flag);
-    else
+    } else {
       do_tile<kLitim>(s, lds, tl.start, tl.count, lane, flag);
+    }
   }
 }
 
@@ -96,21 +112,24 @@ __global__ void reset_counter_kernel(int *c) {
 
 // Tensor grid.  A workgroup of W waves owns one momentum p[a] and
 // W * M * MB consecutive masses; wave w takes mass blocks w, w + W, ... of M
-// masses each.  The table Hk(s_ij) of this p lives in LDS (lane-major,
-// conflict-free) and serves every mass block; tables larger than g.chunk
-// rows are streamed through LDS in chunks (then MB = 1).  The (t, u) visiting
-// order and the arithmetic are those of lane_point, so results match the
-// point kernel bit for bit.
+// masses each.  The table H'_ij = Hk(s_ij) rmu_j of this p lives in LDS
+// (lane-major, conflict-free) and serves every mass block; tables larger than
+// g.chunk rows are streamed through LDS in chunks (then MB = 1).  The (t, u)
+// visiting order, the grouping and the arithmetic are those of lane_point, so
+// results match the point kernel bit for bit.
 
 // Accumulate the rows [c0, c1) of the table for the M masses of one wave.
+// `gmask` bit m: mass m takes the grouped form.
 template <int M>
 __device__ __forceinline__ void grid_rows(const GridArgs &g, const double *lH, const double *lc,
-                                          const double *lq, const double *lm, int c0, int c1,
-                                          int lane, const double *dm, unsigned four_mask, int &t,
+                                          const double *lq, const double *lr, int c0, int c1,
+                                          int lane, const double *dm, unsigned gmask, int &t,
                                           int &u, double *A, double *in, double *tot) {
   const int rho = lane & (g.R - 1);
   const int iota = lane / g.R;
   const int n_r = g.n_r, n_a = g.n_a;
+  const int G = grouped_u(n_a, g.J);
+  const unsigned all = (M == 32) ? ~0u : ((1u << M) - 1u);
   int tu = c0;
   while (tu < c1) {
     if (u == 0) {
@@ -125,40 +144,47 @@ __device__ __forceinline__ void grid_rows(const GridArgs &g, const double *lH, c
         in[m] = 0.0;
       }
     }
-    if (u + 4 <= g.U && tu + 4 <= c1) {
-      double H[4], mu[4];
+    if (u < G) {
+      // a whole group lies in this chunk (chunk_end never splits one)
+      double H[kGroup], r[kGroup];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int j = iota + g.J * (u + k);
-        mu[k] = j < n_a ? lm[j] : 0.0;
+      for (int k = 0; k < kGroup; ++k) {
+        r[k] = lr[iota + g.J * (u + k)];
         H[k] = lH[(tu + k - c0) * kWave + lane];
       }
-      if (four_mask == (M == 32 ? ~0u : ((1u << M) - 1u))) {
-        // common case: every mass takes the four-term form (no branches)
+      if (gmask == all) {
+        // common case: every mass takes the grouped form (no branches)
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-          in[m] = sum4(H[0] + dm[m], H[1] + dm[m], H[2] + dm[m], H[3] + dm[m], mu[0], mu[1],
-                       mu[2], mu[3], in[m]);
+        for (int m = 0; m < M; ++m) {
+          double Dp[kGroup];
+#pragma unroll
+          for (int k = 0; k < kGroup; ++k) Dp[k] = __builtin_fma(dm[m], r[k], H[k]);
+          in[m] = chain_sum(Dp, in[m]);
+        }
       } else {
 #pragma unroll
-      for (int m = 0; m < M; ++m) {
-        if ((four_mask >> m) & 1u) {
-          in[m] = sum4(H[0] + dm[m], H[1] + dm[m], H[2] + dm[m], H[3] + dm[m], mu[0], mu[1],
-                       mu[2], mu[3], in[m]);
-        } else {
+        for (int m = 0; m < M; ++m) {
+          double Dp[kGroup];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) in[m] = __builtin_fma(mu[k], rcp64(H[k] + dm[m]), in[m]);
+          for (int k = 0; k < kGroup; ++k) Dp[k] = __builtin_fma(dm[m], r[k], H[k]);
+          if ((gmask >> m) & 1u) {
+            in[m] = chain_sum(Dp, in[m]);
+          } else {
+#pragma unroll
+            for (int k = 0; k < kGroup; ++k) in[m] = in[m] + rcp64(Dp[k]);
+          }
         }
       }
-      }
-      u += 4;
-      tu += 4;
+      u += kGroup;
+      tu += kGroup;
     } else {
       const int j = iota + g.J * u;
-      const double mu = j < n_a ? lm[j] : 0.0;
-      const double H = lH[(tu - c0) * kWave + lane];
+      if (j < n_a) {
+        const double r = lr[j];
+        const double H = lH[(tu - c0) * kWave + lane];
 #pragma unroll
-      for (int m = 0; m < M; ++m) in[m] = __builtin_fma(mu, rcp64(H + dm[m]), in[m]);
+        for (int m = 0; m < M; ++m) in[m] = in[m] + rcp64(__builtin_fma(dm[m], r, H));
+      }
       ++u;
       ++tu;
     }
@@ -171,14 +197,72 @@ __device__ __forceinline__ void grid_rows(const GridArgs &g, const double *lH, c
   }
 }
 
+// Resident table (all T U rows in LDS): the same visiting order and
+// arithmetic as grid_rows, as plain nested loops.  ALL: every mass of the
+// wave takes the grouped form.
+template <int M, bool ALL>
+__device__ __forceinline__ void grid_resident(const GridArgs &g, const double *lH,
+                                              const double *lc, const double *lq,
+                                              const double *lr, int lane, const double *dm,
+                                              unsigned gmask, double *tot) {
+  const int rho = lane & (g.R - 1);
+  const int iota = lane / g.R;
+  const int G = grouped_u(g.n_a, g.J);
+  for (int t = 0; t < g.T; ++t) {
+    const int i = rho + g.R * t;
+    const bool vi = i < g.n_r;
+    const double c = vi ? lc[i] : 0.0;
+    const double Hq = vi ? lq[i] : 1.0;
+    double A[M], in[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const double Gq = rcp64(Hq + dm[m]);
+      A[m] = (c * Gq) * Gq;
+      in[m] = 0.0;
+    }
+    const double *row = lH + (t * g.U) * kWave + lane;
+    int u = 0;
+    for (; u < G; u += kGroup) {
+      double H[kGroup], r[kGroup];
+#pragma unroll
+      for (int k = 0; k < kGroup; ++k) {
+        r[k] = lr[iota + g.J * (u + k)];
+        H[k] = row[(u + k) * kWave];
+      }
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        double Dp[kGroup];
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k) Dp[k] = __builtin_fma(dm[m], r[k], H[k]);
+        if (ALL || ((gmask >> m) & 1u)) {
+          in[m] = chain_sum(Dp, in[m]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < kGroup; ++k) in[m] = in[m] + rcp64(Dp[k]);
+        }
+      }
+    }
+    for (; u < g.U; ++u) {
+      const int j = iota + g.J * u;
+      if (j < g.n_a) {
+        const double r = lr[j];
+        const double H = row[u * kWave];
+#pragma unroll
+        for (int m = 0; m < M; ++m) in[m] = in[m] + rcp64(__builtin_fma(dm[m], r, H));
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) tot[m] = __builtin_fma(A[m], in[m], tot[m]);
+  }
+}
+
 // End of the LDS chunk that starts at row c0: at most C rows, moved back to
-// a group-of-four boundary so that no four-term group is split (C >= 8).
+// a group boundary so that no group is split (C >= kGroup).
 __device__ __forceinline__ int chunk_end(const GridArgs &g, int c0, int C, int TU) {
   int c1 = c0 + C < TU ? c0 + C : TU;
   if (c1 < TU) {
     const int t1 = c1 / g.U, u1 = c1 - t1 * g.U;
-    const int grouped = g.U - (g.U & 3);
-    if (u1 < grouped) c1 = t1 * g.U + (u1 & ~3);
+    if (u1 < grouped_u(g.n_a, g.J)) c1 = t1 * g.U + (u1 - u1 % kGroup);
   }
   return c1;
 }
@@ -187,6 +271,7 @@ template <int REG>
 __device__ __forceinline__ void grid_fill(const GridArgs &g, double *lH, int c0, int c1, double p) {
   const double *tq = g.tab;
   const double *to = g.tab + 3 * g.n_r;
+  const double *tr = to + 2 * g.n_a;
   for (int idx = threadIdx.x; idx < (c1 - c0) * kWave; idx += blockDim.x) {
     const int l = idx & (kWave - 1);
     const int tu = c0 + idx / kWave;
@@ -194,18 +279,20 @@ __device__ __forceinline__ void grid_fill(const GridArgs &g, double *lH, int c0,
     const int i = (l & (g.R - 1)) + g.R * tt;
     const int j = (l / g.R) + g.J * uu;
     double v = 1.0;
-    if (i < g.n_r && j < g.n_a) {
-      const double q = tq[i];
+    if (j < g.n_a) {
+      // padded radial lanes (i >= n_r) see q = 0, as in lane_point
+      const double q = i < g.n_r ? tq[i] : 0.0;
       const double qm = q - p;
       const double aa = qm * qm;
       const double b = (2.0 * q) * p;
-      v = hk<REG>(__builtin_fma(b, to[j], aa), g.k2, g.inv_k2);
+      v = hk<REG>(__builtin_fma(b, to[j], aa), g.k2, g.inv_k2) * tr[j];
     }
     lH[idx] = v;
   }
 }
 
-template <int REG, int M>
+// RESIDENT: the whole table fits in g.chunk rows (host-checked).
+template <int REG, int M, bool RESIDENT>
 __global__ __launch_bounds__(512) void grid_kernel(GridArgs g) {
   extern __shared__ double lds[];
   const int W = blockDim.x / kWave;
@@ -216,18 +303,18 @@ __global__ __launch_bounds__(512) void grid_kernel(GridArgs g) {
   const double p = g.p[a];
   const int n_r = g.n_r, n_a = g.n_a;
   const int TU = g.T * g.U;
-  const bool resident = TU <= g.chunk;
+  constexpr bool resident = RESIDENT;
   const int C = resident ? TU : g.chunk;
   const int MB = resident ? g.mblocks : 1;
   double *lH = lds;
   double *lc = lH + C * kWave;
   double *lq = lc + n_r;
-  double *lm = lq + n_r;
+  double *lr = lq + n_r;
   for (int idx = threadIdx.x; idx < n_r; idx += blockDim.x) {
     lc[idx] = g.tab[n_r + idx];
     lq[idx] = g.tab[2 * n_r + idx];
   }
-  for (int idx = threadIdx.x; idx < n_a; idx += blockDim.x) lm[idx] = g.tab[3 * n_r + n_a + idx];
+  for (int idx = threadIdx.x; idx < n_a; idx += blockDim.x) lr[idx] = g.tab[3 * n_r + 2 * n_a + idx];
   if (resident) {
     grid_fill<REG>(g, lH, 0, TU, p);
     __syncthreads();
@@ -246,37 +333,46 @@ __global__ __launch_bounds__(512) void grid_kernel(GridArgs g) {
       const double d = valid ? g.m2[idx] + g.k2 : 1.0;
       ok[m] = valid && p_ok && d > 0.0;
       dm[m] = ok[m] ? d : 1.0;
-      mask |= four_ok(dm[m]) ? (1u << m) : 0u;
+      mask |= chain_ok(dm[m], p, g.q_top, g.rmu_max) ? (1u << m) : 0u;
     }
     // the masses are the same in every lane: make the choice wave-uniform
-    const unsigned four_mask = __builtin_amdgcn_readfirstlane(mask);
-    double tot[M], A[M], in[M];
+    const unsigned gmask = __builtin_amdgcn_readfirstlane(mask);
+    double tot[M];
 #pragma unroll
-    for (int m = 0; m < M; ++m) tot[m] = A[m] = in[m] = 0.0;
-    int t = 0, u = 0;
-    if (resident) {
-      grid_rows<M>(g, lH, lc, lq, lm, 0, TU, lane, dm, four_mask, t, u, A, in, tot);
+    for (int m = 0; m < M; ++m) tot[m] = 0.0;
+    if constexpr (RESIDENT) {
+      if (gmask == (M == 32 ? ~0u : ((1u << M) - 1u)))
+        grid_resident<M, true>(g, lH, lc, lq, lr, lane, dm, gmask, tot);
+      else
+        grid_resident<M, false>(g, lH, lc, lq, lr, lane, dm, gmask, tot);
     } else {
+      double A[M], in[M];
+#pragma unroll
+      for (int m = 0; m < M; ++m) A[m] = in[m] = 0.0;
+      int t = 0, u = 0;
       for (int c0 = 0; c0 < TU;) {
         const int c1 = chunk_end(g, c0, C, TU);
         __syncthreads();  // previous chunk consumed; also orders the small tables
         grid_fill<REG>(g, lH, c0, c1, p);
         __syncthreads();
-        grid_rows<M>(g, lH, lc, lq, lm, c0, c1, lane, dm, four_mask, t, u, A, in, tot);
+        grid_rows<M>(g, lH, lc, lq, lr, c0, c1, lane, dm, gmask, t, u, A, in, tot);
         c0 = c1;
       }
     }
-    double res = 0.0;
+    // lane l ends with the total of mass l / (64 / M)
+    const double v = g.pref * wave_sum_split<M>(tot, lane);
+    const int mine = lane / (kWave / M);
+    unsigned okbits = 0;
     bool bad = false;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-      const double v = g.pref * wave_sum(tot[m]);
-      const bool valid = m0 + m < g.n_m;
-      if (lane == m) res = ok[m] ? v : __builtin_nan("");
-      bad |= valid && !ok[m];
+      okbits |= ok[m] ? (1u << m) : 0u;
+      bad |= (m0 + m < g.n_m) && !ok[m];
     }
+    const bool okm = (okbits >> mine) & 1u;
     if (bad && lane == 0) *g.flag = 1;
-    if (lane < M && m0 + lane < g.n_m) g.out[a * g.n_m + m0 + lane] = res;
+    if (lane % (kWave / M) == 0 && m0 + mine < g.n_m)
+      g.out[a * g.n_m + m0 + mine] = okm ? v : __builtin_nan("");
   }
 }
 
@@ -383,7 +479,7 @@ int launch_points_plain(const SetDev &s, int tile_points, int *d_flag, void *str
   const int64_t n_tiles = (s.n_ext + tile_points - 1) / tile_points;
   const int waves = 4;
   const int64_t blocks = (n_tiles + waves - 1) / waves;
-  const size_t lds = sizeof(double) * (3 * s.n_r + 2 * s.n_a);
+  const size_t lds = sizeof(double) * table_doubles(s.n_r, s.n_a);
   hipStream_t st = (hipStream_t)stream;
   if (s.reg == kExp)
     hipLaunchKernelGGL(points_plain_kernel<kExp>, dim3((unsigned)blocks), dim3(64 * waves), lds, st,
@@ -400,11 +496,15 @@ int launch_reset_counter(int *d_counter, void *stream) {
 }
 
 int launch_points_persistent(const SetDev *d_sets, const Tile *d_tiles, int n_tiles, int *d_counter,
-                             int lds_doubles, int n_blocks, int *d_flag, void *stream) {
+                             int lds_bytes, int n_blocks, bool with_f32, int *d_flag,
+                             void *stream) {
   if (n_tiles <= 0) return 0;
-  hipLaunchKernelGGL(points_persistent_kernel, dim3(n_blocks), dim3(64),
-                     sizeof(double) * lds_doubles, (hipStream_t)stream, d_sets, d_tiles, n_tiles,
-                     d_counter, d_flag);
+  if (with_f32)
+    hipLaunchKernelGGL(points_persistent_kernel<true>, dim3(n_blocks), dim3(64), (size_t)lds_bytes,
+                       (hipStream_t)stream, d_sets, d_tiles, n_tiles, d_counter, d_flag);
+  else
+    hipLaunchKernelGGL(points_persistent_kernel<false>, dim3(n_blocks), dim3(64), (size_t)lds_bytes,
+                       (hipStream_t)stream, d_sets, d_tiles, n_tiles, d_counter, d_flag);
   return (int)hipGetLastError();
 }
 
@@ -417,8 +517,12 @@ int grid_lds_bytes(const GridArgs &g) {
 template <int REG, int M>
 static void grid_launch_t(const GridArgs &g, int W, hipStream_t st) {
   const int64_t blocks = g.n_p * g.n_mb;
-  hipLaunchKernelGGL((grid_kernel<REG, M>), dim3((unsigned)blocks), dim3(kWave * W),
-                     grid_lds_bytes(g), st, g);
+  if (g.T * g.U <= g.chunk)
+    hipLaunchKernelGGL((grid_kernel<REG, M, true>), dim3((unsigned)blocks), dim3(kWave * W),
+                       grid_lds_bytes(g), st, g);
+  else
+    hipLaunchKernelGGL((grid_kernel<REG, M, false>), dim3((unsigned)blocks), dim3(kWave * W),
+                       grid_lds_bytes(g), st, g);
 }
 
 int launch_grid(const GridArgs &g, int reg, int M, int W, void *stream) {

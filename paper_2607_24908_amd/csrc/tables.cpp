@@ -124,7 +124,9 @@ QuadTable build_quad_table(const frg_quad &q) {
   t.k2 = q.k * q.k;
   t.inv_k2 = 1.0 / t.k2;
   t.pref = omega_sphere(q.d - 1) / std::pow(2.0 * M_PI, q.d);
-  t.data.assign(3 * nr + 2 * na, 0.0);
+  t.q_top = q.q_max;
+  t.rmu_max = 0.0;
+  t.data.assign(table_doubles(nr, na), 0.0);
   std::vector<double> xr(nr), wr(nr), xa(na), wa(na);
   gauss_legendre_gw(nr, xr.data(), wr.data());
   gauss_legendre_gw(na, xa.data(), wa.data());
@@ -142,7 +144,10 @@ QuadTable build_quad_table(const frg_quad &q) {
   }
   for (int j = 0; j < na; ++j) {
     t.data[3 * nr + j] = 1.0 + xa[j];
-    t.data[3 * nr + na + j] = wa[j] * angular_weight_factor(q.d, xa[j]);
+    const double mu = wa[j] * angular_weight_factor(q.d, xa[j]);
+    t.data[3 * nr + na + j] = mu;
+    t.data[3 * nr + 2 * na + j] = 1.0 / mu;
+    t.rmu_max = std::max(t.rmu_max, 1.0 / mu);
   }
   return t;
 }

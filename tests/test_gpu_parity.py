@@ -101,7 +101,11 @@ def test_plain_d4_points_all_launch_forms_bitwise(ctx):
 
 SHAPES = [(100, 12, 3, frg.FRG_REG_EXP), (7, 3, 4, frg.FRG_REG_LITIM), (33, 5, 5, frg.FRG_REG_EXP),
           (256, 32, 3, frg.FRG_REG_LITIM), (1, 1, 3, frg.FRG_REG_EXP), (64, 1, 4, frg.FRG_REG_EXP),
-          (129, 17, 4, frg.FRG_REG_EXP), (32, 256, 3, frg.FRG_REG_EXP)]
+          (129, 17, 4, frg.FRG_REG_EXP), (32, 256, 3, frg.FRG_REG_EXP),
+          # J > 1 with n_a % J != 0: grouped part, then a tail with padded lanes
+          (16, 70, 3, frg.FRG_REG_EXP), (8, 100, 4, frg.FRG_REG_LITIM),
+          # streamed table (T U > 64 rows) whose chunk ends fall inside groups
+          (400, 20, 4, frg.FRG_REG_LITIM), (300, 44, 3, frg.FRG_REG_EXP)]
 
 
 @pytest.mark.parametrize("n_r,n_a,d,reg", SHAPES)
@@ -121,6 +125,27 @@ def test_ragged_shapes_grid_and_points(ctx, n_r, n_a, d, reg):
     M = np.tile(m2, p.size)
     pts = run_points(ctx, quad, P, M)
     assert np.array_equal(pts, got)
+
+
+def test_grouped_and_single_forms_mixed(ctx):
+    """Points on both sides of the range test of the grouped reciprocal sums
+    (delta around 1e-30, (q_top + p)^2 around 1e37), in one grid: the masses
+    of one wave take different forms.  Both forms match the oracle and the
+    point kernel bit for bit."""
+    k = 3e-16
+    p = np.array([0.0, 1e-16, 1e-15, 1e-10, 1e3, 1e17, 1e18, 1e19])
+    m2 = np.array([0.0, 5e-31, 2e-30, 1e-29, 1e-20, 1e-3, 0.0, 3e-30, 2e-31, 1e-28, 7e-31])
+    for d, reg, n_r, n_a in [(3, frg.FRG_REG_EXP, 96, 24), (4, frg.FRG_REG_LITIM, 20, 40)]:
+        quad = frg.make_quad(d, reg, k, 6 * k, n_r, n_a)
+        got = run_grid(ctx, quad, p, m2)
+        want = oracle.integrate_grid(d, reg, k, 6 * k, n_r, n_a, p, m2).ravel()
+        err = relerr(got, want)
+        print(f"d={d} reg={reg}: max rel err {err.max():.3e}")
+        assert np.all(np.isfinite(got))
+        assert err.max() < RTOL
+        P = np.repeat(p, m2.size)
+        M = np.tile(m2, p.size)
+        assert np.array_equal(run_points(ctx, quad, P, M), got)
 
 
 # ------------------------------------------------------- scale-up d = 3 --
