@@ -260,7 +260,7 @@ int frg_autotune(frg_ctx *ctx, int32_t mode, const char *cache_path);
  * "persist_tile" (1..64), "persist_wpc" (1..64).  Setting a knob drops the
  * tuned choices so that it takes effect.  Two knobs route FRG_PREC_FP32C
  * points to FP64 and do change results (within the FP32 tolerance):
- * "fp32c_flag_ppb" (error-estimate threshold in units of 1e-9, default 80)
+ * "fp32c_flag_ppb" (error-estimate threshold in units of 1e-9, default 100)
  * and "fp32c_band_ppm" (pole band on (m^2 + k^2)/k^2 in units of 1e-6,
  * default 10000). */
 int frg_tune_set(frg_ctx *ctx, const char *key, int32_t value);

@@ -160,6 +160,32 @@ int Ctx::quad_table(const frg_quad &q, const double **dev, QuadTable *host_copy)
   return FRG_OK;
 }
 
+int Ctx::grid32_table(const frg_quad &q, int J, const double **dev, Grid32Table *host_copy) {
+  const double *tab;
+  int rc = quad_table(q, &tab, nullptr);
+  if (rc) return rc;
+  auto key = std::make_tuple(q.d, q.reg, dbits(q.k), dbits(q.q_max), q.n_radial, q.n_angular);
+  QEntry &ent = qtabs.at(key);
+  if (!ent.buf32) {
+    Grid32Table t = build_grid32_table(ent.host, J);
+    const int na = q.n_angular;
+    std::vector<char> blob(2 * na * sizeof(double) + na * sizeof(float));
+    std::memcpy(blob.data(), t.gam.data(), na * sizeof(double));
+    std::memcpy(blob.data() + na * sizeof(double), t.sig.data(), na * sizeof(double));
+    std::memcpy(blob.data() + 2 * na * sizeof(double), t.rho.data(), na * sizeof(float));
+    auto buf = std::make_unique<DevBuf>();
+    rc = buf->reserve(blob.size());
+    if (rc) return rc;
+    hipError_t e = hipMemcpy(buf->ptr, blob.data(), blob.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "upload FP32 grid table");
+    ent.buf32 = std::move(buf);
+    ent.host32 = std::move(t);
+  }
+  *dev = (const double *)ent.buf32->ptr;
+  if (host_copy) *host_copy = ent.host32;
+  return FRG_OK;
+}
+
 int Ctx::lpa_table(int d, int reg, int n_r, double qmk, const double **dev, double *Cd) {
   auto key = std::make_tuple(d, reg, n_r, dbits(qmk));
   auto it = ltabs.find(key);
@@ -493,7 +519,7 @@ int Ctx::grid_device(const frg_quad &q, int64_t n_p, const double *p, int64_t n_
   return grid_launch(g, q.reg, cfg, st);
 }
 
-int Ctx::grid_launch(GridArgs g, int reg, const GridCfg &cfg, hipStream_t st) {
+int Ctx::grid_launch(GridArgs g, int reg, const GridCfg &cfg, hipStream_t st, bool f32) {
   const bool resident = g.T * g.U <= g.chunk;
   const int64_t per_wg_min = (int64_t)cfg.M * cfg.W;
   // mass blocks per wave: fewer workgroups per momentum, but keep at least
@@ -503,8 +529,8 @@ int Ctx::grid_launch(GridArgs g, int reg, const GridCfg &cfg, hipStream_t st) {
     mbk /= 2;
   g.mblocks = mbk;
   g.n_mb = (int)((g.n_m + per_wg_min * mbk - 1) / (per_wg_min * mbk));
-  int e = launch_grid(g, reg, cfg.M, cfg.W, st);
-  if (e) return hip_fail((hipError_t)e, "grid_kernel launch");
+  const int e = f32 ? launch_grid32(g, reg, cfg.M, cfg.W, st) : launch_grid(g, reg, cfg.M, cfg.W, st);
+  if (e) return hip_fail((hipError_t)e, f32 ? "grid32_kernel launch" : "grid_kernel launch");
   return FRG_OK;
 }
 
@@ -534,6 +560,48 @@ int Ctx::integrate_fp32c_sets(const std::vector<SetDev> &sd, int flags, hipStrea
 
 int Ctx::grid_fp32c(const frg_quad &q, int64_t n_p, const double *p, int64_t n_m,
                     const double *m2, double *out, double *err, uint8_t *used, hipStream_t st) {
+  // Tensor-grid kernel (exponential regulator) when the whole table of one
+  // momentum fits in LDS.  Litim grids take the point-list kernel, which sums
+  // the flat region s <= k^2 (identical denominators, hence identical FP32
+  // roundings in every radial row) in FP64.
+  const double *tab;
+  QuadTable h;
+  int rc = quad_table(q, &tab, &h);
+  if (rc) return rc;
+  GridArgs g{};
+  g.p = p;
+  g.m2 = m2;
+  g.out = out;
+  g.err = err;
+  g.used64 = used;
+  g.tab = tab;
+  g.flag = d_flag;
+  g.k2 = h.k2;
+  g.inv_k2 = h.inv_k2;
+  g.pref = h.pref;
+  g.q_top = h.q_top;
+  g.rmu_max = h.rmu_max;
+  g.n_p = n_p;
+  g.n_m = n_m;
+  g.n_r = q.n_radial;
+  g.n_a = q.n_angular;
+  lane_split(g.n_r, g.n_a, &g.R, &g.J, &g.T, &g.U);
+  g.chunk = g.T * g.U;
+  if (q.reg == FRG_REG_EXP && g.T * g.U <= std::max(8, tune.grid_lds_rows) &&
+      grid32_lds_bytes(g) <= 64 * 1024) {
+    Grid32Table t32;
+    rc = grid32_table(q, g.J, &g.tab32, &t32);
+    if (rc) return rc;
+    g.f32_band = tune.fp32c_band_ppm * 1e-6;
+    g.f32_flag = tune.fp32c_flag_ppb * 1e-9;
+    g.f32_erho = t32.erho;
+    g.f32_rmin = t32.rmin;
+    g.f32_rmax = t32.rmax;
+    GridCfg cfg = tune.grid;
+    if (cfg.M > 8) cfg.M = 8;  // the FP32 kernel keeps two accumulators per mass
+    return grid_launch(g, q.reg, cfg, st, true);
+  }
+  // Otherwise the point-list FP32C kernel over the (p, m^2) pairs.
   frg_set fs{};
   fs.quad = q;
   fs.n_ext = n_p * n_m;
@@ -543,7 +611,7 @@ int Ctx::grid_fp32c(const frg_quad &q, int64_t n_p, const double *p, int64_t n_m
   fs.err_est = err;
   fs.used_fp64 = used;
   SetDev s;
-  int rc = make_setdev(fs, &s);
+  rc = make_setdev(fs, &s);
   if (rc) return rc;
   int e = launch_fp32c(s, tune.plain_tile, n_m, d_flag, st);
   if (e) return hip_fail((hipError_t)e, "fp32c_kernel launch");

@@ -20,7 +20,7 @@
 // bounded 99.94 % of the observed errors, the largest of which was 7.1e-8.
 // A point is evaluated in FP64 instead (bit-identical to the FP64 kernels)
 // when it lies near the pole, dhat < f32_band (default 1e-2), or when err
-// exceeds f32_flag (default 8e-8).
+// exceeds f32_flag (default 1e-7).
 #pragma once
 
 #include <hip/hip_runtime.h>

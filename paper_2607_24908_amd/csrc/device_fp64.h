@@ -66,6 +66,26 @@ __device__ __forceinline__ double chain_sum(const double *Dp, double acc) {
   return __builtin_fma(N, rcp64(P), acc);
 }
 
+// Two running fractions in lockstep (the same operations as chain_sum on
+// each; interleaving gives the FP64 pipeline two independent chains).
+__device__ __forceinline__ void chain_sum2(const double *Da, const double *Db, double &acc_a,
+                                           double &acc_b) {
+  double Na = 1.0, Pa = Da[0], Nb = 1.0, Pb = Db[0];
+#pragma unroll
+  for (int k = 1; k < kGroup; ++k) {
+    Na = __builtin_fma(Na, Da[k], Pa);
+    Nb = __builtin_fma(Nb, Db[k], Pb);
+    Pa = Pa * Da[k];
+    Pb = Pb * Db[k];
+    // keep the two chains interleaved (the scheduler would otherwise run
+    // them one after the other)
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  const double ra = rcp64(Pa), rb = rcp64(Pb);
+  acc_a = __builtin_fma(Na, ra, acc_a);
+  acc_b = __builtin_fma(Nb, rb, acc_b);
+}
+
 // Whether the grouped form is safe for this point (same test in every kernel).
 __device__ __forceinline__ bool chain_ok(double delta, double p, double q_top, double rmu_max) {
   const double qp = q_top + p;

@@ -71,7 +71,7 @@ struct Tune {
   int plain_tile = 8;
   PersistCfg persist;
   int grid_lds_rows = 64;  // (t, u) rows of 64 doubles staged per LDS chunk
-  int fp32c_flag_ppb = 80;     // FP32C: FP64 redo above this error estimate (1e-9 units)
+  int fp32c_flag_ppb = 100;    // FP32C: FP64 redo above this error estimate (1e-9 units)
   int fp32c_band_ppm = 10000;  // FP32C: FP64 below this delta/k^2 (1e-6 units)
   int mode = 0;            // 0: defaults and cached choices, 1: tune new keys
   std::string cache_path;
@@ -107,6 +107,8 @@ struct Context {
   struct QEntry {
     std::unique_ptr<frg::DevBuf> buf;
     frg::QuadTable host;
+    std::unique_ptr<frg::DevBuf> buf32;  // Grid32Table on the device (lazy)
+    frg::Grid32Table host32;
   };
   struct LEntry {
     std::unique_ptr<frg::DevBuf> buf;
@@ -119,6 +121,7 @@ struct Context {
 
   virtual ~Context();
   int quad_table(const frg_quad &q, const double **dev, frg::QuadTable *host_copy);
+  int grid32_table(const frg_quad &q, int J, const double **dev, frg::Grid32Table *host_copy);
   int lpa_table(int d, int reg, int n_r, double qmk, const double **dev, double *Cd);
   int make_setdev(const frg_set &s, frg::SetDev *out);
   int integrate_device(const frg_set *sets, int n_sets, int flags, hipStream_t st);
@@ -134,7 +137,7 @@ struct Context {
                double *const *dUdt, double *const *jac, int *flags_dev, hipStream_t st);
   void stop_server();
   // autotune.cpp
-  int grid_launch(GridArgs g, int reg, const GridCfg &cfg, hipStream_t st);
+  int grid_launch(GridArgs g, int reg, const GridCfg &cfg, hipStream_t st, bool f32 = false);
   GridCfg grid_cfg(const frg_quad &q, const GridArgs &g, hipStream_t st);
   int plain_tile_for(const SetDev &s, hipStream_t st);
   PersistCfg persist_cfg(const std::vector<SetDev> &sd, int prec, hipStream_t st);

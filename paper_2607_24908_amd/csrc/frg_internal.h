@@ -90,7 +90,29 @@ struct GridArgs {
   int32_t chunk;    // (t, u) rows of the Hk table held in LDS at once
   int32_t mblocks;  // mass blocks per wave when the table is resident
   int32_t pad;
+  // compensated-FP32 grid only (Grid32Table on the device, see below)
+  const double *tab32;
+  double f32_band, f32_flag;  // FP64 below dhat = f32_band; re-done in FP64 above err f32_flag
+  double f32_erho;            // bound of the coherent weight error of the FP32 terms
+  double f32_rmin, f32_rmax;  // range of rho_j
 };
+
+// Angular data of the compensated-FP32 grid kernel for one quadrature key
+// and lane split.  A group of eight angular terms of one lane takes the FP32
+// running fraction over D''_ij = (Hk(s_ij)/k^2 + dhat) rho_j and is scaled by
+// gam_g, with rho_j = fl32(gam_g / mu_j) so that gam_g / rho_j = mu_j (1 + e_j);
+// gam_g is searched per group to make max |e_j| small.  Angular terms outside
+// the groups use rho_j = fl32(1/mu_j), gam_j = mu_j rho_j (e_j = 0).  Device
+// layout: gam[n_a] (the group's value at each of its j), sig[n_a] =
+// rho_j mu_j / k^2 (the factor taking H'_ij = Hk rmu_j to H''_ij), then
+// rho[n_a] as float.
+struct Grid32Table {
+  std::vector<double> gam, sig;
+  std::vector<float> rho;
+  double rmin = 0.0, rmax = 0.0, erho = 0.0;
+};
+Grid32Table build_grid32_table(const QuadTable &t, int J);
+constexpr int grid32_group_size = 8;
 
 struct LpaJob {
   const double *U;
@@ -117,6 +139,8 @@ int launch_reset_counter(int *d_counter, void *stream);
 int launch_grid(const GridArgs &g, int reg, int M, int W, void *stream);
 int grid_lds_bytes(const GridArgs &g);
 int launch_fp32c(const SetDev &s, int tile_points, int64_t grid_nm, int *d_flag, void *stream);
+int launch_grid32(const GridArgs &g, int reg, int M, int W, void *stream);
+int grid32_lds_bytes(const GridArgs &g);
 int launch_lpa(const LpaJob *d_jobs, const int64_t *d_start, int n_jobs, int64_t total_points,
                void *stream);
 

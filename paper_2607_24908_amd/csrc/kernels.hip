@@ -12,6 +12,7 @@
 
 #include "device_fp32c.h"
 #include "device_fp64.h"
+#include "device_grid.h"
 
 namespace frg {
 
@@ -118,179 +119,6 @@ __global__ void reset_counter_kernel(int *c) {
 // visiting order, the grouping and the arithmetic are those of lane_point, so
 // results match the point kernel bit for bit.
 
-// Accumulate the rows [c0, c1) of the table for the M masses of one wave.
-// `gmask` bit m: mass m takes the grouped form.
-template <int M>
-__device__ __forceinline__ void grid_rows(const GridArgs &g, const double *lH, const double *lc,
-                                          const double *lq, const double *lr, int c0, int c1,
-                                          int lane, const double *dm, unsigned gmask, int &t,
-                                          int &u, double *A, double *in, double *tot) {
-  const int rho = lane & (g.R - 1);
-  const int iota = lane / g.R;
-  const int n_r = g.n_r, n_a = g.n_a;
-  const int G = grouped_u(n_a, g.J);
-  const unsigned all = (M == 32) ? ~0u : ((1u << M) - 1u);
-  int tu = c0;
-  while (tu < c1) {
-    if (u == 0) {
-      const int i = rho + g.R * t;
-      const bool vi = i < n_r;
-      const double c = vi ? lc[i] : 0.0;
-      const double Hq = vi ? lq[i] : 1.0;
-#pragma unroll
-      for (int m = 0; m < M; ++m) {
-        const double Gq = rcp64(Hq + dm[m]);
-        A[m] = (c * Gq) * Gq;
-        in[m] = 0.0;
-      }
-    }
-    if (u < G) {
-      // a whole group lies in this chunk (chunk_end never splits one)
-      double H[kGroup], r[kGroup];
-#pragma unroll
-      for (int k = 0; k < kGroup; ++k) {
-        r[k] = lr[iota + g.J * (u + k)];
-        H[k] = lH[(tu + k - c0) * kWave + lane];
-      }
-      if (gmask == all) {
-        // common case: every mass takes the grouped form (no branches)
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-          double Dp[kGroup];
-#pragma unroll
-          for (int k = 0; k < kGroup; ++k) Dp[k] = __builtin_fma(dm[m], r[k], H[k]);
-          in[m] = chain_sum(Dp, in[m]);
-        }
-      } else {
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-          double Dp[kGroup];
-#pragma unroll
-          for (int k = 0; k < kGroup; ++k) Dp[k] = __builtin_fma(dm[m], r[k], H[k]);
-          if ((gmask >> m) & 1u) {
-            in[m] = chain_sum(Dp, in[m]);
-          } else {
-#pragma unroll
-            for (int k = 0; k < kGroup; ++k) in[m] = in[m] + rcp64(Dp[k]);
-          }
-        }
-      }
-      u += kGroup;
-      tu += kGroup;
-    } else {
-      const int j = iota + g.J * u;
-      if (j < n_a) {
-        const double r = lr[j];
-        const double H = lH[(tu - c0) * kWave + lane];
-#pragma unroll
-        for (int m = 0; m < M; ++m) in[m] = in[m] + rcp64(__builtin_fma(dm[m], r, H));
-      }
-      ++u;
-      ++tu;
-    }
-    if (u == g.U) {
-#pragma unroll
-      for (int m = 0; m < M; ++m) tot[m] = __builtin_fma(A[m], in[m], tot[m]);
-      u = 0;
-      ++t;
-    }
-  }
-}
-
-// Resident table (all T U rows in LDS): the same visiting order and
-// arithmetic as grid_rows, as plain nested loops.  ALL: every mass of the
-// wave takes the grouped form.
-template <int M, bool ALL>
-__device__ __forceinline__ void grid_resident(const GridArgs &g, const double *lH,
-                                              const double *lc, const double *lq,
-                                              const double *lr, int lane, const double *dm,
-                                              unsigned gmask, double *tot) {
-  const int rho = lane & (g.R - 1);
-  const int iota = lane / g.R;
-  const int G = grouped_u(g.n_a, g.J);
-  for (int t = 0; t < g.T; ++t) {
-    const int i = rho + g.R * t;
-    const bool vi = i < g.n_r;
-    const double c = vi ? lc[i] : 0.0;
-    const double Hq = vi ? lq[i] : 1.0;
-    double A[M], in[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-      const double Gq = rcp64(Hq + dm[m]);
-      A[m] = (c * Gq) * Gq;
-      in[m] = 0.0;
-    }
-    const double *row = lH + (t * g.U) * kWave + lane;
-    int u = 0;
-    for (; u < G; u += kGroup) {
-      double H[kGroup], r[kGroup];
-#pragma unroll
-      for (int k = 0; k < kGroup; ++k) {
-        r[k] = lr[iota + g.J * (u + k)];
-        H[k] = row[(u + k) * kWave];
-      }
-#pragma unroll
-      for (int m = 0; m < M; ++m) {
-        double Dp[kGroup];
-#pragma unroll
-        for (int k = 0; k < kGroup; ++k) Dp[k] = __builtin_fma(dm[m], r[k], H[k]);
-        if (ALL || ((gmask >> m) & 1u)) {
-          in[m] = chain_sum(Dp, in[m]);
-        } else {
-#pragma unroll
-          for (int k = 0; k < kGroup; ++k) in[m] = in[m] + rcp64(Dp[k]);
-        }
-      }
-    }
-    for (; u < g.U; ++u) {
-      const int j = iota + g.J * u;
-      if (j < g.n_a) {
-        const double r = lr[j];
-        const double H = row[u * kWave];
-#pragma unroll
-        for (int m = 0; m < M; ++m) in[m] = in[m] + rcp64(__builtin_fma(dm[m], r, H));
-      }
-    }
-#pragma unroll
-    for (int m = 0; m < M; ++m) tot[m] = __builtin_fma(A[m], in[m], tot[m]);
-  }
-}
-
-// End of the LDS chunk that starts at row c0: at most C rows, moved back to
-// a group boundary so that no group is split (C >= kGroup).
-__device__ __forceinline__ int chunk_end(const GridArgs &g, int c0, int C, int TU) {
-  int c1 = c0 + C < TU ? c0 + C : TU;
-  if (c1 < TU) {
-    const int t1 = c1 / g.U, u1 = c1 - t1 * g.U;
-    if (u1 < grouped_u(g.n_a, g.J)) c1 = t1 * g.U + (u1 - u1 % kGroup);
-  }
-  return c1;
-}
-
-template <int REG>
-__device__ __forceinline__ void grid_fill(const GridArgs &g, double *lH, int c0, int c1, double p) {
-  const double *tq = g.tab;
-  const double *to = g.tab + 3 * g.n_r;
-  const double *tr = to + 2 * g.n_a;
-  for (int idx = threadIdx.x; idx < (c1 - c0) * kWave; idx += blockDim.x) {
-    const int l = idx & (kWave - 1);
-    const int tu = c0 + idx / kWave;
-    const int tt = tu / g.U, uu = tu - tt * g.U;
-    const int i = (l & (g.R - 1)) + g.R * tt;
-    const int j = (l / g.R) + g.J * uu;
-    double v = 1.0;
-    if (j < g.n_a) {
-      // padded radial lanes (i >= n_r) see q = 0, as in lane_point
-      const double q = i < g.n_r ? tq[i] : 0.0;
-      const double qm = q - p;
-      const double aa = qm * qm;
-      const double b = (2.0 * q) * p;
-      v = hk<REG>(__builtin_fma(b, to[j], aa), g.k2, g.inv_k2) * tr[j];
-    }
-    lH[idx] = v;
-  }
-}
-
 // RESIDENT: the whole table fits in g.chunk rows (host-checked).
 template <int REG, int M, bool RESIDENT>
 __global__ __launch_bounds__(512) void grid_kernel(GridArgs g) {
@@ -342,9 +170,9 @@ __global__ __launch_bounds__(512) void grid_kernel(GridArgs g) {
     for (int m = 0; m < M; ++m) tot[m] = 0.0;
     if constexpr (RESIDENT) {
       if (gmask == (M == 32 ? ~0u : ((1u << M) - 1u)))
-        grid_resident<M, true>(g, lH, lc, lq, lr, lane, dm, gmask, tot);
+        grid_resident<M, true>(g, lH, lc, lq, lr, lane, dm, ~0u, gmask, tot);
       else
-        grid_resident<M, false>(g, lH, lc, lq, lr, lane, dm, gmask, tot);
+        grid_resident<M, false>(g, lH, lc, lq, lr, lane, dm, ~0u, gmask, tot);
     } else {
       double A[M], in[M];
 #pragma unroll

@@ -68,7 +68,7 @@ def test_precision_workload_within_1e7(ctx, seed):
     assert f32.sum() > 0.5 * np.sum(delta >= 1e-2)
     # the estimate is below the routing threshold and bounds the observed
     # error of (almost) every FP32 result
-    assert np.all(err[f32] <= 8e-8)
+    assert np.all(err[f32] <= TOL32)
     assert np.mean(rel[f32] <= err[f32]) > 0.99
 
 
@@ -83,7 +83,11 @@ def test_fp64_fallback_is_bit_identical(ctx):
     assert np.all(err[sel] == 1e-14)
 
 
-def test_points_equal_grid_fp32c(ctx):
+def test_points_and_grid_fp32c_agree(ctx):
+    """The tensor-grid FP32C kernel (shared per-momentum table, grouped FP32
+    running fractions) and the point-list FP32C kernel (per-term FP32 with
+    two-sum) are different FP32 algorithms: both stay within the bar of the
+    oracle, and where both fall back to FP64 they return the same bits."""
     w = workloads.precision_d4(1)
     q = w.quad
     g, ge, gu = grid(ctx, q, w.p, w.m2, frg.FRG_PREC_FP32C)
@@ -96,8 +100,13 @@ def test_points_equal_grid_fp32c(ctx):
     frg.frg_integrate(ctx, [dict(quad=quad, p=dev(P), m2=dev(M), out=out, err_est=err,
                                  used_fp64=used)])
     torch.cuda.synchronize()
-    assert np.array_equal(out.cpu().numpy(), g)
-    assert np.array_equal(used.cpu().numpy(), gu)
+    pt, pu = out.cpu().numpy(), used.cpu().numpy()
+    want = oracle.integrate_grid(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a, w.p, w.m2).ravel()
+    assert np.max(np.abs(pt - want) / want) < TOL32
+    assert np.max(np.abs(g - want) / want) < TOL32
+    both = (pu == 1) & (gu == 1)
+    assert both.any()
+    assert np.array_equal(pt[both], g[both])
 
 
 @pytest.mark.parametrize("d,reg,n_r,n_a", [(3, frg.FRG_REG_EXP, 128, 32), (3, frg.FRG_REG_LITIM, 64, 16),
