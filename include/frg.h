@@ -256,8 +256,10 @@ int frg_server_stats(frg_ctx *ctx, int64_t *flows_done, int64_t *launches, doubl
 int frg_autotune(frg_ctx *ctx, int32_t mode, const char *cache_path);
 
 /* Set / read one default launch-shape knob: "grid_M" (4, 8, 16), "grid_W"
- * (1..8), "grid_MB" (1..64), "grid_lds_rows" (8..96), "plain_tile",
- * "persist_tile" (1..64), "persist_wpc" (1..64).  Setting a knob drops the
+ * (1..8), "grid_MB" (1..64) of the FP64 tensor-grid kernel, "grid32_M" (4, 8),
+ * "grid32_W" (1..8), "grid32_MB" (1..64) of the compensated-FP32 one,
+ * "grid_lds_rows" (8..96), "plain_tile", "persist_tile" (1..64),
+ * "persist_wpc" (1..64).  Setting a knob drops the
  * tuned choices so that it takes effect.  Two knobs route FRG_PREC_FP32C
  * points to FP64 and do change results (within the FP32 tolerance):
  * "fp32c_flag_ppb" (error-estimate threshold in units of 1e-9, default 100)

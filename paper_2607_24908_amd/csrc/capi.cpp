@@ -519,7 +519,7 @@ int Ctx::grid_device(const frg_quad &q, int64_t n_p, const double *p, int64_t n_
   return grid_launch(g, q.reg, cfg, st);
 }
 
-int Ctx::grid_launch(GridArgs g, int reg, const GridCfg &cfg, hipStream_t st, bool f32) {
+int Ctx::grid_launch(GridArgs g, int reg, const GridCfg &cfg, hipStream_t st, int kind) {
   const bool resident = g.T * g.U <= g.chunk;
   const int64_t per_wg_min = (int64_t)cfg.M * cfg.W;
   // mass blocks per wave: fewer workgroups per momentum, but keep at least
@@ -529,8 +529,9 @@ int Ctx::grid_launch(GridArgs g, int reg, const GridCfg &cfg, hipStream_t st, bo
     mbk /= 2;
   g.mblocks = mbk;
   g.n_mb = (int)((g.n_m + per_wg_min * mbk - 1) / (per_wg_min * mbk));
-  const int e = f32 ? launch_grid32(g, reg, cfg.M, cfg.W, st) : launch_grid(g, reg, cfg.M, cfg.W, st);
-  if (e) return hip_fail((hipError_t)e, f32 ? "grid32_kernel launch" : "grid_kernel launch");
+  const int e = kind == 1 ? launch_grid32(g, reg, cfg.M, cfg.W, st)
+                          : launch_grid(g, reg, cfg.M, cfg.W, st, kind == 2);
+  if (e) return hip_fail((hipError_t)e, kind == 1 ? "grid32_kernel launch" : "grid_kernel launch");
   return FRG_OK;
 }
 
@@ -597,9 +598,18 @@ int Ctx::grid_fp32c(const frg_quad &q, int64_t n_p, const double *p, int64_t n_m
     g.f32_erho = t32.erho;
     g.f32_rmin = t32.rmin;
     g.f32_rmax = t32.rmax;
-    GridCfg cfg = tune.grid;
-    if (cfg.M > 8) cfg.M = 8;  // the FP32 kernel keeps two accumulators per mass
-    return grid_launch(g, q.reg, cfg, st, true);
+    // the FP64 redo pass reads which points it owns from used64: the
+    // caller's array, else a scratch array of the context
+    if (!used) {
+      rc = flags8.reserve((size_t)n_p * n_m);
+      if (rc) return rc;
+      g.used64 = (uint8_t *)flags8.ptr;
+    }
+    GridCfg cfg = tune.grid32;
+    if (cfg.M > 8) cfg.M = 8;  // FP32 kernel: two accumulators per mass
+    rc = grid_launch(g, q.reg, cfg, st, 1);
+    if (rc) return rc;
+    return grid_launch(g, q.reg, tune.grid, st, 2);
   }
   // Otherwise the point-list FP32C kernel over the (p, m^2) pairs.
   frg_set fs{};

@@ -188,8 +188,9 @@ __device__ __forceinline__ int chunk_end(const GridArgs &g, int c0, int C, int T
   return c1;
 }
 
-// Fill rows [c0, c1) of the table of momentum p.  With lH32 non-null the
-// compensated-FP32 copy lH32 = fl32(H' sig_j) is written beside it.
+// Fill rows [c0, c1) of the table of momentum p into lH and, when lH32 is
+// non-null, its compensated-FP32 form lH32 = fl32(H' sig_j) (either may be
+// null).
 template <int REG>
 __device__ __forceinline__ void grid_fill(const GridArgs &g, double *lH, int c0, int c1, double p,
                                           float *lH32 = nullptr, const double *sig = nullptr) {
@@ -215,7 +216,7 @@ __device__ __forceinline__ void grid_fill(const GridArgs &g, double *lH, int c0,
       const double b = (2.0 * q) * p;
       v = hk<REG>(__builtin_fma(b, to[j], aa), g.k2, g.inv_k2) * tr[j];
     }
-    lH[(row - c0) * kWave + l] = v;
+    if (lH) lH[(row - c0) * kWave + l] = v;
     if (lH32) lH32[(row - c0) * kWave + l] = (float)(v * (j < g.n_a ? sig[j] : 1.0));
     uu += W;
     while (uu >= g.U) {

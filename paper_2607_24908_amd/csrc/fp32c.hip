@@ -39,21 +39,21 @@ __global__ __launch_bounds__(256) void fp32c_kernel(SetDev s, int tile_points, i
 }
 
 // ------------------------------------------------------ tensor grid --
-// Compensated-FP32 tensor grid (exponential regulator).  The workgroup layout, the FP64 table H' and
-// its fill are those of the FP64 grid kernel; the fill also writes the FP32
-// table H''_ij = fl32(H'_ij sig_j) = fl32((Hk(s_ij)/k^2) rho_j).  Each mass of
-// a wave is FP32 (dhat >= band and the running fraction stays in the FP32
-// normal range) or FP64.  FP32 masses take, per group of eight angular
-// terms, N/P over D''_k = fma(dhat, rho_k, H''_k) in FP32 (one FMA, one FMA and
-// one multiply per term, one hardware reciprocal per group), scaled by gam_g
-// and accumulated in FP64.  Per result the estimate
+// Compensated-FP32 tensor grid (exponential regulator).  The workgroup layout
+// and the fill are those of the FP64 grid kernel; LDS holds the FP32 table
+// H''_ij = fl32(H'_ij sig_j) = fl32((Hk(s_ij)/k^2) rho_j).  Each mass of a wave
+// is FP32 (dhat >= band and the running fraction stays in the FP32 normal
+// range) or FP64.  FP32 masses take, per group of eight angular terms, N/P
+// over D''_k = fma(dhat, rho_k, H''_k) in FP32 (one FMA, one FMA and one
+// multiply per term, one hardware reciprocal per group), scaled by gam_g and
+// accumulated in FP64.  Per result the estimate
 //   err = kKappa * kSigma32 * sqrt(sum_i A_i^2 sum_g g^2) / |I|
 //         + |fl32(dhat) - dhat| / dhat + erho
 // (statistical rounding of the group sums g, rounding of dhat shared by all
 // terms, and the largest weight error |gam/rho_j - mu_j| / mu_j) decides
-// whether the FP32 value is returned; masses above f32_flag and the FP64
-// masses are computed by the FP64 grid pass over the same table, bit for bit
-// equal to the FP64 grid kernel.
+// whether the FP32 value is returned.  Masses above f32_flag and the FP64
+// masses are marked used64 = 1 and computed by the FP64 grid kernel in redo
+// mode (bit for bit its ordinary results), launched right after.
 
 constexpr double kSigma32 = 1.3 * 5.9604644775390625e-08;  // rms rounding of a group sum, relative
 
@@ -66,6 +66,9 @@ __device__ __forceinline__ void grid32_resident(const GridArgs &g, const double 
   const int rho_l = lane & (g.R - 1);
   const int iota = lane / g.R;
   const int G = grouped_u(g.n_a, g.J);
+  // this lane's angular data, u-major: rb[u] = rho_j, gb[u] = gam_j, j = iota + J u
+  const float *rb = lrho + iota * g.U;
+  const double *gb = lgam + iota * g.U;
   for (int t = 0; t < g.T; ++t) {
     const int i = rho_l + g.R * t;
     const bool vi = i < g.n_r;
@@ -87,10 +90,10 @@ __device__ __forceinline__ void grid32_resident(const GridArgs &g, const double 
       float H[kGroup], r[kGroup];
 #pragma unroll
       for (int k = 0; k < kGroup; ++k) {
-        r[k] = lrho[iota + g.J * (u + k)];
+        r[k] = rb[u + k];
         H[k] = row[(u + k) * kWave];
       }
-      const double gam = lgam[iota + g.J * u];
+      const double gam = gb[u];
       const float gam32 = (float)gam;
       // masses four at a time (ALL) or one by one: four independent chains
       // in flight cover the latency of the FP32 pipeline
@@ -129,9 +132,9 @@ __device__ __forceinline__ void grid32_resident(const GridArgs &g, const double 
     for (; u < g.U; ++u) {
       const int j = iota + g.J * u;
       if (j < g.n_a) {
-        const float r = lrho[j];
+        const float r = rb[u];
         const float H = row[u * kWave];
-        const double gam = lgam[j];
+        const double gam = gb[u];
         const float gam32 = (float)gam;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
@@ -170,12 +173,10 @@ __global__ __launch_bounds__(512) void grid32_kernel(GridArgs g) {
   const double p = g.p[a];
   const int n_r = g.n_r, n_a = g.n_a;
   const int TU = g.T * g.U;
-  double *lH = lds;
-  double *lc = lH + TU * kWave;
+  double *lc = lds;
   double *lq = lc + n_r;
-  double *lr = lq + n_r;
-  double *lgam = lr + n_a;
-  float *lH32 = reinterpret_cast<float *>(lgam + n_a);
+  double *lgam = lq + n_r;
+  float *lH32 = reinterpret_cast<float *>(lgam + g.J * g.U);
   float *lrho = lH32 + TU * kWave;
   const double *gsig = g.tab32 + n_a;
   const float *grho = reinterpret_cast<const float *>(g.tab32 + 2 * n_a);
@@ -183,12 +184,14 @@ __global__ __launch_bounds__(512) void grid32_kernel(GridArgs g) {
     lc[idx] = g.tab[n_r + idx];
     lq[idx] = g.tab[2 * n_r + idx];
   }
-  for (int idx = threadIdx.x; idx < n_a; idx += blockDim.x) {
-    lr[idx] = g.tab[3 * n_r + 2 * n_a + idx];
-    lgam[idx] = g.tab32[idx];
-    lrho[idx] = grho[idx];
+  for (int idx = threadIdx.x; idx < g.J * g.U; idx += blockDim.x) {
+    // lane-major copies: entry (iota, u) holds angular node j = iota + J u
+    const int iota = idx / g.U, u = idx - iota * g.U;
+    const int j = iota + g.J * u;
+    lgam[idx] = j < n_a ? g.tab32[j] : 0.0;
+    lrho[idx] = j < n_a ? grho[j] : 1.0f;
   }
-  grid_fill<REG>(g, lH, 0, TU, p, lH32, gsig);
+  grid_fill<REG>(g, nullptr, 0, TU, p, lH32, gsig);
   __syncthreads();
   const bool p_ok = p >= 0.0;
   const unsigned all = (M == 32) ? ~0u : ((1u << M) - 1u);
@@ -197,7 +200,7 @@ __global__ __launch_bounds__(512) void grid32_kernel(GridArgs g) {
     if (m0 >= g.n_m) break;  // wave-uniform
     double dm[M], edel[M];
     float dh[M];
-    unsigned okm = 0, m32 = 0, gm = 0;
+    unsigned okm = 0, m32 = 0;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       const int64_t idx = m0 + m;
@@ -210,12 +213,10 @@ __global__ __launch_bounds__(512) void grid32_kernel(GridArgs g) {
       edel[m] = fabs((double)dh[m] - dhat) * __builtin_amdgcn_rcp(dhat);  // a bound: few digits
       okm |= ok ? (1u << m) : 0u;
       m32 |= (ok && dhat >= g.f32_band && range32_ok(g, dhat, p)) ? (1u << m) : 0u;
-      gm |= chain_ok(dm[m], p, g.q_top, g.rmu_max) ? (1u << m) : 0u;
     }
     // the masses are the same in every lane: make the choices wave-uniform
     okm = __builtin_amdgcn_readfirstlane(okm);
     m32 = __builtin_amdgcn_readfirstlane(m32);
-    gm = __builtin_amdgcn_readfirstlane(gm);
     const int mine = lane / (kWave / M);
     const bool leader = lane % (kWave / M) == 0;
     double s32 = 0.0, err32 = 0.0;
@@ -242,40 +243,25 @@ __global__ __launch_bounds__(512) void grid32_kernel(GridArgs g) {
       for (int m = 0; m < M; ++m) flagged |= ((b >> (m * (kWave / M))) & 1ull) ? (1u << m) : 0u;
     }
     const unsigned m64 = (okm & ~m32) | flagged;
-    double s64 = 0.0;
-    if (m64) {
-      double tot[M];
-#pragma unroll
-      for (int m = 0; m < M; ++m) tot[m] = 0.0;
-      if (m64 == all && gm == all)
-        grid_resident<M, true>(g, lH, lc, lq, lr, lane, dm, m64, gm, tot);
-      else
-        grid_resident<M, false>(g, lH, lc, lq, lr, lane, dm, m64, gm, tot);
-      s64 = wave_sum_split<M>(tot, lane);
-    }
     bool badm = false;
 #pragma unroll
     for (int m = 0; m < M; ++m) badm |= (m0 + m < g.n_m) && !((okm >> m) & 1u);
     if (badm && lane == 0) *g.flag = 1;
+    // FP64 masses are marked used64 = 1 here and computed by the FP64 grid
+    // kernel in redo mode, launched next on the same stream
     if (leader && m0 + mine < g.n_m) {
       const int64_t o = a * g.n_m + m0 + mine;
-      double v, e;
-      uint8_t used;
       if (!((okm >> mine) & 1u)) {
-        v = e = __builtin_nan("");
-        used = 0;
+        g.out[o] = __builtin_nan("");
+        if (g.err) g.err[o] = __builtin_nan("");
+        g.used64[o] = 0;
       } else if ((m64 >> mine) & 1u) {
-        v = g.pref * s64;
-        e = kErr64;
-        used = 1;
+        g.used64[o] = 1;
       } else {
-        v = (g.pref * g.inv_k2) * s32;
-        e = err32;
-        used = 0;
+        g.out[o] = (g.pref * g.inv_k2) * s32;
+        if (g.err) g.err[o] = err32;
+        g.used64[o] = 0;
       }
-      g.out[o] = v;
-      if (g.err) g.err[o] = e;
-      if (g.used64) g.used64[o] = used;
     }
   }
 }
@@ -300,8 +286,7 @@ int launch_fp32c(const SetDev &s, int tile_points, int64_t grid_nm, int *d_flag,
 
 int grid32_lds_bytes(const GridArgs &g) {
   const int TU = g.T * g.U;
-  return (int)(sizeof(double) * (TU * kWave + 2 * g.n_r + 2 * g.n_a) +
-               sizeof(float) * (TU * kWave + g.n_a));
+  return (int)(sizeof(double) * (2 * g.n_r + g.J * g.U) + sizeof(float) * (TU * kWave + g.J * g.U));
 }
 
 template <int REG, int M>

@@ -57,8 +57,8 @@ struct DescRing {
 // them per key with measured choices.  No launch shape changes a result.
 struct GridCfg {
   int M = 8;    // masses per wave
-  int W = 8;    // waves per workgroup
-  int MB = 8;   // mass blocks per wave while the table is resident
+  int W = 4;    // waves per workgroup
+  int MB = 16;  // mass blocks per wave while the table is resident
 };
 struct PersistCfg {
   int tile = 4;  // points per tile
@@ -68,6 +68,7 @@ using ShapeKey = std::tuple<int, int, int, int>;  // (regulator, n_r, n_a, preci
 
 struct Tune {
   GridCfg grid;
+  GridCfg grid32{4, 8, 16};  // compensated-FP32 grid kernel (M <= 8)
   int plain_tile = 8;
   PersistCfg persist;
   int grid_lds_rows = 64;  // (t, u) rows of 64 doubles staged per LDS chunk
@@ -101,6 +102,7 @@ struct Context {
   int *d_counter = nullptr;
   frg::DescRing ring;
   frg::DevBuf stage_in, stage_out;
+  frg::DevBuf flags8;  // per-point FP64-redo marks of FP32C grids without used_fp64
   frg::Tune tune;
   uint64_t hbm_budget = 0;
 
@@ -137,7 +139,8 @@ struct Context {
                double *const *dUdt, double *const *jac, int *flags_dev, hipStream_t st);
   void stop_server();
   // autotune.cpp
-  int grid_launch(GridArgs g, int reg, const GridCfg &cfg, hipStream_t st, bool f32 = false);
+  // kind: 0 FP64 grid kernel, 1 compensated-FP32 grid kernel, 2 FP64 redo pass
+  int grid_launch(GridArgs g, int reg, const GridCfg &cfg, hipStream_t st, int kind = 0);
   GridCfg grid_cfg(const frg_quad &q, const GridArgs &g, hipStream_t st);
   int plain_tile_for(const SetDev &s, hipStream_t st);
   PersistCfg persist_cfg(const std::vector<SetDev> &sd, int prec, hipStream_t st);

@@ -136,7 +136,7 @@ int launch_points_persistent(const SetDev *d_sets, const Tile *d_tiles, int n_ti
                              int *d_counter, int lds_bytes, int n_blocks, bool with_f32,
                              int *d_flag, void *stream);
 int launch_reset_counter(int *d_counter, void *stream);
-int launch_grid(const GridArgs &g, int reg, int M, int W, void *stream);
+int launch_grid(const GridArgs &g, int reg, int M, int W, void *stream, bool redo = false);
 int grid_lds_bytes(const GridArgs &g);
 int launch_fp32c(const SetDev &s, int tile_points, int64_t grid_nm, int *d_flag, void *stream);
 int launch_grid32(const GridArgs &g, int reg, int M, int W, void *stream);

@@ -119,8 +119,10 @@ __global__ void reset_counter_kernel(int *c) {
 // visiting order, the grouping and the arithmetic are those of lane_point, so
 // results match the point kernel bit for bit.
 
-// RESIDENT: the whole table fits in g.chunk rows (host-checked).
-template <int REG, int M, bool RESIDENT>
+// RESIDENT: the whole table fits in g.chunk rows (host-checked).  REDO: only
+// the masses with used64 == 1 (left for FP64 by the compensated-FP32 grid
+// kernel) are computed; a workgroup with none of them returns before its fill.
+template <int REG, int M, bool RESIDENT, bool REDO>
 __global__ __launch_bounds__(512) void grid_kernel(GridArgs g) {
   extern __shared__ double lds[];
   const int W = blockDim.x / kWave;
@@ -134,6 +136,13 @@ __global__ __launch_bounds__(512) void grid_kernel(GridArgs g) {
   constexpr bool resident = RESIDENT;
   const int C = resident ? TU : g.chunk;
   const int MB = resident ? g.mblocks : 1;
+  if constexpr (REDO) {
+    const int64_t first = (int64_t)mb * MB * W * M;
+    bool any = false;
+    for (int idx = threadIdx.x; idx < MB * W * M; idx += blockDim.x)
+      any |= first + idx < g.n_m && g.used64[a * g.n_m + first + idx] == 1;
+    if (!__syncthreads_or(any)) return;  // workgroup-uniform
+  }
   double *lH = lds;
   double *lc = lH + C * kWave;
   double *lq = lc + n_r;
@@ -148,12 +157,13 @@ __global__ __launch_bounds__(512) void grid_kernel(GridArgs g) {
     __syncthreads();
   }
   const bool p_ok = p >= 0.0;
+  const unsigned all = (M == 32) ? ~0u : ((1u << M) - 1u);
   for (int rep = 0; rep < MB; ++rep) {
     const int64_t m0 = (((int64_t)mb * MB + rep) * W + wave) * M;
     if (m0 >= g.n_m && resident) break;  // wave-uniform
     double dm[M];
     bool ok[M];
-    unsigned mask = 0;
+    unsigned mask = 0, act = all;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       const int64_t idx = m0 + m;
@@ -162,17 +172,22 @@ __global__ __launch_bounds__(512) void grid_kernel(GridArgs g) {
       ok[m] = valid && p_ok && d > 0.0;
       dm[m] = ok[m] ? d : 1.0;
       mask |= chain_ok(dm[m], p, g.q_top, g.rmu_max) ? (1u << m) : 0u;
+      if (REDO && !(valid && g.used64[a * g.n_m + idx] == 1)) act &= ~(1u << m);
     }
-    // the masses are the same in every lane: make the choice wave-uniform
+    // the masses are the same in every lane: make the choices wave-uniform
     const unsigned gmask = __builtin_amdgcn_readfirstlane(mask);
+    if (REDO) {
+      act = __builtin_amdgcn_readfirstlane(act);
+      if (!act) continue;
+    }
     double tot[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) tot[m] = 0.0;
     if constexpr (RESIDENT) {
-      if (gmask == (M == 32 ? ~0u : ((1u << M) - 1u)))
-        grid_resident<M, true>(g, lH, lc, lq, lr, lane, dm, ~0u, gmask, tot);
+      if (act == all && gmask == all)
+        grid_resident<M, true>(g, lH, lc, lq, lr, lane, dm, act, gmask, tot);
       else
-        grid_resident<M, false>(g, lH, lc, lq, lr, lane, dm, ~0u, gmask, tot);
+        grid_resident<M, false>(g, lH, lc, lq, lr, lane, dm, act, gmask, tot);
     } else {
       double A[M], in[M];
 #pragma unroll
@@ -198,6 +213,15 @@ __global__ __launch_bounds__(512) void grid_kernel(GridArgs g) {
       bad |= (m0 + m < g.n_m) && !ok[m];
     }
     const bool okm = (okbits >> mine) & 1u;
+    if (REDO) {
+      // the FP32 kernel has already written the other points and the flag
+      if (lane % (kWave / M) == 0 && ((act >> mine) & 1u)) {
+        const int64_t o = a * g.n_m + m0 + mine;
+        g.out[o] = okm ? v : __builtin_nan("");
+        if (g.err) g.err[o] = kErr64;
+      }
+      continue;
+    }
     if (bad && lane == 0) *g.flag = 1;
     if (lane % (kWave / M) == 0 && m0 + mine < g.n_m)
       g.out[a * g.n_m + m0 + mine] = okm ? v : __builtin_nan("");
@@ -343,30 +367,33 @@ int grid_lds_bytes(const GridArgs &g) {
 }
 
 template <int REG, int M>
-static void grid_launch_t(const GridArgs &g, int W, hipStream_t st) {
+static void grid_launch_t(const GridArgs &g, int W, bool redo, hipStream_t st) {
   const int64_t blocks = g.n_p * g.n_mb;
-  if (g.T * g.U <= g.chunk)
-    hipLaunchKernelGGL((grid_kernel<REG, M, true>), dim3((unsigned)blocks), dim3(kWave * W),
+  if (redo)  // resident tables only (host-checked)
+    hipLaunchKernelGGL((grid_kernel<REG, M, true, true>), dim3((unsigned)blocks), dim3(kWave * W),
                        grid_lds_bytes(g), st, g);
+  else if (g.T * g.U <= g.chunk)
+    hipLaunchKernelGGL((grid_kernel<REG, M, true, false>), dim3((unsigned)blocks),
+                       dim3(kWave * W), grid_lds_bytes(g), st, g);
   else
-    hipLaunchKernelGGL((grid_kernel<REG, M, false>), dim3((unsigned)blocks), dim3(kWave * W),
-                       grid_lds_bytes(g), st, g);
+    hipLaunchKernelGGL((grid_kernel<REG, M, false, false>), dim3((unsigned)blocks),
+                       dim3(kWave * W), grid_lds_bytes(g), st, g);
 }
 
-int launch_grid(const GridArgs &g, int reg, int M, int W, void *stream) {
+int launch_grid(const GridArgs &g, int reg, int M, int W, void *stream, bool redo) {
   if (g.n_p <= 0 || g.n_m <= 0) return 0;
   hipStream_t st = (hipStream_t)stream;
   if (reg == kExp) {
     switch (M) {
-      case 4: grid_launch_t<kExp, 4>(g, W, st); break;
-      case 8: grid_launch_t<kExp, 8>(g, W, st); break;
-      default: grid_launch_t<kExp, 16>(g, W, st); break;
+      case 4: grid_launch_t<kExp, 4>(g, W, redo, st); break;
+      case 8: grid_launch_t<kExp, 8>(g, W, redo, st); break;
+      default: grid_launch_t<kExp, 16>(g, W, redo, st); break;
     }
   } else {
     switch (M) {
-      case 4: grid_launch_t<kLitim, 4>(g, W, st); break;
-      case 8: grid_launch_t<kLitim, 8>(g, W, st); break;
-      default: grid_launch_t<kLitim, 16>(g, W, st); break;
+      case 4: grid_launch_t<kLitim, 4>(g, W, redo, st); break;
+      case 8: grid_launch_t<kLitim, 8>(g, W, redo, st); break;
+      default: grid_launch_t<kLitim, 16>(g, W, redo, st); break;
     }
   }
   return (int)hipGetLastError();
