@@ -35,9 +35,9 @@ sys.path.insert(0, ROOT)
 # a group of eight terms and left out of the floor.
 VALU_LANE_CYCLES = 256 * 4 * 16 * 2.4e9
 # HBM bytes per grid_kernel launch from rocprofv3 FETCH_SIZE / WRITE_SIZE,
-# scaled by a 1 GiB device copy read the same way; None until the counters
-# have been taken on the current kernel.
-TRAFFIC = None
+# scaled by a 1 GiB device copy read the same way (fetch x2.00, write x1.00):
+# 360 KiB x 2.00 + 16384 KiB x 1.00.
+TRAFFIC = 360 * 1024 * 2.00 + 16384 * 1024 * 1.00
 CYCLES_PER_EVAL_FLOOR = 3
 PEAK_EVALS = VALU_LANE_CYCLES / CYCLES_PER_EVAL_FLOOR
 
@@ -51,9 +51,10 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device-to-device copy of 1 GiB (PMC traffic calibration)")
-    ap.add_argument("--only", choices=["uneven64", "uneven32"], default=None,
+    ap.add_argument("--only", choices=["uneven64", "uneven32", "grid32"], default=None,
                     help="profiling aid: run only --steps persistent launches of the uneven sets "
-                         "(FP64 or FP32C) and print their timing")
+                         "(FP64 or FP32C), or --steps FP32C scale-up grid calls, and print "
+                         "their timing")
     return ap.parse_args()
 
 
@@ -81,16 +82,43 @@ def only_uneven(prec_name, steps, warmup):
                       "evals_per_s": evals / dt}), flush=True)
 
 
+def only_grid32(steps, warmup):
+    import torch
+    from paper_2607_24908_amd import frg, workloads
+    ctx = frg.frg_create(0)
+    w = workloads.scaleup_d3()
+    q = w.quad
+    quad = frg.make_quad(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a, frg.FRG_PREC_FP32C)
+    P = torch.as_tensor(w.p, device="cuda")
+    M = torch.as_tensor(w.m2, device="cuda")
+    out = torch.empty(w.n_integrals, dtype=torch.float64, device="cuda")
+    err = torch.empty_like(out)
+    used = torch.empty(w.n_integrals, dtype=torch.uint8, device="cuda")
+    for _ in range(warmup):
+        frg.frg_integrate_grid(ctx, quad, P, M, out, err, used)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        frg.frg_integrate_grid(ctx, quad, P, M, out, err, used)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    share = float(used.float().mean().item())
+    frg.frg_destroy(ctx)
+    print(json.dumps({"only": "grid32", "steps": steps, "ms_per_call": dt * 1e3,
+                      "evals_per_s": w.n_evals / dt, "fp64_share": share}), flush=True)
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def cpu_baseline(w):
-    """The FP64 oracle, as it stands, on 1/16 of the workload (every 16th mass
-    for all momenta), OpenMP over points on the host cores."""
+    """The FP64 oracle, as it stands, on 1/4 of the workload (every 4th mass
+    for all momenta, about 20-30 core-seconds), OpenMP over points on the host
+    cores."""
     import oracle
     q = w.quad
-    m2 = w.m2[::16]
+    m2 = w.m2[::4]
     P = np.repeat(w.p, m2.size)
     M = np.tile(m2, w.p.size)
     try:
@@ -103,7 +131,7 @@ def cpu_baseline(w):
     dt = time.perf_counter() - t0
     evals = P.size * q.n_r * q.n_a
     return {"value": evals / dt, "unit": "integrand evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"1/16 of the workload: all {w.p.size} momenta x every 16th mass "
+            "sample": f"1/4 of the workload: all {w.p.size} momenta x every 4th mass "
                       f"({P.size} integrals, {evals:.3e} evals), {dt:.2f} s wall"}
 
 
@@ -114,6 +142,9 @@ def main():
               "(integral sets and flows shard across GPUs with no exchange; see DESIGN.md)",
               file=sys.stderr)
         sys.exit(2)
+    if args.only == "grid32":
+        only_grid32(args.steps, args.warmup)
+        return
     if args.only:
         only_uneven(args.only, args.steps, args.warmup)
         return
