@@ -56,6 +56,10 @@ def lib():
         L.oracle_threshold.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_long, dp, dp]
+        L.oracle_integrate_tab.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_long, ctypes.c_long, ctypes.c_double, dp,
+                                           ctypes.c_long, dp, dp, ctypes.c_int]
         L.oracle_lpa_rhs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                      ctypes.c_double, ctypes.c_double, ctypes.c_long,
                                      ctypes.c_double, dp, dp, dp]
@@ -117,6 +121,24 @@ def integrate_grid(d, reg, k, q_max, n_r, n_a, p, m2, threads=1):
     P = np.repeat(p, m2.size)
     M = np.tile(m2, p.size)
     return integrate(d, reg, k, q_max, n_r, n_a, P, M, threads).reshape(p.size, m2.size)
+
+
+def integrate_tab(d, reg, k, q_max, n_r, n_a, G, s_max, p, threads=1, allow_domain=False):
+    """Tabulated-propagator variant: out[a, r] = I(p[a], row r) with the
+    propagator taken from row r of G (shape (n_rows, n_s)) by piecewise-linear
+    interpolation on the uniform grid s_k = k s_max/(n_s - 1) (constant beyond
+    s_max), in both G(q_i^2) and G(s_ij); d_tR stays analytic."""
+    G = np.ascontiguousarray(np.asarray(G, dtype=np.float64))
+    if G.ndim != 2:
+        raise ValueError("G must be (n_rows, n_s)")
+    p = _f64(p).ravel()
+    out = np.empty((p.size, G.shape[0]))
+    rc = lib().oracle_integrate_tab(int(d), int(reg), float(k), float(q_max), int(n_r), int(n_a),
+                                    G.shape[0], G.shape[1], float(s_max), _ptr(G), p.size, _ptr(p),
+                                    _ptr(out), int(threads))
+    if rc == E_INVAL or (rc == E_DOMAIN and not allow_domain):
+        raise ValueError(f"oracle_integrate_tab rc={rc}")
+    return out
 
 
 def threshold(d, reg, k, q_max, n_r, n, m2, allow_domain=False):

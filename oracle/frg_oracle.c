@@ -37,6 +37,14 @@
  *   Radial domain Q = q_max (exponential), Q = min(q_max, k) (Litim: the
  *   support of d_tR).
  *
+ *   Tabulated-propagator variant: the propagator of row r of a caller's
+ *   table (a dressed propagator from an earlier solution, n_s values on the
+ *   uniform grid s_k = k s_max/(n_s - 1)) replaces G in both places, the
+ *   regulator insertion d_tR stays analytic:
+ *     I(p, r) = P_d sum_i sum_j w_i q_i^{d-1} d_tR(q_i^2) G_r(q_i^2)^2 mu_j G_r(s_ij),
+ *     G_r(s) = (1 - f) g_r[k] + f g_r[k+1],  t = s/h, k = floor(t), f = t - k,
+ *   (piecewise-linear interpolation; s >= s_max takes g_r[n_s - 1]).
+ *
  *   Threshold functions (radial only, LPA):
  *     F_n(m^2) = C_d sum_i w_i q_i^{d-1} d_tR(q_i^2) G(q_i^2)^n,
  *     C_d = Omega_d/(2pi)^d.
@@ -216,6 +224,61 @@ int oracle_integrate(int d, int reg, double k, double q_max, int n_r, int n_a, l
       }
     }
     out[e] = Pd * (double)acc;
+  }
+  free(q); free(w); free(x); free(v); free(mu);
+  return domain ? OR_E_DOMAIN : OR_OK;
+}
+
+/* piecewise-linear interpolation of one table row at s (constant beyond s_max) */
+static double interp_row(const double *g, long n_s, double s_max, double s) {
+  double h = s_max / (double)(n_s - 1);
+  double t = s / h;
+  if (t >= (double)(n_s - 1)) return g[n_s - 1];
+  if (t < 0.0) t = 0.0;
+  long k = (long)floor(t);
+  double f = t - (double)k;
+  return (1.0 - f) * g[k] + f * g[k + 1];
+}
+
+/* Tabulated variant: out[a * n_rows + r] = I(p_a, row r). */
+int oracle_integrate_tab(int d, int reg, double k, double q_max, int n_r, int n_a, long n_rows,
+                         long n_s, double s_max, const double *G, long n_p, const double *p,
+                         double *out, int n_threads) {
+  if (check_common(d, reg, k, q_max, n_r) || d < 3 || n_a < 1 || n_p < 0 || n_rows < 0)
+    return OR_E_INVAL;
+  if (n_s < 2 || !(s_max > 0.0)) return OR_E_INVAL;
+  if (n_p > 0 && n_rows > 0 && (!p || !G || !out)) return OR_E_INVAL;
+  double *q = malloc(sizeof(double) * n_r), *w = malloc(sizeof(double) * n_r);
+  double *x = malloc(sizeof(double) * n_a), *v = malloc(sizeof(double) * n_a);
+  double *mu = malloc(sizeof(double) * n_a);
+  radial_rule(reg, k, q_max, n_r, q, w);
+  oracle_gauss_legendre(n_a, x, v);
+  for (int j = 0; j < n_a; ++j) mu[j] = v[j] * angular_factor(d, x[j]);
+  const double k2 = k * k;
+  const double Pd = oracle_Pd(d);
+  int domain = 0;
+  if (n_threads < 1) n_threads = 1;
+#pragma omp parallel for collapse(2) schedule(dynamic, 8) num_threads(n_threads) reduction(| : domain)
+  for (long a = 0; a < n_p; ++a) {
+    for (long r = 0; r < n_rows; ++r) {
+      const double *g = G + r * n_s;
+      if (!(p[a] >= 0.0)) {
+        out[a * n_rows + r] = NAN;
+        domain |= 1;
+        continue;
+      }
+      long double acc = 0.0L;
+      for (int i = 0; i < n_r; ++i) {
+        double qi = q[i];
+        double Gq = interp_row(g, n_s, s_max, qi * qi);
+        double A = w[i] * ipow(qi, d - 1) * dtR(reg, k2, qi * qi) * Gq * Gq;
+        for (int j = 0; j < n_a; ++j) {
+          double s = (qi - p[a]) * (qi - p[a]) + 2.0 * qi * p[a] * (1.0 + x[j]);
+          acc += (long double)(A * mu[j] * interp_row(g, n_s, s_max, s));
+        }
+      }
+      out[a * n_rows + r] = Pd * (double)acc;
+    }
   }
   free(q); free(w); free(x); free(v); free(mu);
   return domain ? OR_E_DOMAIN : OR_OK;
