@@ -139,6 +139,35 @@ int frg_integrate_grid(frg_ctx *ctx, const frg_quad *quad, int64_t n_p, const do
                        int64_t n_m, const double *m2, double *out, double *err_est,
                        uint8_t *used_fp64, int32_t mem, void *hip_stream);
 
+/* ---- tabulated-propagator variant ---------------------------------------- */
+/* A table of n_rows propagators G_r(s), s = q^2 (for instance dressed
+ * propagators 1/(Gamma^(2)(q) + R_k(q)) from an earlier solution, one row per
+ * field value), each sampled at n_s >= 2 points of the uniform grid
+ * s_k = k s_max/(n_s - 1): g[r * n_s + k], contiguous float64.  Between nodes
+ * G_r is the piecewise-linear interpolant, G_r(s) = g_r[k] + f (g_r[k+1] -
+ * g_r[k]) with k = floor(s/h), f = s/h - k, h = s_max/(n_s - 1); beyond s_max
+ * it is the last node g_r[n_s - 1]. */
+typedef struct {
+  int64_t n_rows;
+  int64_t n_s;
+  double s_max;
+  const double *g;
+} frg_gtab;
+
+/* Flow diagram with tabulated propagators (the regulator insertion d_tR stays
+ * analytic; quad.prec must be FRG_PREC_FP64):
+ *   out[a * n_rows + r] = P_d sum_i sum_j w_i q_i^{d-1} d_tR(q_i^2)
+ *                          G_r(q_i^2)^2 mu_j G_r(s_ij),
+ *   s_ij = (q_i - p_a)^2 + 2 q_i p_a (1 + x_j)   (rules as for frg_set).
+ * p[a] >= 0 (a negative p gives NaN in its row of out and FRG_E_DOMAIN as
+ * for frg_integrate).  Rows that fit in LDS beside the quadrature tables (up
+ * to 6144 nodes, knob "tab_lds_nodes") are staged there; longer rows are read
+ * from HBM through the caches (the workgroups of one row run on one XCD so
+ * that its L2 serves them); both give the same bits.  mem says where p,
+ * tab->g and out live; n_p * n_rows results. */
+int frg_integrate_tab(frg_ctx *ctx, const frg_quad *quad, const frg_gtab *tab, int64_t n_p,
+                      const double *p, double *out, int32_t mem, void *hip_stream);
+
 /* ---- LPA O(N) flow -------------------------------------------------------- */
 /* Local potential approximation of the O(N) model, effective potential U(rho)
  * with rho = phi^2/2 on the uniform grid rho_j = j rho_max/(n_grid-1):
@@ -259,7 +288,8 @@ int frg_autotune(frg_ctx *ctx, int32_t mode, const char *cache_path);
  * (1..8), "grid_MB" (1..64) of the FP64 tensor-grid kernel, "grid32_M" (4, 8),
  * "grid32_W" (1..8), "grid32_MB" (1..64) of the compensated-FP32 one,
  * "grid_lds_rows" (8..96), "plain_tile", "persist_tile" (1..64),
- * "persist_wpc" (1..64).  Setting a knob drops the
+ * "persist_wpc" (1..64), and of the tabulated variant "tab_W" (1..4),
+ * "tab_pw" (momenta per wave, 1..64), "tab_lds_nodes" (2..6144).  Setting a knob drops the
  * tuned choices so that it takes effect.  Two knobs route FRG_PREC_FP32C
  * points to FP64 and do change results (within the FP32 tolerance):
  * "fp32c_flag_ppb" (error-estimate threshold in units of 1e-9, default 100)

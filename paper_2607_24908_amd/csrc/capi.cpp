@@ -535,6 +535,40 @@ int Ctx::grid_launch(GridArgs g, int reg, const GridCfg &cfg, hipStream_t st, in
   return FRG_OK;
 }
 
+// ------------------------------------------------------ tabulated G --
+int Ctx::tab_device(const frg_quad &q, const frg_gtab &tb, int64_t n_p, const double *p,
+                    double *out, hipStream_t st) {
+  const double *tab;
+  QuadTable h;
+  int rc = quad_table(q, &tab, &h);
+  if (rc) return rc;
+  TabArgs a{};
+  a.p = p;
+  a.out = out;
+  a.g = tb.g;
+  a.tab = tab;
+  a.flag = d_flag;
+  a.pref = h.pref;
+  a.k2 = h.k2;
+  a.inv_h = (double)(tb.n_s - 1) / tb.s_max;
+  a.t_last = (double)(tb.n_s - 1);
+  a.n_p = n_p;
+  a.n_rows = tb.n_rows;
+  a.n_s = tb.n_s;
+  a.n_r = q.n_radial;
+  a.n_a = q.n_angular;
+  tab_lane_split(a.n_r, a.n_a, &a.R, &a.J, &a.T, &a.U);
+  const int W = std::max(1, std::min(4, tune.tab_W));
+  a.pw = std::max(1, std::min(64, tune.tab_pw));
+  a.n_pb = (int)((n_p + (int64_t)W * a.pw - 1) / ((int64_t)W * a.pw));
+  const bool lds_rows = tb.n_s <= std::min<int64_t>(tune.tab_lds_nodes, tab_lds_max_nodes) &&
+                        tab_lds_bytes(a, true) <= 64 * 1024;
+  if (tb.n_rows * a.n_pb > ((int64_t)1 << 31) - 1) return fail(FRG_E_INVAL, "tabulated problem too large");
+  int e = launch_tab(a, q.reg, W, lds_rows, st);
+  if (e) return hip_fail((hipError_t)e, "tab_kernel launch");
+  return FRG_OK;
+}
+
 // --------------------------------------------------------------- FP32C --
 // Sets with FRG_PREC_FP32C run the compensated-FP32 kernel (one launch per
 // set); FP64 sets of the same call take the FP64 paths.
@@ -805,6 +839,50 @@ int frg_integrate_grid(frg_ctx *ctx, const frg_quad *quad, int64_t n_p, const do
   hipError_t e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
   if (flag) return fail(FRG_E_DOMAIN, "some masses have m^2 + k^2 <= 0; their results are NaN");
+  return FRG_OK;
+}
+
+int frg_integrate_tab(frg_ctx *ctx, const frg_quad *quad, const frg_gtab *tab, int64_t n_p,
+                      const double *p, double *out, int32_t mem, void *hip_stream) {
+  if (!ctx || !quad || !tab) return fail(FRG_E_INVAL, "NULL argument");
+  int rc = check_quad(*quad);
+  if (rc) return rc;
+  if (quad->prec != FRG_PREC_FP64) return fail(FRG_E_INVAL, "the tabulated variant is FP64 only");
+  if (n_p < 0 || tab->n_rows < 0) return fail(FRG_E_INVAL, "negative size");
+  if (tab->n_s < 2 || tab->n_s > ((int64_t)1 << 30)) return fail(FRG_E_INVAL, "tab.n_s outside [2, 2^30]");
+  if (!(tab->s_max > 0.0) || !std::isfinite(tab->s_max)) return fail(FRG_E_INVAL, "tab.s_max must be finite and > 0");
+  if (n_p > ((int64_t)1 << 30) || tab->n_rows > ((int64_t)1 << 24)) return fail(FRG_E_INVAL, "problem too large");
+  if (mem != FRG_MEM_HOST && mem != FRG_MEM_DEVICE) return fail(FRG_E_INVAL, "bad mem");
+  if (n_p == 0 || tab->n_rows == 0) return FRG_OK;
+  if (!p || !out || !tab->g) return fail(FRG_E_INVAL, "NULL array");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  hipSetDevice(ctx->device);
+  clear_error();
+  if (mem == FRG_MEM_DEVICE) return ctx->tab_device(*quad, *tab, n_p, p, out, (hipStream_t)hip_stream);
+  const size_t gbytes = (size_t)(tab->n_rows * tab->n_s) * sizeof(double);
+  const size_t nout = (size_t)(n_p * tab->n_rows);
+  rc = ctx->stage_in.reserve(n_p * sizeof(double) + gbytes + 64);
+  if (!rc) rc = ctx->stage_out.reserve(nout * sizeof(double) + 64);
+  if (rc) return rc;
+  double *dp = (double *)ctx->stage_in.ptr, *dg = dp + n_p;
+  double *dout = (double *)ctx->stage_out.ptr;
+  hipStream_t st = ctx->stream;
+  hipMemcpyAsync(dp, p, n_p * sizeof(double), hipMemcpyHostToDevice, st);
+  hipMemcpyAsync(dg, tab->g, gbytes, hipMemcpyHostToDevice, st);
+  hipMemsetAsync(ctx->d_flag, 0, sizeof(int), st);
+  frg_gtab dt = *tab;
+  dt.g = dg;
+  rc = ctx->tab_device(*quad, dt, n_p, dp, dout, st);
+  if (rc) {
+    hipStreamSynchronize(st);
+    return rc;
+  }
+  hipMemcpyAsync(out, dout, nout * sizeof(double), hipMemcpyDeviceToHost, st);
+  int flag = 0;
+  hipMemcpyAsync(&flag, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, st);
+  hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  if (flag) return fail(FRG_E_DOMAIN, "some momenta are negative; their results are NaN");
   return FRG_OK;
 }
 

@@ -70,6 +70,9 @@ struct Tune {
   GridCfg grid;
   GridCfg grid32{4, 8, 16};  // compensated-FP32 grid kernel (M <= 8)
   int plain_tile = 8;
+  int tab_W = 4;           // tabulated variant: waves per workgroup
+  int tab_pw = 16;         // tabulated variant: momenta per wave
+  int tab_lds_nodes = 6144;  // tabulated variant: rows up to this many nodes staged in LDS
   PersistCfg persist;
   int grid_lds_rows = 64;  // (t, u) rows of 64 doubles staged per LDS chunk
   int fp32c_flag_ppb = 100;    // FP32C: FP64 redo above this error estimate (1e-9 units)
@@ -131,6 +134,8 @@ struct Context {
   int persistent(const std::vector<frg::SetDev> &sd, const frg_set *sets, int n_sets, int flags,
                  hipStream_t st);
   int integrate_fp32c_sets(const std::vector<frg::SetDev> &sd, int flags, hipStream_t st);
+  int tab_device(const frg_quad &q, const frg_gtab &tab, int64_t n_p, const double *p, double *out,
+                 hipStream_t st);
   int grid_device(const frg_quad &q, int64_t n_p, const double *p, int64_t n_m, const double *m2,
                   double *out, double *err, uint8_t *used, hipStream_t st);
   int grid_fp32c(const frg_quad &q, int64_t n_p, const double *p, int64_t n_m, const double *m2,

@@ -129,6 +129,26 @@ struct LpaJob {
 
 void lane_split(int n_r, int n_a, int *R, int *J, int *T, int *U);
 
+// Tabulated-propagator kernel arguments.  Lane map: J = largest power of two
+// <= min(n_a, 8) angular lanes (neighbouring lanes read neighbouring table
+// entries), R = 64 / J radial lanes.
+struct TabArgs {
+  const double *p;
+  double *out;
+  const double *g;    // table rows, g[r * n_s + k]
+  const double *tab;  // QuadTable::data on the device
+  int *flag;
+  double pref, k2, inv_h, t_last;  // t_last = n_s - 1
+  int64_t n_p, n_rows, n_s;
+  int32_t n_r, n_a, R, J, T, U;
+  int32_t pw;     // momenta per wave
+  int32_t n_pb;   // momentum blocks per row (W * pw momenta each)
+};
+void tab_lane_split(int n_r, int n_a, int *R, int *J, int *T, int *U);
+constexpr int64_t tab_lds_max_nodes = 6144;  // rows up to this many nodes are staged in LDS
+
+
+
 // -------------------------------------------------------------- launchers --
 // All return hipError_t as int (0 = success).
 int launch_points_plain(const SetDev &s, int tile_points, int *d_flag, void *stream);
@@ -140,6 +160,8 @@ int launch_grid(const GridArgs &g, int reg, int M, int W, void *stream, bool red
 int grid_lds_bytes(const GridArgs &g);
 int launch_fp32c(const SetDev &s, int tile_points, int64_t grid_nm, int *d_flag, void *stream);
 int launch_grid32(const GridArgs &g, int reg, int M, int W, void *stream);
+int launch_tab(const TabArgs &t, int reg, int W, bool lds_rows, void *stream);
+int tab_lds_bytes(const TabArgs &t, bool lds_rows);
 int grid32_lds_bytes(const GridArgs &g);
 int launch_lpa(const LpaJob *d_jobs, const int64_t *d_start, int n_jobs, int64_t total_points,
                void *stream);

@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "FRG_OK", 1: "FRG_PENDING", -1: "FRG_E_INVAL", -2: "FRG_E_DOM
                 -6: "FRG_E_NOTFOUND", -7: "FRG_E_STEP"}
 
 EXPORTS = ["frg_create", "frg_destroy", "frg_last_error", "frg_version", "frg_integrate",
-           "frg_integrate_grid", "frg_flow_rhs", "frg_flow_rhs_batch", "frg_flow_solve",
+           "frg_integrate_grid", "frg_integrate_tab", "frg_flow_rhs", "frg_flow_rhs_batch", "frg_flow_solve",
            "frg_submit", "frg_poll", "frg_server_stats", "frg_gauss_legendre",
            "frg_flow_footprint", "frg_autotune", "frg_tune_set", "frg_tune_get"]
 
@@ -45,6 +45,11 @@ class frg_set(ctypes.Structure):
     _fields_ = [("quad", frg_quad), ("n_ext", ctypes.c_int64), ("p", ctypes.c_void_p),
                 ("m2", ctypes.c_void_p), ("out", ctypes.c_void_p), ("err_est", ctypes.c_void_p),
                 ("used_fp64", ctypes.c_void_p)]
+
+
+class frg_gtab(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("n_s", ctypes.c_int64), ("s_max", ctypes.c_double),
+                ("g", ctypes.c_void_p)]
 
 
 class frg_lpa(ctypes.Structure):
@@ -101,6 +106,8 @@ def _load():
     L.frg_integrate.argtypes = [vp, ctypes.POINTER(frg_set), i32, i32, i32, vp]
     L.frg_integrate_grid.argtypes = [vp, ctypes.POINTER(frg_quad), i64, vp, i64, vp, vp, vp, vp,
                                      i32, vp]
+    L.frg_integrate_tab.argtypes = [vp, ctypes.POINTER(frg_quad), ctypes.POINTER(frg_gtab), i64,
+                                    vp, vp, i32, vp]
     L.frg_flow_rhs.argtypes = [vp, ctypes.POINTER(frg_lpa), dbl, vp, vp, vp, i32, vp]
     L.frg_flow_rhs_batch.argtypes = [vp, i32, ctypes.POINTER(frg_lpa), ctypes.POINTER(dbl),
                                      ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
@@ -195,6 +202,21 @@ def frg_integrate_grid(ctx, quad, p, m2, out, err_est=None, used_fp64=None, mem=
     st = 0 if mem == FRG_MEM_HOST else _stream(stream)
     return _check(lib.frg_integrate_grid(ctx, ctypes.byref(quad), n_p, _addr(p), n_m, _addr(m2),
                                          _addr(out), _addr(err_est), _addr(used_fp64), mem, st),
+                  (FRG_E_DOMAIN,) if allow_domain else ())
+
+
+def frg_integrate_tab(ctx, quad, g, s_max, p, out, mem=FRG_MEM_DEVICE, stream=None,
+                      allow_domain=False):
+    """g: (n_rows, n_s) float64 table (torch tensor or numpy array, contiguous),
+    out: n_p * n_rows results, out[a * n_rows + r]."""
+    shape = tuple(g.shape)
+    if len(shape) != 2:
+        raise ValueError("g must be (n_rows, n_s)")
+    tab = frg_gtab(shape[0], shape[1], float(s_max), _addr(g))
+    n_p = int(p.numel() if hasattr(p, "numel") else p.size)
+    st = 0 if mem == FRG_MEM_HOST else _stream(stream)
+    return _check(lib.frg_integrate_tab(ctx, ctypes.byref(quad), ctypes.byref(tab), n_p, _addr(p),
+                                        _addr(out), mem, st),
                   (FRG_E_DOMAIN,) if allow_domain else ())
 
 

@@ -19,6 +19,13 @@ regulator):
   [1e-3, 10] and m^2 uniform in [-0.5, 5].
 * ``precision_d4`` -- the plain_d4 shape with half of the masses close to the
   pole, m^2 = -k^2 + 10^U(-8,-1), and half uniform in [-0.9, 10].
+* ``tabulated_d3`` -- the tabulated-propagator variant: d = 3, exponential
+  regulator insertion, 1024 momenta log-spaced in [1e-4, 20], 64 table rows
+  (field values) of n_s nodes on s in [0, 676] = [0, (q_max + p_max)^2],
+  128 radial x 32 angular nodes.  Row r holds the smooth positive function
+  g_r(s) = (1 + 0.1/(1 + s))/(s + M_r), M_r evenly spaced in [0.1, 11] (an input
+  standing in for a dressed propagator; nothing of the method is computed).
+  n_s = 4096 (rows staged in LDS) and 2^20 (8 MB rows read through the caches).
 * ``lpa_requests`` -- a Poisson stream (rate 50/s) of LPA O(N) flow requests:
   N in {1, 2, 4}, d = 3, exponential regulator, grid of 128..1024 points on
   rho in [0, 0.5], initial U = lambda/8 (rho - rho0)^2 with lambda ~ U(1, 20),
@@ -120,6 +127,38 @@ def precision_d4(seed: int = 0) -> GridWorkload:
     q = Quad(d=4, reg=REG_EXP, k=1.0, q_max=6.0, n_r=64, n_a=16)
     return GridWorkload(f"precision_d4_seed{seed}", q, np.logspace(-3.0, 1.0, 64),
                         np.concatenate([np.sort(near), np.sort(far)]))
+
+
+@dataclass
+class TabWorkload:
+    name: str
+    quad: Quad
+    p: np.ndarray
+    g: np.ndarray      # (n_rows, n_s)
+    s_max: float
+
+    @property
+    def n_integrals(self) -> int:
+        return self.p.size * self.g.shape[0]
+
+    @property
+    def n_evals(self) -> int:
+        return self.n_integrals * self.quad.n_r * self.quad.n_a
+
+
+def tab_rows(n_rows: int, n_s: int, s_max: float, m_lo: float = 0.1, m_hi: float = 11.0) -> np.ndarray:
+    """Rows g_r(s_k) = (1 + 0.1/(1 + s_k))/(s_k + M_r) on s_k = k s_max/(n_s - 1)."""
+    s = np.linspace(0.0, s_max, n_s)
+    M = np.linspace(m_lo, m_hi, n_rows)
+    return (1.0 + 0.1 / (1.0 + s))[None, :] / (s[None, :] + M[:, None])
+
+
+def tabulated_d3(n_s: int = 4096, n_p: int = 1024, n_rows: int = 64) -> TabWorkload:
+    q = Quad(d=3, reg=REG_EXP, k=1.0, q_max=6.0, n_r=128, n_a=32)
+    p = np.logspace(-4.0, np.log10(20.0), n_p)
+    s_max = (q.q_max + 20.0) ** 2
+    return TabWorkload(f"tabulated_d3_{n_p}p_{n_rows}rows_{n_s}s_128r32a", q, p,
+                       tab_rows(n_rows, n_s, s_max), s_max)
 
 
 @dataclass

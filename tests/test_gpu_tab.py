@@ -1,0 +1,124 @@
+"""Tabulated-propagator variant (frg_integrate_tab) against the FP64 oracle.
+
+Bar: 1e-12 relative per result (smooth tables: the interpolation coordinate
+is formed with a different rounding on each side, which moves a result by
+about u times the relative slope of the row over its range).  The LDS-row
+and streamed-row forms of the kernel do the same arithmetic in the same
+order and must agree bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2607_24908_amd import frg, workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available()
+    h = frg.frg_create(0)
+    yield h
+    torch.cuda.synchronize()
+    frg.frg_destroy(h)
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+def run_tab(ctx, q, g, s_max, p, lds_nodes=6144, pw=16, W=4):
+    frg.frg_tune_set(ctx, "tab_lds_nodes", lds_nodes)
+    frg.frg_tune_set(ctx, "tab_pw", pw)
+    frg.frg_tune_set(ctx, "tab_W", W)
+    quad = frg.make_quad(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a)
+    out = torch.full((len(p) * g.shape[0],), float("nan"), dtype=torch.float64, device="cuda")
+    frg.frg_integrate_tab(ctx, quad, dev(g), s_max, dev(p), out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().reshape(len(p), g.shape[0])
+
+
+def want_of(q, g, s_max, p):
+    return oracle.integrate_tab(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a, g, s_max, p, threads=8)
+
+
+SHAPES = [(3, 0, 48, 12), (4, 1, 33, 5), (3, 0, 128, 32), (4, 0, 64, 16), (3, 1, 1, 1),
+          (3, 0, 17, 40), (4, 0, 200, 3)]
+
+
+@pytest.mark.parametrize("d,reg,n_r,n_a", SHAPES)
+def test_tab_matches_oracle_and_forms_agree(ctx, d, reg, n_r, n_a):
+    print(f"[case] tab d={d} reg={reg} {n_r}x{n_a}", flush=True)
+    q = workloads.Quad(d, reg, 0.9, 5.4, n_r, n_a)
+    rng = np.random.Generator(np.random.PCG64(n_r * 100 + n_a))
+    p = np.concatenate([[0.0, 1e-9], 10 ** rng.uniform(-3, 1.2, 37)])
+    s_max = 40.0   # momenta up to ~16: many s beyond the table (constant tail)
+    g = workloads.tab_rows(7, 1537, s_max)
+    got = run_tab(ctx, q, g, s_max, p)
+    want = want_of(q, g, s_max, p)
+    err = np.abs(got - want) / np.abs(want)
+    print(f"max rel err {err.max():.3e}")
+    assert err.max() < RTOL
+    streamed = run_tab(ctx, q, g, s_max, p, lds_nodes=2, pw=5, W=3)
+    assert np.array_equal(streamed, got)
+
+
+def test_tab_long_rows_sampled(ctx):
+    """Rows of 2^20 nodes (8 MB each, streamed through the caches) at the
+    sizes of the bench workload, checked on a sample of momenta and rows."""
+    w = workloads.tabulated_d3(n_s=1 << 20, n_p=64, n_rows=8)
+    print(f"[case] {w.name}", flush=True)
+    got = run_tab(ctx, w.quad, w.g, w.s_max, w.p)
+    sel = np.arange(0, w.p.size, 7)
+    want = want_of(w.quad, w.g, w.s_max, w.p[sel])
+    err = np.abs(got[sel] - want) / want
+    print(f"max rel err {err.max():.3e}")
+    assert err.max() < RTOL
+
+
+def test_tab_bench_shape_sampled(ctx):
+    """The LDS-row bench workload (1024 momenta x 64 rows of 4096 nodes) on
+    a sample of momenta against the oracle."""
+    w = workloads.tabulated_d3()
+    got = run_tab(ctx, w.quad, w.g, w.s_max, w.p)
+    sel = np.arange(3, w.p.size, 97)
+    want = want_of(w.quad, w.g, w.s_max, w.p[sel])
+    assert np.max(np.abs(got[sel] - want) / want) < RTOL
+    assert np.all(got > 0)
+
+
+def test_tab_host_memory_and_domain(ctx):
+    frg.frg_tune_set(ctx, "tab_lds_nodes", 6144)
+    q = workloads.Quad(3, 0, 1.0, 6.0, 32, 8)
+    quad = frg.make_quad(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a)
+    g = workloads.tab_rows(3, 100, 50.0)
+    p = np.array([0.1, -1.0, 2.0])
+    out = np.zeros(p.size * 3)
+    rc = frg.frg_integrate_tab(ctx, quad, g, 50.0, p, out, mem=frg.FRG_MEM_HOST, allow_domain=True)
+    assert rc == frg.FRG_E_DOMAIN
+    out = out.reshape(3, 3)
+    assert np.all(np.isnan(out[1])) and np.all(np.isfinite(out[[0, 2]]))
+    want = want_of(q, g, 50.0, p[[0, 2]])
+    assert np.max(np.abs(out[[0, 2]] - want) / want) < RTOL
+    dout = torch.zeros(9, dtype=torch.float64, device="cuda")
+    frg.frg_integrate_tab(ctx, quad, dev(g), 50.0, dev(p), dout)
+    torch.cuda.synchronize()
+    assert np.array_equal(dout.cpu().numpy().reshape(3, 3)[[0, 2]], out[[0, 2]])
+
+
+def test_tab_bad_arguments(ctx):
+    q = frg.make_quad(3, 0, 1.0, 6.0, 16, 8)
+    p = np.array([0.5])
+    out = np.zeros(4)
+    for g, s_max in [(np.ones((4, 1)), 1.0), (np.ones((4, 3)), 0.0), (np.ones((4, 3)), np.inf)]:
+        with pytest.raises(frg.FrgError) as ei:
+            frg.frg_integrate_tab(ctx, q, g, s_max, p, out, mem=frg.FRG_MEM_HOST)
+        assert ei.value.code == frg.FRG_E_INVAL
+    q32 = frg.make_quad(3, 0, 1.0, 6.0, 16, 8, frg.FRG_PREC_FP32C)
+    with pytest.raises(frg.FrgError):
+        frg.frg_integrate_tab(ctx, q32, np.ones((4, 3)), 1.0, p, out, mem=frg.FRG_MEM_HOST)
+    # empty problems are no-ops
+    frg.frg_integrate_tab(ctx, q, np.ones((0, 3)), 1.0, p, out, mem=frg.FRG_MEM_HOST)
