@@ -51,9 +51,11 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device-to-device copy of 1 GiB (PMC traffic calibration)")
-    ap.add_argument("--only", choices=["uneven64", "uneven32", "grid32"], default=None,
+    ap.add_argument("--only", choices=["uneven64", "uneven32", "grid32", "tab4096", "tab1m"],
+                    default=None,
                     help="profiling aid: run only --steps persistent launches of the uneven sets "
-                         "(FP64 or FP32C), or --steps FP32C scale-up grid calls, and print "
+                         "(FP64 or FP32C), --steps FP32C scale-up grid calls, or --steps calls "
+                         "of the tabulated variant (rows of 4096 or 2^20 nodes), and print "
                          "their timing")
     return ap.parse_args()
 
@@ -144,6 +146,14 @@ def main():
         sys.exit(2)
     if args.only == "grid32":
         only_grid32(args.steps, args.warmup)
+        return
+    if args.only in ("tab4096", "tab1m"):
+        import torch
+        from paper_2607_24908_amd import frg, workloads
+        ctx = frg.frg_create(0)
+        n_s = 4096 if args.only == "tab4096" else 1 << 20
+        r = tabulated(ctx, frg, workloads, torch, which=(n_s,), reps=args.steps)
+        print(json.dumps({"only": args.only, **r[f"tabulated_{n_s}"]}), flush=True)
         return
     if args.only:
         only_uneven(args.only, args.steps, args.warmup)
@@ -311,8 +321,35 @@ def secondary(ctx, frg, workloads, torch):
                      "max_rel_dev_vs_fp64": rel, "max_err_estimate": err.max().item()}
         log(f"{name}: fp32c {wk.n_evals / t32:.3e} evals/s, fp64 {wk.n_evals / t64:.3e}, "
             f"max dev {rel:.2e}")
+    sec.update(tabulated(ctx, frg, workloads, torch))
     sec["serving"] = serving(frg, workloads)
     return sec
+
+
+def tabulated(ctx, frg, workloads, torch, which=(4096, 1 << 20), reps=None, steps_only=False):
+    """Tabulated-propagator variant: 1024 momenta x 64 rows, rows of 4096 nodes
+    (staged in LDS) and of 2^20 nodes (8 MB rows read through the caches).
+    Each evaluation gathers two neighbouring table values (16 B)."""
+    res = {}
+    for n_s in which:
+        w = workloads.tabulated_d3(n_s=n_s)
+        q = w.quad
+        quad = frg.make_quad(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a)
+        G = torch.as_tensor(w.g, device="cuda")
+        P = torch.as_tensor(w.p, device="cuda")
+        out = torch.empty(w.n_integrals, dtype=torch.float64, device="cuda")
+        t = timed(lambda: frg.frg_integrate_tab(ctx, quad, G, w.s_max, P, out), torch,
+                  reps or (10 if n_s <= 8192 else 5))
+        tb = w.g.nbytes
+        res[f"tabulated_{n_s}"] = {
+            "workload": w.name, "ms_per_call": t * 1e3, "evals_per_s": w.n_evals / t,
+            "integrals_per_s": w.n_integrals / t, "table_bytes": tb,
+            "rows_in_lds": n_s <= 6144, "gathered_bytes_per_eval": 16,
+            "gathered_GB_per_s": 16 * w.n_evals / t / 1e9, "table_GB_per_s_if_read_once": tb / t / 1e9}
+        log(f"tabulated n_s={n_s}: {t * 1e3:.3f} ms, {w.n_evals / t:.3e} evals/s, "
+            f"gathered {16 * w.n_evals / t / 1e9:.0f} GB/s")
+        del G
+    return res
 
 
 def serving(frg, workloads, n_req=100, seed=0):

@@ -162,8 +162,8 @@ typedef struct {
  * p[a] >= 0 (a negative p gives NaN in its row of out and FRG_E_DOMAIN as
  * for frg_integrate).  Rows that fit in LDS beside the quadrature tables (up
  * to 6144 nodes, knob "tab_lds_nodes") are staged there; longer rows are read
- * from HBM through the caches (the workgroups of one row run on one XCD so
- * that its L2 serves them); both give the same bits.  mem says where p,
+ * from HBM through the caches, each XCD working through its rows one at a
+ * time so that the rows in flight stay in cache; both give the same bits.  mem says where p,
  * tab->g and out live; n_p * n_rows results. */
 int frg_integrate_tab(frg_ctx *ctx, const frg_quad *quad, const frg_gtab *tab, int64_t n_p,
                       const double *p, double *out, int32_t mem, void *hip_stream);
@@ -289,7 +289,9 @@ int frg_autotune(frg_ctx *ctx, int32_t mode, const char *cache_path);
  * "grid32_W" (1..8), "grid32_MB" (1..64) of the compensated-FP32 one,
  * "grid_lds_rows" (8..96), "plain_tile", "persist_tile" (1..64),
  * "persist_wpc" (1..64), and of the tabulated variant "tab_W" (1..4),
- * "tab_pw" (momenta per wave, 1..64), "tab_lds_nodes" (2..6144).  Setting a knob drops the
+ * "tab_pw" (momenta per wave, 1..64), "tab_lds_nodes" (2..6144), and for
+ * streamed rows "tab_wpc" (workgroups per CU, 1..16), "tab_sW" (1..4),
+ * "tab_spw" (1..64).  Setting a knob drops the
  * tuned choices so that it takes effect.  Two knobs route FRG_PREC_FP32C
  * points to FP64 and do change results (within the FP32 tolerance):
  * "fp32c_flag_ppb" (error-estimate threshold in units of 1e-9, default 100)

@@ -204,6 +204,9 @@ static int *knob(frg_ctx *ctx, const char *key) {
   if (!std::strcmp(key, "tab_W")) return &t.tab_W;
   if (!std::strcmp(key, "tab_pw")) return &t.tab_pw;
   if (!std::strcmp(key, "tab_lds_nodes")) return &t.tab_lds_nodes;
+  if (!std::strcmp(key, "tab_wpc")) return &t.tab_wpc;
+  if (!std::strcmp(key, "tab_sW")) return &t.tab_sW;
+  if (!std::strcmp(key, "tab_spw")) return &t.tab_spw;
   if (!std::strcmp(key, "plain_tile")) return &t.plain_tile;
   if (!std::strcmp(key, "persist_tile")) return &t.persist.tile;
   if (!std::strcmp(key, "persist_wpc")) return &t.persist.wpc;
@@ -222,6 +225,9 @@ static bool knob_ok(const char *key, int v) {
   if (!std::strcmp(key, "tab_W")) return v >= 1 && v <= 4;
   if (!std::strcmp(key, "tab_pw")) return v >= 1 && v <= 64;
   if (!std::strcmp(key, "tab_lds_nodes")) return v >= 2 && v <= (int)tab_lds_max_nodes;
+  if (!std::strcmp(key, "tab_wpc")) return v >= 1 && v <= 16;
+  if (!std::strcmp(key, "tab_sW")) return v >= 1 && v <= 4;
+  if (!std::strcmp(key, "tab_spw")) return v >= 1 && v <= 64;
   if (!std::strcmp(key, "plain_tile") || !std::strcmp(key, "persist_tile")) return v >= 1 && v <= 64;
   if (!std::strcmp(key, "persist_wpc")) return v >= 1 && v <= 64;
   if (!std::strcmp(key, "fp32c_flag_ppb")) return v >= 0;

@@ -558,13 +558,22 @@ int Ctx::tab_device(const frg_quad &q, const frg_gtab &tb, int64_t n_p, const do
   a.n_r = q.n_radial;
   a.n_a = q.n_angular;
   tab_lane_split(a.n_r, a.n_a, &a.R, &a.J, &a.T, &a.U);
-  const int W = std::max(1, std::min(4, tune.tab_W));
-  a.pw = std::max(1, std::min(64, tune.tab_pw));
-  a.n_pb = (int)((n_p + (int64_t)W * a.pw - 1) / ((int64_t)W * a.pw));
   const bool lds_rows = tb.n_s <= std::min<int64_t>(tune.tab_lds_nodes, tab_lds_max_nodes) &&
                         tab_lds_bytes(a, true) <= 64 * 1024;
+  const int W = std::max(1, std::min(4, lds_rows ? tune.tab_W : tune.tab_sW));
+  a.pw = std::max(1, std::min(64, lds_rows ? tune.tab_pw : tune.tab_spw));
+  // streamed rows: tab_wpc workgroups per CU work through the rows of their
+  // XCD one at a time; momentum blocks are made small enough that every
+  // workgroup of an XCD has a share of each row
+  const int64_t sblocks = (int64_t)n_cu * std::max(1, tune.tab_wpc);
+  if (!lds_rows) {
+    const int64_t slots = std::max<int64_t>(1, sblocks / 8);
+    const int64_t fit = n_p / ((int64_t)W * slots);
+    a.pw = (int)std::max<int64_t>(1, std::min<int64_t>(a.pw, fit));
+  }
+  a.n_pb = (int)((n_p + (int64_t)W * a.pw - 1) / ((int64_t)W * a.pw));
   if (tb.n_rows * a.n_pb > ((int64_t)1 << 31) - 1) return fail(FRG_E_INVAL, "tabulated problem too large");
-  int e = launch_tab(a, q.reg, W, lds_rows, st);
+  int e = launch_tab(a, q.reg, W, lds_rows, sblocks, st);
   if (e) return hip_fail((hipError_t)e, "tab_kernel launch");
   return FRG_OK;
 }

@@ -73,6 +73,9 @@ struct Tune {
   int tab_W = 4;           // tabulated variant: waves per workgroup
   int tab_pw = 16;         // tabulated variant: momenta per wave
   int tab_lds_nodes = 6144;  // tabulated variant: rows up to this many nodes staged in LDS
+  int tab_wpc = 8;         // tabulated variant, streamed rows: workgroups per CU
+  int tab_sW = 2;          // tabulated variant, streamed rows: waves per workgroup
+  int tab_spw = 1;         // tabulated variant, streamed rows: momenta per wave (at most)
   PersistCfg persist;
   int grid_lds_rows = 64;  // (t, u) rows of 64 doubles staged per LDS chunk
   int fp32c_flag_ppb = 100;    // FP32C: FP64 redo above this error estimate (1e-9 units)

@@ -160,7 +160,9 @@ int launch_grid(const GridArgs &g, int reg, int M, int W, void *stream, bool red
 int grid_lds_bytes(const GridArgs &g);
 int launch_fp32c(const SetDev &s, int tile_points, int64_t grid_nm, int *d_flag, void *stream);
 int launch_grid32(const GridArgs &g, int reg, int M, int W, void *stream);
-int launch_tab(const TabArgs &t, int reg, int W, bool lds_rows, void *stream);
+// stream_blocks: workgroups of the streamed-row form (rounded up to a multiple of 8)
+int launch_tab(const TabArgs &t, int reg, int W, bool lds_rows, int64_t stream_blocks,
+               void *stream);
 int tab_lds_bytes(const TabArgs &t, bool lds_rows);
 int grid32_lds_bytes(const GridArgs &g);
 int launch_lpa(const LpaJob *d_jobs, const int64_t *d_start, int n_jobs, int64_t total_points,

@@ -34,48 +34,14 @@ __device__ __forceinline__ double interp(const double *__restrict__ row, double 
   return __builtin_fma(f, g1 - g0, g0);
 }
 
-// Block -> (row, momentum block), such that the blocks the hardware sends to
-// one XCD (b mod 8) are consecutive in (row, block) order.
-__device__ __forceinline__ int64_t xcd_order(int64_t b, int64_t total) {
-  const int64_t x = b & 7, q = total >> 3, rem = total & 7;
-  return x * q + (x < rem ? x : rem) + (b >> 3);
-}
-
-// UR > 0: every lane holds at most UR angular nodes (U <= UR), kept in
-// registers; UR == 0: read from LDS.
-template <bool LDS_ROW, int UR>
-__global__ __launch_bounds__(256) void tab_kernel(TabArgs a) {
-  extern __shared__ double lds[];
-  const int W = blockDim.x / kWave;
-  const int wave = threadIdx.x / kWave;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int64_t total = a.n_rows * a.n_pb;
-  const int64_t ord = LDS_ROW ? (int64_t)blockIdx.x : xcd_order(blockIdx.x, total);
-  const int64_t r = ord / a.n_pb;
-  const int64_t pb = ord - r * a.n_pb;
-  const int n_r = a.n_r, n_a = a.n_a;
+// One (row, momentum block) of work: A_i of the row, then W * pw momenta.
+// lq / lo / lm are staged; `row` is the LDS copy or the row in memory.
+template <int UR>
+__device__ __forceinline__ void tab_block(const TabArgs &a, const double *row, const double *lq,
+                                          const double *lA, const double *lo, const double *lm,
+                                          int64_t r, int64_t pb, int W, int wave, int lane) {
+  const int n_a = a.n_a, n_r = a.n_r;
   const int k_last = (int)a.n_s - 2;
-  double *lq = lds;           // q_i
-  double *lA = lq + n_r;      // c_i G_r(q_i^2)^2
-  double *lo = lA + n_r;      // 1 + x_j
-  double *lm = lo + n_a;      // mu_j
-  double *lg = lm + n_a;      // the row (LDS_ROW)
-  const double *grow = a.g + r * a.n_s;
-  if (LDS_ROW)
-    for (int k = threadIdx.x; k < (int)a.n_s; k += blockDim.x) lg[k] = grow[k];
-  for (int j = threadIdx.x; j < n_a; j += blockDim.x) {
-    lo[j] = a.tab[3 * n_r + j];
-    lm[j] = a.tab[3 * n_r + n_a + j];
-  }
-  __syncthreads();
-  const double *row = LDS_ROW ? lg : grow;
-  for (int i = threadIdx.x; i < n_r; i += blockDim.x) {
-    const double q = a.tab[i];
-    const double G = interp(row, (q * q) * a.inv_h, a.t_last, k_last);
-    lq[i] = q;
-    lA[i] = (a.tab[n_r + i] * G) * G;
-  }
-  __syncthreads();
   const int rho = lane & (a.R - 1);
   const int iota = lane / a.R;
   // this lane's angular nodes j = iota + J u (padded ones get mu = 0)
@@ -132,6 +98,64 @@ __global__ __launch_bounds__(256) void tab_kernel(TabArgs a) {
   if (lane < a.pw && ia < a.n_p) a.out[ia * a.n_rows + r] = res;
 }
 
+// Stage the row-dependent factors A_i = c_i G_r(q_i^2)^2 (and q_i).
+__device__ __forceinline__ void tab_stage_A(const TabArgs &a, const double *row, double *lq,
+                                            double *lA) {
+  for (int i = threadIdx.x; i < a.n_r; i += blockDim.x) {
+    const double q = a.tab[i];
+    const double G = interp(row, (q * q) * a.inv_h, a.t_last, (int)a.n_s - 2);
+    lq[i] = q;
+    lA[i] = (a.tab[a.n_r + i] * G) * G;
+  }
+}
+
+// LDS_ROW: one workgroup per (row, momentum block), the row staged in LDS.
+// Otherwise a fixed grid of 8 * slots workgroups: workgroup b runs on XCD
+// b mod 8 (round-robin dispatch) and works through the rows of that XCD one
+// after another, taking momentum blocks slot, slot + slots, ... of each, so
+// that each XCD streams one row at a time through its L2 and the rows in
+// flight on the chip stay within the memory-side cache.
+// UR > 0: every lane holds at most UR angular nodes (U <= UR), kept in
+// registers; UR == 0: read from LDS.
+template <bool LDS_ROW, int UR>
+__global__ __launch_bounds__(256) void tab_kernel(TabArgs a) {
+  extern __shared__ double lds[];
+  const int W = blockDim.x / kWave;
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int n_r = a.n_r, n_a = a.n_a;
+  double *lq = lds;           // q_i
+  double *lA = lq + n_r;      // c_i G_r(q_i^2)^2
+  double *lo = lA + n_r;      // 1 + x_j
+  double *lm = lo + n_a;      // mu_j
+  double *lg = lm + n_a;      // the row (LDS_ROW)
+  for (int j = threadIdx.x; j < n_a; j += blockDim.x) {
+    lo[j] = a.tab[3 * n_r + j];
+    lm[j] = a.tab[3 * n_r + n_a + j];
+  }
+  if constexpr (LDS_ROW) {
+    const int64_t r = blockIdx.x / a.n_pb;
+    const int64_t pb = blockIdx.x - r * a.n_pb;
+    const double *grow = a.g + r * a.n_s;
+    for (int k = threadIdx.x; k < (int)a.n_s; k += blockDim.x) lg[k] = grow[k];
+    __syncthreads();
+    tab_stage_A(a, lg, lq, lA);
+    __syncthreads();
+    tab_block<UR>(a, lg, lq, lA, lo, lm, r, pb, W, wave, lane);
+  } else {
+    const int x = blockIdx.x & 7;
+    const int64_t slot = blockIdx.x >> 3, slots = gridDim.x >> 3;
+    for (int64_t r = x; r < a.n_rows; r += 8) {
+      const double *grow = a.g + r * a.n_s;
+      __syncthreads();  // the previous row's A_i are no longer read
+      tab_stage_A(a, grow, lq, lA);
+      __syncthreads();
+      for (int64_t pb = slot; pb < a.n_pb; pb += slots)
+        tab_block<UR>(a, grow, lq, lA, lo, lm, r, pb, W, wave, lane);
+    }
+  }
+}
+
 }  // namespace
 
 void tab_lane_split(int n_r, int n_a, int *R, int *J, int *T, int *U) {
@@ -148,21 +172,24 @@ int tab_lds_bytes(const TabArgs &t, bool lds_rows) {
 }
 
 template <bool L, int UR>
-static void tab_launch_t(const TabArgs &t, int W, hipStream_t st) {
-  const int64_t blocks = t.n_rows * t.n_pb;
+static void tab_launch_t(const TabArgs &t, int W, int64_t blocks, hipStream_t st) {
   hipLaunchKernelGGL((tab_kernel<L, UR>), dim3((unsigned)blocks), dim3(kWave * W),
                      tab_lds_bytes(t, L), st, t);
 }
 
-int launch_tab(const TabArgs &t, int reg, int W, bool lds_rows, void *stream) {
+int launch_tab(const TabArgs &t, int reg, int W, bool lds_rows, int64_t stream_blocks,
+               void *stream) {
   (void)reg;  // the regulator enters through the quadrature table only
   if (t.n_p <= 0 || t.n_rows <= 0) return 0;
   hipStream_t st = (hipStream_t)stream;
   const bool regs = t.U <= 4;
-  if (lds_rows)
-    regs ? tab_launch_t<true, 4>(t, W, st) : tab_launch_t<true, 0>(t, W, st);
-  else
-    regs ? tab_launch_t<false, 4>(t, W, st) : tab_launch_t<false, 0>(t, W, st);
+  if (lds_rows) {
+    const int64_t blocks = t.n_rows * t.n_pb;
+    regs ? tab_launch_t<true, 4>(t, W, blocks, st) : tab_launch_t<true, 0>(t, W, blocks, st);
+  } else {
+    const int64_t blocks = 8 * ((stream_blocks + 7) / 8);
+    regs ? tab_launch_t<false, 4>(t, W, blocks, st) : tab_launch_t<false, 0>(t, W, blocks, st);
+  }
   return (int)hipGetLastError();
 }
 

@@ -34,6 +34,8 @@ def run_tab(ctx, q, g, s_max, p, lds_nodes=6144, pw=16, W=4):
     frg.frg_tune_set(ctx, "tab_lds_nodes", lds_nodes)
     frg.frg_tune_set(ctx, "tab_pw", pw)
     frg.frg_tune_set(ctx, "tab_W", W)
+    frg.frg_tune_set(ctx, "tab_spw", pw)
+    frg.frg_tune_set(ctx, "tab_sW", W)
     quad = frg.make_quad(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a)
     out = torch.full((len(p) * g.shape[0],), float("nan"), dtype=torch.float64, device="cuda")
     frg.frg_integrate_tab(ctx, quad, dev(g), s_max, dev(p), out)
