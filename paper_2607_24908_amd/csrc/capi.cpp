@@ -514,13 +514,16 @@ int Ctx::grid_device(const frg_quad &q, int64_t n_p, const double *p, int64_t n_
   g.n_a = q.n_angular;
   lane_split(g.n_r, g.n_a, &g.R, &g.J, &g.T, &g.U);
   g.chunk = std::max(8, tune.grid_lds_rows);
+  g.form = tune.grid_form;
   if (grid_lds_bytes(g) > 64 * 1024) return fail(FRG_E_INVAL, "grid tables exceed 64 KiB of LDS");
   const GridCfg cfg = grid_cfg(q, g, st);
   return grid_launch(g, q.reg, cfg, st);
 }
 
-int Ctx::grid_launch(GridArgs g, int reg, const GridCfg &cfg, hipStream_t st, int kind) {
-  const bool resident = g.T * g.U <= g.chunk;
+int Ctx::grid_launch(GridArgs g, int reg, const GridCfg &cfg_in, hipStream_t st, int kind) {
+  const bool resident = kind == 1 ? true : grid_resident(g);
+  GridCfg cfg = cfg_in;
+  if ((kind == 1 || grid_uses_coef(g)) && cfg.M > 8) cfg.M = 8;  // at most 8 masses per wave there
   const int64_t per_wg_min = (int64_t)cfg.M * cfg.W;
   // mass blocks per wave: fewer workgroups per momentum, but keep at least
   // ~4 workgroups per CU in flight
@@ -631,8 +634,9 @@ int Ctx::grid_fp32c(const frg_quad &q, int64_t n_p, const double *p, int64_t n_m
   g.n_a = q.n_angular;
   lane_split(g.n_r, g.n_a, &g.R, &g.J, &g.T, &g.U);
   g.chunk = g.T * g.U;
+  g.form = tune.grid_form;
   if (q.reg == FRG_REG_EXP && g.T * g.U <= std::max(8, tune.grid_lds_rows) &&
-      grid32_lds_bytes(g) <= 64 * 1024) {
+      grid32_lds_bytes(g) <= 64 * 1024 && grid_resident(g)) {
     Grid32Table t32;
     rc = grid32_table(q, g.J, &g.tab32, &t32);
     if (rc) return rc;

@@ -228,3 +228,254 @@ __device__ __forceinline__ void grid_fill(const GridArgs &g, double *lH, int c0,
 
 }  // namespace dev
 }  // namespace frg
+
+namespace frg {
+namespace dev {
+
+// ------------------------------------------------ coefficient form --
+// Resident tables of the FP64 grid kernel.  For a group of G angular terms
+// of one lane (one radial node i; u = gi G .. gi G + G - 1), with
+// H_k = Hk(s_ik) and weights mu_k,
+//   sum_k mu_k / (delta + H_k) = N(delta) / P(delta),
+//   P(delta) = prod_k (delta + H_k) = delta^G + sum_{m<G} c_m delta^m,
+//   N(delta) = sum_k mu_k prod_{l != k} (delta + H_l) = sum_{m<G} d_m delta^m.
+// The coefficients depend on the momentum only, so the workgroup builds them
+// once (G^2 FMAs per group) and every mass evaluates two Horner chains
+// (2G - 1 FMAs and one add) and one reciprocal per G terms.  Every H_k >= 0
+// and mu_k > 0, so all coefficients are positive and both the expansion and
+// the Horner sums add positive terms only (relative error O(G u)).
+//
+// Layout (lane-major, like the H' table): group (t, gi) occupies rows
+// (t NG + gi) 2G + m, m < G holding c_m and m >= G holding d_{m-G}; the
+// remaining angular terms of a row (u >= Gfull) hold H in rows
+// T NG 2G + t UT + (u - Gfull).
+template <int G>
+struct CoefShape {
+  int Gfull, NG, UT, rows;
+  __host__ __device__ CoefShape(int n_a, int J, int T, int U) {
+    const int umin = n_a / J;
+    Gfull = umin - umin % G;
+    NG = Gfull / G;
+    UT = U - Gfull;
+    rows = T * (2 * Gfull + UT);
+  }
+};
+
+// Ranges where no coefficient, Horner partial sum or P over- or underflows:
+// per momentum (q_max + p)^2 <= kCoefHi (bounds every H), per mass
+// kCoefLo <= delta <= kCoefHi.
+template <int G>
+struct CoefRange;
+template <>
+struct CoefRange<8> {
+  static constexpr double lo = 1e-36, hi = 1e36;
+};
+template <>
+struct CoefRange<16> {
+  static constexpr double lo = 1e-18, hi = 5e17;
+};
+
+template <int G>
+__device__ __forceinline__ bool coef_p_ok(double p, double q_top) {
+  const double qp = q_top + p;
+  return qp * qp <= CoefRange<G>::hi;
+}
+
+template <int G>
+__device__ __forceinline__ bool coef_m_ok(double delta) {
+  return delta >= CoefRange<G>::lo && delta <= CoefRange<G>::hi;
+}
+
+// Build the coefficient table of momentum p (all threads of the workgroup).
+template <int REG, int G>
+__device__ void grid_fill_coef(const GridArgs &g, double *lC, double p, const CoefShape<G> &cs) {
+  const double *tq = g.tab;
+  const double *to = g.tab + 3 * g.n_r;
+  const double *tm = to + g.n_a;
+  const int n_group = kWave * g.T * cs.NG;
+  const int n_tail = kWave * g.T * cs.UT;
+  for (int task = threadIdx.x; task < n_group + n_tail; task += blockDim.x) {
+    const int l = task & (kWave - 1);
+    const int rho = l & (g.R - 1), iota = l / g.R;
+    if (task < n_group) {
+      const int rest = task / kWave;
+      const int t = rest / cs.NG, gi = rest - t * cs.NG;
+      const int i = rho + g.R * t;
+      const double q = i < g.n_r ? tq[i] : 0.0;  // padded radial lanes: any finite value
+      const double qm = q - p;
+      const double a = qm * qm;
+      const double b = (2.0 * q) * p;
+      double P[G + 1], N[G];
+#pragma unroll
+      for (int m = 0; m <= G; ++m) P[m] = m == 0 ? 1.0 : 0.0;
+#pragma unroll
+      for (int m = 0; m < G; ++m) N[m] = 0.0;
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        const int j = iota + g.J * (gi * G + k);
+        const double H = hk<REG>(__builtin_fma(b, to[j], a), g.k2, g.inv_k2);
+        const double mu = tm[j];
+        // N <- N (delta + H) + mu P, then P <- P (delta + H), on the old P.
+        // Before term k, P has degree k with P[k] = 1 and N degree k - 1;
+        // only those entries are touched (k is a compile-time index here).
+        if (k == 0) {
+          N[0] = mu;
+          P[1] = 1.0;
+          P[0] = H;
+        } else {
+          N[k] = __builtin_fma(mu, P[k], N[k - 1]);
+#pragma unroll
+          for (int m = G - 1; m >= 1; --m)
+            if (m < k) N[m] = __builtin_fma(mu, P[m], __builtin_fma(H, N[m], N[m - 1]));
+          N[0] = __builtin_fma(mu, P[0], H * N[0]);
+          P[k + 1 <= G ? k + 1 : G] = 1.0;
+#pragma unroll
+          for (int m = G; m >= 1; --m)
+            if (m <= k) P[m] = __builtin_fma(H, P[m], P[m - 1]);
+          P[0] = H * P[0];
+        }
+      }
+      double *dst = lC + ((t * cs.NG + gi) * 2 * G) * kWave + l;
+#pragma unroll
+      for (int m = 0; m < G; ++m) {
+        dst[m * kWave] = P[m];
+        dst[(G + m) * kWave] = N[m];
+      }
+    } else {
+      const int rest = (task - n_group) / kWave;
+      const int t = rest / cs.UT, ut = rest - t * cs.UT;
+      const int i = rho + g.R * t;
+      const int j = iota + g.J * (cs.Gfull + ut);
+      double H = 1.0;
+      if (j < g.n_a) {
+        const double q = i < g.n_r ? tq[i] : 0.0;
+        const double qm = q - p;
+        H = hk<REG>(__builtin_fma((2.0 * q) * p, to[j], qm * qm), g.k2, g.inv_k2);
+      }
+      lC[(g.T * cs.NG * 2 * G + t * cs.UT + ut) * kWave + l] = H;
+    }
+  }
+}
+
+// Accumulate, for the masses set in `active`, the lane partials of the
+// coefficient form into tot[m].  ALL: every mass active.
+template <int M, int G, bool ALL>
+__device__ __forceinline__ void grid_coef_rows(const GridArgs &g, const double *lC,
+                                               const double *lc, const double *lq,
+                                               const double *lm, int lane, const double *dm,
+                                               unsigned active, const CoefShape<G> &cs,
+                                               double *tot) {
+  const int rho = lane & (g.R - 1);
+  const int iota = lane / g.R;
+  for (int t = 0; t < g.T; ++t) {
+    const int i = rho + g.R * t;
+    const bool vi = i < g.n_r;
+    const double c = vi ? lc[i] : 0.0;
+    const double Hq = vi ? lq[i] : 1.0;
+    double A[M], in[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      if (!ALL && !((active >> m) & 1u)) continue;
+      const double Gq = rcp64(Hq + dm[m]);
+      A[m] = (c * Gq) * Gq;
+      in[m] = 0.0;
+    }
+    for (int gi = 0; gi < cs.NG; ++gi) {
+      const double *src = lC + ((t * cs.NG + gi) * 2 * G) * kWave + lane;
+      double cc[G], dd[G];
+#pragma unroll
+      for (int m = 0; m < G; ++m) {
+        cc[m] = src[m * kWave];
+        dd[m] = src[(G + m) * kWave];
+      }
+      if constexpr (ALL) {
+        // masses in pairs: four independent Horner chains in flight
+#pragma unroll
+        for (int m = 0; m < M; m += 2) {
+          const double xa = dm[m], xb = dm[m + 1];
+          double Pa = xa + cc[G - 1], Pb = xb + cc[G - 1];
+          double Na = dd[G - 1], Nb = dd[G - 1];
+#pragma unroll
+          for (int k = G - 2; k >= 0; --k) {
+            Pa = __builtin_fma(Pa, xa, cc[k]);
+            Pb = __builtin_fma(Pb, xb, cc[k]);
+            Na = __builtin_fma(Na, xa, dd[k]);
+            Nb = __builtin_fma(Nb, xb, dd[k]);
+            __builtin_amdgcn_sched_barrier(0);
+          }
+          in[m] = __builtin_fma(Na, rcp64(Pa), in[m]);
+          in[m + 1] = __builtin_fma(Nb, rcp64(Pb), in[m + 1]);
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+          if (!((active >> m) & 1u)) continue;
+          const double x = dm[m];
+          double P = x + cc[G - 1], N = dd[G - 1];
+#pragma unroll
+          for (int k = G - 2; k >= 0; --k) {
+            P = __builtin_fma(P, x, cc[k]);
+            N = __builtin_fma(N, x, dd[k]);
+          }
+          in[m] = __builtin_fma(N, rcp64(P), in[m]);
+        }
+      }
+    }
+    for (int ut = 0; ut < cs.UT; ++ut) {
+      const int j = iota + g.J * (cs.Gfull + ut);
+      if (j < g.n_a) {
+        const double mu = lm[j];
+        const double H = lC[(g.T * cs.NG * 2 * G + t * cs.UT + ut) * kWave + lane];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+          if (!ALL && !((active >> m) & 1u)) continue;
+          in[m] = __builtin_fma(mu, rcp64(H + dm[m]), in[m]);
+        }
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      if (!ALL && !((active >> m) & 1u)) continue;
+      tot[m] = __builtin_fma(A[m], in[m], tot[m]);
+    }
+  }
+}
+
+// Lane partial of one mass outside the coefficient range: every term on its
+// own, the regulator evaluated again per term (rare: extreme masses or
+// momenta).
+template <int REG>
+__device__ __forceinline__ double grid_single_mass(const GridArgs &g, const double *lc,
+                                                const double *lq, const double *lm, int lane,
+                                                double p, double delta) {
+  const int rho = lane & (g.R - 1);
+  const int iota = lane / g.R;
+  const double *tq = g.tab;
+  const double *to = g.tab + 3 * g.n_r;
+  double total = 0.0;
+  for (int t = 0; t < g.T; ++t) {
+    const int i = rho + g.R * t;
+    const bool vi = i < g.n_r;
+    const double q = vi ? tq[i] : 0.0;
+    const double c = vi ? lc[i] : 0.0;
+    const double Hq = vi ? lq[i] : 1.0;
+    const double Gq = rcp64(Hq + delta);
+    const double A = (c * Gq) * Gq;
+    const double qm = q - p;
+    const double a = qm * qm;
+    const double b = (2.0 * q) * p;
+    double inner = 0.0;
+    for (int u = 0; u < g.U; ++u) {
+      const int j = iota + g.J * u;
+      if (j < g.n_a) {
+        const double H = hk<REG>(__builtin_fma(b, to[j], a), g.k2, g.inv_k2);
+        inner = __builtin_fma(lm[j], rcp64(H + delta), inner);
+      }
+    }
+    total = __builtin_fma(A, inner, total);
+  }
+  return total;
+}
+
+}  // namespace dev
+}  // namespace frg

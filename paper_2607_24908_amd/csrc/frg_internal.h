@@ -89,7 +89,7 @@ struct GridArgs {
   int32_t n_mb;     // workgroups per momentum
   int32_t chunk;    // (t, u) rows of the Hk table held in LDS at once
   int32_t mblocks;  // mass blocks per wave when the table is resident
-  int32_t pad;
+  int32_t form;     // resident FP64 form: 0 coefficients (when they fit), 1 running fractions
   // compensated-FP32 grid only (Grid32Table on the device, see below)
   const double *tab32;
   double f32_band, f32_flag;  // FP64 below dhat = f32_band; re-done in FP64 above err f32_flag
@@ -158,6 +158,13 @@ int launch_points_persistent(const SetDev *d_sets, const Tile *d_tiles, int n_ti
 int launch_reset_counter(int *d_counter, void *stream);
 int launch_grid(const GridArgs &g, int reg, int M, int W, void *stream, bool redo = false);
 int grid_lds_bytes(const GridArgs &g);
+// Resident coefficient form of the FP64 grid kernel: used when its table fits.
+constexpr int kGridCoefLdsMax = 150 * 1024;
+int grid_coef_group(const GridArgs &g);
+int grid_coef_lds_bytes(const GridArgs &g);
+// Whether the FP64 grid kernel keeps its table resident, and in which form.
+bool grid_uses_coef(const GridArgs &g);
+bool grid_resident(const GridArgs &g);
 int launch_fp32c(const SetDev &s, int tile_points, int64_t grid_nm, int *d_flag, void *stream);
 int launch_grid32(const GridArgs &g, int reg, int M, int W, void *stream);
 // stream_blocks: workgroups of the streamed-row form (rounded up to a multiple of 8)

@@ -228,6 +228,102 @@ __global__ __launch_bounds__(512) void grid_kernel(GridArgs g) {
   }
 }
 
+// Tensor grid, resident coefficient form (device_grid.h): a workgroup owns
+// one momentum and W * M * MB masses; it builds the per-group coefficients of
+// its momentum once in LDS and every mass evaluates them by Horner.  REDO:
+// only the masses with used64 == 1 (left for FP64 by the compensated-FP32
+// grid kernel) are computed; a workgroup with none of them returns before
+// building its table.
+template <int REG, int M, int G, bool REDO>
+__global__ __launch_bounds__(512) void grid_coef_kernel(GridArgs g) {
+  extern __shared__ double lds[];
+  const int W = blockDim.x / kWave;
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t a = blockIdx.x / g.n_mb;
+  const int mb = (int)(blockIdx.x - a * g.n_mb);
+  const double p = g.p[a];
+  const int n_r = g.n_r, n_a = g.n_a;
+  const int MB = g.mblocks;
+  if constexpr (REDO) {
+    const int64_t first = (int64_t)mb * MB * W * M;
+    bool any = false;
+    for (int idx = threadIdx.x; idx < MB * W * M; idx += blockDim.x)
+      any |= first + idx < g.n_m && g.used64[a * g.n_m + first + idx] == 1;
+    if (!__syncthreads_or(any)) return;  // workgroup-uniform
+  }
+  const CoefShape<G> cs(n_a, g.J, g.T, g.U);
+  double *lC = lds;
+  double *lc = lC + cs.rows * kWave;
+  double *lq = lc + n_r;
+  double *lm = lq + n_r;
+  for (int idx = threadIdx.x; idx < n_r; idx += blockDim.x) {
+    lc[idx] = g.tab[n_r + idx];
+    lq[idx] = g.tab[2 * n_r + idx];
+  }
+  for (int idx = threadIdx.x; idx < n_a; idx += blockDim.x) lm[idx] = g.tab[3 * n_r + n_a + idx];
+  const bool p_ok = p >= 0.0;
+  const bool table = p_ok && coef_p_ok<G>(p, g.q_top);  // workgroup-uniform
+  if (table) grid_fill_coef<REG, G>(g, lC, p, cs);
+  __syncthreads();
+  const unsigned all = (M == 32) ? ~0u : ((1u << M) - 1u);
+  for (int rep = 0; rep < MB; ++rep) {
+    const int64_t m0 = (((int64_t)mb * MB + rep) * W + wave) * M;
+    if (m0 >= g.n_m) break;  // wave-uniform
+    double dm[M];
+    unsigned okbits = 0, cmask = 0, act = all;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int64_t idx = m0 + m;
+      const bool valid = idx < g.n_m;
+      const double d = valid ? g.m2[idx] + g.k2 : 1.0;
+      const bool ok = valid && p_ok && d > 0.0;
+      dm[m] = ok ? d : 1.0;
+      okbits |= ok ? (1u << m) : 0u;
+      cmask |= (table && coef_m_ok<G>(dm[m])) ? (1u << m) : 0u;
+      if (REDO && !(valid && g.used64[a * g.n_m + idx] == 1)) act &= ~(1u << m);
+    }
+    // the masses are the same in every lane: make the choices wave-uniform
+    okbits = __builtin_amdgcn_readfirstlane(okbits);
+    cmask = __builtin_amdgcn_readfirstlane(cmask);
+    act = __builtin_amdgcn_readfirstlane(act);
+    if (REDO && !act) continue;
+    double tot[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) tot[m] = 0.0;
+    const unsigned cm = act & cmask;
+    if (cm == all)
+      grid_coef_rows<M, G, true>(g, lC, lc, lq, lm, lane, dm, cm, cs, tot);
+    else if (cm)
+      grid_coef_rows<M, G, false>(g, lC, lc, lq, lm, lane, dm, cm, cs, tot);
+    const unsigned sm = act & ~cmask;
+    if (sm) {
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+        if ((sm >> m) & 1u) tot[m] = grid_single_mass<REG>(g, lc, lq, lm, lane, p, dm[m]);
+    }
+    // lane l ends with the total of mass l / (64 / M)
+    const double v = g.pref * wave_sum_split<M>(tot, lane);
+    const int mine = lane / (kWave / M);
+    const bool okm = (okbits >> mine) & 1u;
+    if (REDO) {
+      // the FP32 kernel has already written the other points and the flag
+      if (lane % (kWave / M) == 0 && ((act >> mine) & 1u)) {
+        const int64_t o = a * g.n_m + m0 + mine;
+        g.out[o] = okm ? v : __builtin_nan("");
+        if (g.err) g.err[o] = kErr64;
+      }
+      continue;
+    }
+    bool bad = false;
+#pragma unroll
+    for (int m = 0; m < M; ++m) bad |= (m0 + m < g.n_m) && !((okbits >> m) & 1u);
+    if (bad && lane == 0) *g.flag = 1;
+    if (lane % (kWave / M) == 0 && m0 + mine < g.n_m)
+      g.out[a * g.n_m + m0 + mine] = okm ? v : __builtin_nan("");
+  }
+}
+
 // Coefficient of U[j+o] in U' (c1) and U'' (c2) of the difference formulas.
 __device__ __forceinline__ void fd_coef(int64_t j, int64_t n, int o, double i2, double i1,
                                         double *c1, double *c2) {
@@ -366,36 +462,98 @@ int grid_lds_bytes(const GridArgs &g) {
   return (int)sizeof(double) * (C * kWave + 2 * g.n_r + g.n_a);
 }
 
-template <int REG, int M>
-static void grid_launch_t(const GridArgs &g, int W, bool redo, hipStream_t st) {
+int grid_coef_group(const GridArgs &g) {
+  const int umin = g.n_a / g.J;
+  return umin >= 16 ? 16 : 8;
+}
+
+int grid_coef_lds_bytes(const GridArgs &g) {
+  const int G = grid_coef_group(g);
+  const int rows = G == 16 ? CoefShape<16>(g.n_a, g.J, g.T, g.U).rows
+                           : CoefShape<8>(g.n_a, g.J, g.T, g.U).rows;
+  return (int)sizeof(double) * (rows * kWave + 2 * g.n_r + g.n_a);
+}
+
+// Ask for dynamic LDS beyond 64 KiB for one kernel (gfx950: 160 KiB per
+// workgroup).  The runtime may refuse the request where no opt-in is needed;
+// that status is cleared so that it cannot be taken for a launch error.
+static void allow_large_lds(const void *fn) {
+  (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  (void)hipGetLastError();
+}
+
+template <int REG, int M, int G>
+static void coef_launch_t(const GridArgs &g, int W, bool redo, hipStream_t st) {
+  static const bool once = (allow_large_lds((const void *)&grid_coef_kernel<REG, M, G, false>),
+                            allow_large_lds((const void *)&grid_coef_kernel<REG, M, G, true>), true);
+  (void)once;
   const int64_t blocks = g.n_p * g.n_mb;
-  if (redo)  // resident tables only (host-checked)
-    hipLaunchKernelGGL((grid_kernel<REG, M, true, true>), dim3((unsigned)blocks), dim3(kWave * W),
-                       grid_lds_bytes(g), st, g);
-  else if (g.T * g.U <= g.chunk)
-    hipLaunchKernelGGL((grid_kernel<REG, M, true, false>), dim3((unsigned)blocks),
-                       dim3(kWave * W), grid_lds_bytes(g), st, g);
+  const int lds = grid_coef_lds_bytes(g);
+  if (redo)
+    hipLaunchKernelGGL((grid_coef_kernel<REG, M, G, true>), dim3((unsigned)blocks),
+                       dim3(kWave * W), lds, st, g);
   else
-    hipLaunchKernelGGL((grid_kernel<REG, M, false, false>), dim3((unsigned)blocks),
-                       dim3(kWave * W), grid_lds_bytes(g), st, g);
+    hipLaunchKernelGGL((grid_coef_kernel<REG, M, G, false>), dim3((unsigned)blocks),
+                       dim3(kWave * W), lds, st, g);
+}
+
+// Returns false when the shape has no kernel (the host passes M <= 8 for the
+// resident coefficient form and never asks a redo pass of streamed tables).
+bool grid_uses_coef(const GridArgs &g) {
+  return g.form == 0 && grid_coef_lds_bytes(g) <= kGridCoefLdsMax;
+}
+
+bool grid_resident(const GridArgs &g) { return grid_uses_coef(g) || g.T * g.U <= g.chunk; }
+
+template <int REG, int M>
+static bool grid_launch_t(const GridArgs &g, int W, bool redo, hipStream_t st) {
+  if (grid_uses_coef(g)) {
+    if constexpr (M > 8) {
+      return false;
+    } else {
+      if (grid_coef_group(g) == 16)
+        coef_launch_t<REG, M, 16>(g, W, redo, st);
+      else
+        coef_launch_t<REG, M, 8>(g, W, redo, st);
+      return true;
+    }
+  }
+  const int64_t blocks = g.n_p * g.n_mb;
+  if (g.T * g.U <= g.chunk) {
+    // resident table, running-fraction form
+    if (redo)
+      hipLaunchKernelGGL((grid_kernel<REG, M, true, true>), dim3((unsigned)blocks),
+                         dim3(kWave * W), grid_lds_bytes(g), st, g);
+    else
+      hipLaunchKernelGGL((grid_kernel<REG, M, true, false>), dim3((unsigned)blocks),
+                         dim3(kWave * W), grid_lds_bytes(g), st, g);
+    return true;
+  }
+  if (redo) return false;
+  // tables too large for LDS: streamed in chunks (running-fraction form)
+  hipLaunchKernelGGL((grid_kernel<REG, M, false, false>), dim3((unsigned)blocks), dim3(kWave * W),
+                     grid_lds_bytes(g), st, g);
+  return true;
 }
 
 int launch_grid(const GridArgs &g, int reg, int M, int W, void *stream, bool redo) {
   if (g.n_p <= 0 || g.n_m <= 0) return 0;
   hipStream_t st = (hipStream_t)stream;
+  bool ok;
   if (reg == kExp) {
     switch (M) {
-      case 4: grid_launch_t<kExp, 4>(g, W, redo, st); break;
-      case 8: grid_launch_t<kExp, 8>(g, W, redo, st); break;
-      default: grid_launch_t<kExp, 16>(g, W, redo, st); break;
+      case 4: ok = grid_launch_t<kExp, 4>(g, W, redo, st); break;
+      case 8: ok = grid_launch_t<kExp, 8>(g, W, redo, st); break;
+      default: ok = grid_launch_t<kExp, 16>(g, W, redo, st); break;
     }
   } else {
     switch (M) {
-      case 4: grid_launch_t<kLitim, 4>(g, W, redo, st); break;
-      case 8: grid_launch_t<kLitim, 8>(g, W, redo, st); break;
-      default: grid_launch_t<kLitim, 16>(g, W, redo, st); break;
+      case 4: ok = grid_launch_t<kLitim, 4>(g, W, redo, st); break;
+      case 8: ok = grid_launch_t<kLitim, 8>(g, W, redo, st); break;
+      default: ok = grid_launch_t<kLitim, 16>(g, W, redo, st); break;
     }
   }
+  if (!ok) return (int)hipErrorInvalidValue;
   return (int)hipGetLastError();
 }
 

@@ -87,7 +87,8 @@ def test_points_and_grid_fp32c_agree(ctx):
     """The tensor-grid FP32C kernel (shared per-momentum table, grouped FP32
     running fractions) and the point-list FP32C kernel (per-term FP32 with
     two-sum) are different FP32 algorithms: both stay within the bar of the
-    oracle, and where both fall back to FP64 they return the same bits."""
+    oracle, and where both fall back to FP64 (grid kernel and point kernel)
+    they agree to a few ulp."""
     w = workloads.precision_d4(1)
     q = w.quad
     g, ge, gu = grid(ctx, q, w.p, w.m2, frg.FRG_PREC_FP32C)
@@ -106,7 +107,7 @@ def test_points_and_grid_fp32c_agree(ctx):
     assert np.max(np.abs(g - want) / want) < TOL32
     both = (pu == 1) & (gu == 1)
     assert both.any()
-    assert np.array_equal(pt[both], g[both])
+    assert np.all(np.abs(pt[both] - g[both]) <= 1e-13 * np.abs(g[both]))
 
 
 @pytest.mark.parametrize("d,reg,n_r,n_a", [(3, frg.FRG_REG_EXP, 128, 32), (3, frg.FRG_REG_LITIM, 64, 16),
