@@ -28,25 +28,26 @@ sys.path.insert(0, ROOT)
 
 # ALU roofline of the FP64 path.  Issue rate of the FP64 VALU of MI355X:
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 lane-cycles/s.  Floor of
-# the per-evaluation work of the reciprocal sum sum_j 1/D'_j (mu_j folded
-# into D'_j = delta rmu_j + H'_j): 3 FP64 VALU operations per term (the FMA
-# forming D', the FMA N <- N D' + P and the product P <- P D' of the running
-# fraction), the quarter-rate reciprocal and its Newton step being shared by
-# a group of eight terms and left out of the floor.
+# the per-evaluation work of the grid kernel: for a group of G angular terms
+# sum_k mu_k/(delta + H_k) = N(delta)/P(delta) with per-momentum polynomial
+# coefficients, so each (term, mass) costs one Horner FMA of P and one of N;
+# the reciprocal of P, its Newton step and the accumulation are shared by
+# the G = 16 terms of a group and the coefficient build by every mass of
+# the momentum, and are left out of the floor: 2 FP64 operations per eval.
 VALU_LANE_CYCLES = 256 * 4 * 16 * 2.4e9
-# HBM bytes per grid_kernel launch from rocprofv3 FETCH_SIZE / WRITE_SIZE,
+# HBM bytes per grid-kernel launch from rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # scaled by a 1 GiB device copy read the same way (fetch x2.00, write x1.00):
-# 360 KiB x 2.00 + 16384 KiB x 1.00.
-TRAFFIC = 360 * 1024 * 2.00 + 16384 * 1024 * 1.00
-CYCLES_PER_EVAL_FLOOR = 3
+# 456 KiB x 2.00 + 16384 KiB x 1.00.
+TRAFFIC = 456 * 1024 * 2.00 + 16384 * 1024 * 1.00
+CYCLES_PER_EVAL_FLOOR = 2
 PEAK_EVALS = VALU_LANE_CYCLES / CYCLES_PER_EVAL_FLOOR
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -212,9 +213,9 @@ def main():
         "integrals_per_s": w.n_integrals / (ms_step * 1e-3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_EVALS / 1e9,
                      "unit": "Geval/s", "frac": achieved * 1e9 / PEAK_EVALS, "traffic": TRAFFIC,
-                     "kernel": "grid_kernel<exp>", "kernel_ms": gpu_ms,
+                     "kernel": "grid_coef_kernel<exp>", "kernel_ms": gpu_ms,
                      "evals_per_launch": int(w.n_evals), "traffic_unit": "bytes per launch",
-                     "peak_basis": "FP64 VALU 3.93e13 lane-cycles/s / 3 cycles per eval"},
+                     "peak_basis": "FP64 VALU 3.93e13 lane-cycles/s / 2 cycles per eval"},
     }
     if not args.no_secondary:
         line["secondary"] = secondary(ctx, frg, workloads, torch)

@@ -370,16 +370,9 @@ __device__ __forceinline__ void grid_coef_rows(const GridArgs &g, const double *
   for (int t = 0; t < g.T; ++t) {
     const int i = rho + g.R * t;
     const bool vi = i < g.n_r;
-    const double c = vi ? lc[i] : 0.0;
-    const double Hq = vi ? lq[i] : 1.0;
-    double A[M], in[M];
+    double in[M];
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-      if (!ALL && !((active >> m) & 1u)) continue;
-      const double Gq = rcp64(Hq + dm[m]);
-      A[m] = (c * Gq) * Gq;
-      in[m] = 0.0;
-    }
+    for (int m = 0; m < M; ++m) in[m] = 0.0;
     for (int gi = 0; gi < cs.NG; ++gi) {
       const double *src = lC + ((t * cs.NG + gi) * 2 * G) * kWave + lane;
       double cc[G], dd[G];
@@ -433,10 +426,15 @@ __device__ __forceinline__ void grid_coef_rows(const GridArgs &g, const double *
         }
       }
     }
+    // radial factor A_i = c_i / (Hq_i + delta)^2, formed after the angular
+    // sums so that it holds no registers during them
+    const double c = vi ? lc[i] : 0.0;
+    const double Hq = vi ? lq[i] : 1.0;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       if (!ALL && !((active >> m) & 1u)) continue;
-      tot[m] = __builtin_fma(A[m], in[m], tot[m]);
+      const double Gq = rcp64(Hq + dm[m]);
+      tot[m] = __builtin_fma((c * Gq) * Gq, in[m], tot[m]);
     }
   }
 }

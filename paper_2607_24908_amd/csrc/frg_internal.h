@@ -89,7 +89,8 @@ struct GridArgs {
   int32_t n_mb;     // workgroups per momentum
   int32_t chunk;    // (t, u) rows of the Hk table held in LDS at once
   int32_t mblocks;  // mass blocks per wave when the table is resident
-  int32_t form;     // resident FP64 form: 0 coefficients (when they fit), 1 running fractions
+  int32_t form;     // resident FP64 form: 0 coefficients (when they fit; groups of 16 where
+                    // possible), 1 running fractions, 2 coefficients in groups of 8
   // compensated-FP32 grid only (Grid32Table on the device, see below)
   const double *tab32;
   double f32_band, f32_flag;  // FP64 below dhat = f32_band; re-done in FP64 above err f32_flag

@@ -464,7 +464,7 @@ int grid_lds_bytes(const GridArgs &g) {
 
 int grid_coef_group(const GridArgs &g) {
   const int umin = g.n_a / g.J;
-  return umin >= 16 ? 16 : 8;
+  return (umin >= 16 && g.form != 2) ? 16 : 8;
 }
 
 int grid_coef_lds_bytes(const GridArgs &g) {
@@ -500,7 +500,7 @@ static void coef_launch_t(const GridArgs &g, int W, bool redo, hipStream_t st) {
 // Returns false when the shape has no kernel (the host passes M <= 8 for the
 // resident coefficient form and never asks a redo pass of streamed tables).
 bool grid_uses_coef(const GridArgs &g) {
-  return g.form == 0 && grid_coef_lds_bytes(g) <= kGridCoefLdsMax;
+  return g.form != 1 && grid_coef_lds_bytes(g) <= kGridCoefLdsMax;
 }
 
 bool grid_resident(const GridArgs &g) { return grid_uses_coef(g) || g.T * g.U <= g.chunk; }
