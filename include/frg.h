@@ -287,10 +287,11 @@ int frg_autotune(frg_ctx *ctx, int32_t mode, const char *cache_path);
 /* Set / read one default launch-shape knob: "grid_M" (4, 8, 16), "grid_W"
  * (1..8), "grid_MB" (1..64) of the FP64 tensor-grid kernel, "grid32_M" (4, 8),
  * "grid32_W" (1..8), "grid32_MB" (1..64) of the compensated-FP32 one,
- * "grid_form" (0: per-momentum Horner coefficients in groups of 16 angular
- * terms (8 when a lane has fewer) when the table fits in LDS, the default;
- * 1: eight-term running fractions as in frg_integrate; 2: coefficients in
- * groups of 8; the forms agree to a few ulp), "grid_lds_rows" (8..96), "plain_tile", "persist_tile" (1..64),
+ * "grid_form" (0: per-momentum Horner coefficients of one rational function
+ * per lane, radial node and group of up to 32 angular terms, radial factor
+ * included, when the table fits in LDS, the default; 1: eight-term running
+ * fractions as in frg_integrate; 2 / 3: coefficients in groups of 8 / 16;
+ * the forms agree to a few ulp), "grid_lds_rows" (8..96), "plain_tile", "persist_tile" (1..64),
  * "persist_wpc" (1..64), and of the tabulated variant "tab_W" (1..4),
  * "tab_pw" (momenta per wave, 1..64), "tab_lds_nodes" (2..6144), and for
  * streamed rows "tab_wpc" (workgroups per CU, 1..16), "tab_sW" (1..4),

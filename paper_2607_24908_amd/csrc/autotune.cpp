@@ -223,7 +223,7 @@ static bool knob_ok(const char *key, int v) {
   if (!std::strcmp(key, "grid32_M")) return v == 4 || v == 8;
   if (!std::strcmp(key, "grid32_W")) return v >= 1 && v <= 8;
   if (!std::strcmp(key, "grid_lds_rows")) return v >= 8 && v <= 96;
-  if (!std::strcmp(key, "grid_form")) return v >= 0 && v <= 2;
+  if (!std::strcmp(key, "grid_form")) return v >= 0 && v <= 3;
   if (!std::strcmp(key, "tab_W")) return v >= 1 && v <= 4;
   if (!std::strcmp(key, "tab_pw")) return v >= 1 && v <= 64;
   if (!std::strcmp(key, "tab_lds_nodes")) return v >= 2 && v <= (int)tab_lds_max_nodes;

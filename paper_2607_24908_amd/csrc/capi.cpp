@@ -508,6 +508,7 @@ int Ctx::grid_device(const frg_quad &q, int64_t n_p, const double *p, int64_t n_
   g.pref = h.pref;
   g.q_top = h.q_top;
   g.rmu_max = h.rmu_max;
+  set_fold_scale(g, h);
   g.n_p = n_p;
   g.n_m = n_m;
   g.n_r = q.n_radial;
@@ -530,6 +531,8 @@ int Ctx::grid_launch(GridArgs g, int reg, const GridCfg &cfg_in, hipStream_t st,
   int mbk = resident ? std::max(1, cfg.MB) : 1;
   while (mbk > 1 && g.n_p * ((g.n_m + per_wg_min * mbk - 1) / (per_wg_min * mbk)) < 4LL * n_cu)
     mbk /= 2;
+  if (kind != 1 && grid_uses_coef(g))
+    while (mbk > 1 && grid_coef_stage_bytes(mbk, cfg.W, cfg.M) > kGridCoefStageMax) mbk /= 2;
   g.mblocks = mbk;
   g.n_mb = (int)((g.n_m + per_wg_min * mbk - 1) / (per_wg_min * mbk));
   const int e = kind == 1 ? launch_grid32(g, reg, cfg.M, cfg.W, st)
@@ -628,6 +631,7 @@ int Ctx::grid_fp32c(const frg_quad &q, int64_t n_p, const double *p, int64_t n_m
   g.pref = h.pref;
   g.q_top = h.q_top;
   g.rmu_max = h.rmu_max;
+  set_fold_scale(g, h);
   g.n_p = n_p;
   g.n_m = n_m;
   g.n_r = q.n_radial;

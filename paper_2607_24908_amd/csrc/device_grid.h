@@ -233,210 +233,288 @@ namespace frg {
 namespace dev {
 
 // ------------------------------------------------ coefficient form --
-// Resident tables of the FP64 grid kernel.  For a group of G angular terms
-// of one lane (one radial node i; u = gi G .. gi G + G - 1), with
-// H_k = Hk(s_ik) and weights mu_k,
-//   sum_k mu_k / (delta + H_k) = N(delta) / P(delta),
-//   P(delta) = prod_k (delta + H_k) = delta^G + sum_{m<G} c_m delta^m,
-//   N(delta) = sum_k mu_k prod_{l != k} (delta + H_l) = sum_{m<G} d_m delta^m.
-// The coefficients depend on the momentum only, so the workgroup builds them
-// once (G^2 FMAs per group) and every mass evaluates two Horner chains
-// (2G - 1 FMAs and one add) and one reciprocal per G terms.  Every H_k >= 0
-// and mu_k > 0, so all coefficients are positive and both the expansion and
-// the Horner sums add positive terms only (relative error O(G u)).
+// Resident tables of the FP64 grid kernel.  Take one lane and one radial
+// node i of it, and a group of G of the lane's angular terms k (weights
+// mu_k, regulator values H_k = Hk(s_ik); terms past the end of the row are
+// padding with mu = H = 0).  The group's part of the result at mass delta,
+//   c_i / (Hq_i + delta)^2 * sum_k mu_k / (delta + H_k) = N(delta) / P(delta),
+// is one rational function with
+//   P(x) = (x + Hq_i)^2 prod_k (x + H_k)            (monic, degree G + 2),
+//   N(x) = c_i sum_k mu_k prod_{l != k} (x + H_l)    (degree G - 1).
+// Their coefficients depend on the momentum only: the workgroup builds them
+// once, and every mass then costs two Horner sums (2G + 1 FMAs and one add),
+// one reciprocal and one FMA per G terms, radial factor included.  Every
+// H >= 0, mu >= 0 and c >= 0, so all coefficients are non-negative and both
+// the expansion and the Horner sums add non-negative terms only (relative
+// error O(G u), no cancellation).
 //
-// Layout (lane-major, like the H' table): group (t, gi) occupies rows
-// (t NG + gi) 2G + m, m < G holding c_m and m >= G holding d_{m-G}; the
-// remaining angular terms of a row (u >= Gfull) hold H in rows
-// T NG 2G + t UT + (u - Gfull).
+// Scaling.  The coefficients are products of up to G + 2 factors, so they
+// are formed in units where k^2 is about one: x = sig delta, H -> sig H,
+// Hq -> sig Hq and c -> kap c, with sig and kap powers of two (exact), sig
+// k^2 in [1, 2) and kap max_i c_i in [1/2, 1).  N/P then carries the factor
+// kap / sig^3, which the host folds into the prefactor (pref_c).
+//
+// Range.  With X = sig (q_top + p)^2 (every sig H and sig Hq lies below it)
+// and x in [lo, hi], X <= hi: every coefficient and Horner partial sum lies
+// below (2 hi)^(G+2) <= 1e297 and P(x) >= x^(G+2) >= 1e-290, so nothing
+// over- or underflows where it matters.  Masses outside the range, and every
+// mass of a momentum outside it, take the per-term path (grid_single_mass).
+//
+// Layout (lane-major, like the H' table): group (t, gi), gi < NG, occupies
+// 2G + 2 rows from (t NG + gi)(2G + 2): rows m < G + 2 hold the coefficient
+// of x^m of P, rows G + 2 + m that of x^m of N.
 template <int G>
-struct CoefShape {
-  int Gfull, NG, UT, rows;
-  __host__ __device__ CoefShape(int n_a, int J, int T, int U) {
-    const int umin = n_a / J;
-    Gfull = umin - umin % G;
-    NG = Gfull / G;
-    UT = U - Gfull;
-    rows = T * (2 * Gfull + UT);
+struct FoldShape {
+  int NG, rows;
+  __host__ __device__ FoldShape(int U, int T) {
+    NG = (U + G - 1) / G;
+    rows = T * NG * (2 * G + 2);
   }
 };
 
-// Ranges where no coefficient, Horner partial sum or P over- or underflows:
-// per momentum (q_max + p)^2 <= kCoefHi (bounds every H), per mass
-// kCoefLo <= delta <= kCoefHi.
 template <int G>
-struct CoefRange;
+struct FoldRange;
 template <>
-struct CoefRange<8> {
-  static constexpr double lo = 1e-36, hi = 1e36;
+struct FoldRange<8> {
+  static constexpr double lo = 1e-29, hi = 2e29;
 };
 template <>
-struct CoefRange<16> {
-  static constexpr double lo = 1e-18, hi = 5e17;
+struct FoldRange<16> {
+  static constexpr double lo = 1e-16, hi = 1.5e16;
+};
+template <>
+struct FoldRange<32> {
+  static constexpr double lo = 4e-9, hi = 2.5e8;
 };
 
 template <int G>
-__device__ __forceinline__ bool coef_p_ok(double p, double q_top) {
-  const double qp = q_top + p;
-  return qp * qp <= CoefRange<G>::hi;
+__device__ __forceinline__ bool fold_p_ok(double p, const GridArgs &g) {
+  const double qp = g.q_top + p;
+  return g.sig * (qp * qp) <= FoldRange<G>::hi;
 }
 
 template <int G>
-__device__ __forceinline__ bool coef_m_ok(double delta) {
-  return delta >= CoefRange<G>::lo && delta <= CoefRange<G>::hi;
+__device__ __forceinline__ bool fold_m_ok(double x) {
+  return x >= FoldRange<G>::lo && x <= FoldRange<G>::hi;
 }
 
-// Build the coefficient table of momentum p (all threads of the workgroup).
+// Build the coefficient table of momentum p (all threads of the workgroup;
+// lc, lq, lm: c_i, Hq_i and mu_j already staged in LDS).  Pass 1 spreads the
+// regulator evaluations over all threads and parks the scaled H of each
+// group in the group's own P rows; pass 2 expands one group per thread.
 template <int REG, int G>
-__device__ void grid_fill_coef(const GridArgs &g, double *lC, double p, const CoefShape<G> &cs) {
+__device__ void grid_fill_fold(const GridArgs &g, double *lC, const double *lc, const double *lq,
+                               const double *lm, double p, const FoldShape<G> &fs) {
   const double *tq = g.tab;
   const double *to = g.tab + 3 * g.n_r;
-  const double *tm = to + g.n_a;
-  const int n_group = kWave * g.T * cs.NG;
-  const int n_tail = kWave * g.T * cs.UT;
-  for (int task = threadIdx.x; task < n_group + n_tail; task += blockDim.x) {
+  const int n_grp = g.T * fs.NG;
+  for (int task = threadIdx.x; task < kWave * n_grp * G; task += blockDim.x) {
     const int l = task & (kWave - 1);
-    const int rho = l & (g.R - 1), iota = l / g.R;
-    if (task < n_group) {
-      const int rest = task / kWave;
-      const int t = rest / cs.NG, gi = rest - t * cs.NG;
-      const int i = rho + g.R * t;
-      const double q = i < g.n_r ? tq[i] : 0.0;  // padded radial lanes: any finite value
+    const int rest = task / kWave;
+    const int tg = rest / G, k = rest - tg * G;
+    const int t = tg / fs.NG, gi = tg - t * fs.NG;
+    const int i = (l & (g.R - 1)) + g.R * t;
+    const int j = l / g.R + g.J * (gi * G + k);
+    double H = 0.0;
+    if (i < g.n_r && j < g.n_a) {
+      const double q = tq[i];
       const double qm = q - p;
-      const double a = qm * qm;
-      const double b = (2.0 * q) * p;
-      double P[G + 1], N[G];
-#pragma unroll
-      for (int m = 0; m <= G; ++m) P[m] = m == 0 ? 1.0 : 0.0;
-#pragma unroll
-      for (int m = 0; m < G; ++m) N[m] = 0.0;
-#pragma unroll
-      for (int k = 0; k < G; ++k) {
-        const int j = iota + g.J * (gi * G + k);
-        const double H = hk<REG>(__builtin_fma(b, to[j], a), g.k2, g.inv_k2);
-        const double mu = tm[j];
-        // N <- N (delta + H) + mu P, then P <- P (delta + H), on the old P.
-        // Before term k, P has degree k with P[k] = 1 and N degree k - 1;
-        // only those entries are touched (k is a compile-time index here).
-        if (k == 0) {
-          N[0] = mu;
-          P[1] = 1.0;
-          P[0] = H;
-        } else {
-          N[k] = __builtin_fma(mu, P[k], N[k - 1]);
-#pragma unroll
-          for (int m = G - 1; m >= 1; --m)
-            if (m < k) N[m] = __builtin_fma(mu, P[m], __builtin_fma(H, N[m], N[m - 1]));
-          N[0] = __builtin_fma(mu, P[0], H * N[0]);
-          P[k + 1 <= G ? k + 1 : G] = 1.0;
-#pragma unroll
-          for (int m = G; m >= 1; --m)
-            if (m <= k) P[m] = __builtin_fma(H, P[m], P[m - 1]);
-          P[0] = H * P[0];
-        }
-      }
-      double *dst = lC + ((t * cs.NG + gi) * 2 * G) * kWave + l;
-#pragma unroll
-      for (int m = 0; m < G; ++m) {
-        dst[m * kWave] = P[m];
-        dst[(G + m) * kWave] = N[m];
-      }
-    } else {
-      const int rest = (task - n_group) / kWave;
-      const int t = rest / cs.UT, ut = rest - t * cs.UT;
-      const int i = rho + g.R * t;
-      const int j = iota + g.J * (cs.Gfull + ut);
-      double H = 1.0;
-      if (j < g.n_a) {
-        const double q = i < g.n_r ? tq[i] : 0.0;
-        const double qm = q - p;
-        H = hk<REG>(__builtin_fma((2.0 * q) * p, to[j], qm * qm), g.k2, g.inv_k2);
-      }
-      lC[(g.T * cs.NG * 2 * G + t * cs.UT + ut) * kWave + l] = H;
+      H = g.sig * hk<REG>(__builtin_fma((2.0 * q) * p, to[j], qm * qm), g.k2, g.inv_k2);
     }
+    lC[(tg * (2 * G + 2) + k) * kWave + l] = H;
+  }
+  __syncthreads();
+  for (int task = threadIdx.x; task < kWave * n_grp; task += blockDim.x) {
+    const int l = task & (kWave - 1);
+    const int tg = task / kWave;
+    const int t = tg / fs.NG, gi = tg - t * fs.NG;
+    const int i = (l & (g.R - 1)) + g.R * t;
+    const int j0 = l / g.R + g.J * gi * G;
+    const bool vi = i < g.n_r;
+    double *col = lC + tg * (2 * G + 2) * kWave + l;
+    double P[G + 3], N[G];
+#pragma unroll
+    for (int m = 0; m < G + 3; ++m) P[m] = 0.0;
+#pragma unroll
+    for (int m = 0; m < G; ++m) N[m] = 0.0;
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const double H = col[k * kWave];
+      const int j = j0 + g.J * k;
+      const double mu = (vi && j < g.n_a) ? lm[j] : 0.0;
+      // N <- N (x + H) + mu P, then P <- P (x + H), on the old P.  Before
+      // term k, P has degree k with P[k] = 1 and N degree k - 1; only those
+      // entries are touched (k is a compile-time index here).
+      if (k == 0) {
+        N[0] = mu;
+        P[1] = 1.0;
+        P[0] = H;
+      } else {
+        N[k] = __builtin_fma(mu, P[k], N[k - 1]);
+#pragma unroll
+        for (int m = G - 1; m >= 1; --m)
+          if (m < k) N[m] = __builtin_fma(mu, P[m], __builtin_fma(H, N[m], N[m - 1]));
+        N[0] = __builtin_fma(mu, P[0], H * N[0]);
+        P[k + 1] = 1.0;
+#pragma unroll
+        for (int m = G; m >= 1; --m)
+          if (m <= k) P[m] = __builtin_fma(H, P[m], P[m - 1]);
+        P[0] = H * P[0];
+      }
+    }
+    // radial factor: P <- P (x + Hq)^2, N <- c N
+    const double Hq = vi ? g.sig * lq[i] : 0.0;
+    const double c = vi ? g.kap * lc[i] : 0.0;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int deg = G + r;  // P[deg] = 1
+      P[deg + 1] = 1.0;
+#pragma unroll
+      for (int m = G + 1; m >= 1; --m)
+        if (m <= deg) P[m] = __builtin_fma(Hq, P[m], P[m - 1]);
+      P[0] = Hq * P[0];
+    }
+#pragma unroll
+    for (int m = 0; m < G + 2; ++m) col[m * kWave] = P[m];
+#pragma unroll
+    for (int m = 0; m < G; ++m) col[(G + 2 + m) * kWave] = c * N[m];
   }
 }
 
 // Accumulate, for the masses set in `active`, the lane partials of the
-// coefficient form into tot[m].  ALL: every mass active.
+// coefficient form into tot[m]; xs[m] = sig delta_m.  ALL: every mass active.
 template <int M, int G, bool ALL>
-__device__ __forceinline__ void grid_coef_rows(const GridArgs &g, const double *lC,
-                                               const double *lc, const double *lq,
-                                               const double *lm, int lane, const double *dm,
-                                               unsigned active, const CoefShape<G> &cs,
-                                               double *tot) {
-  const int rho = lane & (g.R - 1);
-  const int iota = lane / g.R;
-  for (int t = 0; t < g.T; ++t) {
-    const int i = rho + g.R * t;
-    const bool vi = i < g.n_r;
-    double in[M];
+__device__ __forceinline__ void grid_fold_rows(const GridArgs &g, const double *lC, int lane,
+                                               const double *xs, unsigned active,
+                                               const FoldShape<G> &fs, double *tot) {
+  const int n_grp = g.T * fs.NG;
+  for (int tg = 0; tg < n_grp; ++tg) {
+    const double *src = lC + tg * (2 * G + 2) * kWave + lane;
+    double a[G + 2], b[G];
 #pragma unroll
-    for (int m = 0; m < M; ++m) in[m] = 0.0;
-    for (int gi = 0; gi < cs.NG; ++gi) {
-      const double *src = lC + ((t * cs.NG + gi) * 2 * G) * kWave + lane;
-      double cc[G], dd[G];
+    for (int m = 0; m < G + 2; ++m) a[m] = src[m * kWave];
 #pragma unroll
-      for (int m = 0; m < G; ++m) {
-        cc[m] = src[m * kWave];
-        dd[m] = src[(G + m) * kWave];
-      }
-      if constexpr (ALL) {
-        // masses in pairs: four independent Horner chains in flight
+    for (int m = 0; m < G; ++m) b[m] = src[(G + 2 + m) * kWave];
+    if constexpr (ALL) {
+      // masses in pairs: four independent Horner chains in flight
 #pragma unroll
-        for (int m = 0; m < M; m += 2) {
-          const double xa = dm[m], xb = dm[m + 1];
-          double Pa = xa + cc[G - 1], Pb = xb + cc[G - 1];
-          double Na = dd[G - 1], Nb = dd[G - 1];
+      for (int m = 0; m < M; m += 2) {
+        const double xa = xs[m], xb = xs[m + 1];
+        double Pa = xa + a[G + 1], Pb = xb + a[G + 1];
+        Pa = __builtin_fma(Pa, xa, a[G]);
+        Pb = __builtin_fma(Pb, xb, a[G]);
+        Pa = __builtin_fma(Pa, xa, a[G - 1]);
+        Pb = __builtin_fma(Pb, xb, a[G - 1]);
+        double Na = b[G - 1], Nb = b[G - 1];
 #pragma unroll
-          for (int k = G - 2; k >= 0; --k) {
-            Pa = __builtin_fma(Pa, xa, cc[k]);
-            Pb = __builtin_fma(Pb, xb, cc[k]);
-            Na = __builtin_fma(Na, xa, dd[k]);
-            Nb = __builtin_fma(Nb, xb, dd[k]);
-            __builtin_amdgcn_sched_barrier(0);
-          }
-          in[m] = __builtin_fma(Na, rcp64(Pa), in[m]);
-          in[m + 1] = __builtin_fma(Nb, rcp64(Pb), in[m + 1]);
+        for (int k = G - 2; k >= 0; --k) {
+          Pa = __builtin_fma(Pa, xa, a[k]);
+          Pb = __builtin_fma(Pb, xb, a[k]);
+          Na = __builtin_fma(Na, xa, b[k]);
+          Nb = __builtin_fma(Nb, xb, b[k]);
+          __builtin_amdgcn_sched_barrier(0);
         }
-      } else {
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-          if (!((active >> m) & 1u)) continue;
-          const double x = dm[m];
-          double P = x + cc[G - 1], N = dd[G - 1];
-#pragma unroll
-          for (int k = G - 2; k >= 0; --k) {
-            P = __builtin_fma(P, x, cc[k]);
-            N = __builtin_fma(N, x, dd[k]);
-          }
-          in[m] = __builtin_fma(N, rcp64(P), in[m]);
-        }
+        tot[m] = __builtin_fma(Na, rcp64(Pa), tot[m]);
+        tot[m + 1] = __builtin_fma(Nb, rcp64(Pb), tot[m + 1]);
       }
-    }
-    for (int ut = 0; ut < cs.UT; ++ut) {
-      const int j = iota + g.J * (cs.Gfull + ut);
-      if (j < g.n_a) {
-        const double mu = lm[j];
-        const double H = lC[(g.T * cs.NG * 2 * G + t * cs.UT + ut) * kWave + lane];
+    } else {
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-          if (!ALL && !((active >> m) & 1u)) continue;
-          in[m] = __builtin_fma(mu, rcp64(H + dm[m]), in[m]);
+      for (int m = 0; m < M; ++m) {
+        if (!((active >> m) & 1u)) continue;
+        const double x = xs[m];
+        double P = x + a[G + 1], N = b[G - 1];
+        P = __builtin_fma(P, x, a[G]);
+        P = __builtin_fma(P, x, a[G - 1]);
+#pragma unroll
+        for (int k = G - 2; k >= 0; --k) {
+          P = __builtin_fma(P, x, a[k]);
+          N = __builtin_fma(N, x, b[k]);
         }
+        tot[m] = __builtin_fma(N, rcp64(P), tot[m]);
       }
-    }
-    // radial factor A_i = c_i / (Hq_i + delta)^2, formed after the angular
-    // sums so that it holds no registers during them
-    const double c = vi ? lc[i] : 0.0;
-    const double Hq = vi ? lq[i] : 1.0;
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-      if (!ALL && !((active >> m) & 1u)) continue;
-      const double Gq = rcp64(Hq + dm[m]);
-      tot[m] = __builtin_fma((c * Gq) * Gq, in[m], tot[m]);
     }
   }
+}
+
+// ------------------------------------------- cross-lane sums (gfx950) --
+// Lane permutations of a double: DPP within rows of 16 lanes (CTRL: 0xB1
+// swaps neighbours, 0x4E swaps pairs, 0x141 mirrors each half-row, 0x128
+// rotates each row by 8) and the gfx950 lane swaps (half-waves, odd/even
+// rows), each moving the two 32-bit halves separately.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// For values a, b in every lane, returns a' + b' where (a', b') is a and b
+// with lanes [32, 64) of a exchanged with lanes [0, 32) of b (W32) or with
+// rows 1 and 3 of a exchanged with rows 0 and 2 of b (W16): lane l gets
+// a_l + a_{l+w} in the lower part of each 2w block and b_{l-w} + b_l in the
+// upper part.
+template <int W>
+__device__ __forceinline__ double swap_add(double a, double b) {
+  const unsigned long long ua = __builtin_bit_cast(unsigned long long, a);
+  const unsigned long long ub = __builtin_bit_cast(unsigned long long, b);
+  unsigned lo0, lo1, hi0, hi1;
+  if constexpr (W == 32) {
+    const auto rl = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+    const auto rh = __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+    lo0 = rl[0]; lo1 = rl[1]; hi0 = rh[0]; hi1 = rh[1];
+  } else {
+    const auto rl = __builtin_amdgcn_permlane16_swap((unsigned)ua, (unsigned)ub, false, false);
+    const auto rh = __builtin_amdgcn_permlane16_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+    lo0 = rl[0]; lo1 = rl[1]; hi0 = rh[0]; hi1 = rh[1];
+  }
+  const double x = __builtin_bit_cast(double, ((unsigned long long)hi0 << 32) | lo0);
+  const double y = __builtin_bit_cast(double, ((unsigned long long)hi1 << 32) | lo1);
+  return x + y;
+}
+
+// Sums of M values (M = 1, 2, 4, 8) over the 64 lanes at once.  The pairing
+// is the same for every M: lane offsets 32, 16, 8, then 1, 2 and 4 (as the
+// half-row mirror, equivalent once each quad holds equal values), each step
+// own + partner.  The first log2 M steps halve the number of live values (a
+// lane keeps the half selected by the offset's bit of its index), so lane l
+// ends with the total of value l / (64 / M), the same bits for every M.
+template <int M>
+__device__ __forceinline__ double wave_sum_fold(const double *v, int lane) {
+  static_assert(M == 1 || M == 2 || M == 4 || M == 8, "M must be 1, 2, 4 or 8");
+  double w[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) w[m] = v[m];
+  // offset 32
+  if constexpr (M >= 2) {
+#pragma unroll
+    for (int k = 0; k < M / 2; ++k) w[k] = swap_add<32>(w[k], w[M / 2 + k]);
+  } else {
+    w[0] = swap_add<32>(w[0], w[0]);
+  }
+  // offset 16
+  if constexpr (M >= 4) {
+#pragma unroll
+    for (int k = 0; k < M / 4; ++k) w[k] = swap_add<16>(w[k], w[M / 4 + k]);
+  } else {
+    w[0] = swap_add<16>(w[0], w[0]);
+  }
+  // offset 8 (rotation by 8 within a row of 16 is the exchange of offset 8)
+  double x;
+  if constexpr (M == 8) {
+    double lo = w[0], hi = w[1];
+    asm("" : "+v"(lo), "+v"(hi));
+    const bool upper = (lane & 8) != 0;
+    const double keep = upper ? hi : lo;
+    const double send = upper ? lo : hi;
+    x = keep + dpp_f64<0x128>(send);
+  } else {
+    x = w[0] + dpp_f64<0x128>(w[0]);
+  }
+  x = x + dpp_f64<0xB1>(x);
+  x = x + dpp_f64<0x4E>(x);
+  x = x + dpp_f64<0x141>(x);
+  return x;
 }
 
 // Lane partial of one mass outside the coefficient range: every term on its

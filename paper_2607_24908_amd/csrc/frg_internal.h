@@ -89,8 +89,9 @@ struct GridArgs {
   int32_t n_mb;     // workgroups per momentum
   int32_t chunk;    // (t, u) rows of the Hk table held in LDS at once
   int32_t mblocks;  // mass blocks per wave when the table is resident
-  int32_t form;     // resident FP64 form: 0 coefficients (when they fit; groups of 16 where
-                    // possible), 1 running fractions, 2 coefficients in groups of 8
+  int32_t form;     // resident FP64 form: 0 coefficients (when they fit; group size from U),
+                    // 1 running fractions, 2 / 3 coefficients in groups of 8 / 16
+  double sig, kap, pref_c;  // coefficient form: scale of x and H, of c; pref kap^-1 sig^3
   // compensated-FP32 grid only (Grid32Table on the device, see below)
   const double *tab32;
   double f32_band, f32_flag;  // FP64 below dhat = f32_band; re-done in FP64 above err f32_flag
@@ -161,8 +162,12 @@ int launch_grid(const GridArgs &g, int reg, int M, int W, void *stream, bool red
 int grid_lds_bytes(const GridArgs &g);
 // Resident coefficient form of the FP64 grid kernel: used when its table fits.
 constexpr int kGridCoefLdsMax = 150 * 1024;
+// staged masses and masks of one workgroup: MB W (16 + 8 M) bytes, at most
+constexpr int kGridCoefStageMax = 8192;
 int grid_coef_group(const GridArgs &g);
-int grid_coef_lds_bytes(const GridArgs &g);
+int grid_coef_lds_bytes(const GridArgs &g);  // with the largest staging area
+int grid_coef_stage_bytes(int MB, int W, int M);
+void set_fold_scale(GridArgs &g, const QuadTable &h);
 // Whether the FP64 grid kernel keeps its table resident, and in which form.
 bool grid_uses_coef(const GridArgs &g);
 bool grid_resident(const GridArgs &g);

@@ -4,6 +4,7 @@
 // summation order are in device_fp64.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "frg_internal.h"
@@ -238,23 +239,28 @@ template <int REG, int M, int G, bool REDO>
 __global__ __launch_bounds__(512) void grid_coef_kernel(GridArgs g) {
   extern __shared__ double lds[];
   const int W = blockDim.x / kWave;
-  const int wave = threadIdx.x / kWave;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t a = blockIdx.x / g.n_mb;
   const int mb = (int)(blockIdx.x - a * g.n_mb);
   const double p = g.p[a];
   const int n_r = g.n_r, n_a = g.n_a;
   const int MB = g.mblocks;
+  const int nblk = MB * W;  // mass blocks of M masses in this workgroup
+  const int64_t wg_m0 = (int64_t)mb * nblk * M;
   if constexpr (REDO) {
-    const int64_t first = (int64_t)mb * MB * W * M;
     bool any = false;
-    for (int idx = threadIdx.x; idx < MB * W * M; idx += blockDim.x)
-      any |= first + idx < g.n_m && g.used64[a * g.n_m + first + idx] == 1;
+    for (int idx = threadIdx.x; idx < nblk * M; idx += blockDim.x)
+      any |= wg_m0 + idx < g.n_m && g.used64[a * g.n_m + wg_m0 + idx] == 1;
     if (!__syncthreads_or(any)) return;  // workgroup-uniform
   }
-  const CoefShape<G> cs(n_a, g.J, g.T, g.U);
+  // LDS: coefficients | per-block masks (valid, ok, coefficient form,
+  // active) | masses delta | c_i | Hq_i | mu_j
+  const FoldShape<G> fs(g.U, g.T);
   double *lC = lds;
-  double *lc = lC + cs.rows * kWave;
+  unsigned *lmask = reinterpret_cast<unsigned *>(lC + fs.rows * kWave);
+  double *ldm = reinterpret_cast<double *>(lmask + 4 * nblk);
+  double *lc = ldm + nblk * M;
   double *lq = lc + n_r;
   double *lm = lq + n_r;
   for (int idx = threadIdx.x; idx < n_r; idx += blockDim.x) {
@@ -263,64 +269,79 @@ __global__ __launch_bounds__(512) void grid_coef_kernel(GridArgs g) {
   }
   for (int idx = threadIdx.x; idx < n_a; idx += blockDim.x) lm[idx] = g.tab[3 * n_r + n_a + idx];
   const bool p_ok = p >= 0.0;
-  const bool table = p_ok && coef_p_ok<G>(p, g.q_top);  // workgroup-uniform
-  if (table) grid_fill_coef<REG, G>(g, lC, p, cs);
-  __syncthreads();
-  const unsigned all = (M == 32) ? ~0u : ((1u << M) - 1u);
-  for (int rep = 0; rep < MB; ++rep) {
-    const int64_t m0 = (((int64_t)mb * MB + rep) * W + wave) * M;
-    if (m0 >= g.n_m) break;  // wave-uniform
-    double dm[M];
-    unsigned okbits = 0, cmask = 0, act = all;
+  const bool table = p_ok && fold_p_ok<G>(p, g);  // workgroup-uniform
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    unsigned vb = 0, okb = 0, cmb = 0, act = 0;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-      const int64_t idx = m0 + m;
+      const int64_t idx = wg_m0 + (int64_t)b * M + m;
       const bool valid = idx < g.n_m;
       const double d = valid ? g.m2[idx] + g.k2 : 1.0;
       const bool ok = valid && p_ok && d > 0.0;
-      dm[m] = ok ? d : 1.0;
-      okbits |= ok ? (1u << m) : 0u;
-      cmask |= (table && coef_m_ok<G>(dm[m])) ? (1u << m) : 0u;
-      if (REDO && !(valid && g.used64[a * g.n_m + idx] == 1)) act &= ~(1u << m);
+      const double dd = ok ? d : 1.0;
+      ldm[b * M + m] = dd;
+      vb |= valid ? (1u << m) : 0u;
+      okb |= ok ? (1u << m) : 0u;
+      cmb |= (table && fold_m_ok<G>(g.sig * dd)) ? (1u << m) : 0u;
+      act |= (!REDO || (valid && g.used64[a * g.n_m + idx] == 1)) ? (1u << m) : 0u;
     }
-    // the masses are the same in every lane: make the choices wave-uniform
-    okbits = __builtin_amdgcn_readfirstlane(okbits);
-    cmask = __builtin_amdgcn_readfirstlane(cmask);
-    act = __builtin_amdgcn_readfirstlane(act);
+    lmask[4 * b] = vb;
+    lmask[4 * b + 1] = okb;
+    lmask[4 * b + 2] = cmb;
+    lmask[4 * b + 3] = act;
+  }
+  __syncthreads();
+  if (table) grid_fill_fold<REG, G>(g, lC, lc, lq, lm, p, fs);
+  __syncthreads();
+  const unsigned all = (1u << M) - 1u;
+  for (int rep = 0; rep < MB; ++rep) {
+    const int b = rep * W + wave;
+    const int64_t m0 = wg_m0 + (int64_t)b * M;
+    if (m0 >= g.n_m) break;  // wave-uniform
+    // the masses are the same in every lane: the choices are wave-uniform
+    const unsigned validbits = __builtin_amdgcn_readfirstlane(lmask[4 * b]);
+    const unsigned okbits = __builtin_amdgcn_readfirstlane(lmask[4 * b + 1]);
+    const unsigned cmask = __builtin_amdgcn_readfirstlane(lmask[4 * b + 2]);
+    const unsigned act = __builtin_amdgcn_readfirstlane(lmask[4 * b + 3]);
     if (REDO && !act) continue;
+    double dm[M], xs[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      dm[m] = ldm[b * M + m];
+      xs[m] = g.sig * dm[m];
+    }
     double tot[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) tot[m] = 0.0;
     const unsigned cm = act & cmask;
     if (cm == all)
-      grid_coef_rows<M, G, true>(g, lC, lc, lq, lm, lane, dm, cm, cs, tot);
+      grid_fold_rows<M, G, true>(g, lC, lane, xs, cm, fs, tot);
     else if (cm)
-      grid_coef_rows<M, G, false>(g, lC, lc, lq, lm, lane, dm, cm, cs, tot);
+      grid_fold_rows<M, G, false>(g, lC, lane, xs, cm, fs, tot);
     const unsigned sm = act & ~cmask;
     if (sm) {
 #pragma unroll
       for (int m = 0; m < M; ++m)
         if ((sm >> m) & 1u) tot[m] = grid_single_mass<REG>(g, lc, lq, lm, lane, p, dm[m]);
     }
-    // lane l ends with the total of mass l / (64 / M)
-    const double v = g.pref * wave_sum_split<M>(tot, lane);
+    // lane l ends with the total of mass l / (64 / M); the coefficient form
+    // carries the factor kap / sig^3 (folded into pref_c)
+    const double s = wave_sum_fold<M>(tot, lane);
     const int mine = lane / (kWave / M);
+    const double v = (((cmask >> mine) & 1u) ? g.pref_c : g.pref) * s;
     const bool okm = (okbits >> mine) & 1u;
+    const bool mine_out = lane % (kWave / M) == 0 && ((validbits >> mine) & 1u);
     if (REDO) {
       // the FP32 kernel has already written the other points and the flag
-      if (lane % (kWave / M) == 0 && ((act >> mine) & 1u)) {
+      if (mine_out && ((act >> mine) & 1u)) {
         const int64_t o = a * g.n_m + m0 + mine;
         g.out[o] = okm ? v : __builtin_nan("");
         if (g.err) g.err[o] = kErr64;
       }
       continue;
     }
-    bool bad = false;
-#pragma unroll
-    for (int m = 0; m < M; ++m) bad |= (m0 + m < g.n_m) && !((okbits >> m) & 1u);
-    if (bad && lane == 0) *g.flag = 1;
-    if (lane % (kWave / M) == 0 && m0 + mine < g.n_m)
-      g.out[a * g.n_m + m0 + mine] = okm ? v : __builtin_nan("");
+    if ((validbits & ~okbits) && lane == 0) *g.flag = 1;
+    if (mine_out) g.out[a * g.n_m + m0 + mine] = okm ? v : __builtin_nan("");
   }
 }
 
@@ -463,15 +484,34 @@ int grid_lds_bytes(const GridArgs &g) {
 }
 
 int grid_coef_group(const GridArgs &g) {
-  const int umin = g.n_a / g.J;
-  return (umin >= 16 && g.form != 2) ? 16 : 8;
+  if (g.form == 2) return 8;
+  if (g.form == 3) return 16;
+  return g.U <= 8 ? 8 : g.U <= 16 ? 16 : 32;
 }
 
 int grid_coef_lds_bytes(const GridArgs &g) {
   const int G = grid_coef_group(g);
-  const int rows = G == 16 ? CoefShape<16>(g.n_a, g.J, g.T, g.U).rows
-                           : CoefShape<8>(g.n_a, g.J, g.T, g.U).rows;
-  return (int)sizeof(double) * (rows * kWave + 2 * g.n_r + g.n_a);
+  const int rows = G == 32   ? FoldShape<32>(g.U, g.T).rows
+                   : G == 16 ? FoldShape<16>(g.U, g.T).rows
+                             : FoldShape<8>(g.U, g.T).rows;
+  return (int)sizeof(double) * (rows * kWave + 2 * g.n_r + g.n_a) + kGridCoefStageMax;
+}
+
+int grid_coef_stage_bytes(int MB, int W, int M) { return MB * W * (16 + 8 * M); }
+
+void set_fold_scale(GridArgs &g, const QuadTable &h) {
+  int e_k, e_c;
+  (void)std::frexp(h.k2, &e_k);  // k2 = f 2^e_k, f in [1/2, 1)
+  double cmax = 0.0;
+  for (int i = 0; i < h.n_r; ++i) cmax = std::max(cmax, h.data[h.n_r + i]);
+  if (cmax > 0.0)
+    (void)std::frexp(cmax, &e_c);
+  else
+    e_c = 0;
+  g.sig = std::ldexp(1.0, 1 - e_k);
+  g.kap = std::ldexp(1.0, -e_c);
+  // N/P carries kap / sig^3
+  g.pref_c = std::ldexp(h.pref, 3 * (1 - e_k) + e_c);
 }
 
 // Ask for dynamic LDS beyond 64 KiB for one kernel (gfx950: 160 KiB per
@@ -488,7 +528,7 @@ static void coef_launch_t(const GridArgs &g, int W, bool redo, hipStream_t st) {
                             allow_large_lds((const void *)&grid_coef_kernel<REG, M, G, true>), true);
   (void)once;
   const int64_t blocks = g.n_p * g.n_mb;
-  const int lds = grid_coef_lds_bytes(g);
+  const int lds = grid_coef_lds_bytes(g) - kGridCoefStageMax + grid_coef_stage_bytes(g.mblocks, W, M);
   if (redo)
     hipLaunchKernelGGL((grid_coef_kernel<REG, M, G, true>), dim3((unsigned)blocks),
                        dim3(kWave * W), lds, st, g);
@@ -500,7 +540,8 @@ static void coef_launch_t(const GridArgs &g, int W, bool redo, hipStream_t st) {
 // Returns false when the shape has no kernel (the host passes M <= 8 for the
 // resident coefficient form and never asks a redo pass of streamed tables).
 bool grid_uses_coef(const GridArgs &g) {
-  return g.form != 1 && grid_coef_lds_bytes(g) <= kGridCoefLdsMax;
+  return g.form != 1 && std::isnormal(g.pref_c) && std::isnormal(g.sig) &&
+         grid_coef_lds_bytes(g) <= kGridCoefLdsMax;
 }
 
 bool grid_resident(const GridArgs &g) { return grid_uses_coef(g) || g.T * g.U <= g.chunk; }
@@ -511,7 +552,10 @@ static bool grid_launch_t(const GridArgs &g, int W, bool redo, hipStream_t st) {
     if constexpr (M > 8) {
       return false;
     } else {
-      if (grid_coef_group(g) == 16)
+      const int G = grid_coef_group(g);
+      if (G == 32)
+        coef_launch_t<REG, M, 32>(g, W, redo, st);
+      else if (G == 16)
         coef_launch_t<REG, M, 16>(g, W, redo, st);
       else
         coef_launch_t<REG, M, 8>(g, W, redo, st);

@@ -137,6 +137,36 @@ def test_grid_launch_shapes_bitwise(ctx):
             frg.frg_tune_set(ctx, k, v)
 
 
+def test_grid_forms_agree(ctx):
+    """The resident forms of the grid kernel (coefficients with the group
+    size from the row length, groups of 8 and of 16, running fractions) all
+    match the oracle; rows of several groups (64 x 48: two 32-term groups per
+    lane row) and padded groups (100 x 12) included."""
+    cases = [(3, frg.FRG_REG_EXP, 128, 32), (4, frg.FRG_REG_LITIM, 100, 12),
+             (3, frg.FRG_REG_EXP, 64, 48), (4, frg.FRG_REG_EXP, 16, 70)]
+    rng = np.random.Generator(np.random.PCG64(11))
+    k = 1.3
+    p = np.concatenate([[0.0], 10 ** rng.uniform(-3, 1.2, 12)])
+    m2 = np.concatenate([[-k * k + 1e-6, 0.0], rng.uniform(-0.9 * k * k, 9.0, 29)])
+    default = frg.frg_tune_get(ctx, "grid_form")
+    try:
+        for d, reg, n_r, n_a in cases:
+            want = oracle.integrate_grid(d, reg, k, 6 * k, n_r, n_a, p, m2).ravel()
+            quad = frg.make_quad(d, reg, k, 6 * k, n_r, n_a)
+            outs = []
+            for form in (0, 1, 2, 3):
+                print(f"[case] forms {n_r}x{n_a} reg={reg} form={form}", flush=True)
+                frg.frg_tune_set(ctx, "grid_form", form)
+                got = run_grid(ctx, quad, p, m2)
+                err = relerr(got, want)
+                assert err.max() < RTOL, (form, err.max())
+                outs.append(got)
+            for o in outs[1:]:
+                assert close(o, outs[0])
+    finally:
+        frg.frg_tune_set(ctx, "grid_form", default)
+
+
 # --------------------------------------------------------- ragged shapes --
 
 SHAPES = [(100, 12, 3, frg.FRG_REG_EXP), (7, 3, 4, frg.FRG_REG_LITIM), (33, 5, 5, frg.FRG_REG_EXP),
@@ -168,28 +198,46 @@ def test_ragged_shapes_grid_and_points(ctx, n_r, n_a, d, reg):
 
 
 def test_grouped_and_single_forms_mixed(ctx):
-    """Points on both sides of the range test of the grouped reciprocal sums
-    (delta around 1e-30, (q_top + p)^2 around 1e37), in one grid: the masses
-    of one wave take different forms.  Both forms match the oracle and the
-    point kernel."""
-    cases = [(3e-16, np.array([0.0, 1e-16, 1e-15, 1e-10, 1e3, 1e17, 1e18, 1e19]),
-              np.array([0.0, 5e-31, 2e-30, 1e-29, 1e-20, 1e-3, 0.0, 3e-30, 2e-31, 1e-28, 7e-31])),
-             # around the bounds of the 16-term coefficient form (delta 1e-18,
-             # (q_max + p)^2 5e17): masses of one wave on both sides
-             (1e-9, np.array([0.0, 1e-9, 1e-6, 1e-3, 1e8, 7e8, 1e9]),
-              np.array([0.0, -0.5e-18, 1e-17, -0.9e-18, 3e-18, 1e-12, -0.2e-18, 5e-18, 0.0]))]
-    for (k, p, m2), (d, reg, n_r, n_a) in [(c, s) for c in cases for s in
-                                            [(3, frg.FRG_REG_EXP, 96, 24), (4, frg.FRG_REG_LITIM, 20, 40)]]:
-        quad = frg.make_quad(d, reg, k, 6 * k, n_r, n_a)
-        got = run_grid(ctx, quad, p, m2)
-        want = oracle.integrate_grid(d, reg, k, 6 * k, n_r, n_a, p, m2).ravel()
-        err = relerr(got, want)
-        print(f"d={d} reg={reg}: max rel err {err.max():.3e}")
-        assert np.all(np.isfinite(got))
-        assert err.max() < RTOL
-        P = np.repeat(p, m2.size)
-        M = np.tile(m2, p.size)
-        assert close(run_points(ctx, quad, P, M), got)
+    """Points on both sides of the range tests of the grouped forms, in one
+    grid, so that the masses of one wave take different forms: the eight-term
+    running fractions of the point kernel (delta around 1e-30, (q_top + p)^2
+    around 1e37) and the coefficient form of the grid kernel, whose bounds
+    are on x = sig delta and sig (q_top + p)^2 with sig k^2 = 1.15 here (sig a
+    power of two): [4e-9, 2.5e8] for 32-term groups (a lane holds U = 24
+    angular terms at 96 x 24), at most 1.5e16 for 16-term groups (U = 10 at
+    20 x 40), at most 2e29 for 8-term groups (U = 8 at 64 x 8).  Every form
+    matches the oracle and the point kernel."""
+    exp, lit = frg.FRG_REG_EXP, frg.FRG_REG_LITIM
+    k = 1e-9
+    kk = k * k
+    cases = [
+        (3e-16, np.array([0.0, 1e-16, 1e-15, 1e-10, 1e3, 1e17, 1e18, 1e19]),
+         np.array([0.0, 5e-31, 2e-30, 1e-29, 1e-20, 1e-3, 0.0, 3e-30, 2e-31, 1e-28, 7e-31]),
+         [(3, exp, 96, 24), (4, lit, 20, 40)]),
+        (k, np.array([0.0, 1e-9, 1e-6, 1.4e-5, 1.6e-5, 1e-3]),
+         np.array([0.0, -kk + 2e-27, -kk + 5e-27, -kk + 1e-20, 1e-12, 2e-10, 3e-10,
+                   -kk + 3.4e-27, -kk + 3.6e-27]),
+         [(3, exp, 96, 24), (4, lit, 96, 24)]),
+        (k, np.array([0.0, 0.1, 0.12, 1.0]),
+         np.array([0.0, 0.01, 0.012, 0.014, 0.02, -kk + 1e-20, 1e-15]),
+         [(3, exp, 20, 40), (4, lit, 20, 40)]),
+        (k, np.array([0.0, 1.0, 4e5, 4.2e5]),
+         np.array([0.0, 1e11, 1.7e11, 1.8e11, -kk + 1e-25, 1e-3]),
+         [(3, exp, 64, 8), (4, lit, 64, 8)]),
+    ]
+    for kc, p, m2, shapes in cases:
+        for d, reg, n_r, n_a in shapes:
+            print(f"[case] k={kc} d={d} reg={reg} {n_r}x{n_a}", flush=True)
+            quad = frg.make_quad(d, reg, kc, 6 * kc, n_r, n_a)
+            got = run_grid(ctx, quad, p, m2)
+            want = oracle.integrate_grid(d, reg, kc, 6 * kc, n_r, n_a, p, m2).ravel()
+            err = relerr(got, want)
+            print(f"  max rel err {err.max():.3e}")
+            assert np.all(np.isfinite(got))
+            assert err.max() < RTOL
+            P = np.repeat(p, m2.size)
+            M = np.tile(m2, p.size)
+            assert close(run_points(ctx, quad, P, M), got)
 
 
 # ------------------------------------------------------- scale-up d = 3 --
