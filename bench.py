@@ -28,17 +28,19 @@ sys.path.insert(0, ROOT)
 
 # ALU roofline of the FP64 path.  Issue rate of the FP64 VALU of MI355X:
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 lane-cycles/s.  Floor of
-# the per-evaluation work of the grid kernel: for a group of G angular terms
-# sum_k mu_k/(delta + H_k) = N(delta)/P(delta) with per-momentum polynomial
-# coefficients, so each (term, mass) costs one Horner FMA of P and one of N;
-# the reciprocal of P, its Newton step and the accumulation are shared by
-# the G = 16 terms of a group and the coefficient build by every mass of
-# the momentum, and are left out of the floor: 2 FP64 operations per eval.
+# the per-evaluation work of the grid kernel: for one radial node and a group
+# of G angular terms of a lane, c/(Hq + delta)^2 sum_k mu_k/(delta + H_k) =
+# N(delta)/P(delta) with per-momentum polynomial coefficients, so each
+# (term, mass) costs one Horner FMA of P and one of N; the two extra FMAs of
+# the radial factor, the reciprocal of P, its Newton step and the
+# accumulation are shared by the G = 32 terms of a group and the coefficient
+# build by every mass of the momentum, and are left out of the floor: 2 FP64
+# operations per eval.
 VALU_LANE_CYCLES = 256 * 4 * 16 * 2.4e9
 # HBM bytes per grid-kernel launch from rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # scaled by a 1 GiB device copy read the same way (fetch x2.00, write x1.00):
-# 456 KiB x 2.00 + 16384 KiB x 1.00.
-TRAFFIC = 456 * 1024 * 2.00 + 16384 * 1024 * 1.00
+# 487.5 KiB x 2.00 + 16384 KiB x 1.00.
+TRAFFIC = 487.5 * 1024 * 2.00 + 16384 * 1024 * 1.00
 CYCLES_PER_EVAL_FLOOR = 2
 PEAK_EVALS = VALU_LANE_CYCLES / CYCLES_PER_EVAL_FLOOR
 
