@@ -63,6 +63,15 @@ def lib():
         L.oracle_lpa_rhs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                      ctypes.c_double, ctypes.c_double, ctypes.c_long,
                                      ctypes.c_double, dp, dp, dp]
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.oracle_pflow_rhs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_long, ctypes.c_long, ctypes.c_double, dp, dp,
+                                       ctypes.c_double, dp, dp, ip, ctypes.c_int]
+        L.oracle_pflow_solve.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_long, ctypes.c_long, ctypes.c_double, dp, dp,
+                                         ctypes.c_double, ctypes.c_long, dp, dp, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -166,6 +175,49 @@ def lpa_rhs(d, N, reg, n_r, q_max_over_k, k, rho_max, U, jacobian=True, allow_do
     if rc == E_INVAL or (rc == E_DOMAIN and not allow_domain):
         raise ValueError(f"oracle_lpa_rhs rc={rc}")
     return dUdt, jac, rc
+
+
+def pflow_rhs(d, reg, Lam, kappa, n_r, n_a, s_max, lam3, lam4, t, Sigma, threads=1,
+              allow_domain=False):
+    """Right-hand side of the momentum-dependent two-point flow (constant
+    vertices): dSigma_r(p_a)/dt = lam3_r^2 J_r(p_a) - lam4_r/2 T_r with the
+    propagator table g_r[a] = 1/(s_a + R_k(s_a) + Sigma_r[a]) on the nodes
+    s_a = a s_max/(n_s - 1), p_a = sqrt(s_a), k = Lam e^t, q_max = kappa k;
+    J is the tabulated diagram, T = C_d sum_i w_i q_i^{d-1} d_tR G(q_i^2)^2.
+    Sigma has shape (n_flows, n_s).  Returns (dSdt, dead)."""
+    S = np.ascontiguousarray(np.asarray(Sigma, dtype=np.float64))
+    if S.ndim != 2:
+        raise ValueError("Sigma must be (n_flows, n_s)")
+    l3 = _f64(lam3).ravel()
+    l4 = _f64(lam4).ravel()
+    out = np.empty_like(S)
+    dead = np.zeros(S.shape[0], dtype=np.int32)
+    rc = lib().oracle_pflow_rhs(int(d), int(reg), float(Lam), float(kappa), int(n_r), int(n_a),
+                                S.shape[0], S.shape[1], float(s_max), _ptr(l3), _ptr(l4),
+                                float(t), _ptr(S), _ptr(out),
+                                dead.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), int(threads))
+    if rc == E_INVAL or (rc == E_DOMAIN and not allow_domain):
+        raise ValueError(f"oracle_pflow_rhs rc={rc}")
+    return out, dead
+
+
+def pflow_solve(d, reg, Lam, kappa, n_r, n_a, s_max, lam3, lam4, t_end, n_steps, Sigma0,
+                threads=1):
+    """The two-point flow integrated by classical RK4 from t = 0 to t_end in
+    n_steps equal steps (see pflow_rhs).  Returns (Sigma(t_end), t_reached);
+    a flow that meets the domain boundary keeps the state at the start of
+    that step and reports that time."""
+    S = np.array(Sigma0, dtype=np.float64, copy=True, order="C")
+    l3 = _f64(lam3).ravel()
+    l4 = _f64(lam4).ravel()
+    t_reached = np.empty(S.shape[0])
+    rc = lib().oracle_pflow_solve(int(d), int(reg), float(Lam), float(kappa), int(n_r), int(n_a),
+                                  S.shape[0], S.shape[1], float(s_max), _ptr(l3), _ptr(l4),
+                                  float(t_end), int(n_steps), _ptr(S), _ptr(t_reached),
+                                  int(threads))
+    if rc == E_INVAL:
+        raise ValueError("oracle_pflow_solve: invalid arguments")
+    return S, t_reached
 
 
 def Omega(n: int) -> float:

@@ -45,6 +45,26 @@
  *     G_r(s) = (1 - f) g_r[k] + f g_r[k+1],  t = s/h, k = floor(t), f = t - k,
  *   (piecewise-linear interpolation; s >= s_max takes g_r[n_s - 1]).
  *
+ *   Momentum-dependent two-point flow (one loop, constant vertices): the
+ *   two-point function Gamma2_k(p) = p^2 + Sigma_k(p) of a scalar with
+ *   momentum-independent three- and four-point couplings lam3, lam4 flows by
+ *   the second field derivative of the Wetterich equation,
+ *     d_t Sigma(p) = lam3^2 J(p) - (lam4/2) T,
+ *     J(p) = int d^dq/(2pi)^d d_tR(q^2) G(q^2)^2 G(|q+p|^2),
+ *     T    = int d^dq/(2pi)^d d_tR(q^2) G(q^2)^2,
+ *     G(s) = 1/(s + R_k(s) + Sigma(sqrt s)).
+ *   Sigma lives on the nodes s_a = a s_max/(n_s - 1); at each RG time the
+ *   table g[a] = 1/(s_a + R_k(s_a) + Sigma_a) is the propagator of the
+ *   tabulated variant above (piecewise linear, constant beyond s_max), J is
+ *   that variant at p_a = sqrt(s_a) and T its radial part with C_d:
+ *     T = C_d sum_i w_i q_i^{d-1} d_tR(q_i^2) G(q_i^2)^2,
+ *   with the quadrature at scale k = Lambda e^t and q_max = kappa k.  A
+ *   non-positive table denominator ends the flow (domain).  Time stepping:
+ *   classical fourth-order Runge-Kutta from t = 0 to t_end with n_steps equal
+ *   steps h = t_end/n_steps, t_n = n h; a flow whose right-hand side meets the
+ *   domain boundary at any stage of step n keeps its state at t_n and
+ *   reports t_n as the time reached.
+ *
  *   Threshold functions (radial only, LPA):
  *     F_n(m^2) = C_d sum_i w_i q_i^{d-1} d_tR(q_i^2) G(q_i^2)^n,
  *     C_d = Omega_d/(2pi)^d.
@@ -378,4 +398,104 @@ int oracle_lpa_rhs(int d, int N, int reg, int n_r, double q_max_over_k, double k
     }
   }
   return domain ? OR_E_DOMAIN : OR_OK;
+}
+
+/* ------------------------------------------- momentum-dependent flow -- */
+
+/* Right-hand side of the two-point flow for n_rows flows at RG time t:
+ * dSdt[r * n_s + a] = lam3[r]^2 J_r(p_a) - lam4[r]/2 T_r.  A flow with a
+ * non-positive table denominator gets dead[r] = 1 and NaN in its row. */
+int oracle_pflow_rhs(int d, int reg, double Lambda, double kappa, int n_r, int n_a, long n_rows,
+                     long n_s, double s_max, const double *lam3, const double *lam4, double t,
+                     const double *Sigma, double *dSdt, int *dead, int n_threads) {
+  if (!(Lambda > 0.0) || !(kappa > 0.0) || n_s < 2 || !(s_max > 0.0) || n_rows < 0) return OR_E_INVAL;
+  const double k = Lambda * exp(t), k2 = k * k;
+  const double q_max = kappa * k;
+  if (check_common(d, reg, k, q_max, n_r) || d < 3 || n_a < 1) return OR_E_INVAL;
+  double *g = malloc(sizeof(double) * n_rows * n_s);
+  double *p = malloc(sizeof(double) * n_s);
+  double *J = malloc(sizeof(double) * n_s * (n_rows > 0 ? n_rows : 1));
+  double *q = malloc(sizeof(double) * n_r), *w = malloc(sizeof(double) * n_r);
+  const double h = s_max / (double)(n_s - 1);
+  for (long a = 0; a < n_s; ++a) p[a] = sqrt((double)a * h);
+  for (long r = 0; r < n_rows; ++r) {
+    dead[r] = 0;
+    for (long a = 0; a < n_s; ++a) {
+      double s = (double)a * h;
+      double den = denom(reg, k2, s, k2 + Sigma[r * n_s + a]);
+      if (!(den > 0.0)) dead[r] = 1;
+      g[r * n_s + a] = (den > 0.0) ? 1.0 / den : 0.0;
+    }
+  }
+  int rc = oracle_integrate_tab(d, reg, k, q_max, n_r, n_a, n_rows, n_s, s_max, g, n_s, p, J,
+                                n_threads);
+  radial_rule(reg, k, q_max, n_r, q, w);
+  const double Cd = oracle_Cd(d);
+  for (long r = 0; r < n_rows && rc == OR_OK; ++r) {
+    long double T = 0.0L;
+    for (int i = 0; i < n_r; ++i) {
+      double Gq = interp_row(g + r * n_s, n_s, s_max, q[i] * q[i]);
+      T += (long double)(w[i] * ipow(q[i], d - 1) * dtR(reg, k2, q[i] * q[i]) * Gq * Gq);
+    }
+    const double Tr = Cd * (double)T;
+    for (long a = 0; a < n_s; ++a)
+      dSdt[r * n_s + a] = dead[r] ? NAN : lam3[r] * lam3[r] * J[a * n_rows + r] - 0.5 * lam4[r] * Tr;
+  }
+  free(g); free(p); free(J); free(q); free(w);
+  if (rc != OR_OK) return rc;
+  for (long r = 0; r < n_rows; ++r)
+    if (dead[r]) return OR_E_DOMAIN;
+  return OR_OK;
+}
+
+/* Classical RK4 from t = 0 to t_end in n_steps equal steps for every flow;
+ * Sigma is updated in place, t_reached[r] = t_end or the start of the step
+ * whose right-hand side met the domain boundary. */
+int oracle_pflow_solve(int d, int reg, double Lambda, double kappa, int n_r, int n_a, long n_rows,
+                       long n_s, double s_max, const double *lam3, const double *lam4,
+                       double t_end, long n_steps, double *Sigma, double *t_reached, int n_threads) {
+  if (!(t_end <= 0.0) || n_steps < 1 || n_rows < 0) return OR_E_INVAL;
+  const long n = n_rows * n_s;
+  double *y = malloc(sizeof(double) * n), *acc = malloc(sizeof(double) * n);
+  double *kk = malloc(sizeof(double) * n);
+  int *alive = malloc(sizeof(int) * (n_rows > 0 ? n_rows : 1));
+  int *dead = malloc(sizeof(int) * (n_rows > 0 ? n_rows : 1));
+  const double h = t_end / (double)n_steps;
+  const double cs[4] = {0.0, 0.5, 0.5, 1.0};  /* stage times */
+  const double bs[4] = {1.0, 2.0, 2.0, 1.0};  /* stage weights (times 1/6) */
+  int rc = OR_OK;
+  for (long r = 0; r < n_rows; ++r) {
+    alive[r] = 1;
+    t_reached[r] = t_end;
+  }
+  for (long step = 0; step < n_steps && rc != OR_E_INVAL; ++step) {
+    const double tn = (double)step * h;
+    for (long e = 0; e < n; ++e) {
+      y[e] = Sigma[e];
+      acc[e] = 0.0;
+    }
+    for (int st = 0; st < 4; ++st) {
+      rc = oracle_pflow_rhs(d, reg, Lambda, kappa, n_r, n_a, n_rows, n_s, s_max, lam3, lam4,
+                            tn + cs[st] * h, y, kk, dead, n_threads);
+      if (rc == OR_E_INVAL) break;
+      for (long r = 0; r < n_rows; ++r) {
+        if (!alive[r]) continue;
+        if (dead[r]) {
+          alive[r] = 0;
+          t_reached[r] = tn;
+          continue;
+        }
+        for (long a = 0; a < n_s; ++a) {
+          const long e = r * n_s + a;
+          acc[e] += bs[st] * kk[e];
+          if (st < 3) y[e] = Sigma[e] + cs[st + 1] * h * kk[e];
+        }
+      }
+    }
+    for (long r = 0; r < n_rows; ++r)
+      if (alive[r])
+        for (long a = 0; a < n_s; ++a) Sigma[r * n_s + a] += (h / 6.0) * acc[r * n_s + a];
+  }
+  free(y); free(acc); free(kk); free(alive); free(dead);
+  return rc == OR_E_INVAL ? OR_E_INVAL : OR_OK;
 }

@@ -37,7 +37,7 @@ def closed_Pd(d):
 
 
 def closed_Cd(d):
-    return {3: 1.0 / (2 * PI ** 2), 4: 1.0 / (8 * PI ** 2)}[d]
+    return {3: 1.0 / (2 * PI ** 2), 4: 1.0 / (8 * PI ** 2), 5: 1.0 / (12 * PI ** 3)}[d]
 
 
 def mu_sum(d, n_a):
@@ -435,3 +435,110 @@ def test_tab_domain_and_arguments():
         oracle.integrate_tab(3, REG_EXP, 1.0, 6.0, 8, 4, np.ones((2, 1)), 10.0, [0.5])
     with pytest.raises(ValueError):
         oracle.integrate_tab(3, REG_EXP, 1.0, 6.0, 8, 4, G, 0.0, [0.5])
+
+
+# ------------------------------------------- momentum-dependent flow (f2) --
+
+@pytest.mark.parametrize("d", [3, 5])
+@pytest.mark.parametrize("t", [0.0, math.log(0.5)])
+def test_pflow_rhs_litim_p0_closed_form(d, t):
+    """Litim regulator, uniform Sigma = m^2, k^2 on a node of the table
+    (h = 1/4; k^2 = 1 at t = 0, 1/4 at t = ln 1/2): below k^2 every node holds
+    1/(k^2 + m^2), so at p = 0 the diagram is closed-form,
+    J(0) = C_d (2/d) k^(d+2) / (k^2 + m^2)^3 and T = C_d (2/d) k^(d+2) / (k^2 + m^2)^2
+    (d = 3, 5: the angular weight (1 - x^2)^((d-3)/2) is a polynomial, so the
+    angular rule is exact and P_d sum_j mu_j = C_d)."""
+    k = math.exp(t)
+    lam3 = np.array([1.0, 0.0, 2.5, 0.7])
+    lam4 = np.array([0.0, 1.0, 3.0, -2.0])
+    m2 = np.array([0.3, -0.1, 2.0, 0.05]) * k * k
+    Sigma = np.repeat(m2[:, None], 17, axis=1)
+    rhs, dead = oracle.pflow_rhs(d, REG_LITIM, 1.0, 6.0, 12, 6, 4.0, lam3, lam4, t, Sigma)
+    assert not dead.any()
+    base = closed_Cd(d) * (2.0 / d) * k ** (d + 2)
+    want = base * (lam3 ** 2 / (k * k + m2) ** 3 - 0.5 * lam4 / (k * k + m2) ** 2)
+    np.testing.assert_allclose(rhs[:, 0], want, rtol=1e-13, atol=1e-15 * base)
+
+
+def test_pflow_rhs_is_linear_in_the_couplings():
+    """d_t Sigma = lam3^2 J - lam4/2 T: the right-hand side for (lam3, lam4)
+    is lam3^2 times that for (1, 0) plus lam4 times that for (0, 1)."""
+    rng = np.random.Generator(np.random.PCG64(3))
+    Sigma = rng.uniform(0.1, 1.0, (1, 21))
+    args = (3, REG_EXP, 1.0, 6.0, 16, 8, 9.0)
+    a, _ = oracle.pflow_rhs(*args, [1.0], [0.0], -0.3, Sigma)
+    b, _ = oracle.pflow_rhs(*args, [0.0], [1.0], -0.3, Sigma)
+    c, _ = oracle.pflow_rhs(*args, [1.7], [-2.3], -0.3, Sigma)
+    np.testing.assert_allclose(c, 1.7 ** 2 * a - 2.3 * b, rtol=1e-13, atol=1e-16)
+    assert np.all(a > 0) and np.all(b < 0)  # J > 0, T > 0
+
+
+def test_pflow_without_cubic_coupling_stays_uniform():
+    """With lam3 = 0 the right-hand side is the same at every momentum, so a
+    uniform Sigma stays uniform (to the bit) under the RK4 steps."""
+    S0 = np.full((2, 33), 0.4)
+    S, tr = oracle.pflow_solve(4, REG_EXP, 1.0, 6.0, 24, 8, 16.0, [0.0, 0.0], [1.5, -3.0],
+                               -1.5, 30, S0)
+    assert np.all(tr == -1.5)
+    for r in range(2):
+        assert np.all(S[r] == S[r, 0])
+    assert S[0, 0] > 0.4 and S[1, 0] < 0.4  # -lam4/2 T dt with dt < 0
+
+
+@pytest.mark.parametrize("d", [3, 4])
+def test_pflow_matches_the_continuum_mass_flow(d):
+    """lam3 = 0, Litim: Sigma stays uniform, m^2(t), and the radial rule is
+    exact for the Litim integrand; once the table is fine enough that no
+    radial node falls in the cell across the kink of R at s = k^2, the
+    interpolation is exact too and the discrete flow is the continuum ODE
+    d_t m^2 = -(lam4/2) C_d (2/d) k^(d+2) / (k^2 + m^2)^2, k = e^t (integrated
+    here by scipy at tight tolerance) up to the RK4 error.  On a coarse table
+    the kink cell costs a visible but bounded error."""
+    lam4, m20, t_end = 4.0, 0.2, -1.0
+    Cd = closed_Cd(d)
+
+    def f(t, y):
+        k = math.exp(t)
+        return [-0.5 * lam4 * Cd * (2.0 / d) * k ** (d + 2) / (k * k + y[0]) ** 2]
+
+    ref = integrate.solve_ivp(f, (0.0, t_end), [m20], method="DOP853", rtol=1e-13,
+                              atol=1e-15).y[0, -1]
+    errs = {}
+    for n_s in (65, 1025):
+        S, tr = oracle.pflow_solve(d, REG_LITIM, 1.0, 6.0, 8, 4, 1.0, [0.0], [lam4], t_end, 200,
+                                   np.full((1, n_s), m20))
+        assert tr[0] == t_end
+        errs[n_s] = abs(S[0, 0] - ref) / abs(ref - m20)
+    assert errs[1025] < 1e-10
+    assert 1e-7 < errs[65] < 1e-3
+
+
+def test_pflow_rk4_is_fourth_order():
+    """Halving the step divides the error of the final state by ~16 (a
+    table clamped beyond a tiny s_max makes the right-hand side smooth in t:
+    G = 1/(s_max + R_k(s_max) + Sigma), the same at every node)."""
+    args = (3, REG_EXP, 1.0, 6.0, 16, 8, 1e-6, [2.0], [1.0], -1.0)
+    S0 = np.full((1, 3), 0.5)
+    ref, _ = oracle.pflow_solve(*args, 512, S0)
+    errs = [np.max(np.abs(oracle.pflow_solve(*args, n, S0)[0] - ref)) for n in (4, 8, 16, 32)]
+    assert abs(ref[0, 0] - 0.5) > 0.1
+    for e1, e2 in zip(errs, errs[1:]):
+        assert 11.0 < e1 / e2 < 17.0
+
+
+def test_pflow_domain_stops():
+    """A flow whose table denominator s + R_k(s) + Sigma is not positive stops
+    at the start of that step with its state kept; the other flows of the
+    batch are unaffected (rows are independent)."""
+    args = (3, REG_EXP, 1.0, 6.0, 16, 8, 4.0)
+    S0 = np.vstack([np.full(17, -1.5), np.full(17, 0.5), np.full(17, -0.5)])
+    lam3, lam4 = [1.0, 1.0, 2.0], [0.0, 0.0, 0.0]
+    S, tr = oracle.pflow_solve(*args, lam3, lam4, -2.0, 40, S0)
+    assert tr[0] == 0.0 and np.all(S[0] == -1.5)  # k^2 - 1.5 < 0 at p = 0
+    assert tr[1] == -2.0
+    assert tr[2] == 3 * (-2.0 / 40)  # driven to the pole during the fourth step
+    assert np.all(np.isfinite(S[2])) and np.all(S[2] < -0.5)
+    alone, tr1 = oracle.pflow_solve(*args, lam3[1:2], lam4[1:2], -2.0, 40, S0[1:2])
+    assert np.array_equal(alone[0], S[1]) and tr1[0] == -2.0
+    _, dead = oracle.pflow_rhs(*args, lam3, lam4, 0.0, S0, allow_domain=True)
+    assert list(dead) == [1, 0, 0]
