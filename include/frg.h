@@ -168,6 +168,56 @@ typedef struct {
 int frg_integrate_tab(frg_ctx *ctx, const frg_quad *quad, const frg_gtab *tab, int64_t n_p,
                       const double *p, double *out, int32_t mem, void *hip_stream);
 
+/* ---- momentum-dependent two-point flow ------------------------------------ */
+/* Flow of the momentum-dependent two-point function Gamma2_k(p) = p^2 +
+ * Sigma_k(p) of one scalar with constant three- and four-point couplings
+ * lam3, lam4: the second field derivative of the Wetterich equation, with the
+ * one-loop flow diagram of frg_integrate_tab as its momentum-dependent part,
+ *   d_t Sigma(p) = lam3^2 J(p) - (lam4/2) T,
+ *   J(p) = int d^dq/(2pi)^d d_tR(q^2) G(q^2)^2 G(|q+p|^2),
+ *   T    = int d^dq/(2pi)^d d_tR(q^2) G(q^2)^2,
+ *   G(s) = 1/(s + R_k(s) + Sigma(sqrt s)),   k = lambda e^t.
+ * Sigma of each flow lives on the n_s nodes s_a = a s_max/(n_s - 1) (p_a =
+ * sqrt(s_a)); at each RG time the propagator table of the flow is
+ * g[a] = 1/(s_a + R_k(s_a) + Sigma_a) (piecewise linear in s, the last node
+ * beyond s_max, as in frg_gtab), J(p_a) is frg_integrate_tab of that row and
+ * T = C_d sum_i w_i q_i^{d-1} d_tR(q_i^2) G(q_i^2)^2 its radial part, with the
+ * quadrature rules at scale k (q_max = q_max_over_k k; Litim: min(q_max, k)).
+ * A flow whose table has a denominator <= 0 has left the domain. */
+typedef struct {
+  int32_t d;            /* 3 <= d <= 8                                         */
+  int32_t reg;          /* FRG_REG_EXP or FRG_REG_LITIM                        */
+  int32_t n_radial;     /* 1..1024                                             */
+  int32_t n_angular;    /* 1..256                                              */
+  double lambda;        /* UV scale, > 0: k = lambda e^t                       */
+  double q_max_over_k;  /* > 0 (usually 6)                                     */
+  int64_t n_s;          /* momentum nodes, 2..2^24                             */
+  double s_max;         /* > 0: last node                                      */
+} frg_pflow;
+
+/* One right-hand side at RG time t for n_flows flows:
+ *   dsdt[r * n_s + a] = lam3[r]^2 J_r(p_a) - lam4[r]/2 T_r   given
+ *   sigma[r * n_s + a] = Sigma_r(p_a);
+ * lam3, lam4: n_flows each.  A flow outside the domain gets NaN in its row
+ * (FRG_E_DOMAIN for host memory; device calls are asynchronous and return
+ * FRG_OK).  mem says where all arrays live. */
+int frg_pflow_rhs(frg_ctx *ctx, const frg_pflow *pf, int64_t n_flows, const double *lam3,
+                  const double *lam4, double t, const double *sigma, double *dsdt, int32_t mem,
+                  void *hip_stream);
+
+/* Integrate n_flows flows from t = 0 to t_end <= 0 with the classical
+ * fourth-order Runge-Kutta method in n_steps >= 1 equal steps h = t_end/n_steps
+ * (stage times t_n + {0, h/2, h/2, h}, t_n = n h), every stage on the device.
+ * sigma (n_flows * n_s, row r = flow r) holds Sigma at t = 0 on entry and at
+ * t_reached[r] on return.  A flow whose right-hand side leaves the domain at
+ * any stage of step n keeps its state at t_n and reports t_reached[r] = t_n;
+ * the others report t_end (flows are independent: a batch gives the same
+ * bits as each flow alone).  Returns FRG_OK whether or not flows stopped (the
+ * stop is a result, read from t_reached); device calls are asynchronous. */
+int frg_pflow_solve(frg_ctx *ctx, const frg_pflow *pf, int64_t n_flows, const double *lam3,
+                    const double *lam4, double t_end, int64_t n_steps, double *sigma,
+                    double *t_reached, int32_t mem, void *hip_stream);
+
 /* ---- LPA O(N) flow -------------------------------------------------------- */
 /* Local potential approximation of the O(N) model, effective potential U(rho)
  * with rho = phi^2/2 on the uniform grid rho_j = j rho_max/(n_grid-1):

@@ -563,8 +563,15 @@ int Ctx::tab_device(const frg_quad &q, const frg_gtab &tb, int64_t n_p, const do
   a.n_s = tb.n_s;
   a.n_r = q.n_radial;
   a.n_a = q.n_angular;
+  return tab_launch(a, q.reg, st);
+}
+
+// Launch shape of tab_kernel for the problem in `a` (p, out, g, tab, flag,
+// pref, k2, inv_h, t_last, n_p, n_rows, n_s, n_r, n_a set by the caller).
+int Ctx::tab_launch(TabArgs a, int reg, hipStream_t st) {
+  const int64_t n_p = a.n_p;
   tab_lane_split(a.n_r, a.n_a, &a.R, &a.J, &a.T, &a.U);
-  const bool lds_rows = tb.n_s <= std::min<int64_t>(tune.tab_lds_nodes, tab_lds_max_nodes) &&
+  const bool lds_rows = a.n_s <= std::min<int64_t>(tune.tab_lds_nodes, tab_lds_max_nodes) &&
                         tab_lds_bytes(a, true) <= 64 * 1024;
   const int W = std::max(1, std::min(4, lds_rows ? tune.tab_W : tune.tab_sW));
   a.pw = std::max(1, std::min(64, lds_rows ? tune.tab_pw : tune.tab_spw));
@@ -578,8 +585,8 @@ int Ctx::tab_device(const frg_quad &q, const frg_gtab &tb, int64_t n_p, const do
     a.pw = (int)std::max<int64_t>(1, std::min<int64_t>(a.pw, fit));
   }
   a.n_pb = (int)((n_p + (int64_t)W * a.pw - 1) / ((int64_t)W * a.pw));
-  if (tb.n_rows * a.n_pb > ((int64_t)1 << 31) - 1) return fail(FRG_E_INVAL, "tabulated problem too large");
-  int e = launch_tab(a, q.reg, W, lds_rows, sblocks, st);
+  if (a.n_rows * a.n_pb > ((int64_t)1 << 31) - 1) return fail(FRG_E_INVAL, "tabulated problem too large");
+  int e = launch_tab(a, reg, W, lds_rows, sblocks, st);
   if (e) return hip_fail((hipError_t)e, "tab_kernel launch");
   return FRG_OK;
 }

@@ -140,6 +140,12 @@ struct Context {
   int integrate_fp32c_sets(const std::vector<frg::SetDev> &sd, int flags, hipStream_t st);
   int tab_device(const frg_quad &q, const frg_gtab &tab, int64_t n_p, const double *p, double *out,
                  hipStream_t st);
+  int tab_launch(frg::TabArgs a, int reg, hipStream_t st);
+  // pflow_api.cpp: momentum-dependent flow; dsdt != nullptr: one right-hand side
+  // at t_rhs, else RK4 from 0 to t_end (all arrays on the device)
+  int pflow_device(const frg_pflow &pf, int64_t n_flows, const double *lam3, const double *lam4,
+                   double t_end, int64_t n_steps, double *sigma, double *t_reached,
+                   double *dsdt, double t_rhs, int *flag, hipStream_t st);
   int grid_device(const frg_quad &q, int64_t n_p, const double *p, int64_t n_m, const double *m2,
                   double *out, double *err, uint8_t *used, hipStream_t st);
   int grid_fp32c(const frg_quad &q, int64_t n_p, const double *p, int64_t n_m, const double *m2,

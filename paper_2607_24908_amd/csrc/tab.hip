@@ -16,23 +16,13 @@
 #pragma clang fp contract(off)
 
 #include "device_fp64.h"
+#include "device_tab.h"
 
 namespace frg {
 
 namespace {
 
 using namespace dev;
-
-// Interpolated propagator of one row at table coordinate t = s / h (t >= 0).
-__device__ __forceinline__ double interp(const double *__restrict__ row, double t, double t_last,
-                                         int k_last) {
-  t = fmin(t, t_last);
-  int k = (int)t;
-  k = k < k_last ? k : k_last;
-  const double f = t - (double)k;
-  const double g0 = row[k], g1 = row[k + 1];
-  return __builtin_fma(f, g1 - g0, g0);
-}
 
 // One (row, momentum block) of work: A_i of the row, then W * pw momenta.
 // lq / lo / lm are staged; `row` is the LDS copy or the row in memory.

@@ -29,7 +29,8 @@ STATUS_NAMES = {0: "FRG_OK", 1: "FRG_PENDING", -1: "FRG_E_INVAL", -2: "FRG_E_DOM
                 -6: "FRG_E_NOTFOUND", -7: "FRG_E_STEP"}
 
 EXPORTS = ["frg_create", "frg_destroy", "frg_last_error", "frg_version", "frg_integrate",
-           "frg_integrate_grid", "frg_integrate_tab", "frg_flow_rhs", "frg_flow_rhs_batch", "frg_flow_solve",
+           "frg_integrate_grid", "frg_integrate_tab", "frg_pflow_rhs", "frg_pflow_solve",
+           "frg_flow_rhs", "frg_flow_rhs_batch", "frg_flow_solve",
            "frg_submit", "frg_poll", "frg_server_stats", "frg_gauss_legendre",
            "frg_flow_footprint", "frg_autotune", "frg_tune_set", "frg_tune_get"]
 
@@ -50,6 +51,13 @@ class frg_set(ctypes.Structure):
 class frg_gtab(ctypes.Structure):
     _fields_ = [("n_rows", ctypes.c_int64), ("n_s", ctypes.c_int64), ("s_max", ctypes.c_double),
                 ("g", ctypes.c_void_p)]
+
+
+class frg_pflow(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("reg", ctypes.c_int32), ("n_radial", ctypes.c_int32),
+                ("n_angular", ctypes.c_int32), ("lambda_", ctypes.c_double),
+                ("q_max_over_k", ctypes.c_double), ("n_s", ctypes.c_int64),
+                ("s_max", ctypes.c_double)]
 
 
 class frg_lpa(ctypes.Structure):
@@ -108,6 +116,9 @@ def _load():
                                      i32, vp]
     L.frg_integrate_tab.argtypes = [vp, ctypes.POINTER(frg_quad), ctypes.POINTER(frg_gtab), i64,
                                     vp, vp, i32, vp]
+    L.frg_pflow_rhs.argtypes = [vp, ctypes.POINTER(frg_pflow), i64, vp, vp, dbl, vp, vp, i32, vp]
+    L.frg_pflow_solve.argtypes = [vp, ctypes.POINTER(frg_pflow), i64, vp, vp, dbl, i64, vp, vp,
+                                  i32, vp]
     L.frg_flow_rhs.argtypes = [vp, ctypes.POINTER(frg_lpa), dbl, vp, vp, vp, i32, vp]
     L.frg_flow_rhs_batch.argtypes = [vp, i32, ctypes.POINTER(frg_lpa), ctypes.POINTER(dbl),
                                      ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
@@ -218,6 +229,32 @@ def frg_integrate_tab(ctx, quad, g, s_max, p, out, mem=FRG_MEM_DEVICE, stream=No
     return _check(lib.frg_integrate_tab(ctx, ctypes.byref(quad), ctypes.byref(tab), n_p, _addr(p),
                                         _addr(out), mem, st),
                   (FRG_E_DOMAIN,) if allow_domain else ())
+
+
+def make_pflow(d, reg, n_radial, n_angular, lam, q_max_over_k, n_s, s_max):
+    return frg_pflow(int(d), int(reg), int(n_radial), int(n_angular), float(lam),
+                     float(q_max_over_k), int(n_s), float(s_max))
+
+
+def frg_pflow_rhs(ctx, pf, lam3, lam4, t, sigma, dsdt, mem=FRG_MEM_DEVICE, stream=None,
+                  allow_domain=False):
+    """sigma, dsdt: n_flows * n_s values, row r = flow r; lam3, lam4: n_flows."""
+    n = int(lam3.numel() if hasattr(lam3, "numel") else np.asarray(lam3).size)
+    st = 0 if mem == FRG_MEM_HOST else _stream(stream)
+    return _check(lib.frg_pflow_rhs(ctx, ctypes.byref(pf), n, _addr(lam3), _addr(lam4), float(t),
+                                    _addr(sigma), _addr(dsdt), mem, st),
+                  (FRG_E_DOMAIN,) if allow_domain else ())
+
+
+def frg_pflow_solve(ctx, pf, lam3, lam4, t_end, n_steps, sigma, t_reached, mem=FRG_MEM_DEVICE,
+                    stream=None):
+    """RK4 from t = 0 to t_end; sigma (n_flows * n_s) is updated in place,
+    t_reached (n_flows) receives where each flow stopped."""
+    n = int(lam3.numel() if hasattr(lam3, "numel") else np.asarray(lam3).size)
+    st = 0 if mem == FRG_MEM_HOST else _stream(stream)
+    return _check(lib.frg_pflow_solve(ctx, ctypes.byref(pf), n, _addr(lam3), _addr(lam4),
+                                      float(t_end), int(n_steps), _addr(sigma), _addr(t_reached),
+                                      mem, st))
 
 
 def frg_flow_rhs(ctx, lpa, t, U, dUdt, jac_bands=None, mem=FRG_MEM_DEVICE, stream=None,

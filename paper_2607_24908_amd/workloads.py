@@ -26,6 +26,11 @@ regulator):
   g_r(s) = (1 + 0.1/(1 + s))/(s + M_r), M_r evenly spaced in [0.1, 11] (an input
   standing in for a dressed propagator; nothing of the method is computed).
   n_s = 4096 (rows staged in LDS) and 2^20 (8 MB rows read through the caches).
+* ``pflow_d3`` -- momentum-dependent two-point flows: d = 3, exponential
+  regulator, Lambda = 1, q_max = 6k, 128 radial x 32 angular nodes, Sigma on
+  256 nodes of s in [0, 49] (p up to 7 Lambda), 64 flows with lam3 uniform in
+  [0.5, 2.5], lam4 uniform in [0, 8], Sigma(t = 0) = m^2 uniform in [0.2, 1]
+  (Gamma2 = p^2 + m^2), RG time 0 -> -4 in 100 RK4 steps.
 * ``lpa_requests`` -- a Poisson stream (rate 50/s) of LPA O(N) flow requests:
   N in {1, 2, 4}, d = 3, exponential regulator, grid of 128..1024 points on
   rho in [0, 0.5], initial U = lambda/8 (rho - rho0)^2 with lambda ~ U(1, 20),
@@ -159,6 +164,47 @@ def tabulated_d3(n_s: int = 4096, n_p: int = 1024, n_rows: int = 64) -> TabWorkl
     s_max = (q.q_max + 20.0) ** 2
     return TabWorkload(f"tabulated_d3_{n_p}p_{n_rows}rows_{n_s}s_128r32a", q, p,
                        tab_rows(n_rows, n_s, s_max), s_max)
+
+
+@dataclass
+class PflowWorkload:
+    name: str
+    d: int
+    reg: int
+    n_r: int
+    n_a: int
+    lam: float          # UV scale
+    kappa: float        # q_max / k
+    n_s: int
+    s_max: float
+    lam3: np.ndarray    # (n_flows,)
+    lam4: np.ndarray    # (n_flows,)
+    sigma0: np.ndarray  # (n_flows, n_s)
+    t_end: float
+    n_steps: int
+
+    @property
+    def n_flows(self) -> int:
+        return self.lam3.size
+
+    @property
+    def evals_per_rhs(self) -> int:
+        return self.n_flows * self.n_s * self.n_r * self.n_a
+
+    @property
+    def n_evals(self) -> int:
+        return 4 * self.n_steps * self.evals_per_rhs
+
+
+def pflow_d3(seed: int = 0, n_flows: int = 64, n_s: int = 256, n_steps: int = 100,
+             n_r: int = 128, n_a: int = 32) -> PflowWorkload:
+    rng = _rng(seed)
+    lam3 = rng.uniform(0.5, 2.5, n_flows)
+    lam4 = rng.uniform(0.0, 8.0, n_flows)
+    m2 = rng.uniform(0.2, 1.0, n_flows)
+    sigma0 = np.repeat(m2[:, None], n_s, axis=1)
+    return PflowWorkload(f"pflow_d3_exp_{n_flows}flows_{n_s}s_{n_r}r{n_a}a_{n_steps}steps", 3,
+                         REG_EXP, n_r, n_a, 1.0, 6.0, n_s, 49.0, lam3, lam4, sigma0, -4.0, n_steps)
 
 
 @dataclass
