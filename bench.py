@@ -54,10 +54,11 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device-to-device copy of 1 GiB (PMC traffic calibration)")
-    ap.add_argument("--only", choices=["uneven64", "uneven32", "grid32", "tab4096", "tab1m"],
+    ap.add_argument("--only", choices=["uneven64", "uneven32", "grid32", "tab4096", "tab1m", "pflow"],
                     default=None,
                     help="profiling aid: run only --steps persistent launches of the uneven sets "
-                         "(FP64 or FP32C), --steps FP32C scale-up grid calls, or --steps calls "
+                         "(FP64 or FP32C), --steps FP32C scale-up grid calls, --steps momentum-flow "
+                         "solves, or --steps calls "
                          "of the tabulated variant (rows of 4096 or 2^20 nodes), and print "
                          "their timing")
     return ap.parse_args()
@@ -149,6 +150,13 @@ def main():
         sys.exit(2)
     if args.only == "grid32":
         only_grid32(args.steps, args.warmup)
+        return
+    if args.only == "pflow":
+        import torch
+        from paper_2607_24908_amd import frg, workloads
+        ctx = frg.frg_create(0)
+        r = momentum_flow(ctx, frg, workloads, torch, reps=args.steps)
+        print(json.dumps({"only": args.only, **r}), flush=True)
         return
     if args.only in ("tab4096", "tab1m"):
         import torch
@@ -325,8 +333,35 @@ def secondary(ctx, frg, workloads, torch):
         log(f"{name}: fp32c {wk.n_evals / t32:.3e} evals/s, fp64 {wk.n_evals / t64:.3e}, "
             f"max dev {rel:.2e}")
     sec.update(tabulated(ctx, frg, workloads, torch))
+    sec["momentum_flow"] = momentum_flow(ctx, frg, workloads, torch)
     sec["serving"] = serving(frg, workloads)
     return sec
+
+
+def momentum_flow(ctx, frg, workloads, torch, reps=3):
+    """Momentum-dependent two-point flows: 64 flows x 256 momentum nodes,
+    128 x 32 rule, 100 RK4 steps (400 right-hand sides, each one tabulated
+    diagram over all flows and nodes plus the table / tadpole and stage
+    kernels), all on the device; time per whole solve."""
+    w = workloads.pflow_d3()
+    pf = frg.make_pflow(w.d, w.reg, w.n_r, w.n_a, w.lam, w.kappa, w.n_s, w.s_max)
+    l3 = torch.as_tensor(w.lam3, device="cuda")
+    l4 = torch.as_tensor(w.lam4, device="cuda")
+    S0 = torch.as_tensor(w.sigma0, device="cuda")
+    S = torch.empty_like(S0)
+    tr = torch.empty(w.n_flows, dtype=torch.float64, device="cuda")
+
+    def run():
+        S.copy_(S0)
+        frg.frg_pflow_solve(ctx, pf, l3, l4, w.t_end, w.n_steps, S, tr)
+
+    t = timed(run, torch, reps)
+    reached = int((tr == w.t_end).sum().item())
+    log(f"momentum flow {w.name}: {t * 1e3:.2f} ms per solve, {w.n_evals / t:.3e} evals/s, "
+        f"{reached}/{w.n_flows} flows to t_end")
+    return {"workload": w.name, "ms_per_solve": t * 1e3, "evals_per_solve": w.n_evals,
+            "evals_per_s": w.n_evals / t, "rhs_per_s": 4 * w.n_steps / t,
+            "flows_to_t_end": reached, "flows": w.n_flows}
 
 
 def tabulated(ctx, frg, workloads, torch, which=(4096, 1 << 20), reps=None, steps_only=False):

@@ -585,6 +585,12 @@ int Ctx::tab_launch(TabArgs a, int reg, hipStream_t st) {
     a.pw = (int)std::max<int64_t>(1, std::min<int64_t>(a.pw, fit));
   }
   a.n_pb = (int)((n_p + (int64_t)W * a.pw - 1) / ((int64_t)W * a.pw));
+  // rows in LDS: small problems take fewer momenta per wave so that about
+  // four workgroups per CU are in flight
+  while (lds_rows && a.pw > 1 && a.n_rows * a.n_pb < 4LL * n_cu) {
+    a.pw /= 2;
+    a.n_pb = (int)((n_p + (int64_t)W * a.pw - 1) / ((int64_t)W * a.pw));
+  }
   if (a.n_rows * a.n_pb > ((int64_t)1 << 31) - 1) return fail(FRG_E_INVAL, "tabulated problem too large");
   int e = launch_tab(a, reg, W, lds_rows, sblocks, st);
   if (e) return hip_fail((hipError_t)e, "tab_kernel launch");

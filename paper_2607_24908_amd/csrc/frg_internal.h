@@ -149,11 +149,12 @@ struct TabArgs {
 void tab_lane_split(int n_r, int n_a, int *R, int *J, int *T, int *U);
 
 // Momentum-dependent two-point flow (pflow.hip).  State Sigma_r(s_a) of
-// n_rows flows on the nodes s_a = a h_s; one right-hand side at RG time t
-// is: the prep kernel (propagator table g_r[a] = 1/(s_a + R_k(s_a) + Sigma),
-// domain check, tadpole T_r, and the quadrature table at scale k), the
-// tabulated diagram J[a * n_rows + r] at p_a = sqrt(s_a) (tab_kernel), and
-// the stage kernel (rhs = lam3^2 J - lam4/2 T and the RK4 stage update).
+// n_rows flows on the nodes s_a = a h_s.  A right-hand side at RG time t
+// needs the propagator rows g_r[a] = 1/(s_a + R_k(s_a) + Sigma), the domain
+// check, the tadpoles T_r and the quadrature table at scale k (prep), then
+// the tabulated diagram J[a * n_rows + r] at p_a = sqrt(s_a) (tab_kernel),
+// then rhs = lam3^2 J - lam4/2 T and the RK4 stage update (stage kernel,
+// which also does the prep of the next stage).
 struct PflowArgs {
   const double *base;  // QuadTable data at k = 1, q_max = kappa (device)
   double *tabk;        // the same table at scale k (written by the prep kernel)
@@ -169,17 +170,17 @@ struct PflowArgs {
   double *t_reached;
   double *dsdt;        // right-hand side only (stage = 4)
   int *flag;
-  double k, k2, kd2, Cd;  // kd2 = k^(d+2)
+  double k, k2, kd2, Cd;  // scale of the (next) prep, kd2 = k^(d+2)
   double h_s, inv_h, t_last;
-  double t_n, h;        // start of the step, step size
+  double t_n, h;        // start of the step of the (next) prep, step size
   int64_t n_rows, n_s;
   int32_t n_r, n_a;
-  int32_t stage;        // 0..3 RK4 stages, 4: right-hand side only
-  int32_t first;        // prep: read y0 (stage 0 / rhs) instead of ys
+  int32_t stage;        // update: 0..3 RK4 stages, 4: right-hand side only
+  int32_t prep;         // stage kernel: also prepare the next stage (at k, t_n)
 };
 int launch_pflow_init(const PflowArgs &a, double t_end, void *stream);
 int launch_pflow_prep(const PflowArgs &a, int reg, void *stream);
-int launch_pflow_stage(const PflowArgs &a, void *stream);
+int launch_pflow_stage(const PflowArgs &a, int reg, void *stream);
 constexpr int64_t tab_lds_max_nodes = 6144;  // rows up to this many nodes are staged in LDS
 
 

@@ -33,22 +33,12 @@ __global__ __launch_bounds__(256) void pflow_init_kernel(PflowArgs a, double t_e
   if (e < a.n_s) a.p[e] = sqrt((double)e * a.h_s);
 }
 
-// One workgroup per flow: the propagator row, the domain check, the tadpole.
-// Workgroup 0 also writes the quadrature table at scale k for tab_kernel.
+// Table row, domain check and tadpole of flow r at scale a.k for the state
+// `state` (all threads of the workgroup; alive is workgroup-uniform).
 template <int REG>
-__global__ __launch_bounds__(256) void pflow_prep_kernel(PflowArgs a) {
-  const int64_t r = blockIdx.x;
-  const int n_r = a.n_r, n_a = a.n_a;
-  if (r == 0) {
-    for (int i = threadIdx.x; i < n_r; i += blockDim.x) {
-      a.tabk[i] = a.k * a.base[i];
-      a.tabk[n_r + i] = a.kd2 * a.base[n_r + i];
-      a.tabk[2 * n_r + i] = a.k2 * a.base[2 * n_r + i];
-    }
-    for (int j = threadIdx.x; j < 3 * n_a; j += blockDim.x) a.tabk[3 * n_r + j] = a.base[3 * n_r + j];
-  }
-  const bool alive = a.alive[r] != 0;  // workgroup-uniform
-  const double *state = (a.first ? a.y0 : a.ys) + r * a.n_s;
+__device__ __forceinline__ void prep_row(const PflowArgs &a, int64_t r, const double *state,
+                                         bool alive) {
+  const int n_r = a.n_r;
   double *row = a.g + r * a.n_s;
   const double inv_k2 = 1.0 / a.k2;
   bool bad = false;
@@ -84,37 +74,69 @@ __global__ __launch_bounds__(256) void pflow_prep_kernel(PflowArgs a) {
   }
 }
 
-// Right-hand side and RK4 stage update, one thread per (flow, node).
+// The quadrature table at scale a.k for tab_kernel (workgroup 0).
+__device__ __forceinline__ void scale_table(const PflowArgs &a) {
+  const int n_r = a.n_r, n_a = a.n_a;
+  for (int i = threadIdx.x; i < n_r; i += blockDim.x) {
+    a.tabk[i] = a.k * a.base[i];
+    a.tabk[n_r + i] = a.kd2 * a.base[n_r + i];
+    a.tabk[2 * n_r + i] = a.k2 * a.base[2 * n_r + i];
+  }
+  for (int j = threadIdx.x; j < 3 * n_a; j += blockDim.x) a.tabk[3 * n_r + j] = a.base[3 * n_r + j];
+}
+
+// One workgroup per flow: table row, domain check and tadpole of the first
+// stage (state y0), and the quadrature table at scale k.
+template <int REG>
+__global__ __launch_bounds__(256) void pflow_prep_kernel(PflowArgs a) {
+  const int64_t r = blockIdx.x;
+  if (r == 0) scale_table(a);
+  prep_row<REG>(a, r, a.y0 + r * a.n_s, a.alive[r] != 0);
+}
+
+// One workgroup per flow: right-hand side rhs = lam3^2 J - lam4/2 T of the
+// stage just evaluated and its RK4 update (stage 0..3; 4: rhs only), then,
+// if a.prep, the table row, domain check and tadpole of the next stage (at
+// a.k, step start a.t_n; state ys after stages 0..2, y0 after stage 3).
+template <int REG>
 __global__ __launch_bounds__(256) void pflow_stage_kernel(PflowArgs a) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= a.n_rows * a.n_s) return;
-  const int64_t r = e / a.n_s, i = e - r * a.n_s;
-  if (!a.alive[r]) {
-    if (a.stage == 4) a.dsdt[e] = __builtin_nan("");
-    return;
+  const int64_t r = blockIdx.x;
+  const int64_t ns = a.n_s;
+  const bool alive = a.alive[r] != 0;  // workgroup-uniform
+  if (alive) {
+    const double l3 = a.lam3[r];
+    const double c4 = 0.5 * a.lam4[r] * a.T[r];
+    for (int64_t i = threadIdx.x; i < ns; i += blockDim.x) {
+      const int64_t e = r * ns + i;
+      const double rhs = l3 * l3 * a.J[i * a.n_rows + r] - c4;
+      switch (a.stage) {
+        case 0:
+          a.acc[e] = rhs;
+          a.ys[e] = a.y0[e] + (0.5 * a.h) * rhs;
+          break;
+        case 1:
+          a.acc[e] += 2.0 * rhs;
+          a.ys[e] = a.y0[e] + (0.5 * a.h) * rhs;
+          break;
+        case 2:
+          a.acc[e] += 2.0 * rhs;
+          a.ys[e] = a.y0[e] + a.h * rhs;
+          break;
+        case 3:
+          a.y0[e] += (a.h / 6.0) * (a.acc[e] + rhs);
+          break;
+        default:
+          a.dsdt[e] = rhs;
+          break;
+      }
+    }
+  } else if (a.stage == 4) {
+    for (int64_t i = threadIdx.x; i < ns; i += blockDim.x) a.dsdt[r * ns + i] = __builtin_nan("");
   }
-  const double l3 = a.lam3[r];
-  const double rhs = l3 * l3 * a.J[i * a.n_rows + r] - 0.5 * a.lam4[r] * a.T[r];
-  switch (a.stage) {
-    case 0:
-      a.acc[e] = rhs;
-      a.ys[e] = a.y0[e] + (0.5 * a.h) * rhs;
-      break;
-    case 1:
-      a.acc[e] += 2.0 * rhs;
-      a.ys[e] = a.y0[e] + (0.5 * a.h) * rhs;
-      break;
-    case 2:
-      a.acc[e] += 2.0 * rhs;
-      a.ys[e] = a.y0[e] + a.h * rhs;
-      break;
-    case 3:
-      a.y0[e] += (a.h / 6.0) * (a.acc[e] + rhs);
-      break;
-    default:
-      a.dsdt[e] = rhs;
-      break;
-  }
+  if (!a.prep) return;  // kernel-uniform
+  __syncthreads();      // the row's new state is complete
+  if (r == 0) scale_table(a);
+  prep_row<REG>(a, r, (a.stage == 3 ? a.y0 : a.ys) + r * ns, alive);
 }
 
 }  // namespace
@@ -138,11 +160,14 @@ int launch_pflow_prep(const PflowArgs &a, int reg, void *stream) {
   return (int)hipGetLastError();
 }
 
-int launch_pflow_stage(const PflowArgs &a, void *stream) {
-  const int64_t n = a.n_rows * a.n_s;
-  if (n <= 0) return 0;
-  hipLaunchKernelGGL(pflow_stage_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                     (hipStream_t)stream, a);
+int launch_pflow_stage(const PflowArgs &a, int reg, void *stream) {
+  if (a.n_rows <= 0) return 0;
+  if (reg == kExp)
+    hipLaunchKernelGGL(pflow_stage_kernel<kExp>, dim3((unsigned)a.n_rows), dim3(256), 0,
+                       (hipStream_t)stream, a);
+  else
+    hipLaunchKernelGGL(pflow_stage_kernel<kLitim>, dim3((unsigned)a.n_rows), dim3(256), 0,
+                       (hipStream_t)stream, a);
   return (int)hipGetLastError();
 }
 

@@ -103,35 +103,48 @@ int Ctx::pflow_device(const frg_pflow &pf, int64_t n, const double *lam3, const 
   tb.n_s = ns;
   tb.n_r = pf.n_radial;
   tb.n_a = pf.n_angular;
-  auto rhs_at = [&](double t, int stage, int first) -> int {
+  auto set_scale = [&](double t, double tn) {
     a.k = pf.lambda * std::exp(t);
     a.k2 = a.k * a.k;
     a.kd2 = std::pow(a.k, pf.d + 2);
-    a.stage = stage;
-    a.first = first;
-    int r = launch_pflow_prep(a, pf.reg, st);
-    if (r) return hip_fail((hipError_t)r, "pflow_prep_kernel launch");
+    a.t_n = tn;
     tb.k2 = a.k2;
-    r = tab_launch(tb, pf.reg, st);
+  };
+  // prep of the first stage, then per stage: diagram, update (+ next prep)
+  auto first_prep = [&](double t, double tn) -> int {
+    set_scale(t, tn);
+    int r = launch_pflow_prep(a, pf.reg, st);
+    return r ? hip_fail((hipError_t)r, "pflow_prep_kernel launch") : FRG_OK;
+  };
+  auto stage_step = [&](int stage, bool prep_next, double t_next, double tn_next) -> int {
+    int r = tab_launch(tb, pf.reg, st);
     if (r) return r;
-    r = launch_pflow_stage(a, st);
-    if (r) return hip_fail((hipError_t)r, "pflow_stage_kernel launch");
-    return FRG_OK;
+    a.stage = stage;
+    a.prep = prep_next ? 1 : 0;
+    if (prep_next) set_scale(t_next, tn_next);
+    r = launch_pflow_stage(a, pf.reg, st);
+    return r ? hip_fail((hipError_t)r, "pflow_stage_kernel launch") : FRG_OK;
   };
   rc = launch_pflow_init(a, solve ? t_end : t_rhs, st);
   if (rc) rc = hip_fail((hipError_t)rc, "pflow_init_kernel launch");
   if (!rc && !solve) {
-    a.t_n = t_rhs;
-    rc = rhs_at(t_rhs, 4, 1);
+    rc = first_prep(t_rhs, t_rhs);
+    if (!rc) rc = stage_step(4, false, 0.0, 0.0);
   }
   if (!rc && solve) {
     const double hh = t_end / (double)n_steps;
     const double cs[4] = {0.0, 0.5, 0.5, 1.0};
     a.h = hh;
+    rc = first_prep(0.0, 0.0);
     for (int64_t step = 0; step < n_steps && !rc; ++step) {
       const double tn = (double)step * hh;
-      a.t_n = tn;
-      for (int s = 0; s < 4 && !rc; ++s) rc = rhs_at(tn + cs[s] * hh, s, s == 0);
+      for (int s = 0; s < 4 && !rc; ++s) {
+        // the stage after (step, s): (step, s + 1), or (step + 1, 0)
+        const bool last = s == 3 && step + 1 == n_steps;
+        const double tn_next = s < 3 ? tn : (double)(step + 1) * hh;
+        const double t_next = s < 3 ? tn + cs[s + 1] * hh : tn_next;
+        rc = stage_step(s, !last, t_next, tn_next);
+      }
     }
   }
   (void)hipFreeAsync(buf, st);
