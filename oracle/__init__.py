@@ -63,6 +63,10 @@ def lib():
         L.oracle_lpa_rhs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                      ctypes.c_double, ctypes.c_double, ctypes.c_long,
                                      ctypes.c_double, dp, dp, dp]
+        L.oracle_integrate_vertex.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                              ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                              ctypes.c_int, ctypes.c_long, dp, dp, dp, dp, dp,
+                                              ctypes.c_int]
         ip = ctypes.POINTER(ctypes.c_int)
         L.oracle_pflow_rhs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_int, ctypes.c_int,
@@ -175,6 +179,26 @@ def lpa_rhs(d, N, reg, n_r, q_max_over_k, k, rho_max, U, jacobian=True, allow_do
     if rc == E_INVAL or (rc == E_DOMAIN and not allow_domain):
         raise ValueError(f"oracle_lpa_rhs rc={rc}")
     return dUdt, jac, rc
+
+
+def integrate_vertex(d, reg, k, q_max, n_r, n_a, n_phi, p1, p2, c12, m2, threads=1,
+                     allow_domain=False):
+    """Vertex diagram V(p1, p2, th, m^2) = int d^dq/(2pi)^d d_tR G(q^2)^2
+    G(|q+p1|^2) G(|q+p2|^2) for independent points (p1[e], p2[e], c12[e] =
+    cos th, m2[e]): radial and polar rules as for I, Gauss-Legendre in the
+    azimuth phi on [0, pi] with weight sin^{d-3} phi, prefactor
+    Omega_{d-2}/(2pi)^d."""
+    p1 = _f64(p1).ravel()
+    p2 = _f64(p2).ravel()
+    c12 = _f64(c12).ravel()
+    m2 = _f64(m2).ravel()
+    out = np.empty_like(p1)
+    rc = lib().oracle_integrate_vertex(int(d), int(reg), float(k), float(q_max), int(n_r),
+                                       int(n_a), int(n_phi), p1.size, _ptr(p1), _ptr(p2),
+                                       _ptr(c12), _ptr(m2), _ptr(out), int(threads))
+    if rc == E_INVAL or (rc == E_DOMAIN and not allow_domain):
+        raise ValueError(f"oracle_integrate_vertex rc={rc}")
+    return out
 
 
 def pflow_rhs(d, reg, Lam, kappa, n_r, n_a, s_max, lam3, lam4, t, Sigma, threads=1,

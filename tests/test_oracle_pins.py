@@ -542,3 +542,98 @@ def test_pflow_domain_stops():
     assert np.array_equal(alone[0], S[1]) and tr1[0] == -2.0
     _, dead = oracle.pflow_rhs(*args, lam3, lam4, 0.0, S0, allow_domain=True)
     assert list(dead) == [1, 0, 0]
+
+
+# ------------------------------------------------------- vertex diagram (f3) --
+
+def _exp_parts(k, m2):
+    """Continuum integrand pieces written from the regulator's definition
+    (R = s/(e^{s/k^2} - 1), d_tR = k dR/dk), independent of the oracle."""
+    def dtR(s):
+        y = s / k ** 2
+        if y == 0.0:
+            return 2.0 * k * k
+        return 2.0 * s * math.exp(y) * y / math.expm1(y) ** 2
+
+    def G(s):
+        y = s / k ** 2
+        R = s / math.expm1(y) if y > 0 else k * k
+        return 1.0 / (s + R + m2)
+    return dtR, G
+
+
+@pytest.mark.parametrize("d,n_ang,rtol", [(3, 4, 1e-14), (5, 24, 1e-12)])
+def test_vertex_litim_zero_momenta_closed_form(d, n_ang, rtol):
+    """Litim, p1 = p2 = 0: every propagator is 1/(k^2 + m^2) inside the
+    support, V = C_d (2/d) k^(d+2)/(k^2 + m^2)^4 (d = 3: both angular weights
+    are 1, the rule is exact; d = 5: (1 - x^2) is exact, sin^2 phi converges)."""
+    k, m2 = 1.3, np.array([0.2, -0.5, 4.0])
+    v = oracle.integrate_vertex(d, REG_LITIM, k, 6 * k, 8, n_ang, n_ang, np.zeros(3), np.zeros(3),
+                                [0.3, -1.0, 1.0], m2)
+    want = closed_Cd(d) * (2.0 / d) * k ** (d + 2) / (k * k + m2) ** 4
+    np.testing.assert_allclose(v, want, rtol=rtol)
+
+
+@pytest.mark.parametrize("p1,p2,ct", [(0.7, 1.3, 0.25), (2.0, 0.5, -0.8), (1.1, 1.1, -0.5)])
+def test_vertex_matches_continuum_d3(p1, p2, ct):
+    """d = 3, exponential regulator, generic configurations: the product
+    rule converges spectrally to the continuum integral over (q, x, phi)
+    (scipy tplquad of the integrand written from the definitions)."""
+    k, m2 = 1.0, 0.3
+    dtR, G = _exp_parts(k, m2)
+    st = math.sqrt(1 - ct * ct)
+
+    def f(phi, x, q):
+        s1 = q * q + p1 * p1 + 2 * q * p1 * x
+        s2 = q * q + p2 * p2 + 2 * q * p2 * (x * ct + math.sqrt(1 - x * x) * math.cos(phi) * st)
+        return q * q * dtR(q * q) * G(q * q) ** 2 * G(s1) * G(s2)
+
+    val, _ = integrate.tplquad(f, 0, 6 * k, -1, 1, 0, PI, epsabs=1e-14, epsrel=1e-12)
+    want = 2.0 / (2 * PI) ** 3 * val
+    got = oracle.integrate_vertex(3, REG_EXP, k, 6 * k, 64, 32, 32, [p1], [p2], [ct], [m2])[0]
+    assert abs(got - want) <= 1e-11 * want
+
+
+def test_vertex_d4_converges_at_third_order():
+    """d = 4: the polar weight sqrt(1 - x^2) taken literally (as for I) gives
+    O(n^-3) convergence to the continuum (scipy tplquad with weights
+    sqrt(1 - x^2) sin phi and prefactor 2 pi/(2 pi)^4)."""
+    k, m2, p1, p2, ct = 1.0, 0.3, 0.7, 1.3, 0.25
+    dtR, G = _exp_parts(k, m2)
+    st = math.sqrt(1 - ct * ct)
+
+    def f(phi, x, q):
+        s1 = q * q + p1 * p1 + 2 * q * p1 * x
+        s2 = q * q + p2 * p2 + 2 * q * p2 * (x * ct + math.sqrt(1 - x * x) * math.cos(phi) * st)
+        return (q ** 3 * math.sqrt(1 - x * x) * math.sin(phi) * dtR(q * q) * G(q * q) ** 2 * G(s1)
+                * G(s2))
+
+    val, _ = integrate.tplquad(f, 0, 6 * k, -1, 1, 0, PI, epsabs=1e-14, epsrel=1e-11)
+    want = 2 * PI / (2 * PI) ** 4 * val
+    errs = [abs(oracle.integrate_vertex(4, REG_EXP, k, 6 * k, 48, n, n, [p1], [p2], [ct], [m2])[0]
+                - want) / want for n in (16, 32, 64)]
+    for e1, e2 in zip(errs, errs[1:]):
+        assert 6.0 < e1 / e2 < 10.0
+    assert errs[-1] < 3e-6
+
+
+def test_vertex_symmetries():
+    """Swapping p1 and p2 (same angle) is a symmetry of the integral; the rule
+    (tied to p1's axis) reproduces it to rounding once converged.  With
+    p2 = 0 the angle does not enter: the same bits for every cos th."""
+    k, m2 = 1.0, 0.4
+    a = oracle.integrate_vertex(3, REG_EXP, k, 6 * k, 48, 24, 24, [0.7, 1.9], [1.9, 0.7],
+                                [0.1, 0.1], [m2, m2])
+    assert abs(a[0] - a[1]) <= 1e-13 * a[0]
+    v = oracle.integrate_vertex(4, REG_LITIM, k, 6 * k, 16, 8, 8, np.full(3, 0.9), np.zeros(3),
+                                [-1.0, 0.2, 1.0], np.full(3, m2))
+    assert v[0] == v[1] == v[2]
+
+
+def test_vertex_domain():
+    v = oracle.integrate_vertex(3, REG_EXP, 1.0, 6.0, 8, 4, 4, [0.5, -0.1, 0.5, 0.5],
+                                [0.5, 0.5, 0.5, 0.5], [0.2, 0.2, 1.5, 0.2], [0.1, 0.1, 0.1, -1.0],
+                                allow_domain=True)
+    assert np.isfinite(v[0]) and np.all(np.isnan(v[1:]))
+    with pytest.raises(ValueError):
+        oracle.integrate_vertex(3, REG_EXP, 1.0, 6.0, 8, 4, 0, [0.5], [0.5], [0.2], [0.1])
