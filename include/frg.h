@@ -168,6 +168,27 @@ typedef struct {
 int frg_integrate_tab(frg_ctx *ctx, const frg_quad *quad, const frg_gtab *tab, int64_t n_p,
                       const double *p, double *out, int32_t mem, void *hip_stream);
 
+/* ---- two-external-momentum (vertex) diagram -------------------------------- */
+/* One-loop diagram with two external momenta p1, p2 at angle th:
+ *   V(p1, p2, th, m^2) = int d^dq/(2pi)^d d_tR(q^2) G(q^2)^2 G(|q+p1|^2) G(|q+p2|^2),
+ *   G(s) = 1/(s + R_k(s) + m^2),
+ *   |q+p1|^2 = q^2 + p1^2 + 2 q p1 x,
+ *   |q+p2|^2 = q^2 + p2^2 + 2 q p2 (x cos th + sqrt(1 - x^2) cos phi sin th),
+ * with x the polar cosine of q to p1 and phi its azimuth about p1 measured
+ * from the (p1, p2) plane.  Discretised as
+ *   V = Omega_{d-2}/(2pi)^d sum_i sum_j sum_l w_i q_i^{d-1} d_tR(q_i^2) G(q_i^2)^2
+ *         mu_j G(s1_ij) nu_l G(s2_ijl),
+ * the radial and polar rules of frg_set (quad; FP64 only), and n_azimuth
+ * Gauss-Legendre nodes phi_l on [0, pi] with nu_l = (pi/2) w_l sin^{d-3}(phi_l).
+ * Tensor grid of configurations and masses:
+ *   out[c * n_m + b] = V(p1[c], p2[c], acos(cos12[c]), m2[b]).
+ * p1, p2 >= 0, -1 <= cos12 <= 1 and m2 + k^2 > 0, else NaN and FRG_E_DOMAIN
+ * (host memory; device calls are asynchronous and return FRG_OK).  mem says
+ * where p1, p2, cos12, m2 and out live. */
+int frg_integrate_vertex(frg_ctx *ctx, const frg_quad *quad, int32_t n_azimuth, int64_t n_c,
+                         const double *p1, const double *p2, const double *cos12, int64_t n_m,
+                         const double *m2, double *out, int32_t mem, void *hip_stream);
+
 /* ---- momentum-dependent two-point flow ------------------------------------ */
 /* Flow of the momentum-dependent two-point function Gamma2_k(p) = p^2 +
  * Sigma_k(p) of one scalar with constant three- and four-point couplings

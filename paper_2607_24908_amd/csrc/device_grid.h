@@ -263,39 +263,55 @@ namespace dev {
 // Layout (lane-major, like the H' table): group (t, gi), gi < NG, occupies
 // 2G + 2 rows from (t NG + gi)(2G + 2): rows m < G + 2 hold the coefficient
 // of x^m of P, rows G + 2 + m that of x^m of N.
-template <int G>
+// E = number of extra linear factors folded into P (2: (x + Hq)^2 of the
+// two-point diagram; 3: also (x + H1) of the vertex diagram); a group takes
+// 2G + E rows: G + E coefficients of the monic P, G of N.
+template <int G, int E = 2>
 struct FoldShape {
   int NG, rows;
   __host__ __device__ FoldShape(int U, int T) {
     NG = (U + G - 1) / G;
-    rows = T * NG * (2 * G + 2);
+    rows = T * NG * (2 * G + E);
   }
 };
 
-template <int G>
+// (lo, hi) with (2 hi)^(G+E) <= 1e297 and lo^(G+E) >= 1e-290.
+template <int G, int E = 2>
 struct FoldRange;
 template <>
-struct FoldRange<8> {
+struct FoldRange<8, 2> {
   static constexpr double lo = 1e-29, hi = 2e29;
 };
 template <>
-struct FoldRange<16> {
+struct FoldRange<16, 2> {
   static constexpr double lo = 1e-16, hi = 1.5e16;
 };
 template <>
-struct FoldRange<32> {
+struct FoldRange<32, 2> {
   static constexpr double lo = 4e-9, hi = 2.5e8;
 };
+template <>
+struct FoldRange<8, 3> {
+  static constexpr double lo = 5e-27, hi = 4e26;
+};
+template <>
+struct FoldRange<16, 3> {
+  static constexpr double lo = 6e-16, hi = 2e15;
+};
+template <>
+struct FoldRange<32, 3> {
+  static constexpr double lo = 6e-9, hi = 1.5e8;
+};
 
-template <int G>
+template <int G, int E = 2>
 __device__ __forceinline__ bool fold_p_ok(double p, const GridArgs &g) {
   const double qp = g.q_top + p;
-  return g.sig * (qp * qp) <= FoldRange<G>::hi;
+  return g.sig * (qp * qp) <= FoldRange<G, E>::hi;
 }
 
-template <int G>
+template <int G, int E = 2>
 __device__ __forceinline__ bool fold_m_ok(double x) {
-  return x >= FoldRange<G>::lo && x <= FoldRange<G>::hi;
+  return x >= FoldRange<G, E>::lo && x <= FoldRange<G, E>::hi;
 }
 
 // Build the coefficient table of momentum p (all threads of the workgroup;
@@ -383,28 +399,30 @@ __device__ void grid_fill_fold(const GridArgs &g, double *lC, const double *lc, 
 
 // Accumulate, for the masses set in `active`, the lane partials of the
 // coefficient form into tot[m]; xs[m] = sig delta_m.  ALL: every mass active.
-template <int M, int G, bool ALL>
+template <int M, int G, bool ALL, int E = 2>
 __device__ __forceinline__ void grid_fold_rows(const GridArgs &g, const double *lC, int lane,
                                                const double *xs, unsigned active,
-                                               const FoldShape<G> &fs, double *tot) {
+                                               const FoldShape<G, E> &fs, double *tot) {
   const int n_grp = g.T * fs.NG;
   for (int tg = 0; tg < n_grp; ++tg) {
-    const double *src = lC + tg * (2 * G + 2) * kWave + lane;
-    double a[G + 2], b[G];
+    const double *src = lC + tg * (2 * G + E) * kWave + lane;
+    double a[G + E], b[G];
 #pragma unroll
-    for (int m = 0; m < G + 2; ++m) a[m] = src[m * kWave];
+    for (int m = 0; m < G + E; ++m) a[m] = src[m * kWave];
 #pragma unroll
-    for (int m = 0; m < G; ++m) b[m] = src[(G + 2 + m) * kWave];
+    for (int m = 0; m < G; ++m) b[m] = src[(G + E + m) * kWave];
     if constexpr (ALL) {
       // masses in pairs: four independent Horner chains in flight
 #pragma unroll
       for (int m = 0; m < M; m += 2) {
         const double xa = xs[m], xb = xs[m + 1];
-        double Pa = xa + a[G + 1], Pb = xb + a[G + 1];
-        Pa = __builtin_fma(Pa, xa, a[G]);
-        Pb = __builtin_fma(Pb, xb, a[G]);
-        Pa = __builtin_fma(Pa, xa, a[G - 1]);
-        Pb = __builtin_fma(Pb, xb, a[G - 1]);
+        double Pa = xa + a[G + E - 1], Pb = xb + a[G + E - 1];
+        // P has E more coefficients than N: those steps first
+#pragma unroll
+        for (int k = G + E - 2; k >= G - 1; --k) {
+          Pa = __builtin_fma(Pa, xa, a[k]);
+          Pb = __builtin_fma(Pb, xb, a[k]);
+        }
         double Na = b[G - 1], Nb = b[G - 1];
 #pragma unroll
         for (int k = G - 2; k >= 0; --k) {
@@ -422,9 +440,9 @@ __device__ __forceinline__ void grid_fold_rows(const GridArgs &g, const double *
       for (int m = 0; m < M; ++m) {
         if (!((active >> m) & 1u)) continue;
         const double x = xs[m];
-        double P = x + a[G + 1], N = b[G - 1];
-        P = __builtin_fma(P, x, a[G]);
-        P = __builtin_fma(P, x, a[G - 1]);
+        double P = x + a[G + E - 1], N = b[G - 1];
+#pragma unroll
+        for (int k = G + E - 2; k >= G - 1; --k) P = __builtin_fma(P, x, a[k]);
 #pragma unroll
         for (int k = G - 2; k >= 0; --k) {
           P = __builtin_fma(P, x, a[k]);
@@ -515,6 +533,136 @@ __device__ __forceinline__ double wave_sum_fold(const double *v, int lane) {
   x = x + dpp_f64<0x4E>(x);
   x = x + dpp_f64<0x141>(x);
   return x;
+}
+
+// ------------------------------------------------ vertex diagram --
+// Lane rows are (radial, polar) node pairs pi = lane + 64 t (i = pi / n_a,
+// j = pi mod n_a); a group is G azimuthal nodes l of one pair, weights nu_l,
+// H_l = Hk(s2_ijl); with H1 = Hk(s1_ij) the group's share of the result is
+//   c_i mu_j/(Hq_i + x)^2/(H1 + x) sum_l nu_l/(x + H_l) = N(x)/P(x),
+//   P = (x + Hq_i)^2 (x + H1) prod_l (x + H_l)  (monic, degree G + 3),
+//   N = c_i mu_j sum_l nu_l prod_{l' != l}(x + H_l')  (degree G - 1),
+// in the scaled units of the two-point form (N/P carries kap / sig^4).
+template <int REG>
+__device__ __forceinline__ double vertex_s2(double q, double p2, double x, double sx, double cph,
+                                            double ct, double st) {
+  return fmax((q * q + p2 * p2) + (2.0 * q) * p2 * (x * ct + (sx * cph) * st), 0.0);
+}
+
+template <int REG, int G>
+__device__ void vertex_fill(const GridArgs &g, double *lC, const double *lc, const double *lq,
+                            const double *lx, const double *lm, const double *lsx,
+                            const double *lcp, const double *lnu, double p1, double p2, double ct,
+                            double st, const FoldShape<G, 3> &fs) {
+  const double *tq = g.tab;
+  const int n_pairs = g.n_r * g.n_a;
+  const int n_grp = g.T * fs.NG;
+  for (int task = threadIdx.x; task < kWave * n_grp * G; task += blockDim.x) {
+    const int l = task & (kWave - 1);
+    const int rest = task / kWave;
+    const int tg = rest / G, k = rest - tg * G;
+    const int t = tg / fs.NG, gi = tg - t * fs.NG;
+    const int pi = l + kWave * t;
+    const int az = gi * G + k;
+    double H = 0.0;
+    if (pi < n_pairs && az < g.n_phi) {
+      const int i = pi / g.n_a, j = pi - i * g.n_a;
+      const double s2 = vertex_s2<REG>(tq[i], p2, lx[j], lsx[j], lcp[az], ct, st);
+      H = g.sig * hk<REG>(s2, g.k2, g.inv_k2);
+    }
+    lC[(tg * (2 * G + 3) + k) * kWave + l] = H;
+  }
+  __syncthreads();
+  for (int task = threadIdx.x; task < kWave * n_grp; task += blockDim.x) {
+    const int l = task & (kWave - 1);
+    const int tg = task / kWave;
+    const int t = tg / fs.NG, gi = tg - t * fs.NG;
+    const int pi = l + kWave * t;
+    const bool vp = pi < n_pairs;
+    const int i = vp ? pi / g.n_a : 0, j = vp ? pi - i * g.n_a : 0;
+    double *col = lC + tg * (2 * G + 3) * kWave + l;
+    double P[G + 4], N[G];
+#pragma unroll
+    for (int m = 0; m < G + 4; ++m) P[m] = 0.0;
+#pragma unroll
+    for (int m = 0; m < G; ++m) N[m] = 0.0;
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const double H = col[k * kWave];
+      const int az = gi * G + k;
+      const double mu = (vp && az < g.n_phi) ? lnu[az] : 0.0;
+      // N <- N (x + H) + mu P, then P <- P (x + H), as for the two-point form
+      if (k == 0) {
+        N[0] = mu;
+        P[1] = 1.0;
+        P[0] = H;
+      } else {
+        N[k] = __builtin_fma(mu, P[k], N[k - 1]);
+#pragma unroll
+        for (int m = G - 1; m >= 1; --m)
+          if (m < k) N[m] = __builtin_fma(mu, P[m], __builtin_fma(H, N[m], N[m - 1]));
+        N[0] = __builtin_fma(mu, P[0], H * N[0]);
+        P[k + 1] = 1.0;
+#pragma unroll
+        for (int m = G; m >= 1; --m)
+          if (m <= k) P[m] = __builtin_fma(H, P[m], P[m - 1]);
+        P[0] = H * P[0];
+      }
+    }
+    // P <- P (x + Hq)^2 (x + H1), N <- c_i mu_j N
+    double q = 0.0, H1 = 0.0;
+    if (vp) {
+      q = g.tab[i];
+      const double s1 = fmax((q * q + p1 * p1) + (2.0 * q) * p1 * lx[j], 0.0);
+      H1 = g.sig * hk<REG>(s1, g.k2, g.inv_k2);
+    }
+    const double Hq = vp ? g.sig * lq[i] : 0.0;
+    const double c = vp ? (g.kap * lc[i]) * lm[j] : 0.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const double f = r < 2 ? Hq : H1;
+      const int deg = G + r;  // P[deg] = 1
+      P[deg + 1] = 1.0;
+#pragma unroll
+      for (int m = G + 2; m >= 1; --m)
+        if (m <= deg) P[m] = __builtin_fma(f, P[m], P[m - 1]);
+      P[0] = f * P[0];
+    }
+#pragma unroll
+    for (int m = 0; m < G + 3; ++m) col[m * kWave] = P[m];
+#pragma unroll
+    for (int m = 0; m < G; ++m) col[(G + 3 + m) * kWave] = c * N[m];
+  }
+}
+
+// Lane partial of one vertex mass outside the coefficient range: every term
+// on its own.
+template <int REG>
+__device__ __forceinline__ double vertex_single_mass(const GridArgs &g, const double *lc,
+                                                  const double *lq, const double *lx,
+                                                  const double *lm, const double *lsx,
+                                                  const double *lcp, const double *lnu, int lane,
+                                                  double p1, double p2, double ct, double st,
+                                                  double delta) {
+  const int n_pairs = g.n_r * g.n_a;
+  double total = 0.0;
+  for (int t = 0; t < g.T; ++t) {
+    const int pi = lane + kWave * t;
+    if (pi >= n_pairs) break;
+    const int i = pi / g.n_a, j = pi - i * g.n_a;
+    const double q = g.tab[i];
+    const double Gq = rcp64(lq[i] + delta);
+    const double A = (lc[i] * Gq) * Gq;
+    const double s1 = fmax((q * q + p1 * p1) + (2.0 * q) * p1 * lx[j], 0.0);
+    const double G1 = rcp64(hk<REG>(s1, g.k2, g.inv_k2) + delta);
+    double inner = 0.0;
+    for (int az = 0; az < g.n_phi; ++az) {
+      const double s2 = vertex_s2<REG>(q, p2, lx[j], lsx[j], lcp[az], ct, st);
+      inner = __builtin_fma(lnu[az], rcp64(hk<REG>(s2, g.k2, g.inv_k2) + delta), inner);
+    }
+    total = __builtin_fma((A * lm[j]) * G1, inner, total);
+  }
+  return total;
 }
 
 // Lane partial of one mass outside the coefficient range: every term on its

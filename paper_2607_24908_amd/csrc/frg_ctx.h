@@ -126,6 +126,7 @@ struct Context {
   std::map<std::tuple<int, int, uint64_t, uint64_t, int, int>, QEntry> qtabs;
   std::map<std::tuple<int, int, int, uint64_t>, LEntry> ltabs;
   std::map<uint64_t, std::unique_ptr<frg::GraphEntry>> graphs;
+  std::map<std::tuple<int, int, int>, std::unique_ptr<frg::DevBuf>> vtabs;  // (d, n_a, n_phi)
   frg::Server *server = nullptr;
 
   virtual ~Context();
@@ -153,6 +154,10 @@ struct Context {
   int lpa_jobs(int n, const frg_lpa *lpa, const double *t, const double *const *U,
                double *const *dUdt, double *const *jac, int *flags_dev, hipStream_t st);
   void stop_server();
+  // vertex_api.cpp: two-external-momentum diagram on a (configuration x mass) grid
+  int vertex_device(const frg_quad &q, int n_phi, int64_t n_c, const double *p1,
+                    const double *p2, const double *c12, int64_t n_m, const double *m2,
+                    double *out, hipStream_t st);
   // autotune.cpp
   // kind: 0 FP64 grid kernel, 1 compensated-FP32 grid kernel, 2 FP64 redo pass
   int grid_launch(GridArgs g, int reg, const GridCfg &cfg, hipStream_t st, int kind = 0);

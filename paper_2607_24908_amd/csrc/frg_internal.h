@@ -91,7 +91,11 @@ struct GridArgs {
   int32_t mblocks;  // mass blocks per wave when the table is resident
   int32_t form;     // resident FP64 form: 0 coefficients (when they fit; group size from U),
                     // 1 running fractions, 2 / 3 coefficients in groups of 8 / 16
-  double sig, kap, pref_c;  // coefficient form: scale of x and H, of c; pref kap^-1 sig^3
+  double sig, kap, pref_c;  // coefficient form: scale of x and H, of c; pref kap^-1 sig^(E+1)
+  // vertex diagram only: second momentum, cos of the angle, per-config;
+  // vtab = [x_j | sqrt(1 - x_j^2) | cos phi_l | nu_l]
+  const double *p2, *c12, *vtab;
+  int32_t n_phi;
   // compensated-FP32 grid only (Grid32Table on the device, see below)
   const double *tab32;
   double f32_band, f32_flag;  // FP64 below dhat = f32_band; re-done in FP64 above err f32_flag
@@ -201,7 +205,13 @@ constexpr int kGridCoefStageMax = 8192;
 int grid_coef_group(const GridArgs &g);
 int grid_coef_lds_bytes(const GridArgs &g);  // with the largest staging area
 int grid_coef_stage_bytes(int MB, int W, int M);
-void set_fold_scale(GridArgs &g, const QuadTable &h);
+void set_fold_scale(GridArgs &g, const QuadTable &h, int E = 2);
+// Vertex diagram (vertex_kernel): group size from n_phi, LDS bytes of the
+// resident coefficient table (0 if it does not fit), launch.
+int vertex_group(int n_phi);
+int vertex_lds_bytes(const GridArgs &g, int M, int W, bool table);
+int launch_vertex(const GridArgs &g, int reg, int M, int W, void *stream);
+std::vector<double> build_vertex_table(int d, int n_a, int n_phi);
 // Whether the FP64 grid kernel keeps its table resident, and in which form.
 bool grid_uses_coef(const GridArgs &g);
 bool grid_resident(const GridArgs &g);

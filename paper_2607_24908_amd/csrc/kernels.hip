@@ -229,6 +229,93 @@ __global__ __launch_bounds__(512) void grid_kernel(GridArgs g) {
   }
 }
 
+// Stage the masses of one workgroup (blocks of M) in LDS with their masks:
+// lmask[4b..4b+3] = valid, ok (domain), coefficient form, active (REDO:
+// left for FP64 by the compensated-FP32 kernel), ldm[bM + m] = delta.
+template <int M, int G, int E, bool REDO>
+__device__ __forceinline__ void stage_masses(const GridArgs &g, int64_t a, int64_t wg_m0, int nblk,
+                                             bool p_ok, bool table, unsigned *lmask, double *ldm) {
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    unsigned vb = 0, okb = 0, cmb = 0, act = 0;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int64_t idx = wg_m0 + (int64_t)b * M + m;
+      const bool valid = idx < g.n_m;
+      const double d = valid ? g.m2[idx] + g.k2 : 1.0;
+      const bool ok = valid && p_ok && d > 0.0;
+      const double dd = ok ? d : 1.0;
+      ldm[b * M + m] = dd;
+      vb |= valid ? (1u << m) : 0u;
+      okb |= ok ? (1u << m) : 0u;
+      cmb |= (table && fold_m_ok<G, E>(g.sig * dd)) ? (1u << m) : 0u;
+      act |= (!REDO || (valid && g.used64[a * g.n_m + idx] == 1)) ? (1u << m) : 0u;
+    }
+    lmask[4 * b] = vb;
+    lmask[4 * b + 1] = okb;
+    lmask[4 * b + 2] = cmb;
+    lmask[4 * b + 3] = act;
+  }
+}
+
+// The mass blocks of one wave: coefficient form for the masses in range,
+// single(delta) (per-term lane partial) for the others, reduction, store.
+template <int M, int G, int E, bool REDO, class Single>
+__device__ __forceinline__ void coef_blocks(const GridArgs &g, const double *lC,
+                                            const unsigned *lmask, const double *ldm, int64_t a,
+                                            int64_t wg_m0, int MB, int W, int wave, int lane,
+                                            const FoldShape<G, E> &fs, Single single) {
+  const unsigned all = (1u << M) - 1u;
+  for (int rep = 0; rep < MB; ++rep) {
+    const int b = rep * W + wave;
+    const int64_t m0 = wg_m0 + (int64_t)b * M;
+    if (m0 >= g.n_m) break;  // wave-uniform
+    // the masses are the same in every lane: the choices are wave-uniform
+    const unsigned validbits = __builtin_amdgcn_readfirstlane(lmask[4 * b]);
+    const unsigned okbits = __builtin_amdgcn_readfirstlane(lmask[4 * b + 1]);
+    const unsigned cmask = __builtin_amdgcn_readfirstlane(lmask[4 * b + 2]);
+    const unsigned act = __builtin_amdgcn_readfirstlane(lmask[4 * b + 3]);
+    if (REDO && !act) continue;
+    double dm[M], xs[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      dm[m] = ldm[b * M + m];
+      xs[m] = g.sig * dm[m];
+    }
+    double tot[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) tot[m] = 0.0;
+    const unsigned cm = act & cmask;
+    if (cm == all)
+      grid_fold_rows<M, G, true, E>(g, lC, lane, xs, cm, fs, tot);
+    else if (cm)
+      grid_fold_rows<M, G, false, E>(g, lC, lane, xs, cm, fs, tot);
+    const unsigned sm = act & ~cmask;
+    if (sm) {
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+        if ((sm >> m) & 1u) tot[m] = single(dm[m]);
+    }
+    // lane l ends with the total of mass l / (64 / M); the coefficient form
+    // carries the factor kap / sig^(E+1) (folded into pref_c)
+    const double s = wave_sum_fold<M>(tot, lane);
+    const int mine = lane / (kWave / M);
+    const double v = (((cmask >> mine) & 1u) ? g.pref_c : g.pref) * s;
+    const bool okm = (okbits >> mine) & 1u;
+    const bool mine_out = lane % (kWave / M) == 0 && ((validbits >> mine) & 1u);
+    if (REDO) {
+      // the FP32 kernel has already written the other points and the flag
+      if (mine_out && ((act >> mine) & 1u)) {
+        const int64_t o = a * g.n_m + m0 + mine;
+        g.out[o] = okm ? v : __builtin_nan("");
+        if (g.err) g.err[o] = kErr64;
+      }
+      continue;
+    }
+    if ((validbits & ~okbits) && lane == 0) *g.flag = 1;
+    if (mine_out) g.out[a * g.n_m + m0 + mine] = okm ? v : __builtin_nan("");
+  }
+}
+
 // Tensor grid, resident coefficient form (device_grid.h): a workgroup owns
 // one momentum and W * M * MB masses; it builds the per-group coefficients of
 // its momentum once in LDS and every mass evaluates them by Horner.  REDO:
@@ -254,8 +341,7 @@ __global__ __launch_bounds__(512) void grid_coef_kernel(GridArgs g) {
       any |= wg_m0 + idx < g.n_m && g.used64[a * g.n_m + wg_m0 + idx] == 1;
     if (!__syncthreads_or(any)) return;  // workgroup-uniform
   }
-  // LDS: coefficients | per-block masks (valid, ok, coefficient form,
-  // active) | masses delta | c_i | Hq_i | mu_j
+  // LDS: coefficients | per-block masks | masses delta | c_i | Hq_i | mu_j
   const FoldShape<G> fs(g.U, g.T);
   double *lC = lds;
   unsigned *lmask = reinterpret_cast<unsigned *>(lC + fs.rows * kWave);
@@ -270,79 +356,71 @@ __global__ __launch_bounds__(512) void grid_coef_kernel(GridArgs g) {
   for (int idx = threadIdx.x; idx < n_a; idx += blockDim.x) lm[idx] = g.tab[3 * n_r + n_a + idx];
   const bool p_ok = p >= 0.0;
   const bool table = p_ok && fold_p_ok<G>(p, g);  // workgroup-uniform
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-    unsigned vb = 0, okb = 0, cmb = 0, act = 0;
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-      const int64_t idx = wg_m0 + (int64_t)b * M + m;
-      const bool valid = idx < g.n_m;
-      const double d = valid ? g.m2[idx] + g.k2 : 1.0;
-      const bool ok = valid && p_ok && d > 0.0;
-      const double dd = ok ? d : 1.0;
-      ldm[b * M + m] = dd;
-      vb |= valid ? (1u << m) : 0u;
-      okb |= ok ? (1u << m) : 0u;
-      cmb |= (table && fold_m_ok<G>(g.sig * dd)) ? (1u << m) : 0u;
-      act |= (!REDO || (valid && g.used64[a * g.n_m + idx] == 1)) ? (1u << m) : 0u;
-    }
-    lmask[4 * b] = vb;
-    lmask[4 * b + 1] = okb;
-    lmask[4 * b + 2] = cmb;
-    lmask[4 * b + 3] = act;
-  }
+  stage_masses<M, G, 2, REDO>(g, a, wg_m0, nblk, p_ok, table, lmask, ldm);
   __syncthreads();
   if (table) grid_fill_fold<REG, G>(g, lC, lc, lq, lm, p, fs);
   __syncthreads();
-  const unsigned all = (1u << M) - 1u;
-  for (int rep = 0; rep < MB; ++rep) {
-    const int b = rep * W + wave;
-    const int64_t m0 = wg_m0 + (int64_t)b * M;
-    if (m0 >= g.n_m) break;  // wave-uniform
-    // the masses are the same in every lane: the choices are wave-uniform
-    const unsigned validbits = __builtin_amdgcn_readfirstlane(lmask[4 * b]);
-    const unsigned okbits = __builtin_amdgcn_readfirstlane(lmask[4 * b + 1]);
-    const unsigned cmask = __builtin_amdgcn_readfirstlane(lmask[4 * b + 2]);
-    const unsigned act = __builtin_amdgcn_readfirstlane(lmask[4 * b + 3]);
-    if (REDO && !act) continue;
-    double dm[M], xs[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-      dm[m] = ldm[b * M + m];
-      xs[m] = g.sig * dm[m];
-    }
-    double tot[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) tot[m] = 0.0;
-    const unsigned cm = act & cmask;
-    if (cm == all)
-      grid_fold_rows<M, G, true>(g, lC, lane, xs, cm, fs, tot);
-    else if (cm)
-      grid_fold_rows<M, G, false>(g, lC, lane, xs, cm, fs, tot);
-    const unsigned sm = act & ~cmask;
-    if (sm) {
-#pragma unroll
-      for (int m = 0; m < M; ++m)
-        if ((sm >> m) & 1u) tot[m] = grid_single_mass<REG>(g, lc, lq, lm, lane, p, dm[m]);
-    }
-    // lane l ends with the total of mass l / (64 / M); the coefficient form
-    // carries the factor kap / sig^3 (folded into pref_c)
-    const double s = wave_sum_fold<M>(tot, lane);
-    const int mine = lane / (kWave / M);
-    const double v = (((cmask >> mine) & 1u) ? g.pref_c : g.pref) * s;
-    const bool okm = (okbits >> mine) & 1u;
-    const bool mine_out = lane % (kWave / M) == 0 && ((validbits >> mine) & 1u);
-    if (REDO) {
-      // the FP32 kernel has already written the other points and the flag
-      if (mine_out && ((act >> mine) & 1u)) {
-        const int64_t o = a * g.n_m + m0 + mine;
-        g.out[o] = okm ? v : __builtin_nan("");
-        if (g.err) g.err[o] = kErr64;
-      }
-      continue;
-    }
-    if ((validbits & ~okbits) && lane == 0) *g.flag = 1;
-    if (mine_out) g.out[a * g.n_m + m0 + mine] = okm ? v : __builtin_nan("");
+  coef_blocks<M, G, 2, REDO>(g, lC, lmask, ldm, a, wg_m0, MB, W, wave, lane, fs,
+                             [&](double delta) {
+                               return grid_single_mass<REG>(g, lc, lq, lm, lane, p, delta);
+                             });
+}
+
+// Vertex diagram on a tensor grid (configurations x masses): a workgroup owns
+// one configuration (p1, p2, cos th) and W * M * MB masses.  Lane rows are
+// (radial, polar) node pairs, groups are azimuthal nodes; P carries the
+// extra factor (x + H1) of G(|q + p1|) (device_grid.h, vertex section).
+// g.form == 1: no coefficient table (every mass per term).
+template <int REG, int M, int G>
+__global__ __launch_bounds__(512) void vertex_kernel(GridArgs g) {
+  extern __shared__ double lds[];
+  const int W = blockDim.x / kWave;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t a = blockIdx.x / g.n_mb;
+  const int mb = (int)(blockIdx.x - a * g.n_mb);
+  const double p1 = g.p[a], p2 = g.p2[a], ct = g.c12[a];
+  const int n_r = g.n_r, n_a = g.n_a, n_phi = g.n_phi;
+  const int MB = g.mblocks;
+  const int nblk = MB * W;
+  const int64_t wg_m0 = (int64_t)mb * nblk * M;
+  const FoldShape<G, 3> fs(g.U, g.T);
+  const bool table_form = g.form != 1;
+  double *lC = lds;
+  unsigned *lmask = reinterpret_cast<unsigned *>(lC + (table_form ? fs.rows * kWave : 0));
+  double *ldm = reinterpret_cast<double *>(lmask + 4 * nblk);
+  double *lc = ldm + nblk * M;  // c_i
+  double *lq = lc + n_r;        // Hq_i
+  double *lx = lq + n_r;        // x_j
+  double *lm = lx + n_a;        // mu_j
+  double *lsx = lm + n_a;       // sqrt(1 - x_j^2)
+  double *lcp = lsx + n_a;      // cos phi_l
+  double *lnu = lcp + n_phi;    // nu_l
+  for (int idx = threadIdx.x; idx < n_r; idx += blockDim.x) {
+    lc[idx] = g.tab[n_r + idx];
+    lq[idx] = g.tab[2 * n_r + idx];
   }
+  for (int idx = threadIdx.x; idx < n_a; idx += blockDim.x) {
+    lx[idx] = g.vtab[idx];
+    lm[idx] = g.tab[3 * n_r + n_a + idx];
+    lsx[idx] = g.vtab[n_a + idx];
+  }
+  for (int idx = threadIdx.x; idx < n_phi; idx += blockDim.x) {
+    lcp[idx] = g.vtab[2 * n_a + idx];
+    lnu[idx] = g.vtab[2 * n_a + n_phi + idx];
+  }
+  const bool p_ok = p1 >= 0.0 && p2 >= 0.0 && ct >= -1.0 && ct <= 1.0;
+  const double st = p_ok ? sqrt((1.0 - ct) * (1.0 + ct)) : 0.0;
+  const bool table = table_form && p_ok && fold_p_ok<G, 3>(fmax(p1, p2), g);
+  stage_masses<M, G, 3, false>(g, a, wg_m0, nblk, p_ok, table, lmask, ldm);
+  __syncthreads();
+  if (table) vertex_fill<REG, G>(g, lC, lc, lq, lx, lm, lsx, lcp, lnu, p1, p2, ct, st, fs);
+  __syncthreads();
+  coef_blocks<M, G, 3, false>(g, lC, lmask, ldm, a, wg_m0, MB, W, wave, lane, fs,
+                              [&](double delta) {
+                                return vertex_single_mass<REG>(g, lc, lq, lx, lm, lsx, lcp, lnu,
+                                                               lane, p1, p2, ct, st, delta);
+                              });
 }
 
 // Coefficient of U[j+o] in U' (c1) and U'' (c2) of the difference formulas.
@@ -499,7 +577,7 @@ int grid_coef_lds_bytes(const GridArgs &g) {
 
 int grid_coef_stage_bytes(int MB, int W, int M) { return MB * W * (16 + 8 * M); }
 
-void set_fold_scale(GridArgs &g, const QuadTable &h) {
+void set_fold_scale(GridArgs &g, const QuadTable &h, int E) {
   int e_k, e_c;
   (void)std::frexp(h.k2, &e_k);  // k2 = f 2^e_k, f in [1/2, 1)
   double cmax = 0.0;
@@ -510,9 +588,11 @@ void set_fold_scale(GridArgs &g, const QuadTable &h) {
     e_c = 0;
   g.sig = std::ldexp(1.0, 1 - e_k);
   g.kap = std::ldexp(1.0, -e_c);
-  // N/P carries kap / sig^3
-  g.pref_c = std::ldexp(h.pref, 3 * (1 - e_k) + e_c);
+  // N/P carries kap / sig^(E+1) (g.pref: the prefactor of the diagram)
+  g.pref_c = std::ldexp(g.pref, (E + 1) * (1 - e_k) + e_c);
 }
+
+
 
 // Ask for dynamic LDS beyond 64 KiB for one kernel (gfx950: 160 KiB per
 // workgroup).  The runtime may refuse the request where no opt-in is needed;
@@ -520,6 +600,52 @@ void set_fold_scale(GridArgs &g, const QuadTable &h) {
 static void allow_large_lds(const void *fn) {
   (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   (void)hipGetLastError();
+}
+
+int vertex_group(int n_phi) { return n_phi <= 8 ? 8 : n_phi <= 16 ? 16 : 32; }
+
+static int vertex_rows(const GridArgs &g) {
+  const int G = vertex_group(g.n_phi);
+  return G == 32 ? FoldShape<32, 3>(g.U, g.T).rows
+                 : G == 16 ? FoldShape<16, 3>(g.U, g.T).rows : FoldShape<8, 3>(g.U, g.T).rows;
+}
+
+// LDS of vertex_kernel: coefficient table (if resident) | masks and masses |
+// c, Hq | x, mu, sqrt(1 - x^2) | cos phi, nu.
+int vertex_lds_bytes(const GridArgs &g, int M, int W, bool table) {
+  return (int)sizeof(double) * ((table ? vertex_rows(g) * kWave : 0) + 2 * g.n_r + 3 * g.n_a +
+                                2 * g.n_phi) +
+         grid_coef_stage_bytes(g.mblocks, W, M);
+}
+
+template <int REG, int M, int G>
+static void vertex_launch_t(const GridArgs &g, int W, hipStream_t st) {
+  static const bool once = (allow_large_lds((const void *)&vertex_kernel<REG, M, G>), true);
+  (void)once;
+  hipLaunchKernelGGL((vertex_kernel<REG, M, G>), dim3((unsigned)(g.n_p * g.n_mb)),
+                     dim3(kWave * W), vertex_lds_bytes(g, M, W, g.form != 1), st, g);
+}
+
+template <int REG, int M>
+static void vertex_launch_m(const GridArgs &g, int W, hipStream_t st) {
+  const int G = vertex_group(g.n_phi);
+  if (G == 32)
+    vertex_launch_t<REG, M, 32>(g, W, st);
+  else if (G == 16)
+    vertex_launch_t<REG, M, 16>(g, W, st);
+  else
+    vertex_launch_t<REG, M, 8>(g, W, st);
+}
+
+int launch_vertex(const GridArgs &g, int reg, int M, int W, void *stream) {
+  if (g.n_p <= 0 || g.n_m <= 0) return 0;
+  hipStream_t st = (hipStream_t)stream;
+  if (M != 4 && M != 8) return (int)hipErrorInvalidValue;
+  if (reg == kExp)
+    M == 8 ? vertex_launch_m<kExp, 8>(g, W, st) : vertex_launch_m<kExp, 4>(g, W, st);
+  else
+    M == 8 ? vertex_launch_m<kLitim, 8>(g, W, st) : vertex_launch_m<kLitim, 4>(g, W, st);
+  return (int)hipGetLastError();
 }
 
 template <int REG, int M, int G>

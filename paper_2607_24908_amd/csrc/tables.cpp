@@ -233,6 +233,26 @@ LpaTable build_lpa_table(int d, int reg, int n_r, double q_max_over_k) {
   return t;
 }
 
+// Angular data of the vertex diagram: [x_j | sqrt(1 - x_j^2) | cos phi_l |
+// nu_l], x_j the polar Gauss-Legendre nodes (as in build_quad_table),
+// phi_l the Gauss-Legendre nodes on [0, pi] and nu_l = (pi/2) w_l sin^{d-3}(phi_l).
+std::vector<double> build_vertex_table(int d, int n_a, int n_phi) {
+  std::vector<double> xa(n_a), wa(n_a), xp(n_phi), wp(n_phi);
+  gauss_legendre_gw(n_a, xa.data(), wa.data());
+  gauss_legendre_gw(n_phi, xp.data(), wp.data());
+  std::vector<double> t(2 * n_a + 2 * n_phi);
+  for (int j = 0; j < n_a; ++j) {
+    t[j] = xa[j];
+    t[n_a + j] = std::sqrt((1.0 - xa[j]) * (1.0 + xa[j]));
+  }
+  for (int l = 0; l < n_phi; ++l) {
+    const double f = 0.5 * M_PI * (1.0 + xp[l]);
+    t[2 * n_a + l] = std::cos(f);
+    t[2 * n_a + n_phi + l] = 0.5 * M_PI * wp[l] * std::pow(std::sin(f), d - 3);
+  }
+  return t;
+}
+
 void lane_split(int n_r, int n_a, int *R, int *J, int *T, int *U) {
   int r = 1;
   while (r * 2 <= n_r && r * 2 <= kWave) r *= 2;

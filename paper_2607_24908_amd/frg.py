@@ -29,7 +29,8 @@ STATUS_NAMES = {0: "FRG_OK", 1: "FRG_PENDING", -1: "FRG_E_INVAL", -2: "FRG_E_DOM
                 -6: "FRG_E_NOTFOUND", -7: "FRG_E_STEP"}
 
 EXPORTS = ["frg_create", "frg_destroy", "frg_last_error", "frg_version", "frg_integrate",
-           "frg_integrate_grid", "frg_integrate_tab", "frg_pflow_rhs", "frg_pflow_solve",
+           "frg_integrate_grid", "frg_integrate_tab", "frg_integrate_vertex", "frg_pflow_rhs",
+           "frg_pflow_solve",
            "frg_flow_rhs", "frg_flow_rhs_batch", "frg_flow_solve",
            "frg_submit", "frg_poll", "frg_server_stats", "frg_gauss_legendre",
            "frg_flow_footprint", "frg_autotune", "frg_tune_set", "frg_tune_get"]
@@ -116,6 +117,8 @@ def _load():
                                      i32, vp]
     L.frg_integrate_tab.argtypes = [vp, ctypes.POINTER(frg_quad), ctypes.POINTER(frg_gtab), i64,
                                     vp, vp, i32, vp]
+    L.frg_integrate_vertex.argtypes = [vp, ctypes.POINTER(frg_quad), i32, i64, vp, vp, vp, i64,
+                                       vp, vp, i32, vp]
     L.frg_pflow_rhs.argtypes = [vp, ctypes.POINTER(frg_pflow), i64, vp, vp, dbl, vp, vp, i32, vp]
     L.frg_pflow_solve.argtypes = [vp, ctypes.POINTER(frg_pflow), i64, vp, vp, dbl, i64, vp, vp,
                                   i32, vp]
@@ -228,6 +231,18 @@ def frg_integrate_tab(ctx, quad, g, s_max, p, out, mem=FRG_MEM_DEVICE, stream=No
     st = 0 if mem == FRG_MEM_HOST else _stream(stream)
     return _check(lib.frg_integrate_tab(ctx, ctypes.byref(quad), ctypes.byref(tab), n_p, _addr(p),
                                         _addr(out), mem, st),
+                  (FRG_E_DOMAIN,) if allow_domain else ())
+
+
+def frg_integrate_vertex(ctx, quad, n_azimuth, p1, p2, cos12, m2, out, mem=FRG_MEM_DEVICE,
+                         stream=None, allow_domain=False):
+    """out[c * n_m + b] = V(p1[c], p2[c], acos(cos12[c]), m2[b])."""
+    n_c = int(p1.numel() if hasattr(p1, "numel") else p1.size)
+    n_m = int(m2.numel() if hasattr(m2, "numel") else m2.size)
+    st = 0 if mem == FRG_MEM_HOST else _stream(stream)
+    return _check(lib.frg_integrate_vertex(ctx, ctypes.byref(quad), int(n_azimuth), n_c,
+                                           _addr(p1), _addr(p2), _addr(cos12), n_m, _addr(m2),
+                                           _addr(out), mem, st),
                   (FRG_E_DOMAIN,) if allow_domain else ())
 
 

@@ -26,6 +26,11 @@ regulator):
   g_r(s) = (1 + 0.1/(1 + s))/(s + M_r), M_r evenly spaced in [0.1, 11] (an input
   standing in for a dressed propagator; nothing of the method is computed).
   n_s = 4096 (rows staged in LDS) and 2^20 (8 MB rows read through the caches).
+* ``vertex_d3`` -- two-external-momentum diagram: d = 3, exponential regulator,
+  k = 1, q_max = 6, 48 radial x 8 polar x 16 azimuthal nodes; 256 momentum
+  configurations (128 at the symmetric point p1 = p2 log-spaced in [1e-3, 10]
+  with cos th = -1/2, 128 with p1, p2 log-uniform in [1e-3, 10] and cos th
+  uniform in [-1, 1]) x 512 masses uniform in [-0.9, 10].
 * ``pflow_d3`` -- momentum-dependent two-point flows: d = 3, exponential
   regulator, Lambda = 1, q_max = 6k, 128 radial x 32 angular nodes, Sigma on
   256 nodes of s in [0, 49] (p up to 7 Lambda), 64 flows with lam3 uniform in
@@ -164,6 +169,36 @@ def tabulated_d3(n_s: int = 4096, n_p: int = 1024, n_rows: int = 64) -> TabWorkl
     s_max = (q.q_max + 20.0) ** 2
     return TabWorkload(f"tabulated_d3_{n_p}p_{n_rows}rows_{n_s}s_128r32a", q, p,
                        tab_rows(n_rows, n_s, s_max), s_max)
+
+
+@dataclass
+class VertexWorkload:
+    name: str
+    quad: Quad
+    n_phi: int
+    p1: np.ndarray
+    p2: np.ndarray
+    c12: np.ndarray
+    m2: np.ndarray
+
+    @property
+    def n_integrals(self) -> int:
+        return self.p1.size * self.m2.size
+
+    @property
+    def n_evals(self) -> int:
+        return self.n_integrals * self.quad.n_r * self.quad.n_a * self.n_phi
+
+
+def vertex_d3(seed: int = 0, n_sym: int = 128, n_rand: int = 128, n_m: int = 512) -> VertexWorkload:
+    rng = _rng(seed)
+    p_sym = np.logspace(-3.0, 1.0, n_sym)
+    p1 = np.concatenate([p_sym, 10.0 ** rng.uniform(-3.0, 1.0, n_rand)])
+    p2 = np.concatenate([p_sym, 10.0 ** rng.uniform(-3.0, 1.0, n_rand)])
+    c12 = np.concatenate([np.full(n_sym, -0.5), rng.uniform(-1.0, 1.0, n_rand)])
+    q = Quad(d=3, reg=REG_EXP, k=1.0, q_max=6.0, n_r=48, n_a=8)
+    return VertexWorkload(f"vertex_d3_exp_{p1.size}c_{n_m}m_48r8x16phi", q, 16, p1, p2, c12,
+                          np.linspace(-0.9, 10.0, n_m))
 
 
 @dataclass
