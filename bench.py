@@ -54,11 +54,12 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device-to-device copy of 1 GiB (PMC traffic calibration)")
-    ap.add_argument("--only", choices=["uneven64", "uneven32", "grid32", "tab4096", "tab1m", "pflow"],
+    ap.add_argument("--only", choices=["uneven64", "uneven32", "grid32", "tab4096", "tab1m", "pflow",
+                                       "vertex"],
                     default=None,
                     help="profiling aid: run only --steps persistent launches of the uneven sets "
                          "(FP64 or FP32C), --steps FP32C scale-up grid calls, --steps momentum-flow "
-                         "solves, or --steps calls "
+                         "solves or vertex-diagram calls, or --steps calls "
                          "of the tabulated variant (rows of 4096 or 2^20 nodes), and print "
                          "their timing")
     return ap.parse_args()
@@ -151,11 +152,12 @@ def main():
     if args.only == "grid32":
         only_grid32(args.steps, args.warmup)
         return
-    if args.only == "pflow":
+    if args.only in ("pflow", "vertex"):
         import torch
         from paper_2607_24908_amd import frg, workloads
         ctx = frg.frg_create(0)
-        r = momentum_flow(ctx, frg, workloads, torch, reps=args.steps)
+        fn = momentum_flow if args.only == "pflow" else vertex
+        r = fn(ctx, frg, workloads, torch, reps=args.steps)
         print(json.dumps({"only": args.only, **r}), flush=True)
         return
     if args.only in ("tab4096", "tab1m"):
@@ -333,9 +335,26 @@ def secondary(ctx, frg, workloads, torch):
         log(f"{name}: fp32c {wk.n_evals / t32:.3e} evals/s, fp64 {wk.n_evals / t64:.3e}, "
             f"max dev {rel:.2e}")
     sec.update(tabulated(ctx, frg, workloads, torch))
+    sec["vertex"] = vertex(ctx, frg, workloads, torch)
     sec["momentum_flow"] = momentum_flow(ctx, frg, workloads, torch)
     sec["serving"] = serving(frg, workloads)
     return sec
+
+
+def vertex(ctx, frg, workloads, torch, reps=20):
+    """Two-external-momentum diagram: 256 configurations x 512 masses, 48 x 8
+    x 16 rule (coefficient form over the azimuthal nodes); the same 2-FMA
+    floor per (term, mass) as the scale-up grid."""
+    w = workloads.vertex_d3()
+    q = w.quad
+    quad = frg.make_quad(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a)
+    args = [torch.as_tensor(a, device="cuda") for a in (w.p1, w.p2, w.c12, w.m2)]
+    out = torch.empty(w.n_integrals, dtype=torch.float64, device="cuda")
+    t = timed(lambda: frg.frg_integrate_vertex(ctx, quad, w.n_phi, *args, out), torch, reps)
+    log(f"vertex {w.name}: {t * 1e3:.3f} ms, {w.n_evals / t:.3e} evals/s")
+    return {"workload": w.name, "ms_per_call": t * 1e3, "evals_per_s": w.n_evals / t,
+            "integrals_per_s": w.n_integrals / t,
+            "frac_of_2op_floor": w.n_evals / t / PEAK_EVALS}
 
 
 def momentum_flow(ctx, frg, workloads, torch, reps=3):

@@ -49,17 +49,20 @@ int Ctx::vertex_device(const frg_quad &q, int n_phi, int64_t n_c, const double *
   g.T = (q.n_radial * q.n_angular + kWave - 1) / kWave;  // (radial, polar) pairs per lane
   g.U = n_phi;
   set_fold_scale(g, h, 3);
-  // launch shape: the grid kernel's (M <= 8), mass blocks so that about four
-  // workgroups per CU are in flight
+  // launch shape: the grid kernel's (M <= 8); mass blocks so that about four
+  // workgroups per CU are in flight -- or one, when the table takes more than
+  // half the LDS (one workgroup per CU can be resident; it gets eight waves,
+  // two per SIMD, and splitting a configuration's masses over more
+  // workgroups would only repeat its table build)
   GridCfg cfg = tune.grid;
   if (cfg.M > 8) cfg.M = 8;
-  // a table of more than half the LDS leaves one workgroup per CU: give it
-  // eight waves (two per SIMD)
   g.mblocks = 1;
-  if (vertex_lds_bytes(g, cfg.M, cfg.W, true) > 80 * 1024) cfg.W = 8;
+  const bool big = vertex_lds_bytes(g, cfg.M, cfg.W, true) > 80 * 1024;
+  if (big) cfg.W = 8;
   const int64_t per_wg = (int64_t)cfg.M * cfg.W;
+  const int64_t want_wgs = (big ? 1LL : 4LL) * n_cu;
   int mbk = std::max(1, cfg.MB);
-  while (mbk > 1 && (n_c * ((n_m + per_wg * mbk - 1) / (per_wg * mbk)) < 4LL * n_cu ||
+  while (mbk > 1 && (n_c * ((n_m + per_wg * mbk - 1) / (per_wg * mbk)) < want_wgs ||
                      grid_coef_stage_bytes(mbk, cfg.W, cfg.M) > kGridCoefStageMax))
     mbk /= 2;
   g.mblocks = mbk;
