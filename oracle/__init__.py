@@ -68,6 +68,14 @@ def lib():
                                               ctypes.c_int, ctypes.c_long, dp, dp, dp, dp, dp,
                                               ctypes.c_int]
         ip = ctypes.POINTER(ctypes.c_int)
+        L.oracle_fvlpa_rhs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_long,
+                                       ctypes.c_long, ctypes.c_double, ctypes.c_double, dp, dp,
+                                       dp, ip]
+        L.oracle_fvlpa_solve.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_long,
+                                         ctypes.c_long, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_long, dp, dp]
         L.oracle_pflow_rhs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_long, ctypes.c_long, ctypes.c_double, dp, dp,
@@ -242,6 +250,38 @@ def pflow_solve(d, reg, Lam, kappa, n_r, n_a, s_max, lam3, lam4, t_end, n_steps,
     if rc == E_INVAL:
         raise ValueError("oracle_pflow_solve: invalid arguments")
     return S, t_reached
+
+
+def fvlpa_rhs(d, N, reg, n_r, Lam, kappa, sigma_max, t, u, allow_domain=False):
+    """Finite-volume LPA right-hand side d_t u_i = (Q_{i+1} - Q_i)/ds for
+    u = dU/dsigma cell averages of shape (n_flows, n) (flux definitions in
+    frg_oracle.c).  Returns (dudt, dt_estimate, dead)."""
+    U = np.ascontiguousarray(np.asarray(u, dtype=np.float64))
+    if U.ndim != 2:
+        raise ValueError("u must be (n_flows, n)")
+    out = np.empty_like(U)
+    dt = np.empty(U.shape[0])
+    dead = np.zeros(U.shape[0], dtype=np.int32)
+    rc = lib().oracle_fvlpa_rhs(int(d), int(N), int(reg), int(n_r), float(Lam), float(kappa),
+                                U.shape[0], U.shape[1], float(sigma_max), float(t), _ptr(U),
+                                _ptr(out), _ptr(dt),
+                                dead.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    if rc == E_INVAL or (rc == E_DOMAIN and not allow_domain):
+        raise ValueError(f"oracle_fvlpa_rhs rc={rc}")
+    return out, dt, dead
+
+
+def fvlpa_solve(d, N, reg, n_r, Lam, kappa, sigma_max, t_end, n_steps, u0):
+    """Three-stage SSP Runge-Kutta integration of the finite-volume LPA from
+    t = 0 to t_end; returns (u(t_end), t_reached)."""
+    U = np.array(u0, dtype=np.float64, copy=True, order="C")
+    tr = np.empty(U.shape[0])
+    rc = lib().oracle_fvlpa_solve(int(d), int(N), int(reg), int(n_r), float(Lam), float(kappa),
+                                  U.shape[0], U.shape[1], float(sigma_max), float(t_end),
+                                  int(n_steps), _ptr(U), _ptr(tr))
+    if rc == E_INVAL:
+        raise ValueError("oracle_fvlpa_solve: invalid arguments")
+    return U, tr
 
 
 def Omega(n: int) -> float:

@@ -79,6 +79,31 @@
  *   domain boundary at any stage of step n keeps its state at t_n and
  *   reports t_n as the time reached.
  *
+ *   Finite-volume LPA (O(N), field amplitude sigma, u = dU/dsigma): with
+ *   rho = sigma^2/2 the LPA flow below becomes the conservation law
+ *     d_t u = d_sigma Q,  Q = 1/2 F_1(d_sigma u) + (N-1)/2 F_1(u/sigma).
+ *   Cells i = 0..n-1 of width ds = sigma_max/n hold averages u_i; interface
+ *   j = 0..n sits at sigma_j = j ds between cells j-1 and j; ghost cells
+ *   u_{-1} = -u_0, u_{-2} = -u_1 (u odd in sigma) and u_n = 2 u_{n-1} - u_{n-2},
+ *   u_{n+1} = 2 u_n - u_{n-1} (linear extrapolation).  Piecewise-linear
+ *   reconstruction with minmod slopes, s_i = minmod(u_i - u_{i-1}, u_{i+1} - u_i)
+ *   (minmod(a, b) = 0 if ab <= 0, else the one of smaller modulus), gives the
+ *   states u-_j = u_{j-1} + s_{j-1}/2 and u+_j = u_j - s_j/2 at interface j.
+ *   Interface fluxes:
+ *     j = 0:  Q_0 = N/2 F_1(2 u_0/ds)  (sigma = 0: d_sigma u = u/sigma there),
+ *     j >= 1: Q_j = 1/2 F_1((u_j - u_{j-1})/ds)
+ *                   + 1/2 (f(u-_j) + f(u+_j)) - 1/2 a_j (u+_j - u-_j),
+ *             f(u) = (N-1)/2 F_1(u/sigma_j)  (local Lax-Friedrichs flux),
+ *             a_j = max |f'| over u-_j, u+_j,  f'(u) = -(N-1)/2 F_2(u/sigma_j)/sigma_j
+ *   (the semi-discrete central scheme of Kurganov and Tadmor);
+ *   d_t u_i = (Q_{i+1} - Q_i)/ds.  F_n at scale k = Lambda e^t with the radial
+ *   rule on [0, kappa k].  A step estimate per flow: 1/max_j (2 D_j/ds^2 +
+ *   a_j/ds) with D_0 = N/2 F_2(2 u_0/ds), D_j = 1/2 F_2((u_j - u_{j-1})/ds).
+ *   Time stepping: three-stage strong-stability-preserving Runge-Kutta
+ *   (Shu-Osher) in n_steps equal steps h = t_end/n_steps, stage times
+ *   t_n, t_n + h, t_n + h/2; a flow whose right-hand side meets m^2 + k^2 <= 0
+ *   stops at t_n with its state kept.
+ *
  *   Threshold functions (radial only, LPA):
  *     F_n(m^2) = C_d sum_i w_i q_i^{d-1} d_tR(q_i^2) G(q_i^2)^n,
  *     C_d = Omega_d/(2pi)^d.
@@ -570,4 +595,144 @@ int oracle_integrate_vertex(int d, int reg, double k, double q_max, int n_r, int
   }
   free(q); free(w); free(x); free(v); free(mu); free(ph); free(pw); free(nu); free(cph);
   return domain ? OR_E_DOMAIN : OR_OK;
+}
+
+/* ------------------------------------------------ finite-volume LPA -- */
+
+static double minmod(double a, double b) {
+  if (a * b <= 0.0) return 0.0;
+  return fabs(a) < fabs(b) ? a : b;
+}
+
+/* F_1 and F_2 at m^2 (radial rule q, w at scale k); 0 on the domain
+ * boundary m^2 + k^2 <= 0 (flagged). */
+static void fv_F12(int d, int reg, double k2, int n_r, const double *q, const double *w,
+                   double Cd, double m2, double *F1, double *F2, int *bad) {
+  const double delta = m2 + k2;
+  if (!(delta > 0.0)) {
+    *bad = 1;
+    *F1 = *F2 = 0.0;
+    return;
+  }
+  long double a1 = 0.0L, a2 = 0.0L;
+  for (int i = 0; i < n_r; ++i) {
+    double G = 1.0 / denom(reg, k2, q[i] * q[i], delta);
+    double c = w[i] * ipow(q[i], d - 1) * dtR(reg, k2, q[i] * q[i]);
+    a1 += (long double)(c * G);
+    a2 += (long double)(c * G * G);
+  }
+  *F1 = Cd * (double)a1;
+  *F2 = Cd * (double)a2;
+}
+
+/* Right-hand side of n_rows flows (u[r * n + i]) at RG time t; dt_est[r]
+ * (may be NULL) the step estimate, dead[r] = 1 where the domain is left. */
+int oracle_fvlpa_rhs(int d, int N, int reg, int n_r, double Lambda, double kappa, long n_rows,
+                     long n, double sigma_max, double t, const double *u, double *dudt,
+                     double *dt_est, int *dead) {
+  if (!(Lambda > 0.0) || !(kappa > 0.0) || n < 2 || !(sigma_max > 0.0) || N < 1 || n_rows < 0)
+    return OR_E_INVAL;
+  const double k = Lambda * exp(t), k2 = k * k;
+  if (check_common(d, reg, k, kappa * k, n_r)) return OR_E_INVAL;
+  double *q = malloc(sizeof(double) * n_r), *w = malloc(sizeof(double) * n_r);
+  double *Q = malloc(sizeof(double) * (n + 1));
+  double *g = malloc(sizeof(double) * (n + 4)); /* u_{-2} .. u_{n+1} at g[i + 2] */
+  radial_rule(reg, k, kappa * k, n_r, q, w);
+  const double Cd = oracle_Cd(d), ds = sigma_max / (double)n;
+  int any = 0;
+  for (long r = 0; r < n_rows; ++r) {
+    const double *ur = u + r * n;
+    for (long i = 0; i < n; ++i) g[i + 2] = ur[i];
+    g[1] = -ur[0];
+    g[0] = -ur[1];
+    g[n + 2] = 2.0 * ur[n - 1] - ur[n - 2];
+    g[n + 3] = 2.0 * g[n + 2] - ur[n - 1];
+    int bad = 0;
+    double lam = 0.0;
+    for (long j = 0; j <= n; ++j) {
+      double F1, F2;
+      if (j == 0) {
+        fv_F12(d, reg, k2, n_r, q, w, Cd, 2.0 * ur[0] / ds, &F1, &F2, &bad);
+        Q[0] = 0.5 * (double)N * F1;
+        double l = 2.0 * (0.5 * (double)N * F2) / (ds * ds);
+        lam = fmax(lam, l);
+        continue;
+      }
+      const double uL = g[j + 1], uR = g[j + 2]; /* cells j-1 and j */
+      const double sj = (double)j * ds;
+      fv_F12(d, reg, k2, n_r, q, w, Cd, (uR - uL) / ds, &F1, &F2, &bad);
+      const double sL = minmod(uL - g[j], uR - uL), sR = minmod(uR - uL, g[j + 3] - uR);
+      const double um = uL + 0.5 * sL, up = uR - 0.5 * sR;
+      double Qj = 0.5 * F1;
+      double l = 2.0 * (0.5 * F2) / (ds * ds);
+      if (N > 1) {
+        double F1L, F2L, F1R, F2R;
+        fv_F12(d, reg, k2, n_r, q, w, Cd, um / sj, &F1L, &F2L, &bad);
+        fv_F12(d, reg, k2, n_r, q, w, Cd, up / sj, &F1R, &F2R, &bad);
+        const double c = 0.5 * (double)(N - 1);
+        const double a = fmax(c * F2L / sj, c * F2R / sj);
+        Qj += 0.5 * (c * F1L + c * F1R) - 0.5 * a * (up - um);
+        l += a / ds;
+      }
+      Q[j] = Qj;
+      lam = fmax(lam, l);
+    }
+    dead[r] = bad;
+    any |= bad;
+    for (long i = 0; i < n; ++i) dudt[r * n + i] = bad ? NAN : (Q[i + 1] - Q[i]) / ds;
+    if (dt_est) dt_est[r] = bad ? NAN : 1.0 / lam;
+  }
+  free(q); free(w); free(Q); free(g);
+  return any ? OR_E_DOMAIN : OR_OK;
+}
+
+/* Three-stage SSP Runge-Kutta from t = 0 to t_end in n_steps equal steps;
+ * u updated in place, t_reached[r] = t_end or the start of the step whose
+ * right-hand side left the domain. */
+int oracle_fvlpa_solve(int d, int N, int reg, int n_r, double Lambda, double kappa, long n_rows,
+                       long n, double sigma_max, double t_end, long n_steps, double *u,
+                       double *t_reached) {
+  if (!(t_end <= 0.0) || n_steps < 1 || n_rows < 0) return OR_E_INVAL;
+  const long m = n_rows * n;
+  double *us = malloc(sizeof(double) * (m > 0 ? m : 1)), *L = malloc(sizeof(double) * (m > 0 ? m : 1));
+  int *alive = malloc(sizeof(int) * (n_rows > 0 ? n_rows : 1));
+  int *dead = malloc(sizeof(int) * (n_rows > 0 ? n_rows : 1));
+  const double h = t_end / (double)n_steps;
+  const double cs[3] = {0.0, 1.0, 0.5};
+  int rc = OR_OK;
+  for (long r = 0; r < n_rows; ++r) {
+    alive[r] = 1;
+    t_reached[r] = t_end;
+  }
+  for (long step = 0; step < n_steps && rc != OR_E_INVAL; ++step) {
+    const double tn = (double)step * h;
+    for (int st = 0; st < 3; ++st) {
+      const double *state = (st == 0) ? u : us;
+      rc = oracle_fvlpa_rhs(d, N, reg, n_r, Lambda, kappa, n_rows, n, sigma_max, tn + cs[st] * h,
+                            state, L, NULL, dead);
+      if (rc == OR_E_INVAL) break;
+      for (long r = 0; r < n_rows; ++r) {
+        if (!alive[r]) continue;
+        if (dead[r]) {
+          alive[r] = 0;
+          t_reached[r] = tn;
+          continue;
+        }
+        for (long i = 0; i < n; ++i) {
+          const long e = r * n + i;
+          if (st == 0)
+            us[e] = u[e] + h * L[e];
+          else if (st == 1)
+            us[e] = 0.75 * u[e] + 0.25 * (us[e] + h * L[e]);
+          else
+            us[e] = u[e] / 3.0 + (2.0 / 3.0) * (us[e] + h * L[e]);
+        }
+      }
+    }
+    for (long r = 0; r < n_rows; ++r)
+      if (alive[r])
+        for (long i = 0; i < n; ++i) u[r * n + i] = us[r * n + i];
+  }
+  free(us); free(L); free(alive); free(dead);
+  return rc == OR_E_INVAL ? OR_E_INVAL : OR_OK;
 }

@@ -637,3 +637,121 @@ def test_vertex_domain():
     assert np.isfinite(v[0]) and np.all(np.isnan(v[1:]))
     with pytest.raises(ValueError):
         oracle.integrate_vertex(3, REG_EXP, 1.0, 6.0, 8, 4, 0, [0.5], [0.5], [0.2], [0.1])
+
+
+# ------------------------------------------------- finite-volume LPA (f4) --
+
+def _litim_F(n_, m2, d, k=1.0):
+    """Litim threshold functions in closed form, C_d (2/d) k^(d+2)/(k^2 + m^2)^n."""
+    return closed_Cd(d) * (2.0 / d) * k ** (d + 2) / (k * k + m2) ** n_
+
+
+def _quartic(n, smax, lam=1.0, s02=0.5):
+    """Exact cell averages of u = U' for U = lam/8 (sigma^2 - s02)^2, and the
+    exact cell averages of the continuum right-hand side d_sigma Q, i.e. the
+    continuum flux Q(sigma) = 1/2 F_1(u') + (N-1)/2 F_1(u/sigma) differenced
+    over each cell (Litim closed forms)."""
+    U = lambda s: lam / 8 * (s * s - s02) ** 2
+    u = lambda s: lam / 2 * s * (s * s - s02)
+    up = lambda s: lam / 2 * (3 * s * s - s02)
+    ds = smax / n
+    f = np.arange(n + 1) * ds
+    ubar = (U(f[1:]) - U(f[:-1])) / ds
+
+    def rhs(N, d):
+        gold = np.empty_like(f)
+        gold[0] = up(0.0)
+        gold[1:] = u(f[1:]) / f[1:]
+        Q = 0.5 * _litim_F(1, up(f), d) + 0.5 * (N - 1) * _litim_F(1, gold, d)
+        return (Q[1:] - Q[:-1]) / ds
+    return ubar, rhs
+
+
+@pytest.mark.parametrize("reg", [REG_EXP, REG_LITIM])
+@pytest.mark.parametrize("N", [1, 2, 4])
+def test_fvlpa_linear_u_is_stationary(N, reg):
+    """A quadratic potential (u = m^2 sigma, linear) has a constant continuum
+    flux N/2 F_1(m^2): the reconstruction is exact on linear data, every
+    interface state has u/sigma = m^2, and the right-hand side vanishes to
+    rounding in every cell (N = 1, 2, 4)."""
+    n, smax = 48, 2.0
+    s = (np.arange(n) + 0.5) * smax / n
+    u = np.vstack([0.3 * s, -0.2 * s, 4.0 * s])
+    r, dt, dead = oracle.fvlpa_rhs(3, N, reg, 24, 1.0, 6.0, smax, -0.4, u)
+    assert not dead.any() and np.all(dt > 0)
+    scale = _litim_F(1, 0.0, 3) / (smax / n)
+    assert np.abs(r).max() < 1e-13 * scale
+
+
+@pytest.mark.parametrize("d", [3, 4])
+def test_fvlpa_converges_to_the_continuum(d):
+    """Litim, quartic potential with a minimum at sigma^2 = 1/2: against the
+    exact cell averages of the continuum right-hand side, N = 1 converges at
+    second order in every cell but the two at the extrapolated edge; N = 4 at
+    second order away from sigma = 0, the extremum of u (minmod clipping)
+    and the edge, and at first order including them."""
+    smax = 1.5
+    e1, e4, e4s = [], [], []
+    for n in (64, 128, 256):
+        ubar, rhs = _quartic(n, smax)
+        ds = smax / n
+        g1, _, _ = oracle.fvlpa_rhs(d, 1, REG_LITIM, 8, 1.0, 6.0, smax, 0.0, ubar[None, :])
+        g4, _, _ = oracle.fvlpa_rhs(d, 4, REG_LITIM, 8, 1.0, 6.0, smax, 0.0, ubar[None, :])
+        e1.append(np.abs(g1[0] - rhs(1, d))[:-2].max())
+        err4 = np.abs(g4[0] - rhs(4, d))[:-2]
+        e4.append(err4.sum() * ds)
+        centers = (np.arange(n - 2) + 0.5) * ds
+        smooth = (centers > 0.1) & (np.abs(centers - math.sqrt(0.5 / 3)) > 0.1)
+        e4s.append(err4[smooth].max())
+    for a, b in zip(e1, e1[1:]):
+        assert 3.5 < a / b < 4.5
+    for a, b in zip(e4s, e4s[1:]):
+        assert a / b > 3.5
+    for a, b in zip(e4, e4[1:]):
+        assert a / b > 1.8
+
+
+@pytest.mark.parametrize("N", [1, 4])
+def test_fvlpa_ssp_rk3_is_third_order(N):
+    """Fixed steps well inside the stability bound: halving the step divides
+    the error of the final state by ~8."""
+    ubar, _ = _quartic(16, 1.5)
+    args = (3, N, REG_EXP, 16, 1.0, 6.0, 1.5, -0.5)
+    ref, _ = oracle.fvlpa_solve(*args, 2048, ubar[None, :])
+    errs = [np.abs(oracle.fvlpa_solve(*args, m, ubar[None, :])[0] - ref).max() for m in (64, 128, 256)]
+    for a, b in zip(errs, errs[1:]):
+        assert 7.0 < a / b < 9.0
+
+
+def test_fvlpa_step_estimate_and_domain_stop():
+    """The step estimate follows the diffusive bound ds^2/(2D) (a quarter
+    when the cells halve, N = 1), and it separates stable from unstable
+    steps: a sawtooth of 1e-6 on a symmetric-phase potential does not grow
+    over three steps of 0.8 of it and grows over three steps of four times
+    it.  A state outside the domain stops at t = 0 with the state kept."""
+    dts = {}
+    for n in (16, 32):
+        smax = 1.5
+        ds = smax / n
+        f = np.arange(n + 1) * ds
+        U = lambda x: x ** 4 / 8 + 0.25 * x * x
+        u0 = ((U(f[1:]) - U(f[:-1])) / ds)[None, :]
+        _, dt, _ = oracle.fvlpa_rhs(3, 1, REG_EXP, 16, 1.0, 6.0, smax, 0.0, u0)
+        dts[n] = dt[0]
+    assert 0.24 < dts[32] / dts[16] < 0.26
+    saw = 1e-6 * (-1.0) ** np.arange(32)
+    growth = {}
+    for fac in (0.8, 4.0):
+        h = fac * dts[32]
+        ref, _ = oracle.fvlpa_solve(3, 1, REG_EXP, 16, 1.0, 6.0, 1.5, -3 * h, 3, u0)
+        S, tr = oracle.fvlpa_solve(3, 1, REG_EXP, 16, 1.0, 6.0, 1.5, -3 * h, 3, u0 + saw)
+        assert tr[0] == -3 * h
+        growth[fac] = np.abs(S - ref).max() / 1e-6
+    assert growth[0.8] < 1.01 and growth[4.0] > 2.0
+    bad = u0.copy()
+    bad[0, 3] = -5.0
+    S, tr = oracle.fvlpa_solve(3, 1, REG_EXP, 16, 1.0, 6.0, 1.5, -0.5, 20, bad)
+    assert tr[0] == 0.0 and np.array_equal(S, bad)
+    _, _, dead = oracle.fvlpa_rhs(3, 1, REG_EXP, 16, 1.0, 6.0, 1.5, 0.0, np.vstack([bad, u0]),
+                                  allow_domain=True)
+    assert list(dead) == [1, 0]
