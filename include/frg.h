@@ -189,6 +189,56 @@ int frg_integrate_vertex(frg_ctx *ctx, const frg_quad *quad, int32_t n_azimuth, 
                          const double *p1, const double *p2, const double *cos12, int64_t n_m,
                          const double *m2, double *out, int32_t mem, void *hip_stream);
 
+/* ---- finite-volume LPA ----------------------------------------------------- */
+/* The LPA O(N) flow of the potential (frg_lpa) written for u = dU/dsigma,
+ * sigma the field amplitude (rho = sigma^2/2), as a conservation law
+ *   d_t u = d_sigma Q,  Q = 1/2 F_1(d_sigma u) + (N-1)/2 F_1(u/sigma),
+ * F_n(m^2) = C_d sum_i w_i q_i^{d-1} d_tR(q_i^2) G(q_i^2)^n at k = lambda e^t
+ * (radial rule on [0, q_max_over_k k]; Litim: [0, k]).  Finite volumes:
+ * n_cells cells of width ds = sigma_max/n_cells hold averages u_i (cell i
+ * = [i ds, (i+1) ds]); interface j = 0..n_cells at sigma_j = j ds;
+ *   d_t u_i = (Q_{i+1} - Q_i)/ds,
+ *   Q_0 = N/2 F_1(2 u_0/ds)   (sigma = 0, where u/sigma = d_sigma u),
+ *   Q_j = 1/2 F_1((u_j - u_{j-1})/ds) + 1/2 (f(u-) + f(u+)) - 1/2 a_j (u+ - u-),
+ *   f(u) = (N-1)/2 F_1(u/sigma_j),  a_j = max(|f'(u-)|, |f'(u+)|),
+ *   f'(u) = -(N-1)/2 F_2(u/sigma_j)/sigma_j   (local Lax-Friedrichs flux),
+ *   u- = u_{j-1} + s_{j-1}/2, u+ = u_j - s_j/2, s_i = minmod(u_i - u_{i-1}, u_{i+1} - u_i)
+ * (minmod(a, b) = 0 if ab <= 0, else the one of smaller modulus; the
+ * semi-discrete central scheme of Kurganov and Tadmor), with ghost cells
+ * u_{-1} = -u_0, u_{-2} = -u_1 (u odd) and u_n = 2u_{n-1} - u_{n-2},
+ * u_{n+1} = 2u_n - u_{n-1} (linear extrapolation).  A flow leaves the domain
+ * when a mass argument has m^2 + k^2 <= 0. */
+typedef struct {
+  int32_t d;            /* 2 <= d <= 8                                         */
+  int32_t N;            /* O(N), 1..64                                         */
+  int32_t reg;          /* FRG_REG_EXP or FRG_REG_LITIM                        */
+  int32_t n_radial;     /* 1..1024                                             */
+  double lambda;        /* UV scale, > 0: k = lambda e^t                       */
+  double q_max_over_k;  /* > 0 (usually 6)                                     */
+  int64_t n_cells;      /* 2..2^24                                             */
+  double sigma_max;     /* > 0                                                 */
+} frg_fvlpa;
+
+/* One right-hand side at RG time t for n_flows flows: u and dudt hold
+ * n_flows * n_cells values (row r = flow r).  dt_est (n_flows, may be NULL)
+ * receives a step bound for explicit stepping, 1/max_j (2 D_j/ds^2 + a_j/ds)
+ * with D_0 = N/2 F_2(2 u_0/ds), D_j = 1/2 F_2((u_j - u_{j-1})/ds).  A flow
+ * outside the domain gets NaN (FRG_E_DOMAIN for host memory; device calls are
+ * asynchronous and return FRG_OK).  mem says where all arrays live. */
+int frg_fvlpa_rhs(frg_ctx *ctx, const frg_fvlpa *fv, int64_t n_flows, double t, const double *u,
+                  double *dudt, double *dt_est, int32_t mem, void *hip_stream);
+
+/* Integrate from t = 0 to t_end <= 0 with the three-stage strong-stability-
+ * preserving Runge-Kutta method (Shu-Osher) in n_steps >= 1 equal steps h =
+ * t_end/n_steps (stage times t_n, t_n + h, t_n + h/2), every stage on the
+ * device; the step must respect the bound of frg_fvlpa_rhs (explicit
+ * scheme).  u is updated in place; a flow whose right-hand side leaves the
+ * domain at any stage of step n keeps its state at t_n and reports
+ * t_reached = t_n, the others t_end.  Returns FRG_OK whether or not flows
+ * stopped; device calls are asynchronous. */
+int frg_fvlpa_solve(frg_ctx *ctx, const frg_fvlpa *fv, int64_t n_flows, double t_end,
+                    int64_t n_steps, double *u, double *t_reached, int32_t mem, void *hip_stream);
+
 /* ---- momentum-dependent two-point flow ------------------------------------ */
 /* Flow of the momentum-dependent two-point function Gamma2_k(p) = p^2 +
  * Sigma_k(p) of one scalar with constant three- and four-point couplings

@@ -154,6 +154,11 @@ struct Context {
   int lpa_jobs(int n, const frg_lpa *lpa, const double *t, const double *const *U,
                double *const *dUdt, double *const *jac, int *flags_dev, hipStream_t st);
   void stop_server();
+  // fvlpa_api.cpp: finite-volume LPA; dudt != nullptr: one right-hand side
+  // at t_rhs (and dt_est if not null), else SSP-RK3 from 0 to t_end
+  int fvlpa_device(const frg_fvlpa &f, int64_t n_flows, double t_end, int64_t n_steps, double *u,
+                   double *t_reached, double *dudt, double *dt_est, double t_rhs, int *flag,
+                   hipStream_t st);
   // vertex_api.cpp: two-external-momentum diagram on a (configuration x mass) grid
   int vertex_device(const frg_quad &q, int n_phi, int64_t n_c, const double *p1,
                     const double *p2, const double *c12, int64_t n_m, const double *m2,

@@ -182,6 +182,30 @@ struct PflowArgs {
   int32_t stage;        // update: 0..3 RK4 stages, 4: right-hand side only
   int32_t prep;         // stage kernel: also prepare the next stage (at k, t_n)
 };
+// Finite-volume LPA (fvlpa.hip): cell averages u[r * n + i] of u = dU/dsigma
+// for n_rows flows; interface fluxes Q[r * (n + 1) + j] and their local rate
+// bounds lam (same layout); F_n from the scale-free LPA table [chat | hhat].
+struct FvArgs {
+  const double *tab;   // LpaTable::data on the device
+  double *y0;          // state at the start of the step
+  double *ys;          // stage state
+  double *Q, *lam;
+  double *dudt;        // right-hand side only (stage = 3)
+  double *dt;          // right-hand side only: step estimate per flow (may be null)
+  int *alive;
+  double *t_reached;
+  int *flag;
+  double Cd, k2, inv_k2, kd, kdm2;  // kd = k^d, kdm2 = k^(d-2)
+  double ds, h, t_n;
+  int64_t n_rows, n;
+  int32_t n_r, N;
+  int32_t stage;       // 0..2 SSP-RK3 stages, 3: right-hand side only
+  int32_t first;       // flux kernel: read y0 (first stage / rhs) instead of ys
+};
+int launch_fv_init(const FvArgs &a, double t_end, void *stream);
+int launch_fv_flux(const FvArgs &a, void *stream);
+int launch_fv_stage(const FvArgs &a, void *stream);
+int launch_fv_dt(const FvArgs &a, void *stream);
 int launch_pflow_init(const PflowArgs &a, double t_end, void *stream);
 int launch_pflow_prep(const PflowArgs &a, int reg, void *stream);
 int launch_pflow_stage(const PflowArgs &a, int reg, void *stream);

@@ -30,7 +30,7 @@ STATUS_NAMES = {0: "FRG_OK", 1: "FRG_PENDING", -1: "FRG_E_INVAL", -2: "FRG_E_DOM
 
 EXPORTS = ["frg_create", "frg_destroy", "frg_last_error", "frg_version", "frg_integrate",
            "frg_integrate_grid", "frg_integrate_tab", "frg_integrate_vertex", "frg_pflow_rhs",
-           "frg_pflow_solve",
+           "frg_pflow_solve", "frg_fvlpa_rhs", "frg_fvlpa_solve",
            "frg_flow_rhs", "frg_flow_rhs_batch", "frg_flow_solve",
            "frg_submit", "frg_poll", "frg_server_stats", "frg_gauss_legendre",
            "frg_flow_footprint", "frg_autotune", "frg_tune_set", "frg_tune_get"]
@@ -52,6 +52,13 @@ class frg_set(ctypes.Structure):
 class frg_gtab(ctypes.Structure):
     _fields_ = [("n_rows", ctypes.c_int64), ("n_s", ctypes.c_int64), ("s_max", ctypes.c_double),
                 ("g", ctypes.c_void_p)]
+
+
+class frg_fvlpa(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("N", ctypes.c_int32), ("reg", ctypes.c_int32),
+                ("n_radial", ctypes.c_int32), ("lambda_", ctypes.c_double),
+                ("q_max_over_k", ctypes.c_double), ("n_cells", ctypes.c_int64),
+                ("sigma_max", ctypes.c_double)]
 
 
 class frg_pflow(ctypes.Structure):
@@ -119,6 +126,8 @@ def _load():
                                     vp, vp, i32, vp]
     L.frg_integrate_vertex.argtypes = [vp, ctypes.POINTER(frg_quad), i32, i64, vp, vp, vp, i64,
                                        vp, vp, i32, vp]
+    L.frg_fvlpa_rhs.argtypes = [vp, ctypes.POINTER(frg_fvlpa), i64, dbl, vp, vp, vp, i32, vp]
+    L.frg_fvlpa_solve.argtypes = [vp, ctypes.POINTER(frg_fvlpa), i64, dbl, i64, vp, vp, i32, vp]
     L.frg_pflow_rhs.argtypes = [vp, ctypes.POINTER(frg_pflow), i64, vp, vp, dbl, vp, vp, i32, vp]
     L.frg_pflow_solve.argtypes = [vp, ctypes.POINTER(frg_pflow), i64, vp, vp, dbl, i64, vp, vp,
                                   i32, vp]
@@ -244,6 +253,28 @@ def frg_integrate_vertex(ctx, quad, n_azimuth, p1, p2, cos12, m2, out, mem=FRG_M
                                            _addr(p1), _addr(p2), _addr(cos12), n_m, _addr(m2),
                                            _addr(out), mem, st),
                   (FRG_E_DOMAIN,) if allow_domain else ())
+
+
+def make_fvlpa(d, N, reg, n_radial, lam, q_max_over_k, n_cells, sigma_max):
+    return frg_fvlpa(int(d), int(N), int(reg), int(n_radial), float(lam), float(q_max_over_k),
+                     int(n_cells), float(sigma_max))
+
+
+def frg_fvlpa_rhs(ctx, fv, t, u, dudt, dt_est=None, mem=FRG_MEM_DEVICE, stream=None,
+                  allow_domain=False):
+    """u, dudt: n_flows * n_cells values (row r = flow r); dt_est: n_flows or None."""
+    n = int((u.numel() if hasattr(u, "numel") else u.size) // fv.n_cells)
+    st = 0 if mem == FRG_MEM_HOST else _stream(stream)
+    return _check(lib.frg_fvlpa_rhs(ctx, ctypes.byref(fv), n, float(t), _addr(u), _addr(dudt),
+                                    _addr(dt_est), mem, st),
+                  (FRG_E_DOMAIN,) if allow_domain else ())
+
+
+def frg_fvlpa_solve(ctx, fv, t_end, n_steps, u, t_reached, mem=FRG_MEM_DEVICE, stream=None):
+    n = int((u.numel() if hasattr(u, "numel") else u.size) // fv.n_cells)
+    st = 0 if mem == FRG_MEM_HOST else _stream(stream)
+    return _check(lib.frg_fvlpa_solve(ctx, ctypes.byref(fv), n, float(t_end), int(n_steps),
+                                      _addr(u), _addr(t_reached), mem, st))
 
 
 def make_pflow(d, reg, n_radial, n_angular, lam, q_max_over_k, n_s, s_max):

@@ -31,6 +31,11 @@ regulator):
   configurations (128 at the symmetric point p1 = p2 log-spaced in [1e-3, 10]
   with cos th = -1/2, 128 with p1, p2 log-uniform in [1e-3, 10] and cos th
   uniform in [-1, 1]) x 512 masses uniform in [-0.9, 10].
+* ``fvlpa_d3`` -- finite-volume LPA, O(4), d = 3, exponential regulator, 64
+  radial nodes, 128 flows of 256 cells on sigma in [0, 2] starting from the
+  cell averages of U = lam/8 sigma^4 + m^2/2 sigma^2 with lam uniform in
+  [1, 20], m^2 uniform in [0.05, 0.5]; RG time 0 -> -0.5 in 2000 SSP-RK3 steps
+  (inside the explicit step bound at t = 0).
 * ``pflow_d3`` -- momentum-dependent two-point flows: d = 3, exponential
   regulator, Lambda = 1, q_max = 6k, 128 radial x 32 angular nodes, Sigma on
   256 nodes of s in [0, 49] (p up to 7 Lambda), 64 flows with lam3 uniform in
@@ -199,6 +204,46 @@ def vertex_d3(seed: int = 0, n_sym: int = 128, n_rand: int = 128, n_m: int = 512
     q = Quad(d=3, reg=REG_EXP, k=1.0, q_max=6.0, n_r=48, n_a=8)
     return VertexWorkload(f"vertex_d3_exp_{p1.size}c_{n_m}m_48r8x16phi", q, 16, p1, p2, c12,
                           np.linspace(-0.9, 10.0, n_m))
+
+
+@dataclass
+class FvlpaWorkload:
+    name: str
+    d: int
+    N: int
+    reg: int
+    n_r: int
+    lam: float
+    kappa: float
+    n_cells: int
+    sigma_max: float
+    u0: np.ndarray      # (n_flows, n_cells) cell averages of dU/dsigma
+    t_end: float
+    n_steps: int
+
+    @property
+    def n_flows(self) -> int:
+        return self.u0.shape[0]
+
+
+def quartic_cell_averages(coef4: np.ndarray, coef2: np.ndarray, n_cells: int,
+                          sigma_max: float) -> np.ndarray:
+    """Exact cell averages of u = dU/dsigma for U = coef4/8 sigma^4 + coef2/2 sigma^2
+    (one row per (coef4, coef2)): (U(right face) - U(left face))/ds."""
+    ds = sigma_max / n_cells
+    f = np.arange(n_cells + 1) * ds
+    U = coef4[:, None] / 8.0 * f[None, :] ** 4 + coef2[:, None] / 2.0 * f[None, :] ** 2
+    return (U[:, 1:] - U[:, :-1]) / ds
+
+
+def fvlpa_d3(seed: int = 0, n_flows: int = 128, n_cells: int = 256, n_steps: int = 2000,
+             t_end: float = -0.5) -> FvlpaWorkload:
+    rng = _rng(seed)
+    lam = rng.uniform(1.0, 20.0, n_flows)
+    m2 = rng.uniform(0.05, 0.5, n_flows)
+    u0 = quartic_cell_averages(lam, m2, n_cells, 2.0)
+    return FvlpaWorkload(f"fvlpa_d3_O4_exp_{n_flows}flows_{n_cells}cells_{n_steps}steps", 3, 4,
+                         REG_EXP, 64, 1.0, 6.0, n_cells, 2.0, u0, t_end, n_steps)
 
 
 @dataclass
