@@ -55,11 +55,11 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device-to-device copy of 1 GiB (PMC traffic calibration)")
     ap.add_argument("--only", choices=["uneven64", "uneven32", "grid32", "tab4096", "tab1m", "pflow",
-                                       "vertex"],
+                                       "vertex", "fvlpa"],
                     default=None,
                     help="profiling aid: run only --steps persistent launches of the uneven sets "
                          "(FP64 or FP32C), --steps FP32C scale-up grid calls, --steps momentum-flow "
-                         "solves or vertex-diagram calls, or --steps calls "
+                         "or finite-volume LPA solves or vertex-diagram calls, or --steps calls "
                          "of the tabulated variant (rows of 4096 or 2^20 nodes), and print "
                          "their timing")
     return ap.parse_args()
@@ -152,11 +152,11 @@ def main():
     if args.only == "grid32":
         only_grid32(args.steps, args.warmup)
         return
-    if args.only in ("pflow", "vertex"):
+    if args.only in ("pflow", "vertex", "fvlpa"):
         import torch
         from paper_2607_24908_amd import frg, workloads
         ctx = frg.frg_create(0)
-        fn = momentum_flow if args.only == "pflow" else vertex
+        fn = {"pflow": momentum_flow, "vertex": vertex, "fvlpa": fv_lpa}[args.only]
         r = fn(ctx, frg, workloads, torch, reps=args.steps)
         print(json.dumps({"only": args.only, **r}), flush=True)
         return
@@ -337,6 +337,7 @@ def secondary(ctx, frg, workloads, torch):
     sec.update(tabulated(ctx, frg, workloads, torch))
     sec["vertex"] = vertex(ctx, frg, workloads, torch)
     sec["momentum_flow"] = momentum_flow(ctx, frg, workloads, torch)
+    sec["fv_lpa"] = fv_lpa(ctx, frg, workloads, torch)
     sec["serving"] = serving(frg, workloads)
     return sec
 
@@ -355,6 +356,30 @@ def vertex(ctx, frg, workloads, torch, reps=20):
     return {"workload": w.name, "ms_per_call": t * 1e3, "evals_per_s": w.n_evals / t,
             "integrals_per_s": w.n_integrals / t,
             "frac_of_2op_floor": w.n_evals / t / PEAK_EVALS}
+
+
+def fv_lpa(ctx, frg, workloads, torch, reps=3):
+    """Finite-volume LPA: 128 O(4) flows of 256 cells, 64 radial nodes, 2000
+    SSP-RK3 steps (6000 right-hand sides: 257 interfaces x 128 flows, three
+    threshold masses per Goldstone interface); time per whole solve."""
+    w = workloads.fvlpa_d3()
+    fv = frg.make_fvlpa(w.d, w.N, w.reg, w.n_r, w.lam, w.kappa, w.n_cells, w.sigma_max)
+    U0 = torch.as_tensor(w.u0, device="cuda")
+    U = torch.empty_like(U0)
+    tr = torch.empty(w.n_flows, dtype=torch.float64, device="cuda")
+
+    def run():
+        U.copy_(U0)
+        frg.frg_fvlpa_solve(ctx, fv, w.t_end, w.n_steps, U, tr)
+
+    t = timed(run, torch, reps)
+    reached = int((tr == w.t_end).sum().item())
+    rhs = 3 * w.n_steps
+    log(f"finite-volume LPA {w.name}: {t * 1e3:.1f} ms per solve, {rhs / t:.3e} right-hand "
+        f"sides/s, {reached}/{w.n_flows} flows to t_end")
+    return {"workload": w.name, "ms_per_solve": t * 1e3, "rhs_per_s": rhs / t,
+            "interface_fluxes_per_s": rhs * w.n_flows * (w.n_cells + 1) / t,
+            "flows_to_t_end": reached, "flows": w.n_flows}
 
 
 def momentum_flow(ctx, frg, workloads, torch, reps=3):

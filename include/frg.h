@@ -219,7 +219,7 @@ typedef struct {
   double sigma_max;     /* > 0                                                 */
 } frg_fvlpa;
 
-/* One right-hand side at RG time t for n_flows flows: u and dudt hold
+/* One right-hand side at RG time t for n_flows (0..65535) flows: u and dudt hold
  * n_flows * n_cells values (row r = flow r).  dt_est (n_flows, may be NULL)
  * receives a step bound for explicit stepping, 1/max_j (2 D_j/ds^2 + a_j/ds)
  * with D_0 = N/2 F_2(2 u_0/ds), D_j = 1/2 F_2((u_j - u_{j-1})/ds).  A flow

@@ -140,6 +140,87 @@ __device__ __forceinline__ double wave_sum_split(const double *v, int lane) {
   return x;
 }
 
+// ------------------------------------------- cross-lane sums (gfx950) --
+// Lane permutations of a double: DPP within rows of 16 lanes (CTRL: 0xB1
+// swaps neighbours, 0x4E swaps pairs, 0x141 mirrors each half-row, 0x128
+// rotates each row by 8) and the gfx950 lane swaps (half-waves, odd/even
+// rows), each moving the two 32-bit halves separately.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// For values a, b in every lane, returns a' + b' where (a', b') is a and b
+// with lanes [32, 64) of a exchanged with lanes [0, 32) of b (W32) or with
+// rows 1 and 3 of a exchanged with rows 0 and 2 of b (W16): lane l gets
+// a_l + a_{l+w} in the lower part of each 2w block and b_{l-w} + b_l in the
+// upper part.
+template <int W>
+__device__ __forceinline__ double swap_add(double a, double b) {
+  const unsigned long long ua = __builtin_bit_cast(unsigned long long, a);
+  const unsigned long long ub = __builtin_bit_cast(unsigned long long, b);
+  unsigned lo0, lo1, hi0, hi1;
+  if constexpr (W == 32) {
+    const auto rl = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+    const auto rh = __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+    lo0 = rl[0]; lo1 = rl[1]; hi0 = rh[0]; hi1 = rh[1];
+  } else {
+    const auto rl = __builtin_amdgcn_permlane16_swap((unsigned)ua, (unsigned)ub, false, false);
+    const auto rh = __builtin_amdgcn_permlane16_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+    lo0 = rl[0]; lo1 = rl[1]; hi0 = rh[0]; hi1 = rh[1];
+  }
+  const double x = __builtin_bit_cast(double, ((unsigned long long)hi0 << 32) | lo0);
+  const double y = __builtin_bit_cast(double, ((unsigned long long)hi1 << 32) | lo1);
+  return x + y;
+}
+
+// Sums of M values (M = 1, 2, 4, 8) over the 64 lanes at once.  The pairing
+// is the same for every M: lane offsets 32, 16, 8, then 1, 2 and 4 (as the
+// half-row mirror, equivalent once each quad holds equal values), each step
+// own + partner.  The first log2 M steps halve the number of live values (a
+// lane keeps the half selected by the offset's bit of its index), so lane l
+// ends with the total of value l / (64 / M), the same bits for every M.
+template <int M>
+__device__ __forceinline__ double wave_sum_fold(const double *v, int lane) {
+  static_assert(M == 1 || M == 2 || M == 4 || M == 8, "M must be 1, 2, 4 or 8");
+  double w[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) w[m] = v[m];
+  // offset 32
+  if constexpr (M >= 2) {
+#pragma unroll
+    for (int k = 0; k < M / 2; ++k) w[k] = swap_add<32>(w[k], w[M / 2 + k]);
+  } else {
+    w[0] = swap_add<32>(w[0], w[0]);
+  }
+  // offset 16
+  if constexpr (M >= 4) {
+#pragma unroll
+    for (int k = 0; k < M / 4; ++k) w[k] = swap_add<16>(w[k], w[M / 4 + k]);
+  } else {
+    w[0] = swap_add<16>(w[0], w[0]);
+  }
+  // offset 8 (rotation by 8 within a row of 16 is the exchange of offset 8)
+  double x;
+  if constexpr (M == 8) {
+    double lo = w[0], hi = w[1];
+    asm("" : "+v"(lo), "+v"(hi));
+    const bool upper = (lane & 8) != 0;
+    const double keep = upper ? hi : lo;
+    const double send = upper ? lo : hi;
+    x = keep + dpp_f64<0x128>(send);
+  } else {
+    x = w[0] + dpp_f64<0x128>(w[0]);
+  }
+  x = x + dpp_f64<0xB1>(x);
+  x = x + dpp_f64<0x4E>(x);
+  x = x + dpp_f64<0x141>(x);
+  return x;
+}
+
 // h(y) = y/(1 - e^{-y}) - 1; Bernoulli series y/2 + y^2/12 - y^4/720 + ...
 // below y = 0.1 (truncation < 1e-17 relative there).
 __device__ __forceinline__ double h_exp(double y) {

@@ -196,7 +196,7 @@ struct FvArgs {
   double *t_reached;
   int *flag;
   double Cd, k2, inv_k2, kd, kdm2;  // kd = k^d, kdm2 = k^(d-2)
-  double ds, h, t_n;
+  double ds, inv_ds, h, t_n;
   int64_t n_rows, n;
   int32_t n_r, N;
   int32_t stage;       // 0..2 SSP-RK3 stages, 3: right-hand side only

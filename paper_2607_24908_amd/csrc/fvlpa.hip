@@ -36,14 +36,6 @@ __device__ __forceinline__ double minmod(double a, double b) {
   return fabs(a) < fabs(b) ? a : b;
 }
 
-// Cell average i in [-2, n + 1] with the ghost cells (wave-uniform).
-__device__ __forceinline__ double cell(const double *u, int64_t n, int64_t i) {
-  if (i < 0) return -u[-i - 1];
-  if (i < n) return u[i];
-  const double gn = 2.0 * u[n - 1] - u[n - 2];
-  return i == n ? gn : 2.0 * gn - u[n - 1];
-}
-
 // alive = 1, t_reached = t_end, domain flag cleared.
 __global__ __launch_bounds__(256) void fv_init_kernel(FvArgs a, double t_end) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -54,36 +46,59 @@ __global__ __launch_bounds__(256) void fv_init_kernel(FvArgs a, double t_end) {
   }
 }
 
-// One wave per (flow, interface); lanes over the radial nodes of F_1, F_2 at
-// up to three masses (d_sigma u and the two Goldstone states).
+// Broadcast lane l's double to the wave (uniform).
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, l);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Grid (interface blocks of 4, flows): one wave per (flow, interface);
+// lanes over the radial nodes of F_1, F_2 at up to three masses (d_sigma u
+// and the two Goldstone states), reduced together.
 __global__ __launch_bounds__(256) void fv_flux_kernel(FvArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t gid = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const int64_t r = blockIdx.y;
   const int64_t n = a.n, nq = n + 1;
-  if (gid >= a.n_rows * nq) return;  // wave-uniform
-  const int64_t r = gid / nq, j = gid - r * nq;
+  const int64_t j = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave;
+  if (j >= nq) return;  // wave-uniform
   const int64_t o = r * nq + j;
   if (!a.alive[r]) {
-    a.Q[o] = 0.0;
-    a.lam[o] = 0.0;
+    if (lane == 0) {
+      a.Q[o] = 0.0;
+      a.lam[o] = 0.0;
+    }
     return;
   }
   const double *u = (a.first ? a.y0 : a.ys) + r * n;
-  const double ds = a.ds;
+  const double ds = a.ds, ids = a.inv_ds;
+  // cells j-2 .. j+1 with the ghost cells: loads at clamped indices first
+  // (issued together), the ghost rules after
+  const int64_t nm1 = n - 1;
+  auto cl = [&](int64_t i) { return i < 0 ? (int64_t)0 : (i > nm1 ? nm1 : i); };
+  const double v0 = u[cl(j - 2)], v1 = u[cl(j - 1)], v2 = u[cl(j)], v3 = u[cl(j + 1)];
+  const double e0 = u[0], e1 = u[1], f1 = u[nm1], f2 = u[n - 2];
+  const double gn = 2.0 * f1 - f2, gn1 = 2.0 * gn - f1;
+  auto cell = [&](int64_t i, double v) {
+    return i == -1 ? -e0 : i == -2 ? -e1 : i == n ? gn : i == n + 1 ? gn1 : v;
+  };
   const bool gold = j > 0 && a.N > 1;
-  double ms, um = 0.0, up = 0.0, sj = 0.0;
+  double ms, um = 0.0, up = 0.0, isj = 0.0;
   if (j == 0) {
-    ms = 2.0 * u[0] / ds;
+    ms = 2.0 * e0 * ids;
   } else {
-    const double uL = cell(u, n, j - 1), uR = cell(u, n, j);
-    ms = (uR - uL) / ds;
-    const double sL = minmod(uL - cell(u, n, j - 2), uR - uL);
-    const double sR = minmod(uR - uL, cell(u, n, j + 1) - uR);
+    const double uLL = cell(j - 2, v0), uL = cell(j - 1, v1), uR = cell(j, v2),
+                 uRR = cell(j + 1, v3);
+    ms = (uR - uL) * ids;
+    const double sL = minmod(uL - uLL, uR - uL);
+    const double sR = minmod(uR - uL, uRR - uR);
     um = uL + 0.5 * sL;
     up = uR - 0.5 * sR;
-    sj = (double)j * ds;
+    isj = ids / (double)j;  // 1/sigma_j
   }
-  const double m2[3] = {ms, gold ? um / sj : 0.0, gold ? up / sj : 0.0};
+  const double m2[3] = {ms, um * isj, up * isj};
   const int nm = gold ? 3 : 1;
   bool bad = false;
   double dh[3];
@@ -93,7 +108,7 @@ __global__ __launch_bounds__(256) void fv_flux_kernel(FvArgs a) {
     bad |= m < nm && !(delta > 0.0);
     dh[m] = (m < nm && delta > 0.0) ? delta * a.inv_k2 : 1.0;
   }
-  double s1[3] = {0.0, 0.0, 0.0}, s2[3] = {0.0, 0.0, 0.0};
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // s1, s2 per mass
   for (int i = lane; i < a.n_r; i += kWave) {
     const double c = a.tab[i], hh = a.tab[a.n_r + i];
 #pragma unroll
@@ -101,15 +116,17 @@ __global__ __launch_bounds__(256) void fv_flux_kernel(FvArgs a) {
       if (m >= nm) break;
       const double G = rcp64(hh + dh[m]);
       const double cg = c * G;
-      s1[m] += cg;
-      s2[m] = __builtin_fma(cg, G, s2[m]);
+      acc[2 * m] += cg;
+      acc[2 * m + 1] = __builtin_fma(cg, G, acc[2 * m + 1]);
     }
   }
+  // lane l ends with the total of acc[l / 8]
+  const double tot = wave_sum_fold<8>(acc, lane);
   double F1[3], F2[3];
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
-    F1[m] = m < nm ? a.Cd * a.kd * wave_sum(s1[m]) : 0.0;
-    F2[m] = m < nm ? a.Cd * a.kdm2 * wave_sum(s2[m]) : 0.0;
+    F1[m] = a.Cd * a.kd * lane_value(tot, 16 * m);
+    F2[m] = a.Cd * a.kdm2 * lane_value(tot, 16 * m + 8);
   }
   if (lane != 0) return;
   if (bad) {
@@ -124,32 +141,33 @@ __global__ __launch_bounds__(256) void fv_flux_kernel(FvArgs a) {
   double Q, lam;
   if (j == 0) {
     Q = 0.5 * (double)a.N * F1[0];
-    lam = 2.0 * (0.5 * (double)a.N * F2[0]) / (ds * ds);
+    lam = 2.0 * (0.5 * (double)a.N * F2[0]) * (ids * ids);
   } else {
     Q = 0.5 * F1[0];
-    lam = 2.0 * (0.5 * F2[0]) / (ds * ds);
+    lam = 2.0 * (0.5 * F2[0]) * (ids * ids);
     if (gold) {
       const double c = 0.5 * (double)(a.N - 1);
-      const double am = fmax(c * F2[1] / sj, c * F2[2] / sj);
+      const double am = fmax(c * F2[1] * isj, c * F2[2] * isj);
       Q += 0.5 * (c * F1[1] + c * F1[2]) - 0.5 * am * (up - um);
-      lam += am / ds;
+      lam += am * ids;
     }
   }
   a.Q[o] = Q;
   a.lam[o] = lam;
 }
 
-// One thread per (flow, cell): d_t u_i = (Q_{i+1} - Q_i)/ds and the stage.
+// Grid (cell blocks, flows): d_t u_i = (Q_{i+1} - Q_i)/ds and the stage.
 __global__ __launch_bounds__(256) void fv_stage_kernel(FvArgs a) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= a.n_rows * a.n) return;
-  const int64_t r = e / a.n, i = e - r * a.n;
+  const int64_t r = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int64_t e = r * a.n + i;
   if (!a.alive[r]) {
     if (a.stage == 3) a.dudt[e] = __builtin_nan("");
     return;
   }
   const double *Q = a.Q + r * (a.n + 1);
-  const double L = (Q[i + 1] - Q[i]) / a.ds;
+  const double L = (Q[i + 1] - Q[i]) * a.inv_ds;
   switch (a.stage) {
     case 0:
       a.ys[e] = a.y0[e] + a.h * L;
@@ -191,18 +209,16 @@ int launch_fv_init(const FvArgs &a, double t_end, void *stream) {
 }
 
 int launch_fv_flux(const FvArgs &a, void *stream) {
-  const int64_t waves = a.n_rows * (a.n + 1);
-  if (waves <= 0) return 0;
-  hipLaunchKernelGGL(fv_flux_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0,
-                     (hipStream_t)stream, a);
+  if (a.n_rows <= 0) return 0;
+  hipLaunchKernelGGL(fv_flux_kernel, dim3((unsigned)((a.n + 1 + 3) / 4), (unsigned)a.n_rows),
+                     dim3(256), 0, (hipStream_t)stream, a);
   return (int)hipGetLastError();
 }
 
 int launch_fv_stage(const FvArgs &a, void *stream) {
-  const int64_t m = a.n_rows * a.n;
-  if (m <= 0) return 0;
-  hipLaunchKernelGGL(fv_stage_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0,
-                     (hipStream_t)stream, a);
+  if (a.n_rows <= 0) return 0;
+  hipLaunchKernelGGL(fv_stage_kernel, dim3((unsigned)((a.n + 255) / 256), (unsigned)a.n_rows),
+                     dim3(256), 0, (hipStream_t)stream, a);
   return (int)hipGetLastError();
 }
 

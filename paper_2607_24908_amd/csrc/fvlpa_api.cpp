@@ -22,6 +22,7 @@ static int check_fvlpa(const frg_fvlpa &f, int64_t n_flows) {
   if (!(f.sigma_max > 0.0) || !std::isfinite(f.sigma_max))
     return fail(FRG_E_INVAL, "fvlpa.sigma_max must be finite and > 0");
   if (n_flows < 0 || n_flows > ((int64_t)1 << 24)) return fail(FRG_E_INVAL, "n_flows outside [0, 2^24]");
+  if (n_flows > 65535) return fail(FRG_E_INVAL, "n_flows outside [0, 65535]");
   if (n_flows * (f.n_cells + 1) > ((int64_t)1 << 31)) return fail(FRG_E_INVAL, "n_flows * n_cells too large");
   return FRG_OK;
 }
@@ -64,6 +65,7 @@ int Ctx::fvlpa_device(const frg_fvlpa &f, int64_t n, double t_end, int64_t n_ste
   a.flag = flag;
   a.Cd = Cd;
   a.ds = f.sigma_max / (double)f.n_cells;
+  a.inv_ds = (double)f.n_cells / f.sigma_max;
   a.n_rows = n;
   a.n = f.n_cells;
   a.n_r = f.n_radial;
