@@ -414,9 +414,10 @@ int frg_autotune(frg_ctx *ctx, int32_t mode, const char *cache_path);
  * fractions as in frg_integrate; 2 / 3: coefficients in groups of 8 / 16;
  * the forms agree to a few ulp), "grid_lds_rows" (8..96), "plain_tile", "persist_tile" (1..64),
  * "persist_wpc" (1..64), and of the tabulated variant "tab_W" (1..4),
- * "tab_pw" (momenta per wave, 1..64), "tab_lds_nodes" (2..6144), and for
- * streamed rows "tab_wpc" (workgroups per CU, 1..16), "tab_sW" (1..4),
- * "tab_spw" (1..64).  Setting a knob drops the
+ * "tab_pw" (momenta per wave, 1..64), "tab_lds_nodes" (2..6144),
+ * "tab_pairs" (1: rows in LDS as (value, slope) pairs, the default; 0: as
+ * values; the same bits), and for streamed rows "tab_wpc" (workgroups per
+ * CU, 1..16), "tab_sW" (1..4), "tab_spw" (1..64).  Setting a knob drops the
  * tuned choices so that it takes effect.  Two knobs route FRG_PREC_FP32C
  * points to FP64 and do change results (within the FP32 tolerance):
  * "fp32c_flag_ppb" (error-estimate threshold in units of 1e-9, default 100)

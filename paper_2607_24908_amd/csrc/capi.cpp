@@ -571,8 +571,9 @@ int Ctx::tab_device(const frg_quad &q, const frg_gtab &tb, int64_t n_p, const do
 int Ctx::tab_launch(TabArgs a, int reg, hipStream_t st) {
   const int64_t n_p = a.n_p;
   tab_lane_split(a.n_r, a.n_a, &a.R, &a.J, &a.T, &a.U);
+  a.pairs = tune.tab_pairs ? 1 : 0;
   const bool lds_rows = a.n_s <= std::min<int64_t>(tune.tab_lds_nodes, tab_lds_max_nodes) &&
-                        tab_lds_bytes(a, true) <= 64 * 1024;
+                        tab_lds_bytes(a, true) <= 150 * 1024;
   const int W = std::max(1, std::min(4, lds_rows ? tune.tab_W : tune.tab_sW));
   a.pw = std::max(1, std::min(64, lds_rows ? tune.tab_pw : tune.tab_spw));
   // streamed rows: tab_wpc workgroups per CU work through the rows of their

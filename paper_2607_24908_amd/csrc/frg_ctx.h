@@ -76,6 +76,7 @@ struct Tune {
   int tab_wpc = 8;         // tabulated variant, streamed rows: workgroups per CU
   int tab_sW = 2;          // tabulated variant, streamed rows: waves per workgroup
   int tab_spw = 1;         // tabulated variant, streamed rows: momenta per wave (at most)
+  int tab_pairs = 1;       // tabulated variant: rows in LDS as (value, slope) pairs
   PersistCfg persist;
   int grid_lds_rows = 64;  // (t, u) rows of 64 doubles staged per LDS chunk
   int grid_form = 0;       // resident FP64 grid: 0 per-momentum coefficients, 1 running fractions

@@ -149,6 +149,7 @@ struct TabArgs {
   int32_t n_r, n_a, R, J, T, U;
   int32_t pw;     // momenta per wave
   int32_t n_pb;   // momentum blocks per row (W * pw momenta each)
+  int32_t pairs;  // rows in LDS as (value, slope) pairs
 };
 void tab_lane_split(int n_r, int n_a, int *R, int *J, int *T, int *U);
 

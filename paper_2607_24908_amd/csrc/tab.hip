@@ -24,10 +24,31 @@ namespace {
 
 using namespace dev;
 
+// A table row as plain values g_k (rows read from memory, or staged in LDS
+// as they are) or as pairs (g_k, g_{k+1} - g_k) (rows staged in LDS): one
+// 16-byte read per evaluation; both give the same bits.
+struct PlainRow {
+  const double *g;
+  __device__ __forceinline__ double operator()(double t, double t_last, int k_last) const {
+    return interp(g, t, t_last, k_last);
+  }
+};
+struct PairRow {
+  const double2 *p;
+  __device__ __forceinline__ double operator()(double t, double t_last, int k_last) const {
+    t = fmin(t, t_last);
+    int k = (int)t;
+    k = k < k_last ? k : k_last;
+    const double f = t - (double)k;
+    const double2 gd = p[k];
+    return __builtin_fma(f, gd.y, gd.x);
+  }
+};
+
 // One (row, momentum block) of work: A_i of the row, then W * pw momenta.
 // lq / lo / lm are staged; `row` is the LDS copy or the row in memory.
-template <int UR>
-__device__ __forceinline__ void tab_block(const TabArgs &a, const double *row, const double *lq,
+template <int UR, class Row>
+__device__ __forceinline__ void tab_block(const TabArgs &a, const Row row, const double *lq,
                                           const double *lA, const double *lo, const double *lm,
                                           int64_t r, int64_t pb, int W, int wave, int lane) {
   const int n_a = a.n_a, n_r = a.n_r;
@@ -65,14 +86,14 @@ __device__ __forceinline__ void tab_block(const TabArgs &a, const double *row, c
         if (UR > 0) {
 #pragma unroll
           for (int u = 0; u < UR; ++u) {
-            const double G = interp(row, __builtin_fma(bh, ro[u], ah), a.t_last, k_last);
+            const double G = row(__builtin_fma(bh, ro[u], ah), a.t_last, k_last);
             inner = __builtin_fma(rm[u], G, inner);
           }
         } else {
           for (int u = 0; u < a.U; ++u) {
             const int j = iota + a.J * u;
             if (j < n_a) {
-              const double G = interp(row, __builtin_fma(bh, lo[j], ah), a.t_last, k_last);
+              const double G = row(__builtin_fma(bh, lo[j], ah), a.t_last, k_last);
               inner = __builtin_fma(lm[j], G, inner);
             }
           }
@@ -89,11 +110,12 @@ __device__ __forceinline__ void tab_block(const TabArgs &a, const double *row, c
 }
 
 // Stage the row-dependent factors A_i = c_i G_r(q_i^2)^2 (and q_i).
-__device__ __forceinline__ void tab_stage_A(const TabArgs &a, const double *row, double *lq,
+template <class Row>
+__device__ __forceinline__ void tab_stage_A(const TabArgs &a, const Row row, double *lq,
                                             double *lA) {
   for (int i = threadIdx.x; i < a.n_r; i += blockDim.x) {
     const double q = a.tab[i];
-    const double G = interp(row, (q * q) * a.inv_h, a.t_last, (int)a.n_s - 2);
+    const double G = row((q * q) * a.inv_h, a.t_last, (int)a.n_s - 2);
     lq[i] = q;
     lA[i] = (a.tab[a.n_r + i] * G) * G;
   }
@@ -107,7 +129,7 @@ __device__ __forceinline__ void tab_stage_A(const TabArgs &a, const double *row,
 // flight on the chip stay within the memory-side cache.
 // UR > 0: every lane holds at most UR angular nodes (U <= UR), kept in
 // registers; UR == 0: read from LDS.
-template <bool LDS_ROW, int UR>
+template <bool LDS_ROW, int UR, bool PAIRS>
 __global__ __launch_bounds__(256) void tab_kernel(TabArgs a) {
   extern __shared__ double lds[];
   const int W = blockDim.x / kWave;
@@ -118,7 +140,7 @@ __global__ __launch_bounds__(256) void tab_kernel(TabArgs a) {
   double *lA = lq + n_r;      // c_i G_r(q_i^2)^2
   double *lo = lA + n_r;      // 1 + x_j
   double *lm = lo + n_a;      // mu_j
-  double *lg = lm + n_a;      // the row (LDS_ROW)
+  double *lg = lm + n_a;      // the row (LDS_ROW): values, or (value, slope) pairs
   for (int j = threadIdx.x; j < n_a; j += blockDim.x) {
     lo[j] = a.tab[3 * n_r + j];
     lm[j] = a.tab[3 * n_r + n_a + j];
@@ -127,16 +149,30 @@ __global__ __launch_bounds__(256) void tab_kernel(TabArgs a) {
     const int64_t r = blockIdx.x / a.n_pb;
     const int64_t pb = blockIdx.x - r * a.n_pb;
     const double *grow = a.g + r * a.n_s;
-    for (int k = threadIdx.x; k < (int)a.n_s; k += blockDim.x) lg[k] = grow[k];
-    __syncthreads();
-    tab_stage_A(a, lg, lq, lA);
-    __syncthreads();
-    tab_block<UR>(a, lg, lq, lA, lo, lm, r, pb, W, wave, lane);
+    if constexpr (PAIRS) {
+      double2 *lp = reinterpret_cast<double2 *>(lg);
+      for (int k = threadIdx.x; k < (int)a.n_s - 1; k += blockDim.x) {
+        const double g0 = grow[k], g1 = grow[k + 1];
+        lp[k] = make_double2(g0, g1 - g0);
+      }
+      __syncthreads();
+      const PairRow row{lp};
+      tab_stage_A(a, row, lq, lA);
+      __syncthreads();
+      tab_block<UR>(a, row, lq, lA, lo, lm, r, pb, W, wave, lane);
+    } else {
+      for (int k = threadIdx.x; k < (int)a.n_s; k += blockDim.x) lg[k] = grow[k];
+      __syncthreads();
+      const PlainRow row{lg};
+      tab_stage_A(a, row, lq, lA);
+      __syncthreads();
+      tab_block<UR>(a, row, lq, lA, lo, lm, r, pb, W, wave, lane);
+    }
   } else {
     const int x = blockIdx.x & 7;
     const int64_t slot = blockIdx.x >> 3, slots = gridDim.x >> 3;
     for (int64_t r = x; r < a.n_rows; r += 8) {
-      const double *grow = a.g + r * a.n_s;
+      const PlainRow grow{a.g + r * a.n_s};
       __syncthreads();  // the previous row's A_i are no longer read
       tab_stage_A(a, grow, lq, lA);
       __syncthreads();
@@ -158,12 +194,22 @@ void tab_lane_split(int n_r, int n_a, int *R, int *J, int *T, int *U) {
 }
 
 int tab_lds_bytes(const TabArgs &t, bool lds_rows) {
-  return (int)(sizeof(double) * (2 * t.n_r + 2 * t.n_a + (lds_rows ? t.n_s : 0)));
+  const int row = !lds_rows ? 0 : t.pairs ? (int)(2 * (t.n_s - 1)) : (int)t.n_s;
+  return (int)(sizeof(double) * (2 * t.n_r + 2 * t.n_a + row));
 }
 
-template <bool L, int UR>
+// Dynamic LDS beyond 64 KiB (gfx950: 160 KiB per workgroup); a refusal where
+// no opt-in is needed is cleared so that it cannot be taken for a launch error.
+static void tab_allow_large_lds(const void *fn) {
+  (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  (void)hipGetLastError();
+}
+
+template <bool L, int UR, bool P>
 static void tab_launch_t(const TabArgs &t, int W, int64_t blocks, hipStream_t st) {
-  hipLaunchKernelGGL((tab_kernel<L, UR>), dim3((unsigned)blocks), dim3(kWave * W),
+  static const bool once = (tab_allow_large_lds((const void *)&tab_kernel<L, UR, P>), true);
+  (void)once;
+  hipLaunchKernelGGL((tab_kernel<L, UR, P>), dim3((unsigned)blocks), dim3(kWave * W),
                      tab_lds_bytes(t, L), st, t);
 }
 
@@ -175,10 +221,13 @@ int launch_tab(const TabArgs &t, int reg, int W, bool lds_rows, int64_t stream_b
   const bool regs = t.U <= 4;
   if (lds_rows) {
     const int64_t blocks = t.n_rows * t.n_pb;
-    regs ? tab_launch_t<true, 4>(t, W, blocks, st) : tab_launch_t<true, 0>(t, W, blocks, st);
+    if (t.pairs)
+      regs ? tab_launch_t<true, 4, true>(t, W, blocks, st) : tab_launch_t<true, 0, true>(t, W, blocks, st);
+    else
+      regs ? tab_launch_t<true, 4, false>(t, W, blocks, st) : tab_launch_t<true, 0, false>(t, W, blocks, st);
   } else {
     const int64_t blocks = 8 * ((stream_blocks + 7) / 8);
-    regs ? tab_launch_t<false, 4>(t, W, blocks, st) : tab_launch_t<false, 0>(t, W, blocks, st);
+    regs ? tab_launch_t<false, 4, false>(t, W, blocks, st) : tab_launch_t<false, 0, false>(t, W, blocks, st);
   }
   return (int)hipGetLastError();
 }

@@ -30,7 +30,8 @@ def dev(a):
     return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
 
 
-def run_tab(ctx, q, g, s_max, p, lds_nodes=6144, pw=16, W=4):
+def run_tab(ctx, q, g, s_max, p, lds_nodes=6144, pw=16, W=4, pairs=1):
+    frg.frg_tune_set(ctx, "tab_pairs", pairs)
     frg.frg_tune_set(ctx, "tab_lds_nodes", lds_nodes)
     frg.frg_tune_set(ctx, "tab_pw", pw)
     frg.frg_tune_set(ctx, "tab_W", W)
@@ -66,6 +67,8 @@ def test_tab_matches_oracle_and_forms_agree(ctx, d, reg, n_r, n_a):
     assert err.max() < RTOL
     streamed = run_tab(ctx, q, g, s_max, p, lds_nodes=2, pw=5, W=3)
     assert np.array_equal(streamed, got)
+    values = run_tab(ctx, q, g, s_max, p, pairs=0)  # rows in LDS as values
+    assert np.array_equal(values, got)
 
 
 def test_tab_long_rows_sampled(ctx):
