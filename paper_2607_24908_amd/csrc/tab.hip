@@ -27,10 +27,15 @@ using namespace dev;
 // A table row as plain values g_k (rows read from memory, or staged in LDS
 // as they are) or as pairs (g_k, g_{k+1} - g_k) (rows staged in LDS): one
 // 16-byte read per evaluation; both give the same bits.
+// fetch(k) = (g_k, g_{k+1} - g_k); the value at t = k + f is g_k + f (g_{k+1} - g_k).
 struct PlainRow {
   const double *g;
   __device__ __forceinline__ double operator()(double t, double t_last, int k_last) const {
     return interp(g, t, t_last, k_last);
+  }
+  __device__ __forceinline__ double2 fetch(int k) const {
+    const double g0 = g[k], g1 = g[k + 1];
+    return make_double2(g0, g1 - g0);
   }
 };
 struct PairRow {
@@ -43,6 +48,7 @@ struct PairRow {
     const double2 gd = p[k];
     return __builtin_fma(f, gd.y, gd.x);
   }
+  __device__ __forceinline__ double2 fetch(int k) const { return p[k]; }
 };
 
 // One (row, momentum block) of work: A_i of the row, then W * pw momenta.
@@ -84,11 +90,24 @@ __device__ __forceinline__ void tab_block(const TabArgs &a, const Row row, const
         const double bh = ((2.0 * q) * p) * a.inv_h;
         double inner = 0.0;
         if (UR > 0) {
+          // all table indices first, then all reads, then the sums (the
+          // reads of the UR terms are in flight together)
+          int kq[UR > 0 ? UR : 1];
+          double fq[UR > 0 ? UR : 1];
 #pragma unroll
           for (int u = 0; u < UR; ++u) {
-            const double G = row(__builtin_fma(bh, ro[u], ah), a.t_last, k_last);
-            inner = __builtin_fma(rm[u], G, inner);
+            const double t = fmin(__builtin_fma(bh, ro[u], ah), a.t_last);
+            int k = (int)t;
+            k = k < k_last ? k : k_last;
+            kq[u] = k;
+            fq[u] = t - (double)k;
           }
+          double2 gd[UR > 0 ? UR : 1];
+#pragma unroll
+          for (int u = 0; u < UR; ++u) gd[u] = row.fetch(kq[u]);
+#pragma unroll
+          for (int u = 0; u < UR; ++u)
+            inner = __builtin_fma(rm[u], __builtin_fma(fq[u], gd[u].y, gd[u].x), inner);
         } else {
           for (int u = 0; u < a.U; ++u) {
             const int j = iota + a.J * u;
