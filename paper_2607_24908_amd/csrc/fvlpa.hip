@@ -46,27 +46,28 @@ __global__ __launch_bounds__(256) void fv_init_kernel(FvArgs a, double t_end) {
   }
 }
 
-// Broadcast lane l's double to the wave (uniform).
-__device__ __forceinline__ double lane_value(double v, int l) {
-  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-  const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, l);
-  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), l);
-  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+// Sum over the 8 lanes of an aligned group (xor 1, xor 2, then the mirror
+// of the 8 lanes, equivalent to xor 4 once each quad holds equal values).
+__device__ __forceinline__ double group8_sum(double x) {
+  x = x + dpp_f64<0xB1>(x);
+  x = x + dpp_f64<0x4E>(x);
+  return x + dpp_f64<0x141>(x);
 }
 
-// Grid (interface blocks of 4, flows): one wave per (flow, interface);
-// lanes over the radial nodes of F_1, F_2 at up to three masses (d_sigma u
-// and the two Goldstone states), reduced together.
+// Grid (blocks of 32 interfaces, flows): eight interfaces per wave, eight
+// lanes per interface over the radial nodes of F_1, F_2 at up to three masses
+// (d_sigma u and the two Goldstone states), reduced within the 8 lanes.
 __global__ __launch_bounds__(256) void fv_flux_kernel(FvArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const int wave = threadIdx.x / kWave;
+  const int sub = lane & 7;
   const int64_t r = blockIdx.y;
   const int64_t n = a.n, nq = n + 1;
-  const int64_t j = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave;
-  if (j >= nq) return;  // wave-uniform
+  const int64_t j = ((int64_t)blockIdx.x * (blockDim.x / kWave) + wave) * 8 + (lane >> 3);
+  const bool live = j < nq;  // every lane takes part in the group sums
   const int64_t o = r * nq + j;
-  if (!a.alive[r]) {
-    if (lane == 0) {
+  if (!a.alive[r]) {  // workgroup-uniform
+    if (live && sub == 0) {
       a.Q[o] = 0.0;
       a.lam[o] = 0.0;
     }
@@ -105,30 +106,28 @@ __global__ __launch_bounds__(256) void fv_flux_kernel(FvArgs a) {
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
     const double delta = m2[m] + a.k2;
-    bad |= m < nm && !(delta > 0.0);
+    bad |= live && m < nm && !(delta > 0.0);
     dh[m] = (m < nm && delta > 0.0) ? delta * a.inv_k2 : 1.0;
   }
-  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // s1, s2 per mass
-  for (int i = lane; i < a.n_r; i += kWave) {
+  double s1[3] = {0.0, 0.0, 0.0}, s2[3] = {0.0, 0.0, 0.0};
+  for (int i = sub; i < a.n_r; i += 8) {
     const double c = a.tab[i], hh = a.tab[a.n_r + i];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
       if (m >= nm) break;
       const double G = rcp64(hh + dh[m]);
       const double cg = c * G;
-      acc[2 * m] += cg;
-      acc[2 * m + 1] = __builtin_fma(cg, G, acc[2 * m + 1]);
+      s1[m] += cg;
+      s2[m] = __builtin_fma(cg, G, s2[m]);
     }
   }
-  // lane l ends with the total of acc[l / 8]
-  const double tot = wave_sum_fold<8>(acc, lane);
   double F1[3], F2[3];
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
-    F1[m] = a.Cd * a.kd * lane_value(tot, 16 * m);
-    F2[m] = a.Cd * a.kdm2 * lane_value(tot, 16 * m + 8);
+    F1[m] = a.Cd * a.kd * group8_sum(s1[m]);
+    F2[m] = a.Cd * a.kdm2 * group8_sum(s2[m]);
   }
-  if (lane != 0) return;
+  if (!live || sub != 0) return;
   if (bad) {
     // the flow ends at the start of this step with its state kept
     a.alive[r] = 0;
@@ -210,7 +209,7 @@ int launch_fv_init(const FvArgs &a, double t_end, void *stream) {
 
 int launch_fv_flux(const FvArgs &a, void *stream) {
   if (a.n_rows <= 0) return 0;
-  hipLaunchKernelGGL(fv_flux_kernel, dim3((unsigned)((a.n + 1 + 3) / 4), (unsigned)a.n_rows),
+  hipLaunchKernelGGL(fv_flux_kernel, dim3((unsigned)((a.n + 1 + 31) / 32), (unsigned)a.n_rows),
                      dim3(256), 0, (hipStream_t)stream, a);
   return (int)hipGetLastError();
 }
