@@ -1,0 +1,69 @@
+"""Edge cases across the entry points: empty problems are no-ops (host and
+device memory), the largest azimuthal order of the vertex diagram."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2607_24908_amd import frg
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    h = frg.frg_create(0)
+    yield h
+    torch.cuda.synchronize()
+    frg.frg_destroy(h)
+
+
+def test_empty_problems_are_noops(ctx):
+    quad = frg.make_quad(3, frg.FRG_REG_EXP, 1.0, 6.0, 32, 8)
+    e = np.zeros(0)
+    one = np.ones(1)
+    out = np.full(4, 7.0)
+    H = frg.FRG_MEM_HOST
+    assert frg.frg_integrate_grid(ctx, quad, e, one, out, mem=H) == frg.FRG_OK
+    assert frg.frg_integrate_grid(ctx, quad, one, e, out, mem=H) == frg.FRG_OK
+    assert frg.frg_integrate_vertex(ctx, quad, 8, e, e, e, one, out, mem=H) == frg.FRG_OK
+    assert frg.frg_integrate_vertex(ctx, quad, 8, one, one, one, e, out, mem=H) == frg.FRG_OK
+    assert np.all(out == 7.0)
+    de = torch.zeros(0, dtype=torch.float64, device="cuda")
+    d1 = torch.ones(1, dtype=torch.float64, device="cuda")
+    dout = torch.full((4,), 7.0, dtype=torch.float64, device="cuda")
+    frg.frg_integrate_grid(ctx, quad, de, d1, dout)
+    frg.frg_integrate_vertex(ctx, quad, 8, d1, d1, d1, de, dout)
+    pf = frg.make_pflow(3, frg.FRG_REG_EXP, 16, 8, 1.0, 6.0, 9, 4.0)
+    assert frg.frg_pflow_solve(ctx, pf, e, e, -1.0, 4, e, e, mem=H) == frg.FRG_OK
+    assert frg.frg_pflow_rhs(ctx, pf, e, e, 0.0, e, e, mem=H) == frg.FRG_OK
+    fv = frg.make_fvlpa(3, 2, frg.FRG_REG_EXP, 16, 1.0, 6.0, 8, 1.0)
+    assert frg.frg_fvlpa_solve(ctx, fv, -1.0, 4, e, e, mem=H) == frg.FRG_OK
+    assert frg.frg_fvlpa_rhs(ctx, fv, 0.0, e, e, mem=H) == frg.FRG_OK
+    torch.cuda.synchronize()
+    assert torch.all(dout == 7.0)
+
+
+@pytest.mark.parametrize("n_phi", [64, 40])
+def test_vertex_largest_azimuthal_orders(ctx, n_phi):
+    """n_phi = 64 (two 32-term groups per pair), 40 (the second one padded)."""
+    print(f"[case] vertex n_phi={n_phi}", flush=True)
+    rng = np.random.Generator(np.random.PCG64(n_phi))
+    d, reg, k, n_r, n_a = 3, frg.FRG_REG_EXP, 1.1, 12, 5
+    p1 = np.concatenate([[0.0], 10 ** rng.uniform(-2, 1, 5)])
+    p2 = np.concatenate([[1.0], 10 ** rng.uniform(-2, 1, 5)])
+    c12 = np.concatenate([[0.5], rng.uniform(-1, 1, 5)])
+    m2 = rng.uniform(-0.9 * k * k, 5.0, 9)
+    quad = frg.make_quad(d, reg, k, 6 * k, n_r, n_a)
+    out = torch.full((p1.size * m2.size,), float("nan"), dtype=torch.float64, device="cuda")
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    frg.frg_integrate_vertex(ctx, quad, n_phi, t(p1), t(p2), t(c12), t(m2), out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    want = oracle.integrate_vertex(d, reg, k, 6 * k, n_r, n_a, n_phi, np.repeat(p1, m2.size),
+                                   np.repeat(p2, m2.size), np.repeat(c12, m2.size),
+                                   np.tile(m2, p1.size), threads=8)
+    err = np.abs(got - want) / np.abs(want)
+    print(f"  max rel err {err.max():.3e}")
+    assert err.max() < 1e-12
