@@ -181,8 +181,31 @@ __device__ __forceinline__ double swap_add(double a, double b) {
 // is the same for every M: lane offsets 32, 16, 8, then 1, 2 and 4 (as the
 // half-row mirror, equivalent once each quad holds equal values), each step
 // own + partner.  The first log2 M steps halve the number of live values (a
-// lane keeps the half selected by the offset's bit of its index), so lane l
-// ends with the total of value l / (64 / M), the same bits for every M.
+// lane keeps the half selected by the offset's bit of its index), so every
+// lane ends with the total of one value, the same bits for every M: value
+// fold_owner<M>(lane) = lane / (64/M); fold_leader<M>(lane) marks one lane
+// per value.
+template <int M>
+__device__ __forceinline__ int fold_owner(int lane) {
+  return lane / (64 / M);
+}
+template <int M>
+__device__ __forceinline__ bool fold_leader(int lane) {
+  return lane % (64 / M) == 0;
+}
+
+// Split step at offset 8 (DPP rotation by 8 within a row of 16): a lane
+// keeps w[k] or w[h + k] by bit 3 of its index and adds the partner's copy
+// of the same value.
+template <int CTRL, int BIT>
+__device__ __forceinline__ double split_dpp(double lo, double hi, int lane) {
+  asm("" : "+v"(lo), "+v"(hi));
+  const bool upper = (lane & BIT) != 0;
+  const double keep = upper ? hi : lo;
+  const double send = upper ? lo : hi;
+  return keep + dpp_f64<CTRL>(send);
+}
+
 template <int M>
 __device__ __forceinline__ double wave_sum_fold(const double *v, int lane) {
   static_assert(M == 1 || M == 2 || M == 4 || M == 8, "M must be 1, 2, 4 or 8");
@@ -205,17 +228,13 @@ __device__ __forceinline__ double wave_sum_fold(const double *v, int lane) {
   }
   // offset 8 (rotation by 8 within a row of 16 is the exchange of offset 8)
   double x;
-  if constexpr (M == 8) {
-    double lo = w[0], hi = w[1];
-    asm("" : "+v"(lo), "+v"(hi));
-    const bool upper = (lane & 8) != 0;
-    const double keep = upper ? hi : lo;
-    const double send = upper ? lo : hi;
-    x = keep + dpp_f64<0x128>(send);
+  if constexpr (M >= 8) {
+#pragma unroll
+    for (int k = 0; k < M / 8; ++k) w[k] = split_dpp<0x128, 8>(w[k], w[M / 8 + k], lane);
   } else {
-    x = w[0] + dpp_f64<0x128>(w[0]);
+    w[0] = w[0] + dpp_f64<0x128>(w[0]);
   }
-  x = x + dpp_f64<0xB1>(x);
+  x = w[0] + dpp_f64<0xB1>(w[0]);  // offset 1
   x = x + dpp_f64<0x4E>(x);
   x = x + dpp_f64<0x141>(x);
   return x;

@@ -217,8 +217,8 @@ __global__ __launch_bounds__(512) void grid32_kernel(GridArgs g) {
     // the masses are the same in every lane: make the choices wave-uniform
     okm = __builtin_amdgcn_readfirstlane(okm);
     m32 = __builtin_amdgcn_readfirstlane(m32);
-    const int mine = lane / (kWave / M);
-    const bool leader = lane % (kWave / M) == 0;
+    const int mine = fold_owner<M>(lane);
+    const bool leader = fold_leader<M>(lane);
     double s32 = 0.0, err32 = 0.0;
     unsigned flagged = 0;
     if (m32) {
@@ -229,8 +229,8 @@ __global__ __launch_bounds__(512) void grid32_kernel(GridArgs g) {
         grid32_resident<M, true>(g, lc, lq, lH32, lrho, lgam, lane, dm, dh, m32, tot, var);
       else
         grid32_resident<M, false>(g, lc, lq, lH32, lrho, lgam, lane, dm, dh, m32, tot, var);
-      s32 = wave_sum_split<M>(tot, lane);
-      const double v32 = wave_sum_split<M>(var, lane);
+      s32 = wave_sum_fold<M>(tot, lane);
+      const double v32 = wave_sum_fold<M>(var, lane);
       double ed = 0.0;
 #pragma unroll
       for (int m = 0; m < M; ++m) ed = (m == mine) ? edel[m] : ed;
@@ -299,19 +299,11 @@ static void grid32_launch_t(const GridArgs &g, int W, hipStream_t st) {
 int launch_grid32(const GridArgs &g, int reg, int M, int W, void *stream) {
   if (g.n_p <= 0 || g.n_m <= 0) return 0;
   hipStream_t st = (hipStream_t)stream;
-  if (reg == kExp) {
-    switch (M) {
-      case 4: grid32_launch_t<kExp, 4>(g, W, st); break;
-      case 8: grid32_launch_t<kExp, 8>(g, W, st); break;
-      default: grid32_launch_t<kExp, 16>(g, W, st); break;
-    }
-  } else {
-    switch (M) {
-      case 4: grid32_launch_t<kLitim, 4>(g, W, st); break;
-      case 8: grid32_launch_t<kLitim, 8>(g, W, st); break;
-      default: grid32_launch_t<kLitim, 16>(g, W, st); break;
-    }
-  }
+  if (M != 4 && M != 8) return (int)hipErrorInvalidValue;  // the host passes M <= 8
+  if (reg == kExp)
+    M == 8 ? grid32_launch_t<kExp, 8>(g, W, st) : grid32_launch_t<kExp, 4>(g, W, st);
+  else
+    M == 8 ? grid32_launch_t<kLitim, 8>(g, W, st) : grid32_launch_t<kLitim, 4>(g, W, st);
   return (int)hipGetLastError();
 }
 

@@ -295,13 +295,13 @@ __device__ __forceinline__ void coef_blocks(const GridArgs &g, const double *lC,
       for (int m = 0; m < M; ++m)
         if ((sm >> m) & 1u) tot[m] = single(dm[m]);
     }
-    // lane l ends with the total of mass l / (64 / M); the coefficient form
+    // lane l ends with the total of mass fold_owner(l); the coefficient form
     // carries the factor kap / sig^(E+1) (folded into pref_c)
     const double s = wave_sum_fold<M>(tot, lane);
-    const int mine = lane / (kWave / M);
+    const int mine = fold_owner<M>(lane);
     const double v = (((cmask >> mine) & 1u) ? g.pref_c : g.pref) * s;
     const bool okm = (okbits >> mine) & 1u;
-    const bool mine_out = lane % (kWave / M) == 0 && ((validbits >> mine) & 1u);
+    const bool mine_out = fold_leader<M>(lane) && ((validbits >> mine) & 1u);
     if (REDO) {
       // the FP32 kernel has already written the other points and the flag
       if (mine_out && ((act >> mine) & 1u)) {
