@@ -26,21 +26,23 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# ALU roofline of the FP64 path.  Issue rate of the FP64 VALU of MI355X:
-# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 lane-cycles/s.  Floor of
-# the per-evaluation work of the grid kernel: for one radial node and a group
-# of G angular terms of a lane, c/(Hq + delta)^2 sum_k mu_k/(delta + H_k) =
-# N(delta)/P(delta) with per-momentum polynomial coefficients, so each
-# (term, mass) costs one Horner FMA of P and one of N; the two extra FMAs of
-# the radial factor, the reciprocal of P, its Newton step and the
-# accumulation are shared by the G = 32 terms of a group and the coefficient
-# build by every mass of the momentum, and are left out of the floor: 2 FP64
-# operations per eval.
+# ALU roofline of the FP64 path.  FP64 rate of MI355X: 78.6 TFLOP/s, i.e.
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 FMA/s, the same on the
+# vector units and on the FP64 matrix cores, which share it (a kernel that
+# mixes the two takes the sum of their times).  Floor of the per-evaluation
+# work of the grid kernel: for one radial node and a group of G angular terms
+# of a lane row, c/(Hq + delta)^2 sum_k mu_k/(delta + H_k) = N(delta)/P(delta)
+# with per-momentum polynomial coefficients, so each (term, mass) costs one
+# multiply-add of P and one of N (power sums over 16-mass tiles on the matrix
+# cores, or nested on the vector units); the two extra powers of the radial
+# factor, the reciprocal of P, its Newton step and the accumulation are
+# shared by the G = 32 terms of a group and the coefficient build by every
+# mass of the momentum, and are left out of the floor: 2 FMAs per eval.
 VALU_LANE_CYCLES = 256 * 4 * 16 * 2.4e9
 # HBM bytes per grid-kernel launch from rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # scaled by a 1 GiB device copy read the same way (fetch x2.00, write x1.00):
-# 487.5 KiB x 2.00 + 16384 KiB x 1.00.
-TRAFFIC = 487.5 * 1024 * 2.00 + 16384 * 1024 * 1.00
+# 461.5 KiB x 2.00 + 16384 KiB x 1.00.
+TRAFFIC = 461.5 * 1024 * 2.00 + 16384 * 1024 * 1.00
 CYCLES_PER_EVAL_FLOOR = 2
 PEAK_EVALS = VALU_LANE_CYCLES / CYCLES_PER_EVAL_FLOOR
 
@@ -225,9 +227,10 @@ def main():
         "integrals_per_s": w.n_integrals / (ms_step * 1e-3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_EVALS / 1e9,
                      "unit": "Geval/s", "frac": achieved * 1e9 / PEAK_EVALS, "traffic": TRAFFIC,
-                     "kernel": "grid_coef_kernel<exp>", "kernel_ms": gpu_ms,
+                     "kernel": "grid_coef_kernel<exp> (16-mass tiles, FP64 matrix cores)",
+                     "kernel_ms": gpu_ms,
                      "evals_per_launch": int(w.n_evals), "traffic_unit": "bytes per launch",
-                     "peak_basis": "FP64 VALU 3.93e13 lane-cycles/s / 2 cycles per eval"},
+                     "peak_basis": "FP64 3.93e13 FMA/s (vector or matrix) / 2 FMAs per eval"},
     }
     if not args.no_secondary:
         line["secondary"] = secondary(ctx, frg, workloads, torch)

@@ -412,7 +412,10 @@ int frg_autotune(frg_ctx *ctx, int32_t mode, const char *cache_path);
  * per lane, radial node and group of up to 32 angular terms, radial factor
  * included, when the table fits in LDS, the default; 1: eight-term running
  * fractions as in frg_integrate; 2 / 3: coefficients in groups of 8 / 16;
- * the forms agree to a few ulp), "grid_lds_rows" (8..96), "plain_tile", "persist_tile" (1..64),
+ * the forms agree to a few ulp), "grid_mfma" (coefficient form, 1: power
+ * sums over tiles of 16 masses on the FP64 matrix cores, the default; 0:
+ * nested evaluation on the vector units, at most 8 masses per wave; the two
+ * agree to a few ulp), "grid_lds_rows" (8..96), "plain_tile", "persist_tile" (1..64),
  * "persist_wpc" (1..64), and of the tabulated variant "tab_W" (1..4),
  * "tab_pw" (momenta per wave, 1..64), "tab_lds_nodes" (2..6144),
  * "tab_pairs" (1: rows in LDS as (value, slope) pairs, the default; 0: as

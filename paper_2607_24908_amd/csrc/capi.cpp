@@ -524,7 +524,10 @@ int Ctx::grid_device(const frg_quad &q, int64_t n_p, const double *p, int64_t n_
 int Ctx::grid_launch(GridArgs g, int reg, const GridCfg &cfg_in, hipStream_t st, int kind) {
   const bool resident = kind == 1 ? true : grid_resident(g);
   GridCfg cfg = cfg_in;
-  if ((kind == 1 || grid_uses_coef(g)) && cfg.M > 8) cfg.M = 8;  // at most 8 masses per wave there
+  if (kind == 1 && cfg.M > 8) cfg.M = 8;  // FP32C kernel: at most 8 masses per wave
+  // coefficient form: tiles of 16 masses on the matrix cores, or at most 8
+  // masses per wave on the vector units
+  if (kind != 1 && grid_uses_coef(g)) cfg.M = tune.grid_mfma ? 16 : std::min(cfg.M, 8);
   const int64_t per_wg_min = (int64_t)cfg.M * cfg.W;
   // mass blocks per wave: fewer workgroups per momentum, but keep at least
   // ~4 workgroups per CU in flight

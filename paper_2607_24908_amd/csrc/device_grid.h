@@ -454,6 +454,91 @@ __device__ __forceinline__ void grid_fold_rows(const GridArgs &g, const double *
   }
 }
 
+// ------------------------------------- coefficient form, matrix cores --
+// For a tile of 16 masses x_j the values P_r(x_j) and N_r(x_j) of every lane
+// row r of the table are the products A_P V and A_N V of the coefficient
+// rows with the power matrix V[k][j] = x_j^k: dense contractions over k,
+// taken four powers at a time by v_mfma_f64_16x16x4f64 on a 16-row slice of
+// a 64-row group.  Operand layout of that instruction (A 16 x 4, B 4 x 16,
+// D 16 x 16): lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and
+// holds D[4 e + l / 16][l % 16] in element e of the result.  Lane l thus
+// ends with N/P of four rows of mass l % 16 and sums them in place.
+// Every coefficient and every x_j^k is >= 0 (H >= 0, weights > 0, x > 0),
+// so the power sums carry no cancellation and round like the nested form;
+// each term is at most P(x) or N(x), inside the range of FoldRange.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// P has G + E stored coefficients, then the monic 1 and zero padding to a
+// multiple of four powers: G/4 + 1 slices of k (E = 2, 3).  N: G/4 slices.
+template <int G, int E>
+struct MfmaShape {
+  static_assert(G % 4 == 0 && (E == 2 || E == 3), "G a multiple of 4, E 2 or 3");
+  static constexpr int kP = G / 4 + 1, kN = G / 4;
+};
+
+// x^(4c + e) for c < kP, e = lane / 16: the lane's entries of V.  Powers
+// above G + E (zero coefficients, padding) are set to 0, not computed: they
+// lie outside the range of FoldRange (x^(G+3) overflows for G = 8 near hi),
+// and 0 * inf would poison the sum.
+template <int G, int E>
+__device__ __forceinline__ void mfma_powers(double x, int lane, double *v) {
+  constexpr int kP = MfmaShape<G, E>::kP;
+  const int e = lane >> 4;
+  const double x2 = x * x;
+  const double x4 = x2 * x2;
+  v[0] = e == 0 ? 1.0 : e == 1 ? x : e == 2 ? x2 : x2 * x;
+#pragma unroll
+  for (int c = 1; c < kP; ++c) v[c] = v[c - 1] * x4;
+  if (e > E) v[kP - 1] = 0.0;
+}
+
+// Two 16-row slices (rows 16 s0 + ., 16 s1 + . of one group): four
+// independent accumulator chains.
+template <int G, int E>
+__device__ __forceinline__ void mfma_slice_pair(const double *grp, int lane, const double *v,
+                                                int s0, int s1, double &tot) {
+  constexpr int kP = MfmaShape<G, E>::kP, kN = MfmaShape<G, E>::kN;
+  const int e = lane >> 4;
+  const double *a0 = grp + 16 * s0 + (lane & 15) + e * kWave;  // A[row][k] at grp[k 64 + row]
+  const double *a1 = grp + 16 * s1 + (lane & 15) + e * kWave;
+  const dbl4 z = {0.0, 0.0, 0.0, 0.0};
+  dbl4 P0 = z, N0 = z, P1 = z, N1 = z;
+#pragma unroll
+  for (int c = 0; c < kN; ++c) {
+    P0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[4 * c * kWave], v[c], P0, 0, 0, 0);
+    P1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[4 * c * kWave], v[c], P1, 0, 0, 0);
+    N0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[(G + E + 4 * c) * kWave], v[c], N0, 0, 0, 0);
+    N1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[(G + E + 4 * c) * kWave], v[c], N1, 0, 0, 0);
+  }
+  // last slice of P: power G + e is stored for e < E, the monic 1 at e = E
+  const double tail = e == E ? 1.0 : 0.0;
+  const double l0 = e < E ? a0[4 * (kP - 1) * kWave] : tail;
+  const double l1 = e < E ? a1[4 * (kP - 1) * kWave] : tail;
+  P0 = __builtin_amdgcn_mfma_f64_16x16x4f64(l0, v[kP - 1], P0, 0, 0, 0);
+  P1 = __builtin_amdgcn_mfma_f64_16x16x4f64(l1, v[kP - 1], P1, 0, 0, 0);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) tot = __builtin_fma(N0[r], rcp64(P0[r]), tot);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) tot = __builtin_fma(N1[r], rcp64(P1[r]), tot);
+}
+
+// Lane partial (four rows per 16-row slice, every slice of the table) of
+// sum_r N_r(x)/P_r(x) for mass x = x_{lane % 16}; the whole wave takes part.
+template <int G, int E>
+__device__ __forceinline__ double mfma_fold_rows(const GridArgs &g, const double *lC, int lane,
+                                                 double x, const FoldShape<G, E> &fs) {
+  double v[MfmaShape<G, E>::kP];
+  mfma_powers<G, E>(x, lane, v);
+  double tot = 0.0;
+  const int n_grp = g.T * fs.NG;
+  for (int tg = 0; tg < n_grp; ++tg) {
+    const double *grp = lC + tg * (2 * G + E) * kWave;
+    mfma_slice_pair<G, E>(grp, lane, v, 0, 1, tot);
+    mfma_slice_pair<G, E>(grp, lane, v, 2, 3, tot);
+  }
+  return tot;
+}
+
 
 // ------------------------------------------------ vertex diagram --
 // Lane rows are (radial, polar) node pairs pi = lane + 64 t (i = pi / n_a,

@@ -80,6 +80,7 @@ struct Tune {
   PersistCfg persist;
   int grid_lds_rows = 64;  // (t, u) rows of 64 doubles staged per LDS chunk
   int grid_form = 0;       // resident FP64 grid: 0 per-momentum coefficients, 1 running fractions
+  int grid_mfma = 1;       // coefficient form: 1 tiles of 16 masses on the matrix cores, 0 vector units
   int fp32c_flag_ppb = 100;    // FP32C: FP64 redo above this error estimate (1e-9 units)
   int fp32c_band_ppm = 10000;  // FP32C: FP64 below this delta/k^2 (1e-6 units)
   int mode = 0;            // 0: defaults and cached choices, 1: tune new keys

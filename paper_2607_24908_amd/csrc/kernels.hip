@@ -316,6 +316,60 @@ __device__ __forceinline__ void coef_blocks(const GridArgs &g, const double *lC,
   }
 }
 
+// The 16-mass tiles of one wave on the matrix cores (mfma_fold_rows): lane l
+// carries mass l % 16; the four lanes of a mass add their partials (offsets
+// 32 and 16, the same order in each of them).  Masses outside the range of
+// the coefficient form are evaluated at x = 1 there (in range, result
+// dropped) and take single(delta) with a full-wave sum.  The value of a mass
+// depends on its own column only: tile composition, W and MB change nothing.
+template <int G, int E, bool REDO, class Single>
+__device__ __forceinline__ void mfma_blocks(const GridArgs &g, const double *lC,
+                                            const unsigned *lmask, const double *ldm, int64_t a,
+                                            int64_t wg_m0, int MB, int W, int wave, int lane,
+                                            const FoldShape<G, E> &fs, Single single) {
+  constexpr int M = 16;
+  const int mine = lane & (M - 1);
+  for (int rep = 0; rep < MB; ++rep) {
+    const int b = rep * W + wave;
+    const int64_t m0 = wg_m0 + (int64_t)b * M;
+    if (m0 >= g.n_m) break;  // wave-uniform
+    const unsigned validbits = __builtin_amdgcn_readfirstlane(lmask[4 * b]);
+    const unsigned okbits = __builtin_amdgcn_readfirstlane(lmask[4 * b + 1]);
+    const unsigned cmask = __builtin_amdgcn_readfirstlane(lmask[4 * b + 2]);
+    const unsigned act = __builtin_amdgcn_readfirstlane(lmask[4 * b + 3]);
+    if (REDO && !act) continue;
+    const unsigned cm = act & cmask;
+    double s = 0.0;
+    if (cm) {
+      const double x = ((cm >> mine) & 1u) ? g.sig * ldm[b * M + mine] : 1.0;
+      s = mfma_fold_rows<G, E>(g, lC, lane, x, fs);
+      s = swap_add<32>(s, s);
+      s = swap_add<16>(s, s);
+    }
+    unsigned sm = act & ~cmask;
+    while (sm) {  // wave-uniform
+      const int m = __builtin_ctz(sm);
+      sm &= sm - 1u;
+      const double one = single(ldm[b * M + m]);
+      const double t = wave_sum_fold<1>(&one, lane);
+      if (mine == m) s = t;
+    }
+    const double v = (((cmask >> mine) & 1u) ? g.pref_c : g.pref) * s;
+    const bool okm = (okbits >> mine) & 1u;
+    const bool mine_out = lane < M && ((validbits >> mine) & 1u);
+    if (REDO) {
+      if (mine_out && ((act >> mine) & 1u)) {
+        const int64_t o = a * g.n_m + m0 + mine;
+        g.out[o] = okm ? v : __builtin_nan("");
+        if (g.err) g.err[o] = kErr64;
+      }
+      continue;
+    }
+    if ((validbits & ~okbits) && lane == 0) *g.flag = 1;
+    if (mine_out) g.out[a * g.n_m + m0 + mine] = okm ? v : __builtin_nan("");
+  }
+}
+
 // Tensor grid, resident coefficient form (device_grid.h): a workgroup owns
 // one momentum and W * M * MB masses; it builds the per-group coefficients of
 // its momentum once in LDS and every mass evaluates them by Horner.  REDO:
@@ -360,10 +414,13 @@ __global__ __launch_bounds__(512) void grid_coef_kernel(GridArgs g) {
   __syncthreads();
   if (table) grid_fill_fold<REG, G>(g, lC, lc, lq, lm, p, fs);
   __syncthreads();
-  coef_blocks<M, G, 2, REDO>(g, lC, lmask, ldm, a, wg_m0, MB, W, wave, lane, fs,
-                             [&](double delta) {
-                               return grid_single_mass<REG>(g, lc, lq, lm, lane, p, delta);
-                             });
+  auto single = [&](double delta) {
+    return grid_single_mass<REG>(g, lc, lq, lm, lane, p, delta);
+  };
+  if constexpr (M == 16)
+    mfma_blocks<G, 2, REDO>(g, lC, lmask, ldm, a, wg_m0, MB, W, wave, lane, fs, single);
+  else
+    coef_blocks<M, G, 2, REDO>(g, lC, lmask, ldm, a, wg_m0, MB, W, wave, lane, fs, single);
 }
 
 // Vertex diagram on a tensor grid (configurations x masses): a workgroup owns
@@ -663,8 +720,8 @@ static void coef_launch_t(const GridArgs &g, int W, bool redo, hipStream_t st) {
                        dim3(kWave * W), lds, st, g);
 }
 
-// Returns false when the shape has no kernel (the host passes M <= 8 for the
-// resident coefficient form and never asks a redo pass of streamed tables).
+// Returns false when the shape has no kernel (the host never asks a redo
+// pass of streamed tables).
 bool grid_uses_coef(const GridArgs &g) {
   return g.form != 1 && std::isnormal(g.pref_c) && std::isnormal(g.sig) &&
          grid_coef_lds_bytes(g) <= kGridCoefLdsMax;
@@ -675,18 +732,15 @@ bool grid_resident(const GridArgs &g) { return grid_uses_coef(g) || g.T * g.U <=
 template <int REG, int M>
 static bool grid_launch_t(const GridArgs &g, int W, bool redo, hipStream_t st) {
   if (grid_uses_coef(g)) {
-    if constexpr (M > 8) {
-      return false;
-    } else {
-      const int G = grid_coef_group(g);
-      if (G == 32)
-        coef_launch_t<REG, M, 32>(g, W, redo, st);
-      else if (G == 16)
-        coef_launch_t<REG, M, 16>(g, W, redo, st);
-      else
-        coef_launch_t<REG, M, 8>(g, W, redo, st);
-      return true;
-    }
+    // M = 16: tiles of 16 masses on the matrix cores; M <= 8: vector units
+    const int G = grid_coef_group(g);
+    if (G == 32)
+      coef_launch_t<REG, M, 32>(g, W, redo, st);
+    else if (G == 16)
+      coef_launch_t<REG, M, 16>(g, W, redo, st);
+    else
+      coef_launch_t<REG, M, 8>(g, W, redo, st);
+    return true;
   }
   const int64_t blocks = g.n_p * g.n_mb;
   if (g.T * g.U <= g.chunk) {

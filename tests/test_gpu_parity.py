@@ -139,7 +139,8 @@ def test_grid_launch_shapes_bitwise(ctx):
 
 def test_grid_forms_agree(ctx):
     """The resident forms of the grid kernel (coefficients with the group
-    size from the row length, groups of 8 and of 16, running fractions) all
+    size from the row length, groups of 8 and of 16, each as power sums on the
+    matrix cores and nested on the vector units; running fractions) all
     match the oracle; rows of several groups (64 x 48: two 32-term groups per
     lane row) and padded groups (100 x 12) included."""
     cases = [(3, frg.FRG_REG_EXP, 128, 32), (4, frg.FRG_REG_LITIM, 100, 12),
@@ -149,22 +150,25 @@ def test_grid_forms_agree(ctx):
     p = np.concatenate([[0.0], 10 ** rng.uniform(-3, 1.2, 12)])
     m2 = np.concatenate([[-k * k + 1e-6, 0.0], rng.uniform(-0.9 * k * k, 9.0, 29)])
     default = frg.frg_tune_get(ctx, "grid_form")
+    default_mfma = frg.frg_tune_get(ctx, "grid_mfma")
     try:
         for d, reg, n_r, n_a in cases:
             want = oracle.integrate_grid(d, reg, k, 6 * k, n_r, n_a, p, m2).ravel()
             quad = frg.make_quad(d, reg, k, 6 * k, n_r, n_a)
             outs = []
-            for form in (0, 1, 2, 3):
-                print(f"[case] forms {n_r}x{n_a} reg={reg} form={form}", flush=True)
+            for form, mfma in ((0, 1), (0, 0), (1, 1), (2, 1), (2, 0), (3, 1), (3, 0)):
+                print(f"[case] forms {n_r}x{n_a} reg={reg} form={form} mfma={mfma}", flush=True)
                 frg.frg_tune_set(ctx, "grid_form", form)
+                frg.frg_tune_set(ctx, "grid_mfma", mfma)
                 got = run_grid(ctx, quad, p, m2)
                 err = relerr(got, want)
-                assert err.max() < RTOL, (form, err.max())
+                assert err.max() < RTOL, (form, mfma, err.max())
                 outs.append(got)
             for o in outs[1:]:
                 assert close(o, outs[0])
     finally:
         frg.frg_tune_set(ctx, "grid_form", default)
+        frg.frg_tune_set(ctx, "grid_mfma", default_mfma)
 
 
 # --------------------------------------------------------- ragged shapes --
