@@ -473,11 +473,13 @@ __global__ __launch_bounds__(512) void vertex_kernel(GridArgs g) {
   __syncthreads();
   if (table) vertex_fill<REG, G>(g, lC, lc, lq, lx, lm, lsx, lcp, lnu, p1, p2, ct, st, fs);
   __syncthreads();
-  coef_blocks<M, G, 3, false>(g, lC, lmask, ldm, a, wg_m0, MB, W, wave, lane, fs,
-                              [&](double delta) {
-                                return vertex_single_mass<REG>(g, lc, lq, lx, lm, lsx, lcp, lnu,
-                                                               lane, p1, p2, ct, st, delta);
-                              });
+  auto single = [&](double delta) {
+    return vertex_single_mass<REG>(g, lc, lq, lx, lm, lsx, lcp, lnu, lane, p1, p2, ct, st, delta);
+  };
+  if constexpr (M == 16)
+    mfma_blocks<G, 3, false>(g, lC, lmask, ldm, a, wg_m0, MB, W, wave, lane, fs, single);
+  else
+    coef_blocks<M, G, 3, false>(g, lC, lmask, ldm, a, wg_m0, MB, W, wave, lane, fs, single);
 }
 
 // Coefficient of U[j+o] in U' (c1) and U'' (c2) of the difference formulas.
@@ -694,14 +696,20 @@ static void vertex_launch_m(const GridArgs &g, int W, hipStream_t st) {
     vertex_launch_t<REG, M, 8>(g, W, st);
 }
 
+// M = 16: tiles of 16 masses on the matrix cores; M = 4, 8: vector units.
 int launch_vertex(const GridArgs &g, int reg, int M, int W, void *stream) {
   if (g.n_p <= 0 || g.n_m <= 0) return 0;
   hipStream_t st = (hipStream_t)stream;
-  if (M != 4 && M != 8) return (int)hipErrorInvalidValue;
-  if (reg == kExp)
-    M == 8 ? vertex_launch_m<kExp, 8>(g, W, st) : vertex_launch_m<kExp, 4>(g, W, st);
-  else
-    M == 8 ? vertex_launch_m<kLitim, 8>(g, W, st) : vertex_launch_m<kLitim, 4>(g, W, st);
+  if (M != 4 && M != 8 && M != 16) return (int)hipErrorInvalidValue;
+  if (reg == kExp) {
+    if (M == 16) vertex_launch_m<kExp, 16>(g, W, st);
+    else if (M == 8) vertex_launch_m<kExp, 8>(g, W, st);
+    else vertex_launch_m<kExp, 4>(g, W, st);
+  } else {
+    if (M == 16) vertex_launch_m<kLitim, 16>(g, W, st);
+    else if (M == 8) vertex_launch_m<kLitim, 8>(g, W, st);
+    else vertex_launch_m<kLitim, 4>(g, W, st);
+  }
   return (int)hipGetLastError();
 }
 

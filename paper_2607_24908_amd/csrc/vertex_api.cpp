@@ -49,13 +49,14 @@ int Ctx::vertex_device(const frg_quad &q, int n_phi, int64_t n_c, const double *
   g.T = (q.n_radial * q.n_angular + kWave - 1) / kWave;  // (radial, polar) pairs per lane
   g.U = n_phi;
   set_fold_scale(g, h, 3);
-  // launch shape: the grid kernel's (M <= 8); mass blocks so that about four
+  // launch shape: the grid kernel's (tiles of 16 masses on the matrix cores,
+  // or M <= 8 on the vector units); mass blocks so that about four
   // workgroups per CU are in flight -- or one, when the table takes more than
   // half the LDS (one workgroup per CU can be resident; it gets eight waves,
   // two per SIMD, and splitting a configuration's masses over more
   // workgroups would only repeat its table build)
   GridCfg cfg = tune.grid;
-  if (cfg.M > 8) cfg.M = 8;
+  cfg.M = tune.grid_mfma ? 16 : std::min(cfg.M, 8);
   g.mblocks = 1;
   const bool big = vertex_lds_bytes(g, cfg.M, cfg.W, true) > 80 * 1024;
   if (big) cfg.W = 8;

@@ -72,19 +72,29 @@ def test_vertex_matches_oracle(ctx, d, reg, n_r, n_a, n_phi):
 
 
 def test_vertex_forms_agree(ctx):
-    """The per-term form (grid_form = 1) and the coefficient form agree."""
+    """The per-term form (grid_form = 1) and the coefficient form, as power
+    sums on the matrix cores (grid_mfma = 1) and nested on the vector units
+    (grid_mfma = 0), agree with each other and with the oracle."""
     rng = np.random.Generator(np.random.PCG64(4))
     p1, p2, c12 = configs(rng, 9)
     m2 = rng.uniform(-0.5, 6.0, 17)
     quad = frg.make_quad(3, EXP, 1.0, 6.0, 32, 8)
-    ref = run(ctx, quad, 16, p1, p2, c12, m2)
+    w = want(3, EXP, 1.0, 32, 8, 16, p1, p2, c12, m2)
     default = frg.frg_tune_get(ctx, "grid_form")
+    default_mfma = frg.frg_tune_get(ctx, "grid_mfma")
+    outs = []
     try:
-        frg.frg_tune_set(ctx, "grid_form", 1)
-        alt = run(ctx, quad, 16, p1, p2, c12, m2)
+        for form, mfma in ((0, 1), (0, 0), (1, 1), (1, 0)):
+            frg.frg_tune_set(ctx, "grid_form", form)
+            frg.frg_tune_set(ctx, "grid_mfma", mfma)
+            got = run(ctx, quad, 16, p1, p2, c12, m2)
+            assert np.max(np.abs(got - w) / np.abs(w)) < RTOL, (form, mfma)
+            outs.append(got)
     finally:
         frg.frg_tune_set(ctx, "grid_form", default)
-    assert np.all(np.abs(alt - ref) <= XTOL * np.abs(ref))
+        frg.frg_tune_set(ctx, "grid_mfma", default_mfma)
+    for alt in outs[1:]:
+        assert np.all(np.abs(alt - outs[0]) <= XTOL * np.abs(outs[0]))
 
 
 def test_vertex_range_boundaries(ctx):
@@ -115,17 +125,18 @@ def test_vertex_launch_shapes_bitwise(ctx):
     p1, p2, c12 = configs(rng, 7)
     m2 = rng.uniform(-0.5, 6.0, 75)
     quad = frg.make_quad(4, EXP, 1.0, 6.0, 24, 6)
-    keys = ("grid_M", "grid_W", "grid_MB")
+    keys = ("grid_M", "grid_W", "grid_MB", "grid_mfma")
     defaults = {key: frg.frg_tune_get(ctx, key) for key in keys}
     try:
-        ref = None
-        for M, W, MB in [(8, 4, 16), (4, 2, 1), (16, 8, 4), (4, 8, 8), (8, 1, 3)]:
-            for key, v in zip(keys, (M, W, MB)):
-                frg.frg_tune_set(ctx, key, v)
-            got = run(ctx, quad, 8, p1, p2, c12, m2)
-            if ref is None:
-                ref = got
-            assert np.array_equal(got, ref), (M, W, MB)
+        for mfma in (1, 0):
+            ref = None
+            for M, W, MB in [(8, 4, 16), (4, 2, 1), (16, 8, 4), (4, 8, 8), (8, 1, 3)]:
+                for key, v in zip(keys, (M, W, MB, mfma)):
+                    frg.frg_tune_set(ctx, key, v)
+                got = run(ctx, quad, 8, p1, p2, c12, m2)
+                if ref is None:
+                    ref = got
+                assert np.array_equal(got, ref), (mfma, M, W, MB)
     finally:
         for key, v in defaults.items():
             frg.frg_tune_set(ctx, key, v)
