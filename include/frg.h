@@ -415,7 +415,10 @@ int frg_autotune(frg_ctx *ctx, int32_t mode, const char *cache_path);
  * the forms agree to a few ulp), "grid_mfma" (coefficient form, 1: power
  * sums over tiles of 16 masses on the FP64 matrix cores, the default; 0:
  * nested evaluation on the vector units, at most 8 masses per wave; the two
- * agree to a few ulp), "grid_lds_rows" (8..96), "plain_tile", "persist_tile" (1..64),
+ * agree to a few ulp), "fv_persistent" (finite-volume solves, 1: one
+ * workgroup per flow runs the steps with its cells in LDS, the default where
+ * 3 n_cells + 2 n_radial doubles fit in 64 KiB; 0: two launches per stage;
+ * the same bits), "grid_lds_rows" (8..96), "plain_tile", "persist_tile" (1..64),
  * "persist_wpc" (1..64), and of the tabulated variant "tab_W" (1..4),
  * "tab_pw" (momenta per wave, 1..64), "tab_lds_nodes" (2..6144),
  * "tab_pairs" (1: rows in LDS as (value, slope) pairs, the default; 0: as

@@ -196,10 +196,11 @@ struct FvArgs {
   int *alive;
   double *t_reached;
   int *flag;
-  double Cd, k2, inv_k2, kd, kdm2;  // kd = k^d, kdm2 = k^(d-2)
+  double Cd, lambda;    // k = lambda e^t
+  double t;             // flux kernel: RG time of the stage
   double ds, inv_ds, h, t_n;
   int64_t n_rows, n;
-  int32_t n_r, N;
+  int32_t n_r, N, d;
   int32_t stage;       // 0..2 SSP-RK3 stages, 3: right-hand side only
   int32_t first;       // flux kernel: read y0 (first stage / rhs) instead of ys
 };
@@ -207,6 +208,11 @@ int launch_fv_init(const FvArgs &a, double t_end, void *stream);
 int launch_fv_flux(const FvArgs &a, void *stream);
 int launch_fv_stage(const FvArgs &a, void *stream);
 int launch_fv_dt(const FvArgs &a, void *stream);
+// Steps [s0, s0 + n_st) of a solve, one workgroup of `threads` per flow with
+// its state in LDS (fv_solve_lds_bytes); alive, t_reached and flag set up by
+// launch_fv_init.
+int fv_solve_lds_bytes(const FvArgs &a);
+int launch_fv_solve(const FvArgs &a, int64_t s0, int64_t n_st, int threads, void *stream);
 int launch_pflow_init(const PflowArgs &a, double t_end, void *stream);
 int launch_pflow_prep(const PflowArgs &a, int reg, void *stream);
 int launch_pflow_stage(const PflowArgs &a, int reg, void *stream);

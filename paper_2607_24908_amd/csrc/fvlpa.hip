@@ -54,27 +54,36 @@ __device__ __forceinline__ double group8_sum(double x) {
   return x + dpp_f64<0x141>(x);
 }
 
-// Grid (blocks of 32 interfaces, flows): eight interfaces per wave, eight
-// lanes per interface over the radial nodes of F_1, F_2 at up to three masses
-// (d_sigma u and the two Goldstone states), reduced within the 8 lanes.
-__global__ __launch_bounds__(256) void fv_flux_kernel(FvArgs a) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
-  const int sub = lane & 7;
-  const int64_t r = blockIdx.y;
-  const int64_t n = a.n, nq = n + 1;
-  const int64_t j = ((int64_t)blockIdx.x * (blockDim.x / kWave) + wave) * 8 + (lane >> 3);
-  const bool live = j < nq;  // every lane takes part in the group sums
-  const int64_t o = r * nq + j;
-  if (!a.alive[r]) {  // workgroup-uniform
-    if (live && sub == 0) {
-      a.Q[o] = 0.0;
-      a.lam[o] = 0.0;
-    }
-    return;
-  }
-  const double *u = (a.first ? a.y0 : a.ys) + r * n;
-  const double ds = a.ds, ids = a.inv_ds;
+// Scales of the stage at RG time t: k = lambda e^t, k^2, 1/k^2, k^d, k^(d-2)
+// (integer powers by products).  Every kernel forms them the same way.
+struct FvScale {
+  double k2, inv_k2, kd, kdm2;
+};
+__device__ __forceinline__ FvScale fv_scale(const FvArgs &a, double t) {
+  const double k = a.lambda * exp(t);
+  FvScale sc;
+  sc.k2 = k * k;
+  sc.inv_k2 = 1.0 / sc.k2;
+  double p = 1.0;
+  for (int i = 0; i < a.d - 2; ++i) p *= k;
+  sc.kdm2 = p;
+  sc.kd = p * sc.k2;
+  return sc;
+}
+
+// Flux Q and the local bound lam of the step estimate at interface j of one
+// flow with cell values u[0..n) (global memory or LDS) and radial table tab
+// (chat | hhat, global memory or LDS); the eight lanes of an aligned group
+// (sub = 0..7) take radial nodes sub, sub + 8, ... of F_1, F_2 at up to three
+// masses (d_sigma u and the two Goldstone states) and meet in group8_sum, so
+// every lane of the group returns the same Q, lam.  bad: a mass of a live
+// interface has left the domain.  Interfaces past n (not live) load clamped
+// cells; their results are not used.
+__device__ __forceinline__ void fv_interface(const FvArgs &a, const FvScale &sc, const double *u,
+                                             const double *tab, int64_t j, int sub, bool live,
+                                             double &Q, double &lam, bool &bad) {
+  const int64_t n = a.n;
+  const double ids = a.inv_ds;
   // cells j-2 .. j+1 with the ghost cells: loads at clamped indices first
   // (issued together), the ghost rules after
   const int64_t nm1 = n - 1;
@@ -101,17 +110,17 @@ __global__ __launch_bounds__(256) void fv_flux_kernel(FvArgs a) {
   }
   const double m2[3] = {ms, um * isj, up * isj};
   const int nm = gold ? 3 : 1;
-  bool bad = false;
+  bad = false;
   double dh[3];
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
-    const double delta = m2[m] + a.k2;
+    const double delta = m2[m] + sc.k2;
     bad |= live && m < nm && !(delta > 0.0);
-    dh[m] = (m < nm && delta > 0.0) ? delta * a.inv_k2 : 1.0;
+    dh[m] = (m < nm && delta > 0.0) ? delta * sc.inv_k2 : 1.0;
   }
   double s1[3] = {0.0, 0.0, 0.0}, s2[3] = {0.0, 0.0, 0.0};
   for (int i = sub; i < a.n_r; i += 8) {
-    const double c = a.tab[i], hh = a.tab[a.n_r + i];
+    const double c = tab[i], hh = tab[a.n_r + i];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
       if (m >= nm) break;
@@ -124,20 +133,9 @@ __global__ __launch_bounds__(256) void fv_flux_kernel(FvArgs a) {
   double F1[3], F2[3];
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
-    F1[m] = a.Cd * a.kd * group8_sum(s1[m]);
-    F2[m] = a.Cd * a.kdm2 * group8_sum(s2[m]);
+    F1[m] = a.Cd * sc.kd * group8_sum(s1[m]);
+    F2[m] = a.Cd * sc.kdm2 * group8_sum(s2[m]);
   }
-  if (!live || sub != 0) return;
-  if (bad) {
-    // the flow ends at the start of this step with its state kept
-    a.alive[r] = 0;
-    a.t_reached[r] = a.t_n;
-    *a.flag = 1;
-    a.Q[o] = 0.0;
-    a.lam[o] = 0.0;
-    return;
-  }
-  double Q, lam;
   if (j == 0) {
     Q = 0.5 * (double)a.N * F1[0];
     lam = 2.0 * (0.5 * (double)a.N * F2[0]) * (ids * ids);
@@ -150,6 +148,56 @@ __global__ __launch_bounds__(256) void fv_flux_kernel(FvArgs a) {
       Q += 0.5 * (c * F1[1] + c * F1[2]) - 0.5 * am * (up - um);
       lam += am * ids;
     }
+  }
+}
+
+// SSP-RK3 stage `stage` (0..2) of one cell with right-hand side L.
+__device__ __forceinline__ void fv_update(int stage, double L, double h, double &y0, double &ys) {
+  switch (stage) {
+    case 0:
+      ys = y0 + h * L;
+      break;
+    case 1:
+      ys = 0.75 * y0 + 0.25 * (ys + h * L);
+      break;
+    default:
+      y0 = y0 / 3.0 + (2.0 / 3.0) * (ys + h * L);
+      break;
+  }
+}
+
+// Grid (blocks of 32 interfaces, flows): eight interfaces per wave, eight
+// lanes per interface (fv_interface) at the stage time a.t.
+__global__ __launch_bounds__(256) void fv_flux_kernel(FvArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int sub = lane & 7;
+  const int64_t r = blockIdx.y;
+  const int64_t n = a.n, nq = n + 1;
+  const int64_t j = ((int64_t)blockIdx.x * (blockDim.x / kWave) + wave) * 8 + (lane >> 3);
+  const bool live = j < nq;  // every lane takes part in the group sums
+  const int64_t o = r * nq + j;
+  if (!a.alive[r]) {  // workgroup-uniform
+    if (live && sub == 0) {
+      a.Q[o] = 0.0;
+      a.lam[o] = 0.0;
+    }
+    return;
+  }
+  const double *u = (a.first ? a.y0 : a.ys) + r * n;
+  const FvScale sc = fv_scale(a, a.t);
+  double Q, lam;
+  bool bad;
+  fv_interface(a, sc, u, a.tab, j, sub, live, Q, lam, bad);
+  if (!live || sub != 0) return;
+  if (bad) {
+    // the flow ends at the start of this step with its state kept
+    a.alive[r] = 0;
+    a.t_reached[r] = a.t_n;
+    *a.flag = 1;
+    a.Q[o] = 0.0;
+    a.lam[o] = 0.0;
+    return;
   }
   a.Q[o] = Q;
   a.lam[o] = lam;
@@ -167,20 +215,82 @@ __global__ __launch_bounds__(256) void fv_stage_kernel(FvArgs a) {
   }
   const double *Q = a.Q + r * (a.n + 1);
   const double L = (Q[i + 1] - Q[i]) * a.inv_ds;
-  switch (a.stage) {
-    case 0:
-      a.ys[e] = a.y0[e] + a.h * L;
-      break;
-    case 1:
-      a.ys[e] = 0.75 * a.y0[e] + 0.25 * (a.ys[e] + a.h * L);
-      break;
-    case 2:
-      a.y0[e] = a.y0[e] / 3.0 + (2.0 / 3.0) * (a.ys[e] + a.h * L);
-      break;
-    default:
-      a.dudt[e] = L;
-      break;
+  if (a.stage == 3) {
+    a.dudt[e] = L;
+  } else {
+    double y0 = a.y0[e], ys = a.stage == 0 ? 0.0 : a.ys[e];
+    fv_update(a.stage, L, a.h, y0, ys);
+    if (a.stage == 2)
+      a.y0[e] = y0;
+    else
+      a.ys[e] = ys;
   }
+}
+
+// Steps [s0, s0 + n_st) of one flow per workgroup: state, stage state,
+// fluxes and the radial table in LDS; per stage the fluxes of all n + 1
+// interfaces (groups of eight lanes over interfaces 1..n, interface 0 with
+// the group that holds one interface fewer), a barrier, the cell updates, a
+// barrier.  The per-interface and per-cell arithmetic is that of the flux
+// and stage kernels (same bits); no launch per stage.  A flow whose masses
+// leave the domain in a stage ends with the state of the start of that step.
+__global__ __launch_bounds__(1024) void fv_solve_kernel(FvArgs a, int64_t s0, int64_t n_st) {
+  extern __shared__ double lds[];
+  const int64_t r = blockIdx.x;
+  if (!a.alive[r]) return;  // workgroup-uniform
+  const int64_t n = a.n;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  double *y0 = lds;
+  double *ys = y0 + n;
+  double *Q = ys + n;
+  double *tab = Q + n + 1;
+  int *bad_flag = reinterpret_cast<int *>(tab + 2 * a.n_r);
+  for (int64_t i = tid; i < n; i += bs) y0[i] = a.y0[r * n + i];
+  for (int i = tid; i < 2 * a.n_r; i += bs) tab[i] = a.tab[i];
+  if (tid == 0) *bad_flag = 0;
+  __syncthreads();
+  const int G = bs / 8, grp = tid / 8, sub = tid & 7;
+  const int j0grp = (int)(n % G);  // holds one interface fewer (or as many)
+  const double cs[3] = {0.0, 1.0, 0.5};
+  for (int64_t st = 0; st < n_st; ++st) {
+    const double tn = (double)(s0 + st) * a.h;
+    for (int s = 0; s < 3; ++s) {
+      const FvScale sc = fv_scale(a, tn + cs[s] * a.h);
+      const double *u = s == 0 ? y0 : ys;
+      bool bad = false;
+      for (int64_t j = 1 + grp; j <= n; j += G) {
+        double q, lam;
+        bool b;
+        fv_interface(a, sc, u, tab, j, sub, true, q, lam, b);
+        if (sub == 0) Q[j] = q;
+        bad |= b;
+      }
+      if (grp == j0grp) {
+        double q, lam;
+        bool b;
+        fv_interface(a, sc, u, tab, 0, sub, true, q, lam, b);
+        if (sub == 0) Q[0] = q;
+        bad |= b;
+      }
+      if (bad) *bad_flag = 1;
+      __syncthreads();
+      if (*bad_flag) {  // workgroup-uniform
+        if (tid == 0) {
+          a.alive[r] = 0;
+          a.t_reached[r] = tn;
+          *a.flag = 1;
+        }
+        for (int64_t i = tid; i < n; i += bs) a.y0[r * n + i] = y0[i];
+        return;
+      }
+      for (int64_t i = tid; i < n; i += bs) {
+        const double L = (Q[i + 1] - Q[i]) * a.inv_ds;
+        fv_update(s, L, a.h, y0[i], ys[i]);
+      }
+      __syncthreads();
+    }
+  }
+  for (int64_t i = tid; i < n; i += bs) a.y0[r * n + i] = y0[i];
 }
 
 // One workgroup per flow: step estimate 1 / max_j lam_j.
@@ -218,6 +328,18 @@ int launch_fv_stage(const FvArgs &a, void *stream) {
   if (a.n_rows <= 0) return 0;
   hipLaunchKernelGGL(fv_stage_kernel, dim3((unsigned)((a.n + 255) / 256), (unsigned)a.n_rows),
                      dim3(256), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+int fv_solve_lds_bytes(const FvArgs &a) {
+  return (int)(sizeof(double) * (3 * a.n + 1 + 2 * (int64_t)a.n_r) + 16);
+}
+
+int launch_fv_solve(const FvArgs &a, int64_t s0, int64_t n_st, int threads, void *stream) {
+  if (a.n_rows <= 0 || n_st <= 0) return 0;
+  if (threads < 64 || threads > 1024 || threads % 64) return (int)hipErrorInvalidValue;
+  hipLaunchKernelGGL(fv_solve_kernel, dim3((unsigned)a.n_rows), dim3(threads),
+                     fv_solve_lds_bytes(a), (hipStream_t)stream, a, s0, n_st);
   return (int)hipGetLastError();
 }
 

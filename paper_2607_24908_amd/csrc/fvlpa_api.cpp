@@ -10,6 +10,8 @@
 
 namespace frg {
 
+constexpr int64_t kFvStepsPerLaunch = 2048;
+
 static int check_fvlpa(const frg_fvlpa &f, int64_t n_flows) {
   if (f.d < 2 || f.d > 8) return fail(FRG_E_INVAL, "fvlpa.d=%d outside [2, 8]", f.d);
   if (f.N < 1 || f.N > 64) return fail(FRG_E_INVAL, "fvlpa.N=%d outside [1, 64]", f.N);
@@ -70,12 +72,10 @@ int Ctx::fvlpa_device(const frg_fvlpa &f, int64_t n, double t_end, int64_t n_ste
   a.n = f.n_cells;
   a.n_r = f.n_radial;
   a.N = f.N;
+  a.d = f.d;
+  a.lambda = f.lambda;
   auto rhs_at = [&](double t, int stage, int first) -> int {
-    const double k = f.lambda * std::exp(t);
-    a.k2 = k * k;
-    a.inv_k2 = 1.0 / a.k2;
-    a.kd = std::pow(k, f.d);
-    a.kdm2 = std::pow(k, f.d - 2);
+    a.t = t;  // the kernels form k = lambda e^t and its powers
     a.stage = stage;
     a.first = first;
     int r = launch_fv_flux(a, st);
@@ -96,12 +96,23 @@ int Ctx::fvlpa_device(const frg_fvlpa &f, int64_t n, double t_end, int64_t n_ste
   }
   if (!rc && solve) {
     const double hh = t_end / (double)n_steps;
-    const double cs[3] = {0.0, 1.0, 0.5};
     a.h = hh;
-    for (int64_t step = 0; step < n_steps && !rc; ++step) {
-      const double tn = (double)step * hh;
-      a.t_n = tn;
-      for (int s = 0; s < 3 && !rc; ++s) rc = rhs_at(tn + cs[s] * hh, s, s == 0);
+    if (tune.fv_persistent && fv_solve_lds_bytes(a) <= 64 * 1024) {
+      // one workgroup per flow runs the steps with its state in LDS, in
+      // launches of at most kFvStepsPerLaunch steps; the whole chip's
+      // threads per flow while there are at most as many flows as CUs
+      const int threads = n <= n_cu ? 1024 : n <= 2 * n_cu ? 512 : 256;
+      for (int64_t s0 = 0; s0 < n_steps && !rc; s0 += kFvStepsPerLaunch) {
+        const int r = launch_fv_solve(a, s0, std::min(kFvStepsPerLaunch, n_steps - s0), threads, st);
+        if (r) rc = hip_fail((hipError_t)r, "fv_solve_kernel launch");
+      }
+    } else {
+      const double cs[3] = {0.0, 1.0, 0.5};
+      for (int64_t step = 0; step < n_steps && !rc; ++step) {
+        const double tn = (double)step * hh;
+        a.t_n = tn;
+        for (int s = 0; s < 3 && !rc; ++s) rc = rhs_at(tn + cs[s] * hh, s, s == 0);
+      }
     }
   }
   (void)hipFreeAsync(buf, st);

@@ -155,3 +155,35 @@ def test_bad_arguments(ctx):
         frg.frg_fvlpa_solve(ctx, fv, 0.1, 4, u, tr, mem=frg.FRG_MEM_HOST)
     with pytest.raises(frg.FrgError):
         frg.frg_fvlpa_solve(ctx, fv, -1.0, 0, u, tr, mem=frg.FRG_MEM_HOST)
+
+
+@pytest.mark.parametrize("case,n_flows,steps", [(1, 4, 60), (3, 300, 40), (4, 600, 2100)])
+def test_fused_and_per_stage_solves_same_bits(ctx, case, n_flows, steps):
+    """The fused solve (one workgroup per flow, cells in LDS; 1024, 512 or
+    256 threads by the number of flows; launches of at most 2048 steps) and
+    the solve with two launches per stage share the per-interface and per-cell
+    arithmetic: the same bits, flows that reach the pole included."""
+    d, N, reg, n_r, n, smax = CASES[case]
+    print(f"[case] fvlpa fused vs per-stage d={d} N={N} n={n} flows={n_flows} steps={steps}",
+          flush=True)
+    rng = np.random.Generator(np.random.PCG64(case * 7 + n_flows))
+    u0 = initial(rng, n_flows, n, smax, broken=True)
+    fv = frg.make_fvlpa(d, N, reg, n_r, 1.0, 6.0, n, smax)
+    _, dt, _ = oracle.fvlpa_rhs(d, N, reg, n_r, 1.0, 6.0, smax, 0.0, u0, allow_domain=True)
+    t_end = -steps * 0.5 * np.nanmin(dt)  # inside the explicit step bound at t = 0
+    default = frg.frg_tune_get(ctx, "fv_persistent")
+    outs = []
+    try:
+        for fused in (1, 0):
+            frg.frg_tune_set(ctx, "fv_persistent", fused)
+            U = dev(u0)
+            tr = torch.empty(n_flows, dtype=torch.float64, device="cuda")
+            frg.frg_fvlpa_solve(ctx, fv, t_end, steps, U, tr)
+            torch.cuda.synchronize()
+            outs.append((U.cpu().numpy(), tr.cpu().numpy()))
+    finally:
+        frg.frg_tune_set(ctx, "fv_persistent", default)
+    (ua, ta), (ub, tb) = outs
+    print(f"  flows to t_end {np.sum(ta == t_end)}/{n_flows}")
+    assert np.array_equal(ta, tb) and np.array_equal(ua, ub)
+    assert np.all(np.isfinite(ua))
