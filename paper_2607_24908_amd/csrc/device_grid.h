@@ -315,29 +315,48 @@ __device__ __forceinline__ bool fold_m_ok(double x) {
 }
 
 // Build the coefficient table of momentum p (all threads of the workgroup;
-// lc, lq, lm: c_i, Hq_i and mu_j already staged in LDS).  Pass 1 spreads the
-// regulator evaluations over all threads and parks the scaled H of each
-// group in the group's own P rows; pass 2 expands one group per thread.
+// lc, lq, lm: c_i, Hq_i and mu_j, lqn, lo: q_i and 1 + x_j, already staged in
+// LDS).  Pass 1 spreads the regulator evaluations over all threads and parks
+// the scaled H of each group in the group's own P rows; pass 2 expands one
+// group per thread.  In pass 1 a thread keeps its lane (the stride is a
+// multiple of 64 lanes) and steps the group row (t, gi, k) by the number of
+// waves without divisions.
 template <int REG, int G>
 __device__ void grid_fill_fold(const GridArgs &g, double *lC, const double *lc, const double *lq,
-                               const double *lm, double p, const FoldShape<G> &fs) {
-  const double *tq = g.tab;
-  const double *to = g.tab + 3 * g.n_r;
+                               const double *lm, const double *lqn, const double *lo, double p,
+                               const FoldShape<G> &fs) {
   const int n_grp = g.T * fs.NG;
-  for (int task = threadIdx.x; task < kWave * n_grp * G; task += blockDim.x) {
-    const int l = task & (kWave - 1);
-    const int rest = task / kWave;
-    const int tg = rest / G, k = rest - tg * G;
-    const int t = tg / fs.NG, gi = tg - t * fs.NG;
-    const int i = (l & (g.R - 1)) + g.R * t;
-    const int j = l / g.R + g.J * (gi * G + k);
-    double H = 0.0;
-    if (i < g.n_r && j < g.n_a) {
-      const double q = tq[i];
-      const double qm = q - p;
-      H = g.sig * hk<REG>(__builtin_fma((2.0 * q) * p, to[j], qm * qm), g.k2, g.inv_k2);
+  {
+    const int l = threadIdx.x & (kWave - 1);
+    const int W = blockDim.x / kWave;
+    const int rho = l & (g.R - 1), iota = l >> __builtin_ctz(g.R);  // R is a power of two
+    int k = threadIdx.x / kWave, gi = 0, t = 0;
+    while (k >= G) {
+      k -= G;
+      if (++gi == fs.NG) {
+        gi = 0;
+        ++t;
+      }
     }
-    lC[(tg * (2 * G + 2) + k) * kWave + l] = H;
+    for (int row = threadIdx.x / kWave; row < n_grp * G; row += W) {
+      const int i = rho + g.R * t;
+      const int j = iota + g.J * (gi * G + k);
+      double H = 0.0;
+      if (i < g.n_r && j < g.n_a) {
+        const double q = lqn[i];
+        const double qm = q - p;
+        H = g.sig * hk<REG>(__builtin_fma((2.0 * q) * p, lo[j], qm * qm), g.k2, g.inv_k2);
+      }
+      lC[((t * fs.NG + gi) * (2 * G + 2) + k) * kWave + l] = H;
+      k += W;
+      while (k >= G) {
+        k -= G;
+        if (++gi == fs.NG) {
+          gi = 0;
+          ++t;
+        }
+      }
+    }
   }
   __syncthreads();
   for (int task = threadIdx.x; task < kWave * n_grp; task += blockDim.x) {
@@ -556,26 +575,50 @@ __device__ __forceinline__ double vertex_s2(double q, double p2, double x, doubl
 
 template <int REG, int G>
 __device__ void vertex_fill(const GridArgs &g, double *lC, const double *lc, const double *lq,
-                            const double *lx, const double *lm, const double *lsx,
-                            const double *lcp, const double *lnu, double p1, double p2, double ct,
-                            double st, const FoldShape<G, 3> &fs) {
-  const double *tq = g.tab;
+                            const double *lqn, const double *lx, const double *lm,
+                            const double *lsx, const double *lcp, const double *lnu, double p1,
+                            double p2, double ct, double st, const FoldShape<G, 3> &fs) {
   const int n_pairs = g.n_r * g.n_a;
   const int n_grp = g.T * fs.NG;
-  for (int task = threadIdx.x; task < kWave * n_grp * G; task += blockDim.x) {
-    const int l = task & (kWave - 1);
-    const int rest = task / kWave;
-    const int tg = rest / G, k = rest - tg * G;
-    const int t = tg / fs.NG, gi = tg - t * fs.NG;
-    const int pi = l + kWave * t;
-    const int az = gi * G + k;
-    double H = 0.0;
-    if (pi < n_pairs && az < g.n_phi) {
-      const int i = pi / g.n_a, j = pi - i * g.n_a;
-      const double s2 = vertex_s2<REG>(tq[i], p2, lx[j], lsx[j], lcp[az], ct, st);
-      H = g.sig * hk<REG>(s2, g.k2, g.inv_k2);
+  {
+    // as in grid_fill_fold: a thread keeps its lane and steps (t, gi, k);
+    // its pair (i, j) changes with t only
+    const int l = threadIdx.x & (kWave - 1);
+    const int W = blockDim.x / kWave;
+    int k = threadIdx.x / kWave, gi = 0, t = 0;
+    while (k >= G) {
+      k -= G;
+      if (++gi == fs.NG) {
+        gi = 0;
+        ++t;
+      }
     }
-    lC[(tg * (2 * G + 3) + k) * kWave + l] = H;
+    int pi = l + kWave * t;
+    int i = pi / g.n_a, j = pi - i * g.n_a;
+    for (int row = threadIdx.x / kWave; row < n_grp * G; row += W) {
+      const int az = gi * G + k;
+      double H = 0.0;
+      if (pi < n_pairs && az < g.n_phi) {
+        const double s2 = vertex_s2<REG>(lqn[i], p2, lx[j], lsx[j], lcp[az], ct, st);
+        H = g.sig * hk<REG>(s2, g.k2, g.inv_k2);
+      }
+      lC[((t * fs.NG + gi) * (2 * G + 3) + k) * kWave + l] = H;
+      k += W;
+      bool moved = false;
+      while (k >= G) {
+        k -= G;
+        if (++gi == fs.NG) {
+          gi = 0;
+          ++t;
+          moved = true;
+        }
+      }
+      if (moved) {
+        pi = l + kWave * t;
+        i = pi / g.n_a;
+        j = pi - i * g.n_a;
+      }
+    }
   }
   __syncthreads();
   for (int task = threadIdx.x; task < kWave * n_grp; task += blockDim.x) {
@@ -617,7 +660,7 @@ __device__ void vertex_fill(const GridArgs &g, double *lC, const double *lc, con
     // P <- P (x + Hq)^2 (x + H1), N <- c_i mu_j N
     double q = 0.0, H1 = 0.0;
     if (vp) {
-      q = g.tab[i];
+      q = lqn[i];
       const double s1 = fmax((q * q + p1 * p1) + (2.0 * q) * p1 * lx[j], 0.0);
       H1 = g.sig * hk<REG>(s1, g.k2, g.inv_k2);
     }

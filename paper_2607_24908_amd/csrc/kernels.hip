@@ -395,7 +395,8 @@ __global__ __launch_bounds__(512) void grid_coef_kernel(GridArgs g) {
       any |= wg_m0 + idx < g.n_m && g.used64[a * g.n_m + wg_m0 + idx] == 1;
     if (!__syncthreads_or(any)) return;  // workgroup-uniform
   }
-  // LDS: coefficients | per-block masks | masses delta | c_i | Hq_i | mu_j
+  // LDS: coefficients | per-block masks | masses delta | c_i | Hq_i | mu_j |
+  // q_i | 1 + x_j
   const FoldShape<G> fs(g.U, g.T);
   double *lC = lds;
   unsigned *lmask = reinterpret_cast<unsigned *>(lC + fs.rows * kWave);
@@ -403,16 +404,22 @@ __global__ __launch_bounds__(512) void grid_coef_kernel(GridArgs g) {
   double *lc = ldm + nblk * M;
   double *lq = lc + n_r;
   double *lm = lq + n_r;
+  double *lqn = lm + n_a;
+  double *lo = lqn + n_r;
   for (int idx = threadIdx.x; idx < n_r; idx += blockDim.x) {
     lc[idx] = g.tab[n_r + idx];
     lq[idx] = g.tab[2 * n_r + idx];
+    lqn[idx] = g.tab[idx];
   }
-  for (int idx = threadIdx.x; idx < n_a; idx += blockDim.x) lm[idx] = g.tab[3 * n_r + n_a + idx];
+  for (int idx = threadIdx.x; idx < n_a; idx += blockDim.x) {
+    lm[idx] = g.tab[3 * n_r + n_a + idx];
+    lo[idx] = g.tab[3 * n_r + idx];
+  }
   const bool p_ok = p >= 0.0;
   const bool table = p_ok && fold_p_ok<G>(p, g);  // workgroup-uniform
   stage_masses<M, G, 2, REDO>(g, a, wg_m0, nblk, p_ok, table, lmask, ldm);
   __syncthreads();
-  if (table) grid_fill_fold<REG, G>(g, lC, lc, lq, lm, p, fs);
+  if (table) grid_fill_fold<REG, G>(g, lC, lc, lq, lm, lqn, lo, p, fs);
   __syncthreads();
   auto single = [&](double delta) {
     return grid_single_mass<REG>(g, lc, lq, lm, lane, p, delta);
@@ -453,9 +460,11 @@ __global__ __launch_bounds__(512) void vertex_kernel(GridArgs g) {
   double *lsx = lm + n_a;       // sqrt(1 - x_j^2)
   double *lcp = lsx + n_a;      // cos phi_l
   double *lnu = lcp + n_phi;    // nu_l
+  double *lqn = lnu + n_phi;    // q_i
   for (int idx = threadIdx.x; idx < n_r; idx += blockDim.x) {
     lc[idx] = g.tab[n_r + idx];
     lq[idx] = g.tab[2 * n_r + idx];
+    lqn[idx] = g.tab[idx];
   }
   for (int idx = threadIdx.x; idx < n_a; idx += blockDim.x) {
     lx[idx] = g.vtab[idx];
@@ -471,7 +480,7 @@ __global__ __launch_bounds__(512) void vertex_kernel(GridArgs g) {
   const bool table = table_form && p_ok && fold_p_ok<G, 3>(fmax(p1, p2), g);
   stage_masses<M, G, 3, false>(g, a, wg_m0, nblk, p_ok, table, lmask, ldm);
   __syncthreads();
-  if (table) vertex_fill<REG, G>(g, lC, lc, lq, lx, lm, lsx, lcp, lnu, p1, p2, ct, st, fs);
+  if (table) vertex_fill<REG, G>(g, lC, lc, lq, lqn, lx, lm, lsx, lcp, lnu, p1, p2, ct, st, fs);
   __syncthreads();
   auto single = [&](double delta) {
     return vertex_single_mass<REG>(g, lc, lq, lx, lm, lsx, lcp, lnu, lane, p1, p2, ct, st, delta);
@@ -631,7 +640,7 @@ int grid_coef_lds_bytes(const GridArgs &g) {
   const int rows = G == 32   ? FoldShape<32>(g.U, g.T).rows
                    : G == 16 ? FoldShape<16>(g.U, g.T).rows
                              : FoldShape<8>(g.U, g.T).rows;
-  return (int)sizeof(double) * (rows * kWave + 2 * g.n_r + g.n_a) + kGridCoefStageMax;
+  return (int)sizeof(double) * (rows * kWave + 3 * g.n_r + 2 * g.n_a) + kGridCoefStageMax;
 }
 
 int grid_coef_stage_bytes(int MB, int W, int M) { return MB * W * (16 + 8 * M); }
@@ -670,9 +679,9 @@ static int vertex_rows(const GridArgs &g) {
 }
 
 // LDS of vertex_kernel: coefficient table (if resident) | masks and masses |
-// c, Hq | x, mu, sqrt(1 - x^2) | cos phi, nu.
+// c, Hq | x, mu, sqrt(1 - x^2) | cos phi, nu | q.
 int vertex_lds_bytes(const GridArgs &g, int M, int W, bool table) {
-  return (int)sizeof(double) * ((table ? vertex_rows(g) * kWave : 0) + 2 * g.n_r + 3 * g.n_a +
+  return (int)sizeof(double) * ((table ? vertex_rows(g) * kWave : 0) + 3 * g.n_r + 3 * g.n_a +
                                 2 * g.n_phi) +
          grid_coef_stage_bytes(g.mblocks, W, M);
 }
