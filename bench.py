@@ -57,13 +57,13 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device-to-device copy of 1 GiB (PMC traffic calibration)")
     ap.add_argument("--only", choices=["uneven64", "uneven32", "grid32", "tab4096", "tab1m", "pflow",
-                                       "vertex", "fvlpa"],
+                                       "vertex", "fvlpa", "serving"],
                     default=None,
                     help="profiling aid: run only --steps persistent launches of the uneven sets "
                          "(FP64 or FP32C), --steps FP32C scale-up grid calls, --steps momentum-flow "
-                         "or finite-volume LPA solves or vertex-diagram calls, or --steps calls "
-                         "of the tabulated variant (rows of 4096 or 2^20 nodes), and print "
-                         "their timing")
+                         "or finite-volume LPA solves or vertex-diagram calls, --steps calls "
+                         "of the tabulated variant (rows of 4096 or 2^20 nodes), or --steps "
+                         "served flow requests (after --warmup more), and print their timing")
     return ap.parse_args()
 
 
@@ -160,6 +160,11 @@ def main():
         ctx = frg.frg_create(0)
         fn = {"pflow": momentum_flow, "vertex": vertex, "fvlpa": fv_lpa}[args.only]
         r = fn(ctx, frg, workloads, torch, reps=args.steps)
+        print(json.dumps({"only": args.only, **r}), flush=True)
+        return
+    if args.only == "serving":
+        from paper_2607_24908_amd import frg, workloads
+        r = serving(frg, workloads, n_warm=args.warmup, n_timed=args.steps)
         print(json.dumps({"only": args.only, **r}), flush=True)
         return
     if args.only in ("tab4096", "tab1m"):

@@ -378,9 +378,9 @@ int frg_flow_solve(const frg_request *req, frg_rhs_fn rhs, void *user, frg_resul
 
 /* Submit a flow to the context's server (never blocks).  The server admits
  * a flow when a slot is free and its device footprint fits the HBM budget,
- * keeps its state resident, and batches the right-hand-side evaluations of
- * all running flows into shared launches (continuous batching).
- * FRG_E_AGAIN if the queue is full. */
+ * and batches the right-hand-side evaluations of all running flows into
+ * shared launches (continuous batching), each with one packed upload and one
+ * packed download.  FRG_E_AGAIN if the queue is full. */
 int frg_submit(frg_ctx *ctx, const frg_request *req, uint64_t *ticket);
 
 /* FRG_PENDING until the flow finishes; then the result (status inside) and
@@ -437,8 +437,8 @@ int frg_tune_get(frg_ctx *ctx, const char *key, int32_t *value);
  * the Golub-Welsch eigenvalue method (no GPU use). */
 int frg_gauss_legendre(int32_t n, double *x, double *w);
 
-/* Bytes of device memory one flow of this shape keeps resident while it runs
- * (what the server's HBM admission charges). */
+/* Bytes of device memory one flow of this shape takes in the server's staging
+ * buffer during a batched call (what the server's HBM admission charges). */
 int64_t frg_flow_footprint(const frg_lpa *lpa);
 
 #ifdef __cplusplus

@@ -697,10 +697,9 @@ int Ctx::grid_fp32c(const frg_quad &q, int64_t n_p, const double *p, int64_t n_m
 }
 
 // ----------------------------------------------------------------- LPA --
-int Ctx::lpa_jobs(int n, const frg_lpa *lpa, const double *t, const double *const *U,
-                  double *const *dUdt, double *const *jac, int *flags_dev, hipStream_t st) {
-  std::vector<LpaJob> jobs(n);
-  std::vector<int64_t> start(n + 1);
+int Ctx::lpa_job_table(int n, const frg_lpa *lpa, const double *t, const double *const *U,
+                       double *const *dUdt, double *const *jac, int *flags_dev, LpaJob *jobs,
+                       int64_t *start) {
   int64_t total = 0;
   for (int f = 0; f < n; ++f) {
     const frg_lpa &l = lpa[f];
@@ -728,13 +727,23 @@ int Ctx::lpa_jobs(int n, const frg_lpa *lpa, const double *t, const double *cons
     total += l.n_grid;
   }
   start[n] = total;
+  return FRG_OK;
+}
+
+int Ctx::lpa_jobs(int n, const frg_lpa *lpa, const double *t, const double *const *U,
+                  double *const *dUdt, double *const *jac, int *flags_dev, hipStream_t st) {
+  std::vector<LpaJob> jobs(n);
+  std::vector<int64_t> start(n + 1);
+  int rc = lpa_job_table(n, lpa, t, U, dUdt, jac, flags_dev, jobs.data(), start.data());
+  if (rc) return rc;
+  const int64_t total = start[n];
   const size_t jb = n * sizeof(LpaJob);
   std::vector<char> blob(jb + (n + 1) * sizeof(int64_t));
   std::memcpy(blob.data(), jobs.data(), jb);
   std::memcpy(blob.data() + jb, start.data(), (n + 1) * sizeof(int64_t));
   void *dev;
   int slot;
-  int rc = ring.upload(blob.data(), blob.size(), st, &dev, &slot);
+  rc = ring.upload(blob.data(), blob.size(), st, &dev, &slot);
   if (rc) return rc;
   int e = launch_lpa((const LpaJob *)dev, (const int64_t *)((char *)dev + jb), n, total, st);
   rc = ring.release(slot, st);
@@ -989,7 +998,8 @@ int frg_gauss_legendre(int32_t n, double *x, double *w) {
 
 int64_t frg_flow_footprint(const frg_lpa *lpa) {
   if (!lpa || lpa->n_grid < 1) return -1;
-  // U, dUdt and 7 Jacobian bands resident per flow, plus a 4 KiB descriptor share
+  // the flow's share of the server's staging buffer: U, dUdt and 7 Jacobian
+  // bands, plus a 4 KiB descriptor share
   return (int64_t)(9 * lpa->n_grid * sizeof(double)) + 4096;
 }
 

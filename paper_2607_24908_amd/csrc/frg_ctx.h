@@ -156,6 +156,11 @@ struct Context {
                  double *out, double *err, uint8_t *used, hipStream_t st);
   int lpa_jobs(int n, const frg_lpa *lpa, const double *t, const double *const *U,
                double *const *dUdt, double *const *jac, int *flags_dev, hipStream_t st);
+  // Descriptors of n LPA jobs (device pointers given) and their grid offsets
+  // start[0..n]; no GPU work except building missing LPA tables.
+  int lpa_job_table(int n, const frg_lpa *lpa, const double *t, const double *const *U,
+                    double *const *dUdt, double *const *jac, int *flags_dev, LpaJob *jobs,
+                    int64_t *start);
   void stop_server();
   // fvlpa_api.cpp: finite-volume LPA; dudt != nullptr: one right-hand side
   // at t_rhs (and dt_est if not null), else SSP-RK3 from 0 to t_end

@@ -1,8 +1,9 @@
 // Flow server behind frg_submit / frg_poll.
 //
 // Admission: a submitted flow waits in a FIFO queue until a slot is free
-// and its device footprint (U, dU/dt and the 7 Jacobian bands, resident for
-// the flow's lifetime) fits the context's HBM budget.
+// and its device footprint (its share of the staging buffer: U, dU/dt and
+// the 7 Jacobian bands of one call) fits the context's HBM budget, so the
+// staging buffer of any batch stays within the budget.
 //
 // Execution: every admitted flow runs the FP64 host stepper in its own
 // thread.  Its right-hand-side calls are handed to one dispatcher thread,
@@ -13,6 +14,11 @@
 // is on the GPU form the next batch).  A flow's result does not depend on
 // which flows shared its launches: the kernel evaluates each grid point of
 // each flow independently, in a fixed order.
+//
+// Round trip of a batch: descriptors, the U of every flow and zeroed domain
+// flags are packed into one pinned host buffer and go up in one copy; one
+// launch; the flags and every flow's outputs come back in one copy and are
+// written into the waiting flows' own buffers.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,12 +47,11 @@ struct Flow {
   frg_result res{};
   int64_t n = 0;
   int64_t bytes = 0;
-  double *h_U = nullptr;    // pinned: U for the next call
-  double *h_out = nullptr;  // pinned: dU/dt (n) then the bands (7n)
-  double *d_U = nullptr;    // device, resident
-  double *d_out = nullptr;  // device, resident
-  // right-hand-side hand-off
+  // right-hand-side hand-off: the stepper's buffers, valid while it waits
   double t = 0.0;
+  const double *U_src = nullptr;
+  double *dUdt_dst = nullptr;
+  double *jac_dst = nullptr;
   bool want_jac = false;
   bool ready = false;
   int rc = FRG_OK;
@@ -58,9 +63,9 @@ struct Flow {
 struct Server {
   Context *ctx = nullptr;
   hipStream_t stream = nullptr;
-  int *d_flags = nullptr;
-  int *h_flags = nullptr;
-  int flag_cap = 0;
+  char *h_stage = nullptr;  // pinned mirror of d_stage
+  char *d_stage = nullptr;
+  size_t stage_cap = 0;
   std::mutex m;
   std::condition_variable cv_disp;
   std::deque<Flow *> queue;
@@ -82,7 +87,7 @@ struct Server {
   void admit_locked();
   static int rhs_cb(void *user, double t, const double *U, int64_t n, double *dUdt, double *jac);
   void run_flow(Flow *f);
-  void release(Flow *f);
+  bool grow_stage(size_t bytes);
 };
 
 int Server::start() {
@@ -103,40 +108,40 @@ void Server::shutdown() {
   if (disp.joinable()) disp.join();
   for (auto &kv : flows) {
     if (kv.second->th.joinable()) kv.second->th.join();
-    release(kv.second);
     delete kv.second;
   }
   flows.clear();
   for (Flow *f : queue) delete f;
   queue.clear();
-  if (d_flags) hipFree(d_flags);
-  if (h_flags) hipHostFree(h_flags);
+  if (d_stage) hipFree(d_stage);
+  if (h_stage) hipHostFree(h_stage);
   if (stream) hipStreamDestroy(stream);
 }
 
-void Server::release(Flow *f) {
-  if (f->d_U) hipFree(f->d_U);
-  if (f->d_out) hipFree(f->d_out);
-  if (f->h_U) hipHostFree(f->h_U);
-  if (f->h_out) hipHostFree(f->h_out);
-  f->d_U = f->d_out = f->h_U = f->h_out = nullptr;
+// Dispatcher thread only (no batch in flight): make the staging buffer hold
+// `bytes`.
+bool Server::grow_stage(size_t bytes) {
+  if (bytes <= stage_cap) return true;
+  const size_t cap = std::max(bytes, 2 * stage_cap);
+  if (d_stage) hipFree(d_stage);
+  if (h_stage) hipHostFree(h_stage);
+  d_stage = h_stage = nullptr;
+  stage_cap = 0;
+  if (hipMalloc((void **)&d_stage, cap) != hipSuccess) return false;
+  if (hipHostMalloc((void **)&h_stage, cap, hipHostMallocDefault) != hipSuccess) {
+    hipFree(d_stage);
+    d_stage = nullptr;
+    return false;
+  }
+  stage_cap = cap;
+  return true;
 }
 
 // Under m: start queued flows while slots and budget allow (strict FIFO).
 void Server::admit_locked() {
-  if (!queue.empty()) hipSetDevice(ctx->device);
   while (!queue.empty() && active < max_active && !stop) {
     Flow *f = queue.front();
     if (used + (uint64_t)f->bytes > budget) break;
-    const size_t n = (size_t)f->n;
-    bool ok = hipMalloc(&f->d_U, n * sizeof(double)) == hipSuccess &&
-              hipMalloc(&f->d_out, 8 * n * sizeof(double)) == hipSuccess &&
-              hipHostMalloc(&f->h_U, n * sizeof(double), hipHostMallocDefault) == hipSuccess &&
-              hipHostMalloc(&f->h_out, 8 * n * sizeof(double), hipHostMallocDefault) == hipSuccess;
-    if (!ok) {
-      release(f);
-      break;  // retry when another flow frees memory
-    }
     queue.pop_front();
     used += f->bytes;
     ++active;
@@ -148,20 +153,19 @@ void Server::admit_locked() {
 int Server::rhs_cb(void *user, double t, const double *U, int64_t n, double *dUdt, double *jac) {
   Flow *f = static_cast<Flow *>(user);
   Server *s = f->srv;
-  std::memcpy(f->h_U, U, n * sizeof(double));
-  {
-    std::unique_lock<std::mutex> lk(s->m);
-    if (s->stop) return FRG_E_DEVICE;
-    f->t = t;
-    f->want_jac = jac != nullptr;
-    f->ready = false;
-    s->pending.push_back(f);
-    s->cv_disp.notify_one();
-    f->cv.wait(lk, [&] { return f->ready || s->stop; });
-    if (!f->ready) return FRG_E_DEVICE;
-  }
-  std::memcpy(dUdt, f->h_out, n * sizeof(double));
-  if (jac) std::memcpy(jac, f->h_out + n, 7 * n * sizeof(double));
+  if (n != f->n) return FRG_E_INVAL;
+  std::unique_lock<std::mutex> lk(s->m);
+  if (s->stop) return FRG_E_DEVICE;
+  f->t = t;
+  f->U_src = U;
+  f->dUdt_dst = dUdt;
+  f->jac_dst = jac;
+  f->want_jac = jac != nullptr;
+  f->ready = false;
+  s->pending.push_back(f);
+  s->cv_disp.notify_one();
+  f->cv.wait(lk, [&] { return f->ready || s->stop; });
+  if (!f->ready) return FRG_E_DEVICE;
   return f->rc;
 }
 
@@ -188,6 +192,10 @@ void Server::dispatch_loop() {
   std::vector<double> ts;
   std::vector<const double *> Us;
   std::vector<double *> Ds, Js;
+  std::vector<LpaJob> jobs;
+  std::vector<int64_t> start;
+  std::vector<size_t> o_u, o_o;
+  auto up8 = [](size_t x) { return (x + 7) & ~(size_t)7; };
   hipSetDevice(ctx->device);
   for (;;) {
     batch.clear();
@@ -198,47 +206,79 @@ void Server::dispatch_loop() {
       batch.swap(pending);
     }
     const int nb = (int)batch.size();
-    if (nb > flag_cap) {
-      if (d_flags) hipFree(d_flags);
-      if (h_flags) hipHostFree(h_flags);
-      flag_cap = std::max(64, 2 * nb);
-      hipMalloc(&d_flags, flag_cap * sizeof(int));
-      hipHostMalloc(&h_flags, flag_cap * sizeof(int), hipHostMallocDefault);
-    }
     lpas.resize(nb);
     ts.resize(nb);
     Us.resize(nb);
     Ds.resize(nb);
     Js.resize(nb);
+    jobs.resize(nb);
+    start.resize(nb + 1);
+    o_u.resize(nb);
+    o_o.resize(nb);
+    // staging layout: jobs | start | U of each flow | flags | outputs of each
+    // flow (dU/dt, then the 7 bands when asked); [0, o_out) goes up,
+    // [o_flags, end) comes back
+    const size_t o_start = up8(nb * sizeof(LpaJob));
+    const size_t o_U = up8(o_start + (nb + 1) * sizeof(int64_t));
+    size_t cu = o_U;
     for (int i = 0; i < nb; ++i) {
-      Flow *f = batch[i];
-      lpas[i] = f->req.lpa;
-      ts[i] = f->t;
-      Us[i] = f->d_U;
-      Ds[i] = f->d_out;
-      Js[i] = f->want_jac ? f->d_out + f->n : nullptr;
-      hipMemcpyAsync(f->d_U, f->h_U, f->n * sizeof(double), hipMemcpyHostToDevice, stream);
+      o_u[i] = cu;
+      cu += batch[i]->n * sizeof(double);
     }
-    hipMemsetAsync(d_flags, 0, nb * sizeof(int), stream);
-    int rc;
-    {
-      std::lock_guard<std::mutex> lk(ctx->mu);
-      rc = ctx->lpa_jobs(nb, lpas.data(), ts.data(), Us.data(), Ds.data(), Js.data(), d_flags,
-                         stream);
-    }
+    const size_t o_flags = cu;
+    size_t co = up8(o_flags + nb * sizeof(int));
+    const size_t o_out = co;
     for (int i = 0; i < nb; ++i) {
-      Flow *f = batch[i];
-      hipMemcpyAsync(f->h_out, f->d_out, (f->want_jac ? 8 : 1) * f->n * sizeof(double),
-                     hipMemcpyDeviceToHost, stream);
+      o_o[i] = co;
+      co += (batch[i]->want_jac ? 8 : 1) * batch[i]->n * sizeof(double);
     }
-    hipMemcpyAsync(h_flags, d_flags, nb * sizeof(int), hipMemcpyDeviceToHost, stream);
-    const bool ok = hipStreamSynchronize(stream) == hipSuccess && rc == FRG_OK;
+    const size_t end = co;
+    bool ok = grow_stage(end);
+    int rc = ok ? FRG_OK : FRG_E_NOMEM;
+    if (ok) {
+      for (int i = 0; i < nb; ++i) {
+        Flow *f = batch[i];
+        lpas[i] = f->req.lpa;
+        ts[i] = f->t;
+        std::memcpy(h_stage + o_u[i], f->U_src, f->n * sizeof(double));
+        Us[i] = (const double *)(d_stage + o_u[i]);
+        Ds[i] = (double *)(d_stage + o_o[i]);
+        Js[i] = f->want_jac ? Ds[i] + f->n : nullptr;
+      }
+      std::memset(h_stage + o_flags, 0, o_out - o_flags);
+      {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        rc = ctx->lpa_job_table(nb, lpas.data(), ts.data(), Us.data(), Ds.data(), Js.data(),
+                                (int *)(d_stage + o_flags), jobs.data(), start.data());
+      }
+      ok = rc == FRG_OK;
+    }
+    if (ok) {
+      std::memcpy(h_stage, jobs.data(), nb * sizeof(LpaJob));
+      std::memcpy(h_stage + o_start, start.data(), (nb + 1) * sizeof(int64_t));
+      ok = hipMemcpyAsync(d_stage, h_stage, o_out, hipMemcpyHostToDevice, stream) == hipSuccess &&
+           launch_lpa((const LpaJob *)d_stage, (const int64_t *)(d_stage + o_start), nb, start[nb],
+                      stream) == 0 &&
+           hipMemcpyAsync(h_stage + o_flags, d_stage + o_flags, end - o_flags,
+                          hipMemcpyDeviceToHost, stream) == hipSuccess;
+      ok = hipStreamSynchronize(stream) == hipSuccess && ok;
+      if (!ok) rc = FRG_E_DEVICE;
+    }
+    if (ok) {
+      for (int i = 0; i < nb; ++i) {
+        Flow *f = batch[i];
+        const double *o = (const double *)(h_stage + o_o[i]);
+        std::memcpy(f->dUdt_dst, o, f->n * sizeof(double));
+        if (f->want_jac) std::memcpy(f->jac_dst, o + f->n, 7 * f->n * sizeof(double));
+      }
+    }
+    const int *flags = ok ? (const int *)(h_stage + o_flags) : nullptr;
     std::lock_guard<std::mutex> lk(m);
     ++launches;
     batched += nb;
     for (int i = 0; i < nb; ++i) {
       Flow *f = batch[i];
-      f->rc = !ok ? FRG_E_DEVICE : (h_flags[i] ? FRG_E_DOMAIN : FRG_OK);
+      f->rc = !ok ? rc : (flags[i] ? FRG_E_DOMAIN : FRG_OK);
       f->ready = true;
       f->cv.notify_one();
     }
@@ -323,7 +363,6 @@ int frg_poll(frg_ctx *ctx, uint64_t ticket, frg_result *out) {
   }
   if (f->th.joinable()) f->th.join();
   *out = f->res;
-  s->release(f);
   delete f;
   clear_error();
   return FRG_OK;
