@@ -379,8 +379,8 @@ int frg_flow_solve(const frg_request *req, frg_rhs_fn rhs, void *user, frg_resul
 /* Submit a flow to the context's server (never blocks).  The server admits
  * a flow when a slot is free and its device footprint fits the HBM budget,
  * and batches the right-hand-side evaluations of all running flows into
- * shared launches (continuous batching), each with one packed upload and one
- * packed download.  FRG_E_AGAIN if the queue is full. */
+ * shared launches (continuous batching), each reading and writing one packed
+ * pinned buffer.  FRG_E_AGAIN if the queue is full. */
 int frg_submit(frg_ctx *ctx, const frg_request *req, uint64_t *ticket);
 
 /* FRG_PENDING until the flow finishes; then the result (status inside) and
@@ -418,7 +418,9 @@ int frg_autotune(frg_ctx *ctx, int32_t mode, const char *cache_path);
  * agree to a few ulp), "fv_persistent" (finite-volume solves, 1: one
  * workgroup per flow runs the steps with its cells in LDS, the default where
  * 3 n_cells + 2 n_radial doubles fit in 64 KiB; 0: two launches per stage;
- * the same bits), "grid_lds_rows" (8..96), "plain_tile", "persist_tile" (1..64),
+ * the same bits), "server_zero_copy" (flow server, 1: the LPA kernel reads
+ * and writes the pinned batch buffer in place, the default; 0: one upload and
+ * one download per batch; the same bits), "grid_lds_rows" (8..96), "plain_tile", "persist_tile" (1..64),
  * "persist_wpc" (1..64), and of the tabulated variant "tab_W" (1..4),
  * "tab_pw" (momenta per wave, 1..64), "tab_lds_nodes" (2..6144),
  * "tab_pairs" (1: rows in LDS as (value, slope) pairs, the default; 0: as

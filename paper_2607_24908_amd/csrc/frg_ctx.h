@@ -82,6 +82,7 @@ struct Tune {
   int grid_form = 0;       // resident FP64 grid: 0 per-momentum coefficients, 1 running fractions
   int grid_mfma = 1;       // coefficient form: 1 tiles of 16 masses on the matrix cores, 0 vector units
   int fv_persistent = 1;   // finite-volume solves: 1 one workgroup per flow, state in LDS; 0 launches per stage
+  int server_zero_copy = 1;  // flow server: 1 kernel reads/writes the pinned batch buffer; 0 two copies
   int fp32c_flag_ppb = 100;    // FP32C: FP64 redo above this error estimate (1e-9 units)
   int fp32c_band_ppm = 10000;  // FP32C: FP64 below this delta/k^2 (1e-6 units)
   int mode = 0;            // 0: defaults and cached choices, 1: tune new keys

@@ -16,9 +16,12 @@
 // each flow independently, in a fixed order.
 //
 // Round trip of a batch: descriptors, the U of every flow and zeroed domain
-// flags are packed into one pinned host buffer and go up in one copy; one
-// launch; the flags and every flow's outputs come back in one copy and are
-// written into the waiting flows' own buffers.
+// flags are packed into one pinned host buffer; the kernel reads them there
+// and writes the flags and every flow's outputs back into it (zero copy, one
+// launch and one synchronisation per batch; knob server_zero_copy), or the
+// packed head goes up in one copy and the flags and outputs come back in
+// one (a device mirror of the buffer).  The outputs are then written into
+// the waiting flows' own buffers.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -63,8 +66,9 @@ struct Flow {
 struct Server {
   Context *ctx = nullptr;
   hipStream_t stream = nullptr;
-  char *h_stage = nullptr;  // pinned mirror of d_stage
-  char *d_stage = nullptr;
+  char *h_stage = nullptr;   // pinned, mapped, coherent
+  char *hd_stage = nullptr;  // its device address
+  char *d_stage = nullptr;   // device mirror (copy mode)
   size_t stage_cap = 0;
   std::mutex m;
   std::condition_variable cv_disp;
@@ -125,12 +129,15 @@ bool Server::grow_stage(size_t bytes) {
   const size_t cap = std::max(bytes, 2 * stage_cap);
   if (d_stage) hipFree(d_stage);
   if (h_stage) hipHostFree(h_stage);
-  d_stage = h_stage = nullptr;
+  d_stage = h_stage = hd_stage = nullptr;
   stage_cap = 0;
   if (hipMalloc((void **)&d_stage, cap) != hipSuccess) return false;
-  if (hipHostMalloc((void **)&h_stage, cap, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void **)&h_stage, cap, hipHostMallocMapped | hipHostMallocCoherent) !=
+          hipSuccess ||
+      hipHostGetDevicePointer((void **)&hd_stage, h_stage, 0) != hipSuccess) {
+    if (h_stage) hipHostFree(h_stage);
     hipFree(d_stage);
-    d_stage = nullptr;
+    d_stage = h_stage = hd_stage = nullptr;
     return false;
   }
   stage_cap = cap;
@@ -235,34 +242,46 @@ void Server::dispatch_loop() {
     const size_t end = co;
     bool ok = grow_stage(end);
     int rc = ok ? FRG_OK : FRG_E_NOMEM;
+    bool zero_copy = false;
     if (ok) {
+      {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        zero_copy = ctx->tune.server_zero_copy != 0;
+      }
+      char *dev = zero_copy ? hd_stage : d_stage;  // where the kernel finds the buffer
       for (int i = 0; i < nb; ++i) {
         Flow *f = batch[i];
         lpas[i] = f->req.lpa;
         ts[i] = f->t;
         std::memcpy(h_stage + o_u[i], f->U_src, f->n * sizeof(double));
-        Us[i] = (const double *)(d_stage + o_u[i]);
-        Ds[i] = (double *)(d_stage + o_o[i]);
+        Us[i] = (const double *)(dev + o_u[i]);
+        Ds[i] = (double *)(dev + o_o[i]);
         Js[i] = f->want_jac ? Ds[i] + f->n : nullptr;
       }
       std::memset(h_stage + o_flags, 0, o_out - o_flags);
       {
         std::lock_guard<std::mutex> lk(ctx->mu);
         rc = ctx->lpa_job_table(nb, lpas.data(), ts.data(), Us.data(), Ds.data(), Js.data(),
-                                (int *)(d_stage + o_flags), jobs.data(), start.data());
+                                (int *)(dev + o_flags), jobs.data(), start.data());
       }
       ok = rc == FRG_OK;
-    }
-    if (ok) {
-      std::memcpy(h_stage, jobs.data(), nb * sizeof(LpaJob));
-      std::memcpy(h_stage + o_start, start.data(), (nb + 1) * sizeof(int64_t));
-      ok = hipMemcpyAsync(d_stage, h_stage, o_out, hipMemcpyHostToDevice, stream) == hipSuccess &&
-           launch_lpa((const LpaJob *)d_stage, (const int64_t *)(d_stage + o_start), nb, start[nb],
-                      stream) == 0 &&
-           hipMemcpyAsync(h_stage + o_flags, d_stage + o_flags, end - o_flags,
-                          hipMemcpyDeviceToHost, stream) == hipSuccess;
-      ok = hipStreamSynchronize(stream) == hipSuccess && ok;
-      if (!ok) rc = FRG_E_DEVICE;
+      if (ok) {
+        std::memcpy(h_stage, jobs.data(), nb * sizeof(LpaJob));
+        std::memcpy(h_stage + o_start, start.data(), (nb + 1) * sizeof(int64_t));
+        if (zero_copy) {
+          ok = launch_lpa((const LpaJob *)dev, (const int64_t *)(dev + o_start), nb, start[nb],
+                          stream) == 0;
+        } else {
+          ok = hipMemcpyAsync(d_stage, h_stage, o_out, hipMemcpyHostToDevice, stream) ==
+                   hipSuccess &&
+               launch_lpa((const LpaJob *)dev, (const int64_t *)(dev + o_start), nb, start[nb],
+                          stream) == 0 &&
+               hipMemcpyAsync(h_stage + o_flags, d_stage + o_flags, end - o_flags,
+                              hipMemcpyDeviceToHost, stream) == hipSuccess;
+        }
+        ok = hipStreamSynchronize(stream) == hipSuccess && ok;
+        if (!ok) rc = FRG_E_DEVICE;
+      }
     }
     if (ok) {
       for (int i = 0; i < nb; ++i) {

@@ -62,10 +62,19 @@ def gpu_rhs(ctx, lpa):
     return f
 
 
-def test_served_equals_alone_bitwise(ctx):
+@pytest.mark.parametrize("zero_copy", [1, 0])
+def test_served_equals_alone_bitwise(ctx, zero_copy):
+    """Served flows (batch buffer read and written in place by the kernel, or
+    moved by one upload and one download) give the bits of the same flow
+    stepped alone through frg_flow_rhs."""
     reqs = requests(10, seed=5)
-    print("[case] server mix of 10 flows", flush=True)
-    outs, res = serve(ctx, reqs)
+    print(f"[case] server mix of 10 flows, zero copy {zero_copy}", flush=True)
+    default = frg.frg_tune_get(ctx, "server_zero_copy")
+    frg.frg_tune_set(ctx, "server_zero_copy", zero_copy)
+    try:
+        outs, res = serve(ctx, reqs)
+    finally:
+        frg.frg_tune_set(ctx, "server_zero_copy", default)
     n_ok = 0
     for r, U, rs in zip(reqs, outs, res):
         assert rs.status in (frg.FRG_OK, frg.FRG_E_DOMAIN), rs.status
