@@ -295,23 +295,39 @@ int Ctx::integrate_device(const frg_set *sets, int n_sets, int flags, hipStream_
 }
 
 // Work list: tiles of up to `tile` points, sorted longest-first.
+// Tiles of up to `tile` points, longest first (weight = per-point cost x
+// points; ties in set order, then point order).  All full tiles of a set
+// weigh the same, so a stable sort of runs -- the full tiles of a set, then
+// its last partial tile -- gives the order of a stable sort of the tiles
+// without sorting them one by one.
 void build_tiles(const std::vector<SetDev> &sd, int tile, std::vector<Tile> *tiles) {
-  std::vector<std::pair<double, Tile>> tw;
+  struct Run {
+    double w;
+    int set;
+    int64_t start, count;  // tiles [start, start + count * tile) of `set`
+  };
+  std::vector<Run> runs;
+  runs.reserve(2 * sd.size());
+  int64_t n_tiles = 0;
   for (int i = 0; i < (int)sd.size(); ++i) {
     const double w = sd[i].reg == FRG_REG_EXP ? (sd[i].prec == FRG_PREC_FP32C ? 2.0 : 5.0) : 1.0;
     const double per = w * sd[i].n_r * sd[i].n_a;
-    for (int64_t st = 0; st < sd[i].n_ext; st += tile) {
-      Tile t;
-      t.set = i;
-      t.start = st;
-      t.count = (int)std::min<int64_t>(tile, sd[i].n_ext - st);
-      tw.push_back({per * t.count, t});
+    const int64_t full = sd[i].n_ext / tile, rem = sd[i].n_ext - full * tile;
+    if (full) runs.push_back({per * tile, i, 0, full});
+    if (rem) runs.push_back({per * rem, i, full * tile, 1});
+    n_tiles += full + (rem ? 1 : 0);
+  }
+  std::stable_sort(runs.begin(), runs.end(), [](const Run &a, const Run &b) { return a.w > b.w; });
+  tiles->resize(n_tiles);
+  int64_t k = 0;
+  for (const Run &r : runs) {
+    for (int64_t c = 0; c < r.count; ++c) {
+      Tile &t = (*tiles)[k++];
+      t.set = r.set;
+      t.start = r.start + c * tile;
+      t.count = (int)std::min<int64_t>(tile, sd[r.set].n_ext - t.start);
     }
   }
-  std::stable_sort(tw.begin(), tw.end(),
-                   [](const auto &a, const auto &b) { return a.first > b.first; });
-  tiles->resize(tw.size());
-  for (size_t i = 0; i < tw.size(); ++i) (*tiles)[i] = tw[i].second;
 }
 
 bool any_fp32c(const std::vector<SetDev> &sd) {
