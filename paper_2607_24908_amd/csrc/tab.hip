@@ -26,12 +26,22 @@ using namespace dev;
 
 // A table row as plain values g_k (rows read from memory, or staged in LDS
 // as they are) or as pairs (g_k, g_{k+1} - g_k) (rows staged in LDS): one
-// 16-byte read per evaluation; both give the same bits.
-// fetch(k) = (g_k, g_{k+1} - g_k); the value at t = k + f is g_k + f (g_{k+1} - g_k).
+// 16-byte read per evaluation; both give the same bits.  locate(t, k, f)
+// splits a clamped coordinate t <= t_last = n_s - 1 into a node and a
+// fraction, fetch(k) = (g_k, g_{k+1} - g_k), and the value is
+// g_k + f (g_{k+1} - g_k).  Plain rows clamp k to n_s - 2 (f = 1 at t_last);
+// pair rows append the node (g_{n_s-2} + (g_{n_s-1} - g_{n_s-2}), 0), the
+// value of that same expression, so they need no clamp: k = floor(t),
+// f = t - k (exact).
 struct PlainRow {
   const double *g;
   __device__ __forceinline__ double operator()(double t, double t_last, int k_last) const {
     return interp(g, t, t_last, k_last);
+  }
+  __device__ __forceinline__ void locate(double t, int k_last, int &k, double &f) const {
+    const int kk = (int)t;
+    k = kk < k_last ? kk : k_last;
+    f = t - (double)k;
   }
   __device__ __forceinline__ double2 fetch(int k) const {
     const double g0 = g[k], g1 = g[k + 1];
@@ -40,13 +50,14 @@ struct PlainRow {
 };
 struct PairRow {
   const double2 *p;
-  __device__ __forceinline__ double operator()(double t, double t_last, int k_last) const {
+  __device__ __forceinline__ double operator()(double t, double t_last, int) const {
     t = fmin(t, t_last);
-    int k = (int)t;
-    k = k < k_last ? k : k_last;
-    const double f = t - (double)k;
-    const double2 gd = p[k];
-    return __builtin_fma(f, gd.y, gd.x);
+    const double2 gd = p[(int)t];
+    return __builtin_fma(__builtin_amdgcn_fract(t), gd.y, gd.x);
+  }
+  __device__ __forceinline__ void locate(double t, int, int &k, double &f) const {
+    k = (int)t;                       // t >= 0: floor
+    f = __builtin_amdgcn_fract(t);    // t - floor(t), exact
   }
   __device__ __forceinline__ double2 fetch(int k) const { return p[k]; }
 };
@@ -95,13 +106,8 @@ __device__ __forceinline__ void tab_block(const TabArgs &a, const Row row, const
           int kq[UR > 0 ? UR : 1];
           double fq[UR > 0 ? UR : 1];
 #pragma unroll
-          for (int u = 0; u < UR; ++u) {
-            const double t = fmin(__builtin_fma(bh, ro[u], ah), a.t_last);
-            int k = (int)t;
-            k = k < k_last ? k : k_last;
-            kq[u] = k;
-            fq[u] = t - (double)k;
-          }
+          for (int u = 0; u < UR; ++u)
+            row.locate(fmin(__builtin_fma(bh, ro[u], ah), a.t_last), k_last, kq[u], fq[u]);
           double2 gd[UR > 0 ? UR : 1];
 #pragma unroll
           for (int u = 0; u < UR; ++u) gd[u] = row.fetch(kq[u]);
@@ -170,9 +176,15 @@ __global__ __launch_bounds__(256) void tab_kernel(TabArgs a) {
     const double *grow = a.g + r * a.n_s;
     if constexpr (PAIRS) {
       double2 *lp = reinterpret_cast<double2 *>(lg);
-      for (int k = threadIdx.x; k < (int)a.n_s - 1; k += blockDim.x) {
-        const double g0 = grow[k], g1 = grow[k + 1];
-        lp[k] = make_double2(g0, g1 - g0);
+      const int n_s = (int)a.n_s;
+      for (int k = threadIdx.x; k < n_s; k += blockDim.x) {
+        if (k + 1 < n_s) {
+          const double g0 = grow[k];
+          lp[k] = make_double2(g0, grow[k + 1] - g0);
+        } else {
+          const double g0 = grow[n_s - 2];
+          lp[k] = make_double2(__builtin_fma(1.0, grow[n_s - 1] - g0, g0), 0.0);
+        }
       }
       __syncthreads();
       const PairRow row{lp};
@@ -213,7 +225,7 @@ void tab_lane_split(int n_r, int n_a, int *R, int *J, int *T, int *U) {
 }
 
 int tab_lds_bytes(const TabArgs &t, bool lds_rows) {
-  const int row = !lds_rows ? 0 : t.pairs ? (int)(2 * (t.n_s - 1)) : (int)t.n_s;
+  const int row = !lds_rows ? 0 : t.pairs ? (int)(2 * t.n_s) : (int)t.n_s;
   return (int)(sizeof(double) * (2 * t.n_r + 2 * t.n_a + row));
 }
 
