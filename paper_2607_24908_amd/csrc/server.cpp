@@ -25,6 +25,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <condition_variable>
 #include <cstdlib>
@@ -57,6 +59,7 @@ struct Flow {
   double *jac_dst = nullptr;
   bool want_jac = false;
   bool ready = false;
+  std::atomic<bool> ready_a{false};  // mirror of ready for waiting without the lock
   int rc = FRG_OK;
   bool done = false;
   std::condition_variable cv;
@@ -74,6 +77,7 @@ struct Server {
   std::condition_variable cv_disp;
   std::deque<Flow *> queue;
   std::vector<Flow *> pending;
+  std::atomic<int> n_pending{0};  // size of pending, for waiting without the lock
   std::map<uint64_t, Flow *> flows;
   uint64_t next_ticket = 1;
   int active = 0;
@@ -93,6 +97,23 @@ struct Server {
   void run_flow(Flow *f);
   bool grow_stage(size_t bytes);
 };
+
+// A right-hand side comes back, and the next call arrives, within tens of
+// microseconds while flows run; the dispatcher and the steppers poll for
+// that long before they sleep on their condition variables (a wake-up
+// through the kernel costs about as much as the call itself).
+constexpr double kSpinSeconds = 200e-6;
+
+template <class Cond>
+static bool spin_until(Cond cond) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int i = 0;; ++i) {
+    if (cond()) return true;
+    if ((i & 63) == 63 && std::chrono::duration<double>(std::chrono::steady_clock::now() - t0)
+                                  .count() > kSpinSeconds)
+      return false;
+  }
+}
 
 int Server::start() {
   if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess)
@@ -161,18 +182,25 @@ int Server::rhs_cb(void *user, double t, const double *U, int64_t n, double *dUd
   Flow *f = static_cast<Flow *>(user);
   Server *s = f->srv;
   if (n != f->n) return FRG_E_INVAL;
-  std::unique_lock<std::mutex> lk(s->m);
-  if (s->stop) return FRG_E_DEVICE;
-  f->t = t;
-  f->U_src = U;
-  f->dUdt_dst = dUdt;
-  f->jac_dst = jac;
-  f->want_jac = jac != nullptr;
-  f->ready = false;
-  s->pending.push_back(f);
+  {
+    std::lock_guard<std::mutex> lk(s->m);
+    if (s->stop) return FRG_E_DEVICE;
+    f->t = t;
+    f->U_src = U;
+    f->dUdt_dst = dUdt;
+    f->jac_dst = jac;
+    f->want_jac = jac != nullptr;
+    f->ready = false;
+    f->ready_a.store(false, std::memory_order_relaxed);
+    s->pending.push_back(f);
+    s->n_pending.fetch_add(1, std::memory_order_release);
+  }
   s->cv_disp.notify_one();
-  f->cv.wait(lk, [&] { return f->ready || s->stop; });
-  if (!f->ready) return FRG_E_DEVICE;
+  if (!spin_until([&] { return f->ready_a.load(std::memory_order_acquire); })) {
+    std::unique_lock<std::mutex> lk(s->m);
+    f->cv.wait(lk, [&] { return f->ready || s->stop; });
+    if (!f->ready) return FRG_E_DEVICE;
+  }
   return f->rc;
 }
 
@@ -206,11 +234,13 @@ void Server::dispatch_loop() {
   hipSetDevice(ctx->device);
   for (;;) {
     batch.clear();
+    spin_until([&] { return n_pending.load(std::memory_order_acquire) > 0; });
     {
       std::unique_lock<std::mutex> lk(m);
       cv_disp.wait(lk, [&] { return !pending.empty() || stop; });
       if (stop) return;
       batch.swap(pending);
+      n_pending.store(0, std::memory_order_relaxed);
     }
     const int nb = (int)batch.size();
     lpas.resize(nb);
@@ -299,6 +329,7 @@ void Server::dispatch_loop() {
       Flow *f = batch[i];
       f->rc = !ok ? rc : (flags[i] ? FRG_E_DOMAIN : FRG_OK);
       f->ready = true;
+      f->ready_a.store(true, std::memory_order_release);
       f->cv.notify_one();
     }
   }
