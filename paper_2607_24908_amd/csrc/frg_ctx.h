@@ -62,7 +62,7 @@ struct GridCfg {
 };
 struct PersistCfg {
   int tile = 4;  // points per tile
-  int wpc = 16;  // resident one-wave workgroups per CU
+  int wpc = 24;  // resident one-wave workgroups per CU
 };
 using ShapeKey = std::tuple<int, int, int, int>;  // (regulator, n_r, n_a, precision)
 

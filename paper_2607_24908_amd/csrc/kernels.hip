@@ -78,7 +78,9 @@ __global__ __launch_bounds__(64) void points_persistent_kernel(const SetDev *__r
   for (;;) {
     int t = 0;
     if (lane == 0) t = atomicAdd(counter, 1);
-    t = __shfl(t, 0, kWave);
+    // lane 0 holds the tile: make it (and the tile and set descriptors read
+    // with it) wave-uniform, in scalar registers
+    t = __builtin_amdgcn_readfirstlane(t);
     if (t >= n_tiles) break;
     const Tile tl = tiles[t];
     const SetDev s = sets[tl.set];
