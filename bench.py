@@ -252,7 +252,10 @@ def main():
 
 
 def timed(fn, torch, reps=5):
-    fn()
+    """Seconds per call of fn over `reps` calls after max(2, reps // 2)
+    warm-up calls (the clock ramps up under load)."""
+    for _ in range(max(2, reps // 2)):
+        fn()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
@@ -275,9 +278,9 @@ def secondary(ctx, frg, workloads, torch):
                        out=torch.empty(s.p.size, dtype=torch.float64, device="cuda")))
     n_int = sum(s.p.size for s in sets)
     t_plain = timed(lambda: frg.frg_integrate(ctx, ds, flags=frg.FRG_PLAIN), torch)
-    t_pers = timed(lambda: frg.frg_integrate(ctx, ds, flags=frg.FRG_PERSISTENT), torch)
+    t_pers = timed(lambda: frg.frg_integrate(ctx, ds, flags=frg.FRG_PERSISTENT), torch, reps=20)
     t_graph = timed(lambda: frg.frg_integrate(ctx, ds, flags=frg.FRG_PERSISTENT | frg.FRG_GRAPH),
-                    torch)
+                    torch, reps=20)
     sec["uneven_sets_seed0"] = {
         "sets": len(sets), "integrals": n_int, "evals": evals,
         "plain_evals_per_s": evals / t_plain, "persistent_evals_per_s": evals / t_pers,
@@ -306,7 +309,7 @@ def secondary(ctx, frg, workloads, torch):
                                                device="cuda")))
     t32 = timed(lambda: frg.frg_integrate(ctx, ds32, flags=frg.FRG_PLAIN), torch)
     t32g = timed(lambda: frg.frg_integrate(ctx, ds32, flags=frg.FRG_PERSISTENT | frg.FRG_GRAPH),
-                 torch)
+                 torch, reps=20)
     frg.frg_integrate(ctx, ds, flags=frg.FRG_PLAIN)
     torch.cuda.synchronize()
     dev_max = max(((a["out"] - b["out"]).abs() / b["out"]).max().item() for a, b in zip(ds32, ds))
