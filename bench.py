@@ -395,9 +395,10 @@ def fv_lpa(ctx, frg, workloads, torch, reps=3):
 
 def momentum_flow(ctx, frg, workloads, torch, reps=3):
     """Momentum-dependent two-point flows: 64 flows x 256 momentum nodes,
-    128 x 32 rule, 100 RK4 steps (400 right-hand sides, each one tabulated
-    diagram over all flows and nodes plus the table / tadpole and stage
-    kernels), all on the device; time per whole solve."""
+    128 x 32 rule, 100 RK4 steps (400 right-hand sides, each one launch that
+    redoes the previous stage's update, builds the table rows and tadpoles
+    and evaluates the tabulated diagram over all flows and nodes), all on
+    the device; time per whole solve."""
     w = workloads.pflow_d3()
     pf = frg.make_pflow(w.d, w.reg, w.n_r, w.n_a, w.lam, w.kappa, w.n_s, w.s_max)
     l3 = torch.as_tensor(w.lam3, device="cuda")

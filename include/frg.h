@@ -418,7 +418,10 @@ int frg_autotune(frg_ctx *ctx, int32_t mode, const char *cache_path);
  * agree to a few ulp), "fv_persistent" (finite-volume solves, 1: one
  * workgroup per flow runs the steps with its cells in LDS, the default where
  * 3 n_cells + 2 n_radial doubles fit in 64 KiB; 0: two launches per stage;
- * the same bits), "server_zero_copy" (flow server, 1: the LPA kernel reads
+ * the same bits), "pflow_fused" (momentum-dependent flows with rows in LDS,
+ * 1: one launch per RK4 stage, each workgroup redoing the previous stage's
+ * update for its row, the default; 0: a diagram launch and a stage launch
+ * per stage; the same bits), "server_zero_copy" (flow server, 1: the LPA kernel reads
  * and writes the pinned batch buffer in place, the default; 0: one upload and
  * one download per batch; the same bits), "grid_lds_rows" (8..96), "plain_tile", "persist_tile" (1..64),
  * "persist_wpc" (1..64), and of the tabulated variant "tab_W" (1..4),

@@ -580,14 +580,17 @@ int Ctx::tab_device(const frg_quad &q, const frg_gtab &tb, int64_t n_p, const do
   a.n_p = n_p;
   a.n_rows = tb.n_rows;
   a.n_s = tb.n_s;
+  a.os_p = tb.n_rows;
+  a.os_r = 1;
   a.n_r = q.n_radial;
   a.n_a = q.n_angular;
   return tab_launch(a, q.reg, st);
 }
 
 // Launch shape of tab_kernel for the problem in `a` (p, out, g, tab, flag,
-// pref, k2, inv_h, t_last, n_p, n_rows, n_s, n_r, n_a set by the caller).
-int Ctx::tab_launch(TabArgs a, int reg, hipStream_t st) {
+// pref, k2, inv_h, t_last, n_p, n_rows, n_s, os_p, os_r, n_r, n_a set by the
+// caller).
+int Ctx::tab_config(TabArgs &a, bool &lds_rows_out, int &W_out, int64_t &sblocks_out) {
   const int64_t n_p = a.n_p;
   tab_lane_split(a.n_r, a.n_a, &a.R, &a.J, &a.T, &a.U);
   a.pairs = tune.tab_pairs ? 1 : 0;
@@ -612,6 +615,18 @@ int Ctx::tab_launch(TabArgs a, int reg, hipStream_t st) {
     a.n_pb = (int)((n_p + (int64_t)W * a.pw - 1) / ((int64_t)W * a.pw));
   }
   if (a.n_rows * a.n_pb > ((int64_t)1 << 31) - 1) return fail(FRG_E_INVAL, "tabulated problem too large");
+  lds_rows_out = lds_rows;
+  W_out = W;
+  sblocks_out = sblocks;
+  return FRG_OK;
+}
+
+int Ctx::tab_launch(TabArgs a, int reg, hipStream_t st) {
+  bool lds_rows = false;
+  int W = 1;
+  int64_t sblocks = 0;
+  const int rc = tab_config(a, lds_rows, W, sblocks);
+  if (rc) return rc;
   int e = launch_tab(a, reg, W, lds_rows, sblocks, st);
   if (e) return hip_fail((hipError_t)e, "tab_kernel launch");
   return FRG_OK;

@@ -81,6 +81,7 @@ struct Tune {
   int grid_lds_rows = 64;  // (t, u) rows of 64 doubles staged per LDS chunk
   int grid_form = 0;       // resident FP64 grid: 0 per-momentum coefficients, 1 running fractions
   int grid_mfma = 1;       // coefficient form: 1 tiles of 16 masses on the matrix cores, 0 vector units
+  int pflow_fused = 1;     // momentum flow, rows in LDS: 1 one launch per stage; 0 diagram + stage launches
   int fv_persistent = 1;   // finite-volume solves: 1 one workgroup per flow, state in LDS; 0 launches per stage
   int server_zero_copy = 1;  // flow server: 1 kernel reads/writes the pinned batch buffer; 0 two copies
   int fp32c_flag_ppb = 100;    // FP32C: FP64 redo above this error estimate (1e-9 units)
@@ -145,6 +146,9 @@ struct Context {
   int integrate_fp32c_sets(const std::vector<frg::SetDev> &sd, int flags, hipStream_t st);
   int tab_device(const frg_quad &q, const frg_gtab &tab, int64_t n_p, const double *p, double *out,
                  hipStream_t st);
+  // Launch shape of the table kernel for a (fills R, J, T, U, pairs, pw and
+  // n_pb of a): rows in LDS or streamed, waves per workgroup, streaming grid.
+  int tab_config(frg::TabArgs &a, bool &lds_rows, int &W, int64_t &sblocks);
   int tab_launch(frg::TabArgs a, int reg, hipStream_t st);
   // pflow_api.cpp: momentum-dependent flow; dsdt != nullptr: one right-hand side
   // at t_rhs, else RK4 from 0 to t_end (all arrays on the device)

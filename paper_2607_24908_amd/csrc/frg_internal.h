@@ -140,12 +140,13 @@ void lane_split(int n_r, int n_a, int *R, int *J, int *T, int *U);
 // entries), R = 64 / J radial lanes.
 struct TabArgs {
   const double *p;
-  double *out;
+  double *out;        // out[a * os_p + r * os_r] for momentum a of row r
   const double *g;    // table rows, g[r * n_s + k]
   const double *tab;  // QuadTable::data on the device
   int *flag;
   double pref, k2, inv_h, t_last;  // t_last = n_s - 1
   int64_t n_p, n_rows, n_s;
+  int64_t os_p, os_r;
   int32_t n_r, n_a, R, J, T, U;
   int32_t pw;     // momenta per wave
   int32_t n_pb;   // momentum blocks per row (W * pw momenta each)
@@ -216,6 +217,31 @@ int launch_fv_solve(const FvArgs &a, int64_t s0, int64_t n_st, int threads, void
 int launch_pflow_init(const PflowArgs &a, double t_end, void *stream);
 int launch_pflow_prep(const PflowArgs &a, int reg, void *stream);
 int launch_pflow_stage(const PflowArgs &a, int reg, void *stream);
+// One launch per stage (pflow_pull_kernel): the update of the previous
+// stage, the prep and the diagram of this one.  Arrays "p" are the previous
+// launch's, arrays "n" this launch's (stored by the workgroup with pb = 0);
+// the two never alias, except y0p / y0n where only y0n is written.
+struct PflowPull {
+  const double *base;  // QuadTable data at k = 1, q_max = kappa (device)
+  const double *lam3, *lam4;
+  const double *Jp, *Tp, *accp, *y0p;  // J[r * n_s + a]; y0p: state at the start of the step
+  const int *alivep;
+  double *Jn, *Tn, *accn, *y0n;        // y0n: new step-start state (prev = 3)
+  int *aliven;
+  double *t_reached;
+  double *dsdt;  // right-hand side only (final update, prev = 4)
+  int *flag;
+  double k, k2, kd2, Cd;  // scale of this stage, kd2 = k^(d+2)
+  double h_s, inv_h, t_last;
+  double t_n, h;  // start of this stage's step, step size
+  int64_t n_rows, n_s;
+  int32_t n_r, n_a;
+  int32_t prev;  // stage of the previous launch (0..3), -1 none; final update: 3 or 4
+};
+int pflow_pull_lds_bytes(const TabArgs &t);
+// t: the diagram (t.tab = the table at k = 1, t.out = a.Jn), rows in LDS, W waves
+int launch_pflow_pull(const TabArgs &t, const PflowPull &a, int reg, int W, void *stream);
+int launch_pflow_final(const PflowPull &a, void *stream);
 constexpr int64_t tab_lds_max_nodes = 6144;  // rows up to this many nodes are staged in LDS
 
 

@@ -94,13 +94,12 @@ __global__ __launch_bounds__(256) void pflow_prep_kernel(PflowArgs a) {
   prep_row<REG>(a, r, a.y0 + r * a.n_s, a.alive[r] != 0);
 }
 
-// One workgroup per flow: right-hand side rhs = lam3^2 J - lam4/2 T of the
+// Flow r (all threads of the workgroup): right-hand side rhs = lam3^2 J - lam4/2 T of the
 // stage just evaluated and its RK4 update (stage 0..3; 4: rhs only), then,
 // if a.prep, the table row, domain check and tadpole of the next stage (at
 // a.k, step start a.t_n; state ys after stages 0..2, y0 after stage 3).
 template <int REG>
-__global__ __launch_bounds__(256) void pflow_stage_kernel(PflowArgs a) {
-  const int64_t r = blockIdx.x;
+__device__ __forceinline__ void stage_row(const PflowArgs &a, int64_t r) {
   const int64_t ns = a.n_s;
   const bool alive = a.alive[r] != 0;  // workgroup-uniform
   if (alive) {
@@ -139,6 +138,158 @@ __global__ __launch_bounds__(256) void pflow_stage_kernel(PflowArgs a) {
   prep_row<REG>(a, r, (a.stage == 3 ? a.y0 : a.ys) + r * ns, alive);
 }
 
+template <int REG>
+__global__ __launch_bounds__(256) void pflow_stage_kernel(PflowArgs a) {
+  stage_row<REG>(a, blockIdx.x);
+}
+
+// ---- one launch per stage -------------------------------------------------
+// Launch m of a solve evaluates the diagram of RK4 stage m.  Each of its
+// workgroups (row r, momentum block pb) first redoes, for the whole row, the
+// update that the stage kernel would do after stage m - 1 (from J, T, the
+// accumulator and the step-start state of the previous launch), then the prep
+// of stage m, with the propagator row built in LDS.  Every workgroup of a row
+// computes the same values; only the one with pb = 0 stores the new state,
+// tadpole and flags, into buffers that no workgroup of the launch reads
+// (read and written state alternate between launches), so a launch needs no
+// communication between workgroups.  Same arithmetic, in the same order, as
+// pflow_stage_kernel + prep_row + tab_kernel: the same bits.
+
+// State of stage m at node i of row r (the previous stage's update): the
+// state itself for the first launch; for a flow that has stopped, its
+// step-start state (carried into the new step-start buffer after stage 3).
+__device__ __forceinline__ double pull_state(const PflowPull &a, int64_t r, int64_t i, bool alive,
+                                             double l3, double c4, bool writer) {
+  const int64_t e = r * a.n_s + i;
+  if (a.prev < 0) return a.y0p[e];
+  if (!alive) {
+    const double y = a.y0p[e];
+    if (a.prev == 3 && writer) a.y0n[e] = y;
+    return y;
+  }
+  const double rhs = l3 * l3 * a.Jp[e] - c4;
+  switch (a.prev) {
+    case 0:
+      if (writer) a.accn[e] = rhs;
+      return a.y0p[e] + (0.5 * a.h) * rhs;
+    case 1:
+      if (writer) a.accn[e] = a.accp[e] + 2.0 * rhs;
+      return a.y0p[e] + (0.5 * a.h) * rhs;
+    case 2:
+      if (writer) a.accn[e] = a.accp[e] + 2.0 * rhs;
+      return a.y0p[e] + a.h * rhs;
+    default: {
+      const double y = a.y0p[e] + (a.h / 6.0) * (a.accp[e] + rhs);
+      if (writer) a.y0n[e] = y;
+      return y;
+    }
+  }
+}
+
+// t: the diagram at scale a.k (t.tab = the table at k = 1, t.out = a.Jn,
+// J[r * n_s + a]).  LDS: tab_lds's layout, then (pairs) the row as plain
+// values.
+template <int REG, int UR, bool PAIRS>
+__global__ __launch_bounds__(256) void pflow_pull_kernel(TabArgs t, PflowPull a) {
+  extern __shared__ double lds[];
+  const int W = blockDim.x / kWave;
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int n_r = a.n_r;
+  const int n_s = (int)a.n_s;
+  const int64_t r = blockIdx.x / t.n_pb;
+  const int64_t pb = blockIdx.x - r * t.n_pb;
+  const bool writer = pb == 0;
+  const TabLds l = tab_lds(t, lds);
+  double *lv = PAIRS ? l.lg + 2 * n_s : l.lg;
+  // update of the previous stage and the row of this one
+  const bool alive = a.alivep[r] != 0;  // workgroup-uniform
+  double l3 = 0.0, c4 = 0.0;
+  if (alive && a.prev >= 0) {
+    l3 = a.lam3[r];
+    c4 = 0.5 * a.lam4[r] * a.Tp[r];
+  }
+  const double inv_k2 = 1.0 / a.k2;
+  bool bad = false;
+  for (int i = threadIdx.x; i < n_s; i += blockDim.x) {
+    const double y = pull_state(a, r, i, alive, l3, c4, writer);
+    const double s = (double)i * a.h_s;
+    const double den = (hk<REG>(s, a.k2, inv_k2) + a.k2) + y;
+    const bool ok = den > 0.0;
+    bad |= !ok;
+    lv[i] = (alive && ok) ? 1.0 / den : 0.0;
+  }
+  bad = __syncthreads_or(bad) && alive;
+  if (bad) {
+    // the flow ends at the start of this step with its state kept
+    for (int i = threadIdx.x; i < n_s; i += blockDim.x) lv[i] = 0.0;
+    if (writer && threadIdx.x == 0) {
+      a.t_reached[r] = a.t_n;
+      *a.flag = 1;
+    }
+    __syncthreads();
+  }
+  if (writer && threadIdx.x == 0) a.aliven[r] = alive && !bad;
+  // the diagram: the row as tab_row_block stages it, q_i and A_i at scale k
+  if constexpr (PAIRS) {
+    double2 *lp = reinterpret_cast<double2 *>(l.lg);
+    for (int k = threadIdx.x; k < n_s; k += blockDim.x) {
+      if (k + 1 < n_s) {
+        const double g0 = lv[k];
+        lp[k] = make_double2(g0, lv[k + 1] - g0);
+      } else {
+        const double g0 = lv[n_s - 2];
+        lp[k] = make_double2(__builtin_fma(1.0, lv[n_s - 1] - g0, g0), 0.0);
+      }
+    }
+  }
+  __syncthreads();
+  auto stage_A = [&](const auto row) {
+    for (int i = threadIdx.x; i < n_r; i += blockDim.x) {
+      const double q = a.k * a.base[i];
+      const double G = row((q * q) * t.inv_h, t.t_last, n_s - 2);
+      l.lq[i] = q;
+      l.lA[i] = ((a.kd2 * a.base[n_r + i]) * G) * G;
+    }
+    __syncthreads();
+    tab_block<UR>(t, row, l.lq, l.lA, l.lo, l.lm, r, pb, W, wave, lane);
+  };
+  if constexpr (PAIRS)
+    stage_A(PairRow{reinterpret_cast<const double2 *>(l.lg)});
+  else
+    stage_A(PlainRow{lv});
+  // tadpole of this stage, as prep_row (wave 0 of the storing workgroup)
+  if (writer && threadIdx.x < kWave) {
+    double acc = 0.0;
+    for (int i = lane; i < n_r; i += kWave) {
+      const double q = a.k * a.base[i];
+      const double c = a.kd2 * a.base[n_r + i];
+      const double G = interp(lv, (q * q) * a.inv_h, a.t_last, n_s - 2);
+      acc = __builtin_fma((c * G), G, acc);
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) a.Tn[r] = a.Cd * acc;
+  }
+}
+
+// The update after the last launch: the final state (a.prev = 3, a.y0n the
+// caller's state) or the right-hand side (a.prev = 4: dsdt, NaN rows for
+// flows outside the domain).  One workgroup per flow.
+__global__ __launch_bounds__(256) void pflow_final_kernel(PflowPull a) {
+  const int64_t r = blockIdx.x;
+  const bool alive = a.alivep[r] != 0;
+  double l3 = 0.0, c4 = 0.0;
+  if (alive) {
+    l3 = a.lam3[r];
+    c4 = 0.5 * a.lam4[r] * a.Tp[r];
+  }
+  for (int64_t i = threadIdx.x; i < a.n_s; i += blockDim.x) {
+    if (a.prev == 4)
+      a.dsdt[r * a.n_s + i] = alive ? l3 * l3 * a.Jp[r * a.n_s + i] - c4 : __builtin_nan("");
+    else
+      (void)pull_state(a, r, i, alive, l3, c4, true);
+  }
+}
 }  // namespace
 
 int launch_pflow_init(const PflowArgs &a, double t_end, void *stream) {
@@ -168,6 +319,51 @@ int launch_pflow_stage(const PflowArgs &a, int reg, void *stream) {
   else
     hipLaunchKernelGGL(pflow_stage_kernel<kLitim>, dim3((unsigned)a.n_rows), dim3(256), 0,
                        (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+int pflow_pull_lds_bytes(const TabArgs &t) {
+  return tab_lds_bytes(t, true) + (t.pairs ? (int)(sizeof(double) * t.n_s) : 0);
+}
+
+// Dynamic LDS beyond 64 KiB (gfx950: 160 KiB per workgroup); a refusal where
+// no opt-in is needed is cleared so that it cannot be taken for a launch error.
+template <int REG, int UR, bool P>
+static void pflow_pull_t(const TabArgs &t, const PflowPull &a, int W, hipStream_t st) {
+  static const bool once = [] {
+    (void)hipFuncSetAttribute((const void *)&pflow_pull_kernel<REG, UR, P>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipGetLastError();
+    return true;
+  }();
+  (void)once;
+  hipLaunchKernelGGL((pflow_pull_kernel<REG, UR, P>), dim3((unsigned)(t.n_rows * t.n_pb)),
+                     dim3(kWave * W), pflow_pull_lds_bytes(t), st, t, a);
+}
+
+template <int REG>
+static void pflow_pull_reg(const TabArgs &t, const PflowPull &a, int W, hipStream_t st) {
+  const bool regs = t.U <= 4;
+  if (t.pairs)
+    regs ? pflow_pull_t<REG, 4, true>(t, a, W, st) : pflow_pull_t<REG, 0, true>(t, a, W, st);
+  else
+    regs ? pflow_pull_t<REG, 4, false>(t, a, W, st) : pflow_pull_t<REG, 0, false>(t, a, W, st);
+}
+
+int launch_pflow_pull(const TabArgs &t, const PflowPull &a, int reg, int W, void *stream) {
+  if (t.n_p <= 0 || t.n_rows <= 0) return 0;
+  hipStream_t st = (hipStream_t)stream;
+  if (reg == kExp)
+    pflow_pull_reg<kExp>(t, a, W, st);
+  else
+    pflow_pull_reg<kLitim>(t, a, W, st);
+  return (int)hipGetLastError();
+}
+
+int launch_pflow_final(const PflowPull &a, void *stream) {
+  if (a.n_rows <= 0) return 0;
+  hipLaunchKernelGGL(pflow_final_kernel, dim3((unsigned)a.n_rows), dim3(256), 0,
+                     (hipStream_t)stream, a);
   return (int)hipGetLastError();
 }
 

@@ -44,11 +44,13 @@ int Ctx::pflow_device(const frg_pflow &pf, int64_t n, const double *lam3, const 
   if (rc) return rc;
   const int64_t ns = pf.n_s, nrs = n * ns;
   const bool solve = dsdt == nullptr;
-  // scratch: tabk | p | g | J | T | [ys | acc] | [t_reached] | alive
+  // scratch: tabk | p | g | J (2) | T (2) | [ys | acc (2) | y0 (one launch per
+  // stage: the step-start state alternates between sigma and this one)] |
+  // [t_reached] | alive (2)
   const size_t tabd = (size_t)table_doubles(pf.n_radial, pf.n_angular);
-  const size_t nd = tabd + ns + 2 * nrs + n + (solve ? 2 * nrs : 0) + (t_reached ? 0 : n);
+  const size_t nd = tabd + ns + 3 * nrs + 2 * n + (solve ? 4 * nrs : 0) + (t_reached ? 0 : n);
   void *buf = nullptr;
-  hipError_t e = hipMallocAsync(&buf, nd * sizeof(double) + (size_t)n * sizeof(int) + 64, st);
+  hipError_t e = hipMallocAsync(&buf, nd * sizeof(double) + 2 * (size_t)n * sizeof(int) + 64, st);
   if (e != hipSuccess) return fail(FRG_E_NOMEM, "pflow scratch: %s", hipGetErrorString(e));
   double *d = (double *)buf;
   PflowArgs a{};
@@ -59,14 +61,17 @@ int Ctx::pflow_device(const frg_pflow &pf, int64_t n, const double *lam3, const 
   d += ns;
   a.g = d;
   d += nrs;
-  a.J = d;
-  d += nrs;
-  a.T = d;
-  d += n;
+  double *const Js = d;  // J of even / odd launches
+  d += 2 * nrs;
+  double *const Ts = d;
+  d += 2 * n;
+  double *accs = nullptr, *y0s = nullptr;
   if (solve) {
     a.ys = d;
     d += nrs;
-    a.acc = d;
+    accs = d;
+    d += 2 * nrs;
+    y0s = d;
     d += nrs;
   }
   if (t_reached) {
@@ -75,7 +80,11 @@ int Ctx::pflow_device(const frg_pflow &pf, int64_t n, const double *lam3, const 
     a.t_reached = d;
     d += n;
   }
-  a.alive = (int *)d;
+  int *const alives = (int *)d;
+  a.J = Js;
+  a.T = Ts;
+  a.acc = accs;
+  a.alive = alives;
   a.lam3 = lam3;
   a.lam4 = lam4;
   a.y0 = sigma;
@@ -101,8 +110,15 @@ int Ctx::pflow_device(const frg_pflow &pf, int64_t n, const double *lam3, const 
   tb.n_p = ns;
   tb.n_rows = n;
   tb.n_s = ns;
+  tb.os_p = n;  // J[a * n_rows + r]; one launch per stage: J[r * n_s + a]
+  tb.os_r = 1;
   tb.n_r = pf.n_radial;
   tb.n_a = pf.n_angular;
+  bool lds_rows = false;
+  int W = 1;
+  int64_t sblocks = 0;
+  rc = tab_config(tb, lds_rows, W, sblocks);
+  const bool pull = tune.pflow_fused && lds_rows && pflow_pull_lds_bytes(tb) <= 150 * 1024;
   auto set_scale = [&](double t, double tn) {
     a.k = pf.lambda * std::exp(t);
     a.k2 = a.k * a.k;
@@ -110,40 +126,121 @@ int Ctx::pflow_device(const frg_pflow &pf, int64_t n, const double *lam3, const 
     a.t_n = tn;
     tb.k2 = a.k2;
   };
-  // prep of the first stage, then per stage: diagram, update (+ next prep)
-  auto first_prep = [&](double t, double tn) -> int {
-    set_scale(t, tn);
-    int r = launch_pflow_prep(a, pf.reg, st);
-    return r ? hip_fail((hipError_t)r, "pflow_prep_kernel launch") : FRG_OK;
-  };
-  auto stage_step = [&](int stage, bool prep_next, double t_next, double tn_next) -> int {
-    int r = tab_launch(tb, pf.reg, st);
-    if (r) return r;
-    a.stage = stage;
-    a.prep = prep_next ? 1 : 0;
-    if (prep_next) set_scale(t_next, tn_next);
-    r = launch_pflow_stage(a, pf.reg, st);
-    return r ? hip_fail((hipError_t)r, "pflow_stage_kernel launch") : FRG_OK;
-  };
-  rc = launch_pflow_init(a, solve ? t_end : t_rhs, st);
-  if (rc) rc = hip_fail((hipError_t)rc, "pflow_init_kernel launch");
-  if (!rc && !solve) {
-    rc = first_prep(t_rhs, t_rhs);
-    if (!rc) rc = stage_step(4, false, 0.0, 0.0);
+  if (!rc) {
+    rc = launch_pflow_init(a, solve ? t_end : t_rhs, st);
+    if (rc) rc = hip_fail((hipError_t)rc, "pflow_init_kernel launch");
   }
-  if (!rc && solve) {
-    const double hh = t_end / (double)n_steps;
-    const double cs[4] = {0.0, 0.5, 0.5, 1.0};
-    a.h = hh;
-    rc = first_prep(0.0, 0.0);
-    for (int64_t step = 0; step < n_steps && !rc; ++step) {
-      const double tn = (double)step * hh;
-      for (int s = 0; s < 4 && !rc; ++s) {
-        // the stage after (step, s): (step, s + 1), or (step + 1, 0)
-        const bool last = s == 3 && step + 1 == n_steps;
-        const double tn_next = s < 3 ? tn : (double)(step + 1) * hh;
-        const double t_next = s < 3 ? tn + cs[s + 1] * hh : tn_next;
-        rc = stage_step(s, !last, t_next, tn_next);
+  const double hh = solve ? t_end / (double)n_steps : 0.0;
+  const double cs[4] = {0.0, 0.5, 0.5, 1.0};
+  a.h = hh;
+  if (!rc && pull) {
+    // launch m (stage m of the solve, or the one right-hand side) reads the
+    // arrays of parity (m - 1) mod 2 and writes those of parity m mod 2
+    // (alive: reads m mod 2, writes (m + 1) mod 2); step s starts from
+    // y0[s mod 2], y0[0] being the caller's state
+    PflowPull u{};
+    u.base = base;
+    u.lam3 = lam3;
+    u.lam4 = lam4;
+    u.t_reached = a.t_reached;
+    u.dsdt = dsdt;
+    u.flag = flag;
+    u.Cd = a.Cd;
+    u.h_s = a.h_s;
+    u.inv_h = a.inv_h;
+    u.t_last = a.t_last;
+    u.h = hh;
+    u.n_rows = n;
+    u.n_s = ns;
+    u.n_r = pf.n_radial;
+    u.n_a = pf.n_angular;
+    tb.tab = base;
+    tb.os_p = 1;
+    tb.os_r = ns;
+    double *const y0b[2] = {sigma, y0s};
+    auto point = [&](int64_t m, int prev, int64_t step) {
+      const int c = (int)(m & 1), o = c ^ 1;
+      u.prev = prev;
+      u.Jp = Js + o * nrs;
+      u.Jn = Js + c * nrs;
+      u.Tp = Ts + o * n;
+      u.Tn = Ts + c * n;
+      if (solve) {
+        u.accp = accs + o * nrs;
+        u.accn = accs + c * nrs;
+        const bool new_step = prev == 3;
+        u.y0p = y0b[(step + (new_step ? 1 : 0)) & 1];
+        u.y0n = y0b[step & 1];
+      } else {
+        u.y0p = sigma;
+        u.y0n = nullptr;
+      }
+      u.alivep = alives + c * n;
+      u.aliven = alives + o * n;
+    };
+    auto stage = [&](int64_t m, int prev, int64_t step, double t, double tn) -> int {
+      point(m, prev, step);
+      set_scale(t, tn);
+      u.k = a.k;
+      u.k2 = a.k2;
+      u.kd2 = a.kd2;
+      u.t_n = tn;
+      tb.out = u.Jn;
+      const int r = launch_pflow_pull(tb, u, pf.reg, W, st);
+      return r ? hip_fail((hipError_t)r, "pflow_pull_kernel launch") : FRG_OK;
+    };
+    int64_t m = 0;
+    if (!solve) {
+      rc = stage(0, -1, 0, t_rhs, t_rhs);
+      m = 1;
+    } else {
+      for (int64_t step = 0; step < n_steps && !rc; ++step) {
+        const double tn = (double)step * hh;
+        for (int s = 0; s < 4 && !rc; ++s, ++m)
+          rc = m == 0 ? stage(0, -1, 0, 0.0, 0.0)
+                      : stage(m, (s + 3) % 4, step, tn + cs[s] * hh, tn);
+      }
+    }
+    if (!rc) {
+      // the update after the last stage: into the caller's state, or dsdt
+      point(m, solve ? 3 : 4, solve ? n_steps : 0);
+      if (solve) {
+        u.y0p = y0b[(n_steps - 1) & 1];
+        u.y0n = sigma;
+      }
+      const int r = launch_pflow_final(u, st);
+      if (r) rc = hip_fail((hipError_t)r, "pflow_final_kernel launch");
+    }
+  } else if (!rc) {
+    // prep of the first stage, then per stage: diagram, update (+ next prep)
+    auto first_prep = [&](double t, double tn) -> int {
+      set_scale(t, tn);
+      int r = launch_pflow_prep(a, pf.reg, st);
+      return r ? hip_fail((hipError_t)r, "pflow_prep_kernel launch") : FRG_OK;
+    };
+    auto stage_step = [&](int stage, bool prep_next, double t_next, double tn_next) -> int {
+      int r = launch_tab(tb, pf.reg, W, lds_rows, sblocks, st);
+      if (r) return hip_fail((hipError_t)r, "tab_kernel launch");
+      a.stage = stage;
+      a.prep = prep_next ? 1 : 0;
+      if (prep_next) set_scale(t_next, tn_next);
+      r = launch_pflow_stage(a, pf.reg, st);
+      return r ? hip_fail((hipError_t)r, "pflow_stage_kernel launch") : FRG_OK;
+    };
+    if (!solve) {
+      rc = first_prep(t_rhs, t_rhs);
+      if (!rc) rc = stage_step(4, false, 0.0, 0.0);
+    } else {
+      rc = first_prep(0.0, 0.0);
+      for (int64_t step = 0; step < n_steps && !rc; ++step) {
+        const double tn = (double)step * hh;
+        for (int s = 0; s < 4 && !rc; ++s) {
+          // the stage after (step, s): (step, s + 1), or (step + 1, 0)
+          const bool last = s == 3 && step + 1 == n_steps;
+          const double tn_next = s < 3 ? tn : (double)(step + 1) * hh;
+          const double t_next = s < 3 ? tn + cs[s + 1] * hh : tn_next;
+          rc = stage_step(s, !last, t_next, tn_next);
+        }
       }
     }
   }

@@ -188,3 +188,51 @@ def test_bad_arguments(ctx):
         frg.frg_pflow_solve(ctx, pf, lam, lam, 0.5, 4, S, tr, mem=frg.FRG_MEM_HOST)
     with pytest.raises(frg.FrgError):
         frg.frg_pflow_solve(ctx, pf, lam, lam, -1.0, 0, S, tr, mem=frg.FRG_MEM_HOST)
+
+
+@pytest.mark.parametrize("case", range(len(SHAPES) + 1))
+def test_fused_and_two_launch_stages_same_bits(ctx, case):
+    """One launch per stage (every workgroup of a row redoes the previous
+    stage's RK4 update and the prep for its row, state buffers alternating
+    between launches), a diagram and a stage launch per stage, and rows
+    streamed from memory instead of LDS (two launches): the same bits, for
+    solves with flows that stop at the domain boundary and for one
+    right-hand side."""
+    rng = np.random.Generator(np.random.PCG64(100 + case))
+    if case < len(SHAPES):
+        d, reg, n_r, n_a, n_s, s_max = SHAPES[case]
+        n_flows = 9
+    else:
+        w = workloads.pflow_d3()
+        d, reg, n_r, n_a, n_s, s_max = w.d, w.reg, w.n_r, w.n_a, w.n_s, w.s_max
+        n_flows = 64
+    print(f"[case] pflow fused vs two launches d={d} n_r={n_r} n_a={n_a} n_s={n_s} "
+          f"flows={n_flows}", flush=True)
+    pf = frg.make_pflow(d, reg, n_r, n_a, 1.0, 6.0, n_s, s_max)
+    lam3 = rng.uniform(0.2, 2.5, n_flows)
+    lam4 = rng.uniform(0.0, 6.0, n_flows)
+    S0 = initial(rng, n_flows, n_s, s_max)
+    S0[0] -= 2.0        # outside the domain at t = 0
+    lam3[1] = 4.0       # driven towards the pole
+    keys = ("pflow_fused", "tab_lds_nodes")
+    default = {k: frg.frg_tune_get(ctx, k) for k in keys}
+    outs = []
+    try:
+        for fused, lds_nodes in ((1, default["tab_lds_nodes"]), (0, default["tab_lds_nodes"]),
+                                 (1, 2)):
+            frg.frg_tune_set(ctx, "pflow_fused", fused)
+            frg.frg_tune_set(ctx, "tab_lds_nodes", lds_nodes)
+            S, tr = gpu_solve(ctx, pf, lam3, lam4, -1.2, 12, S0)
+            r = np.empty_like(S0)
+            frg.frg_pflow_rhs(ctx, pf, lam3, lam4, -0.3, S0, r, mem=frg.FRG_MEM_HOST,
+                              allow_domain=True)
+            outs.append((S, tr, r))
+    finally:
+        for k in keys:
+            frg.frg_tune_set(ctx, k, default[k])
+    print("  t_reached", outs[0][1][:4], f"{np.sum(outs[0][1] == -1.2)}/{n_flows} to t_end")
+    assert outs[0][1][0] == 0.0
+    for S, tr, r in outs[1:]:
+        assert np.array_equal(tr, outs[0][1])
+        assert np.array_equal(S, outs[0][0])
+        assert np.array_equal(r, outs[0][2], equal_nan=True)
