@@ -67,3 +67,44 @@ def test_vertex_largest_azimuthal_orders(ctx, n_phi):
     err = np.abs(got - want) / np.abs(want)
     print(f"  max rel err {err.max():.3e}")
     assert err.max() < 1e-12
+
+
+# every knob of frg_tune_set with its documented range (include/frg.h):
+# (values accepted, values refused)
+KNOBS = {
+    "grid_M": ([4, 8, 16], [2, 12, 32]), "grid_W": ([1, 8], [0, 9]), "grid_MB": ([1, 64], [0, 65]),
+    "grid32_M": ([4, 8], [16]), "grid32_W": ([1, 8], [0, 9]), "grid32_MB": ([1, 64], [0, 65]),
+    "grid_form": ([0, 3], [-1, 4]), "grid_mfma": ([0, 1], [-1, 2]),
+    "fv_persistent": ([0, 1], [2]), "pflow_fused": ([0, 1], [-1, 2]),
+    "server_zero_copy": ([0, 1], [2]), "grid_lds_rows": ([8, 96], [7, 97]),
+    "plain_tile": ([1, 64], [0, 65]), "persist_tile": ([1, 64], [0, 65]),
+    "persist_wpc": ([1, 64], [0, 65]), "tab_W": ([1, 4], [0, 5]), "tab_pw": ([1, 64], [0, 65]),
+    "tab_lds_nodes": ([2, 6144], [1, 6145]), "tab_pairs": ([0, 1], [2]),
+    "tab_wpc": ([1, 16], [0, 17]), "tab_sW": ([1, 4], [0, 5]), "tab_spw": ([1, 64], [0, 65]),
+    "fp32c_flag_ppb": ([0, 100], [-1]), "fp32c_band_ppm": ([0, 1000], [-1]),
+}
+
+
+def test_tune_knobs_ranges_and_names(ctx):
+    """Each documented knob reads back what was set at the ends of its range,
+    refuses values outside it (keeping its value), and unknown names are
+    refused by both calls; the defaults are restored afterwards."""
+    defaults = {k: frg.frg_tune_get(ctx, k) for k in KNOBS}
+    try:
+        for k, (good, bad) in KNOBS.items():
+            for v in good:
+                frg.frg_tune_set(ctx, k, v)
+                assert frg.frg_tune_get(ctx, k) == v, k
+            for v in bad:
+                with pytest.raises(frg.FrgError):
+                    frg.frg_tune_set(ctx, k, v)
+                assert frg.frg_tune_get(ctx, k) == good[-1], k
+    finally:
+        for k, v in defaults.items():
+            frg.frg_tune_set(ctx, k, v)
+    assert {k: frg.frg_tune_get(ctx, k) for k in KNOBS} == defaults
+    for name in ("grid_m", "pflow", "tab_W ", ""):
+        with pytest.raises(frg.FrgError):
+            frg.frg_tune_set(ctx, name, 1)
+        with pytest.raises(frg.FrgError):
+            frg.frg_tune_get(ctx, name)
