@@ -421,7 +421,10 @@ int frg_autotune(frg_ctx *ctx, int32_t mode, const char *cache_path);
  * the same bits), "pflow_fused" (momentum-dependent flows with rows in LDS,
  * 1: one launch per RK4 stage, each workgroup redoing the previous stage's
  * update for its row, the default; 0: a diagram launch and a stage launch
- * per stage; the same bits), "server_zero_copy" (flow server, 1: the LPA kernel reads
+ * per stage; the same bits), "vertex_W" (vertex diagrams whose coefficient
+ * table takes over half the LDS: waves of the one workgroup per CU, 1..12,
+ * default 12; above 8 only for the matrix-core form with groups of up to 16
+ * azimuthal terms, else 8), "server_zero_copy" (flow server, 1: the LPA kernel reads
  * and writes the pinned batch buffer in place, the default; 0: one upload and
  * one download per batch; the same bits), "grid_lds_rows" (8..96), "plain_tile", "persist_tile" (1..64),
  * "persist_wpc" (1..64), and of the tabulated variant "tab_W" (1..4),

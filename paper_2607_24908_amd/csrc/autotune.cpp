@@ -205,6 +205,7 @@ static int *knob(frg_ctx *ctx, const char *key) {
   if (!std::strcmp(key, "grid_mfma")) return &t.grid_mfma;
   if (!std::strcmp(key, "fv_persistent")) return &t.fv_persistent;
   if (!std::strcmp(key, "pflow_fused")) return &t.pflow_fused;
+  if (!std::strcmp(key, "vertex_W")) return &t.vertex_W;
   if (!std::strcmp(key, "server_zero_copy")) return &t.server_zero_copy;
   if (!std::strcmp(key, "tab_W")) return &t.tab_W;
   if (!std::strcmp(key, "tab_pw")) return &t.tab_pw;
@@ -232,6 +233,7 @@ static bool knob_ok(const char *key, int v) {
   if (!std::strcmp(key, "grid_mfma") || !std::strcmp(key, "fv_persistent") ||
       !std::strcmp(key, "pflow_fused") || !std::strcmp(key, "server_zero_copy"))
     return v == 0 || v == 1;
+  if (!std::strcmp(key, "vertex_W")) return v >= 1 && v <= 12;
   if (!std::strcmp(key, "tab_W")) return v >= 1 && v <= 4;
   if (!std::strcmp(key, "tab_pw")) return v >= 1 && v <= 64;
   if (!std::strcmp(key, "tab_lds_nodes")) return v >= 2 && v <= (int)tab_lds_max_nodes;

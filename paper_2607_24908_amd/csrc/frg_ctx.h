@@ -81,6 +81,7 @@ struct Tune {
   int grid_lds_rows = 64;  // (t, u) rows of 64 doubles staged per LDS chunk
   int grid_form = 0;       // resident FP64 grid: 0 per-momentum coefficients, 1 running fractions
   int grid_mfma = 1;       // coefficient form: 1 tiles of 16 masses on the matrix cores, 0 vector units
+  int vertex_W = 12;       // vertex diagram, table over half the LDS: waves per workgroup (capped at 8 where registers need it)
   int pflow_fused = 1;     // momentum flow, rows in LDS: 1 one launch per stage; 0 diagram + stage launches
   int fv_persistent = 1;   // finite-volume solves: 1 one workgroup per flow, state in LDS; 0 launches per stage
   int server_zero_copy = 1;  // flow server: 1 kernel reads/writes the pinned batch buffer; 0 two copies

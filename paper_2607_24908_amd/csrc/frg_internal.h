@@ -266,6 +266,9 @@ void set_fold_scale(GridArgs &g, const QuadTable &h, int E = 2);
 // Vertex diagram (vertex_kernel): group size from n_phi, LDS bytes of the
 // resident coefficient table (0 if it does not fit), launch.
 int vertex_group(int n_phi);
+// Largest waves per workgroup of vertex_kernel for tiles of M masses and
+// groups of G terms: 12 for the matrix-core form with G <= 16, 8 else.
+constexpr int vertex_max_waves(int M, int G) { return M == 16 && G <= 16 ? 12 : 8; }
 int vertex_lds_bytes(const GridArgs &g, int M, int W, bool table);
 int launch_vertex(const GridArgs &g, int reg, int M, int W, void *stream);
 std::vector<double> build_vertex_table(int d, int n_a, int n_phi);

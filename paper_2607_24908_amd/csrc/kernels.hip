@@ -437,8 +437,10 @@ __global__ __launch_bounds__(512) void grid_coef_kernel(GridArgs g) {
 // (radial, polar) node pairs, groups are azimuthal nodes; P carries the
 // extra factor (x + H1) of G(|q + p1|) (device_grid.h, vertex section).
 // g.form == 1: no coefficient table (every mass per term).
-template <int REG, int M, int G>
-__global__ __launch_bounds__(512) void vertex_kernel(GridArgs g) {
+// MAXT: 768 (12 waves, three per SIMD) for the matrix-core form with groups
+// of up to 16 terms, whose registers allow three waves per SIMD; 512 else.
+template <int REG, int M, int G, int MAXT>
+__global__ __launch_bounds__(MAXT) void vertex_kernel(GridArgs g) {
   extern __shared__ double lds[];
   const int W = blockDim.x / kWave;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
@@ -688,12 +690,23 @@ int vertex_lds_bytes(const GridArgs &g, int M, int W, bool table) {
          grid_coef_stage_bytes(g.mblocks, W, M);
 }
 
+template <int REG, int M, int G, int MAXT>
+static void vertex_launch_b(const GridArgs &g, int W, hipStream_t st) {
+  static const bool once = (allow_large_lds((const void *)&vertex_kernel<REG, M, G, MAXT>), true);
+  (void)once;
+  hipLaunchKernelGGL((vertex_kernel<REG, M, G, MAXT>), dim3((unsigned)(g.n_p * g.n_mb)),
+                     dim3(kWave * W), vertex_lds_bytes(g, M, W, g.form != 1), st, g);
+}
+
 template <int REG, int M, int G>
 static void vertex_launch_t(const GridArgs &g, int W, hipStream_t st) {
-  static const bool once = (allow_large_lds((const void *)&vertex_kernel<REG, M, G>), true);
-  (void)once;
-  hipLaunchKernelGGL((vertex_kernel<REG, M, G>), dim3((unsigned)(g.n_p * g.n_mb)),
-                     dim3(kWave * W), vertex_lds_bytes(g, M, W, g.form != 1), st, g);
+  if constexpr (vertex_max_waves(M, G) > 8) {
+    if (W > 8) {
+      vertex_launch_b<REG, M, G, 64 * vertex_max_waves(M, G)>(g, W, st);
+      return;
+    }
+  }
+  vertex_launch_b<REG, M, G, 512>(g, W, st);
 }
 
 template <int REG, int M>
@@ -712,6 +725,7 @@ int launch_vertex(const GridArgs &g, int reg, int M, int W, void *stream) {
   if (g.n_p <= 0 || g.n_m <= 0) return 0;
   hipStream_t st = (hipStream_t)stream;
   if (M != 4 && M != 8 && M != 16) return (int)hipErrorInvalidValue;
+  if (W < 1 || W > vertex_max_waves(M, vertex_group(g.n_phi))) return (int)hipErrorInvalidValue;
   if (reg == kExp) {
     if (M == 16) vertex_launch_m<kExp, 16>(g, W, st);
     else if (M == 8) vertex_launch_m<kExp, 8>(g, W, st);

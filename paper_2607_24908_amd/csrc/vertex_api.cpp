@@ -52,14 +52,15 @@ int Ctx::vertex_device(const frg_quad &q, int n_phi, int64_t n_c, const double *
   // launch shape: the grid kernel's (tiles of 16 masses on the matrix cores,
   // or M <= 8 on the vector units); mass blocks so that about four
   // workgroups per CU are in flight -- or one, when the table takes more than
-  // half the LDS (one workgroup per CU can be resident; it gets eight waves,
-  // two per SIMD, and splitting a configuration's masses over more
-  // workgroups would only repeat its table build)
+  // half the LDS (one workgroup per CU can be resident; it gets vertex_W
+  // waves, up to three per SIMD where the registers allow, and splitting a
+  // configuration's masses over more workgroups would only repeat its table
+  // build)
   GridCfg cfg = tune.grid;
   cfg.M = tune.grid_mfma ? 16 : std::min(cfg.M, 8);
   g.mblocks = 1;
   const bool big = vertex_lds_bytes(g, cfg.M, cfg.W, true) > 80 * 1024;
-  if (big) cfg.W = 8;
+  if (big) cfg.W = std::min(tune.vertex_W, vertex_max_waves(cfg.M, vertex_group(n_phi)));
   const int64_t per_wg = (int64_t)cfg.M * cfg.W;
   const int64_t want_wgs = (big ? 1LL : 4LL) * n_cu;
   int mbk = std::max(1, cfg.MB);
