@@ -131,12 +131,14 @@ void Server::shutdown() {
   }
   cv_disp.notify_all();
   if (disp.joinable()) disp.join();
+  // `flows` owns every flow that has not been polled, admitted or still
+  // queued; `queue` only lists the queued ones, so it is cleared without
+  // deleting anything
   for (auto &kv : flows) {
     if (kv.second->th.joinable()) kv.second->th.join();
     delete kv.second;
   }
   flows.clear();
-  for (Flow *f : queue) delete f;
   queue.clear();
   if (d_stage) hipFree(d_stage);
   if (h_stage) hipHostFree(h_stage);
