@@ -125,8 +125,8 @@ typedef struct {
  * (optionally | FRG_GRAPH).  Results are bitwise identical for every flag
  * and every tile choice: the summation order of each result depends only on
  * (n_radial, n_angular).  Returns FRG_E_DOMAIN if any point had
- * m^2 + k^2 <= 0 (device calls report it only after the stream completes, so
- * device calls return FRG_OK and leave NaN in out). */
+ * m^2 + k^2 <= 0 (host memory; device calls are asynchronous: they return
+ * FRG_OK, leave NaN in out and record the violation for frg_stream_status). */
 int frg_integrate(frg_ctx *ctx, const frg_set *sets, int32_t n_sets, int32_t mem, int32_t flags,
                   void *hip_stream);
 
@@ -426,8 +426,10 @@ int frg_autotune(frg_ctx *ctx, int32_t mode, const char *cache_path);
  * default 12; above 8 only for the matrix-core form with groups of up to 16
  * azimuthal terms, else 8), "server_zero_copy" (flow server, 1: the LPA kernel reads
  * and writes the pinned batch buffer in place, the default; 0: one upload and
- * one download per batch; the same bits), "grid_lds_rows" (8..96), "plain_tile", "persist_tile" (1..64),
- * "persist_wpc" (1..64), and of the tabulated variant "tab_W" (1..4),
+ * one download per batch; the same bits), "grid_lds_rows" (8..96), "plain_tile" (points per
+ * tile of a plain launch, 1..64), "persist_tile" (work of a tile of the persistent list, in
+ * units of 1024 evaluations: 1..64 points of one set), "persist_wpc" (1..64), and of the
+ * tabulated variant "tab_W" (1..4),
  * "tab_pw" (momenta per wave, 1..64), "tab_lds_nodes" (2..6144),
  * "tab_pairs" (1: rows in LDS as (value, slope) pairs, the default; 0: as
  * values; the same bits), and for streamed rows "tab_wpc" (workgroups per
@@ -440,10 +442,32 @@ int frg_autotune(frg_ctx *ctx, int32_t mode, const char *cache_path);
 int frg_tune_set(frg_ctx *ctx, const char *key, int32_t value);
 int frg_tune_get(frg_ctx *ctx, const char *key, int32_t *value);
 
+/* ---- domain status of device calls ----------------------------------------- */
+/* Device-memory calls are asynchronous and return before their kernels run,
+ * so a point outside the domain (m^2 + k^2 <= 0, p < 0, cos12 outside
+ * [-1, 1]) cannot change their return value; the kernels record it in a word
+ * kept per (context, stream).  frg_stream_status waits for hip_stream (as
+ * hipStreamSynchronize) and returns FRG_E_DOMAIN if a device call of
+ * frg_integrate, frg_integrate_grid, frg_integrate_tab, frg_integrate_vertex,
+ * frg_flow_rhs or frg_flow_rhs_batch on that stream met such a point since
+ * the previous frg_stream_status for the stream (the affected results are
+ * NaN), else FRG_OK; the record is then cleared.  The flow solvers
+ * (frg_pflow_solve, frg_fvlpa_solve) report per flow through t_reached. */
+int frg_stream_status(frg_ctx *ctx, void *hip_stream);
+
 /* ---- host-only helpers ------------------------------------------------------ */
 /* Gauss-Legendre nodes (ascending) and weights on [-1, 1], n = 1..4096, by
  * the Golub-Welsch eigenvalue method (no GPU use). */
 int frg_gauss_legendre(int32_t n, double *x, double *w);
+
+/* e^{-y} for n arguments (0 <= y, not NaN), evaluated on the host by the
+ * same operations, in the same order and rounding, as the point kernels use
+ * for the exponential regulator: the table-driven method of Tang (ACM Trans.
+ * Math. Softw. 15, 1989) with 64 entries 2^{j/64}, a Cody-Waite reduction and
+ * a degree-5 polynomial; below 1.6 ulp where the result is normal, 0 above
+ * y = 745.2.  y and out: n float64 each (host memory; no GPU use).
+ * FRG_E_INVAL for n < 0 or NULL arrays with n > 0. */
+int frg_expneg(int64_t n, const double *y, double *out);
 
 /* Bytes of device memory one flow of this shape takes in the server's staging
  * buffer during a batched call (what the server's HBM admission charges). */

@@ -168,6 +168,7 @@ PersistCfg Context::persist_cfg(const std::vector<SetDev> &sd, int prec, hipStre
       }
     }
   tune.persist_best[key] = best;
+  ++tune_gen;
   tune.save_file(arch);
   return best;
 }
@@ -183,6 +184,7 @@ int frg_autotune(frg_ctx *ctx, int32_t mode, const char *cache_path) {
   if (mode != 0 && mode != 1) return fail(FRG_E_INVAL, "mode must be 0 or 1");
   std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->tune.mode = mode;
+  ++ctx->tune_gen;
   if (cache_path) {
     ctx->tune.cache_path = cache_path;
     int rc = ctx->tune.load_file(ctx->arch);
@@ -255,6 +257,7 @@ int frg_tune_set(frg_ctx *ctx, const char *key, int32_t value) {
   if (!k) return fail(FRG_E_INVAL, "unknown knob '%s'", key);
   if (!knob_ok(key, value)) return fail(FRG_E_INVAL, "value %d out of range for '%s'", value, key);
   *k = value;
+  ++ctx->tune_gen;
   // explicit settings take effect for keys that were already tuned, too
   ctx->tune.grid_best.clear();
   ctx->tune.plain_best.clear();

@@ -16,6 +16,7 @@
 #include <tuple>
 #include <vector>
 
+#include "device_exp.h"
 #include "frg_ctx.h"
 
 namespace frg {
@@ -139,7 +140,8 @@ static uint64_t dbits(double x) {
   return u;
 }
 
-int Ctx::quad_table(const frg_quad &q, const double **dev, QuadTable *host_copy) {
+int Ctx::quad_table(const frg_quad &q, const double **dev, QuadTable *host_copy,
+                    QuadTable **host_ref) {
   auto key = std::make_tuple(q.d, q.reg, dbits(q.k), dbits(q.q_max), q.n_radial, q.n_angular);
   auto it = qtabs.find(key);
   if (it == qtabs.end()) {
@@ -157,6 +159,7 @@ int Ctx::quad_table(const frg_quad &q, const double **dev, QuadTable *host_copy)
   }
   *dev = (const double *)it->second.buf->ptr;
   if (host_copy) *host_copy = it->second.host;
+  if (host_ref) *host_ref = &it->second.host;
   return FRG_OK;
 }
 
@@ -238,18 +241,12 @@ int check_lpa(const frg_lpa &l) {
 }
 
 // ----------------------------------------------------------- integrate --
-static double set_cost(const frg_quad &q, int64_t pts) {
-  const double per = (q.reg == FRG_REG_EXP) ? 5.0 : 1.0;
-  return (double)pts * q.n_radial * q.n_angular * per;
-}
-
 int Ctx::make_setdev(const frg_set &s, SetDev *out) {
   const double *tab;
-  int rc = quad_table(s.quad, &tab, nullptr);
+  QuadTable *hp = nullptr;
+  int rc = quad_table(s.quad, &tab, nullptr, &hp);
   if (rc) return rc;
-  QuadTable &h = qtabs[std::make_tuple(s.quad.d, s.quad.reg, dbits(s.quad.k), dbits(s.quad.q_max),
-                                       s.quad.n_radial, s.quad.n_angular)]
-                     .host;
+  const QuadTable &h = *hp;
   SetDev d{};
   d.p = s.p;
   d.m2 = s.m2;
@@ -260,6 +257,7 @@ int Ctx::make_setdev(const frg_set &s, SetDev *out) {
   d.k2 = h.k2;
   d.inv_k2 = h.inv_k2;
   d.pref = h.pref;
+  d.pref_k = h.pref * h.inv_k2;
   d.q_top = h.q_top;
   d.rmu_max = h.rmu_max;
   d.n_ext = s.n_ext;
@@ -274,8 +272,27 @@ int Ctx::make_setdev(const frg_set &s, SetDev *out) {
   return FRG_OK;
 }
 
+int Ctx::replay_graph(const frg_set *sets, int n_sets, hipStream_t st) {
+  for (auto &g : graphs) {
+    if (g->stream != st || g->flag != d_flag || g->gen != tune_gen ||
+        g->raw.size() != (size_t)n_sets ||
+        (n_sets && std::memcmp(g->raw.data(), sets, n_sets * sizeof(frg_set)) != 0))
+      continue;
+    hipError_t e = hipGraphLaunch(g->exec, st);
+    if (e == hipSuccess) e = hipEventRecord(g->done, st);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    g->last_use = ++graph_clock;
+    return 1;
+  }
+  return 0;
+}
+
 // Device-side core: every pointer in `sets` is device memory.
 int Ctx::integrate_device(const frg_set *sets, int n_sets, int flags, hipStream_t st) {
+  if ((flags & FRG_PERSISTENT) && (flags & FRG_GRAPH)) {
+    const int r = replay_graph(sets, n_sets, st);
+    if (r) return r < 0 ? r : FRG_OK;
+  }
   std::vector<SetDev> sd(n_sets);
   for (int i = 0; i < n_sets; ++i) {
     int rc = make_setdev(sets[i], &sd[i]);
@@ -294,27 +311,35 @@ int Ctx::integrate_device(const frg_set *sets, int n_sets, int flags, hipStream_
   return persistent(sd, sets, n_sets, flags, st);
 }
 
-// Work list: tiles of up to `tile` points, sorted longest-first.
-// Tiles of up to `tile` points, longest first (weight = per-point cost x
-// points; ties in set order, then point order).  All full tiles of a set
-// weigh the same, so a stable sort of runs -- the full tiles of a set, then
-// its last partial tile -- gives the order of a stable sort of the tiles
-// without sorting them one by one.
-void build_tiles(const std::vector<SetDev> &sd, int tile, std::vector<Tile> *tiles) {
+// Points per tile of a set: about tile_k * 1024 evaluations per tile (1..64
+// points), so that tiles of every set cost about the same.
+static int tile_points(const SetDev &s, int tile_k) {
+  const double per = (double)s.n_r * s.n_a;
+  const int tp = (int)std::floor((double)tile_k * 1024.0 / per);
+  return std::max(1, std::min(64, tp));
+}
+
+// Work list, longest tile first (weight = per-point cost x points; ties in
+// set order, then point order).  All full tiles of a set weigh the same, so
+// a stable sort of runs -- the full tiles of a set, then its last partial
+// tile -- gives the order of a stable sort of the tiles without sorting them
+// one by one.
+void build_tiles(const std::vector<SetDev> &sd, int tile_k, std::vector<Tile> *tiles) {
   struct Run {
     double w;
-    int set;
-    int64_t start, count;  // tiles [start, start + count * tile) of `set`
+    int set, tp;
+    int64_t start, count;  // tiles [start, start + count * tp) of `set`
   };
   std::vector<Run> runs;
   runs.reserve(2 * sd.size());
   int64_t n_tiles = 0;
   for (int i = 0; i < (int)sd.size(); ++i) {
-    const double w = sd[i].reg == FRG_REG_EXP ? (sd[i].prec == FRG_PREC_FP32C ? 2.0 : 5.0) : 1.0;
+    const double w = sd[i].reg == FRG_REG_EXP ? (sd[i].prec == FRG_PREC_FP32C ? 2.0 : 3.0) : 1.0;
     const double per = w * sd[i].n_r * sd[i].n_a;
-    const int64_t full = sd[i].n_ext / tile, rem = sd[i].n_ext - full * tile;
-    if (full) runs.push_back({per * tile, i, 0, full});
-    if (rem) runs.push_back({per * rem, i, full * tile, 1});
+    const int tp = tile_points(sd[i], tile_k);
+    const int64_t full = sd[i].n_ext / tp, rem = sd[i].n_ext - full * tp;
+    if (full) runs.push_back({per * tp, i, tp, 0, full});
+    if (rem) runs.push_back({per * rem, i, tp, full * tp, 1});
     n_tiles += full + (rem ? 1 : 0);
   }
   std::stable_sort(runs.begin(), runs.end(), [](const Run &a, const Run &b) { return a.w > b.w; });
@@ -324,8 +349,8 @@ void build_tiles(const std::vector<SetDev> &sd, int tile, std::vector<Tile> *til
     for (int64_t c = 0; c < r.count; ++c) {
       Tile &t = (*tiles)[k++];
       t.set = r.set;
-      t.start = r.start + c * tile;
-      t.count = (int)std::min<int64_t>(tile, sd[r.set].n_ext - t.start);
+      t.start = r.start + c * r.tp;
+      t.count = (int)std::min<int64_t>(r.tp, sd[r.set].n_ext - t.start);
     }
   }
 }
@@ -336,114 +361,128 @@ bool any_fp32c(const std::vector<SetDev> &sd) {
   return false;
 }
 
-// LDS bytes the persistent kernel needs for the largest table of the batch
-// (FP32C sets add their FP32 angular tables).
+// LDS bytes the persistent kernel needs for the largest tables of the batch
+// (angular pairs and packed table; FP32C sets add their FP32 angular tables;
+// the launch adds the exponential table).
 int max_table_bytes(const std::vector<SetDev> &sd) {
   size_t m = 0;
   for (auto &s : sd) {
-    size_t b = sizeof(double) * table_doubles(s.n_r, s.n_a);
+    size_t b = sizeof(double) * (2 * s.n_a + table_doubles(s.n_r, s.n_a));
     if (s.prec == FRG_PREC_FP32C) b += sizeof(float) * 3 * s.n_a;
     m = std::max(m, b);
   }
   return (int)m;
 }
 
-uint64_t batch_signature(const frg_set *sets, int n_sets) {
-  uint64_t h = 1469598103934665603ull;
-  auto mix = [&](uint64_t v) {
-    h ^= v;
-    h *= 1099511628211ull;
-  };
-  mix((uint64_t)n_sets);
-  for (int i = 0; i < n_sets; ++i) {
-    const frg_set &s = sets[i];
-    mix((uint64_t)(uintptr_t)s.p);
-    mix((uint64_t)(uintptr_t)s.m2);
-    mix((uint64_t)(uintptr_t)s.out);
-    mix((uint64_t)(uintptr_t)s.err_est);
-    mix((uint64_t)(uintptr_t)s.used_fp64);
-    mix((uint64_t)s.n_ext);
-    mix((uint64_t)s.quad.d | ((uint64_t)s.quad.reg << 8) | ((uint64_t)s.quad.prec << 16));
-    mix(dbits(s.quad.k));
-    mix(dbits(s.quad.q_max));
-    mix((uint64_t)s.quad.n_radial << 32 | (uint64_t)s.quad.n_angular);
+static bool same_sets(const std::vector<SetDev> &a, const std::vector<SetDev> &b) {
+  return a.size() == b.size() &&
+         (a.empty() || std::memcmp(a.data(), b.data(), a.size() * sizeof(SetDev)) == 0);
+}
+
+GraphEntry::~GraphEntry() {
+  if (done) {
+    hipEventSynchronize(done);
+    hipEventDestroy(done);
   }
-  return h;
+  if (exec) hipGraphExecDestroy(exec);
 }
 
 int Ctx::persistent(const std::vector<SetDev> &sd, const frg_set *sets, int n_sets, int flags,
                     hipStream_t st) {
   const bool graph = (flags & FRG_GRAPH) != 0;
-  const uint64_t sig = graph ? batch_signature(sets, n_sets) : 0;
-  if (graph) {
-    auto it = graphs.find(sig);
-    if (it != graphs.end()) {
-      hipError_t e = hipGraphLaunch(it->second->exec, st);
-      if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
-      return FRG_OK;
-    }
-  }
   const PersistCfg pc = persist_cfg(sd, sd.empty() ? 0 : sd[0].prec, st);
+  if (!graph) return persistent_eager(sd, pc, st);
+  for (auto &g : graphs) {
+    if (g->stream != st || g->flag != d_flag || g->pc.tile != pc.tile || g->pc.wpc != pc.wpc ||
+        !same_sets(g->sd, sd))
+      continue;
+    hipError_t e = hipGraphLaunch(g->exec, st);
+    if (e == hipSuccess) e = hipEventRecord(g->done, st);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    g->last_use = ++graph_clock;
+    g->raw.assign(sets, sets + n_sets);
+    g->gen = tune_gen;
+    return FRG_OK;
+  }
   std::vector<Tile> tiles;
   build_tiles(sd, pc.tile, &tiles);
   if (tiles.empty()) return FRG_OK;
   const int lds = max_table_bytes(sd);
-  if (lds > 64 * 1024) return fail(FRG_E_INVAL, "quadrature tables exceed 64 KiB of LDS");
+  if (lds > 60 * 1024) return fail(FRG_E_INVAL, "quadrature tables exceed 60 KiB of LDS");
   const int n_blocks = std::max(1, std::min<int>((int)tiles.size(), n_cu * pc.wpc));
-  if (graph) {
-    auto g = std::make_unique<GraphEntry>();
-    int rc = g->sets.reserve(sd.size() * sizeof(SetDev));
-    if (!rc) rc = g->tiles.reserve(tiles.size() * sizeof(Tile));
-    if (!rc) rc = g->counter.reserve(sizeof(int));
-    if (rc) return rc;
-    hipError_t e = hipMemcpy(g->sets.ptr, sd.data(), sd.size() * sizeof(SetDev), hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-      e = hipMemcpy(g->tiles.ptr, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "upload graph work list");
-    e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    int e1 = launch_reset_counter((int *)g->counter.ptr, cap_stream);
-    int e2 = launch_points_persistent((const SetDev *)g->sets.ptr, (const Tile *)g->tiles.ptr,
-                                      (int)tiles.size(), (int *)g->counter.ptr, lds, n_blocks,
-                                      any_fp32c(sd), d_flag, cap_stream);
-    hipGraph_t graph_h = nullptr;
-    e = hipStreamEndCapture(cap_stream, &graph_h);
-    if (e1 || e2 || e != hipSuccess) {
-      if (graph_h) hipGraphDestroy(graph_h);
-      return fail(FRG_E_DEVICE, "graph capture of the persistent launch failed");
-    }
-    e = hipGraphInstantiate(&g->exec, graph_h, nullptr, nullptr, 0);
-    hipGraphDestroy(graph_h);
-    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
-    e = hipGraphLaunch(g->exec, st);
-    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
-    graphs.emplace(sig, std::move(g));
-    return FRG_OK;
+  if (graphs.size() >= kMaxGraphs) {  // drop the least recently used capture
+    auto lru = std::min_element(graphs.begin(), graphs.end(), [](const auto &x, const auto &y) {
+      return x->last_use < y->last_use;
+    });
+    graphs.erase(lru);
   }
-  return persistent_eager(sd, pc, st);
+  auto g = std::make_unique<GraphEntry>();
+  int rc = g->sets.reserve(sd.size() * sizeof(SetDev));
+  if (!rc) rc = g->tiles.reserve(tiles.size() * sizeof(Tile));
+  if (!rc) rc = g->counter.reserve(kCounterInts * sizeof(int));
+  if (rc) return rc;
+  hipError_t e = hipEventCreateWithFlags(&g->done, hipEventDisableTiming);
+  if (e != hipSuccess) return hip_fail(e, "hipEventCreate(graph)");
+  e = hipMemcpy(g->sets.ptr, sd.data(), sd.size() * sizeof(SetDev), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(g->tiles.ptr, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "upload graph work list");
+  e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  // the counters are cleared by a kernel inside the graph (no memset node)
+  int e1 = launch_reset_counter((int *)g->counter.ptr, cap_stream);
+  int e2 = launch_points_persistent((const SetDev *)g->sets.ptr, (const Tile *)g->tiles.ptr,
+                                    (int)tiles.size(), (int *)g->counter.ptr, lds, n_blocks,
+                                    any_fp32c(sd), d_flag, cap_stream);
+  hipGraph_t graph_h = nullptr;
+  e = hipStreamEndCapture(cap_stream, &graph_h);
+  if (e1 || e2 || e != hipSuccess) {
+    if (graph_h) hipGraphDestroy(graph_h);
+    return fail(FRG_E_DEVICE, "graph capture of the persistent launch failed");
+  }
+  e = hipGraphInstantiate(&g->exec, graph_h, nullptr, nullptr, 0);
+  hipGraphDestroy(graph_h);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  e = hipGraphLaunch(g->exec, st);
+  if (e == hipSuccess) e = hipEventRecord(g->done, st);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  g->stream = st;
+  g->flag = d_flag;
+  g->sd = sd;
+  g->pc = pc;
+  g->last_use = ++graph_clock;
+  g->raw.assign(sets, sets + n_sets);
+  g->gen = tune_gen;
+  graphs.push_back(std::move(g));
+  return FRG_OK;
 }
 
-// Eager persistent launch: work list and descriptors go through the ring.
+// Eager persistent launch: work list, descriptors and zeroed work-list
+// counters go through the ring, so every launch has its own counters (a ring
+// slot is reused only after the launch that read it has completed).
 int Ctx::persistent_eager(const std::vector<SetDev> &sd, const PersistCfg &pc, hipStream_t st) {
   std::vector<Tile> tiles;
   build_tiles(sd, pc.tile, &tiles);
   if (tiles.empty()) return FRG_OK;
   const int lds = max_table_bytes(sd);
+  if (lds > 60 * 1024) return fail(FRG_E_INVAL, "quadrature tables exceed 60 KiB of LDS");
   const int n_blocks = std::max(1, std::min<int>((int)tiles.size(), n_cu * pc.wpc));
-  std::vector<char> blob(sd.size() * sizeof(SetDev) + tiles.size() * sizeof(Tile));
-  std::memcpy(blob.data(), sd.data(), sd.size() * sizeof(SetDev));
-  std::memcpy(blob.data() + sd.size() * sizeof(SetDev), tiles.data(), tiles.size() * sizeof(Tile));
+  const size_t o_tiles = sd.size() * sizeof(SetDev);
+  const size_t o_counter = (o_tiles + tiles.size() * sizeof(Tile) + 255) & ~(size_t)255;
+  std::vector<char> blob(o_counter + kCounterInts * sizeof(int), 0);
+  std::memcpy(blob.data(), sd.data(), o_tiles);
+  std::memcpy(blob.data() + o_tiles, tiles.data(), tiles.size() * sizeof(Tile));
   void *dev;
   int slot;
   int rc = ring.upload(blob.data(), blob.size(), st, &dev, &slot);
   if (rc) return rc;
   const SetDev *d_sets = (const SetDev *)dev;
-  const Tile *d_tiles = (const Tile *)((char *)dev + sd.size() * sizeof(SetDev));
-  int e1 = launch_reset_counter(d_counter, st);
+  const Tile *d_tiles = (const Tile *)((char *)dev + o_tiles);
+  int *d_counter = (int *)((char *)dev + o_counter);
   int e2 = launch_points_persistent(d_sets, d_tiles, (int)tiles.size(), d_counter, lds, n_blocks,
                                     any_fp32c(sd), d_flag, st);
   rc = ring.release(slot, st);
-  if (e1 || e2) return fail(FRG_E_DEVICE, "persistent launch failed");
+  if (e2) return fail(FRG_E_DEVICE, "persistent launch failed");
   return rc;
 }
 
@@ -782,15 +821,28 @@ int Ctx::lpa_jobs(int n, const frg_lpa *lpa, const double *t, const double *cons
   return rc;
 }
 
+int Ctx::use_stream_flag(hipStream_t st) {
+  auto it = stream_flags.find(st);
+  if (it == stream_flags.end()) {
+    int *f = nullptr;
+    if (hipMalloc(&f, sizeof(int)) != hipSuccess) return fail(FRG_E_NOMEM, "hipMalloc(domain word)");
+    if (hipMemset(f, 0, sizeof(int)) != hipSuccess) {
+      hipFree(f);
+      return fail(FRG_E_DEVICE, "hipMemset(domain word)");
+    }
+    it = stream_flags.emplace(st, f).first;
+  }
+  d_flag = it->second;
+  return FRG_OK;
+}
+
 Context::~Context() {
   if (server) stop_server();
   if (stream) hipStreamSynchronize(stream);
-  for (auto &g : graphs)
-    if (g.second->exec) hipGraphExecDestroy(g.second->exec);
   graphs.clear();
   ring.destroy();
-  if (d_flag) hipFree(d_flag);
-  if (d_counter) hipFree(d_counter);
+  for (auto &kv : stream_flags) hipFree(kv.second);
+  stream_flags.clear();
   if (stream) hipStreamDestroy(stream);
   if (cap_stream) hipStreamDestroy(cap_stream);
 }
@@ -825,12 +877,9 @@ int frg_create(frg_ctx **out, int hip_device, uint64_t hbm_budget_bytes) {
   if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)
     return fail(FRG_E_DEVICE, "hipStreamCreate");
-  if (hipMalloc(&c->d_flag, sizeof(int)) != hipSuccess ||
-      hipMalloc(&c->d_counter, sizeof(int)) != hipSuccess)
-    return fail(FRG_E_NOMEM, "hipMalloc flags");
-  hipMemset(c->d_flag, 0, sizeof(int));
-  hipMemset(c->d_counter, 0, sizeof(int));
-  int rc = c->ring.init(1 << 20, 8);
+  int rc = c->use_stream_flag(c->stream);
+  if (rc) return rc;
+  rc = c->ring.init(1 << 20, 8);
   if (rc) return rc;
   size_t free_b = 0, total_b = 0;
   hipMemGetInfo(&free_b, &total_b);
@@ -866,6 +915,8 @@ int frg_integrate(frg_ctx *ctx, const frg_set *sets, int32_t n_sets, int32_t mem
   std::lock_guard<std::mutex> lk(ctx->mu);
   hipSetDevice(ctx->device);
   clear_error();
+  if (int rcf = ctx->use_stream_flag(mem == FRG_MEM_HOST ? ctx->stream : (hipStream_t)hip_stream))
+    return rcf;
   if (mem == FRG_MEM_HOST) return ctx->integrate_host(sets, n_sets, flags);
   return ctx->integrate_device(sets, n_sets, flags, (hipStream_t)hip_stream);
 }
@@ -884,6 +935,8 @@ int frg_integrate_grid(frg_ctx *ctx, const frg_quad *quad, int64_t n_p, const do
   std::lock_guard<std::mutex> lk(ctx->mu);
   hipSetDevice(ctx->device);
   clear_error();
+  if (int rcf = ctx->use_stream_flag(mem == FRG_MEM_HOST ? ctx->stream : (hipStream_t)hip_stream))
+    return rcf;
   if (mem == FRG_MEM_DEVICE)
     return ctx->grid_device(*quad, n_p, p, n_m, m2, out, err_est, used_fp64, (hipStream_t)hip_stream);
   for (int64_t a = 0; a < n_p; ++a)
@@ -932,6 +985,8 @@ int frg_integrate_tab(frg_ctx *ctx, const frg_quad *quad, const frg_gtab *tab, i
   std::lock_guard<std::mutex> lk(ctx->mu);
   hipSetDevice(ctx->device);
   clear_error();
+  if (int rcf = ctx->use_stream_flag(mem == FRG_MEM_HOST ? ctx->stream : (hipStream_t)hip_stream))
+    return rcf;
   if (mem == FRG_MEM_DEVICE) return ctx->tab_device(*quad, *tab, n_p, p, out, (hipStream_t)hip_stream);
   const size_t gbytes = (size_t)(tab->n_rows * tab->n_s) * sizeof(double);
   const size_t nout = (size_t)(n_p * tab->n_rows);
@@ -970,6 +1025,8 @@ int frg_flow_rhs(frg_ctx *ctx, const frg_lpa *lpa, double t, const double *U, do
   std::lock_guard<std::mutex> lk(ctx->mu);
   hipSetDevice(ctx->device);
   clear_error();
+  if (int rcf = ctx->use_stream_flag(mem == FRG_MEM_HOST ? ctx->stream : (hipStream_t)hip_stream))
+    return rcf;
   if (mem == FRG_MEM_DEVICE) {
     const double *Up[1] = {U};
     double *Dp[1] = {dUdt};
@@ -1018,12 +1075,37 @@ int frg_flow_rhs_batch(frg_ctx *ctx, int32_t n_flows, const frg_lpa *lpa, const 
   std::lock_guard<std::mutex> lk(ctx->mu);
   hipSetDevice(ctx->device);
   clear_error();
+  if (int rcf = ctx->use_stream_flag((hipStream_t)hip_stream)) return rcf;
   return ctx->lpa_jobs(n_flows, lpa, t, U, dUdt, jac_bands, nullptr, (hipStream_t)hip_stream);
+}
+
+int frg_stream_status(frg_ctx *ctx, void *hip_stream) {
+  if (!ctx) return fail(FRG_E_INVAL, "ctx is NULL");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  hipSetDevice(ctx->device);
+  clear_error();
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (int rc = ctx->use_stream_flag(st)) return rc;
+  int flag = 0;
+  hipError_t e = hipMemcpyAsync(&flag, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemsetAsync(ctx->d_flag, 0, sizeof(int), st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "frg_stream_status");
+  if (flag)
+    return fail(FRG_E_DOMAIN, "a call on this stream met points with m^2 + k^2 <= 0 or p < 0; "
+                              "their results are NaN");
+  return FRG_OK;
 }
 
 int frg_gauss_legendre(int32_t n, double *x, double *w) {
   int rc = gauss_legendre_gw(n, x, w);
   if (rc) return fail(rc, "n must be in [1, 4096] and x, w non-NULL");
+  return FRG_OK;
+}
+
+int frg_expneg(int64_t n, const double *y, double *out) {
+  if (n < 0 || (n > 0 && (!y || !out))) return fail(FRG_E_INVAL, "bad arguments");
+  for (int64_t i = 0; i < n; ++i) out[i] = exp_neg(y[i], kExp2Tab64);
   return FRG_OK;
 }
 

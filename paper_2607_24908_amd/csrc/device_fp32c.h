@@ -140,9 +140,9 @@ __device__ __forceinline__ double lane_point_f32(const double *__restrict__ tab,
 }
 
 template <int REG>
-__device__ void fp32c_tile(const SetDev &s, const double *tab, const float *fo, const float *fm,
-                           const float *fl, int64_t start, int count, int64_t grid_nm, int lane,
-                           int *flag) {
+__device__ void fp32c_tile(const SetDev &s, const double *tab, const double2 *ang,
+                           const double *etab, const float *fo, const float *fm, const float *fl,
+                           int64_t start, int count, int64_t grid_nm, int lane, int *flag) {
   double res = 0.0, rerr = 0.0;
   int rused = 0;
   for (int e = 0; e < count; ++e) {
@@ -163,7 +163,9 @@ __device__ void fp32c_tile(const SetDev &s, const double *tab, const float *fo, 
         use64 = !(er <= s.f32_flag);
       }
       if (use64) {
-        v = s.pref * wave_sum(lane_point<REG>(tab, s, lane, p, delta));
+        // the FP64 point-kernel path: the same bits as an FP64 set
+        const double part = point_partial<REG>(s, tab, ang, etab, lane, p, delta);
+        v = s.pref_k * wave_sum_fold<1>(&part, lane);
         er = kErr64;
         used = 1;
       }

@@ -11,13 +11,16 @@
 // R radial x J angular lanes (R = largest power of two <= min(n_r, 64),
 // J = 64/R).  Lane (rho, iota) owns radial nodes i = rho + R t and angular
 // nodes j = iota + J u (t < T, u < U, padded nodes contribute an exact 0).
-// It accumulates  sum_t A_t (sum_u mu_u / D_tu)  in t and u order, and the
-// 64 lane partials are combined by a fixed xor butterfly.  The order thus
-// depends only on (n_r, n_a): every kernel and tile choice below gives
-// bitwise-identical results for the same point.
+// It accumulates  sum_t A_t (sum_u mu_u / D_tu)  in t and u order; the 64
+// lane partials are then combined in a fixed order (the grid kernels'
+// running-fraction form: the xor butterfly of wave_sum_split; the point
+// kernels: wave_sum_fold).  The order thus depends only on (n_r, n_a): every
+// launch form and tile choice of one kernel family gives bitwise-identical
+// results for the same point.
 //
-// Reciprocal sums.  With mu folded into the denominators, mu_j / D_ij =
-// 1 / D'_ij,  D'_ij = fma(delta, rmu_j, H'_ij),  H'_ij = fl(Hk(s_ij) rmu_j),
+// Reciprocal sums (grid kernels' running-fraction form, Litim point terms).
+// With mu folded into the denominators, mu_j / D_ij = 1 / D'_ij,
+// D'_ij = fma(delta, rmu_j, H'_ij),  H'_ij = fl(Hk(s_ij) rmu_j),
 // rmu_j = 1/mu_j.  A lane takes its angular terms eight at a time by a running
 // fraction N/P of positive numbers:
 //   N <- 1, P <- D'_0;  then  N <- N D'_k + P,  P <- P D'_k  (k = 1..7),
@@ -37,6 +40,7 @@
 
 #include <cmath>
 
+#include "device_exp.h"
 #include "frg_internal.h"
 
 #pragma clang fp contract(off)
@@ -54,6 +58,7 @@ __device__ __forceinline__ double rcp64(double x) {
 }
 
 constexpr int kGroup = 8;
+constexpr int kHalf = 4;  // terms computed together in the exponential groups
 
 // Running fraction of one group: returns acc + sum_k 1/Dp[k].
 __device__ __forceinline__ double chain_sum(const double *Dp, double acc) {
@@ -264,19 +269,113 @@ __device__ __forceinline__ double hk(double s, double k2, double inv_k2) {
   }
 }
 
-// Lane partial of one point; `tab` is the packed table (LDS).
+// ---------------------------------------------------- point kernels --
+// Lane partial of one external point for the point-list kernels (plain,
+// persistent, and the FP64 path of the compensated-FP32 kernel).  The sum is
+// formed in units of k^2: with y = s/k^2 and dhat = delta/k^2,
+//   mu_j / D_ij = (1/k^2) mu_j / (hh(y_ij) + dhat),   y_ij = ah_i + bh_i (1 + x_j),
+//   ah_i = (q_i - p)^2 / k^2,  bh_i = 2 q_i p / k^2,
+// hh(y) = h(y) (exponential) or max(y - 1, 0) (Litim); the factor 1/k^2 is in
+// SetDev::pref_k.
+//
+// Exponential regulator.  Below y = kY0 the Bernoulli series of h.  Above,
+// with E = e^{-y} (exp_neg, table-driven),
+//   h(y) + dhat = num / (1 - E),   num = (y + dhat - 1) + E (1 - dhat),
+// so that each term is a fraction a/b with a = mu_j (1 - E) and b = num: the
+// division inside h joins the running fraction of the group, and no expm1 or
+// reciprocal is spent per term.  num cancels at most by a factor
+// (|y + dhat - 1| + E |1 - dhat|) / num <= 53 (at y = kY0, dhat -> 0), so a
+// term keeps a relative error below ~60 u.
+// The terms of a lane are taken eight at a time as a running fraction
+//   N/P = sum_k a_k / b_k:  N <- a_0, P <- b_0;  N <- N b_k + a_k P,  P <- P b_k,
+// (three operations per term, one reciprocal per eight), all of them
+// positive.  The range test exp_chain_ok keeps every N and P normal
+// (b >= min(dhat, 0.028), a >= mu_min (1 - e^{-kY0}), b <= y_top + dhat).
+// Litim: b_k = (max(y - 1, 0) + dhat) / mu_j as before (two operations per
+// term, mu in the denominator).
+//
+// Lane map and order: as at the top of this file (R radial x J angular lanes,
+// (t, u) order within a lane); the cross-lane sum is wave_sum_fold, whose
+// pairing is the same for tiles of 1, 2, 4 or 8 points, so every point
+// kernel returns the same bits for the same point.
+constexpr double kY0 = 0.25;
+
+// h(y) for 0 <= y < kY0: y/2 + y^2/12 - y^4/720 + y^6/30240 - y^8/1209600
+// + y^10/47900160, truncation < 3e-19 relative at y = kY0.
+__device__ __forceinline__ double h_series(double y) {
+  const double y2 = y * y;
+  double t = __builtin_fma(y2, 1.0 / 47900160.0, -1.0 / 1209600.0);
+  t = __builtin_fma(y2, t, 1.0 / 30240.0);
+  t = __builtin_fma(y2, t, -1.0 / 720.0);
+  t = __builtin_fma(y2, t, 1.0 / 12.0);
+  return __builtin_fma(y2, t, 0.5 * y);
+}
+
+// The E-form of exp_frac alone (a valid fraction for y >= kY0; finite for
+// any y >= 0, so that it can be computed for a whole group and replaced).
+__device__ __forceinline__ void exp_frac_e(double y, double mu, double cm, double cp,
+                                           const double *etab, double &a, double &b) {
+  const double E = exp_neg(y, etab);
+  b = __builtin_fma(E, cp, y + cm);
+  a = __builtin_fma(-mu, E, mu);
+}
+
+// a/b = mu / (h(y) + dhat) (exponential regulator); cm = dhat - 1, cp = 1 - dhat.
+__device__ __forceinline__ void exp_frac(double y, double mu, double dh, double cm, double cp,
+                                         const double *etab, double &a, double &b) {
+  if (y < kY0) {
+    b = h_series(y) + dh;
+    a = mu;
+  } else {
+    const double E = exp_neg(y, etab);
+    b = __builtin_fma(E, cp, y + cm);
+    a = __builtin_fma(-mu, E, mu);
+  }
+}
+
+// Every N, P of the grouped forms stays normal: dhat >= 1e-30 and
+// (y_top + dhat) (Litim: times max 1/mu) <= 1e37, y_top = (q_top + p)^2/k^2.
 template <int REG>
-__device__ __forceinline__ double lane_point(const double *__restrict__ tab, const SetDev &s,
+__device__ __forceinline__ bool point_chain_ok(const SetDev &s, double p, double delta) {
+  const double qp = s.q_top + p;
+  const double top = __builtin_fma(qp, qp, delta) * s.inv_k2;
+  const double dh = delta * s.inv_k2;
+  return dh >= 1e-30 && (REG == kExp ? top : top * s.rmu_max) <= 1e37;
+}
+
+// LDS layout of the point kernels: kExp2Tab64 (kExpTab doubles), the
+// angular pairs of the current set, then its packed table (table_doubles).
+// Pair j is (1 + x_j, mu_j) for the exponential regulator and
+// (1 + x_j, 1/mu_j) for Litim: one 16-byte read per term.
+__device__ __forceinline__ int point_lds_doubles(int n_r, int n_a) {
+  return kExpTab + 2 * n_a + table_doubles(n_r, n_a);
+}
+
+__device__ __forceinline__ void stage_pairs(const SetDev &s, double2 *ang, int tid, int nthreads) {
+  const double *o = s.tab + 3 * s.n_r;
+  const double *w = o + (s.reg == kExp ? s.n_a : 2 * s.n_a);
+  for (int j = tid; j < s.n_a; j += nthreads) ang[j] = make_double2(o[j], w[j]);
+}
+
+// `tab`: the packed quadrature table, `ang`: the angular pairs, `etab`:
+// kExp2Tab64, all in LDS.  JT: the lane split J when fixed at compile time
+// (1 or 2), else 0 (J from the set).
+template <int REG, int JT>
+__device__ __forceinline__ double lane_point(const double *__restrict__ tab,
+                                             const double2 *__restrict__ ang,
+                                             const double *__restrict__ etab, const SetDev &s,
                                              int lane, double p, double delta) {
   const int n_r = s.n_r, n_a = s.n_a;
   const double *tq = tab;
   const double *tc = tab + n_r;
   const double *tH = tab + 2 * n_r;
-  const double *to = tab + 3 * n_r;
-  const double *tr = to + 2 * n_a;
+  const int J = JT ? JT : s.J;
   const int rho = lane & (s.R - 1);
-  const int iota = lane / s.R;
-  const int G = chain_ok(delta, p, s.q_top, s.rmu_max) ? grouped_u(n_a, s.J) : 0;
+  const int iota = JT == 1 ? 0 : lane / s.R;
+  const double2 *al = ang + iota;  // the lane's angular nodes: al[J u]
+  const double dh = delta * s.inv_k2;
+  const double cm = dh - 1.0, cp = 1.0 - dh;
+  const int G = point_chain_ok<REG>(s, p, delta) ? grouped_u(n_a, J) : 0;
   double total = 0.0;
   for (int t = 0; t < s.T; ++t) {
     const int i = rho + s.R * t;
@@ -287,32 +386,94 @@ __device__ __forceinline__ double lane_point(const double *__restrict__ tab, con
     const double Gq = rcp64(Hq + delta);
     const double A = (c * Gq) * Gq;
     const double qm = q - p;
-    const double a = qm * qm;
-    const double b = (2.0 * q) * p;
+    const double ah = (qm * qm) * s.inv_k2;
+    const double bh = ((2.0 * q) * p) * s.inv_k2;
+    const double ah1 = ah - 1.0;
     double inner = 0.0;
     int u = 0;
     for (; u < G; u += kGroup) {
-      double Dp[kGroup];
+      const double2 *ag = al + J * u;
+      if constexpr (REG == kExp) {
+        // two halves of four terms (fewer live registers); the same
+        // operations in the same order as one pass over eight
+        double N = 0.0, P = 1.0;
 #pragma unroll
-      for (int k = 0; k < kGroup; ++k) {
-        const int j = iota + s.J * (u + k);
-        const double r = tr[j];
-        const double H = hk<REG>(__builtin_fma(b, to[j], a), s.k2, s.inv_k2) * r;
-        Dp[k] = __builtin_fma(delta, r, H);
+        for (int h = 0; h < kGroup; h += kHalf) {
+          double a[kHalf], b[kHalf], y[kHalf], mu[kHalf];
+#pragma unroll
+          for (int k = 0; k < kHalf; ++k) {
+            const double2 w = ag[J * (h + k)];
+            y[k] = __builtin_fma(bh, w.x, ah);
+            mu[k] = w.y;
+          }
+#pragma unroll
+          for (int k = 0; k < kHalf; ++k) exp_frac_e(y[k], mu[k], cm, cp, etab, a[k], b[k]);
+          // the angular nodes ascend, so y[0] is the smallest y of the half;
+          // lanes below kY0 (if any in the wave) take the series instead
+          if (__builtin_amdgcn_ballot_w64(y[0] < kY0)) {
+#pragma unroll
+            for (int k = 0; k < kHalf; ++k) {
+              const bool lo = y[k] < kY0;
+              const double bs = h_series(y[k]) + dh;
+              b[k] = lo ? bs : b[k];
+              a[k] = lo ? mu[k] : a[k];
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < kHalf; ++k) {
+            if (h == 0 && k == 0) {
+              N = a[0];
+              P = b[0];
+            } else {
+              N = __builtin_fma(N, b[k], a[k] * P);
+              P = P * b[k];
+            }
+          }
+        }
+        inner = __builtin_fma(N, rcp64(P), inner);
+      } else {
+        double2 w[kGroup];
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k) w[k] = ag[J * k];
+        double Dp[kGroup];
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k) {
+          const double H = fmax(__builtin_fma(bh, w[k].x, ah1), 0.0) * w[k].y;
+          Dp[k] = __builtin_fma(dh, w[k].y, H);
+        }
+        inner = chain_sum(Dp, inner);
       }
-      inner = chain_sum(Dp, inner);
     }
     for (; u < s.U; ++u) {
-      const int j = iota + s.J * u;
+      const int j = iota + J * u;
       if (j < n_a) {
-        const double r = tr[j];
-        const double H = hk<REG>(__builtin_fma(b, to[j], a), s.k2, s.inv_k2) * r;
-        inner = inner + rcp64(__builtin_fma(delta, r, H));
+        const double2 w = al[J * u];
+        if constexpr (REG == kExp) {
+          double a, b;
+          const double y = __builtin_fma(bh, w.x, ah);
+          exp_frac(y, w.y, dh, cm, cp, etab, a, b);
+          // b is +inf only for momenta beyond the grouped range: the term is 0
+          inner = inner + (b < INFINITY ? a * rcp64(b) : 0.0);
+        } else {
+          const double H = fmax(__builtin_fma(bh, w.x, ah1), 0.0) * w.y;
+          const double D = __builtin_fma(dh, w.y, H);
+          inner = inner + (D < INFINITY ? rcp64(D) : 0.0);
+        }
       }
     }
     total = __builtin_fma(A, inner, total);
   }
   return total;
+}
+
+// lane_point with the lane split of the set.
+template <int REG>
+__device__ __forceinline__ double point_partial(const SetDev &s, const double *tab,
+                                                const double2 *ang, const double *etab, int lane,
+                                                double p, double delta) {
+  if (s.J == 1) return lane_point<REG, 1>(tab, ang, etab, s, lane, p, delta);
+  if (s.J == 2) return lane_point<REG, 2>(tab, ang, etab, s, lane, p, delta);
+  return lane_point<REG, 0>(tab, ang, etab, s, lane, p, delta);
 }
 
 }  // namespace dev

@@ -23,11 +23,16 @@ template <int REG>
 __global__ __launch_bounds__(256) void fp32c_kernel(SetDev s, int tile_points, int64_t n_tiles,
                                                     int64_t grid_nm, int *flag) {
   extern __shared__ double lds[];
+  double *etab = lds;  // kExp2Tab64 and the angular pairs for the FP64 path
+  double2 *ang = reinterpret_cast<double2 *>(lds + kExpTab);
+  double *tab = lds + kExpTab + 2 * s.n_a;
   const int ntab = table_doubles(s.n_r, s.n_a);
-  const float *fo = reinterpret_cast<const float *>(lds + ntab);
+  const float *fo = reinterpret_cast<const float *>(tab + ntab);
   const float *fm = fo + s.n_a;
   const float *fl = fm + s.n_a;
-  stage_fp32c(s, lds, threadIdx.x, blockDim.x);
+  for (int i = threadIdx.x; i < kExpTab; i += blockDim.x) etab[i] = kExp2Tab64[i];
+  stage_pairs(s, ang, threadIdx.x, blockDim.x);
+  stage_fp32c(s, tab, threadIdx.x, blockDim.x);
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t tile = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
@@ -35,7 +40,7 @@ __global__ __launch_bounds__(256) void fp32c_kernel(SetDev s, int tile_points, i
   const int64_t start = tile * tile_points;
   const int64_t left = s.n_ext - start;
   const int count = left < tile_points ? (int)left : tile_points;
-  fp32c_tile<REG>(s, lds, fo, fm, fl, start, count, grid_nm, lane, flag);
+  fp32c_tile<REG>(s, tab, ang, etab, fo, fm, fl, start, count, grid_nm, lane, flag);
 }
 
 // ------------------------------------------------------ tensor grid --
@@ -273,7 +278,7 @@ int launch_fp32c(const SetDev &s, int tile_points, int64_t grid_nm, int *d_flag,
   const int64_t n_tiles = (s.n_ext + tile_points - 1) / tile_points;
   const int waves = 4;
   const int64_t blocks = (n_tiles + waves - 1) / waves;
-  const size_t lds = fp32c_lds_bytes(s.n_r, s.n_a);
+  const size_t lds = sizeof(double) * (kExpTab + 2 * s.n_a) + fp32c_lds_bytes(s.n_r, s.n_a);
   hipStream_t st = (hipStream_t)stream;
   if (s.reg == kExp)
     hipLaunchKernelGGL(fp32c_kernel<kExp>, dim3((unsigned)blocks), dim3(64 * waves), lds, st, s,

@@ -61,7 +61,7 @@ struct GridCfg {
   int MB = 16;  // mass blocks per wave while the table is resident
 };
 struct PersistCfg {
-  int tile = 4;  // points per tile
+  int tile = 4;  // work per tile of the persistent list, in units of 1024 evaluations
   int wpc = 24;  // resident one-wave workgroups per CU
 };
 using ShapeKey = std::tuple<int, int, int, int>;  // (regulator, n_r, n_a, precision)
@@ -97,10 +97,30 @@ struct Tune {
   int save_file(const std::string &arch) const;
 };
 
+// A captured persistent launch (FRG_GRAPH).  It is replayed only for the
+// same stream and the same set descriptors (pointers, shapes, tables and the
+// FP32C routing knobs) and launch shape; its work-list counter is its own,
+// and replays on one stream run in order.
 struct GraphEntry {
   DevBuf sets, tiles, counter;
   hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;  // recorded after every replay
+  hipStream_t stream = nullptr;
+  int *flag = nullptr;
+  std::vector<SetDev> sd;
+  PersistCfg pc;
+  uint64_t last_use = 0;
+  // the caller's set array of the last call that replayed this capture, and
+  // the knob generation then: a call with the same bytes, stream and
+  // generation replays it without rebuilding the descriptors
+  std::vector<frg_set> raw;
+  uint64_t gen = 0;
+  GraphEntry() = default;
+  GraphEntry(const GraphEntry &) = delete;
+  GraphEntry &operator=(const GraphEntry &) = delete;
+  ~GraphEntry();  // waits for the last replay
 };
+constexpr size_t kMaxGraphs = 32;  // least recently used entries are dropped beyond this
 
 struct Server;
 
@@ -111,12 +131,18 @@ struct Context {
   hipStream_t stream = nullptr;      // host-memory calls
   hipStream_t cap_stream = nullptr;  // graph capture
   std::mutex mu;
+  // Domain word of the call in progress: the word of its stream (set at the
+  // entry of every call that can meet a point outside the domain).  Each
+  // stream has its own word, so calls on different streams never share one;
+  // frg_stream_status reads and clears it.
   int *d_flag = nullptr;
-  int *d_counter = nullptr;
+  std::map<hipStream_t, int *> stream_flags;
+  int use_stream_flag(hipStream_t st);
   frg::DescRing ring;
   frg::DevBuf stage_in, stage_out;
   frg::DevBuf flags8;  // per-point FP64-redo marks of FP32C grids without used_fp64
   frg::Tune tune;
+  uint64_t tune_gen = 1;  // advanced whenever a knob or a tuned choice changes
   uint64_t hbm_budget = 0;
 
   struct QEntry {
@@ -131,16 +157,21 @@ struct Context {
   };
   std::map<std::tuple<int, int, uint64_t, uint64_t, int, int>, QEntry> qtabs;
   std::map<std::tuple<int, int, int, uint64_t>, LEntry> ltabs;
-  std::map<uint64_t, std::unique_ptr<frg::GraphEntry>> graphs;
+  std::vector<std::unique_ptr<frg::GraphEntry>> graphs;
+  uint64_t graph_clock = 0;
   std::map<std::tuple<int, int, int>, std::unique_ptr<frg::DevBuf>> vtabs;  // (d, n_a, n_phi)
   frg::Server *server = nullptr;
 
   virtual ~Context();
-  int quad_table(const frg_quad &q, const double **dev, frg::QuadTable *host_copy);
+  int quad_table(const frg_quad &q, const double **dev, frg::QuadTable *host_copy,
+                 frg::QuadTable **host_ref = nullptr);
   int grid32_table(const frg_quad &q, int J, const double **dev, frg::Grid32Table *host_copy);
   int lpa_table(int d, int reg, int n_r, double qmk, const double **dev, double *Cd);
   int make_setdev(const frg_set &s, frg::SetDev *out);
   int integrate_device(const frg_set *sets, int n_sets, int flags, hipStream_t st);
+  // FRG_GRAPH: replay the capture made for exactly this set array, stream
+  // and knob generation (1 if replayed, 0 if none matched, < 0 on error)
+  int replay_graph(const frg_set *sets, int n_sets, hipStream_t st);
   int integrate_host(const frg_set *sets, int n_sets, int flags);
   int persistent(const std::vector<frg::SetDev> &sd, const frg_set *sets, int n_sets, int flags,
                  hipStream_t st);

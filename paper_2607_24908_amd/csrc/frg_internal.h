@@ -59,6 +59,7 @@ struct SetDev {
   uint8_t *used64;
   const double *tab;  // device copy of QuadTable::data
   double k2, inv_k2, pref;
+  double pref_k;  // pref / k^2: the point kernels sum in units of k^2
   int64_t n_ext;
   int32_t n_r, n_a, reg, prec;
   int32_t R, J;  // lanes along radial / angular nodes, R * J = 64
@@ -73,6 +74,13 @@ struct Tile {
   int32_t count;
   int64_t start;
 };
+
+// Work-list counters of the persistent point kernel (one per XCD of MI355X),
+// kCounterStride ints apart (256 bytes: one cache line each); a launch needs
+// kCounters * kCounterStride ints with the counters zero at its start.
+constexpr int kCounters = 8;
+constexpr int kCounterStride = 64;
+constexpr int kCounterInts = kCounters * kCounterStride;
 
 struct GridArgs {
   const double *p;
@@ -250,9 +258,9 @@ constexpr int64_t tab_lds_max_nodes = 6144;  // rows up to this many nodes are s
 // All return hipError_t as int (0 = success).
 int launch_points_plain(const SetDev &s, int tile_points, int *d_flag, void *stream);
 int launch_points_persistent(const SetDev *d_sets, const Tile *d_tiles, int n_tiles,
-                             int *d_counter, int lds_bytes, int n_blocks, bool with_f32,
+                             int *d_counters /* kCounters ints, zero */, int lds_bytes, int n_blocks, bool with_f32,
                              int *d_flag, void *stream);
-int launch_reset_counter(int *d_counter, void *stream);
+int launch_reset_counter(int *d_counters /* kCounters ints */, void *stream);
 int launch_grid(const GridArgs &g, int reg, int M, int W, void *stream, bool redo = false);
 int grid_lds_bytes(const GridArgs &g);
 // Resident coefficient form of the FP64 grid kernel: used when its table fits.

@@ -21,25 +21,63 @@ namespace {
 
 using namespace dev;
 
-// One tile: `count` (<= 64) consecutive points of set s, one after another;
-// lane e keeps the result of point e, stored coalesced at the end.
+// Lane l's value of a double, as a wave-uniform (scalar) value.
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// One tile: `count` (<= 64) consecutive points of set s.  Lane e loads point
+// e, so the tile's inputs arrive with one memory latency; the points are
+// then taken one after another (wave-uniform p, delta) and four at a time
+// summed over the wave (wave_sum_fold<4>: lane l ends with the total of
+// point l/16, the same bits as for any other number of points per fold);
+// lanes 0, 16, 32, 48 store.
+// Lane e's inputs of a tile (0 beyond count).
+__device__ __forceinline__ void load_tile(const SetDev &s, int64_t start, int count, int lane,
+                                          double &pv, double &mv) {
+  pv = lane < count ? s.p[start + lane] : 0.0;
+  mv = lane < count ? s.m2[start + lane] : 0.0;
+}
+
 template <int REG>
-__device__ void do_tile(const SetDev &s, const double *tab, int64_t start, int count, int lane,
-                        int *flag) {
-  double res = 0.0;
-  for (int e = 0; e < count; ++e) {
-    const double p = s.p[start + e];
-    const double delta = s.m2[start + e] + s.k2;
-    double v;
-    if (delta > 0.0 && p >= 0.0) {
-      v = s.pref * wave_sum(lane_point<REG>(tab, s, lane, p, delta));
-    } else {
-      v = __builtin_nan("");
-      if (lane == 0) *flag = 1;
+__device__ void do_tile(const SetDev &s, const double *tab, const double2 *ang, const double *etab,
+                        int64_t start, int count, double pv, double mv, int lane, int *flag) {
+  constexpr int F = 4;
+  for (int e0 = 0; e0 < count; e0 += F) {
+    const int nf = count - e0 < F ? count - e0 : F;
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+    unsigned ok = 0;
+    // one copy of the point code: the partials go to v0..v3 by selects on
+    // the wave-uniform f
+#pragma unroll 1
+    for (int f = 0; f < nf; ++f) {
+      const double p = readlane_f64(pv, e0 + f);
+      const double delta = readlane_f64(mv, e0 + f) + s.k2;
+      double part = 0.0;
+      if (delta > 0.0 && p >= 0.0) {
+        part = point_partial<REG>(s, tab, ang, etab, lane, p, delta);
+        ok |= 1u << f;
+      } else if (lane == 0) {
+        *flag = 1;
+      }
+      v0 = f == 0 ? part : v0;
+      v1 = f == 1 ? part : v1;
+      v2 = f == 2 ? part : v2;
+      v3 = f == 3 ? part : v3;
     }
-    if (lane == e) res = v;
+    const double v[F] = {v0, v1, v2, v3};
+    const double tot = wave_sum_fold<F>(v, lane);
+    const int mine = fold_owner<F>(lane);
+    if (fold_leader<F>(lane) && mine < nf)
+      s.out[start + e0 + mine] = ((ok >> mine) & 1u) ? s.pref_k * tot : __builtin_nan("");
   }
-  if (lane < count) s.out[start + lane] = res;
+}
+
+__device__ __forceinline__ void stage_exp_table(double *etab, int tid, int nthreads) {
+  for (int i = tid; i < kExpTab; i += nthreads) etab[i] = kExp2Tab64[i];
 }
 
 __device__ __forceinline__ void stage_table(const SetDev &s, double *lds, int tid, int nthreads) {
@@ -47,13 +85,19 @@ __device__ __forceinline__ void stage_table(const SetDev &s, double *lds, int ti
   for (int i = tid; i < ntab; i += nthreads) lds[i] = s.tab[i];
 }
 
-// Plain launch over one set: 4 waves per workgroup share the staged table,
-// each wave takes one tile of `tile_points` points.
+// Plain launch over one set: 4 waves per workgroup share the staged tables
+// (LDS layout of point_lds_doubles), each wave takes one tile of
+// `tile_points` points.
 template <int REG>
 __global__ __launch_bounds__(256) void points_plain_kernel(SetDev s, int tile_points, int64_t n_tiles,
                                                            int *flag) {
   extern __shared__ double lds[];
-  stage_table(s, lds, threadIdx.x, blockDim.x);
+  double *etab = lds;
+  double2 *ang = reinterpret_cast<double2 *>(lds + kExpTab);
+  double *tab = lds + kExpTab + 2 * s.n_a;
+  stage_exp_table(etab, threadIdx.x, blockDim.x);
+  stage_pairs(s, ang, threadIdx.x, blockDim.x);
+  stage_table(s, tab, threadIdx.x, blockDim.x);
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t tile = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
@@ -61,57 +105,85 @@ __global__ __launch_bounds__(256) void points_plain_kernel(SetDev s, int tile_po
   const int64_t start = tile * tile_points;
   const int64_t left = s.n_ext - start;
   const int count = left < tile_points ? (int)left : tile_points;
-  do_tile<REG>(s, lds, start, count, lane, flag);
+  double pv, mv;
+  load_tile(s, start, count, lane, pv, mv);
+  do_tile<REG>(s, tab, ang, etab, start, count, pv, mv, lane, flag);
 }
 
 // Persistent launch over many sets (FP64 and FP32C mixed): one wave per
-// workgroup; waves pull tiles (longest first) from an atomic counter until
-// the list is drained.
+// workgroup; waves pull tiles from kCounters counters until the list is
+// drained.  Sub-list x holds tiles x, x + kCounters, ... of the longest-first
+// list (an equal share of every cost class) and is served by workgroups
+// b = x mod kCounters (with round-robin dispatch, the workgroups of one
+// XCD); the counters lie kCounterStride ints apart, on different cache
+// lines, so the claims spread over kCounters atomic units.  A wave ends at
+// its first empty claim; the launch has at least min(n_tiles, kCounters)
+// workgroups, so every non-empty sub-list is served.
 template <bool WITH_F32>
 __global__ __launch_bounds__(64) void points_persistent_kernel(const SetDev *__restrict__ sets,
                                                                const Tile *__restrict__ tiles,
-                                                               int n_tiles, int *counter,
+                                                               int n_tiles, int *counters,
                                                                int *flag) {
   extern __shared__ double lds[];
+  double *etab = lds;
   const int lane = threadIdx.x;
+  stage_exp_table(etab, lane, kWave);
   int cur = -1;
+  // lane 0 claims tiles; the claim of the next tile is issued while the
+  // current one is processed, so its latency is hidden.  Tile indices are
+  // made wave-uniform (scalar registers), and the tile and set descriptors
+  // read with them are scalar loads.
+  const int x = (int)(blockIdx.x % kCounters);
+  int *ctr = counters + x * kCounterStride;
+  auto claim = [&]() -> int {
+    int c = 0;
+    if (lane == 0) c = atomicAdd(ctr, 1);
+    return c;
+  };
+  int c = __builtin_amdgcn_readfirstlane(claim());
   for (;;) {
-    int t = 0;
-    if (lane == 0) t = atomicAdd(counter, 1);
-    // lane 0 holds the tile: make it (and the tile and set descriptors read
-    // with it) wave-uniform, in scalar registers
-    t = __builtin_amdgcn_readfirstlane(t);
-    if (t >= n_tiles) break;
+    const int64_t tt = (int64_t)x + (int64_t)kCounters * c;
+    if (tt >= n_tiles) break;
+    const int t = (int)tt;
     const Tile tl = tiles[t];
     const SetDev s = sets[tl.set];
     const bool f32 = WITH_F32 && s.prec == FRG_PREC_FP32C;
+    double pv = 0.0, mv = 0.0;
+    if (!f32) load_tile(s, tl.start, tl.count, lane, pv, mv);
+    double2 *ang = reinterpret_cast<double2 *>(lds + kExpTab);
+    double *tab = lds + kExpTab + 2 * s.n_a;
     if (tl.set != cur) {
       __syncthreads();
+      stage_pairs(s, ang, lane, kWave);
       if (f32)
-        stage_fp32c(s, lds, lane, kWave);
+        stage_fp32c(s, tab, lane, kWave);
       else
-        stage_table(s, lds, lane, kWave);
+        stage_table(s, tab, lane, kWave);
       __syncthreads();
       cur = tl.set;
     }
+    // claim the next tile after this tile's loads, so that waiting for them
+    // does not wait for the claim
+    const int cn = claim();
     if (f32) {
-      const float *fo = reinterpret_cast<const float *>(lds + table_doubles(s.n_r, s.n_a));
+      const float *fo = reinterpret_cast<const float *>(tab + table_doubles(s.n_r, s.n_a));
       const float *fm = fo + s.n_a;
       const float *fl = fm + s.n_a;
       if (s.reg == kExp)
-        fp32c_tile<kExp>(s, lds, fo, fm, fl, tl.start, tl.count, 0, lane, flag);
+        fp32c_tile<kExp>(s, tab, ang, etab, fo, fm, fl, tl.start, tl.count, 0, lane, flag);
       else
-        fp32c_tile<kLitim>(s, lds, fo, fm, fl, tl.start, tl.count, 0, lane, flag);
+        fp32c_tile<kLitim>(s, tab, ang, etab, fo, fm, fl, tl.start, tl.count, 0, lane, flag);
     } else if (s.reg == kExp) {
-      do_tile<kExp>(s, lds, tl.start, tl.count, lane, flag);
+      do_tile<kExp>(s, tab, ang, etab, tl.start, tl.count, pv, mv, lane, flag);
     } else {
-      do_tile<kLitim>(s, lds, tl.start, tl.count, lane, flag);
+      do_tile<kLitim>(s, tab, ang, etab, tl.start, tl.count, pv, mv, lane, flag);
     }
+    c = __builtin_amdgcn_readfirstlane(cn);
   }
 }
 
 __global__ void reset_counter_kernel(int *c) {
-  if (threadIdx.x == 0) *c = 0;
+  if (threadIdx.x < kCounters) c[threadIdx.x * kCounterStride] = 0;
 }
 
 // Tensor grid.  A workgroup of W waves owns one momentum p[a] and
@@ -598,7 +670,7 @@ int launch_points_plain(const SetDev &s, int tile_points, int *d_flag, void *str
   const int64_t n_tiles = (s.n_ext + tile_points - 1) / tile_points;
   const int waves = 4;
   const int64_t blocks = (n_tiles + waves - 1) / waves;
-  const size_t lds = sizeof(double) * table_doubles(s.n_r, s.n_a);
+  const size_t lds = sizeof(double) * (kExpTab + 2 * s.n_a + table_doubles(s.n_r, s.n_a));
   hipStream_t st = (hipStream_t)stream;
   if (s.reg == kExp)
     hipLaunchKernelGGL(points_plain_kernel<kExp>, dim3((unsigned)blocks), dim3(64 * waves), lds, st,
@@ -618,6 +690,9 @@ int launch_points_persistent(const SetDev *d_sets, const Tile *d_tiles, int n_ti
                              int lds_bytes, int n_blocks, bool with_f32, int *d_flag,
                              void *stream) {
   if (n_tiles <= 0) return 0;
+  // every non-empty sub-list needs a workgroup of its own
+  if (n_blocks < kCounters) n_blocks = n_tiles < kCounters ? n_tiles : kCounters;
+  lds_bytes += (int)sizeof(double) * kExpTab;  // kExp2Tab64 ahead of the set's tables
   if (with_f32)
     hipLaunchKernelGGL(points_persistent_kernel<true>, dim3(n_blocks), dim3(64), (size_t)lds_bytes,
                        (hipStream_t)stream, d_sets, d_tiles, n_tiles, d_counter, d_flag);

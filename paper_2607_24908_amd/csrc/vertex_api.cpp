@@ -102,6 +102,8 @@ int frg_integrate_vertex(frg_ctx *ctx, const frg_quad *quad, int32_t n_azimuth, 
   std::lock_guard<std::mutex> lk(ctx->mu);
   hipSetDevice(ctx->device);
   clear_error();
+  if (int rcf = ctx->use_stream_flag(mem == FRG_MEM_HOST ? ctx->stream : (hipStream_t)hip_stream))
+    return rcf;
   if (mem == FRG_MEM_DEVICE)
     return ctx->vertex_device(*quad, n_azimuth, n_c, p1, p2, cos12, n_m, m2, out,
                               (hipStream_t)hip_stream);

@@ -33,7 +33,8 @@ EXPORTS = ["frg_create", "frg_destroy", "frg_last_error", "frg_version", "frg_in
            "frg_pflow_solve", "frg_fvlpa_rhs", "frg_fvlpa_solve",
            "frg_flow_rhs", "frg_flow_rhs_batch", "frg_flow_solve",
            "frg_submit", "frg_poll", "frg_server_stats", "frg_gauss_legendre",
-           "frg_flow_footprint", "frg_autotune", "frg_tune_set", "frg_tune_get"]
+           "frg_flow_footprint", "frg_autotune", "frg_tune_set", "frg_tune_get", "frg_expneg",
+           "frg_stream_status"]
 
 
 class frg_quad(ctypes.Structure):
@@ -140,6 +141,8 @@ def _load():
     L.frg_server_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                    ctypes.POINTER(dbl)]
     L.frg_gauss_legendre.argtypes = [i32, vp, vp]
+    L.frg_expneg.argtypes = [i64, vp, vp]
+    L.frg_stream_status.argtypes = [vp, vp]
     L.frg_flow_footprint.argtypes = [ctypes.POINTER(frg_lpa)]
     L.frg_flow_footprint.restype = i64
     L.frg_autotune.argtypes = [vp, i32, ctypes.c_char_p]
@@ -206,15 +209,37 @@ def frg_destroy(ctx: int) -> None:
     lib.frg_destroy(ctx)
 
 
-def frg_integrate(ctx, sets, mem=FRG_MEM_DEVICE, flags=FRG_PLAIN, stream=None, allow_domain=False):
-    """sets: list of dicts {quad, p, m2, out, [err_est], [used_fp64]} with tensors/arrays."""
+def make_set_array(sets):
+    """The frg_set array of a list of dicts {quad, p, m2, out, [err_est],
+    [used_fp64]} (tensors/arrays; the caller keeps them alive)."""
     arr = (frg_set * max(1, len(sets)))()
     for i, s in enumerate(sets):
         n = int(s["p"].numel() if hasattr(s["p"], "numel") else s["p"].size)
         arr[i] = frg_set(s["quad"], n, _addr(s["p"]), _addr(s["m2"]), _addr(s["out"]),
                          _addr(s.get("err_est")), _addr(s.get("used_fp64")))
+    return arr
+
+
+def frg_integrate(ctx, sets, mem=FRG_MEM_DEVICE, flags=FRG_PLAIN, stream=None, allow_domain=False):
+    """sets: list of dicts {quad, p, m2, out, [err_est], [used_fp64]} with tensors/arrays."""
+    arr = make_set_array(sets)
     st = 0 if mem == FRG_MEM_HOST else _stream(stream)
     return _check(lib.frg_integrate(ctx, arr, len(sets), mem, flags, st),
+                  (FRG_E_DOMAIN,) if allow_domain else ())
+
+
+def frg_integrate_array(ctx, arr, n_sets, mem=FRG_MEM_DEVICE, flags=FRG_PLAIN, stream=None,
+                        allow_domain=False):
+    """frg_integrate on a set array from make_set_array (no per-call marshalling)."""
+    st = 0 if mem == FRG_MEM_HOST else _stream(stream)
+    return _check(lib.frg_integrate(ctx, arr, n_sets, mem, flags, st),
+                  (FRG_E_DOMAIN,) if allow_domain else ())
+
+
+def frg_stream_status(ctx, stream=None, allow_domain=False):
+    """Wait for the stream; FRG_E_DOMAIN if a device call on it met a point
+    outside the domain since the last query (raises unless allow_domain)."""
+    return _check(lib.frg_stream_status(ctx, _stream(stream)),
                   (FRG_E_DOMAIN,) if allow_domain else ())
 
 
@@ -364,6 +389,13 @@ def frg_gauss_legendre(n: int):
     w = np.empty(n)
     _check(lib.frg_gauss_legendre(n, _addr(x), _addr(w)))
     return x, w
+
+
+def frg_expneg(y: np.ndarray) -> np.ndarray:
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    out = np.empty_like(y)
+    _check(lib.frg_expneg(y.size, _addr(y), _addr(out)))
+    return out
 
 
 def frg_flow_footprint(lpa: frg_lpa) -> int:

@@ -203,3 +203,29 @@ def test_broken_phase_flow_stops_at_pole_exp_regulator():
     k = math.exp(res.t_reached)
     _, _, rc2 = oracle.lpa_rhs(3, N, 0, 64, 6.0, k, 0.5, U, jacobian=False)
     assert rc2 == 0 and np.all(np.isfinite(U))
+
+
+def test_expneg_against_libm_and_mpmath():
+    """The point kernels' table-driven e^{-y} (host copy, the same operations
+    as on the device): within 1.6 ulp of the exact value where the result is
+    normal, 0 beyond the subnormal range, exact at y = 0."""
+    import mpmath as mp
+    rng = np.random.default_rng(7)
+    y = np.concatenate([rng.uniform(0.0, 1.0, 200000), rng.uniform(0.0, 40.0, 200000),
+                        rng.uniform(0.0, 708.0, 200000), np.linspace(0.0, 2.0, 4097)])
+    e = frg.frg_expneg(y)
+    ref = np.exp(-y)  # the C library's exp (within 1 ulp)
+    ulp = np.spacing(ref)
+    assert np.max(np.abs(e - ref) / ulp) <= 2.6
+    # exact values on a sample: 40 digits
+    mp.mp.dps = 40
+    idx = rng.choice(y.size, 400, replace=False)
+    for i in idx:
+        ex = mp.e ** (-mp.mpf(float(y[i])))
+        assert abs(mp.mpf(float(e[i])) - ex) / mp.mpf(float(np.spacing(float(ex)))) <= 1.6
+    assert frg.frg_expneg(np.array([0.0]))[0] == 1.0
+    big = frg.frg_expneg(np.array([746.0, 800.0, 1e6, 1e300, np.inf]))
+    assert np.all(big == 0.0)
+    # subnormal results: absolute error below one subnormal ulp times 2
+    ys = np.linspace(709.0, 745.0, 1001)
+    assert np.max(np.abs(frg.frg_expneg(ys) - np.exp(-ys))) <= 2 * 4.94e-324
