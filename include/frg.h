@@ -442,6 +442,33 @@ int frg_autotune(frg_ctx *ctx, int32_t mode, const char *cache_path);
 int frg_tune_set(frg_ctx *ctx, const char *key, int32_t value);
 int frg_tune_get(frg_ctx *ctx, const char *key, int32_t *value);
 
+/* ---- allocation-free variant ------------------------------------------------- */
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc:
+ * frg_integrate(ctx, sets, n_sets, FRG_MEM_DEVICE, FRG_PERSISTENT, hip_stream),
+ * the same kernel and the same bits, with its work-list counters, set
+ * descriptors, longest-first work list and quadrature tables in a scratch
+ * area of 4 MiB that the library keeps in device memory on every GPU it
+ * runs on (a static device array, held until the process ends), filled by
+ * one copy from a pinned buffer that frg_create allocated.  The call
+ * allocates and frees no device memory (a quadrature key seen for the first
+ * time costs host memory for its table only).  All pointers of `sets` are
+ * device memory; results are asynchronous on hip_stream.
+ * domain_flag (optional, device memory): set to 1 when a point has
+ * m^2 + k^2 <= 0 or p < 0 (its result is NaN); the caller clears it.
+ * Errors: FRG_E_INVAL for bad arguments and for a call whose descriptors,
+ * work list and tables exceed the 4 MiB area (the message gives the bytes
+ * needed: about 150 B per set, 16 B per tile of about 4096 evaluations and
+ * 8 (3 n_radial + 3 n_angular) B per distinct quadrature); nothing is then
+ * launched.
+ * The area is shared by every call on one GPU and keeps the last call's
+ * contents.  A call waits on the host for the previous call of its context
+ * to finish before it overwrites the area, so the calls of one context never
+ * overlap; calls from different contexts (or processes) on one GPU that
+ * overlap in time race. */
+int frg_integrate_noalloc(frg_ctx *ctx, const frg_set *sets, int32_t n_sets, int32_t *domain_flag,
+                          void *hip_stream);
+
 /* ---- domain status of device calls ----------------------------------------- */
 /* Device-memory calls are asynchronous and return before their kernels run,
  * so a point outside the domain (m^2 + k^2 <= 0, p < 0, cos12 outside

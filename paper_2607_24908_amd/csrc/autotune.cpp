@@ -149,6 +149,13 @@ int Context::plain_tile_for(const SetDev &s, hipStream_t st) {
   return best;
 }
 
+PersistCfg Context::persist_cfg_cached(const std::vector<SetDev> &sd, int prec) const {
+  double work = 0.0;
+  for (auto &s : sd) work += (double)s.n_ext * s.n_r * s.n_a;
+  auto it = tune.persist_best.find(prec * 64 + size_class(work));
+  return it != tune.persist_best.end() ? it->second : tune.persist;
+}
+
 PersistCfg Context::persist_cfg(const std::vector<SetDev> &sd, int prec, hipStream_t st) {
   double work = 0.0;
   for (auto &s : sd) work += (double)s.n_ext * s.n_r * s.n_a;

@@ -241,12 +241,8 @@ int check_lpa(const frg_lpa &l) {
 }
 
 // ----------------------------------------------------------- integrate --
-int Ctx::make_setdev(const frg_set &s, SetDev *out) {
-  const double *tab;
-  QuadTable *hp = nullptr;
-  int rc = quad_table(s.quad, &tab, nullptr, &hp);
-  if (rc) return rc;
-  const QuadTable &h = *hp;
+// Descriptor of set s with its quadrature table `h` at device address `tab`.
+void Ctx::fill_setdev(const frg_set &s, const QuadTable &h, const double *tab, SetDev *out) {
   SetDev d{};
   d.p = s.p;
   d.m2 = s.m2;
@@ -269,7 +265,6 @@ int Ctx::make_setdev(const frg_set &s, SetDev *out) {
   d.f32_band = tune.fp32c_band_ppm * 1e-6;
   lane_split(d.n_r, d.n_a, &d.R, &d.J, &d.T, &d.U);
   *out = d;
-  return FRG_OK;
 }
 
 int Ctx::replay_graph(const frg_set *sets, int n_sets, hipStream_t st) {
@@ -285,6 +280,15 @@ int Ctx::replay_graph(const frg_set *sets, int n_sets, hipStream_t st) {
     return 1;
   }
   return 0;
+}
+
+int Ctx::make_setdev(const frg_set &s, SetDev *out) {
+  const double *tab;
+  QuadTable *hp = nullptr;
+  int rc = quad_table(s.quad, &tab, nullptr, &hp);
+  if (rc) return rc;
+  fill_setdev(s, *hp, tab, out);
+  return FRG_OK;
 }
 
 // Device-side core: every pointer in `sets` is device memory.
@@ -841,6 +845,11 @@ Context::~Context() {
   if (stream) hipStreamSynchronize(stream);
   graphs.clear();
   ring.destroy();
+  if (na_done) {
+    hipEventSynchronize(na_done);
+    hipEventDestroy(na_done);
+  }
+  if (na_stage) hipHostFree(na_stage);
   for (auto &kv : stream_flags) hipFree(kv.second);
   stream_flags.clear();
   if (stream) hipStreamDestroy(stream);
@@ -878,6 +887,8 @@ int frg_create(frg_ctx **out, int hip_device, uint64_t hbm_budget_bytes) {
       hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)
     return fail(FRG_E_DEVICE, "hipStreamCreate");
   int rc = c->use_stream_flag(c->stream);
+  if (rc) return rc;
+  rc = noalloc_init(hip_device, c.get());
   if (rc) return rc;
   rc = c->ring.init(1 << 20, 8);
   if (rc) return rc;

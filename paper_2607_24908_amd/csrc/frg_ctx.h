@@ -20,8 +20,13 @@ void clear_error();
 double now_s();
 int check_quad(const frg_quad &q);
 int check_lpa(const frg_lpa &l);
+struct Context;
+// noalloc.hip: once per device (that device current), the device address of
+// the scratch area; and the context's pinned staging buffer
+int noalloc_init(int device, Context *ctx);
 void build_tiles(const std::vector<SetDev> &sd, int tile, std::vector<Tile> *tiles);
 int max_table_bytes(const std::vector<SetDev> &sd);
+bool any_fp32c(const std::vector<SetDev> &sd);
 
 // Grow-only device allocation.
 struct DevBuf {
@@ -168,6 +173,15 @@ struct Context {
   int grid32_table(const frg_quad &q, int J, const double **dev, frg::Grid32Table *host_copy);
   int lpa_table(int d, int reg, int n_r, double qmk, const double **dev, double *Cd);
   int make_setdev(const frg_set &s, frg::SetDev *out);
+  void fill_setdev(const frg_set &s, const frg::QuadTable &h, const double *tab, frg::SetDev *out);
+  // noalloc.hip: pinned staging of the allocation-free call (filled and
+  // copied to the device scratch area), the event after its last kernel, and
+  // host-only quadrature tables of keys not in qtabs
+  char *na_stage = nullptr;
+  hipEvent_t na_done = nullptr;
+  bool na_pending = false;
+  std::map<std::tuple<int, int, uint64_t, uint64_t, int, int>, frg::QuadTable> htabs;
+  const frg::QuadTable &host_quad_table(const frg_quad &q);
   int integrate_device(const frg_set *sets, int n_sets, int flags, hipStream_t st);
   // FRG_GRAPH: replay the capture made for exactly this set array, stream
   // and knob generation (1 if replayed, 0 if none matched, < 0 on error)
@@ -214,6 +228,8 @@ struct Context {
   GridCfg grid_cfg(const frg_quad &q, const GridArgs &g, hipStream_t st);
   int plain_tile_for(const SetDev &s, hipStream_t st);
   PersistCfg persist_cfg(const std::vector<SetDev> &sd, int prec, hipStream_t st);
+  // the tuned or default shape, never timing candidates
+  PersistCfg persist_cfg_cached(const std::vector<SetDev> &sd, int prec) const;
   int persistent_eager(const std::vector<SetDev> &sd, const PersistCfg &pc, hipStream_t st);
 };
 

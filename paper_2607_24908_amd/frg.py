@@ -34,7 +34,7 @@ EXPORTS = ["frg_create", "frg_destroy", "frg_last_error", "frg_version", "frg_in
            "frg_flow_rhs", "frg_flow_rhs_batch", "frg_flow_solve",
            "frg_submit", "frg_poll", "frg_server_stats", "frg_gauss_legendre",
            "frg_flow_footprint", "frg_autotune", "frg_tune_set", "frg_tune_get", "frg_expneg",
-           "frg_stream_status"]
+           "frg_stream_status", "frg_integrate_noalloc"]
 
 
 class frg_quad(ctypes.Structure):
@@ -143,6 +143,7 @@ def _load():
     L.frg_gauss_legendre.argtypes = [i32, vp, vp]
     L.frg_expneg.argtypes = [i64, vp, vp]
     L.frg_stream_status.argtypes = [vp, vp]
+    L.frg_integrate_noalloc.argtypes = [vp, ctypes.POINTER(frg_set), i32, vp, vp]
     L.frg_flow_footprint.argtypes = [ctypes.POINTER(frg_lpa)]
     L.frg_flow_footprint.restype = i64
     L.frg_autotune.argtypes = [vp, i32, ctypes.c_char_p]
@@ -226,6 +227,15 @@ def frg_integrate(ctx, sets, mem=FRG_MEM_DEVICE, flags=FRG_PLAIN, stream=None, a
     st = 0 if mem == FRG_MEM_HOST else _stream(stream)
     return _check(lib.frg_integrate(ctx, arr, len(sets), mem, flags, st),
                   (FRG_E_DOMAIN,) if allow_domain else ())
+
+
+def frg_integrate_noalloc(ctx, sets, domain_flag=None, stream=None):
+    """Allocation-free persistent launch over device-memory sets (the dicts of
+    frg_integrate); domain_flag: optional device int32 tensor set to 1 on a
+    domain violation."""
+    arr = make_set_array(sets)
+    return _check(lib.frg_integrate_noalloc(ctx, arr, len(sets), _addr(domain_flag),
+                                            _stream(stream)))
 
 
 def frg_integrate_array(ctx, arr, n_sets, mem=FRG_MEM_DEVICE, flags=FRG_PLAIN, stream=None,
