@@ -45,6 +45,19 @@ VALU_LANE_CYCLES = 256 * 4 * 16 * 2.4e9
 TRAFFIC = 460.0 * 1024 * 2.00 + 16384 * 1024 * 1.00
 CYCLES_PER_EVAL_FLOOR = 2
 PEAK_EVALS = VALU_LANE_CYCLES / CYCLES_PER_EVAL_FLOOR
+TRAFFIC_SOURCE = ("rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE of grid_coef_kernel on this workload "
+                  "(profiles/grid_kernel_scaleup_d3_hbm_traffic.md), not measured in this run")
+# Point-list (uneven sets) roofline: the algorithmic FP64 vector work of one
+# evaluation with the regulator evaluated per term, taken at the middle of the
+# estimated ranges -- exponential: one expm1-class transcendental, one
+# division, one reciprocal and ~3 FMA/add, 35-45 instructions -> 40;
+# Litim: compare/select, one reciprocal, ~3 FMA/add, 8-12 -> 10 -- weighted by
+# the workload's evaluations per regulator.
+OPS_PER_EVAL = {0: 40.0, 1: 10.0}
+# FP64 vector instructions per evaluation of points_persistent_kernel on the
+# uneven sets, from SQ_INSTS_VALU x 64 / evaluations
+# (profiles/points_persistent_kernel_uneven_sets.md).
+POINT_VALU_PER_EVAL_PROFILE = 20.4
 
 
 def parse():
@@ -121,10 +134,30 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w):
-    """The FP64 oracle, as it stands, on 1/4 of the workload (every 4th mass
-    for all momenta, about 20-30 core-seconds), OpenMP over points on the host
-    cores."""
+def cpu_info():
+    model, flags = "unknown", []
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name") and model == "unknown":
+                    model = line.split(":", 1)[1].strip()
+                if line.startswith("flags"):
+                    fl = line.split(":", 1)[1].split()
+                    flags = sorted(x for x in fl if x.startswith(("avx", "sse4", "fma", "amx")))
+                    break
+    except OSError:
+        pass
+    return model, flags
+
+
+def cpu_baseline(w, gpu_out, checks, workloads):
+    """The oracle leg.  The FP64 oracle, as it stands: OpenMP over points on
+    the host cores on 1/4 of the workload (every 4th mass for all momenta,
+    about 20-30 core-seconds), and single-threaded on 1/256 of it (every 16th
+    momentum of that sample).  The 524 288 results of the first run are
+    compared with the GPU's results of the timed region, element by element;
+    so are the GPU results of the plain d = 4 grid, the 256 uneven sets and
+    (as a per-result histogram) the compensated-FP32 precision workload."""
     import oracle
     q = w.quad
     m2 = w.m2[::4]
@@ -136,12 +169,72 @@ def cpu_baseline(w):
         cores = os.cpu_count() or 1
     cores = max(1, min(cores, 64))
     t0 = time.perf_counter()
-    oracle.integrate(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a, P, M, threads=cores)
+    ref = oracle.integrate(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a, P, M, threads=cores)
     dt = time.perf_counter() - t0
     evals = P.size * q.n_r * q.n_a
-    return {"value": evals / dt, "unit": "integrand evals/s", "cores": cores, "kind": "oracle",
+    got = gpu_out.reshape(w.p.size, w.m2.size)[:, ::4].ravel()
+    rel = np.abs(got - ref) / np.abs(ref)
+    parity = {"max_rel_err": float(rel.max()), "median_rel_err": float(np.median(rel)),
+              "compared": int(rel.size), "tol": 1e-12,
+              "what": "every 4th mass x all 4096 momenta of the timed region's output vs the "
+                      "FP64 oracle"}
+    P1 = np.repeat(w.p[::16], m2.size)
+    M1 = np.tile(m2, w.p[::16].size)
+    t1 = time.perf_counter()
+    oracle.integrate(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a, P1, M1, threads=1)
+    dt1 = time.perf_counter() - t1
+    ev1 = P1.size * q.n_r * q.n_a
+    parity["others"] = oracle_checks(oracle, checks, workloads, cores)
+    model, flags = cpu_info()
+    base = {"value": evals / dt, "unit": "integrand evals/s", "cores": cores, "kind": "oracle",
             "sample": f"1/4 of the workload: all {w.p.size} momenta x every 4th mass "
-                      f"({P.size} integrals, {evals:.3e} evals), {dt:.2f} s wall"}
+                      f"({P.size} integrals, {evals:.3e} evals), {dt:.2f} s wall on {cores} "
+                      f"threads; single thread: 1/256 ({P1.size} integrals), {dt1:.2f} s",
+            "single_thread_value": ev1 / dt1, "cpu_model": model, "simd_flags": flags,
+            "compiled": "-O2 -fno-fast-math -ffp-contract=off, OpenMP over points"}
+    return base, parity
+
+
+def oracle_checks(oracle, checks, workloads, cores):
+    """Element-by-element comparison of GPU results kept by `secondary` with
+    the FP64 oracle; the compensated-FP32 results as a log-binned histogram of
+    the relative error of every result."""
+    out = {}
+    if "plain_d4" in checks:
+        w = workloads.plain_d4()
+        q = w.quad
+        ref = oracle.integrate_grid(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a, w.p, w.m2).ravel()
+        out["plain_d4"] = {"max_rel_err": float(np.max(np.abs(checks["plain_d4"] - ref) / ref)),
+                           "compared": int(ref.size)}
+    if "uneven_seed0" in checks:
+        worst, n = 0.0, 0
+        for s, got in zip(workloads.uneven_sets(seed=0), checks["uneven_seed0"]):
+            q = s.quad
+            ref = oracle.integrate(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a, s.p, s.m2, threads=cores)
+            worst = max(worst, float(np.max(np.abs(got - ref) / ref)))
+            n += ref.size
+        out["uneven_sets_seed0"] = {"max_rel_err": worst, "compared": n}
+    if checks.get("precision_d4"):
+        edges = 10.0 ** np.arange(-17, -3)
+        rels, ests, fp32 = [], [], []
+        for wk, o32, err, used in checks["precision_d4"]:
+            q = wk.quad
+            ref = oracle.integrate_grid(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a, wk.p,
+                                        wk.m2).ravel()
+            rels.append(np.abs(o32 - ref) / ref)
+            ests.append(err)
+            fp32.append(used == 0)
+        rel, est, f32 = np.concatenate(rels), np.concatenate(ests), np.concatenate(fp32)
+        counts, _ = np.histogram(np.clip(rel, 1e-17, 1e-4 * 0.999), bins=edges)
+        out["fp32c_precision_d4_seeds012"] = {
+            "results": int(rel.size), "fp32_returned": int(f32.sum()),
+            "max_rel_err": float(rel.max()),
+            "max_rel_err_fp32_returned": float(rel[f32].max()) if f32.any() else None,
+            "fp32_results_above_their_estimate": int(np.sum(rel[f32] > est[f32])),
+            "histogram_rel_err": {f"[1e{int(np.log10(a))},1e{int(np.log10(b))})": int(c)
+                                  for a, b, c in zip(edges[:-1], edges[1:], counts)},
+            "tol": 1e-7}
+    return out
 
 
 def main():
@@ -235,10 +328,12 @@ def main():
                      "kernel": "grid_coef_kernel<exp> (16-mass tiles, FP64 matrix cores)",
                      "kernel_ms": gpu_ms,
                      "evals_per_launch": int(w.n_evals), "traffic_unit": "bytes per launch",
+                     "traffic_source": TRAFFIC_SOURCE,
                      "peak_basis": "FP64 3.93e13 FMA/s (vector or matrix) / 2 FMAs per eval"},
     }
+    checks = {}
     if not args.no_secondary:
-        line["secondary"] = secondary(ctx, frg, workloads, torch)
+        line["secondary"] = secondary(ctx, frg, workloads, torch, checks)
     if args.copy_calibration:
         x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
         y = torch.empty_like(x)
@@ -246,7 +341,15 @@ def main():
         torch.cuda.synchronize()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        line["cpu_baseline"] = cpu_baseline(w)
+        line["cpu_baseline"], line["parity"] = cpu_baseline(w, res, checks, workloads)
+        log(f"parity vs oracle on {line['parity']['compared']} results: max rel err "
+            f"{line['parity']['max_rel_err']:.2e}")
+        others = line["parity"]["others"]
+        worst64 = max([line["parity"]["max_rel_err"]] +
+                      [v["max_rel_err"] for k, v in others.items() if not k.startswith("fp32c")])
+        if not worst64 <= 1e-12:
+            print(json.dumps(line), flush=True)
+            sys.exit("FP64 parity against the oracle exceeds 1e-12")
     frg.frg_destroy(ctx)
     print(json.dumps(line), flush=True)
 
@@ -264,29 +367,96 @@ def timed(fn, torch, reps=5):
     return (time.perf_counter() - t0) / reps
 
 
-def secondary(ctx, frg, workloads, torch):
-    """Figures for the other workloads, measured after the timed region."""
-    sec = {}
-    # uneven sets: one plain launch per set vs one persistent graph replay
+def events_time(fn, torch, reps=30, warm=3):
+    """Seconds per call from HIP events recorded on the current stream around
+    `reps` back-to-back calls (the calls enqueue on that stream)."""
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) * 1e-3 / reps
+
+
+def uneven_sets_figures(ctx, frg, workloads, torch):
+    """Batched uneven sets (256 sets, seed 0): one persistent launch replayed
+    from a HIP graph against one plain launch per set, the roofline of the
+    persistent kernel, and the autotuned launch shape against the default."""
+    import tempfile
     sets = workloads.uneven_sets(seed=0)
     evals = sum(s.n_evals for s in sets)
+    n_int = sum(s.p.size for s in sets)
     ds = []
     for s in sets:
         q = s.quad
         ds.append(dict(quad=frg.make_quad(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a),
                        p=torch.as_tensor(s.p, device="cuda"), m2=torch.as_tensor(s.m2, device="cuda"),
                        out=torch.empty(s.p.size, dtype=torch.float64, device="cuda")))
+    arr = frg.make_set_array(ds)
+    st = torch.cuda.current_stream().cuda_stream
+
+    def call(flags):
+        return lambda: frg.frg_integrate_array(ctx, arr, len(ds), flags=flags, stream=st)
+
+    t_plain = timed(call(frg.FRG_PLAIN), torch)
+    t_pers = timed(call(frg.FRG_PERSISTENT), torch, reps=20)
+    t_graph = events_time(call(frg.FRG_PERSISTENT | frg.FRG_GRAPH), torch, reps=30)
+    default_out = torch.cat([d["out"] for d in ds])
+    # the project's autotuner: time the candidate shapes of this key once,
+    # keep the fastest, replay with it; the results must not change
+    cache = os.path.join(tempfile.gettempdir(), f"frg_autotune_{os.getpid()}.txt")
+    frg.frg_autotune(ctx, 1, cache)
+    call(frg.FRG_PERSISTENT)()
+    frg.frg_autotune(ctx, 0, None)
+    t_tuned = events_time(call(frg.FRG_PERSISTENT | frg.FRG_GRAPH), torch, reps=30)
+    tuned_same = bool(torch.equal(torch.cat([d["out"] for d in ds]), default_out))
+    try:
+        tuned_line = open(cache).read().strip().splitlines()[-1]
+        os.remove(cache)
+    except OSError:
+        tuned_line = ""
+    ops = sum(s.n_evals * OPS_PER_EVAL[s.quad.reg] for s in sets) / evals
+    peak = VALU_LANE_CYCLES / ops
+    achieved = evals / t_graph
+    roof = {"bound": "alu", "achieved": achieved / 1e9, "peak": peak / 1e9, "unit": "Geval/s",
+            "frac": achieved / peak, "traffic": None,
+            "kernel": "points_persistent_kernel<false> (graph replay incl. its counter reset)",
+            "kernel_ms": t_graph * 1e3, "evals_per_launch": int(evals),
+            "ops_per_eval": ops,
+            "peak_basis": "FP64 vector 3.93e13 lane-ops/s / ops per eval (exponential 40, Litim 10, "
+                          "weighted by this set mix)",
+            "valu_insts_per_eval_profile": POINT_VALU_PER_EVAL_PROFILE,
+            "valu_busy_est": achieved * POINT_VALU_PER_EVAL_PROFILE / VALU_LANE_CYCLES}
+    out = {"sets": len(sets), "integrals": n_int, "evals": evals,
+           "plain_evals_per_s": evals / t_plain, "persistent_evals_per_s": evals / t_pers,
+           "graph_evals_per_s": evals / t_graph, "graph_integrals_per_s": n_int / t_graph,
+           "graph_ms": t_graph * 1e3, "batched_over_plain": t_plain / t_graph,
+           "roofline": roof,
+           "autotuned": {"graph_ms": t_tuned * 1e3, "default_graph_ms": t_graph * 1e3,
+                         "tuned_choice": tuned_line, "results_bitwise_equal": tuned_same}}
+    log(f"uneven sets: plain {evals / t_plain:.3e}, persistent {evals / t_pers:.3e}, graph "
+        f"{evals / t_graph:.3e} evals/s (frac {achieved / peak:.2f} of {peak:.3e}); tuned graph "
+        f"{t_tuned * 1e3:.3f} ms vs {t_graph * 1e3:.3f} ms, same bits {tuned_same}")
+    return out, ds
+
+
+def secondary(ctx, frg, workloads, torch, checks):
+    """Figures for the other workloads, measured after the timed region.
+    `checks` receives GPU results that the oracle leg compares."""
+    sec = {}
+    sec["uneven_sets_seed0"], ds = uneven_sets_figures(ctx, frg, workloads, torch)
+    checks["uneven_seed0"] = [d["out"].cpu().numpy() for d in ds]
+    sets = workloads.uneven_sets(seed=0)
+    evals = sum(s.n_evals for s in sets)
     n_int = sum(s.p.size for s in sets)
-    t_plain = timed(lambda: frg.frg_integrate(ctx, ds, flags=frg.FRG_PLAIN), torch)
-    t_pers = timed(lambda: frg.frg_integrate(ctx, ds, flags=frg.FRG_PERSISTENT), torch, reps=20)
-    t_graph = timed(lambda: frg.frg_integrate(ctx, ds, flags=frg.FRG_PERSISTENT | frg.FRG_GRAPH),
-                    torch, reps=20)
-    sec["uneven_sets_seed0"] = {
-        "sets": len(sets), "integrals": n_int, "evals": evals,
-        "plain_evals_per_s": evals / t_plain, "persistent_evals_per_s": evals / t_pers,
-        "graph_evals_per_s": evals / t_graph, "graph_integrals_per_s": n_int / t_graph,
-        "batched_over_plain": t_plain / t_graph}
-    log(f"uneven sets: plain {evals / t_plain:.3e}, graph {evals / t_graph:.3e} evals/s")
+    t_plain = evals / sec["uneven_sets_seed0"]["plain_evals_per_s"]
+    t_graph = evals / sec["uneven_sets_seed0"]["graph_evals_per_s"]
     # plain d = 4 grid: latency of one small call
     w = workloads.plain_d4()
     q = w.quad
@@ -297,6 +467,7 @@ def secondary(ctx, frg, workloads, torch):
     t1 = timed(lambda: frg.frg_integrate_grid(ctx, quad, P, M, out), torch, reps=50)
     sec["plain_d4"] = {"ms_per_call": t1 * 1e3, "evals_per_s": w.n_evals / t1,
                        "integrals_per_s": w.n_integrals / t1}
+    checks["plain_d4"] = out.cpu().numpy()
     # compensated FP32 on the point kernel (uneven sets): the regulator is
     # evaluated per term there, which is where FP32 pays
     ds32 = []
@@ -322,9 +493,14 @@ def secondary(ctx, frg, workloads, torch):
     log(f"fp32c uneven: plain {evals / t32:.3e}, graph {evals / t32g:.3e} evals/s "
         f"(fp64 plain {evals / t_plain:.3e}, graph {evals / t_graph:.3e}), "
         f"fp32 share {share:.2f}, max dev {dev_max:.2e}")
-    # compensated FP32 on grids (precision workload: half the masses near the
-    # pole); deviation measured against the FP64 kernel's result
+    # compensated FP32 on grids: the precision workload (the plain d = 4 shape,
+    # half of the masses near the pole; three seeds, kept for the oracle
+    # leg's per-result histogram) and the scale-up grid; deviation from the
+    # FP64 kernel's result
+    checks["precision_d4"] = []
     for name, wk in (("fp32c_precision_d4_seed0", workloads.precision_d4(0)),
+                     ("fp32c_precision_d4_seed1", workloads.precision_d4(1)),
+                     ("fp32c_precision_d4_seed2", workloads.precision_d4(2)),
                      ("fp32c_scaleup_d3", workloads.scaleup_d3())):
         q = wk.quad
         P = torch.as_tensor(wk.p, device="cuda")
@@ -339,6 +515,11 @@ def secondary(ctx, frg, workloads, torch):
         t64 = timed(lambda: frg.frg_integrate_grid(ctx, q64, P, M, o64), torch, reps)
         t32 = timed(lambda: frg.frg_integrate_grid(ctx, q32, P, M, o32, err, used), torch, reps)
         rel = ((o32 - o64).abs() / o64).max().item()
+        if name.startswith("fp32c_precision"):
+            checks["precision_d4"].append((wk, o32.cpu().numpy(), err.cpu().numpy(),
+                                           used.cpu().numpy()))
+            if not name.endswith("seed0"):
+                continue
         sec[name] = {"evals": wk.n_evals, "fp32c_evals_per_s": wk.n_evals / t32,
                      "fp64_evals_per_s": wk.n_evals / t64,
                      "fp32_share": 1.0 - used.double().mean().item(),
@@ -350,6 +531,7 @@ def secondary(ctx, frg, workloads, torch):
     sec["momentum_flow"] = momentum_flow(ctx, frg, workloads, torch)
     sec["fv_lpa"] = fv_lpa(ctx, frg, workloads, torch)
     sec["serving"] = serving(frg, workloads)
+    sec["serving_500"] = serving(frg, workloads, n_warm=30, n_timed=300, seed=1, rate=500.0)
     return sec
 
 
@@ -446,12 +628,13 @@ def tabulated(ctx, frg, workloads, torch, which=(4096, 1 << 20), reps=None, step
     return res
 
 
-def serving(frg, workloads, n_warm=50, n_timed=1000, seed=0):
-    """Poisson stream (50/s) of LPA O(N) flow requests through frg_submit /
+def serving(frg, workloads, n_warm=50, n_timed=1000, seed=0, rate=50.0):
+    """Poisson stream of LPA O(N) flow requests through frg_submit /
     frg_poll: n_warm requests, then n_timed whose latencies (done - submit on
-    the library's monotonic clock) are reported."""
+    the library's monotonic clock) are reported, separately for flows that
+    reach t = -9 and flows that stop at the propagator pole."""
     n_req = n_warm + n_timed
-    reqs = workloads.lpa_requests(seed=seed, n=n_req)
+    reqs = workloads.lpa_requests(seed=seed, n=n_req, rate=rate)
     ctx = frg.frg_create(0)
     outs, keep, tickets, res = [], [], [], {}
     t0 = time.perf_counter()
@@ -481,18 +664,30 @@ def serving(frg, workloads, n_warm=50, n_timed=1000, seed=0):
     span = max(x.done_s for x in rs) - min(x.submit_s for x in rs)
     done, launches, mean_batch = frg.frg_server_stats(ctx)
     frg.frg_destroy(ctx)
-    ok = sum(x.status == frg.FRG_OK for x in rs)
-    pole = sum(x.status == frg.FRG_E_DOMAIN for x in rs)
-    out = {"requests": n_timed, "warmup_requests": n_warm, "rate_per_s": 50, "grid": "128..1024",
-           "N": "1,2,4", "completed_to_t_end": ok, "stopped_at_pole": pole,
+    okm = np.array([x.status == frg.FRG_OK for x in rs])
+    polem = np.array([x.status == frg.FRG_E_DOMAIN for x in rs])
+
+    def pct(mask):
+        if not mask.any():
+            return None
+        return {"flows": int(mask.sum()), "p50_ms": float(np.percentile(lat[mask], 50) * 1e3),
+                "p99_ms": float(np.percentile(lat[mask], 99) * 1e3),
+                "mean_steps": float(np.mean([x.steps for x, m in zip(rs, mask) if m]))}
+
+    r0 = reqs[0]
+    out = {"requests": n_timed, "warmup_requests": n_warm, "rate_per_s": rate,
+           "grid": "128..1024", "N": "1,2,4", "rtol": r0.rtol, "atol": r0.atol,
+           "completed_to_t_end": int(okm.sum()), "stopped_at_pole": int(polem.sum()),
            "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
            "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
+           "to_t_end": pct(okm), "at_pole": pct(polem),
            "mean_latency_ms": float(lat.mean() * 1e3), "flows_per_s": n_timed / span,
            "wall_s": wall,
            "rhs_calls_total": int(sum(x.rhs_calls for x in rs)),
            "launches": launches, "mean_flows_per_launch": mean_batch}
-    log(f"serving: p50 {out['p50_latency_ms']:.1f} ms, p99 {out['p99_latency_ms']:.1f} ms, "
-        f"{ok} to t_end, {pole} at the pole, mean batch {mean_batch:.2f}")
+    log(f"serving at {rate:.0f}/s: p50 {out['p50_latency_ms']:.1f} ms, p99 "
+        f"{out['p99_latency_ms']:.1f} ms, {int(okm.sum())} to t_end, {int(polem.sum())} at the "
+        f"pole, mean batch {mean_batch:.2f}")
     return out
 
 

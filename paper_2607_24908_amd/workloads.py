@@ -44,7 +44,8 @@ regulator):
 * ``lpa_requests`` -- a Poisson stream (rate 50/s) of LPA O(N) flow requests:
   N in {1, 2, 4}, d = 3, exponential regulator, grid of 128..1024 points on
   rho in [0, 0.5], initial U = lambda/8 (rho - rho0)^2 with lambda ~ U(1, 20),
-  rho0 ~ U(0, 0.2), RG time 0 -> -9, 64 radial nodes.
+  rho0 ~ U(0, 0.2), RG time 0 -> -9, 64 radial nodes; stepper tolerances
+  rtol 1e-8, atol 1e-10.
 
 All random draws use numpy's PCG64 with an explicit seed.
 """
@@ -301,8 +302,8 @@ class FlowRequest:
     q_max_over_k: float = 6.0
     Lambda: float = 1.0
     arrival_s: float = 0.0
-    rtol: float = 1e-6
-    atol: float = 1e-9
+    rtol: float = 1e-8
+    atol: float = 1e-10
 
     def rho(self) -> np.ndarray:
         return np.linspace(0.0, self.rho_max, self.n_grid)
