@@ -57,7 +57,7 @@ OPS_PER_EVAL = {0: 40.0, 1: 10.0}
 # FP64 vector instructions per evaluation of points_persistent_kernel on the
 # uneven sets, from SQ_INSTS_VALU x 64 / evaluations
 # (profiles/points_persistent_kernel_uneven_sets.md).
-POINT_VALU_PER_EVAL_PROFILE = 20.4
+POINT_VALU_PER_EVAL_PROFILE = 21.0
 
 
 def parse():
