@@ -60,6 +60,7 @@ def lib():
                                            ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_long, ctypes.c_long, ctypes.c_double, dp,
                                            ctypes.c_long, dp, dp, ctypes.c_int]
+        L.oracle_integrate_tab_bound.argtypes = L.oracle_integrate_tab.argtypes
         L.oracle_lpa_rhs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                      ctypes.c_double, ctypes.c_double, ctypes.c_long,
                                      ctypes.c_double, dp, dp, dp]
@@ -159,6 +160,22 @@ def integrate_tab(d, reg, k, q_max, n_r, n_a, G, s_max, p, threads=1, allow_doma
                                     _ptr(out), int(threads))
     if rc == E_INVAL or (rc == E_DOMAIN and not allow_domain):
         raise ValueError(f"oracle_integrate_tab rc={rc}")
+    return out
+
+
+def integrate_tab_bound(d, reg, k, q_max, n_r, n_a, G, s_max, p, threads=1):
+    """Relative deviation that the evaluation coordinate can cause in each
+    result of integrate_tab between two implementations whose rules agree to
+    about an ulp (see oracle_integrate_tab_bound): the tolerance of GPU
+    comparisons on rough tables, not a pinned value."""
+    G = np.ascontiguousarray(np.asarray(G, dtype=np.float64))
+    p = _f64(p).ravel()
+    out = np.empty((p.size, G.shape[0]))
+    rc = lib().oracle_integrate_tab_bound(int(d), int(reg), float(k), float(q_max), int(n_r),
+                                          int(n_a), G.shape[0], G.shape[1], float(s_max), _ptr(G),
+                                          p.size, _ptr(p), _ptr(out), int(threads))
+    if rc == E_INVAL:
+        raise ValueError(f"oracle_integrate_tab_bound rc={rc}")
     return out
 
 

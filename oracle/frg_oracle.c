@@ -343,6 +343,88 @@ int oracle_integrate_tab(int d, int reg, double k, double q_max, int n_r, int n_
   return domain ? OR_E_DOMAIN : OR_OK;
 }
 
+/* Sensitivity of a tabulated result to the evaluation coordinate (test
+ * infrastructure: the tolerance of GPU-vs-oracle comparisons on rough rows).
+ *
+ * Two evaluations of the tabulated diagram on independent Gauss-Legendre
+ * rules (nodes equal to about an ulp) and with different roundings in
+ * forming t = s/h see coordinates that differ by |dt| <= 16 u ((q + p)^2/h + 1)
+ * (u = 2^-53: the node differences |dq| <= 2u q and |d(1 + x)| <= 3u, three
+ * roundings in s and two in t, with room to spare).  The piecewise-linear
+ * G_r then moves by at most sigma(t) |dt| + 4u max(g_k, g_k+1), sigma(t) the
+ * largest |g_{j+1} - g_j| over the intervals j = k-1, k, k+1 (k = floor(t),
+ * intervals clamped to the table; 0 once t lies beyond the last node by more
+ * than |dt|).  Every term c_i mu_j G(q_i^2)^2 G(s_ij) is positive, so the
+ * relative deviation of a result is at most
+ *   B = sum_ij c_i mu_j [G_q^2 dG_s + 2 G_q G_s dG_q] / sum_ij c_i mu_j G_q^2 G_s
+ * plus the accumulation of roundings over the sum (taken as 1e-13).
+ * out[a * n_rows + r] = B for the result of oracle_integrate_tab at (a, r). */
+static double tab_dG(const double *g, long n_s, double h, double s, double qp2) {
+  const double u = 1.1102230246251565e-16;
+  const double t = s / h;
+  const double dt = 16.0 * u * (qp2 / h + 1.0);
+  const double last = (double)(n_s - 1);
+  double tc = t < last ? t : last;
+  long k = (long)floor(tc);
+  if (k > n_s - 2) k = n_s - 2;
+  double sig = 0.0;
+  if (t <= last + dt) {
+    for (long j = k - 1; j <= k + 1; ++j) {
+      if (j < 0 || j > n_s - 2) continue;
+      double dg = fabs(g[j + 1] - g[j]);
+      if (dg > sig) sig = dg;
+    }
+  }
+  double gm = g[k] > g[k + 1] ? g[k] : g[k + 1];
+  return sig * dt + 4.0 * u * gm;
+}
+
+int oracle_integrate_tab_bound(int d, int reg, double k, double q_max, int n_r, int n_a,
+                               long n_rows, long n_s, double s_max, const double *G, long n_p,
+                               const double *p, double *out, int n_threads) {
+  if (check_common(d, reg, k, q_max, n_r) || d < 3 || n_a < 1 || n_p < 0 || n_rows < 0)
+    return OR_E_INVAL;
+  if (n_s < 2 || !(s_max > 0.0)) return OR_E_INVAL;
+  if (n_p > 0 && n_rows > 0 && (!p || !G || !out)) return OR_E_INVAL;
+  double *q = malloc(sizeof(double) * n_r), *w = malloc(sizeof(double) * n_r);
+  double *x = malloc(sizeof(double) * n_a), *v = malloc(sizeof(double) * n_a);
+  double *mu = malloc(sizeof(double) * n_a);
+  radial_rule(reg, k, q_max, n_r, q, w);
+  oracle_gauss_legendre(n_a, x, v);
+  for (int j = 0; j < n_a; ++j) mu[j] = v[j] * angular_factor(d, x[j]);
+  const double k2 = k * k;
+  const double h = s_max / (double)(n_s - 1);
+  if (n_threads < 1) n_threads = 1;
+#pragma omp parallel for collapse(2) schedule(dynamic, 8) num_threads(n_threads)
+  for (long a = 0; a < n_p; ++a) {
+    for (long r = 0; r < n_rows; ++r) {
+      const double *g = G + r * n_s;
+      if (!(p[a] >= 0.0)) {
+        out[a * n_rows + r] = NAN;
+        continue;
+      }
+      long double num = 0.0L, den = 0.0L;
+      for (int i = 0; i < n_r; ++i) {
+        double qi = q[i];
+        double Gq = interp_row(g, n_s, s_max, qi * qi);
+        double dGq = tab_dG(g, n_s, h, qi * qi, qi * qi);
+        double c = w[i] * ipow(qi, d - 1) * dtR(reg, k2, qi * qi);
+        double qp = qi + p[a];
+        for (int j = 0; j < n_a; ++j) {
+          double s = (qi - p[a]) * (qi - p[a]) + 2.0 * qi * p[a] * (1.0 + x[j]);
+          double Gs = interp_row(g, n_s, s_max, s);
+          double dGs = tab_dG(g, n_s, h, s, qp * qp);
+          num += (long double)(c * mu[j] * (Gq * Gq * dGs + 2.0 * Gq * Gs * dGq));
+          den += (long double)(c * mu[j] * Gq * Gq * Gs);
+        }
+      }
+      out[a * n_rows + r] = (double)(num / den) + 1e-13;
+    }
+  }
+  free(q); free(w); free(x); free(v); free(mu);
+  return OR_OK;
+}
+
 /* F_n(m2_e), radial only */
 int oracle_threshold(int d, int reg, double k, double q_max, int n_r, int n, long n_pts,
                      const double *m2, double *out) {

@@ -1,10 +1,14 @@
 """Tabulated-propagator variant (frg_integrate_tab) against the FP64 oracle.
 
-Bar: 1e-12 relative per result (smooth tables: the interpolation coordinate
-is formed with a different rounding on each side, which moves a result by
-about u times the relative slope of the row over its range).  The LDS-row
-and streamed-row forms of the kernel do the same arithmetic in the same
-order and must agree bit for bit."""
+Bar: 1e-12 relative per result on smooth tables; on rough tables the
+per-result bound of oracle.integrate_tab_bound.  A piecewise-linear row is
+sensitive to its evaluation coordinate t = s/h: the kernel and the oracle
+build their quadrature rules independently (nodes equal to about an ulp) and
+round t differently, so t differs by about u t and a result moves by up to
+u t |g_{k+1} - g_k| / G relative -- about 1e-10 for random rows of 2^20
+nodes, whatever the formula; the bound sums that sensitivity over the terms
+of each result.  The LDS-row and streamed-row forms of the kernel do the same
+arithmetic in the same order and must agree bit for bit."""
 import numpy as np
 import pytest
 
@@ -69,6 +73,27 @@ def test_tab_matches_oracle_and_forms_agree(ctx, d, reg, n_r, n_a):
     assert np.array_equal(streamed, got)
     values = run_tab(ctx, q, g, s_max, p, pairs=0)  # rows in LDS as values
     assert np.array_equal(values, got)
+
+
+@pytest.mark.parametrize("n_s,lds", [(4097, True), (4097, False), (1 << 20, False)])
+def test_tab_rough_rows_within_coordinate_bound(ctx, n_s, lds):
+    """Seeded random positive rows (two decades, no smoothness) in LDS and
+    streamed, including rows of 2^20 nodes: every result within its bound."""
+    print(f"[case] rough rows n_s={n_s} lds={lds}", flush=True)
+    rng = np.random.Generator(np.random.PCG64(n_s + lds))
+    n_rows = 6 if n_s < 100000 else 2
+    g = 10.0 ** rng.uniform(-1.0, 1.0, (n_rows, n_s))
+    s_max = 676.0
+    q = workloads.Quad(3, 0, 1.0, 6.0, 128, 32)
+    p = np.concatenate([[0.0, 1e-6], 10 ** rng.uniform(-3.0, np.log10(20.0), 22)])
+    got = run_tab(ctx, q, g, s_max, p, lds_nodes=6144 if lds else 2)
+    want = want_of(q, g, s_max, p)
+    bound = oracle.integrate_tab_bound(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a, g, s_max, p,
+                                       threads=8)
+    rel = np.abs(got - want) / want
+    print(f"max rel err {rel.max():.3e}, max bound {bound.max():.3e}, "
+          f"max err/bound {(rel / bound).max():.3f}")
+    assert np.all(rel <= bound)
 
 
 def test_tab_long_rows_sampled(ctx):

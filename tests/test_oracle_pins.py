@@ -755,3 +755,32 @@ def test_fvlpa_step_estimate_and_domain_stop():
     _, _, dead = oracle.fvlpa_rhs(3, 1, REG_EXP, 16, 1.0, 6.0, 1.5, 0.0, np.vstack([bad, u0]),
                                   allow_domain=True)
     assert list(dead) == [1, 0]
+
+
+@pytest.mark.parametrize("n_s", [4097, 65537])
+def test_tab_coordinate_bound_covers_ulp_perturbations(n_s):
+    """The per-result tolerance for rough tables (oracle.integrate_tab_bound)
+    covers the oracle's own response to ulp-level changes of the evaluation
+    coordinate: s_max and p moved by 4 ulp shift every t by about 4u t, the
+    kind of difference two implementations with ulp-close rules show."""
+    rng = np.random.default_rng(11)
+    g = 10.0 ** rng.uniform(-1.0, 1.0, (4, n_s))  # rough positive rows, two decades
+    s_max = 676.0
+    p = np.array([1e-3, 0.37, 2.0, 7.5])
+    args = (3, REG_EXP, 1.0, 6.0, 48, 12)
+    base = oracle.integrate_tab(*args, g, s_max, p)
+    bound = oracle.integrate_tab_bound(*args, g, s_max, p)
+    u = 2.0 ** -53
+    seen = 0.0
+    for sm, pp in ((s_max * (1 + 4 * u), p), (s_max * (1 - 4 * u), p),
+                   (s_max, p * (1 + 4 * u)), (s_max, p * (1 - 4 * u))):
+        moved = oracle.integrate_tab(*args, g, sm, pp)
+        rel = np.abs(moved - base) / base
+        assert np.all(rel <= bound), (rel / bound).max()
+        seen = max(seen, float((rel / bound).max()))
+    # the perturbation is visible and the bound not vacuous
+    assert seen > 1e-3
+    # smooth rows: the bound is the 1e-13 floor plus a few ulp
+    sg = np.linspace(0.0, s_max, n_s)
+    gs = (1.0 + 0.1 / (1.0 + sg))[None, :] / (sg[None, :] + np.array([0.1, 1.0, 4.0, 11.0])[:, None])
+    assert oracle.integrate_tab_bound(*args, gs, s_max, p).max() < 3e-13
