@@ -69,11 +69,11 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device-to-device copy of 1 GiB (PMC traffic calibration)")
-    ap.add_argument("--only", choices=["uneven64", "uneven32", "grid32", "tab4096", "tab1m", "pflow",
+    ap.add_argument("--only", choices=["uneven64", "uneven32", "tab4096", "tab1m", "pflow",
                                        "vertex", "fvlpa", "serving"],
                     default=None,
                     help="profiling aid: run only --steps persistent launches of the uneven sets "
-                         "(FP64 or FP32C), --steps FP32C scale-up grid calls, --steps momentum-flow "
+                         "(FP64 or FP32C), --steps momentum-flow "
                          "or finite-volume LPA solves or vertex-diagram calls, --steps calls "
                          "of the tabulated variant (rows of 4096 or 2^20 nodes), or --steps "
                          "served flow requests (after --warmup more), and print their timing")
@@ -102,32 +102,6 @@ def only_uneven(prec_name, steps, warmup):
     frg.frg_destroy(ctx)
     print(json.dumps({"only": prec_name, "steps": steps, "ms_per_launch": dt * 1e3,
                       "evals_per_s": evals / dt}), flush=True)
-
-
-def only_grid32(steps, warmup):
-    import torch
-    from paper_2607_24908_amd import frg, workloads
-    ctx = frg.frg_create(0)
-    w = workloads.scaleup_d3()
-    q = w.quad
-    quad = frg.make_quad(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a, frg.FRG_PREC_FP32C)
-    P = torch.as_tensor(w.p, device="cuda")
-    M = torch.as_tensor(w.m2, device="cuda")
-    out = torch.empty(w.n_integrals, dtype=torch.float64, device="cuda")
-    err = torch.empty_like(out)
-    used = torch.empty(w.n_integrals, dtype=torch.uint8, device="cuda")
-    for _ in range(warmup):
-        frg.frg_integrate_grid(ctx, quad, P, M, out, err, used)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        frg.frg_integrate_grid(ctx, quad, P, M, out, err, used)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    share = float(used.float().mean().item())
-    frg.frg_destroy(ctx)
-    print(json.dumps({"only": "grid32", "steps": steps, "ms_per_call": dt * 1e3,
-                      "evals_per_s": w.n_evals / dt, "fp64_share": share}), flush=True)
 
 
 def log(msg):
@@ -208,19 +182,33 @@ def oracle_checks(oracle, checks, workloads, cores):
                            "compared": int(ref.size)}
     if "uneven_seed0" in checks:
         worst, n = 0.0, 0
-        for s, got in zip(workloads.uneven_sets(seed=0), checks["uneven_seed0"]):
+        f32 = checks.get("fp32c_uneven_seed0")
+        w32, n32, above, bmax = 0.0, 0, 0, 0.0
+        for i, (s, got) in enumerate(zip(workloads.uneven_sets(seed=0), checks["uneven_seed0"])):
             q = s.quad
             ref = oracle.integrate(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a, s.p, s.m2, threads=cores)
             worst = max(worst, float(np.max(np.abs(got - ref) / ref)))
             n += ref.size
+            if f32:
+                o32, err, used = f32[i]
+                rel = np.abs(o32 - ref) / ref
+                w32 = max(w32, float(rel.max()))
+                sel = used == 0
+                n32 += int(sel.sum())
+                above += int(np.sum(rel[sel] > err[sel] + 1e-13))
+                bmax = max(bmax, float(err[sel].max()) if sel.any() else 0.0)
         out["uneven_sets_seed0"] = {"max_rel_err": worst, "compared": n}
+        if f32:
+            out["fp32c_uneven_sets_seed0"] = {
+                "max_rel_err": w32, "compared": n, "fp32_returned": n32,
+                "fp32_results_above_their_bound": above, "max_bound_returned": bmax, "tol": 1e-7}
     if checks.get("precision_d4"):
         edges = 10.0 ** np.arange(-17, -3)
         rels, ests, fp32 = [], [], []
         for wk, o32, err, used in checks["precision_d4"]:
             q = wk.quad
             ref = oracle.integrate_grid(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a, wk.p,
-                                        wk.m2).ravel()
+                                        wk.m2).ravel()  # the point order of np.repeat/np.tile
             rels.append(np.abs(o32 - ref) / ref)
             ests.append(err)
             fp32.append(used == 0)
@@ -230,7 +218,7 @@ def oracle_checks(oracle, checks, workloads, cores):
             "results": int(rel.size), "fp32_returned": int(f32.sum()),
             "max_rel_err": float(rel.max()),
             "max_rel_err_fp32_returned": float(rel[f32].max()) if f32.any() else None,
-            "fp32_results_above_their_estimate": int(np.sum(rel[f32] > est[f32])),
+            "fp32_results_above_their_bound": int(np.sum(rel[f32] > est[f32] + 1e-13)),
             "histogram_rel_err": {f"[1e{int(np.log10(a))},1e{int(np.log10(b))})": int(c)
                                   for a, b, c in zip(edges[:-1], edges[1:], counts)},
             "tol": 1e-7}
@@ -244,9 +232,6 @@ def main():
               "(integral sets and flows shard across GPUs with no exchange; see DESIGN.md)",
               file=sys.stderr)
         sys.exit(2)
-    if args.only == "grid32":
-        only_grid32(args.steps, args.warmup)
-        return
     if args.only in ("pflow", "vertex", "fvlpa"):
         import torch
         from paper_2607_24908_amd import frg, workloads
@@ -468,8 +453,8 @@ def secondary(ctx, frg, workloads, torch, checks):
     sec["plain_d4"] = {"ms_per_call": t1 * 1e3, "evals_per_s": w.n_evals / t1,
                        "integrals_per_s": w.n_integrals / t1}
     checks["plain_d4"] = out.cpu().numpy()
-    # compensated FP32 on the point kernel (uneven sets): the regulator is
-    # evaluated per term there, which is where FP32 pays
+    # compensated FP32 on the point kernel (uneven sets): the exponential
+    # of the regulator is evaluated per term there, which is what FP32 replaces
     ds32 = []
     for s, d in zip(sets, ds):
         q = s.quad
@@ -479,53 +464,59 @@ def secondary(ctx, frg, workloads, torch, checks):
                          used_fp64=torch.empty(d["out"].numel(), dtype=torch.uint8,
                                                device="cuda")))
     t32 = timed(lambda: frg.frg_integrate(ctx, ds32, flags=frg.FRG_PLAIN), torch)
-    t32g = timed(lambda: frg.frg_integrate(ctx, ds32, flags=frg.FRG_PERSISTENT | frg.FRG_GRAPH),
-                 torch, reps=20)
-    frg.frg_integrate(ctx, ds, flags=frg.FRG_PLAIN)
+    arr32 = frg.make_set_array(ds32)
+    st = torch.cuda.current_stream().cuda_stream
+    t32g = events_time(lambda: frg.frg_integrate_array(ctx, arr32, len(ds32),
+                                                       flags=frg.FRG_PERSISTENT | frg.FRG_GRAPH,
+                                                       stream=st), torch, reps=30)
     torch.cuda.synchronize()
-    dev_max = max(((a["out"] - b["out"]).abs() / b["out"]).max().item() for a, b in zip(ds32, ds))
-    share = sum((a["used_fp64"] == 0).sum().item() for a in ds32) / n_int
+    checks["fp32c_uneven_seed0"] = [(a["out"].cpu().numpy(), a["err_est"].cpu().numpy(),
+                                     a["used_fp64"].cpu().numpy()) for a in ds32]
+    exp_work = sum(s.n_evals for s in sets if s.quad.reg == workloads.REG_EXP)
+    work32 = sum(int((u == 0).sum()) * s.quad.n_r * s.quad.n_a
+                 for s, (_, _, u) in zip(sets, checks["fp32c_uneven_seed0"]))
+    n32 = sum(int((u == 0).sum()) for _, _, u in checks["fp32c_uneven_seed0"])
     sec["fp32c_uneven_sets_seed0"] = {
         "fp32c_plain_evals_per_s": evals / t32, "fp32c_graph_evals_per_s": evals / t32g,
         "fp32c_graph_integrals_per_s": n_int / t32g, "fp64_plain_evals_per_s": evals / t_plain,
-        "fp64_graph_evals_per_s": evals / t_graph, "fp32_share": share,
-        "max_rel_dev_vs_fp64": dev_max}
+        "fp64_graph_evals_per_s": evals / t_graph, "graph_speedup_vs_fp64": t_graph / t32g,
+        "fp32_returned": n32, "fp32_share_of_exp_work": work32 / exp_work,
+        "max_bound_returned": max(float(e[u == 0].max()) if (u == 0).any() else 0.0
+                                  for _, e, u in checks["fp32c_uneven_seed0"]),
+        "note": "Litim points and points whose bound exceeds 1e-7 are FP64; the oracle leg "
+                "compares every result"}
     log(f"fp32c uneven: plain {evals / t32:.3e}, graph {evals / t32g:.3e} evals/s "
         f"(fp64 plain {evals / t_plain:.3e}, graph {evals / t_graph:.3e}), "
-        f"fp32 share {share:.2f}, max dev {dev_max:.2e}")
-    # compensated FP32 on grids: the precision workload (the plain d = 4 shape,
-    # half of the masses near the pole; three seeds, kept for the oracle
-    # leg's per-result histogram) and the scale-up grid; deviation from the
-    # FP64 kernel's result
+        f"FP32 share of the exponential work {work32 / exp_work:.3f}")
+    # compensated FP32 on the precision workload (the plain d = 4 shape, half
+    # of the masses near the pole; three seeds) as point lists, kept for the
+    # oracle leg's per-result histogram
     checks["precision_d4"] = []
-    for name, wk in (("fp32c_precision_d4_seed0", workloads.precision_d4(0)),
-                     ("fp32c_precision_d4_seed1", workloads.precision_d4(1)),
-                     ("fp32c_precision_d4_seed2", workloads.precision_d4(2)),
-                     ("fp32c_scaleup_d3", workloads.scaleup_d3())):
+    for seed in (0, 1, 2):
+        wk = workloads.precision_d4(seed)
         q = wk.quad
-        P = torch.as_tensor(wk.p, device="cuda")
-        M = torch.as_tensor(wk.m2, device="cuda")
-        o64 = torch.empty(wk.n_integrals, dtype=torch.float64, device="cuda")
-        o32 = torch.empty_like(o64)
-        err = torch.empty_like(o64)
-        used = torch.empty(wk.n_integrals, dtype=torch.uint8, device="cuda")
-        q64 = frg.make_quad(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a, frg.FRG_PREC_FP64)
-        q32 = frg.make_quad(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a, frg.FRG_PREC_FP32C)
-        reps = 3 if wk.n_evals > 1e9 else 20
-        t64 = timed(lambda: frg.frg_integrate_grid(ctx, q64, P, M, o64), torch, reps)
-        t32 = timed(lambda: frg.frg_integrate_grid(ctx, q32, P, M, o32, err, used), torch, reps)
-        rel = ((o32 - o64).abs() / o64).max().item()
-        if name.startswith("fp32c_precision"):
-            checks["precision_d4"].append((wk, o32.cpu().numpy(), err.cpu().numpy(),
-                                           used.cpu().numpy()))
-            if not name.endswith("seed0"):
-                continue
-        sec[name] = {"evals": wk.n_evals, "fp32c_evals_per_s": wk.n_evals / t32,
-                     "fp64_evals_per_s": wk.n_evals / t64,
-                     "fp32_share": 1.0 - used.double().mean().item(),
-                     "max_rel_dev_vs_fp64": rel, "max_err_estimate": err.max().item()}
-        log(f"{name}: fp32c {wk.n_evals / t32:.3e} evals/s, fp64 {wk.n_evals / t64:.3e}, "
-            f"max dev {rel:.2e}")
+        P = torch.as_tensor(np.repeat(wk.p, wk.m2.size), device="cuda")
+        M = torch.as_tensor(np.tile(wk.m2, wk.p.size), device="cuda")
+        d32 = [dict(quad=frg.make_quad(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a,
+                                       frg.FRG_PREC_FP32C), p=P, m2=M,
+                    out=torch.empty(P.numel(), dtype=torch.float64, device="cuda"),
+                    err_est=torch.empty(P.numel(), dtype=torch.float64, device="cuda"),
+                    used_fp64=torch.empty(P.numel(), dtype=torch.uint8, device="cuda"))]
+        d64 = [dict(quad=frg.make_quad(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a), p=P, m2=M,
+                    out=torch.empty(P.numel(), dtype=torch.float64, device="cuda"))]
+        tp32 = timed(lambda: frg.frg_integrate(ctx, d32, flags=frg.FRG_PERSISTENT), torch, 20)
+        tp64 = timed(lambda: frg.frg_integrate(ctx, d64, flags=frg.FRG_PERSISTENT), torch, 20)
+        torch.cuda.synchronize()
+        used = d32[0]["used_fp64"].cpu().numpy()
+        checks["precision_d4"].append((wk, d32[0]["out"].cpu().numpy(),
+                                       d32[0]["err_est"].cpu().numpy(), used))
+        if seed == 0:
+            sec["fp32c_precision_d4_seed0_points"] = {
+                "evals": wk.n_evals, "fp32c_evals_per_s": wk.n_evals / tp32,
+                "fp64_evals_per_s": wk.n_evals / tp64, "fp32_returned": int((used == 0).sum()),
+                "results": int(used.size)}
+            log(f"precision_d4 points: fp32c {wk.n_evals / tp32:.3e} evals/s, "
+                f"fp64 {wk.n_evals / tp64:.3e}, FP32 {int((used == 0).sum())}/{used.size}")
     sec.update(tabulated(ctx, frg, workloads, torch))
     sec["vertex"] = vertex(ctx, frg, workloads, torch)
     sec["momentum_flow"] = momentum_flow(ctx, frg, workloads, torch)

@@ -56,11 +56,18 @@ extern "C" {
 #define FRG_REG_LITIM 1
 
 #define FRG_PREC_FP64 0   /* FP64 throughout                                   */
-#define FRG_PREC_FP32C 1  /* FP32 angular bulk with two-sum compensated sums;
-                             FP64 per-radial-node factors and cross-lane
-                             reduction; results whose error estimate exceeds
-                             the FP32 tolerance, and points near the pole, are
-                             recomputed in FP64                                */
+#define FRG_PREC_FP32C 1  /* relative error at most "fp32c_flag_ppb" (1e-7)
+                             per result, by a stated bound: point lists of
+                             the exponential regulator take e^{-y} from the
+                             FP32 hardware exponential (corrected to first
+                             order in FP64), everything else in FP64, with a
+                             deterministic per-result error bound; points
+                             whose bound exceeds the tolerance, points near
+                             the pole (m^2 + k^2)/k^2 < "fp32c_band_ppm" 1e-6,
+                             Litim points and tensor grids are evaluated in
+                             FP64 (an unpacked FP32 operation costs what an
+                             FP64 one does on this GPU, and the FP64 grid
+                             form runs on the matrix cores)                   */
 
 #define FRG_MEM_HOST 0
 #define FRG_MEM_DEVICE 1
@@ -108,9 +115,9 @@ typedef struct {
  *   P_d = Omega_{d-1}/(2 pi)^d,  Omega_n = 2 pi^{n/2}/Gamma(n/2),
  * the radial x angular Gauss-Legendre form of
  *   int d^dq/(2 pi)^d d_tR_k(q^2) G(q^2)^2 G(|q+p|^2).
- * p[e] >= 0.  err_est (optional, FP32C only) receives an estimate of the
- * relative error of out[e]; used_fp64 (optional, FP32C only) receives 1 where
- * the point was evaluated in FP64.  Arrays are contiguous float64 / uint8. */
+ * p[e] >= 0.  err_est (optional, FP32C only) receives a bound of the
+ * relative error of out[e] (1e-14 for results evaluated in FP64); used_fp64
+ * (optional, FP32C only) receives 1 where the point was evaluated in FP64.  Arrays are contiguous float64 / uint8. */
 typedef struct {
   frg_quad quad;
   int64_t n_ext;
@@ -406,8 +413,7 @@ int frg_server_stats(frg_ctx *ctx, int64_t *flows_done, int64_t *launches, doubl
 int frg_autotune(frg_ctx *ctx, int32_t mode, const char *cache_path);
 
 /* Set / read one default launch-shape knob: "grid_M" (4, 8, 16), "grid_W"
- * (1..8), "grid_MB" (1..64) of the FP64 tensor-grid kernel, "grid32_M" (4, 8),
- * "grid32_W" (1..8), "grid32_MB" (1..64) of the compensated-FP32 one,
+ * (1..8), "grid_MB" (1..64) of the FP64 tensor-grid kernel,
  * "grid_form" (0: per-momentum Horner coefficients of one rational function
  * per lane, radial node and group of up to 32 angular terms, radial factor
  * included, when the table fits in LDS, the default; 1: eight-term running
@@ -436,7 +442,7 @@ int frg_autotune(frg_ctx *ctx, int32_t mode, const char *cache_path);
  * CU, 1..16), "tab_sW" (1..4), "tab_spw" (1..64).  Setting a knob drops the
  * tuned choices so that it takes effect.  Two knobs route FRG_PREC_FP32C
  * points to FP64 and do change results (within the FP32 tolerance):
- * "fp32c_flag_ppb" (error-estimate threshold in units of 1e-9, default 100)
+ * "fp32c_flag_ppb" (error-bound threshold in units of 1e-9, default 100)
  * and "fp32c_band_ppm" (pole band on (m^2 + k^2)/k^2 in units of 1e-6,
  * default 10000). */
 int frg_tune_set(frg_ctx *ctx, const char *key, int32_t value);
@@ -495,6 +501,16 @@ int frg_gauss_legendre(int32_t n, double *x, double *w);
  * y = 745.2.  y and out: n float64 each (host memory; no GPU use).
  * FRG_E_INVAL for n < 0 or NULL arrays with n > 0. */
 int frg_expneg(int64_t n, const double *y, double *out);
+
+/* e^{-y} for n arguments (y >= 0) on the GPU, by the operations the
+ * FRG_PREC_FP32C point path uses: the FP32 hardware exp2 of
+ * fl32(-y log2 e), corrected to first order by the FP64 residual
+ * -y - fl32(-y log2 e) ln 2.  Its relative error (below 1.2e-7 where e^{-y}
+ * is an FP32 normal, y < 87.3; absolute error below 2^-126 beyond) is the
+ * premise of that path's error bound.  y and out: n float64 each in device
+ * memory; asynchronous on hip_stream.  FRG_E_INVAL for a NULL ctx, n < 0 or
+ * NULL arrays with n > 0. */
+int frg_expneg_fp32c(frg_ctx *ctx, int64_t n, const double *y, double *out, void *hip_stream);
 
 /* Bytes of device memory one flow of this shape takes in the server's staging
  * buffer during a batched call (what the server's HBM admission charges). */

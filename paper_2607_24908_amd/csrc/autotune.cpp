@@ -206,9 +206,6 @@ static int *knob(frg_ctx *ctx, const char *key) {
   if (!std::strcmp(key, "grid_M")) return &t.grid.M;
   if (!std::strcmp(key, "grid_W")) return &t.grid.W;
   if (!std::strcmp(key, "grid_MB")) return &t.grid.MB;
-  if (!std::strcmp(key, "grid32_M")) return &t.grid32.M;
-  if (!std::strcmp(key, "grid32_W")) return &t.grid32.W;
-  if (!std::strcmp(key, "grid32_MB")) return &t.grid32.MB;
   if (!std::strcmp(key, "grid_lds_rows")) return &t.grid_lds_rows;
   if (!std::strcmp(key, "grid_form")) return &t.grid_form;
   if (!std::strcmp(key, "grid_mfma")) return &t.grid_mfma;
@@ -234,9 +231,7 @@ static int *knob(frg_ctx *ctx, const char *key) {
 static bool knob_ok(const char *key, int v) {
   if (!std::strcmp(key, "grid_M")) return v == 4 || v == 8 || v == 16;
   if (!std::strcmp(key, "grid_W")) return v >= 1 && v <= 8;
-  if (!std::strcmp(key, "grid_MB") || !std::strcmp(key, "grid32_MB")) return v >= 1 && v <= 64;
-  if (!std::strcmp(key, "grid32_M")) return v == 4 || v == 8;
-  if (!std::strcmp(key, "grid32_W")) return v >= 1 && v <= 8;
+  if (!std::strcmp(key, "grid_MB")) return v >= 1 && v <= 64;
   if (!std::strcmp(key, "grid_lds_rows")) return v >= 8 && v <= 96;
   if (!std::strcmp(key, "grid_form")) return v >= 0 && v <= 3;
   if (!std::strcmp(key, "grid_mfma") || !std::strcmp(key, "fv_persistent") ||

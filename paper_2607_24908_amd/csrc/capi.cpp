@@ -163,32 +163,6 @@ int Ctx::quad_table(const frg_quad &q, const double **dev, QuadTable *host_copy,
   return FRG_OK;
 }
 
-int Ctx::grid32_table(const frg_quad &q, int J, const double **dev, Grid32Table *host_copy) {
-  const double *tab;
-  int rc = quad_table(q, &tab, nullptr);
-  if (rc) return rc;
-  auto key = std::make_tuple(q.d, q.reg, dbits(q.k), dbits(q.q_max), q.n_radial, q.n_angular);
-  QEntry &ent = qtabs.at(key);
-  if (!ent.buf32) {
-    Grid32Table t = build_grid32_table(ent.host, J);
-    const int na = q.n_angular;
-    std::vector<char> blob(2 * na * sizeof(double) + na * sizeof(float));
-    std::memcpy(blob.data(), t.gam.data(), na * sizeof(double));
-    std::memcpy(blob.data() + na * sizeof(double), t.sig.data(), na * sizeof(double));
-    std::memcpy(blob.data() + 2 * na * sizeof(double), t.rho.data(), na * sizeof(float));
-    auto buf = std::make_unique<DevBuf>();
-    rc = buf->reserve(blob.size());
-    if (rc) return rc;
-    hipError_t e = hipMemcpy(buf->ptr, blob.data(), blob.size(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "upload FP32 grid table");
-    ent.buf32 = std::move(buf);
-    ent.host32 = std::move(t);
-  }
-  *dev = (const double *)ent.buf32->ptr;
-  if (host_copy) *host_copy = ent.host32;
-  return FRG_OK;
-}
-
 int Ctx::lpa_table(int d, int reg, int n_r, double qmk, const double **dev, double *Cd) {
   auto key = std::make_tuple(d, reg, n_r, dbits(qmk));
   auto it = ltabs.find(key);
@@ -303,8 +277,6 @@ int Ctx::integrate_device(const frg_set *sets, int n_sets, int flags, hipStream_
     if (rc) return rc;
   }
   if (!(flags & FRG_PERSISTENT)) {
-    for (int i = 0; i < n_sets; ++i)
-      if (sd[i].prec == FRG_PREC_FP32C) return integrate_fp32c_sets(sd, flags, st);
     for (int i = 0; i < n_sets; ++i) {
       if (sd[i].n_ext == 0) continue;
       int e = launch_points_plain(sd[i], plain_tile_for(sd[i], st), d_flag, st);
@@ -366,13 +338,11 @@ bool any_fp32c(const std::vector<SetDev> &sd) {
 }
 
 // LDS bytes the persistent kernel needs for the largest tables of the batch
-// (angular pairs and packed table; FP32C sets add their FP32 angular tables;
-// the launch adds the exponential table).
+// (angular pairs and packed table; the launch adds the exponential table).
 int max_table_bytes(const std::vector<SetDev> &sd) {
   size_t m = 0;
   for (auto &s : sd) {
-    size_t b = sizeof(double) * (2 * s.n_a + table_doubles(s.n_r, s.n_a));
-    if (s.prec == FRG_PREC_FP32C) b += sizeof(float) * 3 * s.n_a;
+    const size_t b = sizeof(double) * (2 * s.n_a + table_doubles(s.n_r, s.n_a));
     m = std::max(m, b);
   }
   return (int)m;
@@ -547,9 +517,14 @@ int Ctx::integrate_host(const frg_set *sets, int n_sets, int flags) {
 }
 
 // ---------------------------------------------------------------- grid --
-int Ctx::grid_device(const frg_quad &q, int64_t n_p, const double *p, int64_t n_m,
+// FRG_PREC_FP32C grids run the FP64 grid kernel and mark every result as
+// FP64 (err 1e-14, used64 1): on this GPU an unpacked FP32 operation issues at
+// the FP64 rate, and the FP64 grid form runs its power sums on the matrix
+// cores, so no FP32 form of the grid is faster.
+int Ctx::grid_device(const frg_quad &q_in, int64_t n_p, const double *p, int64_t n_m,
                      const double *m2, double *out, double *err, uint8_t *used, hipStream_t st) {
-  if (q.prec == FRG_PREC_FP32C) return grid_fp32c(q, n_p, p, n_m, m2, out, err, used, st);
+  frg_quad q = q_in;
+  q.prec = FRG_PREC_FP64;
   const double *tab;
   QuadTable h;
   int rc = quad_table(q, &tab, &h);
@@ -558,8 +533,6 @@ int Ctx::grid_device(const frg_quad &q, int64_t n_p, const double *p, int64_t n_
   g.p = p;
   g.m2 = m2;
   g.out = out;
-  g.err = err;
-  g.used64 = used;
   g.tab = tab;
   g.flag = d_flag;
   g.k2 = h.k2;
@@ -577,29 +550,31 @@ int Ctx::grid_device(const frg_quad &q, int64_t n_p, const double *p, int64_t n_
   g.form = tune.grid_form;
   if (grid_lds_bytes(g) > 64 * 1024) return fail(FRG_E_INVAL, "grid tables exceed 64 KiB of LDS");
   const GridCfg cfg = grid_cfg(q, g, st);
-  return grid_launch(g, q.reg, cfg, st);
+  rc = grid_launch(g, q.reg, cfg, st);
+  if (rc || q_in.prec != FRG_PREC_FP32C) return rc;
+  const int e = launch_fp64_marks(err, used, n_p * n_m, st);
+  if (e) return hip_fail((hipError_t)e, "fp64_marks_kernel launch");
+  return FRG_OK;
 }
 
-int Ctx::grid_launch(GridArgs g, int reg, const GridCfg &cfg_in, hipStream_t st, int kind) {
-  const bool resident = kind == 1 ? true : grid_resident(g);
+int Ctx::grid_launch(GridArgs g, int reg, const GridCfg &cfg_in, hipStream_t st) {
+  const bool resident = grid_resident(g);
   GridCfg cfg = cfg_in;
-  if (kind == 1 && cfg.M > 8) cfg.M = 8;  // FP32C kernel: at most 8 masses per wave
   // coefficient form: tiles of 16 masses on the matrix cores, or at most 8
   // masses per wave on the vector units
-  if (kind != 1 && grid_uses_coef(g)) cfg.M = tune.grid_mfma ? 16 : std::min(cfg.M, 8);
+  if (grid_uses_coef(g)) cfg.M = tune.grid_mfma ? 16 : std::min(cfg.M, 8);
   const int64_t per_wg_min = (int64_t)cfg.M * cfg.W;
   // mass blocks per wave: fewer workgroups per momentum, but keep at least
   // ~4 workgroups per CU in flight
   int mbk = resident ? std::max(1, cfg.MB) : 1;
   while (mbk > 1 && g.n_p * ((g.n_m + per_wg_min * mbk - 1) / (per_wg_min * mbk)) < 4LL * n_cu)
     mbk /= 2;
-  if (kind != 1 && grid_uses_coef(g))
+  if (grid_uses_coef(g))
     while (mbk > 1 && grid_coef_stage_bytes(mbk, cfg.W, cfg.M) > kGridCoefStageMax) mbk /= 2;
   g.mblocks = mbk;
   g.n_mb = (int)((g.n_m + per_wg_min * mbk - 1) / (per_wg_min * mbk));
-  const int e = kind == 1 ? launch_grid32(g, reg, cfg.M, cfg.W, st)
-                          : launch_grid(g, reg, cfg.M, cfg.W, st, kind == 2);
-  if (e) return hip_fail((hipError_t)e, kind == 1 ? "grid32_kernel launch" : "grid_kernel launch");
+  const int e = launch_grid(g, reg, cfg.M, cfg.W, st);
+  if (e) return hip_fail((hipError_t)e, "grid_kernel launch");
   return FRG_OK;
 }
 
@@ -672,101 +647,6 @@ int Ctx::tab_launch(TabArgs a, int reg, hipStream_t st) {
   if (rc) return rc;
   int e = launch_tab(a, reg, W, lds_rows, sblocks, st);
   if (e) return hip_fail((hipError_t)e, "tab_kernel launch");
-  return FRG_OK;
-}
-
-// --------------------------------------------------------------- FP32C --
-// Sets with FRG_PREC_FP32C run the compensated-FP32 kernel (one launch per
-// set); FP64 sets of the same call take the FP64 paths.
-int Ctx::integrate_fp32c_sets(const std::vector<SetDev> &sd, int flags, hipStream_t st) {
-  std::vector<SetDev> f64;
-  for (const SetDev &s : sd) {
-    if (s.prec != FRG_PREC_FP32C) {
-      f64.push_back(s);
-      continue;
-    }
-    if (s.n_ext == 0) continue;
-    int e = launch_fp32c(s, tune.plain_tile, 0, d_flag, st);
-    if (e) return hip_fail((hipError_t)e, "fp32c_kernel launch");
-  }
-  if (f64.empty()) return FRG_OK;
-  if (flags & FRG_PERSISTENT) return persistent_eager(f64, persist_cfg(f64, FRG_PREC_FP64, st), st);
-  for (const SetDev &s : f64) {
-    if (s.n_ext == 0) continue;
-    int e = launch_points_plain(s, plain_tile_for(s, st), d_flag, st);
-    if (e) return hip_fail((hipError_t)e, "points_plain_kernel launch");
-  }
-  return FRG_OK;
-}
-
-int Ctx::grid_fp32c(const frg_quad &q, int64_t n_p, const double *p, int64_t n_m,
-                    const double *m2, double *out, double *err, uint8_t *used, hipStream_t st) {
-  // Tensor-grid kernel (exponential regulator) when the whole table of one
-  // momentum fits in LDS.  Litim grids take the point-list kernel, which sums
-  // the flat region s <= k^2 (identical denominators, hence identical FP32
-  // roundings in every radial row) in FP64.
-  const double *tab;
-  QuadTable h;
-  int rc = quad_table(q, &tab, &h);
-  if (rc) return rc;
-  GridArgs g{};
-  g.p = p;
-  g.m2 = m2;
-  g.out = out;
-  g.err = err;
-  g.used64 = used;
-  g.tab = tab;
-  g.flag = d_flag;
-  g.k2 = h.k2;
-  g.inv_k2 = h.inv_k2;
-  g.pref = h.pref;
-  g.q_top = h.q_top;
-  g.rmu_max = h.rmu_max;
-  set_fold_scale(g, h);
-  g.n_p = n_p;
-  g.n_m = n_m;
-  g.n_r = q.n_radial;
-  g.n_a = q.n_angular;
-  lane_split(g.n_r, g.n_a, &g.R, &g.J, &g.T, &g.U);
-  g.chunk = g.T * g.U;
-  g.form = tune.grid_form;
-  if (q.reg == FRG_REG_EXP && g.T * g.U <= std::max(8, tune.grid_lds_rows) &&
-      grid32_lds_bytes(g) <= 64 * 1024 && grid_resident(g)) {
-    Grid32Table t32;
-    rc = grid32_table(q, g.J, &g.tab32, &t32);
-    if (rc) return rc;
-    g.f32_band = tune.fp32c_band_ppm * 1e-6;
-    g.f32_flag = tune.fp32c_flag_ppb * 1e-9;
-    g.f32_erho = t32.erho;
-    g.f32_rmin = t32.rmin;
-    g.f32_rmax = t32.rmax;
-    // the FP64 redo pass reads which points it owns from used64: the
-    // caller's array, else a scratch array of the context
-    if (!used) {
-      rc = flags8.reserve((size_t)n_p * n_m);
-      if (rc) return rc;
-      g.used64 = (uint8_t *)flags8.ptr;
-    }
-    GridCfg cfg = tune.grid32;
-    if (cfg.M > 8) cfg.M = 8;  // FP32 kernel: two accumulators per mass
-    rc = grid_launch(g, q.reg, cfg, st, 1);
-    if (rc) return rc;
-    return grid_launch(g, q.reg, tune.grid, st, 2);
-  }
-  // Otherwise the point-list FP32C kernel over the (p, m^2) pairs.
-  frg_set fs{};
-  fs.quad = q;
-  fs.n_ext = n_p * n_m;
-  fs.p = p;
-  fs.m2 = m2;
-  fs.out = out;
-  fs.err_est = err;
-  fs.used_fp64 = used;
-  SetDev s;
-  rc = make_setdev(fs, &s);
-  if (rc) return rc;
-  int e = launch_fp32c(s, tune.plain_tile, n_m, d_flag, st);
-  if (e) return hip_fail((hipError_t)e, "fp32c_kernel launch");
   return FRG_OK;
 }
 
@@ -1117,6 +997,17 @@ int frg_gauss_legendre(int32_t n, double *x, double *w) {
 int frg_expneg(int64_t n, const double *y, double *out) {
   if (n < 0 || (n > 0 && (!y || !out))) return fail(FRG_E_INVAL, "bad arguments");
   for (int64_t i = 0; i < n; ++i) out[i] = exp_neg(y[i], kExp2Tab64);
+  return FRG_OK;
+}
+
+int frg_expneg_fp32c(frg_ctx *ctx, int64_t n, const double *y, double *out, void *hip_stream) {
+  if (!ctx) return fail(FRG_E_INVAL, "ctx is NULL");
+  if (n < 0 || (n > 0 && (!y || !out))) return fail(FRG_E_INVAL, "bad arguments");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  hipSetDevice(ctx->device);
+  clear_error();
+  const int e = launch_expneg_fp32c(y, out, n, hip_stream);
+  if (e) return hip_fail((hipError_t)e, "expneg_fp32c_kernel launch");
   return FRG_OK;
 }
 

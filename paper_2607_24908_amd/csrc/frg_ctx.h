@@ -73,7 +73,6 @@ using ShapeKey = std::tuple<int, int, int, int>;  // (regulator, n_r, n_a, preci
 
 struct Tune {
   GridCfg grid;
-  GridCfg grid32{4, 8, 16};  // compensated-FP32 grid kernel (M <= 8)
   int plain_tile = 8;
   int tab_W = 4;           // tabulated variant: waves per workgroup
   int tab_pw = 16;         // tabulated variant: momenta per wave
@@ -90,7 +89,7 @@ struct Tune {
   int pflow_fused = 1;     // momentum flow, rows in LDS: 1 one launch per stage; 0 diagram + stage launches
   int fv_persistent = 1;   // finite-volume solves: 1 one workgroup per flow, state in LDS; 0 launches per stage
   int server_zero_copy = 1;  // flow server: 1 kernel reads/writes the pinned batch buffer; 0 two copies
-  int fp32c_flag_ppb = 100;    // FP32C: FP64 redo above this error estimate (1e-9 units)
+  int fp32c_flag_ppb = 100;    // FP32C: FP64 above this error bound (1e-9 units)
   int fp32c_band_ppm = 10000;  // FP32C: FP64 below this delta/k^2 (1e-6 units)
   int mode = 0;            // 0: defaults and cached choices, 1: tune new keys
   std::string cache_path;
@@ -145,7 +144,6 @@ struct Context {
   int use_stream_flag(hipStream_t st);
   frg::DescRing ring;
   frg::DevBuf stage_in, stage_out;
-  frg::DevBuf flags8;  // per-point FP64-redo marks of FP32C grids without used_fp64
   frg::Tune tune;
   uint64_t tune_gen = 1;  // advanced whenever a knob or a tuned choice changes
   uint64_t hbm_budget = 0;
@@ -153,8 +151,6 @@ struct Context {
   struct QEntry {
     std::unique_ptr<frg::DevBuf> buf;
     frg::QuadTable host;
-    std::unique_ptr<frg::DevBuf> buf32;  // Grid32Table on the device (lazy)
-    frg::Grid32Table host32;
   };
   struct LEntry {
     std::unique_ptr<frg::DevBuf> buf;
@@ -170,7 +166,6 @@ struct Context {
   virtual ~Context();
   int quad_table(const frg_quad &q, const double **dev, frg::QuadTable *host_copy,
                  frg::QuadTable **host_ref = nullptr);
-  int grid32_table(const frg_quad &q, int J, const double **dev, frg::Grid32Table *host_copy);
   int lpa_table(int d, int reg, int n_r, double qmk, const double **dev, double *Cd);
   int make_setdev(const frg_set &s, frg::SetDev *out);
   void fill_setdev(const frg_set &s, const frg::QuadTable &h, const double *tab, frg::SetDev *out);
@@ -189,7 +184,6 @@ struct Context {
   int integrate_host(const frg_set *sets, int n_sets, int flags);
   int persistent(const std::vector<frg::SetDev> &sd, const frg_set *sets, int n_sets, int flags,
                  hipStream_t st);
-  int integrate_fp32c_sets(const std::vector<frg::SetDev> &sd, int flags, hipStream_t st);
   int tab_device(const frg_quad &q, const frg_gtab &tab, int64_t n_p, const double *p, double *out,
                  hipStream_t st);
   // Launch shape of the table kernel for a (fills R, J, T, U, pairs, pw and
@@ -203,8 +197,6 @@ struct Context {
                    double *dsdt, double t_rhs, int *flag, hipStream_t st);
   int grid_device(const frg_quad &q, int64_t n_p, const double *p, int64_t n_m, const double *m2,
                   double *out, double *err, uint8_t *used, hipStream_t st);
-  int grid_fp32c(const frg_quad &q, int64_t n_p, const double *p, int64_t n_m, const double *m2,
-                 double *out, double *err, uint8_t *used, hipStream_t st);
   int lpa_jobs(int n, const frg_lpa *lpa, const double *t, const double *const *U,
                double *const *dUdt, double *const *jac, int *flags_dev, hipStream_t st);
   // Descriptors of n LPA jobs (device pointers given) and their grid offsets
@@ -223,8 +215,7 @@ struct Context {
                     const double *p2, const double *c12, int64_t n_m, const double *m2,
                     double *out, hipStream_t st);
   // autotune.cpp
-  // kind: 0 FP64 grid kernel, 1 compensated-FP32 grid kernel, 2 FP64 redo pass
-  int grid_launch(GridArgs g, int reg, const GridCfg &cfg, hipStream_t st, int kind = 0);
+  int grid_launch(GridArgs g, int reg, const GridCfg &cfg, hipStream_t st);
   GridCfg grid_cfg(const frg_quad &q, const GridArgs &g, hipStream_t st);
   int plain_tile_for(const SetDev &s, hipStream_t st);
   PersistCfg persist_cfg(const std::vector<SetDev> &sd, int prec, hipStream_t st);

@@ -64,8 +64,8 @@ struct SetDev {
   int32_t n_r, n_a, reg, prec;
   int32_t R, J;  // lanes along radial / angular nodes, R * J = 64
   int32_t T, U;  // ceil(n_r / R), ceil(n_a / J)
-  double f32_flag;  // FP32C: error estimate above which a point is redone in FP64
-  double f32_band;  // FP32C: delta/k^2 below which a point is done in FP64
+  double f32_flag;  // FP32C: error bound above which a point is evaluated in FP64
+  double f32_band;  // FP32C: delta/k^2 below which a point is evaluated in FP64
   double q_top, rmu_max;  // range test of the grouped reciprocal sums
 };
 
@@ -86,8 +86,6 @@ struct GridArgs {
   const double *p;
   const double *m2;
   double *out;
-  double *err;
-  uint8_t *used64;
   const double *tab;
   int *flag;
   double k2, inv_k2, pref;
@@ -104,29 +102,8 @@ struct GridArgs {
   // vtab = [x_j | sqrt(1 - x_j^2) | cos phi_l | nu_l]
   const double *p2, *c12, *vtab;
   int32_t n_phi;
-  // compensated-FP32 grid only (Grid32Table on the device, see below)
-  const double *tab32;
-  double f32_band, f32_flag;  // FP64 below dhat = f32_band; re-done in FP64 above err f32_flag
-  double f32_erho;            // bound of the coherent weight error of the FP32 terms
-  double f32_rmin, f32_rmax;  // range of rho_j
 };
 
-// Angular data of the compensated-FP32 grid kernel for one quadrature key
-// and lane split.  A group of eight angular terms of one lane takes the FP32
-// running fraction over D''_ij = (Hk(s_ij)/k^2 + dhat) rho_j and is scaled by
-// gam_g, with rho_j = fl32(gam_g / mu_j) so that gam_g / rho_j = mu_j (1 + e_j);
-// gam_g is searched per group to make max |e_j| small.  Angular terms outside
-// the groups use rho_j = fl32(1/mu_j), gam_j = mu_j rho_j (e_j = 0).  Device
-// layout: gam[n_a] (the group's value at each of its j), sig[n_a] =
-// rho_j mu_j / k^2 (the factor taking H'_ij = Hk rmu_j to H''_ij), then
-// rho[n_a] as float.
-struct Grid32Table {
-  std::vector<double> gam, sig;
-  std::vector<float> rho;
-  double rmin = 0.0, rmax = 0.0, erho = 0.0;
-};
-Grid32Table build_grid32_table(const QuadTable &t, int J);
-constexpr int grid32_group_size = 8;
 
 struct LpaJob {
   const double *U;
@@ -256,12 +233,18 @@ constexpr int64_t tab_lds_max_nodes = 6144;  // rows up to this many nodes are s
 
 // -------------------------------------------------------------- launchers --
 // All return hipError_t as int (0 = success).
+// Plain launch over one set (FP64 or FP32C by s.prec).
 int launch_points_plain(const SetDev &s, int tile_points, int *d_flag, void *stream);
 int launch_points_persistent(const SetDev *d_sets, const Tile *d_tiles, int n_tiles,
                              int *d_counters /* kCounters ints, zero */, int lds_bytes, int n_blocks, bool with_f32,
                              int *d_flag, void *stream);
 int launch_reset_counter(int *d_counters /* kCounters ints */, void *stream);
-int launch_grid(const GridArgs &g, int reg, int M, int W, void *stream, bool redo = false);
+int launch_grid(const GridArgs &g, int reg, int M, int W, void *stream);
+// err[i] = 1e-14, used64[i] = 1 for i < n (either may be null): the marks of
+// FP32C results evaluated in FP64.
+int launch_fp64_marks(double *err, uint8_t *used64, int64_t n, void *stream);
+// out[i] = e^{-y[i]} by the FP32C point path's exponential (exp_neg32).
+int launch_expneg_fp32c(const double *y, double *out, int64_t n, void *stream);
 int grid_lds_bytes(const GridArgs &g);
 // Resident coefficient form of the FP64 grid kernel: used when its table fits.
 constexpr int kGridCoefLdsMax = 150 * 1024;
@@ -283,13 +266,10 @@ std::vector<double> build_vertex_table(int d, int n_a, int n_phi);
 // Whether the FP64 grid kernel keeps its table resident, and in which form.
 bool grid_uses_coef(const GridArgs &g);
 bool grid_resident(const GridArgs &g);
-int launch_fp32c(const SetDev &s, int tile_points, int64_t grid_nm, int *d_flag, void *stream);
-int launch_grid32(const GridArgs &g, int reg, int M, int W, void *stream);
 // stream_blocks: workgroups of the streamed-row form (rounded up to a multiple of 8)
 int launch_tab(const TabArgs &t, int reg, int W, bool lds_rows, int64_t stream_blocks,
                void *stream);
 int tab_lds_bytes(const TabArgs &t, bool lds_rows);
-int grid32_lds_bytes(const GridArgs &g);
 int launch_lpa(const LpaJob *d_jobs, const int64_t *d_start, int n_jobs, int64_t total_points,
                void *stream);
 

@@ -42,7 +42,9 @@ __device__ __forceinline__ void load_tile(const SetDev &s, int64_t start, int co
   mv = lane < count ? s.m2[start + lane] : 0.0;
 }
 
-template <int REG>
+// MARK: the set is FRG_PREC_FP32C evaluated in FP64 (Litim): also store
+// err = kErr64 and used64 = 1 (NaN and 0 for points outside the domain).
+template <int REG, bool MARK>
 __device__ void do_tile(const SetDev &s, const double *tab, const double2 *ang, const double *etab,
                         int64_t start, int count, double pv, double mv, int lane, int *flag) {
   constexpr int F = 4;
@@ -71,8 +73,15 @@ __device__ void do_tile(const SetDev &s, const double *tab, const double2 *ang, 
     const double v[F] = {v0, v1, v2, v3};
     const double tot = wave_sum_fold<F>(v, lane);
     const int mine = fold_owner<F>(lane);
-    if (fold_leader<F>(lane) && mine < nf)
-      s.out[start + e0 + mine] = ((ok >> mine) & 1u) ? s.pref_k * tot : __builtin_nan("");
+    if (fold_leader<F>(lane) && mine < nf) {
+      const int64_t o = start + e0 + mine;
+      const bool okm = (ok >> mine) & 1u;
+      s.out[o] = okm ? s.pref_k * tot : __builtin_nan("");
+      if (MARK) {
+        if (s.err) s.err[o] = okm ? kErr64 : __builtin_nan("");
+        if (s.used64) s.used64[o] = (uint8_t)okm;
+      }
+    }
   }
 }
 
@@ -87,8 +96,8 @@ __device__ __forceinline__ void stage_table(const SetDev &s, double *lds, int ti
 
 // Plain launch over one set: 4 waves per workgroup share the staged tables
 // (LDS layout of point_lds_doubles), each wave takes one tile of
-// `tile_points` points.
-template <int REG>
+// `tile_points` points.  F32: the set is FRG_PREC_FP32C (fp32c_tile).
+template <int REG, bool F32>
 __global__ __launch_bounds__(256) void points_plain_kernel(SetDev s, int tile_points, int64_t n_tiles,
                                                            int *flag) {
   extern __shared__ double lds[];
@@ -107,7 +116,10 @@ __global__ __launch_bounds__(256) void points_plain_kernel(SetDev s, int tile_po
   const int count = left < tile_points ? (int)left : tile_points;
   double pv, mv;
   load_tile(s, start, count, lane, pv, mv);
-  do_tile<REG>(s, tab, ang, etab, start, count, pv, mv, lane, flag);
+  if (F32 && REG == kExp)
+    fp32c_tile(s, tab, ang, etab, start, count, pv, mv, lane, flag);
+  else
+    do_tile<REG, F32>(s, tab, ang, etab, start, count, pv, mv, lane, flag);
 }
 
 // Persistent launch over many sets (FP64 and FP32C mixed): one wave per
@@ -118,9 +130,10 @@ __global__ __launch_bounds__(256) void points_plain_kernel(SetDev s, int tile_po
 // XCD); the counters lie kCounterStride ints apart, on different cache
 // lines, so the claims spread over kCounters atomic units.  A wave ends at
 // its first empty claim; the launch has at least min(n_tiles, kCounters)
-// workgroups, so every non-empty sub-list is served.
+// workgroups, so every non-empty sub-list is served.  At most 128 VGPRs, so
+// that four waves share each SIMD (the FP32C variant needs the bound).
 template <bool WITH_F32>
-__global__ __launch_bounds__(64) void points_persistent_kernel(const SetDev *__restrict__ sets,
+__global__ __launch_bounds__(64, 4) void points_persistent_kernel(const SetDev *__restrict__ sets,
                                                                const Tile *__restrict__ tiles,
                                                                int n_tiles, int *counters,
                                                                int *flag) {
@@ -148,38 +161,44 @@ __global__ __launch_bounds__(64) void points_persistent_kernel(const SetDev *__r
     const Tile tl = tiles[t];
     const SetDev s = sets[tl.set];
     const bool f32 = WITH_F32 && s.prec == FRG_PREC_FP32C;
-    double pv = 0.0, mv = 0.0;
-    if (!f32) load_tile(s, tl.start, tl.count, lane, pv, mv);
+    double pv, mv;
+    load_tile(s, tl.start, tl.count, lane, pv, mv);
     double2 *ang = reinterpret_cast<double2 *>(lds + kExpTab);
     double *tab = lds + kExpTab + 2 * s.n_a;
     if (tl.set != cur) {
       __syncthreads();
       stage_pairs(s, ang, lane, kWave);
-      if (f32)
-        stage_fp32c(s, tab, lane, kWave);
-      else
-        stage_table(s, tab, lane, kWave);
+      stage_table(s, tab, lane, kWave);
       __syncthreads();
       cur = tl.set;
     }
     // claim the next tile after this tile's loads, so that waiting for them
     // does not wait for the claim
     const int cn = claim();
-    if (f32) {
-      const float *fo = reinterpret_cast<const float *>(tab + table_doubles(s.n_r, s.n_a));
-      const float *fm = fo + s.n_a;
-      const float *fl = fm + s.n_a;
-      if (s.reg == kExp)
-        fp32c_tile<kExp>(s, tab, ang, etab, fo, fm, fl, tl.start, tl.count, 0, lane, flag);
+    if (s.reg == kExp) {
+      if (f32)
+        fp32c_tile(s, tab, ang, etab, tl.start, tl.count, pv, mv, lane, flag);
       else
-        fp32c_tile<kLitim>(s, tab, ang, etab, fo, fm, fl, tl.start, tl.count, 0, lane, flag);
-    } else if (s.reg == kExp) {
-      do_tile<kExp>(s, tab, ang, etab, tl.start, tl.count, pv, mv, lane, flag);
+        do_tile<kExp, false>(s, tab, ang, etab, tl.start, tl.count, pv, mv, lane, flag);
+    } else if (f32) {
+      do_tile<kLitim, true>(s, tab, ang, etab, tl.start, tl.count, pv, mv, lane, flag);
     } else {
-      do_tile<kLitim>(s, tab, ang, etab, tl.start, tl.count, pv, mv, lane, flag);
+      do_tile<kLitim, false>(s, tab, ang, etab, tl.start, tl.count, pv, mv, lane, flag);
     }
     c = __builtin_amdgcn_readfirstlane(cn);
   }
+}
+
+__global__ void fp64_marks_kernel(double *err, uint8_t *used64, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (err) err[i] = kErr64;
+  if (used64) used64[i] = 1;
+}
+
+__global__ void expneg_fp32c_kernel(const double *y, double *out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = exp_neg32(y[i]);
 }
 
 __global__ void reset_counter_kernel(int *c) {
@@ -194,10 +213,8 @@ __global__ void reset_counter_kernel(int *c) {
 // visiting order, the grouping and the arithmetic are those of lane_point, so
 // results match the point kernel bit for bit.
 
-// RESIDENT: the whole table fits in g.chunk rows (host-checked).  REDO: only
-// the masses with used64 == 1 (left for FP64 by the compensated-FP32 grid
-// kernel) are computed; a workgroup with none of them returns before its fill.
-template <int REG, int M, bool RESIDENT, bool REDO>
+// RESIDENT: the whole table fits in g.chunk rows (host-checked).
+template <int REG, int M, bool RESIDENT>
 __global__ __launch_bounds__(512) void grid_kernel(GridArgs g) {
   extern __shared__ double lds[];
   const int W = blockDim.x / kWave;
@@ -211,13 +228,6 @@ __global__ __launch_bounds__(512) void grid_kernel(GridArgs g) {
   constexpr bool resident = RESIDENT;
   const int C = resident ? TU : g.chunk;
   const int MB = resident ? g.mblocks : 1;
-  if constexpr (REDO) {
-    const int64_t first = (int64_t)mb * MB * W * M;
-    bool any = false;
-    for (int idx = threadIdx.x; idx < MB * W * M; idx += blockDim.x)
-      any |= first + idx < g.n_m && g.used64[a * g.n_m + first + idx] == 1;
-    if (!__syncthreads_or(any)) return;  // workgroup-uniform
-  }
   double *lH = lds;
   double *lc = lH + C * kWave;
   double *lq = lc + n_r;
@@ -238,7 +248,8 @@ __global__ __launch_bounds__(512) void grid_kernel(GridArgs g) {
     if (m0 >= g.n_m && resident) break;  // wave-uniform
     double dm[M];
     bool ok[M];
-    unsigned mask = 0, act = all;
+    unsigned mask = 0;
+    const unsigned act = all;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       const int64_t idx = m0 + m;
@@ -247,14 +258,9 @@ __global__ __launch_bounds__(512) void grid_kernel(GridArgs g) {
       ok[m] = valid && p_ok && d > 0.0;
       dm[m] = ok[m] ? d : 1.0;
       mask |= chain_ok(dm[m], p, g.q_top, g.rmu_max) ? (1u << m) : 0u;
-      if (REDO && !(valid && g.used64[a * g.n_m + idx] == 1)) act &= ~(1u << m);
     }
     // the masses are the same in every lane: make the choices wave-uniform
     const unsigned gmask = __builtin_amdgcn_readfirstlane(mask);
-    if (REDO) {
-      act = __builtin_amdgcn_readfirstlane(act);
-      if (!act) continue;
-    }
     double tot[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) tot[m] = 0.0;
@@ -288,15 +294,6 @@ __global__ __launch_bounds__(512) void grid_kernel(GridArgs g) {
       bad |= (m0 + m < g.n_m) && !ok[m];
     }
     const bool okm = (okbits >> mine) & 1u;
-    if (REDO) {
-      // the FP32 kernel has already written the other points and the flag
-      if (lane % (kWave / M) == 0 && ((act >> mine) & 1u)) {
-        const int64_t o = a * g.n_m + m0 + mine;
-        g.out[o] = okm ? v : __builtin_nan("");
-        if (g.err) g.err[o] = kErr64;
-      }
-      continue;
-    }
     if (bad && lane == 0) *g.flag = 1;
     if (lane % (kWave / M) == 0 && m0 + mine < g.n_m)
       g.out[a * g.n_m + m0 + mine] = okm ? v : __builtin_nan("");
@@ -304,13 +301,13 @@ __global__ __launch_bounds__(512) void grid_kernel(GridArgs g) {
 }
 
 // Stage the masses of one workgroup (blocks of M) in LDS with their masks:
-// lmask[4b..4b+3] = valid, ok (domain), coefficient form, active (REDO:
-// left for FP64 by the compensated-FP32 kernel), ldm[bM + m] = delta.
-template <int M, int G, int E, bool REDO>
-__device__ __forceinline__ void stage_masses(const GridArgs &g, int64_t a, int64_t wg_m0, int nblk,
-                                             bool p_ok, bool table, unsigned *lmask, double *ldm) {
+// lmask[4b..4b+2] = valid, ok (domain), coefficient form (4b + 3 pads a
+// block's masks to 16 bytes), ldm[bM + m] = delta.
+template <int M, int G, int E>
+__device__ __forceinline__ void stage_masses(const GridArgs &g, int64_t wg_m0, int nblk, bool p_ok,
+                                             bool table, unsigned *lmask, double *ldm) {
   for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-    unsigned vb = 0, okb = 0, cmb = 0, act = 0;
+    unsigned vb = 0, okb = 0, cmb = 0;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       const int64_t idx = wg_m0 + (int64_t)b * M + m;
@@ -322,18 +319,16 @@ __device__ __forceinline__ void stage_masses(const GridArgs &g, int64_t a, int64
       vb |= valid ? (1u << m) : 0u;
       okb |= ok ? (1u << m) : 0u;
       cmb |= (table && fold_m_ok<G, E>(g.sig * dd)) ? (1u << m) : 0u;
-      act |= (!REDO || (valid && g.used64[a * g.n_m + idx] == 1)) ? (1u << m) : 0u;
     }
     lmask[4 * b] = vb;
     lmask[4 * b + 1] = okb;
     lmask[4 * b + 2] = cmb;
-    lmask[4 * b + 3] = act;
   }
 }
 
 // The mass blocks of one wave: coefficient form for the masses in range,
 // single(delta) (per-term lane partial) for the others, reduction, store.
-template <int M, int G, int E, bool REDO, class Single>
+template <int M, int G, int E, class Single>
 __device__ __forceinline__ void coef_blocks(const GridArgs &g, const double *lC,
                                             const unsigned *lmask, const double *ldm, int64_t a,
                                             int64_t wg_m0, int MB, int W, int wave, int lane,
@@ -347,8 +342,6 @@ __device__ __forceinline__ void coef_blocks(const GridArgs &g, const double *lC,
     const unsigned validbits = __builtin_amdgcn_readfirstlane(lmask[4 * b]);
     const unsigned okbits = __builtin_amdgcn_readfirstlane(lmask[4 * b + 1]);
     const unsigned cmask = __builtin_amdgcn_readfirstlane(lmask[4 * b + 2]);
-    const unsigned act = __builtin_amdgcn_readfirstlane(lmask[4 * b + 3]);
-    if (REDO && !act) continue;
     double dm[M], xs[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
@@ -358,12 +351,12 @@ __device__ __forceinline__ void coef_blocks(const GridArgs &g, const double *lC,
     double tot[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) tot[m] = 0.0;
-    const unsigned cm = act & cmask;
+    const unsigned cm = cmask;
     if (cm == all)
       grid_fold_rows<M, G, true, E>(g, lC, lane, xs, cm, fs, tot);
     else if (cm)
       grid_fold_rows<M, G, false, E>(g, lC, lane, xs, cm, fs, tot);
-    const unsigned sm = act & ~cmask;
+    const unsigned sm = all & ~cmask;
     if (sm) {
 #pragma unroll
       for (int m = 0; m < M; ++m)
@@ -376,15 +369,6 @@ __device__ __forceinline__ void coef_blocks(const GridArgs &g, const double *lC,
     const double v = (((cmask >> mine) & 1u) ? g.pref_c : g.pref) * s;
     const bool okm = (okbits >> mine) & 1u;
     const bool mine_out = fold_leader<M>(lane) && ((validbits >> mine) & 1u);
-    if (REDO) {
-      // the FP32 kernel has already written the other points and the flag
-      if (mine_out && ((act >> mine) & 1u)) {
-        const int64_t o = a * g.n_m + m0 + mine;
-        g.out[o] = okm ? v : __builtin_nan("");
-        if (g.err) g.err[o] = kErr64;
-      }
-      continue;
-    }
     if ((validbits & ~okbits) && lane == 0) *g.flag = 1;
     if (mine_out) g.out[a * g.n_m + m0 + mine] = okm ? v : __builtin_nan("");
   }
@@ -396,7 +380,7 @@ __device__ __forceinline__ void coef_blocks(const GridArgs &g, const double *lC,
 // the coefficient form are evaluated at x = 1 there (in range, result
 // dropped) and take single(delta) with a full-wave sum.  The value of a mass
 // depends on its own column only: tile composition, W and MB change nothing.
-template <int G, int E, bool REDO, class Single>
+template <int G, int E, class Single>
 __device__ __forceinline__ void mfma_blocks(const GridArgs &g, const double *lC,
                                             const unsigned *lmask, const double *ldm, int64_t a,
                                             int64_t wg_m0, int MB, int W, int wave, int lane,
@@ -410,9 +394,7 @@ __device__ __forceinline__ void mfma_blocks(const GridArgs &g, const double *lC,
     const unsigned validbits = __builtin_amdgcn_readfirstlane(lmask[4 * b]);
     const unsigned okbits = __builtin_amdgcn_readfirstlane(lmask[4 * b + 1]);
     const unsigned cmask = __builtin_amdgcn_readfirstlane(lmask[4 * b + 2]);
-    const unsigned act = __builtin_amdgcn_readfirstlane(lmask[4 * b + 3]);
-    if (REDO && !act) continue;
-    const unsigned cm = act & cmask;
+    const unsigned cm = cmask;
     double s = 0.0;
     if (cm) {
       const double x = ((cm >> mine) & 1u) ? g.sig * ldm[b * M + mine] : 1.0;
@@ -420,7 +402,7 @@ __device__ __forceinline__ void mfma_blocks(const GridArgs &g, const double *lC,
       s = swap_add<32>(s, s);
       s = swap_add<16>(s, s);
     }
-    unsigned sm = act & ~cmask;
+    unsigned sm = ((1u << M) - 1u) & ~cmask;
     while (sm) {  // wave-uniform
       const int m = __builtin_ctz(sm);
       sm &= sm - 1u;
@@ -431,14 +413,6 @@ __device__ __forceinline__ void mfma_blocks(const GridArgs &g, const double *lC,
     const double v = (((cmask >> mine) & 1u) ? g.pref_c : g.pref) * s;
     const bool okm = (okbits >> mine) & 1u;
     const bool mine_out = lane < M && ((validbits >> mine) & 1u);
-    if (REDO) {
-      if (mine_out && ((act >> mine) & 1u)) {
-        const int64_t o = a * g.n_m + m0 + mine;
-        g.out[o] = okm ? v : __builtin_nan("");
-        if (g.err) g.err[o] = kErr64;
-      }
-      continue;
-    }
     if ((validbits & ~okbits) && lane == 0) *g.flag = 1;
     if (mine_out) g.out[a * g.n_m + m0 + mine] = okm ? v : __builtin_nan("");
   }
@@ -446,11 +420,8 @@ __device__ __forceinline__ void mfma_blocks(const GridArgs &g, const double *lC,
 
 // Tensor grid, resident coefficient form (device_grid.h): a workgroup owns
 // one momentum and W * M * MB masses; it builds the per-group coefficients of
-// its momentum once in LDS and every mass evaluates them by Horner.  REDO:
-// only the masses with used64 == 1 (left for FP64 by the compensated-FP32
-// grid kernel) are computed; a workgroup with none of them returns before
-// building its table.
-template <int REG, int M, int G, bool REDO>
+// its momentum once in LDS and every mass evaluates them by Horner.
+template <int REG, int M, int G>
 __global__ __launch_bounds__(512) void grid_coef_kernel(GridArgs g) {
   extern __shared__ double lds[];
   const int W = blockDim.x / kWave;
@@ -463,12 +434,6 @@ __global__ __launch_bounds__(512) void grid_coef_kernel(GridArgs g) {
   const int MB = g.mblocks;
   const int nblk = MB * W;  // mass blocks of M masses in this workgroup
   const int64_t wg_m0 = (int64_t)mb * nblk * M;
-  if constexpr (REDO) {
-    bool any = false;
-    for (int idx = threadIdx.x; idx < nblk * M; idx += blockDim.x)
-      any |= wg_m0 + idx < g.n_m && g.used64[a * g.n_m + wg_m0 + idx] == 1;
-    if (!__syncthreads_or(any)) return;  // workgroup-uniform
-  }
   // LDS: coefficients | per-block masks | masses delta | c_i | Hq_i | mu_j |
   // q_i | 1 + x_j
   const FoldShape<G> fs(g.U, g.T);
@@ -491,7 +456,7 @@ __global__ __launch_bounds__(512) void grid_coef_kernel(GridArgs g) {
   }
   const bool p_ok = p >= 0.0;
   const bool table = p_ok && fold_p_ok<G>(p, g);  // workgroup-uniform
-  stage_masses<M, G, 2, REDO>(g, a, wg_m0, nblk, p_ok, table, lmask, ldm);
+  stage_masses<M, G, 2>(g, wg_m0, nblk, p_ok, table, lmask, ldm);
   __syncthreads();
   if (table) grid_fill_fold<REG, G>(g, lC, lc, lq, lm, lqn, lo, p, fs);
   __syncthreads();
@@ -499,9 +464,9 @@ __global__ __launch_bounds__(512) void grid_coef_kernel(GridArgs g) {
     return grid_single_mass<REG>(g, lc, lq, lm, lane, p, delta);
   };
   if constexpr (M == 16)
-    mfma_blocks<G, 2, REDO>(g, lC, lmask, ldm, a, wg_m0, MB, W, wave, lane, fs, single);
+    mfma_blocks<G, 2>(g, lC, lmask, ldm, a, wg_m0, MB, W, wave, lane, fs, single);
   else
-    coef_blocks<M, G, 2, REDO>(g, lC, lmask, ldm, a, wg_m0, MB, W, wave, lane, fs, single);
+    coef_blocks<M, G, 2>(g, lC, lmask, ldm, a, wg_m0, MB, W, wave, lane, fs, single);
 }
 
 // Vertex diagram on a tensor grid (configurations x masses): a workgroup owns
@@ -554,7 +519,7 @@ __global__ __launch_bounds__(MAXT) void vertex_kernel(GridArgs g) {
   const bool p_ok = p1 >= 0.0 && p2 >= 0.0 && ct >= -1.0 && ct <= 1.0;
   const double st = p_ok ? sqrt((1.0 - ct) * (1.0 + ct)) : 0.0;
   const bool table = table_form && p_ok && fold_p_ok<G, 3>(fmax(p1, p2), g);
-  stage_masses<M, G, 3, false>(g, a, wg_m0, nblk, p_ok, table, lmask, ldm);
+  stage_masses<M, G, 3>(g, wg_m0, nblk, p_ok, table, lmask, ldm);
   __syncthreads();
   if (table) vertex_fill<REG, G>(g, lC, lc, lq, lqn, lx, lm, lsx, lcp, lnu, p1, p2, ct, st, fs);
   __syncthreads();
@@ -562,9 +527,9 @@ __global__ __launch_bounds__(MAXT) void vertex_kernel(GridArgs g) {
     return vertex_single_mass<REG>(g, lc, lq, lx, lm, lsx, lcp, lnu, lane, p1, p2, ct, st, delta);
   };
   if constexpr (M == 16)
-    mfma_blocks<G, 3, false>(g, lC, lmask, ldm, a, wg_m0, MB, W, wave, lane, fs, single);
+    mfma_blocks<G, 3>(g, lC, lmask, ldm, a, wg_m0, MB, W, wave, lane, fs, single);
   else
-    coef_blocks<M, G, 3, false>(g, lC, lmask, ldm, a, wg_m0, MB, W, wave, lane, fs, single);
+    coef_blocks<M, G, 3>(g, lC, lmask, ldm, a, wg_m0, MB, W, wave, lane, fs, single);
 }
 
 // Coefficient of U[j+o] in U' (c1) and U'' (c2) of the difference formulas.
@@ -672,12 +637,35 @@ int launch_points_plain(const SetDev &s, int tile_points, int *d_flag, void *str
   const int64_t blocks = (n_tiles + waves - 1) / waves;
   const size_t lds = sizeof(double) * (kExpTab + 2 * s.n_a + table_doubles(s.n_r, s.n_a));
   hipStream_t st = (hipStream_t)stream;
-  if (s.reg == kExp)
-    hipLaunchKernelGGL(points_plain_kernel<kExp>, dim3((unsigned)blocks), dim3(64 * waves), lds, st,
-                       s, tile_points, n_tiles, d_flag);
-  else
-    hipLaunchKernelGGL(points_plain_kernel<kLitim>, dim3((unsigned)blocks), dim3(64 * waves), lds,
-                       st, s, tile_points, n_tiles, d_flag);
+  const dim3 grid((unsigned)blocks), block(64 * waves);
+  if (s.prec == FRG_PREC_FP32C) {
+    if (s.reg == kExp)
+      hipLaunchKernelGGL((points_plain_kernel<kExp, true>), grid, block, lds, st, s, tile_points,
+                         n_tiles, d_flag);
+    else
+      hipLaunchKernelGGL((points_plain_kernel<kLitim, true>), grid, block, lds, st, s, tile_points,
+                         n_tiles, d_flag);
+  } else if (s.reg == kExp) {
+    hipLaunchKernelGGL((points_plain_kernel<kExp, false>), grid, block, lds, st, s, tile_points,
+                       n_tiles, d_flag);
+  } else {
+    hipLaunchKernelGGL((points_plain_kernel<kLitim, false>), grid, block, lds, st, s, tile_points,
+                       n_tiles, d_flag);
+  }
+  return (int)hipGetLastError();
+}
+
+int launch_fp64_marks(double *err, uint8_t *used64, int64_t n, void *stream) {
+  if (n <= 0 || (!err && !used64)) return 0;
+  hipLaunchKernelGGL(fp64_marks_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, err, used64, n);
+  return (int)hipGetLastError();
+}
+
+int launch_expneg_fp32c(const double *y, double *out, int64_t n, void *stream) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(expneg_fp32c_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, y, out, n);
   return (int)hipGetLastError();
 }
 
@@ -814,22 +802,15 @@ int launch_vertex(const GridArgs &g, int reg, int M, int W, void *stream) {
 }
 
 template <int REG, int M, int G>
-static void coef_launch_t(const GridArgs &g, int W, bool redo, hipStream_t st) {
-  static const bool once = (allow_large_lds((const void *)&grid_coef_kernel<REG, M, G, false>),
-                            allow_large_lds((const void *)&grid_coef_kernel<REG, M, G, true>), true);
+static void coef_launch_t(const GridArgs &g, int W, hipStream_t st) {
+  static const bool once = (allow_large_lds((const void *)&grid_coef_kernel<REG, M, G>), true);
   (void)once;
   const int64_t blocks = g.n_p * g.n_mb;
   const int lds = grid_coef_lds_bytes(g) - kGridCoefStageMax + grid_coef_stage_bytes(g.mblocks, W, M);
-  if (redo)
-    hipLaunchKernelGGL((grid_coef_kernel<REG, M, G, true>), dim3((unsigned)blocks),
-                       dim3(kWave * W), lds, st, g);
-  else
-    hipLaunchKernelGGL((grid_coef_kernel<REG, M, G, false>), dim3((unsigned)blocks),
-                       dim3(kWave * W), lds, st, g);
+  hipLaunchKernelGGL((grid_coef_kernel<REG, M, G>), dim3((unsigned)blocks), dim3(kWave * W), lds,
+                     st, g);
 }
 
-// Returns false when the shape has no kernel (the host never asks a redo
-// pass of streamed tables).
 bool grid_uses_coef(const GridArgs &g) {
   return g.form != 1 && std::isnormal(g.pref_c) && std::isnormal(g.sig) &&
          grid_coef_lds_bytes(g) <= kGridCoefLdsMax;
@@ -838,54 +819,46 @@ bool grid_uses_coef(const GridArgs &g) {
 bool grid_resident(const GridArgs &g) { return grid_uses_coef(g) || g.T * g.U <= g.chunk; }
 
 template <int REG, int M>
-static bool grid_launch_t(const GridArgs &g, int W, bool redo, hipStream_t st) {
+static void grid_launch_t(const GridArgs &g, int W, hipStream_t st) {
   if (grid_uses_coef(g)) {
     // M = 16: tiles of 16 masses on the matrix cores; M <= 8: vector units
     const int G = grid_coef_group(g);
     if (G == 32)
-      coef_launch_t<REG, M, 32>(g, W, redo, st);
+      coef_launch_t<REG, M, 32>(g, W, st);
     else if (G == 16)
-      coef_launch_t<REG, M, 16>(g, W, redo, st);
+      coef_launch_t<REG, M, 16>(g, W, st);
     else
-      coef_launch_t<REG, M, 8>(g, W, redo, st);
-    return true;
+      coef_launch_t<REG, M, 8>(g, W, st);
+    return;
   }
   const int64_t blocks = g.n_p * g.n_mb;
   if (g.T * g.U <= g.chunk) {
     // resident table, running-fraction form
-    if (redo)
-      hipLaunchKernelGGL((grid_kernel<REG, M, true, true>), dim3((unsigned)blocks),
-                         dim3(kWave * W), grid_lds_bytes(g), st, g);
-    else
-      hipLaunchKernelGGL((grid_kernel<REG, M, true, false>), dim3((unsigned)blocks),
-                         dim3(kWave * W), grid_lds_bytes(g), st, g);
-    return true;
+    hipLaunchKernelGGL((grid_kernel<REG, M, true>), dim3((unsigned)blocks), dim3(kWave * W),
+                       grid_lds_bytes(g), st, g);
+    return;
   }
-  if (redo) return false;
   // tables too large for LDS: streamed in chunks (running-fraction form)
-  hipLaunchKernelGGL((grid_kernel<REG, M, false, false>), dim3((unsigned)blocks), dim3(kWave * W),
+  hipLaunchKernelGGL((grid_kernel<REG, M, false>), dim3((unsigned)blocks), dim3(kWave * W),
                      grid_lds_bytes(g), st, g);
-  return true;
 }
 
-int launch_grid(const GridArgs &g, int reg, int M, int W, void *stream, bool redo) {
+int launch_grid(const GridArgs &g, int reg, int M, int W, void *stream) {
   if (g.n_p <= 0 || g.n_m <= 0) return 0;
   hipStream_t st = (hipStream_t)stream;
-  bool ok;
   if (reg == kExp) {
     switch (M) {
-      case 4: ok = grid_launch_t<kExp, 4>(g, W, redo, st); break;
-      case 8: ok = grid_launch_t<kExp, 8>(g, W, redo, st); break;
-      default: ok = grid_launch_t<kExp, 16>(g, W, redo, st); break;
+      case 4: grid_launch_t<kExp, 4>(g, W, st); break;
+      case 8: grid_launch_t<kExp, 8>(g, W, st); break;
+      default: grid_launch_t<kExp, 16>(g, W, st); break;
     }
   } else {
     switch (M) {
-      case 4: ok = grid_launch_t<kLitim, 4>(g, W, redo, st); break;
-      case 8: ok = grid_launch_t<kLitim, 8>(g, W, redo, st); break;
-      default: ok = grid_launch_t<kLitim, 16>(g, W, redo, st); break;
+      case 4: grid_launch_t<kLitim, 4>(g, W, st); break;
+      case 8: grid_launch_t<kLitim, 8>(g, W, st); break;
+      default: grid_launch_t<kLitim, 16>(g, W, st); break;
     }
   }
-  if (!ok) return (int)hipErrorInvalidValue;
   return (int)hipGetLastError();
 }
 

@@ -158,61 +158,6 @@ QuadTable build_quad_table(const frg_quad &q) {
 // mu_j such that the FP32 values rho_j = fl32(gam / mu_j) give gam / rho_j
 // closest to mu_j: over 2^16 candidates gam0 (1 + n 2^-30) the one with the
 // smallest max_j |rho_j mu_j / gam - 1| is kept.
-Grid32Table build_grid32_table(const QuadTable &t, int J) {
-  const int nr = t.n_r, na = t.n_a;
-  Grid32Table g;
-  g.gam.assign(na, 0.0);
-  g.sig.assign(na, 0.0);
-  g.rho.assign(na, 0.0f);
-  const double *mu = t.data.data() + 3 * nr + na;
-  const int umin = na / J;
-  const int G = umin - umin % grid32_group_size;  // grouped u < G (as in the kernels)
-  std::vector<char> grouped(na, 0);
-  for (int iota = 0; iota < J; ++iota) {
-    for (int u0 = 0; u0 < G; u0 += grid32_group_size) {
-      int js[grid32_group_size];
-      double lg = 0.0;
-      for (int k = 0; k < grid32_group_size; ++k) {
-        js[k] = iota + J * (u0 + k);
-        lg += std::log(mu[js[k]]);
-      }
-      const double gam0 = std::exp(lg / grid32_group_size);
-      double best = 1e300, best_gam = gam0;
-      for (int n = 0; n < (1 << 16); ++n) {
-        const double gam = gam0 * (1.0 + std::ldexp((double)n, -30));
-        double worst = 0.0;
-        for (int k = 0; k < grid32_group_size && worst < best; ++k) {
-          const float r = (float)(gam / mu[js[k]]);
-          worst = std::max(worst, std::fabs((double)r * mu[js[k]] / gam - 1.0));
-        }
-        if (worst < best) {
-          best = worst;
-          best_gam = gam;
-        }
-      }
-      g.erho = std::max(g.erho, best);
-      for (int k = 0; k < grid32_group_size; ++k) {
-        const int j = js[k];
-        g.gam[j] = best_gam;
-        g.rho[j] = (float)(best_gam / mu[j]);
-        grouped[j] = 1;
-      }
-    }
-  }
-  g.rmin = 1e300;
-  g.rmax = 0.0;
-  for (int j = 0; j < na; ++j) {
-    if (!grouped[j]) {
-      g.rho[j] = (float)(1.0 / mu[j]);
-      g.gam[j] = mu[j] * (double)g.rho[j];
-    }
-    g.sig[j] = (double)g.rho[j] * mu[j] * t.inv_k2;
-    g.rmin = std::min(g.rmin, (double)g.rho[j]);
-    g.rmax = std::max(g.rmax, (double)g.rho[j]);
-  }
-  return g;
-}
-
 LpaTable build_lpa_table(int d, int reg, int n_r, double q_max_over_k) {
   LpaTable t;
   t.n_r = n_r;

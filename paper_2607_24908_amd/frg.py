@@ -34,7 +34,7 @@ EXPORTS = ["frg_create", "frg_destroy", "frg_last_error", "frg_version", "frg_in
            "frg_flow_rhs", "frg_flow_rhs_batch", "frg_flow_solve",
            "frg_submit", "frg_poll", "frg_server_stats", "frg_gauss_legendre",
            "frg_flow_footprint", "frg_autotune", "frg_tune_set", "frg_tune_get", "frg_expneg",
-           "frg_stream_status", "frg_integrate_noalloc"]
+           "frg_stream_status", "frg_integrate_noalloc", "frg_expneg_fp32c"]
 
 
 class frg_quad(ctypes.Structure):
@@ -142,6 +142,7 @@ def _load():
                                    ctypes.POINTER(dbl)]
     L.frg_gauss_legendre.argtypes = [i32, vp, vp]
     L.frg_expneg.argtypes = [i64, vp, vp]
+    L.frg_expneg_fp32c.argtypes = [vp, i64, vp, vp, vp]
     L.frg_stream_status.argtypes = [vp, vp]
     L.frg_integrate_noalloc.argtypes = [vp, ctypes.POINTER(frg_set), i32, vp, vp]
     L.frg_flow_footprint.argtypes = [ctypes.POINTER(frg_lpa)]
@@ -406,6 +407,11 @@ def frg_expneg(y: np.ndarray) -> np.ndarray:
     out = np.empty_like(y)
     _check(lib.frg_expneg(y.size, _addr(y), _addr(out)))
     return out
+
+
+def frg_expneg_fp32c(ctx, y, out, stream=None):
+    """e^{-y} on the GPU by the FP32C point path's exponential (device tensors)."""
+    return _check(lib.frg_expneg_fp32c(ctx, int(y.numel()), _addr(y), _addr(out), _stream(stream)))
 
 
 def frg_flow_footprint(lpa: frg_lpa) -> int:

@@ -73,7 +73,6 @@ def test_vertex_largest_azimuthal_orders(ctx, n_phi):
 # (values accepted, values refused)
 KNOBS = {
     "grid_M": ([4, 8, 16], [2, 12, 32]), "grid_W": ([1, 8], [0, 9]), "grid_MB": ([1, 64], [0, 65]),
-    "grid32_M": ([4, 8], [16]), "grid32_W": ([1, 8], [0, 9]), "grid32_MB": ([1, 64], [0, 65]),
     "grid_form": ([0, 3], [-1, 4]), "grid_mfma": ([0, 1], [-1, 2]),
     "fv_persistent": ([0, 1], [2]), "pflow_fused": ([0, 1], [-1, 2]), "vertex_W": ([1, 12], [0, 13]),
     "server_zero_copy": ([0, 1], [2]), "grid_lds_rows": ([8, 96], [7, 97]),

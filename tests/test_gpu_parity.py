@@ -112,20 +112,19 @@ def test_plain_d4_points_all_launch_forms_bitwise(ctx):
 
 def test_grid_launch_shapes_bitwise(ctx):
     """Masses per wave, waves per workgroup and mass blocks per wave change
-    only the schedule: every shape returns the same bits (FP64 and FP32C)."""
+    only the schedule: every shape returns the same bits (FP64; FP32C grids
+    run the same kernel)."""
     cases = [(workloads.plain_d4().quad, workloads.plain_d4().p, workloads.plain_d4().m2),
              (workloads.Quad(3, frg.FRG_REG_EXP, 1.0, 6.0, 100, 12),
               np.logspace(-3, 1, 21), np.linspace(-0.9, 10, 75))]
     defaults = {k: frg.frg_tune_get(ctx, k) for k in
-                ("grid_M", "grid_W", "grid_MB", "grid32_M", "grid32_W", "grid32_MB")}
+                ("grid_M", "grid_W", "grid_MB")}
     try:
         for q, p, m2 in cases:
-            for prec, pre in ((frg.FRG_PREC_FP64, "grid_"), (frg.FRG_PREC_FP32C, "grid32_")):
+            for prec, pre in ((frg.FRG_PREC_FP64, "grid_"), (frg.FRG_PREC_FP32C, "grid_")):
                 quad = frg.make_quad(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a, prec)
                 ref = None
                 for M, W, MB in [(8, 4, 16), (4, 2, 1), (16, 8, 4), (4, 8, 8), (8, 1, 3)]:
-                    if pre == "grid32_" and M == 16:
-                        continue
                     frg.frg_tune_set(ctx, pre + "M", M)
                     frg.frg_tune_set(ctx, pre + "W", W)
                     frg.frg_tune_set(ctx, pre + "MB", MB)
