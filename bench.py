@@ -69,13 +69,14 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device-to-device copy of 1 GiB (PMC traffic calibration)")
-    ap.add_argument("--only", choices=["uneven64", "uneven32", "tab4096", "tab1m", "pflow",
+    ap.add_argument("--only", choices=["uneven64", "uneven32", "tab4096", "tab1m", "tab1mseg", "pflow",
                                        "vertex", "fvlpa", "serving"],
                     default=None,
                     help="profiling aid: run only --steps persistent launches of the uneven sets "
                          "(FP64 or FP32C), --steps momentum-flow "
                          "or finite-volume LPA solves or vertex-diagram calls, --steps calls "
-                         "of the tabulated variant (rows of 4096 or 2^20 nodes), or --steps "
+                         "of the tabulated variant (rows of 4096 or 2^20 nodes; tab1mseg: the "
+                         "segmented form), or --steps "
                          "served flow requests (after --warmup more), and print their timing")
     return ap.parse_args()
 
@@ -245,10 +246,12 @@ def main():
         r = serving(frg, workloads, n_warm=args.warmup, n_timed=args.steps)
         print(json.dumps({"only": args.only, **r}), flush=True)
         return
-    if args.only in ("tab4096", "tab1m"):
+    if args.only in ("tab4096", "tab1m", "tab1mseg"):
         import torch
         from paper_2607_24908_amd import frg, workloads
         ctx = frg.frg_create(0)
+        if args.only == "tab1mseg":
+            frg.frg_tune_set(ctx, "tab_seg", 1)
         n_s = 4096 if args.only == "tab4096" else 1 << 20
         r = tabulated(ctx, frg, workloads, torch, which=(n_s,), reps=args.steps)
         print(json.dumps({"only": args.only, **r[f"tabulated_{n_s}"]}), flush=True)

@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libfrg.so")
 
-SOURCES = ["kernels.hip", "tab.hip", "pflow.hip", "fvlpa.hip", "noalloc.hip", "capi.cpp",
+SOURCES = ["kernels.hip", "tab.hip", "tab_seg.hip", "pflow.hip", "fvlpa.hip", "noalloc.hip", "capi.cpp",
            "tables.cpp",
            "stepper.cpp", "server.cpp", "autotune.cpp", "pflow_api.cpp",
            "vertex_api.cpp", "fvlpa_api.cpp"]

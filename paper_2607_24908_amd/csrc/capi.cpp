@@ -643,8 +643,49 @@ int Ctx::tab_launch(TabArgs a, int reg, hipStream_t st) {
   bool lds_rows = false;
   int W = 1;
   int64_t sblocks = 0;
-  const int rc = tab_config(a, lds_rows, W, sblocks);
+  int rc = tab_config(a, lds_rows, W, sblocks);
   if (rc) return rc;
+  if (!lds_rows && tune.tab_seg) {
+    // segmented form, when its tables fit: LDS, superchunk count, term index
+    // in 16 bits with the sort in 64 KiB of LDS, counts in 32 bits, partial
+    // sums and term lists up to 1 GiB each
+    const TabSegShape s = tab_seg_shape(a, n_cu);
+    const double part_bytes = 8.0 * s.n_super * (double)a.n_rows * (double)a.n_p;
+    const double terms_bytes = 2.0 * (double)a.n_p * a.n_r * a.n_a;
+    const double offs_bytes = 4.0 * (double)a.n_p * (s.n_seg + 1);
+    if (s.lds <= 160 * 1024 && s.n_super <= kTabSegMaxSuper && s.e_pad <= 16384 &&
+        (double)a.n_p * a.n_r * a.n_a < 4.0e9 && part_bytes <= (double)(1u << 30) &&
+        terms_bytes <= (double)(1u << 30) && offs_bytes <= (double)(1u << 30)) {
+      // the buffers are the context's: a launch on another stream waits for
+      // the previous one (a reallocation waits for the device)
+      if (!tab_done && hipEventCreateWithFlags(&tab_done, hipEventDisableTiming) != hipSuccess) {
+        tab_done = nullptr;
+        return fail(FRG_E_DEVICE, "hipEventCreate");
+      }
+      const size_t scr_bytes = sizeof(unsigned) * (s.n_super + 64);
+      if (tab_part.bytes < (size_t)part_bytes || tab_terms.bytes < (size_t)terms_bytes ||
+          tab_offs.bytes < (size_t)offs_bytes || tab_scr.bytes < scr_bytes)
+        hipEventSynchronize(tab_done);
+      rc = tab_part.reserve((size_t)part_bytes);
+      if (!rc) rc = tab_terms.reserve((size_t)terms_bytes);
+      if (!rc) rc = tab_offs.reserve((size_t)offs_bytes);
+      if (!rc) rc = tab_scr.reserve(scr_bytes);
+      if (rc) return rc;
+      hipError_t he = hipStreamWaitEvent(st, tab_done, 0);
+      if (he != hipSuccess) return hip_fail(he, "hipStreamWaitEvent");
+      TabSegBufs bufs;
+      bufs.part = (double *)tab_part.ptr;
+      bufs.terms = (uint16_t *)tab_terms.ptr;
+      bufs.offs = (int *)tab_offs.ptr;
+      bufs.hist = (unsigned *)tab_scr.ptr;
+      bufs.counter = (int *)(bufs.hist + s.n_super + 32);
+      const int e = launch_tab_seg(a, s, bufs, n_cu, st);
+      if (e) return hip_fail((hipError_t)e, "tab_seg_kernel launch");
+      he = hipEventRecord(tab_done, st);
+      if (he != hipSuccess) return hip_fail(he, "hipEventRecord");
+      return FRG_OK;
+    }
+  }
   int e = launch_tab(a, reg, W, lds_rows, sblocks, st);
   if (e) return hip_fail((hipError_t)e, "tab_kernel launch");
   return FRG_OK;
@@ -725,6 +766,10 @@ Context::~Context() {
   if (stream) hipStreamSynchronize(stream);
   graphs.clear();
   ring.destroy();
+  if (tab_done) {
+    hipEventSynchronize(tab_done);
+    hipEventDestroy(tab_done);
+  }
   if (na_done) {
     hipEventSynchronize(na_done);
     hipEventDestroy(na_done);

@@ -81,6 +81,7 @@ struct Tune {
   int tab_sW = 2;          // tabulated variant, streamed rows: waves per workgroup
   int tab_spw = 1;         // tabulated variant, streamed rows: momenta per wave (at most)
   int tab_pairs = 1;       // tabulated variant: rows in LDS as (value, slope) pairs
+  int tab_seg = 0;         // tabulated variant, rows longer than the LDS: segmented form
   PersistCfg persist;
   int grid_lds_rows = 64;  // (t, u) rows of 64 doubles staged per LDS chunk
   int grid_form = 0;       // resident FP64 grid: 0 per-momentum coefficients, 1 running fractions
@@ -144,6 +145,10 @@ struct Context {
   int use_stream_flag(hipStream_t st);
   frg::DescRing ring;
   frg::DevBuf stage_in, stage_out;
+  // segmented tabulated form: partial sums, sorted term lists, their segment
+  // offsets, counts + work counter
+  frg::DevBuf tab_part, tab_terms, tab_offs, tab_scr;
+  hipEvent_t tab_done = nullptr;   // after the last segmented launch (which used them)
   frg::Tune tune;
   uint64_t tune_gen = 1;  // advanced whenever a knob or a tuned choice changes
   uint64_t hbm_budget = 0;

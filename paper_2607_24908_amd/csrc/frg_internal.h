@@ -229,6 +229,35 @@ int launch_pflow_pull(const TabArgs &t, const PflowPull &a, int reg, int W, void
 int launch_pflow_final(const PflowPull &a, void *stream);
 constexpr int64_t tab_lds_max_nodes = 6144;  // rows up to this many nodes are staged in LDS
 
+// Segmented form of the tabulated diagram (tab_seg.hip), for rows longer than
+// the LDS: segments of kTabSegC nodes, kTabSegS per superchunk, batches of
+// kTabSegRows rows, workgroups of kTabSegThreads threads (at most one
+// momentum per thread in a work item).
+constexpr int kTabSegC = 2048;
+constexpr int kTabSegS = 8;
+constexpr int kTabSegRows = 4;
+constexpr int kTabSegThreads = 1024;
+constexpr int kTabSegMaxSuper = 1024;  // superchunks per row at most (rows of ~16.7M nodes)
+struct TabSegShape {
+  int n_seg, n_super, n_batch;
+  int target;  // work items per row batch aimed at
+  int lds;     // dynamic LDS bytes of the main kernel
+  int e_pad;   // n_r n_a rounded up to a power of two (the sort's LDS keys)
+};
+TabSegShape tab_seg_shape(const TabArgs &t, int n_cu);
+// Device buffers of one launch: part n_super * n_rows * n_p doubles, terms
+// n_p * n_r * n_a uint16, offs n_p * (n_seg + 1) ints, hist n_super
+// unsigned, counter one int.
+struct TabSegBufs {
+  double *part;
+  uint16_t *terms;
+  int *offs;
+  unsigned *hist;
+  int *counter;
+};
+int launch_tab_seg(const TabArgs &t, const TabSegShape &s, const TabSegBufs &b, int n_cu,
+                   void *stream);
+
 
 
 // -------------------------------------------------------------- launchers --

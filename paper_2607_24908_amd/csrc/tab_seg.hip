@@ -1,0 +1,413 @@
+// Tabulated-propagator flow diagram, rows too long for LDS (segmented form).
+//
+// Every row shares the interpolation coordinates t_e(p) = s_e / h of the
+// terms e = (i, j): only the table values differ.  A row is cut into segments
+// of kTabSegC nodes and kTabSegS consecutive segments form a superchunk.
+//  1. tab_seg_sort_kernel, once per call: for each momentum, its terms sorted
+//     by (segment of their node index, e) -- a list of e (16 bits) and the
+//     offset of every segment in it; term counts per superchunk.
+//  2. tab_seg_kernel: a work item is (batch of kTabSegRows rows, superchunk,
+//     range of momenta).  Its workgroup copies the superchunk's segments of
+//     its rows into LDS (two buffers: the next segment is copied straight from
+//     memory while the current one is used); for each momentum the terms of
+//     the segment are a run of its list, evaluated from LDS for all rows of
+//     the batch with one coordinate.  Items are balanced on the term counts
+//     (hot superchunks are split by momenta) and taken from a work counter.
+//  3. tab_seg_reduce_kernel: the superchunks' partial sums, in order.
+//
+// Mapping: a momentum's run of a segment is taken by one wave, the 64 lanes
+// on consecutive terms, and folded over the wave (wave_sum_fold).  The sum of
+// one result is fixed by the shapes: per segment, the run's terms split over
+// the lanes by position, each lane's terms in order, the fixed fold; the
+// segments of a superchunk added in order into part[superchunk][row][momentum];
+// the superchunks in order.  How momenta are split into items changes no bit.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "frg_internal.h"
+
+#pragma clang fp contract(off)
+
+#include "device_fp64.h"
+
+namespace frg {
+
+namespace {
+
+using namespace dev;
+
+constexpr int kC = kTabSegC;
+constexpr int kS = kTabSegS;
+constexpr int kRB = kTabSegRows;
+static_assert(kRB == 4, "the run fold leaves one row per group of 16 lanes");
+constexpr int kNT = kTabSegThreads;
+constexpr int kRowLds = kC + 1;           // a segment's nodes and its right neighbour
+constexpr int kBufD = kRB * kRowLds;      // doubles of one segment buffer
+constexpr int kBufW = 2 * kBufD;          // its 4-byte words
+
+// Node index of an evaluation: k = min(floor(min(t, t_last)), k_last),
+// t = fma(bh, 1 + x_j, ah) (the node and fraction of the piecewise-linear
+// interpolant, as in the other tabulated kernels).
+__device__ __forceinline__ int node_of(double t, double t_last, int k_last) {
+  const int k = (int)fmin(t, t_last);
+  return k < k_last ? k : k_last;
+}
+
+// Term counts per superchunk (hist) and the work counter, zeroed.
+__global__ void tab_seg_zero_kernel(unsigned *hist, int n_super, int *counter) {
+  for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n_super; i += blockDim.x * gridDim.x)
+    hist[i] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
+}
+
+// One workgroup per momentum: the keys (segment, e) of its E = n_r n_a terms
+// in LDS, a bitonic sort (E_pad = next power of two, padding keys last), then
+// terms[p][pos] = e and offs[p][s] = first position of segment >= s
+// (s = 0..n_seg).  Momenta outside the domain get empty runs.
+__global__ __launch_bounds__(256) void tab_seg_sort_kernel(TabArgs a, uint16_t *terms,
+                                                           int *offs, unsigned *hist,
+                                                           int n_seg, int n_super, int e_pad) {
+  extern __shared__ unsigned keys[];
+  const int64_t ip = blockIdx.x;
+  const int E = a.n_r * a.n_a;
+  const int n_a = a.n_a;
+  int *po = offs + ip * (n_seg + 1);
+  const double p = a.p[ip];
+  if (!(p >= 0.0)) {  // workgroup-uniform
+    for (int x = threadIdx.x; x <= n_seg; x += blockDim.x) po[x] = 0;
+    return;
+  }
+  const int k_last = (int)a.n_s - 2;
+  const double *opx = a.tab + 3 * a.n_r;
+  // keys[x] lives at x + x / 32 (padding against bank conflicts of the
+  // power-of-two strides)
+  for (int e = threadIdx.x; e < e_pad; e += blockDim.x) {
+    unsigned key = 0xffffffffu;
+    if (e < E) {
+      const int i = e / n_a, j = e - i * n_a;
+      const double q = a.tab[i];
+      const double qm = q - p;
+      const double ah = (qm * qm) * a.inv_h;
+      const double bh = ((2.0 * q) * p) * a.inv_h;
+      const int k = node_of(__builtin_fma(bh, opx[j], ah), a.t_last, k_last);
+      key = (unsigned)(k / kC) * (unsigned)E + (unsigned)e;
+    }
+    keys[e + (e >> 5)] = key;
+  }
+  __syncthreads();
+  for (int size = 2; size <= e_pad; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int x = threadIdx.x; x < (e_pad >> 1); x += blockDim.x) {
+        const int lo = 2 * x - (x & (stride - 1));
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const int plo = lo + (lo >> 5), phi = hi + (hi >> 5);
+        const unsigned u = keys[plo], v = keys[phi];
+        if ((u > v) == up) {
+          keys[plo] = v;
+          keys[phi] = u;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  uint16_t *pt = terms + ip * E;
+  for (int pos = threadIdx.x; pos < E; pos += blockDim.x) {
+    const unsigned key = keys[pos + (pos >> 5)];
+    const int sg = (int)(key / (unsigned)E);
+    pt[pos] = (uint16_t)(key - (unsigned)sg * (unsigned)E);
+    const int sp = pos == 0 ? -1 : (int)(keys[pos - 1 + ((pos - 1) >> 5)] / (unsigned)E);
+    for (int x = sp + 1; x <= sg; ++x) po[x] = pos;  // segments sp+1 .. sg start here
+    if (pos == E - 1)
+      for (int x = sg + 1; x <= n_seg; ++x) po[x] = E;
+  }
+  __syncthreads();  // offs written (global memory, this workgroup)
+  for (int c = threadIdx.x; c < n_super; c += blockDim.x) {
+    const int s0 = c * kS, s1 = min(s0 + kS, n_seg);
+    const int cnt = po[s1] - po[s0];
+    if (cnt) atomicAdd(&hist[c], (unsigned)cnt);
+  }
+}
+
+// Momenta split of superchunk c: between ceil(n_p / kItemMax) items and
+// ceil(n_p / kItemMin), in proportion to its cost (terms + kNodeW * nodes,
+// the copy of a node for the batch weighed against a term's work).
+constexpr double kNodeW = 8.0;
+constexpr int kWaves = kNT / kWave;
+constexpr int kItemMax = kNT;     // momenta per item: one per lane
+constexpr int kItemMin = kWaves;  // one per wave
+
+__device__ __forceinline__ double super_nodes(const TabArgs &a, int c, int n_seg) {
+  const int s0 = c * kS, s1 = min(s0 + kS, n_seg);
+  const int64_t k0 = (int64_t)s0 * kC;
+  const int64_t k1 = min((int64_t)s1 * kC, a.n_s - 1);
+  return (double)(k1 - k0);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Work items from the counter until the list is drained.  Momentum ip of an
+// item is owned by lane l of wave w with ip = p_lo + w + kWaves l; for each
+// segment a wave takes the non-empty runs of its momenta one after another,
+// all 64 lanes on one run (lane l: positions o + l, o + l + 64, ...), and the
+// four row sums of the run are folded over the wave and added by the owner.
+__global__ __launch_bounds__(kNT) void tab_seg_kernel(TabArgs a, const unsigned *hist,
+                                                      const uint16_t *__restrict__ terms,
+                                                      const int *__restrict__ offs, int *counter,
+                                                      double *part, int n_seg, int n_super,
+                                                      int n_batch, int target) {
+  extern __shared__ double lds[];
+  const int n_r = a.n_r, n_a = a.n_a;
+  const int tid = threadIdx.x;
+  double *lg0 = lds;                      // two segment buffers [kRB][kRowLds]
+  double *lq = lg0 + 2 * kBufD;           // q_i
+  double *lA = lq + n_r;                  // [kRB][n_r]
+  double *lo = lA + kRB * n_r;            // 1 + x_j
+  double *lm = lo + n_a;                  // mu_j
+  int *ns = reinterpret_cast<int *>(lm + n_a);  // splits per superchunk
+  int *ord = ns + n_super;                       // superchunks, costliest first
+  long long *pre = reinterpret_cast<long long *>(ord + n_super);  // item prefix (8-byte aligned)
+  int *claim = reinterpret_cast<int *>(pre + n_super + 1);
+  for (int i = tid; i < n_r; i += kNT) lq[i] = a.tab[i];
+  for (int j = tid; j < n_a; j += kNT) {
+    lo[j] = a.tab[3 * n_r + j];
+    lm[j] = a.tab[3 * n_r + n_a + j];
+  }
+  // the plan (the same in every workgroup)
+  const int smin = (int)((a.n_p + kItemMax - 1) / kItemMax);
+  const int smax = (int)((a.n_p + kItemMin - 1) / kItemMin);
+  double total = 0.0;
+  for (int c = 0; c < n_super; ++c) total += (double)hist[c] + kNodeW * super_nodes(a, c, n_seg);
+  const double budget = total / (double)target;
+  for (int c = tid; c < n_super; c += kNT) {
+    const double cost = (double)hist[c] + kNodeW * super_nodes(a, c, n_seg);
+    int s = (int)ceil(cost / budget);
+    s = s < smin ? smin : (s > smax ? smax : s);
+    ns[c] = s;
+    // rank: costlier first, ties by index
+    int rank = 0;
+    for (int d = 0; d < n_super; ++d) {
+      const double cd = (double)hist[d] + kNodeW * super_nodes(a, d, n_seg);
+      rank += (cd > cost || (cd == cost && d < c)) ? 1 : 0;
+    }
+    ord[rank] = c;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    long long acc = 0;
+    for (int r = 0; r < n_super; ++r) {
+      pre[r] = acc;
+      acc += (long long)ns[ord[r]] * n_batch;
+    }
+    pre[n_super] = acc;
+  }
+  __syncthreads();
+  const long long n_items = pre[n_super];
+  const int k_last = (int)a.n_s - 2;
+  const int E = n_r * n_a;
+  const float inv_na = 1.0f / (float)n_a;
+  const int wave = tid / kWave, lane = tid % kWave;
+  for (;;) {
+    if (tid == 0) *claim = atomicAdd(counter, 1);
+    __syncthreads();
+    const long long item = *claim;
+    __syncthreads();  // every thread has read the claim
+    if (item >= n_items) break;
+    // decode: rank (superchunk), then batch, then momentum split
+    int ra = 0, rb = n_super;
+    while (rb - ra > 1) {
+      const int m = (ra + rb) >> 1;
+      if (pre[m] <= item) ra = m; else rb = m;
+    }
+    const int c = ord[ra];
+    const int nsc = ns[c];
+    const long long off = item - pre[ra];
+    const int b = (int)(off / nsc), msp = (int)(off % nsc);
+    const int64_t p_lo = (int64_t)msp * a.n_p / nsc, p_hi = (int64_t)(msp + 1) * a.n_p / nsc;
+    const int64_t r0 = (int64_t)b * kRB;
+    const int nrb = (int)min<int64_t>(kRB, a.n_rows - r0);
+    // A_i = c_i G_r(q_i^2)^2 of the batch's rows
+    for (int x = tid; x < kRB * n_r; x += kNT) {
+      const int r = x / n_r, i = x - r * n_r;
+      double A = 0.0;
+      if (r < nrb) {
+        const double *row = a.g + (r0 + r) * a.n_s;
+        const double q = lq[i];
+        const double t = fmin((q * q) * a.inv_h, a.t_last);
+        int k = (int)t;
+        k = k < k_last ? k : k_last;
+        const double f = t - (double)k;
+        const double g0 = row[k], g1 = row[k + 1];
+        const double G = __builtin_fma(f, g1 - g0, g0);
+        A = (a.tab[n_r + i] * G) * G;
+      }
+      lA[x] = A;
+    }
+    // this lane's momentum
+    const int64_t my = p_lo + wave + (int64_t)kWaves * lane;
+    const bool mine = my < p_hi;
+    const double pv = mine ? a.p[my] : -1.0;
+    const bool live = pv >= 0.0;  // NaN and p < 0 have no terms
+    const int *pof = offs + (mine ? my : 0) * (int64_t)(n_seg + 1);
+    // accumulators: lane L = 16 r + s holds row r of the wave's momenta
+    // l = s, s + 16, s + 32, s + 48 (acc[l / 16]), where the fold below
+    // leaves the row sums of a run
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int sg0 = c * kS, sg1 = min(sg0 + kS, n_seg);
+    // copy segment sg of the batch's rows into buffer d, 4 bytes per lane and
+    // 256 contiguous bytes of LDS per wave instruction; words beyond the table
+    // or the batch are left unwritten (never read)
+    auto load = [&](int sg, int d) {
+      const int64_t T0 = (int64_t)sg * kC;
+      unsigned *dst = reinterpret_cast<unsigned *>(lg0 + d * kBufD);
+      for (int w = wave; w * kWave < kBufW; w += kWaves) {  // wave-uniform
+        const int x = w * kWave + lane;
+        const int r = x / (2 * kRowLds), rem = x - r * 2 * kRowLds;
+        if (x < kBufW && r < nrb && T0 + (rem >> 1) < a.n_s) {
+          const unsigned *src =
+              reinterpret_cast<const unsigned *>(a.g + (r0 + r) * a.n_s + T0) + rem;
+          __builtin_amdgcn_global_load_lds(
+              src, (__attribute__((address_space(3))) void *)(dst + w * kWave), 4, 0, 0);
+        }
+      }
+    };
+    load(sg0, 0);
+    // run bounds of this lane's momentum: segment sg, and sg + 1 ahead
+    int o_cur = live ? pof[sg0] : 0;
+    int o_nxt = live ? pof[sg0 + 1] : 0;
+    for (int sg = sg0; sg < sg1; ++sg) {
+      const int cur = (sg - sg0) & 1;
+      const int o_after = (live && sg + 2 <= n_seg) ? pof[sg + 2] : 0;
+      // this wave's copies of segment sg have landed; after the barrier every
+      // wave's have, and every wave is done with the other buffer
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (sg + 1 < sg1) load(sg + 1, cur ^ 1);
+      const double *lg = lg0 + cur * kBufD;
+      const int T0 = sg * kC;
+      unsigned long long todo = __builtin_amdgcn_ballot_w64(live && o_nxt > o_cur);
+      while (todo) {  // wave-uniform: the momenta with terms in this segment
+        const int l = __builtin_ctzll(todo);
+        todo &= todo - 1ull;
+        const int ra0 = __builtin_amdgcn_readlane(o_cur, l);
+        const int ra1 = __builtin_amdgcn_readlane(o_nxt, l);
+        const double p = readlane_d(pv, l);
+        const int64_t ip = p_lo + wave + (int64_t)kWaves * l;
+        const uint16_t *pt = terms + ip * E;
+        double in[kRB];
+#pragma unroll
+        for (int r = 0; r < kRB; ++r) in[r] = 0.0;
+        for (int pos = ra0 + lane; pos < ra1; pos += kWave) {
+          const unsigned e = pt[pos];
+          // e = i n_a + j (exact: e < 2^16, and e + 1/2 is at least 1/(2 n_a)
+          // away from a multiple of n_a)
+          const int i = (int)(((float)e + 0.5f) * inv_na);
+          const int j = (int)e - i * n_a;
+          const double q = lq[i];
+          const double qm = q - p;
+          const double ah = (qm * qm) * a.inv_h;
+          const double bh = ((2.0 * q) * p) * a.inv_h;
+          const double t = fmin(__builtin_fma(bh, lo[j], ah), a.t_last);
+          int k = (int)t;
+          k = k < k_last ? k : k_last;
+          const double f = t - (double)k;
+          const double mu = lm[j];
+          // k lies in the segment by construction; the clamp only keeps the
+          // LDS index in bounds
+          int x = k - T0;
+          x = x < 0 ? 0 : (x > kC - 1 ? kC - 1 : x);
+#pragma unroll
+          for (int r = 0; r < kRB; ++r) {
+            const double g0 = lg[r * kRowLds + x], g1 = lg[r * kRowLds + x + 1];
+            in[r] = __builtin_fma(lA[r * n_r + i] * mu, __builtin_fma(f, g1 - g0, g0), in[r]);
+          }
+        }
+        // lane groups of 16 end with the sums of rows 0..3
+        const double rs = wave_sum_fold<kRB>(in, lane);
+        if ((lane & 15) == (l & 15)) {
+          const int k = l >> 4;  // wave-uniform
+          acc[0] = k == 0 ? acc[0] + rs : acc[0];
+          acc[1] = k == 1 ? acc[1] + rs : acc[1];
+          acc[2] = k == 2 ? acc[2] + rs : acc[2];
+          acc[3] = k == 3 ? acc[3] + rs : acc[3];
+        }
+      }
+      o_cur = o_nxt;
+      o_nxt = o_after;
+    }
+    {
+      const int r = lane >> 4;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int64_t ip = p_lo + wave + (int64_t)kWaves * ((lane & 15) + 16 * k);
+        if (r < nrb && ip < p_hi) part[((int64_t)c * a.n_rows + r0 + r) * a.n_p + ip] = acc[k];
+      }
+    }
+  }
+}
+
+// out[a, r] = pref sum_c part[c][r][a] (superchunks in order); NaN and the
+// domain flag for p < 0.
+__global__ void tab_seg_reduce_kernel(TabArgs a, const double *part, int n_super) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= a.n_p * a.n_rows) return;
+  const int64_t r = x / a.n_p, ip = x - r * a.n_p;
+  const double p = a.p[ip];
+  double v;
+  if (p >= 0.0) {
+    double s = 0.0;
+    for (int c = 0; c < n_super; ++c) s = s + part[((int64_t)c * a.n_rows + r) * a.n_p + ip];
+    v = a.pref * s;
+  } else {
+    v = __builtin_nan("");
+    if (r == 0) *a.flag = 1;
+  }
+  a.out[ip * a.os_p + r * a.os_r] = v;
+}
+
+}  // namespace
+
+TabSegShape tab_seg_shape(const TabArgs &t, int n_cu) {
+  TabSegShape s;
+  s.n_seg = (int)((t.n_s - 1 + kC - 1) / kC);
+  s.n_super = (s.n_seg + kS - 1) / kS;
+  s.n_batch = (int)((t.n_rows + kRB - 1) / kRB);
+  const int64_t want = 4LL * n_cu;
+  s.target = (int)std::max<int64_t>(s.n_super, (want + s.n_batch - 1) / s.n_batch);
+  int e_pad = 1;
+  while (e_pad < t.n_r * t.n_a) e_pad <<= 1;
+  s.e_pad = e_pad;
+  s.lds = (int)(sizeof(double) * (2 * kBufD + t.n_r + kRB * t.n_r + 2 * t.n_a) +
+                sizeof(int) * 2 * s.n_super + sizeof(long long) * (s.n_super + 1) + sizeof(int));
+  return s;
+}
+
+int launch_tab_seg(const TabArgs &t, const TabSegShape &s, const TabSegBufs &b, int n_cu,
+                   void *stream) {
+  if (t.n_p <= 0 || t.n_rows <= 0) return 0;
+  hipStream_t st = (hipStream_t)stream;
+  static const bool once =
+      ((void)hipFuncSetAttribute((const void *)&tab_seg_kernel,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024),
+       (void)hipGetLastError(), true);
+  (void)once;
+  hipLaunchKernelGGL(tab_seg_zero_kernel, dim3(1), dim3(256), 0, st, b.hist, s.n_super, b.counter);
+  hipLaunchKernelGGL(tab_seg_sort_kernel, dim3((unsigned)t.n_p), dim3(256),
+                     sizeof(unsigned) * (s.e_pad + s.e_pad / 32), st, t, b.terms, b.offs, b.hist, s.n_seg,
+                     s.n_super, s.e_pad);
+  hipLaunchKernelGGL(tab_seg_kernel, dim3((unsigned)n_cu), dim3(kNT), (size_t)s.lds, st, t,
+                     (const unsigned *)b.hist, (const uint16_t *)b.terms, (const int *)b.offs,
+                     b.counter, b.part, s.n_seg, s.n_super, s.n_batch, s.target);
+  const int64_t n = t.n_p * t.n_rows;
+  hipLaunchKernelGGL(tab_seg_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, t,
+                     (const double *)b.part, s.n_super);
+  return (int)hipGetLastError();
+}
+
+}  // namespace frg

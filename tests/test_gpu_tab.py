@@ -7,8 +7,11 @@ build their quadrature rules independently (nodes equal to about an ulp) and
 round t differently, so t differs by about u t and a result moves by up to
 u t |g_{k+1} - g_k| / G relative -- about 1e-10 for random rows of 2^20
 nodes, whatever the formula; the bound sums that sensitivity over the terms
-of each result.  The LDS-row and streamed-row forms of the kernel do the same
-arithmetic in the same order and must agree bit for bit."""
+of each result.  The LDS-row and cache-streamed forms of the kernel do the
+same arithmetic in the same order and must agree bit for bit; the segmented
+form (long rows cut into LDS segments shared by four rows) sums each result
+segment by segment: it agrees with them to rounding, and its bits do not
+depend on how its work is split (which follows the momenta of the call)."""
 import numpy as np
 import pytest
 
@@ -34,8 +37,9 @@ def dev(a):
     return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
 
 
-def run_tab(ctx, q, g, s_max, p, lds_nodes=6144, pw=16, W=4, pairs=1):
+def run_tab(ctx, q, g, s_max, p, lds_nodes=6144, pw=16, W=4, pairs=1, seg=0):
     frg.frg_tune_set(ctx, "tab_pairs", pairs)
+    frg.frg_tune_set(ctx, "tab_seg", seg)
     frg.frg_tune_set(ctx, "tab_lds_nodes", lds_nodes)
     frg.frg_tune_set(ctx, "tab_pw", pw)
     frg.frg_tune_set(ctx, "tab_W", W)
@@ -73,20 +77,26 @@ def test_tab_matches_oracle_and_forms_agree(ctx, d, reg, n_r, n_a):
     assert np.array_equal(streamed, got)
     values = run_tab(ctx, q, g, s_max, p, pairs=0)  # rows in LDS as values
     assert np.array_equal(values, got)
+    segmented = run_tab(ctx, q, g, s_max, p, lds_nodes=2, seg=1)
+    assert np.max(np.abs(segmented - want) / np.abs(want)) < RTOL
+    assert np.all(np.abs(segmented - got) <= 1e-13 * np.abs(got))
 
 
-@pytest.mark.parametrize("n_s,lds", [(4097, True), (4097, False), (1 << 20, False)])
-def test_tab_rough_rows_within_coordinate_bound(ctx, n_s, lds):
-    """Seeded random positive rows (two decades, no smoothness) in LDS and
-    streamed, including rows of 2^20 nodes: every result within its bound."""
-    print(f"[case] rough rows n_s={n_s} lds={lds}", flush=True)
+@pytest.mark.parametrize("n_s,form", [(4097, "lds"), (4097, "cache"), (4097, "seg"),
+                                      (40961, "seg"), (1 << 20, "seg"), (1 << 20, "cache")])
+def test_tab_rough_rows_within_coordinate_bound(ctx, n_s, form):
+    """Seeded random positive rows (two decades, no smoothness) in LDS,
+    cache-streamed and segmented, including rows of 2^20 nodes: every result
+    within its bound."""
+    print(f"[case] rough rows n_s={n_s} form={form}", flush=True)
+    lds = form == "lds"
     rng = np.random.Generator(np.random.PCG64(n_s + lds))
     n_rows = 6 if n_s < 100000 else 2
     g = 10.0 ** rng.uniform(-1.0, 1.0, (n_rows, n_s))
     s_max = 676.0
     q = workloads.Quad(3, 0, 1.0, 6.0, 128, 32)
     p = np.concatenate([[0.0, 1e-6], 10 ** rng.uniform(-3.0, np.log10(20.0), 22)])
-    got = run_tab(ctx, q, g, s_max, p, lds_nodes=6144 if lds else 2)
+    got = run_tab(ctx, q, g, s_max, p, lds_nodes=6144 if lds else 2, seg=int(form == "seg"))
     want = want_of(q, g, s_max, p)
     bound = oracle.integrate_tab_bound(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a, g, s_max, p,
                                        threads=8)
@@ -96,17 +106,49 @@ def test_tab_rough_rows_within_coordinate_bound(ctx, n_s, lds):
     assert np.all(rel <= bound)
 
 
-def test_tab_long_rows_sampled(ctx):
-    """Rows of 2^20 nodes (8 MB each, streamed through the caches) at the
-    sizes of the bench workload, checked on a sample of momenta and rows."""
+@pytest.mark.parametrize("seg", [0, 1])
+def test_tab_long_rows_sampled(ctx, seg):
+    """Rows of 2^20 nodes (8 MB each; read through the caches, or the
+    segmented form) at the sizes of the bench workload, checked on a sample
+    of momenta and rows."""
     w = workloads.tabulated_d3(n_s=1 << 20, n_p=64, n_rows=8)
-    print(f"[case] {w.name}", flush=True)
-    got = run_tab(ctx, w.quad, w.g, w.s_max, w.p)
+    print(f"[case] {w.name} seg={seg}", flush=True)
+    got = run_tab(ctx, w.quad, w.g, w.s_max, w.p, seg=seg)
     sel = np.arange(0, w.p.size, 7)
     want = want_of(w.quad, w.g, w.s_max, w.p[sel])
     err = np.abs(got[sel] - want) / want
     print(f"max rel err {err.max():.3e}")
     assert err.max() < RTOL
+
+
+def test_tab_segmented_bits_independent_of_the_split(ctx):
+    """The segmented form balances its work from the momenta of the call; a
+    momentum's result must not depend on that: results for a subset of the
+    momenta (a different split) equal those of the full call bit for bit, and
+    the full bench-size call is checked against the oracle on a sample."""
+    w = workloads.tabulated_d3(n_s=1 << 20, n_p=1024, n_rows=16)
+    print(f"[case] segmented split independence {w.name}", flush=True)
+    full = run_tab(ctx, w.quad, w.g, w.s_max, w.p, seg=1)
+    for sel in (np.arange(0, w.p.size, 7), np.arange(w.p.size - 100, w.p.size), np.array([5])):
+        part = run_tab(ctx, w.quad, w.g, w.s_max, w.p[sel], seg=1)
+        assert np.array_equal(part, full[sel]), sel[:3]
+    sel = np.arange(1, w.p.size, 61)
+    want = want_of(w.quad, w.g, w.s_max, w.p[sel])
+    err = np.abs(full[sel] - want) / want
+    print(f"max rel err {err.max():.3e}")
+    assert err.max() < RTOL
+    # a momentum outside the domain: NaN in its row, FRG_E_DOMAIN on the host path
+    p = np.array([0.3, -2.0, 7.0])
+    frg.frg_tune_set(ctx, "tab_seg", 1)
+    quad = frg.make_quad(w.quad.d, w.quad.reg, w.quad.k, w.quad.q_max, w.quad.n_r, w.quad.n_a)
+    out = np.zeros(p.size * 2)
+    rc = frg.frg_integrate_tab(ctx, quad, np.ascontiguousarray(w.g[:2]), w.s_max, p, out,
+                               mem=frg.FRG_MEM_HOST, allow_domain=True)
+    assert rc == frg.FRG_E_DOMAIN
+    out = out.reshape(3, 2)
+    assert np.all(np.isnan(out[1])) and np.all(np.isfinite(out[[0, 2]]))
+    assert np.array_equal(out[[0, 2]], run_tab(ctx, w.quad, w.g[:2], w.s_max, p[[0, 2]], seg=1))
+    frg.frg_tune_set(ctx, "tab_seg", 0)
 
 
 def test_tab_bench_shape_sampled(ctx):
