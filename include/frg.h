@@ -83,9 +83,14 @@ extern "C" {
 typedef struct frg_ctx frg_ctx;
 
 /* Create a context on HIP device `hip_device`.  `hbm_budget_bytes` bounds the
- * device memory the context's flow server may hold for resident flow state
- * (0 = 1/2 of the device's free memory at creation).  Tables, work lists and
- * staging buffers are owned by the context and freed by frg_destroy. */
+ * device memory the context holds (0 = 1/2 of the device's free memory at
+ * creation): its working buffers (quadrature, LPA and vertex tables, staging
+ * of host-memory calls, captured work lists, the segmented tabulated form's
+ * buffers) and, beside them, the flow server's flow state.  A call whose
+ * buffers would exceed it returns FRG_E_NOMEM without launching its kernels;
+ * a flow that does not fit beside the context's buffers is refused at
+ * submission.  Tables, work lists and staging buffers are owned by the
+ * context and freed by frg_destroy. */
 int frg_create(frg_ctx **out, int hip_device, uint64_t hbm_budget_bytes);
 
 /* Finish or cancel all flows, free all device and host resources. */

@@ -46,20 +46,29 @@ double now_s() {
 // ------------------------------------------------------------- DevBuf --
 DevBuf::~DevBuf() { release(); }
 void DevBuf::release() {
-  if (ptr) hipFree(ptr);
+  if (ptr) {
+    hipFree(ptr);
+    if (acct) acct->used -= bytes;
+  }
   ptr = nullptr;
   bytes = 0;
 }
 int DevBuf::reserve(size_t b) {
   if (b <= bytes) return FRG_OK;
+  const size_t nb = std::max<size_t>(b, 256);
+  if (acct && acct->used.load() - bytes + nb > acct->budget)
+    return fail(FRG_E_NOMEM,
+                "a buffer of %zu B would take the context's device buffers (%llu B) beyond its "
+                "HBM budget (%llu B)",
+                nb, (unsigned long long)acct->used.load(), (unsigned long long)acct->budget);
   release();
-  size_t nb = std::max<size_t>(b, 256);
   hipError_t e = hipMalloc(&ptr, nb);
   if (e != hipSuccess) {
     ptr = nullptr;
     return fail(FRG_E_NOMEM, "hipMalloc(%zu): %s", nb, hipGetErrorString(e));
   }
   bytes = nb;
+  if (acct) acct->used += nb;
   return FRG_OK;
 }
 
@@ -146,7 +155,7 @@ int Ctx::quad_table(const frg_quad &q, const double **dev, QuadTable *host_copy,
   auto it = qtabs.find(key);
   if (it == qtabs.end()) {
     QuadTable t = build_quad_table(q);
-    auto buf = std::make_unique<DevBuf>();
+    auto buf = std::make_unique<DevBuf>(&hbm);
     int rc = buf->reserve(t.data.size() * sizeof(double));
     if (rc) return rc;
     hipError_t e = hipMemcpy(buf->ptr, t.data.data(), t.data.size() * sizeof(double),
@@ -168,7 +177,7 @@ int Ctx::lpa_table(int d, int reg, int n_r, double qmk, const double **dev, doub
   auto it = ltabs.find(key);
   if (it == ltabs.end()) {
     LpaTable t = build_lpa_table(d, reg, n_r, qmk);
-    auto buf = std::make_unique<DevBuf>();
+    auto buf = std::make_unique<DevBuf>(&hbm);
     int rc = buf->reserve(t.data.size() * sizeof(double));
     if (rc) return rc;
     hipError_t e = hipMemcpy(buf->ptr, t.data.data(), t.data.size() * sizeof(double),
@@ -391,6 +400,7 @@ int Ctx::persistent(const std::vector<SetDev> &sd, const frg_set *sets, int n_se
     graphs.erase(lru);
   }
   auto g = std::make_unique<GraphEntry>();
+  g->sets.acct = g->tiles.acct = g->counter.acct = &hbm;
   int rc = g->sets.reserve(sd.size() * sizeof(SetDev));
   if (!rc) rc = g->tiles.reserve(tiles.size() * sizeof(Tile));
   if (!rc) rc = g->counter.reserve(kCounterInts * sizeof(int));
@@ -820,6 +830,7 @@ int frg_create(frg_ctx **out, int hip_device, uint64_t hbm_budget_bytes) {
   size_t free_b = 0, total_b = 0;
   hipMemGetInfo(&free_b, &total_b);
   c->hbm_budget = hbm_budget_bytes ? hbm_budget_bytes : free_b / 2;
+  c->hbm.budget = c->hbm_budget;
   c->tune.load_env();
   *out = c.release();
   clear_error();

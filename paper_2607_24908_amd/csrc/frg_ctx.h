@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -28,11 +29,20 @@ void build_tiles(const std::vector<SetDev> &sd, int tile, std::vector<Tile> *til
 int max_table_bytes(const std::vector<SetDev> &sd);
 bool any_fp32c(const std::vector<SetDev> &sd);
 
-// Grow-only device allocation.
+// Bytes of device memory held by a context's working buffers, checked
+// against its HBM budget.
+struct HbmAccount {
+  std::atomic<uint64_t> used{0};
+  uint64_t budget = ~0ull;
+};
+
+// Grow-only device allocation, charged to an account when it has one.
 struct DevBuf {
   void *ptr = nullptr;
   size_t bytes = 0;
+  HbmAccount *acct = nullptr;
   DevBuf() = default;
+  explicit DevBuf(HbmAccount *a) : acct(a) {}
   DevBuf(const DevBuf &) = delete;
   DevBuf &operator=(const DevBuf &) = delete;
   ~DevBuf();
@@ -144,10 +154,11 @@ struct Context {
   std::map<hipStream_t, int *> stream_flags;
   int use_stream_flag(hipStream_t st);
   frg::DescRing ring;
-  frg::DevBuf stage_in, stage_out;
+  frg::HbmAccount hbm;  // the working buffers below, the tables and captured work lists
+  frg::DevBuf stage_in{&hbm}, stage_out{&hbm};
   // segmented tabulated form: partial sums, sorted term lists, their segment
   // offsets, counts + work counter
-  frg::DevBuf tab_part, tab_terms, tab_offs, tab_scr;
+  frg::DevBuf tab_part{&hbm}, tab_terms{&hbm}, tab_offs{&hbm}, tab_scr{&hbm};
   hipEvent_t tab_done = nullptr;   // after the last segmented launch (which used them)
   frg::Tune tune;
   uint64_t tune_gen = 1;  // advanced whenever a knob or a tuned choice changes

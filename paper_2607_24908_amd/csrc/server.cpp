@@ -171,7 +171,9 @@ bool Server::grow_stage(size_t bytes) {
 void Server::admit_locked() {
   while (!queue.empty() && active < max_active && !stop) {
     Flow *f = queue.front();
-    if (used + (uint64_t)f->bytes > budget) break;
+    // the context's own device buffers count against the same budget (a flow
+    // is always admitted when none runs: it fitted on its own at submission)
+    if (active > 0 && used + (uint64_t)f->bytes + ctx->hbm.used.load() > budget) break;
     queue.pop_front();
     used += f->bytes;
     ++active;
@@ -377,8 +379,9 @@ int frg_submit(frg_ctx *ctx, const frg_request *req, uint64_t *ticket) {
   }
   const int64_t bytes = frg_flow_footprint(&req->lpa);
   std::lock_guard<std::mutex> lk(s->m);
-  if ((uint64_t)bytes > s->budget)
-    return fail(FRG_E_NOMEM, "flow footprint %lld B exceeds the HBM budget", (long long)bytes);
+  if ((uint64_t)bytes + ctx->hbm.used.load() > s->budget)
+    return fail(FRG_E_NOMEM, "flow footprint %lld B and the context's buffers exceed the HBM budget",
+                (long long)bytes);
   if (s->queue.size() >= s->max_queue) return fail(FRG_E_AGAIN, "submission queue full");
   Flow *f = new Flow();
   f->srv = s;

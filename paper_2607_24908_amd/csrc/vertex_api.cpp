@@ -21,7 +21,7 @@ int Ctx::vertex_device(const frg_quad &q, int n_phi, int64_t n_c, const double *
   auto it = vtabs.find(key);
   if (it == vtabs.end()) {
     const std::vector<double> t = build_vertex_table(q.d, q.n_angular, n_phi);
-    auto buf = std::make_unique<DevBuf>();
+    auto buf = std::make_unique<DevBuf>(&hbm);
     rc = buf->reserve(t.size() * sizeof(double));
     if (rc) return rc;
     hipError_t e = hipMemcpy(buf->ptr, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice);

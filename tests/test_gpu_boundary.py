@@ -1,7 +1,8 @@
 """Boundary behaviour of the C ABI on the GPU: the domain status of
 asynchronous device calls, concurrent persistent launches on two streams,
-graph replays keyed on the full set descriptors, and tearing down a context
-with flows still waiting for admission."""
+graph replays keyed on the full set descriptors, tearing down a context
+with flows still waiting for admission, and the HBM budget of synchronous
+calls."""
 import numpy as np
 import pytest
 
@@ -166,3 +167,32 @@ def test_destroy_with_flows_waiting_for_admission():
         time.sleep(0.001)
     assert rc == frg.FRG_OK and res.status == frg.FRG_OK
     frg.frg_destroy(c)
+
+
+def test_hbm_budget_bounds_synchronous_calls(ctx):
+    """A context created with a 1 MiB budget: a host-memory call whose staging
+    needs more returns FRG_E_NOMEM and leaves its output untouched; calls that
+    fit run and equal those of an unlimited context bit for bit."""
+    print("[case] hbm budget of synchronous calls", flush=True)
+    quad = frg.make_quad(3, frg.FRG_REG_EXP, 1.0, 6.0, 32, 8)
+    rng = np.random.Generator(np.random.PCG64(8))
+    small = frg.frg_create(0, 1 << 20)
+    try:
+        n_big = 100_000  # p, m2 in, out back: 2.4 MB of staging
+        p = rng.uniform(0.0, 3.0, n_big)
+        m2 = rng.uniform(-0.5, 2.0, n_big)
+        out = np.full(n_big, 7.0)
+        with pytest.raises(frg.FrgError) as ei:
+            frg.frg_integrate(small, [dict(quad=quad, p=p, m2=m2, out=out)], mem=frg.FRG_MEM_HOST)
+        assert ei.value.code == frg.FRG_E_NOMEM
+        assert np.all(out == 7.0)
+        # a call that fits, on the same context, and the same call unlimited
+        got = np.zeros(2000)
+        want = np.zeros(2000)
+        frg.frg_integrate(small, [dict(quad=quad, p=p[:2000], m2=m2[:2000], out=got)],
+                          mem=frg.FRG_MEM_HOST)
+        frg.frg_integrate(ctx, [dict(quad=quad, p=p[:2000], m2=m2[:2000], out=want)],
+                          mem=frg.FRG_MEM_HOST)
+        assert np.array_equal(got, want)
+    finally:
+        frg.frg_destroy(small)
