@@ -256,11 +256,14 @@ def scaleup(ctx):
 
 
 def test_scaleup_d3_sampled_outputs(scaleup):
+    """Every momentum at every 16th mass (131 072 results, 1/16 of the
+    launch), 3000 random results and the corners, against the oracle."""
     w, got = scaleup
     q = w.quad
     rng = np.random.Generator(np.random.PCG64(7))
-    ia = rng.integers(0, w.p.size, 3000)
-    ib = rng.integers(0, w.m2.size, 3000)
+    ga, gb = np.meshgrid(np.arange(w.p.size), np.arange(5, w.m2.size, 16), indexing="ij")
+    ia = np.concatenate([ga.ravel(), rng.integers(0, w.p.size, 3000)])
+    ib = np.concatenate([gb.ravel(), rng.integers(0, w.m2.size, 3000)])
     # always include the corners and the extreme masses
     ia = np.concatenate([ia, [0, 0, w.p.size - 1, w.p.size - 1]])
     ib = np.concatenate([ib, [0, w.m2.size - 1, 0, w.m2.size - 1]])
