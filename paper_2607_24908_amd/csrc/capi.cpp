@@ -319,7 +319,8 @@ void build_tiles(const std::vector<SetDev> &sd, int tile_k, std::vector<Tile> *t
   runs.reserve(2 * sd.size());
   int64_t n_tiles = 0;
   for (int i = 0; i < (int)sd.size(); ++i) {
-    const double w = sd[i].reg == FRG_REG_EXP ? (sd[i].prec == FRG_PREC_FP32C ? 2.0 : 3.0) : 1.0;
+    // cost per evaluation: exponential regulator about three times Litim (FP32C alike)
+    const double w = sd[i].reg == FRG_REG_EXP ? 3.0 : 1.0;
     const double per = w * sd[i].n_r * sd[i].n_a;
     const int tp = tile_points(sd[i], tile_k);
     const int64_t full = sd[i].n_ext / tp, rem = sd[i].n_ext - full * tp;

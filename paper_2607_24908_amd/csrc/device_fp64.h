@@ -270,8 +270,8 @@ __device__ __forceinline__ double hk(double s, double k2, double inv_k2) {
 }
 
 // ---------------------------------------------------- point kernels --
-// Lane partial of one external point for the point-list kernels (plain,
-// persistent, and the FP64 path of the compensated-FP32 kernel).  The sum is
+// Lane partial of one external point for the point-list kernels (plain and
+// persistent, and the FP64 path of FRG_PREC_FP32C sets).  The sum is
 // formed in units of k^2: with y = s/k^2 and dhat = delta/k^2,
 //   mu_j / D_ij = (1/k^2) mu_j / (hh(y_ij) + dhat),   y_ij = ah_i + bh_i (1 + x_j),
 //   ah_i = (q_i - p)^2 / k^2,  bh_i = 2 q_i p / k^2,

@@ -1,5 +1,5 @@
-// Tensor-grid device routines shared by the FP64 grid kernel and the
-// compensated-FP32 grid kernel (included by the .hip translation units only).
+// Tensor-grid device routines of the FP64 grid kernels (included by the .hip
+// translation units only).
 //
 // A workgroup owns one momentum p; the table H'_ij = Hk(s_ij) rmu_j of that p
 // sits in LDS, lane-major: row r = t U + u holds, in lane l = rho + R iota,
@@ -188,12 +188,9 @@ __device__ __forceinline__ int chunk_end(const GridArgs &g, int c0, int C, int T
   return c1;
 }
 
-// Fill rows [c0, c1) of the table of momentum p into lH and, when lH32 is
-// non-null, its compensated-FP32 form lH32 = fl32(H' sig_j) (either may be
-// null).
+// Fill rows [c0, c1) of the table of momentum p into lH.
 template <int REG>
-__device__ __forceinline__ void grid_fill(const GridArgs &g, double *lH, int c0, int c1, double p,
-                                          float *lH32 = nullptr, const double *sig = nullptr) {
+__device__ __forceinline__ void grid_fill(const GridArgs &g, double *lH, int c0, int c1, double p) {
   const double *tq = g.tab;
   const double *to = g.tab + 3 * g.n_r;
   const double *tr = to + 2 * g.n_a;
@@ -216,8 +213,7 @@ __device__ __forceinline__ void grid_fill(const GridArgs &g, double *lH, int c0,
       const double b = (2.0 * q) * p;
       v = hk<REG>(__builtin_fma(b, to[j], aa), g.k2, g.inv_k2) * tr[j];
     }
-    if (lH) lH[(row - c0) * kWave + l] = v;
-    if (lH32) lH32[(row - c0) * kWave + l] = (float)(v * (j < g.n_a ? sig[j] : 1.0));
+    lH[(row - c0) * kWave + l] = v;
     uu += W;
     while (uu >= g.U) {
       uu -= g.U;

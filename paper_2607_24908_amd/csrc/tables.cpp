@@ -152,12 +152,6 @@ QuadTable build_quad_table(const frg_quad &q) {
   return t;
 }
 
-// Angular data of the compensated-FP32 grid kernel.  For each group of eight
-// angular nodes of one lane (j = iota + J u, u = 8g .. 8g + 7, inside the
-// grouped range) a common factor gam is chosen near the geometric mean of the
-// mu_j such that the FP32 values rho_j = fl32(gam / mu_j) give gam / rho_j
-// closest to mu_j: over 2^16 candidates gam0 (1 + n 2^-30) the one with the
-// smallest max_j |rho_j mu_j / gam - 1| is kept.
 LpaTable build_lpa_table(int d, int reg, int n_r, double q_max_over_k) {
   LpaTable t;
   t.n_r = n_r;
