@@ -69,14 +69,14 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device-to-device copy of 1 GiB (PMC traffic calibration)")
-    ap.add_argument("--only", choices=["uneven64", "uneven32", "tab4096", "tab1m", "tab1mseg", "pflow",
+    ap.add_argument("--only", choices=["uneven64", "uneven32", "tab4096", "tab1m", "tab1mcache", "pflow",
                                        "vertex", "fvlpa", "serving"],
                     default=None,
                     help="profiling aid: run only --steps persistent launches of the uneven sets "
                          "(FP64 or FP32C), --steps momentum-flow "
                          "or finite-volume LPA solves or vertex-diagram calls, --steps calls "
-                         "of the tabulated variant (rows of 4096 or 2^20 nodes; tab1mseg: the "
-                         "segmented form), or --steps "
+                         "of the tabulated variant (rows of 4096 or 2^20 nodes, the default "
+                         "form; tab1mcache: 2^20 nodes, cache-streamed), or --steps "
                          "served flow requests (after --warmup more), and print their timing")
     return ap.parse_args()
 
@@ -246,12 +246,12 @@ def main():
         r = serving(frg, workloads, n_warm=args.warmup, n_timed=args.steps)
         print(json.dumps({"only": args.only, **r}), flush=True)
         return
-    if args.only in ("tab4096", "tab1m", "tab1mseg"):
+    if args.only in ("tab4096", "tab1m", "tab1mcache"):
         import torch
         from paper_2607_24908_amd import frg, workloads
         ctx = frg.frg_create(0)
-        if args.only == "tab1mseg":
-            frg.frg_tune_set(ctx, "tab_seg", 1)
+        if args.only == "tab1mcache":
+            frg.frg_tune_set(ctx, "tab_seg", 0)
         n_s = 4096 if args.only == "tab4096" else 1 << 20
         r = tabulated(ctx, frg, workloads, torch, which=(n_s,), reps=args.steps)
         print(json.dumps({"only": args.only, **r[f"tabulated_{n_s}"]}), flush=True)
@@ -611,7 +611,11 @@ def tabulated(ctx, frg, workloads, torch, which=(4096, 1 << 20), reps=None, step
         t = timed(lambda: frg.frg_integrate_tab(ctx, quad, G, w.s_max, P, out), torch,
                   reps or (10 if n_s <= 8192 else 5))
         tb = w.g.nbytes
+        seg = frg.frg_tune_get(ctx, "tab_seg")
+        form = ("rows in LDS" if n_s <= 6144 else
+                "segmented" if seg == 1 or (seg == 2 and tb > 256 * 2 ** 20) else "cache-streamed")
         res[f"tabulated_{n_s}"] = {
+            "form": form,
             "workload": w.name, "ms_per_call": t * 1e3, "evals_per_s": w.n_evals / t,
             "integrals_per_s": w.n_integrals / t, "table_bytes": tb,
             "rows_in_lds": n_s <= 6144, "gathered_bytes_per_eval": 16,

@@ -174,16 +174,19 @@ typedef struct {
  * p[a] >= 0 (a negative p gives NaN in its row of out and FRG_E_DOMAIN as
  * for frg_integrate).  Rows that fit in LDS beside the quadrature tables (up
  * to 6144 nodes, knob "tab_lds_nodes") are staged there; longer rows are read
- * from HBM through the caches, each XCD working through its rows one at a
- * time so that the rows in flight stay in cache; both give the same bits.
- * Knob "tab_seg" = 1 takes the segmented form for longer rows instead:
- * segments of 2048 nodes of four rows at a time are copied into LDS and every
- * evaluation that falls in a segment is done there, its coordinate shared by
- * the four rows (terms sorted by segment once per call); the sum of each
- * result runs over segments in order and does not depend on how the work is
- * split; it agrees with the other forms to rounding and keeps
- * n_p * n_rows * ceil(n_s / 16384) doubles of partial sums and
- * n_p * n_r * n_a 16-bit term indices in context buffers.  mem says where p,
+ * from HBM, either through the caches (each XCD working through its rows one
+ * at a time so that the rows in flight stay in cache; the same bits as the
+ * LDS form) or in the segmented form: segments of 2048 nodes of four rows at
+ * a time are copied into LDS and every evaluation that falls in a segment is
+ * done there, its coordinate shared by the four rows (terms sorted by segment
+ * once per call); the sum of each result runs over segments in order and does
+ * not depend on how the work is split; it agrees with the other forms to
+ * rounding and keeps n_p * n_rows * ceil(n_s / 16384) doubles of partial sums
+ * and n_p * n_r * n_a 16-bit term indices in context buffers.  Knob "tab_seg"
+ * chooses: 2 (the default) the segmented form when the table (n_rows * n_s
+ * doubles) exceeds 256 MiB and its buffers fit the context's HBM budget,
+ * else the cache-streamed form; 1 the segmented form; 0 the cache-streamed
+ * form.  mem says where p,
  * tab->g and out live; n_p * n_rows results. */
 int frg_integrate_tab(frg_ctx *ctx, const frg_quad *quad, const frg_gtab *tab, int64_t n_p,
                       const double *p, double *out, int32_t mem, void *hip_stream);
@@ -451,9 +454,9 @@ int frg_autotune(frg_ctx *ctx, int32_t mode, const char *cache_path);
  * tabulated variant "tab_W" (1..4),
  * "tab_pw" (momenta per wave, 1..64), "tab_lds_nodes" (2..6144),
  * "tab_pairs" (1: rows in LDS as (value, slope) pairs, the default; 0: as
- * values; the same bits), "tab_seg" (0: rows that do not fit in LDS are read
- * through the caches, the default; 1: the segmented form; they agree to
- * rounding), and for cache-streamed rows "tab_wpc" (workgroups per
+ * values; the same bits), "tab_seg" (rows that do not fit in LDS: 0 read
+ * through the caches; 1 the segmented form; 2 the segmented form for tables
+ * above 256 MiB, the default; the forms agree to rounding), and for cache-streamed rows "tab_wpc" (workgroups per
  * CU, 1..16), "tab_sW" (1..4), "tab_spw" (1..64).  Setting a knob drops the
  * tuned choices so that it takes effect.  Two knobs route FRG_PREC_FP32C
  * points to FP64 and do change results (within the FP32 tolerance):

@@ -246,7 +246,7 @@ static bool knob_ok(const char *key, int v) {
   if (!std::strcmp(key, "tab_sW")) return v >= 1 && v <= 4;
   if (!std::strcmp(key, "tab_spw")) return v >= 1 && v <= 64;
   if (!std::strcmp(key, "tab_pairs")) return v == 0 || v == 1;
-  if (!std::strcmp(key, "tab_seg")) return v == 0 || v == 1;
+  if (!std::strcmp(key, "tab_seg")) return v >= 0 && v <= 2;
   if (!std::strcmp(key, "plain_tile") || !std::strcmp(key, "persist_tile")) return v >= 1 && v <= 64;
   if (!std::strcmp(key, "persist_wpc")) return v >= 1 && v <= 64;
   if (!std::strcmp(key, "fp32c_flag_ppb")) return v >= 0;

@@ -656,24 +656,38 @@ int Ctx::tab_launch(TabArgs a, int reg, hipStream_t st) {
   int64_t sblocks = 0;
   int rc = tab_config(a, lds_rows, W, sblocks);
   if (rc) return rc;
-  if (!lds_rows && tune.tab_seg) {
+  // knob tab_seg: 1 always, 2 (auto) when the table is larger than the
+  // chip's memory-side cache: smaller tables are served from that cache and
+  // the cache-streamed form is faster there (measured crossover: 2^20-node
+  // rows, about 48 of them)
+  const bool big = 8.0 * (double)a.n_rows * (double)a.n_s > kTabSegAutoBytes;
+  if (!lds_rows && (tune.tab_seg == 1 || (tune.tab_seg == 2 && big))) {
     // segmented form, when its tables fit: LDS, superchunk count, term index
-    // in 16 bits with the sort in 64 KiB of LDS, counts in 32 bits, partial
-    // sums and term lists up to 1 GiB each
+    // in 16 bits, counts in 32 bits, partial sums and term lists up to 1 GiB
+    // each; in the auto mode also the HBM budget
     const TabSegShape s = tab_seg_shape(a, n_cu);
     const double part_bytes = 8.0 * s.n_super * (double)a.n_rows * (double)a.n_p;
     const double terms_bytes = 2.0 * (double)a.n_p * a.n_r * a.n_a;
     const double offs_bytes = 4.0 * (double)a.n_p * (s.n_seg + 1);
-    if (s.lds <= 160 * 1024 && s.n_super <= kTabSegMaxSuper && s.e_pad <= 16384 &&
-        (double)a.n_p * a.n_r * a.n_a < 4.0e9 && part_bytes <= (double)(1u << 30) &&
-        terms_bytes <= (double)(1u << 30) && offs_bytes <= (double)(1u << 30)) {
+    const size_t scr_bytes = sizeof(unsigned) * (s.n_super + 64);
+    bool fits = s.lds <= 160 * 1024 && s.n_super <= kTabSegMaxSuper && a.n_r * a.n_a <= 65536 &&
+                (double)a.n_p * a.n_r * a.n_a < 4.0e9 && part_bytes <= (double)(1u << 30) &&
+                terms_bytes <= (double)(1u << 30) && offs_bytes <= (double)(1u << 30);
+    if (fits && tune.tab_seg == 2) {
+      auto grow = [](const DevBuf &b, double need) {
+        return need > (double)b.bytes ? std::max(need, 256.0) - (double)b.bytes : 0.0;
+      };
+      const double more = grow(tab_part, part_bytes) + grow(tab_terms, terms_bytes) +
+                          grow(tab_offs, offs_bytes) + grow(tab_scr, (double)scr_bytes);
+      fits = (double)hbm.used.load() + more <= (double)hbm.budget;
+    }
+    if (fits) {
       // the buffers are the context's: a launch on another stream waits for
       // the previous one (a reallocation waits for the device)
       if (!tab_done && hipEventCreateWithFlags(&tab_done, hipEventDisableTiming) != hipSuccess) {
         tab_done = nullptr;
         return fail(FRG_E_DEVICE, "hipEventCreate");
       }
-      const size_t scr_bytes = sizeof(unsigned) * (s.n_super + 64);
       if (tab_part.bytes < (size_t)part_bytes || tab_terms.bytes < (size_t)terms_bytes ||
           tab_offs.bytes < (size_t)offs_bytes || tab_scr.bytes < scr_bytes)
         hipEventSynchronize(tab_done);

@@ -91,7 +91,7 @@ struct Tune {
   int tab_sW = 2;          // tabulated variant, streamed rows: waves per workgroup
   int tab_spw = 1;         // tabulated variant, streamed rows: momenta per wave (at most)
   int tab_pairs = 1;       // tabulated variant: rows in LDS as (value, slope) pairs
-  int tab_seg = 0;         // tabulated variant, rows longer than the LDS: segmented form
+  int tab_seg = 2;         // tabulated variant, rows longer than the LDS: segmented form (2: auto)
   PersistCfg persist;
   int grid_lds_rows = 64;  // (t, u) rows of 64 doubles staged per LDS chunk
   int grid_form = 0;       // resident FP64 grid: 0 per-momentum coefficients, 1 running fractions

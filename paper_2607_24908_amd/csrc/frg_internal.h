@@ -238,11 +238,13 @@ constexpr int kTabSegS = 8;
 constexpr int kTabSegRows = 4;
 constexpr int kTabSegThreads = 1024;
 constexpr int kTabSegMaxSuper = 1024;  // superchunks per row at most (rows of ~16.7M nodes)
+// knob tab_seg = 2: the segmented form for tables larger than the chip's
+// 256 MiB memory-side cache
+constexpr double kTabSegAutoBytes = 256.0 * 1024 * 1024;
 struct TabSegShape {
   int n_seg, n_super, n_batch;
   int target;  // work items per row batch aimed at
   int lds;     // dynamic LDS bytes of the main kernel
-  int e_pad;   // n_r n_a rounded up to a power of two (the sort's LDS keys)
 };
 TabSegShape tab_seg_shape(const TabArgs &t, int n_cu);
 // Device buffers of one launch: part n_super * n_rows * n_p doubles, terms

@@ -5,7 +5,8 @@
 // of kTabSegC nodes and kTabSegS consecutive segments form a superchunk.
 //  1. tab_seg_sort_kernel, once per call: for each momentum, its terms sorted
 //     by (segment of their node index, e) -- a list of e (16 bits) and the
-//     offset of every segment in it; term counts per superchunk.
+//     offset of every segment in it, by a counting sort; term counts per
+//     superchunk.
 //  2. tab_seg_kernel: a work item is (batch of kTabSegRows rows, superchunk,
 //     range of momenta).  Its workgroup copies the superchunk's segments of
 //     its rows into LDS (two buffers: the next segment is copied straight from
@@ -44,7 +45,6 @@ static_assert(kRB == 4, "the run fold leaves one row per group of 16 lanes");
 constexpr int kNT = kTabSegThreads;
 constexpr int kRowLds = kC + 1;           // a segment's nodes and its right neighbour
 constexpr int kBufD = kRB * kRowLds;      // doubles of one segment buffer
-constexpr int kBufW = 2 * kBufD;          // its 4-byte words
 
 // Node index of an evaluation: k = min(floor(min(t, t_last)), k_last),
 // t = fma(bh, 1 + x_j, ah) (the node and fraction of the piecewise-linear
@@ -54,6 +54,14 @@ __device__ __forceinline__ int node_of(double t, double t_last, int k_last) {
   return k < k_last ? k : k_last;
 }
 
+// Lane l's value of v (l wave-uniform).
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
 // Term counts per superchunk (hist) and the work counter, zeroed.
 __global__ void tab_seg_zero_kernel(unsigned *hist, int n_super, int *counter) {
   for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n_super; i += blockDim.x * gridDim.x)
@@ -61,72 +69,140 @@ __global__ void tab_seg_zero_kernel(unsigned *hist, int n_super, int *counter) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
 }
 
-// One workgroup per momentum: the keys (segment, e) of its E = n_r n_a terms
-// in LDS, a bitonic sort (E_pad = next power of two, padding keys last), then
-// terms[p][pos] = e and offs[p][s] = first position of segment >= s
-// (s = 0..n_seg).  Momenta outside the domain get empty runs.
-__global__ __launch_bounds__(256) void tab_seg_sort_kernel(TabArgs a, uint16_t *terms,
-                                                           int *offs, unsigned *hist,
-                                                           int n_seg, int n_super, int e_pad) {
-  extern __shared__ unsigned keys[];
+// Four waves per momentum: its terms e = i n_a + j sorted by (segment, e), a
+// counting sort that uses the structure of the coordinates: for a fixed i
+// the node index grows with j (the angular nodes ascend), so the j of one i
+// that fall in one segment form a chunk of consecutive lanes.  Wave w takes
+// the w-th quarter of the radial nodes.
+//  1. counts per wave and segment: each chunk's head adds the chunk's size;
+//  2. offs[p][s] = first position of segment >= s (exclusive scan over the
+//     segments), and per wave and segment a cursor: the segment's start plus
+//     the counts of the waves before it, so the quarters keep their order;
+//     term counts per superchunk go to hist;
+//  3. i in order within each wave: each chunk's head takes its position
+//     from its wave's cursor and advances it; the chunk's lanes write their e.
+// The order within a segment is ascending e.  Momenta outside the domain get
+// empty runs.
+constexpr int kSortW = 4;
+static_assert(kS <= kWave && kWave % kS == 0, "superchunk sums within a wave's block");
+
+__global__ __launch_bounds__(kSortW * kWave) void tab_seg_sort_kernel(TabArgs a, uint16_t *terms,
+                                                                      int *offs, unsigned *hist,
+                                                                      int n_seg) {
+  extern __shared__ int cnt[];  // [kSortW][n_seg]: counts, then cursors
   const int64_t ip = blockIdx.x;
-  const int E = a.n_r * a.n_a;
-  const int n_a = a.n_a;
+  const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
+  const int n_r = a.n_r, n_a = a.n_a;
+  const int E = n_r * n_a;
   int *po = offs + ip * (n_seg + 1);
   const double p = a.p[ip];
-  if (!(p >= 0.0)) {  // workgroup-uniform
-    for (int x = threadIdx.x; x <= n_seg; x += blockDim.x) po[x] = 0;
+  if (!(p >= 0.0)) {  // uniform over the workgroup
+    for (int x = tid; x <= n_seg; x += kSortW * kWave) po[x] = 0;
     return;
   }
   const int k_last = (int)a.n_s - 2;
-  const double *opx = a.tab + 3 * a.n_r;
-  // keys[x] lives at x + x / 32 (padding against bank conflicts of the
-  // power-of-two strides)
-  for (int e = threadIdx.x; e < e_pad; e += blockDim.x) {
-    unsigned key = 0xffffffffu;
-    if (e < E) {
-      const int i = e / n_a, j = e - i * n_a;
-      const double q = a.tab[i];
+  const double *opx = a.tab + 3 * n_r;
+  for (int x = tid; x < kSortW * n_seg; x += kSortW * kWave) cnt[x] = 0;
+  __syncthreads();
+  int *mine = cnt + w * n_seg;
+  const int i_lo = (int)((int64_t)w * n_r / kSortW), i_hi = (int)((int64_t)(w + 1) * n_r / kSortW);
+  // segment of term (i, jb + lane) (q = q_i, oj = 1 + x_{jb + lane}) and the
+  // chunk structure of this block of up to 64 j: head lanes (first lane or
+  // segment change), chunk sizes, the last head at or before each lane
+  auto chunk = [&](double q, double oj, int jb, int &sg, bool &head, int &size, int &hl) {
+    const bool valid = jb + lane < n_a;
+    sg = -1;
+    if (valid) {
       const double qm = q - p;
       const double ah = (qm * qm) * a.inv_h;
       const double bh = ((2.0 * q) * p) * a.inv_h;
-      const int k = node_of(__builtin_fma(bh, opx[j], ah), a.t_last, k_last);
-      key = (unsigned)(k / kC) * (unsigned)E + (unsigned)e;
+      sg = node_of(__builtin_fma(bh, oj, ah), a.t_last, k_last) / kC;
     }
-    keys[e + (e >> 5)] = key;
+    const int prev = __shfl_up(sg, 1, kWave);
+    head = valid && (lane == 0 || prev != sg);
+    const unsigned long long hm = __builtin_amdgcn_ballot_w64(head);
+    const int nv = min(kWave, n_a - jb);  // valid lanes of the block
+    const unsigned long long above = lane == 63 ? 0ull : hm >> (lane + 1);
+    const int next = above ? lane + 1 + __builtin_ctzll(above) : nv;
+    size = next - lane;
+    const unsigned long long upto = hm & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+    hl = 63 - __builtin_clzll(upto | 1ull);
+  };
+  // radial nodes 64 at a time in a register (q_i by readlane), the first 64
+  // angular nodes in a register
+  const double o0 = lane < n_a ? opx[lane] : 0.0;
+  auto oj_of = [&](int jb) { return jb == 0 ? o0 : (jb + lane < n_a ? opx[jb + lane] : 0.0); };
+  for (int i0 = i_lo; i0 < i_hi; i0 += kWave) {
+    const double qv = i0 + lane < i_hi ? a.tab[i0 + lane] : 0.0;
+    const int ni = min(kWave, i_hi - i0);
+    for (int ii = 0; ii < ni; ++ii) {
+      const double q = readlane_d(qv, ii);
+      for (int jb = 0; jb < n_a; jb += kWave) {
+        int sg, size, hl;
+        bool head;
+        chunk(q, oj_of(jb), jb, sg, head, size, hl);
+        if (head) atomicAdd(&mine[sg], size);
+      }
+    }
   }
   __syncthreads();
-  for (int size = 2; size <= e_pad; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int x = threadIdx.x; x < (e_pad >> 1); x += blockDim.x) {
-        const int lo = 2 * x - (x & (stride - 1));
-        const int hi = lo + stride;
-        const bool up = (lo & size) == 0;
-        const int plo = lo + (lo >> 5), phi = hi + (hi >> 5);
-        const unsigned u = keys[plo], v = keys[phi];
-        if ((u > v) == up) {
-          keys[plo] = v;
-          keys[phi] = u;
+  if (w == 0) {
+    // exclusive scan over the segments, blocks of 64
+    int carry = 0;
+    for (int x0 = 0; x0 < n_seg; x0 += kWave) {
+      const int x = x0 + lane;
+      int c[kSortW], tot = 0;
+#pragma unroll
+      for (int v = 0; v < kSortW; ++v) {
+        c[v] = x < n_seg ? cnt[v * n_seg + x] : 0;
+        tot += c[v];
+      }
+      int incl = tot;
+#pragma unroll
+      for (int d = 1; d < kWave; d <<= 1) {
+        const int t = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += t;
+      }
+      int run = carry + incl - tot;
+      if (x < n_seg) {
+        po[x] = run;
+#pragma unroll
+        for (int v = 0; v < kSortW; ++v) {
+          cnt[v * n_seg + x] = run;
+          run += c[v];
         }
       }
-      __syncthreads();
+      // terms of each superchunk of this block (kS lanes each)
+      int hs = tot;
+#pragma unroll
+      for (int d = 1; d < kS; d <<= 1) hs += __shfl_xor(hs, d, kWave);
+      if (lane % kS == 0 && x < n_seg && hs) atomicAdd(&hist[x / kS], (unsigned)hs);
+      carry += __shfl(incl, kWave - 1, kWave);
     }
+    if (lane == 0) po[n_seg] = carry;  // = E
   }
+  __syncthreads();
   uint16_t *pt = terms + ip * E;
-  for (int pos = threadIdx.x; pos < E; pos += blockDim.x) {
-    const unsigned key = keys[pos + (pos >> 5)];
-    const int sg = (int)(key / (unsigned)E);
-    pt[pos] = (uint16_t)(key - (unsigned)sg * (unsigned)E);
-    const int sp = pos == 0 ? -1 : (int)(keys[pos - 1 + ((pos - 1) >> 5)] / (unsigned)E);
-    for (int x = sp + 1; x <= sg; ++x) po[x] = pos;  // segments sp+1 .. sg start here
-    if (pos == E - 1)
-      for (int x = sg + 1; x <= n_seg; ++x) po[x] = E;
-  }
-  __syncthreads();  // offs written (global memory, this workgroup)
-  for (int c = threadIdx.x; c < n_super; c += blockDim.x) {
-    const int s0 = c * kS, s1 = min(s0 + kS, n_seg);
-    const int cnt = po[s1] - po[s0];
-    if (cnt) atomicAdd(&hist[c], (unsigned)cnt);
+  for (int i0 = i_lo; i0 < i_hi; i0 += kWave) {
+    const double qv = i0 + lane < i_hi ? a.tab[i0 + lane] : 0.0;
+    const int ni = min(kWave, i_hi - i0);
+    for (int ii = 0; ii < ni; ++ii) {
+      const double q = readlane_d(qv, ii);
+      const int i = i0 + ii;
+      for (int jb = 0; jb < n_a; jb += kWave) {
+        int sg, size, hl;
+        bool head;
+        chunk(q, oj_of(jb), jb, sg, head, size, hl);
+        int base = 0;
+        if (head) {
+          base = mine[sg];
+          mine[sg] = base + size;
+        }
+        base = __shfl(base, hl, kWave);
+        const int j = jb + lane;
+        if (j < n_a) pt[base + (lane - hl)] = (uint16_t)(i * n_a + j);
+      }
+    }
   }
 }
 
@@ -143,13 +219,6 @@ __device__ __forceinline__ double super_nodes(const TabArgs &a, int c, int n_seg
   const int64_t k0 = (int64_t)s0 * kC;
   const int64_t k1 = min((int64_t)s1 * kC, a.n_s - 1);
   return (double)(k1 - k0);
-}
-
-__device__ __forceinline__ double readlane_d(double v, int l) {
-  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-  const int lo = __builtin_amdgcn_readlane((int)(unsigned)b, l);
-  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
-  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
 // Work items from the counter until the list is drained.  Momentum ip of an
@@ -260,21 +329,22 @@ __global__ __launch_bounds__(kNT) void tab_seg_kernel(TabArgs a, const unsigned 
     // leaves the row sums of a run
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const int sg0 = c * kS, sg1 = min(sg0 + kS, n_seg);
-    // copy segment sg of the batch's rows into buffer d, 4 bytes per lane and
-    // 256 contiguous bytes of LDS per wave instruction; words beyond the table
-    // or the batch are left unwritten (never read)
+    // copy segment sg of the batch's rows into buffer d: waves w, w + kRB, ...
+    // take row w % kRB, 4 bytes per lane and 256 contiguous bytes of LDS per
+    // wave instruction; words beyond the table are left unwritten (never read)
+    const int lrow = wave % kRB;
+    const unsigned *grow32 = reinterpret_cast<const unsigned *>(a.g + (r0 + lrow) * a.n_s);
+    const int64_t words = 2 * a.n_s;  // 4-byte words of a row
     auto load = [&](int sg, int d) {
-      const int64_t T0 = (int64_t)sg * kC;
-      unsigned *dst = reinterpret_cast<unsigned *>(lg0 + d * kBufD);
-      for (int w = wave; w * kWave < kBufW; w += kWaves) {  // wave-uniform
-        const int x = w * kWave + lane;
-        const int r = x / (2 * kRowLds), rem = x - r * 2 * kRowLds;
-        if (x < kBufW && r < nrb && T0 + (rem >> 1) < a.n_s) {
-          const unsigned *src =
-              reinterpret_cast<const unsigned *>(a.g + (r0 + r) * a.n_s + T0) + rem;
+      if (lrow >= nrb) return;  // wave-uniform: no such row in the batch
+      const int64_t w0 = 2 * (int64_t)sg * kC;
+      unsigned *dst = reinterpret_cast<unsigned *>(lg0 + d * kBufD + lrow * kRowLds);
+      for (int m = wave / kRB; m * kWave < 2 * kRowLds; m += kWaves / kRB) {  // wave-uniform
+        const int x = m * kWave + lane;
+        if (x < 2 * kRowLds && w0 + x < words)
           __builtin_amdgcn_global_load_lds(
-              src, (__attribute__((address_space(3))) void *)(dst + w * kWave), 4, 0, 0);
-        }
+              grow32 + w0 + x, (__attribute__((address_space(3))) void *)(dst + m * kWave), 4, 0,
+              0);
       }
     };
     load(sg0, 0);
@@ -380,9 +450,6 @@ TabSegShape tab_seg_shape(const TabArgs &t, int n_cu) {
   s.n_batch = (int)((t.n_rows + kRB - 1) / kRB);
   const int64_t want = 4LL * n_cu;
   s.target = (int)std::max<int64_t>(s.n_super, (want + s.n_batch - 1) / s.n_batch);
-  int e_pad = 1;
-  while (e_pad < t.n_r * t.n_a) e_pad <<= 1;
-  s.e_pad = e_pad;
   s.lds = (int)(sizeof(double) * (2 * kBufD + t.n_r + kRB * t.n_r + 2 * t.n_a) +
                 sizeof(int) * 2 * s.n_super + sizeof(long long) * (s.n_super + 1) + sizeof(int));
   return s;
@@ -395,12 +462,13 @@ int launch_tab_seg(const TabArgs &t, const TabSegShape &s, const TabSegBufs &b, 
   static const bool once =
       ((void)hipFuncSetAttribute((const void *)&tab_seg_kernel,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024),
+       (void)hipFuncSetAttribute((const void *)&tab_seg_sort_kernel,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024),
        (void)hipGetLastError(), true);
   (void)once;
   hipLaunchKernelGGL(tab_seg_zero_kernel, dim3(1), dim3(256), 0, st, b.hist, s.n_super, b.counter);
-  hipLaunchKernelGGL(tab_seg_sort_kernel, dim3((unsigned)t.n_p), dim3(256),
-                     sizeof(unsigned) * (s.e_pad + s.e_pad / 32), st, t, b.terms, b.offs, b.hist, s.n_seg,
-                     s.n_super, s.e_pad);
+  hipLaunchKernelGGL(tab_seg_sort_kernel, dim3((unsigned)t.n_p), dim3(kSortW * kWave),
+                     sizeof(int) * kSortW * s.n_seg, st, t, b.terms, b.offs, b.hist, s.n_seg);
   hipLaunchKernelGGL(tab_seg_kernel, dim3((unsigned)n_cu), dim3(kNT), (size_t)s.lds, st, t,
                      (const unsigned *)b.hist, (const uint16_t *)b.terms, (const int *)b.offs,
                      b.counter, b.part, s.n_seg, s.n_super, s.n_batch, s.target);

@@ -151,6 +151,30 @@ def test_tab_segmented_bits_independent_of_the_split(ctx):
     frg.frg_tune_set(ctx, "tab_seg", 0)
 
 
+def test_tab_auto_mode_picks_by_table_size(ctx):
+    """Knob tab_seg = 2, the default: a table above 256 MiB takes the
+    segmented form, a smaller one the cache-streamed form (the bits of
+    tab_seg = 1 and 0); a context whose HBM budget cannot hold the segmented
+    form's buffers takes the cache-streamed form instead of failing."""
+    fresh = frg.frg_create(0)
+    small = frg.frg_create(0, 1 << 20)
+    try:
+        assert frg.frg_tune_get(fresh, "tab_seg") == 2
+        w = workloads.tabulated_d3(n_s=1 << 20, n_p=256, n_rows=36)  # 288 MiB
+        print(f"[case] tabulated auto mode {w.name}", flush=True)
+        seg = run_tab(ctx, w.quad, w.g, w.s_max, w.p, seg=1)
+        cache = run_tab(ctx, w.quad, w.g, w.s_max, w.p, seg=0)
+        assert not np.array_equal(seg, cache)  # the forms round differently
+        assert np.array_equal(run_tab(ctx, w.quad, w.g, w.s_max, w.p, seg=2), seg)
+        assert np.array_equal(run_tab(small, w.quad, w.g, w.s_max, w.p, seg=2), cache)
+        # 30 rows: 240 MiB
+        assert np.array_equal(run_tab(ctx, w.quad, w.g[:30], w.s_max, w.p, seg=2), cache[:, :30])
+    finally:
+        frg.frg_destroy(small)
+        frg.frg_destroy(fresh)
+        frg.frg_tune_set(ctx, "tab_seg", 0)
+
+
 def test_tab_bench_shape_sampled(ctx):
     """The LDS-row bench workload (1024 momenta x 64 rows of 4096 nodes) on
     a sample of momenta against the oracle."""
