@@ -69,14 +69,15 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device-to-device copy of 1 GiB (PMC traffic calibration)")
-    ap.add_argument("--only", choices=["uneven64", "uneven32", "tab4096", "tab1m", "tab1mcache", "pflow",
+    ap.add_argument("--only", choices=["uneven64", "uneven32", "tab4096", "tab1m", "tab1mcache", "tabsweep", "pflow",
                                        "vertex", "fvlpa", "serving"],
                     default=None,
                     help="profiling aid: run only --steps persistent launches of the uneven sets "
                          "(FP64 or FP32C), --steps momentum-flow "
                          "or finite-volume LPA solves or vertex-diagram calls, --steps calls "
                          "of the tabulated variant (rows of 4096 or 2^20 nodes, the default "
-                         "form; tab1mcache: 2^20 nodes, cache-streamed), or --steps "
+                         "form; tab1mcache: 2^20 nodes, cache-streamed; tabsweep: both long-row "
+                         "forms over rows, row lengths and momenta), or --steps "
                          "served flow requests (after --warmup more), and print their timing")
     return ap.parse_args()
 
@@ -245,6 +246,11 @@ def main():
         from paper_2607_24908_amd import frg, workloads
         r = serving(frg, workloads, n_warm=args.warmup, n_timed=args.steps)
         print(json.dumps({"only": args.only, **r}), flush=True)
+        return
+    if args.only == "tabsweep":
+        import torch
+        from paper_2607_24908_amd import frg, workloads
+        tab_forms_sweep(frg.frg_create(0), frg, workloads, torch)
         return
     if args.only in ("tab4096", "tab1m", "tab1mcache"):
         import torch
@@ -624,6 +630,35 @@ def tabulated(ctx, frg, workloads, torch, which=(4096, 1 << 20), reps=None, step
             f"gathered {16 * w.n_evals / t / 1e9:.0f} GB/s")
         del G
     return res
+
+
+def tab_forms_sweep(ctx, frg, workloads, torch):
+    """Both forms of rows longer than the LDS (knob tab_seg 0: cache-streamed,
+    1: segmented) on the same inputs over rows, row lengths and momenta:
+    host-timed ms per call (10 after 3) and their largest relative
+    difference, one JSON line per shape."""
+    for n_s in (1 << 14, 1 << 16, 1 << 20):
+        for n_p in (64, 1024):
+            for n_rows in (1, 4, 16, 64):
+                w = workloads.tabulated_d3(n_s=n_s, n_p=n_p, n_rows=n_rows)
+                q = w.quad
+                quad = frg.make_quad(q.d, q.reg, q.k, q.q_max, q.n_r, q.n_a)
+                G = torch.as_tensor(w.g, device="cuda")
+                P = torch.as_tensor(w.p, device="cuda")
+                ms, outs = {}, {}
+                for seg in (0, 1):
+                    frg.frg_tune_set(ctx, "tab_seg", seg)
+                    out = torch.empty(w.n_integrals, dtype=torch.float64, device="cuda")
+                    ms[seg] = timed(lambda: frg.frg_integrate_tab(ctx, quad, G, w.s_max, P, out),
+                                    torch, 10) * 1e3
+                    outs[seg] = out.cpu().numpy()
+                rel = float(np.max(np.abs(outs[1] - outs[0]) / np.abs(outs[0])))
+                print(json.dumps({"n_s": n_s, "n_p": n_p, "n_rows": n_rows,
+                                  "table_MiB": w.g.nbytes / 2 ** 20, "cache_ms": ms[0],
+                                  "segmented_ms": ms[1], "cache_over_segmented": ms[0] / ms[1],
+                                  "max_rel_diff": rel}), flush=True)
+                del G
+    frg.frg_tune_set(ctx, "tab_seg", 2)
 
 
 def serving(frg, workloads, n_warm=50, n_timed=1000, seed=0, rate=50.0):
