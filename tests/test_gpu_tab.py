@@ -82,6 +82,33 @@ def test_tab_matches_oracle_and_forms_agree(ctx, d, reg, n_r, n_a):
     assert np.all(np.abs(segmented - got) <= 1e-13 * np.abs(got))
 
 
+@pytest.mark.parametrize("d,reg,n_r,n_a", [(3, 0, 1, 130), (4, 1, 3, 65), (3, 0, 5, 256),
+                                           (5, 0, 70, 200), (3, 1, 9, 64), (4, 0, 300, 256)])
+def test_tab_segmented_sort_shapes(ctx, d, reg, n_r, n_a):
+    """The segmented form's term sort over rules whose angular nodes span one
+    to four blocks of 64 lanes and whose radial nodes are fewer than, equal
+    to or more than its four waves, on rows of 11 segments (the last one
+    ragged): against the oracle, and within 1e-13 of the cache-streamed form.
+    300 x 256 terms exceed its 16-bit term index: the call takes the
+    cache-streamed form (the same bits)."""
+    print(f"[case] segmented sort d={d} reg={reg} {n_r}x{n_a}", flush=True)
+    q = workloads.Quad(d, reg, 0.9, 5.4, n_r, n_a)
+    rng = np.random.Generator(np.random.PCG64(7 * n_r + n_a))
+    p = np.concatenate([[0.0, 1e-9], 10 ** rng.uniform(-3, 1.2, 29)])
+    s_max = 40.0
+    g = workloads.tab_rows(5, 20483, s_max)
+    seg = run_tab(ctx, q, g, s_max, p, lds_nodes=2, seg=1)
+    cache = run_tab(ctx, q, g, s_max, p, lds_nodes=2, seg=0)
+    want = want_of(q, g, s_max, p)
+    err = np.abs(seg - want) / np.abs(want)
+    print(f"max rel err {err.max():.3e}")
+    assert err.max() < RTOL
+    assert np.all(np.abs(seg - cache) <= 1e-13 * np.abs(cache))
+    if n_r * n_a > 65536:
+        assert np.array_equal(seg, cache)
+    frg.frg_tune_set(ctx, "tab_seg", 0)
+
+
 @pytest.mark.parametrize("n_s,form", [(4097, "lds"), (4097, "cache"), (4097, "seg"),
                                       (40961, "seg"), (1 << 20, "seg"), (1 << 20, "cache")])
 def test_tab_rough_rows_within_coordinate_bound(ctx, n_s, form):
