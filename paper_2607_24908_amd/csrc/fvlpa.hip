@@ -151,6 +151,33 @@ __device__ __forceinline__ void fv_interface(const FvArgs &a, const FvScale &sc,
   }
 }
 
+// Interface 0 (flux N/2 F_1(2 u_0/ds), one mass) by a whole wave: lane l
+// takes radial nodes l, l + 64, ..., then the fixed-order wave sum, so every
+// lane returns the same Q, lam, bad.  The fused solve and the flux kernel
+// both take interface 0 this way (the same bits); a group of eight lanes
+// would need eight times as long, and in the fused solve with n a multiple
+// of the group count it is the one interface of a third round.
+__device__ __forceinline__ void fv_interface0(const FvArgs &a, const FvScale &sc, const double *u,
+                                              const double *tab, int lane, double &Q, double &lam,
+                                              bool &bad) {
+  const double ids = a.inv_ds;
+  const double delta = 2.0 * u[0] * ids + sc.k2;
+  bad = !(delta > 0.0);
+  const double dh = delta > 0.0 ? delta * sc.inv_k2 : 1.0;
+  double s1 = 0.0, s2 = 0.0;
+  for (int i = lane; i < a.n_r; i += kWave) {
+    const double c = tab[i], hh = tab[a.n_r + i];
+    const double G = rcp64(hh + dh);
+    const double cg = c * G;
+    s1 += cg;
+    s2 = __builtin_fma(cg, G, s2);
+  }
+  const double F1 = a.Cd * sc.kd * wave_sum_fold<1>(&s1, lane);
+  const double F2 = a.Cd * sc.kdm2 * wave_sum_fold<1>(&s2, lane);
+  Q = 0.5 * (double)a.N * F1;
+  lam = 2.0 * (0.5 * (double)a.N * F2) * (ids * ids);
+}
+
 // SSP-RK3 stage `stage` (0..2) of one cell with right-hand side L.
 __device__ __forceinline__ void fv_update(int stage, double L, double h, double &y0, double &ys) {
   switch (stage) {
@@ -189,6 +216,16 @@ __global__ __launch_bounds__(256) void fv_flux_kernel(FvArgs a) {
   double Q, lam;
   bool bad;
   fv_interface(a, sc, u, a.tab, j, sub, live, Q, lam, bad);
+  if (blockIdx.x == 0 && wave == 0) {  // the wave of interface 0
+    double q0, l0;
+    bool b0;
+    fv_interface0(a, sc, u, a.tab, lane, q0, l0, b0);
+    if (j == 0) {
+      Q = q0;
+      lam = l0;
+      bad = b0;
+    }
+  }
   if (!live || sub != 0) return;
   if (bad) {
     // the flow ends at the start of this step with its state kept
@@ -229,9 +266,8 @@ __global__ __launch_bounds__(256) void fv_stage_kernel(FvArgs a) {
 
 // Steps [s0, s0 + n_st) of one flow per workgroup: state, stage state,
 // fluxes and the radial table in LDS; per stage the fluxes of all n + 1
-// interfaces (groups of eight lanes over interfaces 1..n, interface 0 with
-// the group that holds one interface fewer), a barrier, the cell updates, a
-// barrier.  The per-interface and per-cell arithmetic is that of the flux
+// interfaces (groups of eight lanes over interfaces 1..n, interface 0 by one
+// wave), a barrier, the cell updates, a barrier.  The per-interface and per-cell arithmetic is that of the flux
 // and stage kernels (same bits); no launch per stage.  A flow whose masses
 // leave the domain in a stage ends with the state of the start of that step.
 __global__ __launch_bounds__(1024) void fv_solve_kernel(FvArgs a, int64_t s0, int64_t n_st) {
@@ -250,7 +286,10 @@ __global__ __launch_bounds__(1024) void fv_solve_kernel(FvArgs a, int64_t s0, in
   if (tid == 0) *bad_flag = 0;
   __syncthreads();
   const int G = bs / 8, grp = tid / 8, sub = tid & 7;
-  const int j0grp = (int)(n % G);  // holds one interface fewer (or as many)
+  // interface 0 by a wave whose groups hold one interface fewer than the
+  // first groups (groups n % G and up), or wave 0 when all hold as many
+  int wave0 = ((int)(n % G) + 7) / 8;
+  if (wave0 >= G / 8) wave0 = 0;
   const double cs[3] = {0.0, 1.0, 0.5};
   for (int64_t st = 0; st < n_st; ++st) {
     const double tn = (double)(s0 + st) * a.h;
@@ -265,11 +304,11 @@ __global__ __launch_bounds__(1024) void fv_solve_kernel(FvArgs a, int64_t s0, in
         if (sub == 0) Q[j] = q;
         bad |= b;
       }
-      if (grp == j0grp) {
+      if (tid / kWave == wave0) {  // wave-uniform
         double q, lam;
         bool b;
-        fv_interface(a, sc, u, tab, 0, sub, true, q, lam, b);
-        if (sub == 0) Q[0] = q;
+        fv_interface0(a, sc, u, tab, tid & (kWave - 1), q, lam, b);
+        if ((tid & (kWave - 1)) == 0) Q[0] = q;
         bad |= b;
       }
       if (bad) *bad_flag = 1;

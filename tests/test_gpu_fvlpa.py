@@ -42,7 +42,7 @@ def initial(rng, n_flows, n, smax, broken=False):
 
 
 CASES = [(3, 1, EXP, 32, 16, 2.0), (3, 4, EXP, 64, 40, 2.0), (4, 2, LIT, 24, 33, 1.5),
-         (3, 4, LIT, 100, 7, 1.0), (2, 3, EXP, 16, 2, 0.5)]
+         (3, 4, LIT, 100, 7, 1.0), (2, 3, EXP, 16, 2, 0.5), (3, 2, EXP, 64, 128, 2.0)]
 
 
 @pytest.mark.parametrize("d,N,reg,n_r,n,smax", CASES)
@@ -157,7 +157,8 @@ def test_bad_arguments(ctx):
         frg.frg_fvlpa_solve(ctx, fv, -1.0, 0, u, tr, mem=frg.FRG_MEM_HOST)
 
 
-@pytest.mark.parametrize("case,n_flows,steps", [(1, 4, 60), (3, 300, 40), (4, 600, 2100)])
+@pytest.mark.parametrize("case,n_flows,steps", [(1, 4, 60), (3, 300, 40), (4, 600, 2100),
+                                                (5, 4, 50), (5, 300, 30)])
 def test_fused_and_per_stage_solves_same_bits(ctx, case, n_flows, steps):
     """The fused solve (one workgroup per flow, cells in LDS; 1024, 512 or
     256 threads by the number of flows; launches of at most 2048 steps) and
