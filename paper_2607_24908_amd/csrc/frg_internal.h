@@ -40,10 +40,21 @@ QuadTable build_quad_table(const frg_quad &q);
 //   [n_r, 2n_r)    hhat_i = h(qhat_i^2)
 // so that F_n(m^2) = C_d k^{d+2-2n} sum_i chat_i / (hhat_i + delta/k^2)^n.
 struct LpaTable {
-  std::vector<double> data;
+  std::vector<double> data;  // chat (n_r) | hhat (n_r) | coefficient groups (fv_groups(n_r))
   double Cd;
   int n_r;
 };
+// Coefficient groups of the radial sums of the finite-volume flux: nodes
+// 8g .. 8g + 7 (padded with c = 0, h = 1) form group g, stored as
+// [a_0..a_7 | b_0..b_7 | m_0..m_14] with
+//   P(x) = prod_l (x + h_l) = x^8 + sum_{k<8} a_k x^k,
+//   N(x) = sum_i c_i prod_{l != i} (x + h_l) = sum_{k<8} b_k x^k,
+//   M(x) = sum_i c_i prod_{l != i} (x + h_l)^2 = sum_{k<15} m_k x^k,
+// so that sum_i c_i/(x + h_i) = N/P and sum_i c_i/(x + h_i)^2 = M/P^2 over the
+// group.  Every coefficient is >= 0.
+constexpr int kFvGroup = 8;
+constexpr int kFvCoef = 31;
+inline int fv_groups(int n_r) { return (n_r + kFvGroup - 1) / kFvGroup; }
 LpaTable build_lpa_table(int d, int reg, int n_r, double q_max_over_k);
 
 double omega_sphere(int n);  // area of S^{n-1}
@@ -197,7 +208,8 @@ int launch_fv_dt(const FvArgs &a, void *stream);
 // Steps [s0, s0 + n_st) of a solve, one workgroup of `threads` per flow with
 // its state in LDS (fv_solve_lds_bytes); alive, t_reached and flag set up by
 // launch_fv_init.
-int fv_solve_lds_bytes(const FvArgs &a);
+int64_t fv_solve_lds_bytes(const FvArgs &a);
+constexpr int kFvSolveLdsMax = 160 * 1024;
 int launch_fv_solve(const FvArgs &a, int64_t s0, int64_t n_st, int threads, void *stream);
 int launch_pflow_init(const PflowArgs &a, double t_end, void *stream);
 int launch_pflow_prep(const PflowArgs &a, int reg, void *stream);

@@ -46,14 +46,6 @@ __global__ __launch_bounds__(256) void fv_init_kernel(FvArgs a, double t_end) {
   }
 }
 
-// Sum over the 8 lanes of an aligned group (xor 1, xor 2, then the mirror
-// of the 8 lanes, equivalent to xor 4 once each quad holds equal values).
-__device__ __forceinline__ double group8_sum(double x) {
-  x = x + dpp_f64<0xB1>(x);
-  x = x + dpp_f64<0x4E>(x);
-  return x + dpp_f64<0x141>(x);
-}
-
 // Scales of the stage at RG time t: k = lambda e^t, k^2, 1/k^2, k^d, k^(d-2)
 // (integer powers by products).  Every kernel forms them the same way.
 struct FvScale {
@@ -71,31 +63,36 @@ __device__ __forceinline__ FvScale fv_scale(const FvArgs &a, double t) {
   return sc;
 }
 
-// Flux Q and the local bound lam of the step estimate at interface j of one
-// flow with cell values u[0..n) (global memory or LDS) and radial table tab
-// (chat | hhat, global memory or LDS); the eight lanes of an aligned group
-// (sub = 0..7) take radial nodes sub, sub + 8, ... of F_1, F_2 at up to three
-// masses (d_sigma u and the two Goldstone states) and meet in group8_sum, so
-// every lane of the group returns the same Q, lam.  bad: a mass of a live
-// interface has left the domain.  Interfaces past n (not live) load clamped
-// cells; their results are not used.
-__device__ __forceinline__ void fv_interface(const FvArgs &a, const FvScale &sc, const double *u,
-                                             const double *tab, int64_t j, int sub, bool live,
-                                             double &Q, double &lam, bool &bad) {
-  const int64_t n = a.n;
+// The masses of interface j of one flow with cell values u[0..n) (global
+// memory or LDS): d_sigma u and, on the Goldstone part (j > 0, N > 1), the
+// limited states u-/sigma_j and u+/sigma_j (nm masses).  dh[m] =
+// (m^2 + k^2)/k^2 for the masses in the domain (1 elsewhere); bad: one of them
+// has left it.  The four neighbouring cells are loaded at clamped indices
+// (issued together) and the ghost rules applied afterwards.
+struct FvIface {
+  double dh[3];
+  double um, up, isj;
+  int nm;
+  bool bad;
+};
+__device__ __forceinline__ FvIface fv_prep(const FvArgs &a, const FvScale &sc, const double *u,
+                                           int j) {
+  const int n = (int)a.n;  // at most 2^24 cells
   const double ids = a.inv_ds;
-  // cells j-2 .. j+1 with the ghost cells: loads at clamped indices first
-  // (issued together), the ghost rules after
-  const int64_t nm1 = n - 1;
-  auto cl = [&](int64_t i) { return i < 0 ? (int64_t)0 : (i > nm1 ? nm1 : i); };
+  const int nm1 = n - 1;
+  auto cl = [&](int i) { return i < 0 ? 0 : (i > nm1 ? nm1 : i); };
   const double v0 = u[cl(j - 2)], v1 = u[cl(j - 1)], v2 = u[cl(j)], v3 = u[cl(j + 1)];
   const double e0 = u[0], e1 = u[1], f1 = u[nm1], f2 = u[n - 2];
   const double gn = 2.0 * f1 - f2, gn1 = 2.0 * gn - f1;
-  auto cell = [&](int64_t i, double v) {
+  auto cell = [&](int i, double v) {
     return i == -1 ? -e0 : i == -2 ? -e1 : i == n ? gn : i == n + 1 ? gn1 : v;
   };
-  const bool gold = j > 0 && a.N > 1;
-  double ms, um = 0.0, up = 0.0, isj = 0.0;
+  FvIface f;
+  f.nm = (j > 0 && a.N > 1) ? 3 : 1;
+  f.um = 0.0;
+  f.up = 0.0;
+  f.isj = 0.0;
+  double ms;
   if (j == 0) {
     ms = 2.0 * e0 * ids;
   } else {
@@ -104,78 +101,89 @@ __device__ __forceinline__ void fv_interface(const FvArgs &a, const FvScale &sc,
     ms = (uR - uL) * ids;
     const double sL = minmod(uL - uLL, uR - uL);
     const double sR = minmod(uR - uL, uRR - uR);
-    um = uL + 0.5 * sL;
-    up = uR - 0.5 * sR;
-    isj = ids / (double)j;  // 1/sigma_j
+    f.um = uL + 0.5 * sL;
+    f.up = uR - 0.5 * sR;
+    f.isj = ids / (double)j;  // 1/sigma_j
   }
-  const double m2[3] = {ms, um * isj, up * isj};
-  const int nm = gold ? 3 : 1;
-  bad = false;
-  double dh[3];
+  const double m2[3] = {ms, f.um * f.isj, f.up * f.isj};
+  f.bad = false;
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
     const double delta = m2[m] + sc.k2;
-    bad |= live && m < nm && !(delta > 0.0);
-    dh[m] = (m < nm && delta > 0.0) ? delta * sc.inv_k2 : 1.0;
+    f.bad |= m < f.nm && !(delta > 0.0);
+    f.dh[m] = (m < f.nm && delta > 0.0) ? delta * sc.inv_k2 : 1.0;
   }
-  double s1[3] = {0.0, 0.0, 0.0}, s2[3] = {0.0, 0.0, 0.0};
-  for (int i = sub; i < a.n_r; i += 8) {
-    const double c = tab[i], hh = tab[a.n_r + i];
+  return f;
+}
+
+// s1 = sum_i chat_i/(hhat_i + x) and s2 = sum_i chat_i/(hhat_i + x)^2 over
+// all radial nodes, in one lane.  For x in [kFvXMin, kFvXMax] the table's
+// coefficient groups in order: N/P and M/P^2 by Horner with one reciprocal per
+// group of eight nodes (the powers of x and the products stay inside the
+// FP64 range there); term by term outside it.  Every term and coefficient is
+// positive and x > 0, so neither form cancels.
+constexpr double kFvXMin = 1e-20, kFvXMax = 1e20;
+__device__ __forceinline__ void fv_radial(const FvArgs &a, const double *tab,
+                                          const double *__restrict__ cf, double x, double &s1,
+                                          double &s2) {
+  s1 = 0.0;
+  s2 = 0.0;
+  if (x >= kFvXMin && x <= kFvXMax) {
+    const int ng = (a.n_r + kFvGroup - 1) / kFvGroup;
+    for (int g = 0; g < ng; ++g) {
+      const double *c = cf + kFvCoef * g;
+      double P = x + c[7];
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      if (m >= nm) break;
-      const double G = rcp64(hh + dh[m]);
-      const double cg = c * G;
-      s1[m] += cg;
-      s2[m] = __builtin_fma(cg, G, s2[m]);
+      for (int k = 6; k >= 0; --k) P = __builtin_fma(P, x, c[k]);
+      double N = c[15];
+#pragma unroll
+      for (int k = 14; k >= 8; --k) N = __builtin_fma(N, x, c[k]);
+      double M = c[30];
+#pragma unroll
+      for (int k = 29; k >= 16; --k) M = __builtin_fma(M, x, c[k]);
+      const double r = rcp64(P);
+      s1 = __builtin_fma(N, r, s1);
+      s2 = __builtin_fma(M * r, r, s2);
+    }
+  } else {
+    for (int i = 0; i < a.n_r; ++i) {
+      const double G = rcp64(tab[a.n_r + i] + x);
+      const double cg = tab[i] * G;
+      s1 += cg;
+      s2 = __builtin_fma(cg, G, s2);
     }
   }
-  double F1[3], F2[3];
-#pragma unroll
-  for (int m = 0; m < 3; ++m) {
-    F1[m] = a.Cd * sc.kd * group8_sum(s1[m]);
-    F2[m] = a.Cd * sc.kdm2 * group8_sum(s2[m]);
-  }
+}
+
+// F_1 = C_d k^d s1 and F_2 = C_d k^(d-2) s2 at dh = x.
+__device__ __forceinline__ void fv_mass(const FvArgs &a, const FvScale &sc, const double *tab,
+                                        const double *__restrict__ cf, double x, double &F1,
+                                        double &F2) {
+  double s1, s2;
+  fv_radial(a, tab, cf, x, s1, s2);
+  F1 = a.Cd * sc.kd * s1;
+  F2 = a.Cd * sc.kdm2 * s2;
+}
+
+// Flux Q and the local bound lam of the step estimate at interface j from
+// its masses and F1[m], F2[m] at them.
+__device__ __forceinline__ void fv_flux(const FvArgs &a, const FvIface &f, int j,
+                                        const double *F1, const double *F2, double &Q,
+                                        double &lam) {
+  const double ids = a.inv_ds;
   if (j == 0) {
     Q = 0.5 * (double)a.N * F1[0];
     lam = 2.0 * (0.5 * (double)a.N * F2[0]) * (ids * ids);
   } else {
     Q = 0.5 * F1[0];
     lam = 2.0 * (0.5 * F2[0]) * (ids * ids);
-    if (gold) {
+    if (f.nm == 3) {
       const double c = 0.5 * (double)(a.N - 1);
-      const double am = fmax(c * F2[1] * isj, c * F2[2] * isj);
-      Q += 0.5 * (c * F1[1] + c * F1[2]) - 0.5 * am * (up - um);
+      const double am = fmax(c * F2[1] * f.isj, c * F2[2] * f.isj);
+      Q += 0.5 * (c * F1[1] + c * F1[2]) - 0.5 * am * (f.up - f.um);
       lam += am * ids;
     }
   }
-}
-
-// Interface 0 (flux N/2 F_1(2 u_0/ds), one mass) by a whole wave: lane l
-// takes radial nodes l, l + 64, ..., then the fixed-order wave sum, so every
-// lane returns the same Q, lam, bad.  The fused solve and the flux kernel
-// both take interface 0 this way (the same bits); a group of eight lanes
-// would need eight times as long, and in the fused solve with n a multiple
-// of the group count it is the one interface of a third round.
-__device__ __forceinline__ void fv_interface0(const FvArgs &a, const FvScale &sc, const double *u,
-                                              const double *tab, int lane, double &Q, double &lam,
-                                              bool &bad) {
-  const double ids = a.inv_ds;
-  const double delta = 2.0 * u[0] * ids + sc.k2;
-  bad = !(delta > 0.0);
-  const double dh = delta > 0.0 ? delta * sc.inv_k2 : 1.0;
-  double s1 = 0.0, s2 = 0.0;
-  for (int i = lane; i < a.n_r; i += kWave) {
-    const double c = tab[i], hh = tab[a.n_r + i];
-    const double G = rcp64(hh + dh);
-    const double cg = c * G;
-    s1 += cg;
-    s2 = __builtin_fma(cg, G, s2);
-  }
-  const double F1 = a.Cd * sc.kd * wave_sum_fold<1>(&s1, lane);
-  const double F2 = a.Cd * sc.kdm2 * wave_sum_fold<1>(&s2, lane);
-  Q = 0.5 * (double)a.N * F1;
-  lam = 2.0 * (0.5 * (double)a.N * F2) * (ids * ids);
 }
 
 // SSP-RK3 stage `stage` (0..2) of one cell with right-hand side L.
@@ -193,19 +201,21 @@ __device__ __forceinline__ void fv_update(int stage, double L, double h, double 
   }
 }
 
-// Grid (blocks of 32 interfaces, flows): eight interfaces per wave, eight
-// lanes per interface (fv_interface) at the stage time a.t.
-__global__ __launch_bounds__(256) void fv_flux_kernel(FvArgs a) {
+// Grid (blocks of 4 kFvPerWave interfaces, flows) at the stage time a.t:
+// lane 3 i + m of a wave computes mass m of the wave's interface i
+// (fv_mass), lane 3 i gathers the three and stores Q, lam (lane 63 idles).
+constexpr int kFvPerWave = kWave / 3;
+__global__ __launch_bounds__(256) void fv_flux_kernel(FvArgs a, const double *__restrict__ cf) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
-  const int sub = lane & 7;
   const int64_t r = blockIdx.y;
   const int64_t n = a.n, nq = n + 1;
-  const int64_t j = ((int64_t)blockIdx.x * (blockDim.x / kWave) + wave) * 8 + (lane >> 3);
-  const bool live = j < nq;  // every lane takes part in the group sums
+  const int il = lane / 3, m = lane - 3 * il;
+  const int64_t j = ((int64_t)blockIdx.x * (blockDim.x / kWave) + wave) * kFvPerWave + il;
+  const bool live = il < kFvPerWave && j < nq;
   const int64_t o = r * nq + j;
   if (!a.alive[r]) {  // workgroup-uniform
-    if (live && sub == 0) {
+    if (live && m == 0) {
       a.Q[o] = 0.0;
       a.lam[o] = 0.0;
     }
@@ -213,21 +223,18 @@ __global__ __launch_bounds__(256) void fv_flux_kernel(FvArgs a) {
   }
   const double *u = (a.first ? a.y0 : a.ys) + r * n;
   const FvScale sc = fv_scale(a, a.t);
-  double Q, lam;
-  bool bad;
-  fv_interface(a, sc, u, a.tab, j, sub, live, Q, lam, bad);
-  if (blockIdx.x == 0 && wave == 0) {  // the wave of interface 0
-    double q0, l0;
-    bool b0;
-    fv_interface0(a, sc, u, a.tab, lane, q0, l0, b0);
-    if (j == 0) {
-      Q = q0;
-      lam = l0;
-      bad = b0;
-    }
+  const FvIface f = fv_prep(a, sc, u, (int)(live ? j : n));
+  double F1 = 0.0, F2 = 0.0;
+  const double x = m == 0 ? f.dh[0] : (m == 1 ? f.dh[1] : f.dh[2]);
+  if (live && m < f.nm) fv_mass(a, sc, a.tab, cf, x, F1, F2);
+  double G1[3], G2[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {  // every lane takes part
+    G1[k] = __shfl(F1, lane - m + k, kWave);
+    G2[k] = __shfl(F2, lane - m + k, kWave);
   }
-  if (!live || sub != 0) return;
-  if (bad) {
+  if (!live || m != 0) return;
+  if (f.bad) {
     // the flow ends at the start of this step with its state kept
     a.alive[r] = 0;
     a.t_reached[r] = a.t_n;
@@ -236,6 +243,8 @@ __global__ __launch_bounds__(256) void fv_flux_kernel(FvArgs a) {
     a.lam[o] = 0.0;
     return;
   }
+  double Q, lam;
+  fv_flux(a, f, (int)j, G1, G2, Q, lam);
   a.Q[o] = Q;
   a.lam[o] = lam;
 }
@@ -265,31 +274,34 @@ __global__ __launch_bounds__(256) void fv_stage_kernel(FvArgs a) {
 }
 
 // Steps [s0, s0 + n_st) of one flow per workgroup: state, stage state,
-// fluxes and the radial table in LDS; per stage the fluxes of all n + 1
-// interfaces (groups of eight lanes over interfaces 1..n, interface 0 by one
-// wave), a barrier, the cell updates, a barrier.  The per-interface and per-cell arithmetic is that of the flux
-// and stage kernels (same bits); no launch per stage.  A flow whose masses
-// leave the domain in a stage ends with the state of the start of that step.
-__global__ __launch_bounds__(1024) void fv_solve_kernel(FvArgs a, int64_t s0, int64_t n_st) {
+// fluxes, the radial table and per interface its masses, F_1 and F_2 in LDS
+// (the coefficient groups, the same for every lane, through the scalar
+// cache).  Per stage: one thread per interface forms its masses (fv_prep), a
+// barrier; thread t takes mass t % 3 of interface t / 3 (fv_mass), a barrier;
+// one thread per interface forms the flux (fv_flux), a barrier; the cell
+// updates, a barrier.  The per-mass, per-interface and per-cell arithmetic is
+// that of the flux and stage kernels (same bits); no launch per stage.  A
+// flow whose masses leave the domain in a stage ends with the state of the
+// start of that step.
+__global__ __launch_bounds__(1024) void fv_solve_kernel(FvArgs a, const double *__restrict__ cf,
+                                                       int64_t s0, int64_t n_st) {
   extern __shared__ double lds[];
   const int64_t r = blockIdx.x;
   if (!a.alive[r]) return;  // workgroup-uniform
-  const int64_t n = a.n;
+  const int n = (int)a.n, nq = n + 1;
   const int tid = threadIdx.x, bs = blockDim.x;
   double *y0 = lds;
   double *ys = y0 + n;
   double *Q = ys + n;
-  double *tab = Q + n + 1;
-  int *bad_flag = reinterpret_cast<int *>(tab + 2 * a.n_r);
-  for (int64_t i = tid; i < n; i += bs) y0[i] = a.y0[r * n + i];
+  double *tab = Q + nq;            // chat | hhat
+  double *lP = tab + 2 * a.n_r;    // [n + 1][6]: dh (then F_1) of the masses, um, up, 1/sigma_j
+  double *lF2 = lP + 6 * nq;       // [n + 1][3]: F_2 of the masses
+  int *lN = reinterpret_cast<int *>(lF2 + 3 * nq);  // [n + 1]: number of masses
+  int *bad_flag = lN + nq;
+  for (int i = tid; i < n; i += bs) y0[i] = a.y0[r * n + i];
   for (int i = tid; i < 2 * a.n_r; i += bs) tab[i] = a.tab[i];
   if (tid == 0) *bad_flag = 0;
   __syncthreads();
-  const int G = bs / 8, grp = tid / 8, sub = tid & 7;
-  // interface 0 by a wave whose groups hold one interface fewer than the
-  // first groups (groups n % G and up), or wave 0 when all hold as many
-  int wave0 = ((int)(n % G) + 7) / 8;
-  if (wave0 >= G / 8) wave0 = 0;
   const double cs[3] = {0.0, 1.0, 0.5};
   for (int64_t st = 0; st < n_st; ++st) {
     const double tn = (double)(s0 + st) * a.h;
@@ -297,19 +309,17 @@ __global__ __launch_bounds__(1024) void fv_solve_kernel(FvArgs a, int64_t s0, in
       const FvScale sc = fv_scale(a, tn + cs[s] * a.h);
       const double *u = s == 0 ? y0 : ys;
       bool bad = false;
-      for (int64_t j = 1 + grp; j <= n; j += G) {
-        double q, lam;
-        bool b;
-        fv_interface(a, sc, u, tab, j, sub, true, q, lam, b);
-        if (sub == 0) Q[j] = q;
-        bad |= b;
-      }
-      if (tid / kWave == wave0) {  // wave-uniform
-        double q, lam;
-        bool b;
-        fv_interface0(a, sc, u, tab, tid & (kWave - 1), q, lam, b);
-        if ((tid & (kWave - 1)) == 0) Q[0] = q;
-        bad |= b;
+      for (int j = tid; j < nq; j += bs) {
+        const FvIface f = fv_prep(a, sc, u, j);
+        double *P = lP + 6 * j;
+        P[0] = f.dh[0];
+        P[1] = f.dh[1];
+        P[2] = f.dh[2];
+        P[3] = f.um;
+        P[4] = f.up;
+        P[5] = f.isj;
+        lN[j] = f.nm;
+        bad |= f.bad;
       }
       if (bad) *bad_flag = 1;
       __syncthreads();
@@ -319,17 +329,39 @@ __global__ __launch_bounds__(1024) void fv_solve_kernel(FvArgs a, int64_t s0, in
           a.t_reached[r] = tn;
           *a.flag = 1;
         }
-        for (int64_t i = tid; i < n; i += bs) a.y0[r * n + i] = y0[i];
+        for (int i = tid; i < n; i += bs) a.y0[r * n + i] = y0[i];
         return;
       }
-      for (int64_t i = tid; i < n; i += bs) {
+      for (int t = tid; t < 3 * nq; t += bs) {
+        const int j = t / 3, m = t - 3 * j;
+        if (m < lN[j]) {
+          double F1, F2;
+          fv_mass(a, sc, tab, cf, lP[6 * j + m], F1, F2);
+          lP[6 * j + m] = F1;
+          lF2[3 * j + m] = F2;
+        }
+      }
+      __syncthreads();
+      for (int j = tid; j < nq; j += bs) {
+        const double *P = lP + 6 * j;
+        FvIface f;
+        f.nm = lN[j];
+        f.um = P[3];
+        f.up = P[4];
+        f.isj = P[5];
+        double q, lam;
+        fv_flux(a, f, j, P, lF2 + 3 * j, q, lam);
+        Q[j] = q;
+      }
+      __syncthreads();
+      for (int i = tid; i < n; i += bs) {
         const double L = (Q[i + 1] - Q[i]) * a.inv_ds;
         fv_update(s, L, a.h, y0[i], ys[i]);
       }
       __syncthreads();
     }
   }
-  for (int64_t i = tid; i < n; i += bs) a.y0[r * n + i] = y0[i];
+  for (int i = tid; i < n; i += bs) a.y0[r * n + i] = y0[i];
 }
 
 // One workgroup per flow: step estimate 1 / max_j lam_j.
@@ -358,8 +390,10 @@ int launch_fv_init(const FvArgs &a, double t_end, void *stream) {
 
 int launch_fv_flux(const FvArgs &a, void *stream) {
   if (a.n_rows <= 0) return 0;
-  hipLaunchKernelGGL(fv_flux_kernel, dim3((unsigned)((a.n + 1 + 31) / 32), (unsigned)a.n_rows),
-                     dim3(256), 0, (hipStream_t)stream, a);
+  const int64_t per_block = 4 * kFvPerWave;
+  hipLaunchKernelGGL(fv_flux_kernel,
+                     dim3((unsigned)((a.n + 1 + per_block - 1) / per_block), (unsigned)a.n_rows),
+                     dim3(256), 0, (hipStream_t)stream, a, a.tab + 2 * a.n_r);
   return (int)hipGetLastError();
 }
 
@@ -370,15 +404,23 @@ int launch_fv_stage(const FvArgs &a, void *stream) {
   return (int)hipGetLastError();
 }
 
-int fv_solve_lds_bytes(const FvArgs &a) {
-  return (int)(sizeof(double) * (3 * a.n + 1 + 2 * (int64_t)a.n_r) + 16);
+int64_t fv_solve_lds_bytes(const FvArgs &a) {
+  return (int64_t)sizeof(double) * (3 * a.n + 1 + 2 * (int64_t)a.n_r + 9 * (a.n + 1)) +
+         (int64_t)sizeof(int) * (a.n + 1) + 16;
 }
 
 int launch_fv_solve(const FvArgs &a, int64_t s0, int64_t n_st, int threads, void *stream) {
   if (a.n_rows <= 0 || n_st <= 0) return 0;
   if (threads < 64 || threads > 1024 || threads % 64) return (int)hipErrorInvalidValue;
+  if (fv_solve_lds_bytes(a) > kFvSolveLdsMax) return (int)hipErrorInvalidValue;
+  static const bool once =
+      ((void)hipFuncSetAttribute((const void *)&fv_solve_kernel,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, kFvSolveLdsMax),
+       (void)hipGetLastError(), true);
+  (void)once;
   hipLaunchKernelGGL(fv_solve_kernel, dim3((unsigned)a.n_rows), dim3(threads),
-                     fv_solve_lds_bytes(a), (hipStream_t)stream, a, s0, n_st);
+                     (size_t)fv_solve_lds_bytes(a), (hipStream_t)stream, a, a.tab + 2 * a.n_r,
+                     s0, n_st);
   return (int)hipGetLastError();
 }
 

@@ -97,7 +97,7 @@ int Ctx::fvlpa_device(const frg_fvlpa &f, int64_t n, double t_end, int64_t n_ste
   if (!rc && solve) {
     const double hh = t_end / (double)n_steps;
     a.h = hh;
-    if (tune.fv_persistent && fv_solve_lds_bytes(a) <= 64 * 1024) {
+    if (tune.fv_persistent && fv_solve_lds_bytes(a) <= kFvSolveLdsMax) {
       // one workgroup per flow runs the steps with its state in LDS, in
       // launches of at most kFvStepsPerLaunch steps; the whole chip's
       // threads per flow while there are at most as many flows as CUs

@@ -169,6 +169,38 @@ LpaTable build_lpa_table(int d, int reg, int n_r, double q_max_over_k) {
     t.data[i] = wi * qp * dtR_over_k2_host(reg, y);
     t.data[n_r + i] = (reg == FRG_REG_EXP) ? h_exp_host(y) : std::max(y - 1.0, 0.0);
   }
+  // coefficient groups (products in long double; all terms are >= 0)
+  const int ng = fv_groups(n_r);
+  t.data.resize(2 * (size_t)n_r + (size_t)kFvCoef * ng, 0.0);
+  for (int g = 0; g < ng; ++g) {
+    long double c[kFvGroup], h[kFvGroup];
+    for (int l = 0; l < kFvGroup; ++l) {
+      const int i = kFvGroup * g + l;
+      c[l] = i < n_r ? t.data[i] : 0.0L;
+      h[l] = i < n_r ? t.data[n_r + i] : 1.0L;
+    }
+    // poly *= (x + hl), coefficients from x^0 up
+    auto mul_lin = [](std::vector<long double> &p, long double hl) {
+      p.push_back(0.0L);
+      for (size_t k = p.size() - 1; k > 0; --k) p[k] = p[k - 1] + hl * p[k];
+      p[0] *= hl;
+    };
+    std::vector<long double> P{1.0L};
+    for (int l = 0; l < kFvGroup; ++l) mul_lin(P, h[l]);
+    std::vector<long double> N(kFvGroup, 0.0L), M(2 * kFvGroup - 1, 0.0L);
+    for (int i = 0; i < kFvGroup; ++i) {
+      std::vector<long double> Pi{1.0L};
+      for (int l = 0; l < kFvGroup; ++l)
+        if (l != i) mul_lin(Pi, h[l]);
+      for (int k = 0; k < kFvGroup; ++k) N[k] += c[i] * Pi[k];
+      for (int k = 0; k < kFvGroup; ++k)
+        for (int k2 = 0; k2 < kFvGroup; ++k2) M[k + k2] += c[i] * Pi[k] * Pi[k2];
+    }
+    double *dst = t.data.data() + 2 * (size_t)n_r + (size_t)kFvCoef * g;
+    for (int k = 0; k < kFvGroup; ++k) dst[k] = (double)P[k];
+    for (int k = 0; k < kFvGroup; ++k) dst[kFvGroup + k] = (double)N[k];
+    for (int k = 0; k < 2 * kFvGroup - 1; ++k) dst[2 * kFvGroup + k] = (double)M[k];
+  }
   return t;
 }
 
