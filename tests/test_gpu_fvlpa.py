@@ -67,6 +67,48 @@ def test_rhs_and_step_estimate_match_oracle(ctx, d, N, reg, n_r, n, smax):
         assert np.all(np.abs(gdt[alive] - wdt[alive]) <= 1e-12 * wdt[alive])
 
 
+def test_steep_states_sum_term_by_term(ctx):
+    """Threshold masses above 1e20 k^2 are summed term by term (the coefficient
+    groups serve 1e-20 <= x <= 1e20): a jump of 1e22 between neighbouring
+    cells puts the interface at the jump and the Goldstone masses of the right
+    half past that range.  Right-hand side and step estimate against the
+    oracle; fused and per-stage solves over a few steps give the same bits."""
+    d, N, reg, n_r, n, smax = 3, 4, EXP, 64, 40, 2.0
+    print("[case] fvlpa steep state", flush=True)
+    rng = np.random.Generator(np.random.PCG64(99))
+    u = initial(rng, 3, n, smax)
+    u[:, n // 2:] += 1e22
+    fv = frg.make_fvlpa(d, N, reg, n_r, 1.0, 6.0, n, smax)
+    out = torch.full(u.shape, float("nan"), dtype=torch.float64, device="cuda")
+    dt = torch.full((u.shape[0],), float("nan"), dtype=torch.float64, device="cuda")
+    frg.frg_fvlpa_rhs(ctx, fv, 0.0, dev(u), out, dt)
+    torch.cuda.synchronize()
+    got, gdt = out.cpu().numpy(), dt.cpu().numpy()
+    want, wdt, dead = oracle.fvlpa_rhs(d, N, reg, n_r, 1.0, 6.0, smax, 0.0, u, allow_domain=True)
+    assert np.all(dead == 0)
+    # the dissipation at the jump makes its two cells' rates ~1e20 times the
+    # usual scale: each value against the larger of that scale and itself
+    sc = np.maximum(scale(d, N, reg, n_r, 1.0, smax / n), np.abs(want))
+    err = (np.abs(got - want) / sc).max()
+    print(f"  max scaled err {err:.3e}")
+    assert err < RTOL
+    assert np.all(np.abs(gdt - wdt) <= 1e-12 * wdt)
+    t_end = -5 * 0.5 * np.min(wdt)
+    default = frg.frg_tune_get(ctx, "fv_persistent")
+    outs = []
+    try:
+        for fused in (1, 0):
+            frg.frg_tune_set(ctx, "fv_persistent", fused)
+            U = dev(u)
+            tr = torch.empty(u.shape[0], dtype=torch.float64, device="cuda")
+            frg.frg_fvlpa_solve(ctx, fv, t_end, 5, U, tr)
+            torch.cuda.synchronize()
+            outs.append(U.cpu().numpy())
+    finally:
+        frg.frg_tune_set(ctx, "fv_persistent", default)
+    assert np.array_equal(outs[0], outs[1]) and np.all(np.isfinite(outs[0]))
+
+
 @pytest.mark.parametrize("d,N,reg,n_r,n,smax", CASES[:3])
 def test_solve_matches_oracle(ctx, d, N, reg, n_r, n, smax):
     print(f"[case] fvlpa solve d={d} N={N} reg={reg} n={n}", flush=True)
