@@ -41,7 +41,7 @@ sys.path.insert(0, ROOT)
 VALU_LANE_CYCLES = 256 * 4 * 16 * 2.4e9
 # HBM bytes per grid-kernel launch from rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # scaled by a 1 GiB device copy read the same way (fetch x2.00, write x1.00):
-# 460.0 KiB x 2.00 + 16384 KiB x 1.00.
+# 461.0 KiB x 2.00 + 16384 KiB x 1.00.
 TRAFFIC = 461.0 * 1024 * 2.00 + 16384 * 1024 * 1.00
 CYCLES_PER_EVAL_FLOOR = 2
 PEAK_EVALS = VALU_LANE_CYCLES / CYCLES_PER_EVAL_FLOOR
