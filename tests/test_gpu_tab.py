@@ -109,6 +109,29 @@ def test_tab_segmented_sort_shapes(ctx, d, reg, n_r, n_a):
     frg.frg_tune_set(ctx, "tab_seg", 0)
 
 
+@pytest.mark.parametrize("n_rows,n_p", [(1, 1), (1, 3), (5, 17), (3, 1030)])
+def test_tab_segmented_few_rows_and_momenta(ctx, n_rows, n_p):
+    """The segmented form with one row (a batch of four holding one), a ragged
+    batch, a single momentum (one lane of one wave) and more momenta than
+    the lanes of a workgroup: against the oracle and the cache-streamed
+    form."""
+    print(f"[case] segmented rows={n_rows} momenta={n_p}", flush=True)
+    q = workloads.Quad(3, 0, 1.0, 6.0, 48, 16)
+    rng = np.random.Generator(np.random.PCG64(31 * n_rows + n_p))
+    p = 10 ** rng.uniform(-3, np.log10(20.0), n_p)
+    s_max = 676.0
+    g = workloads.tab_rows(n_rows, 40961, s_max)
+    seg = run_tab(ctx, q, g, s_max, p, lds_nodes=2, seg=1)
+    cache = run_tab(ctx, q, g, s_max, p, lds_nodes=2, seg=0)
+    sel = np.arange(0, n_p, max(1, n_p // 40))
+    want = want_of(q, g, s_max, p[sel])
+    err = np.abs(seg[sel] - want) / np.abs(want)
+    print(f"max rel err {err.max():.3e}")
+    assert err.max() < RTOL
+    assert np.all(np.abs(seg - cache) <= 1e-13 * np.abs(cache))
+    frg.frg_tune_set(ctx, "tab_seg", 0)
+
+
 @pytest.mark.parametrize("n_s,form", [(4097, "lds"), (4097, "cache"), (4097, "seg"),
                                       (40961, "seg"), (1 << 20, "seg"), (1 << 20, "cache")])
 def test_tab_rough_rows_within_coordinate_bound(ctx, n_s, form):
