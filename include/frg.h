@@ -454,7 +454,10 @@ int frg_autotune(frg_ctx *ctx, int32_t mode, const char *cache_path);
  * tabulated variant "tab_W" (1..4),
  * "tab_pw" (momenta per wave, 1..64), "tab_lds_nodes" (2..6144),
  * "tab_pairs" (1: rows in LDS as (value, slope) pairs, the default; 0: as
- * values; the same bits), "tab_seg" (rows that do not fit in LDS: 0 read
+ * values; the same bits), "tab_rb" (rows in LDS per workgroup, sharing every
+ * coordinate: 0 auto (two where there are two and they fit), 1, 2 or 4; the
+ * same bits), "tab_rW" (waves of such a workgroup, 1..16, default 16),
+ * "tab_seg" (rows that do not fit in LDS: 0 read
  * through the caches; 1 the segmented form; 2 the segmented form for tables
  * above 256 MiB, the default; the forms agree to rounding), and for cache-streamed rows "tab_wpc" (workgroups per
  * CU, 1..16), "tab_sW" (1..4), "tab_spw" (1..64).  Setting a knob drops the

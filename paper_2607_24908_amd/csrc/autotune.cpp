@@ -224,6 +224,8 @@ static int *knob(frg_ctx *ctx, const char *key) {
   if (!std::strcmp(key, "persist_wpc")) return &t.persist.wpc;
   if (!std::strcmp(key, "fp32c_flag_ppb")) return &t.fp32c_flag_ppb;
   if (!std::strcmp(key, "tab_pairs")) return &t.tab_pairs;
+  if (!std::strcmp(key, "tab_rb")) return &t.tab_rb;
+  if (!std::strcmp(key, "tab_rW")) return &t.tab_rW;
   if (!std::strcmp(key, "tab_seg")) return &t.tab_seg;
   if (!std::strcmp(key, "fp32c_band_ppm")) return &t.fp32c_band_ppm;
   return nullptr;
@@ -246,6 +248,8 @@ static bool knob_ok(const char *key, int v) {
   if (!std::strcmp(key, "tab_sW")) return v >= 1 && v <= 4;
   if (!std::strcmp(key, "tab_spw")) return v >= 1 && v <= 64;
   if (!std::strcmp(key, "tab_pairs")) return v == 0 || v == 1;
+  if (!std::strcmp(key, "tab_rb")) return v == 0 || v == 1 || v == 2 || v == 4;
+  if (!std::strcmp(key, "tab_rW")) return v >= 1 && v <= 16;
   if (!std::strcmp(key, "tab_seg")) return v >= 0 && v <= 2;
   if (!std::strcmp(key, "plain_tile") || !std::strcmp(key, "persist_tile")) return v >= 1 && v <= 64;
   if (!std::strcmp(key, "persist_wpc")) return v >= 1 && v <= 64;

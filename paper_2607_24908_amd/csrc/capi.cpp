@@ -619,13 +619,30 @@ int Ctx::tab_device(const frg_quad &q, const frg_gtab &tb, int64_t n_p, const do
 // Launch shape of tab_kernel for the problem in `a` (p, out, g, tab, flag,
 // pref, k2, inv_h, t_last, n_p, n_rows, n_s, os_p, os_r, n_r, n_a set by the
 // caller).
-int Ctx::tab_config(TabArgs &a, bool &lds_rows_out, int &W_out, int64_t &sblocks_out) {
+int Ctx::tab_config(TabArgs &a, bool &lds_rows_out, int &W_out, int64_t &sblocks_out,
+                    bool multi_rows) {
   const int64_t n_p = a.n_p;
   tab_lane_split(a.n_r, a.n_a, &a.R, &a.J, &a.T, &a.U);
   a.pairs = tune.tab_pairs ? 1 : 0;
+  a.rb = 1;
   const bool lds_rows = a.n_s <= std::min<int64_t>(tune.tab_lds_nodes, tab_lds_max_nodes) &&
                         tab_lds_bytes(a, true) <= 150 * 1024;
-  const int W = std::max(1, std::min(4, lds_rows ? tune.tab_W : tune.tab_sW));
+  // rows in LDS: several rows per workgroup share every coordinate (knob
+  // tab_rb; auto: two rows when there are two and the LDS holds them, which
+  // measured fastest; four rows of plain values were no faster than two)
+  if (lds_rows && multi_rows) {
+    for (int rb : {4, 2}) {
+      if (tune.tab_rb ? tune.tab_rb != rb : (rb != 2 || a.n_rows < rb)) continue;
+      TabArgs b = a;
+      b.rb = rb;
+      if (tab_lds_bytes(b, true) <= 150 * 1024) {
+        a.rb = rb;
+        break;
+      }
+    }
+  }
+  const int W = a.rb > 1 ? std::max(1, std::min(16, tune.tab_rW))
+                         : std::max(1, std::min(4, lds_rows ? tune.tab_W : tune.tab_sW));
   a.pw = std::max(1, std::min(64, lds_rows ? tune.tab_pw : tune.tab_spw));
   // streamed rows: tab_wpc workgroups per CU work through the rows of their
   // XCD one at a time; momentum blocks are made small enough that every
@@ -638,8 +655,10 @@ int Ctx::tab_config(TabArgs &a, bool &lds_rows_out, int &W_out, int64_t &sblocks
   }
   a.n_pb = (int)((n_p + (int64_t)W * a.pw - 1) / ((int64_t)W * a.pw));
   // rows in LDS: small problems take fewer momenta per wave so that about
-  // four workgroups per CU are in flight
-  while (lds_rows && a.pw > 1 && a.n_rows * a.n_pb < 4LL * n_cu) {
+  // four workgroups per CU (one with several rows per workgroup) are in flight
+  const int64_t n_groups = (a.n_rows + a.rb - 1) / a.rb;
+  const int64_t want_wg = (a.rb > 1 ? 1LL : 4LL) * n_cu;
+  while (lds_rows && a.pw > 1 && n_groups * a.n_pb < want_wg) {
     a.pw /= 2;
     a.n_pb = (int)((n_p + (int64_t)W * a.pw - 1) / ((int64_t)W * a.pw));
   }
@@ -654,7 +673,7 @@ int Ctx::tab_launch(TabArgs a, int reg, hipStream_t st) {
   bool lds_rows = false;
   int W = 1;
   int64_t sblocks = 0;
-  int rc = tab_config(a, lds_rows, W, sblocks);
+  int rc = tab_config(a, lds_rows, W, sblocks, true);
   if (rc) return rc;
   // knob tab_seg: 1 always, 2 (auto) when the table is larger than the
   // chip's memory-side cache: smaller tables are served from that cache and

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_fp64.h"
 #include "frg_internal.h"
 
@@ -63,12 +65,16 @@ struct PairRow {
   __device__ __forceinline__ double2 fetch(int k) const { return p[k]; }
 };
 
-// One (row, momentum block) of work: A_i of the row, then W * pw momenta.
-// lq / lo / lm are staged; `row` is the LDS copy or the row in memory.
-template <int UR, class Row>
-__device__ __forceinline__ void tab_block(const TabArgs &a, const Row row, const double *lq,
-                                          const double *lA, const double *lo, const double *lm,
-                                          int64_t r, int64_t pb, int W, int wave, int lane) {
+// RB rows and one momentum block of work: A_i of the rows, then W * pw
+// momenta.  rows[r] (r < nrb) are the rows (the others alias one of them and
+// are not stored); lA holds A_i of row r at lA[r * n_r + i]; lq / lo / lm are
+// staged.  The rows share the lane's coordinates and node indices; the sum
+// of every row is that of the row alone (same lanes, same order).
+template <int UR, int RB, class Row>
+__device__ __forceinline__ void tab_block_rows(const TabArgs &a, const Row *rows, int nrb,
+                                               const double *lq, const double *lA,
+                                               const double *lo, const double *lm, int64_t r0,
+                                               int64_t pb, int W, int wave, int lane) {
   const int n_a = a.n_a, n_r = a.n_r;
   const int k_last = (int)a.n_s - 2;
   const int rho = lane & (a.R - 1);
@@ -85,54 +91,83 @@ __device__ __forceinline__ void tab_block(const TabArgs &a, const Row row, const
     }
   }
   const int64_t p0 = (pb * W + wave) * a.pw;
-  double res = 0.0;
+  double res[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) res[r] = 0.0;
   for (int e = 0; e < a.pw; ++e) {
     const int64_t ia = p0 + e;
     if (ia >= a.n_p) break;  // wave-uniform
     const double p = a.p[ia];
-    double total_l = 0.0;
+    double total_l[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) total_l[r] = 0.0;
     if (p >= 0.0) {
       for (int t = 0; t < a.T; ++t) {
         const int i = rho + a.R * t;
         const bool vi = i < n_r;
         const double q = vi ? lq[i] : 0.0;
-        const double A = vi ? lA[i] : 0.0;
+        double A[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) A[r] = vi ? lA[r * n_r + i] : 0.0;
         const double qm = q - p;
         const double ah = (qm * qm) * a.inv_h;
         const double bh = ((2.0 * q) * p) * a.inv_h;
-        double inner = 0.0;
+        double inner[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) inner[r] = 0.0;
         if (UR > 0) {
-          // all table indices first, then all reads, then the sums (the
-          // reads of the UR terms are in flight together)
+          // all table indices first, then each row's reads (the reads of its
+          // UR terms in flight together), then its sums
           int kq[UR > 0 ? UR : 1];
           double fq[UR > 0 ? UR : 1];
 #pragma unroll
           for (int u = 0; u < UR; ++u)
-            row.locate(fmin(__builtin_fma(bh, ro[u], ah), a.t_last), k_last, kq[u], fq[u]);
-          double2 gd[UR > 0 ? UR : 1];
+            rows[0].locate(fmin(__builtin_fma(bh, ro[u], ah), a.t_last), k_last, kq[u], fq[u]);
 #pragma unroll
-          for (int u = 0; u < UR; ++u) gd[u] = row.fetch(kq[u]);
+          for (int r = 0; r < RB; ++r) {
+            double2 gd[UR > 0 ? UR : 1];
 #pragma unroll
-          for (int u = 0; u < UR; ++u)
-            inner = __builtin_fma(rm[u], __builtin_fma(fq[u], gd[u].y, gd[u].x), inner);
+            for (int u = 0; u < UR; ++u) gd[u] = rows[r].fetch(kq[u]);
+#pragma unroll
+            for (int u = 0; u < UR; ++u)
+              inner[r] = __builtin_fma(rm[u], __builtin_fma(fq[u], gd[u].y, gd[u].x), inner[r]);
+          }
         } else {
           for (int u = 0; u < a.U; ++u) {
             const int j = iota + a.J * u;
             if (j < n_a) {
-              const double G = row(__builtin_fma(bh, lo[j], ah), a.t_last, k_last);
-              inner = __builtin_fma(lm[j], G, inner);
+              const double tc = __builtin_fma(bh, lo[j], ah);
+#pragma unroll
+              for (int r = 0; r < RB; ++r)
+                inner[r] = __builtin_fma(lm[j], rows[r](tc, a.t_last, k_last), inner[r]);
             }
           }
         }
-        total_l = __builtin_fma(A, inner, total_l);
+#pragma unroll
+        for (int r = 0; r < RB; ++r) total_l[r] = __builtin_fma(A[r], inner[r], total_l[r]);
       }
     }
-    const double v = a.pref * wave_sum(total_l);
-    if (lane == e) res = p >= 0.0 ? v : __builtin_nan("");
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const double v = a.pref * wave_sum(total_l[r]);
+      if (lane == e) res[r] = p >= 0.0 ? v : __builtin_nan("");
+    }
     if (!(p >= 0.0) && lane == 0) *a.flag = 1;
   }
   const int64_t ia = p0 + lane;
-  if (lane < a.pw && ia < a.n_p) a.out[ia * a.os_p + r * a.os_r] = res;
+  if (lane < a.pw && ia < a.n_p) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+      if (r < nrb) a.out[ia * a.os_p + (r0 + r) * a.os_r] = res[r];
+  }
+}
+
+// One (row, momentum block) of work: tab_block_rows with one row.
+template <int UR, class Row>
+__device__ __forceinline__ void tab_block(const TabArgs &a, const Row row, const double *lq,
+                                          const double *lA, const double *lo, const double *lm,
+                                          int64_t r, int64_t pb, int W, int wave, int lane) {
+  tab_block_rows<UR, 1>(a, &row, 1, lq, lA, lo, lm, r, pb, W, wave, lane);
 }
 
 // Stage the row-dependent factors A_i = c_i G_r(q_i^2)^2 (and q_i).
@@ -154,12 +189,12 @@ __device__ __forceinline__ void tab_stage_A(const TabArgs &a, const Row row, dou
 struct TabLds {
   double *lq, *lA, *lo, *lm, *lg;
 };
-__device__ __forceinline__ TabLds tab_lds(const TabArgs &a, double *lds) {
+__device__ __forceinline__ TabLds tab_lds(const TabArgs &a, double *lds, int rb = 1) {
   const int n_r = a.n_r, n_a = a.n_a;
   TabLds l;
   l.lq = lds;
   l.lA = l.lq + n_r;
-  l.lo = l.lA + n_r;
+  l.lo = l.lA + rb * n_r;
   l.lm = l.lo + n_a;
   l.lg = l.lm + n_a;
   for (int j = threadIdx.x; j < n_a; j += blockDim.x) {
@@ -169,37 +204,60 @@ __device__ __forceinline__ TabLds tab_lds(const TabArgs &a, double *lds) {
   return l;
 }
 
-// One (row, momentum block) with the row staged in LDS: the whole workgroup
-// stages the row and the A_i, then each wave evaluates its momenta.
-template <int UR, bool PAIRS>
-__device__ __forceinline__ void tab_row_block(const TabArgs &a, const TabLds &l, int64_t r,
-                                              int64_t pb, int W, int wave, int lane) {
-  const double *grow = a.g + r * a.n_s;
-  if constexpr (PAIRS) {
-    double2 *lp = reinterpret_cast<double2 *>(l.lg);
-    const int n_s = (int)a.n_s;
-    for (int k = threadIdx.x; k < n_s; k += blockDim.x) {
-      if (k + 1 < n_s) {
-        const double g0 = grow[k];
-        lp[k] = make_double2(g0, grow[k + 1] - g0);
-      } else {
-        const double g0 = grow[n_s - 2];
-        lp[k] = make_double2(__builtin_fma(1.0, grow[n_s - 1] - g0, g0), 0.0);
+// RB rows (group rg) and one momentum block with the rows staged in LDS: the
+// whole workgroup stages the rows and their A_i, then each wave evaluates its
+// momenta for all of them.
+template <int UR, bool PAIRS, int RB>
+__device__ __forceinline__ void tab_rows_block(const TabArgs &a, const TabLds &l, int64_t rg,
+                                               int64_t pb, int W, int wave, int lane) {
+  const int64_t r0 = rg * RB;
+  const int nrb = (int)min<int64_t>(RB, a.n_rows - r0);
+  const int n_s = (int)a.n_s, n_r = a.n_r;
+  const int len = PAIRS ? 2 * n_s : n_s;  // doubles of one staged row
+  for (int r = 0; r < nrb; ++r) {
+    const double *grow = a.g + (r0 + r) * a.n_s;
+    double *dst = l.lg + r * len;
+    if constexpr (PAIRS) {
+      double2 *lp = reinterpret_cast<double2 *>(dst);
+      for (int k = threadIdx.x; k < n_s; k += blockDim.x) {
+        if (k + 1 < n_s) {
+          const double g0 = grow[k];
+          lp[k] = make_double2(g0, grow[k + 1] - g0);
+        } else {
+          const double g0 = grow[n_s - 2];
+          lp[k] = make_double2(__builtin_fma(1.0, grow[n_s - 1] - g0, g0), 0.0);
+        }
       }
+    } else {
+      for (int k = threadIdx.x; k < n_s; k += blockDim.x) dst[k] = grow[k];
     }
-    __syncthreads();
-    const PairRow row{lp};
-    tab_stage_A(a, row, l.lq, l.lA);
-    __syncthreads();
-    tab_block<UR>(a, row, l.lq, l.lA, l.lo, l.lm, r, pb, W, wave, lane);
-  } else {
-    for (int k = threadIdx.x; k < (int)a.n_s; k += blockDim.x) l.lg[k] = grow[k];
-    __syncthreads();
-    const PlainRow row{l.lg};
-    tab_stage_A(a, row, l.lq, l.lA);
-    __syncthreads();
-    tab_block<UR>(a, row, l.lq, l.lA, l.lo, l.lm, r, pb, W, wave, lane);
   }
+  __syncthreads();
+  using Row = typename std::conditional<PAIRS, PairRow, PlainRow>::type;
+  Row rows[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    double *src = l.lg + (r < nrb ? r : nrb - 1) * len;
+    if constexpr (PAIRS)
+      rows[r] = PairRow{reinterpret_cast<const double2 *>(src)};
+    else
+      rows[r] = PlainRow{src};
+  }
+  // A_i = c_i G_r(q_i^2)^2 of each row (and q_i)
+  for (int x = threadIdx.x; x < nrb * n_r; x += blockDim.x) {
+    const int r = x / n_r, i = x - r * n_r;
+    const double q = a.tab[i];
+    const double *src = l.lg + r * len;
+    double G;
+    if constexpr (PAIRS)
+      G = PairRow{reinterpret_cast<const double2 *>(src)}((q * q) * a.inv_h, a.t_last, n_s - 2);
+    else
+      G = PlainRow{src}((q * q) * a.inv_h, a.t_last, n_s - 2);
+    if (r == 0) l.lq[i] = q;
+    l.lA[r * n_r + i] = (a.tab[n_r + i] * G) * G;
+  }
+  __syncthreads();
+  tab_block_rows<UR, RB>(a, rows, nrb, l.lq, l.lA, l.lo, l.lm, r0, pb, W, wave, lane);
 }
 
 }  // namespace dev

@@ -91,6 +91,8 @@ struct Tune {
   int tab_sW = 2;          // tabulated variant, streamed rows: waves per workgroup
   int tab_spw = 1;         // tabulated variant, streamed rows: momenta per wave (at most)
   int tab_pairs = 1;       // tabulated variant: rows in LDS as (value, slope) pairs
+  int tab_rb = 0;          // tabulated variant, rows in LDS: rows per workgroup (0: auto)
+  int tab_rW = 16;         // tabulated variant, several rows per workgroup: waves per workgroup
   int tab_seg = 2;         // tabulated variant, rows longer than the LDS: segmented form (2: auto)
   PersistCfg persist;
   int grid_lds_rows = 64;  // (t, u) rows of 64 doubles staged per LDS chunk
@@ -204,7 +206,10 @@ struct Context {
                  hipStream_t st);
   // Launch shape of the table kernel for a (fills R, J, T, U, pairs, pw and
   // n_pb of a): rows in LDS or streamed, waves per workgroup, streaming grid.
-  int tab_config(frg::TabArgs &a, bool &lds_rows, int &W, int64_t &sblocks);
+  // launch shape of the tabulated diagram; several rows per workgroup only
+  // where the caller's kernel takes them (tab_kernel does, the momentum
+  // flow's one-row kernel does not)
+  int tab_config(frg::TabArgs &a, bool &lds_rows, int &W, int64_t &sblocks, bool multi_rows);
   int tab_launch(frg::TabArgs a, int reg, hipStream_t st);
   // pflow_api.cpp: momentum-dependent flow; dsdt != nullptr: one right-hand side
   // at t_rhs, else RK4 from 0 to t_end (all arrays on the device)

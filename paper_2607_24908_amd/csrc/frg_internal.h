@@ -147,6 +147,7 @@ struct TabArgs {
   int32_t pw;     // momenta per wave
   int32_t n_pb;   // momentum blocks per row (W * pw momenta each)
   int32_t pairs;  // rows in LDS as (value, slope) pairs
+  int32_t rb;     // rows in LDS: rows per workgroup (1, 2 or 4; 0 means 1)
 };
 void tab_lane_split(int n_r, int n_a, int *R, int *J, int *T, int *U);
 

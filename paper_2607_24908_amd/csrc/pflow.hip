@@ -352,6 +352,8 @@ static void pflow_pull_reg(const TabArgs &t, const PflowPull &a, int W, hipStrea
 
 int launch_pflow_pull(const TabArgs &t, const PflowPull &a, int reg, int W, void *stream) {
   if (t.n_p <= 0 || t.n_rows <= 0) return 0;
+  // one row per workgroup of at most 256 threads (the kernel's launch bounds)
+  if (W < 1 || W * kWave > 256 || t.rb > 1) return (int)hipErrorInvalidValue;
   hipStream_t st = (hipStream_t)stream;
   if (reg == kExp)
     pflow_pull_reg<kExp>(t, a, W, st);

@@ -31,17 +31,19 @@ using namespace dev;
 // that each XCD streams one row at a time through its L2 and the rows in
 // flight on the chip stay within the memory-side cache.
 // UR > 0: every lane holds at most UR angular nodes (U <= UR), kept in
-// registers; UR == 0: read from LDS.
-template <bool LDS_ROW, int UR, bool PAIRS>
-__global__ __launch_bounds__(256) void tab_kernel(TabArgs a) {
+// registers; UR == 0: read from LDS.  RB rows per workgroup (rows in LDS):
+// the rows share every coordinate and node index, each row's sums are those
+// of the row alone.
+template <bool LDS_ROW, int UR, bool PAIRS, int RB>
+__global__ __launch_bounds__(RB > 1 ? 1024 : 256) void tab_kernel(TabArgs a) {
   extern __shared__ double lds[];
   const int W = blockDim.x / kWave;
   const int wave = threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
-  const TabLds l = tab_lds(a, lds);
+  const TabLds l = tab_lds(a, lds, RB);
   if constexpr (LDS_ROW) {
-    const int64_t r = blockIdx.x / a.n_pb;
-    tab_row_block<UR, PAIRS>(a, l, r, blockIdx.x - r * a.n_pb, W, wave, lane);
+    const int64_t rg = blockIdx.x / a.n_pb;
+    tab_rows_block<UR, PAIRS, RB>(a, l, rg, blockIdx.x - rg * a.n_pb, W, wave, lane);
   } else {
     const int x = blockIdx.x & 7;
     const int64_t slot = blockIdx.x >> 3, slots = gridDim.x >> 3;
@@ -68,8 +70,9 @@ void tab_lane_split(int n_r, int n_a, int *R, int *J, int *T, int *U) {
 }
 
 int tab_lds_bytes(const TabArgs &t, bool lds_rows) {
+  const int rb = lds_rows && t.rb > 1 ? t.rb : 1;
   const int row = !lds_rows ? 0 : t.pairs ? (int)(2 * t.n_s) : (int)t.n_s;
-  return (int)(sizeof(double) * (2 * t.n_r + 2 * t.n_a + row));
+  return (int)(sizeof(double) * ((1 + rb) * t.n_r + 2 * t.n_a + rb * row));
 }
 
 // Dynamic LDS beyond 64 KiB (gfx950: 160 KiB per workgroup); a refusal where
@@ -79,12 +82,18 @@ static void tab_allow_large_lds(const void *fn) {
   (void)hipGetLastError();
 }
 
-template <bool L, int UR, bool P>
+template <bool L, int UR, bool P, int RB = 1>
 static void tab_launch_t(const TabArgs &t, int W, int64_t blocks, hipStream_t st) {
-  static const bool once = (tab_allow_large_lds((const void *)&tab_kernel<L, UR, P>), true);
+  static const bool once = (tab_allow_large_lds((const void *)&tab_kernel<L, UR, P, RB>), true);
   (void)once;
-  hipLaunchKernelGGL((tab_kernel<L, UR, P>), dim3((unsigned)blocks), dim3(kWave * W),
+  hipLaunchKernelGGL((tab_kernel<L, UR, P, RB>), dim3((unsigned)blocks), dim3(kWave * W),
                      tab_lds_bytes(t, L), st, t);
+}
+
+template <bool P, int RB>
+static void tab_launch_rows(const TabArgs &t, bool regs, int W, int64_t blocks, hipStream_t st) {
+  regs ? tab_launch_t<true, 4, P, RB>(t, W, blocks, st)
+       : tab_launch_t<true, 0, P, RB>(t, W, blocks, st);
 }
 
 int launch_tab(const TabArgs &t, int reg, int W, bool lds_rows, int64_t stream_blocks,
@@ -94,11 +103,19 @@ int launch_tab(const TabArgs &t, int reg, int W, bool lds_rows, int64_t stream_b
   hipStream_t st = (hipStream_t)stream;
   const bool regs = t.U <= 4;
   if (lds_rows) {
-    const int64_t blocks = t.n_rows * t.n_pb;
-    if (t.pairs)
-      regs ? tab_launch_t<true, 4, true>(t, W, blocks, st) : tab_launch_t<true, 0, true>(t, W, blocks, st);
+    const int rb = t.rb > 1 ? t.rb : 1;
+    if (rb != 1 && rb != 2 && rb != 4) return (int)hipErrorInvalidValue;
+    if (W < 1 || W * kWave > (rb > 1 ? 1024 : 256)) return (int)hipErrorInvalidValue;
+    const int64_t blocks = ((t.n_rows + rb - 1) / rb) * t.n_pb;
+    if (rb == 4)
+      t.pairs ? tab_launch_rows<true, 4>(t, regs, W, blocks, st)
+              : tab_launch_rows<false, 4>(t, regs, W, blocks, st);
+    else if (rb == 2)
+      t.pairs ? tab_launch_rows<true, 2>(t, regs, W, blocks, st)
+              : tab_launch_rows<false, 2>(t, regs, W, blocks, st);
     else
-      regs ? tab_launch_t<true, 4, false>(t, W, blocks, st) : tab_launch_t<true, 0, false>(t, W, blocks, st);
+      t.pairs ? tab_launch_rows<true, 1>(t, regs, W, blocks, st)
+              : tab_launch_rows<false, 1>(t, regs, W, blocks, st);
   } else {
     const int64_t blocks = 8 * ((stream_blocks + 7) / 8);
     regs ? tab_launch_t<false, 4, false>(t, W, blocks, st) : tab_launch_t<false, 0, false>(t, W, blocks, st);

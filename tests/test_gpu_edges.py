@@ -79,6 +79,7 @@ KNOBS = {
     "plain_tile": ([1, 64], [0, 65]), "persist_tile": ([1, 64], [0, 65]),
     "persist_wpc": ([1, 64], [0, 65]), "tab_W": ([1, 4], [0, 5]), "tab_pw": ([1, 64], [0, 65]),
     "tab_lds_nodes": ([2, 6144], [1, 6145]), "tab_pairs": ([0, 1], [2]), "tab_seg": ([0, 2], [-1, 3]),
+    "tab_rb": ([0, 1, 2, 4], [3, 5]), "tab_rW": ([1, 16], [0, 17]),
     "tab_wpc": ([1, 16], [0, 17]), "tab_sW": ([1, 4], [0, 5]), "tab_spw": ([1, 64], [0, 65]),
     "fp32c_flag_ppb": ([0, 100], [-1]), "fp32c_band_ppm": ([0, 1000], [-1]),
 }

@@ -37,9 +37,11 @@ def dev(a):
     return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
 
 
-def run_tab(ctx, q, g, s_max, p, lds_nodes=6144, pw=16, W=4, pairs=1, seg=0):
+def run_tab(ctx, q, g, s_max, p, lds_nodes=6144, pw=16, W=4, pairs=1, seg=0, rb=0, rW=16):
     frg.frg_tune_set(ctx, "tab_pairs", pairs)
     frg.frg_tune_set(ctx, "tab_seg", seg)
+    frg.frg_tune_set(ctx, "tab_rb", rb)
+    frg.frg_tune_set(ctx, "tab_rW", rW)
     frg.frg_tune_set(ctx, "tab_lds_nodes", lds_nodes)
     frg.frg_tune_set(ctx, "tab_pw", pw)
     frg.frg_tune_set(ctx, "tab_W", W)
@@ -77,6 +79,11 @@ def test_tab_matches_oracle_and_forms_agree(ctx, d, reg, n_r, n_a):
     assert np.array_equal(streamed, got)
     values = run_tab(ctx, q, g, s_max, p, pairs=0)  # rows in LDS as values
     assert np.array_equal(values, got)
+    # one, two or four rows per workgroup (7 rows: ragged last groups)
+    for pairs in (1, 0):
+        for rb, rW in ((1, 16), (2, 16), (2, 3), (4, 8)):
+            rows = run_tab(ctx, q, g, s_max, p, pairs=pairs, rb=rb, rW=rW)
+            assert np.array_equal(rows, got), (pairs, rb, rW)
     segmented = run_tab(ctx, q, g, s_max, p, lds_nodes=2, seg=1)
     assert np.max(np.abs(segmented - want) / np.abs(want)) < RTOL
     assert np.all(np.abs(segmented - got) <= 1e-13 * np.abs(got))
