@@ -207,8 +207,7 @@ struct Context {
   // Launch shape of the table kernel for a (fills R, J, T, U, pairs, pw and
   // n_pb of a): rows in LDS or streamed, waves per workgroup, streaming grid.
   // launch shape of the tabulated diagram; several rows per workgroup only
-  // where the caller's kernel takes them (tab_kernel does, the momentum
-  // flow's one-row kernel does not)
+  // where the caller's kernel takes them
   int tab_config(frg::TabArgs &a, bool &lds_rows, int &W, int64_t &sblocks, bool multi_rows);
   int tab_launch(frg::TabArgs a, int reg, hipStream_t st);
   // pflow_api.cpp: momentum-dependent flow; dsdt != nullptr: one right-hand side

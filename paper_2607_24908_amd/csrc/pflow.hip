@@ -7,6 +7,8 @@
 // at k = 1 (q_max = kappa k): q_i -> k q_i, c_i -> k^(d+2) c_i, Hq_i -> k^2 Hq_i.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <cmath>
 
 #include "frg_internal.h"
@@ -187,88 +189,113 @@ __device__ __forceinline__ double pull_state(const PflowPull &a, int64_t r, int6
 }
 
 // t: the diagram at scale a.k (t.tab = the table at k = 1, t.out = a.Jn,
-// J[r * n_s + a]).  LDS: tab_lds's layout, then (pairs) the row as plain
-// values.
-template <int REG, int UR, bool PAIRS>
-__global__ __launch_bounds__(256) void pflow_pull_kernel(TabArgs t, PflowPull a) {
+// J[r * n_s + a]).  RB flows (rows) per workgroup, flows rg RB .. rg RB +
+// nrb - 1: each flow's update and row as for one flow; the diagram of the
+// rows shares every coordinate (tab_block_rows: each row's sums as alone).
+// LDS: tab_lds's layout for RB rows, then (pairs) the rows as plain values.
+template <int REG, int UR, bool PAIRS, int RB>
+__global__ __launch_bounds__(RB > 1 ? 1024 : 256) void pflow_pull_kernel(TabArgs t, PflowPull a) {
   extern __shared__ double lds[];
   const int W = blockDim.x / kWave;
   const int wave = threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   const int n_r = a.n_r;
   const int n_s = (int)a.n_s;
-  const int64_t r = blockIdx.x / t.n_pb;
-  const int64_t pb = blockIdx.x - r * t.n_pb;
+  const int64_t rg = blockIdx.x / t.n_pb;
+  const int64_t pb = blockIdx.x - rg * t.n_pb;
+  const int64_t r0 = rg * RB;
+  const int nrb = (int)min<int64_t>(RB, a.n_rows - r0);
   const bool writer = pb == 0;
-  const TabLds l = tab_lds(t, lds);
-  double *lv = PAIRS ? l.lg + 2 * n_s : l.lg;
-  // update of the previous stage and the row of this one
-  const bool alive = a.alivep[r] != 0;  // workgroup-uniform
-  double l3 = 0.0, c4 = 0.0;
-  if (alive && a.prev >= 0) {
-    l3 = a.lam3[r];
-    c4 = 0.5 * a.lam4[r] * a.Tp[r];
-  }
+  const TabLds l = tab_lds(t, lds, RB);
+  const int len = PAIRS ? 2 * n_s : n_s;  // doubles of one staged row
+  // the rows as plain values: after the pair rows, or the staged rows
+  double *lv0 = PAIRS ? l.lg + RB * len : l.lg;
   const double inv_k2 = 1.0 / a.k2;
-  bool bad = false;
-  for (int i = threadIdx.x; i < n_s; i += blockDim.x) {
-    const double y = pull_state(a, r, i, alive, l3, c4, writer);
-    const double s = (double)i * a.h_s;
-    const double den = (hk<REG>(s, a.k2, inv_k2) + a.k2) + y;
-    const bool ok = den > 0.0;
-    bad |= !ok;
-    lv[i] = (alive && ok) ? 1.0 / den : 0.0;
-  }
-  bad = __syncthreads_or(bad) && alive;
-  if (bad) {
-    // the flow ends at the start of this step with its state kept
-    for (int i = threadIdx.x; i < n_s; i += blockDim.x) lv[i] = 0.0;
-    if (writer && threadIdx.x == 0) {
-      a.t_reached[r] = a.t_n;
-      *a.flag = 1;
+  for (int rr = 0; rr < nrb; ++rr) {
+    const int64_t r = r0 + rr;
+    double *lv = lv0 + rr * n_s;
+    // update of the previous stage and the row of this one
+    const bool alive = a.alivep[r] != 0;  // workgroup-uniform
+    double l3 = 0.0, c4 = 0.0;
+    if (alive && a.prev >= 0) {
+      l3 = a.lam3[r];
+      c4 = 0.5 * a.lam4[r] * a.Tp[r];
     }
-    __syncthreads();
-  }
-  if (writer && threadIdx.x == 0) a.aliven[r] = alive && !bad;
-  // the diagram: the row as tab_row_block stages it, q_i and A_i at scale k
-  if constexpr (PAIRS) {
-    double2 *lp = reinterpret_cast<double2 *>(l.lg);
-    for (int k = threadIdx.x; k < n_s; k += blockDim.x) {
-      if (k + 1 < n_s) {
-        const double g0 = lv[k];
-        lp[k] = make_double2(g0, lv[k + 1] - g0);
-      } else {
-        const double g0 = lv[n_s - 2];
-        lp[k] = make_double2(__builtin_fma(1.0, lv[n_s - 1] - g0, g0), 0.0);
+    bool bad = false;
+    for (int i = threadIdx.x; i < n_s; i += blockDim.x) {
+      const double y = pull_state(a, r, i, alive, l3, c4, writer);
+      const double s = (double)i * a.h_s;
+      const double den = (hk<REG>(s, a.k2, inv_k2) + a.k2) + y;
+      const bool ok = den > 0.0;
+      bad |= !ok;
+      lv[i] = (alive && ok) ? 1.0 / den : 0.0;
+    }
+    bad = __syncthreads_or(bad) && alive;
+    if (bad) {
+      // the flow ends at the start of this step with its state kept
+      for (int i = threadIdx.x; i < n_s; i += blockDim.x) lv[i] = 0.0;
+      if (writer && threadIdx.x == 0) {
+        a.t_reached[r] = a.t_n;
+        *a.flag = 1;
+      }
+      __syncthreads();
+    }
+    if (writer && threadIdx.x == 0) a.aliven[r] = alive && !bad;
+    // the diagram's row as tab_rows_block stages it
+    if constexpr (PAIRS) {
+      double2 *lp = reinterpret_cast<double2 *>(l.lg + rr * len);
+      for (int k = threadIdx.x; k < n_s; k += blockDim.x) {
+        if (k + 1 < n_s) {
+          const double g0 = lv[k];
+          lp[k] = make_double2(g0, lv[k + 1] - g0);
+        } else {
+          const double g0 = lv[n_s - 2];
+          lp[k] = make_double2(__builtin_fma(1.0, lv[n_s - 1] - g0, g0), 0.0);
+        }
       }
     }
   }
   __syncthreads();
-  auto stage_A = [&](const auto row) {
-    for (int i = threadIdx.x; i < n_r; i += blockDim.x) {
-      const double q = a.k * a.base[i];
-      const double G = row((q * q) * t.inv_h, t.t_last, n_s - 2);
-      l.lq[i] = q;
-      l.lA[i] = ((a.kd2 * a.base[n_r + i]) * G) * G;
-    }
-    __syncthreads();
-    tab_block<UR>(t, row, l.lq, l.lA, l.lo, l.lm, r, pb, W, wave, lane);
-  };
-  if constexpr (PAIRS)
-    stage_A(PairRow{reinterpret_cast<const double2 *>(l.lg)});
-  else
-    stage_A(PlainRow{lv});
-  // tadpole of this stage, as prep_row (wave 0 of the storing workgroup)
+  using Row = typename std::conditional<PAIRS, PairRow, PlainRow>::type;
+  Row rows[RB];
+#pragma unroll
+  for (int rr = 0; rr < RB; ++rr) {
+    const double *src = l.lg + (rr < nrb ? rr : nrb - 1) * len;
+    if constexpr (PAIRS)
+      rows[rr] = PairRow{reinterpret_cast<const double2 *>(src)};
+    else
+      rows[rr] = PlainRow{src};
+  }
+  // q_i and A_i of each row at scale k
+  for (int x = threadIdx.x; x < nrb * n_r; x += blockDim.x) {
+    const int rr = x / n_r, i = x - rr * n_r;
+    const double q = a.k * a.base[i];
+    const double *src = l.lg + rr * len;
+    double G;
+    if constexpr (PAIRS)
+      G = PairRow{reinterpret_cast<const double2 *>(src)}((q * q) * t.inv_h, t.t_last, n_s - 2);
+    else
+      G = PlainRow{src}((q * q) * t.inv_h, t.t_last, n_s - 2);
+    if (rr == 0) l.lq[i] = q;
+    l.lA[rr * n_r + i] = ((a.kd2 * a.base[n_r + i]) * G) * G;
+  }
+  __syncthreads();
+  tab_block_rows<UR, RB>(t, rows, nrb, l.lq, l.lA, l.lo, l.lm, r0, pb, W, wave, lane);
+  // tadpole of this stage of each flow, as prep_row (wave 0 of the storing
+  // workgroup)
   if (writer && threadIdx.x < kWave) {
-    double acc = 0.0;
-    for (int i = lane; i < n_r; i += kWave) {
-      const double q = a.k * a.base[i];
-      const double c = a.kd2 * a.base[n_r + i];
-      const double G = interp(lv, (q * q) * a.inv_h, a.t_last, n_s - 2);
-      acc = __builtin_fma((c * G), G, acc);
+    for (int rr = 0; rr < nrb; ++rr) {
+      const double *lv = lv0 + rr * n_s;
+      double acc = 0.0;
+      for (int i = lane; i < n_r; i += kWave) {
+        const double q = a.k * a.base[i];
+        const double c = a.kd2 * a.base[n_r + i];
+        const double G = interp(lv, (q * q) * a.inv_h, a.t_last, n_s - 2);
+        acc = __builtin_fma((c * G), G, acc);
+      }
+      acc = wave_sum(acc);
+      if (lane == 0) a.Tn[r0 + rr] = a.Cd * acc;
     }
-    acc = wave_sum(acc);
-    if (lane == 0) a.Tn[r] = a.Cd * acc;
   }
 }
 
@@ -323,37 +350,52 @@ int launch_pflow_stage(const PflowArgs &a, int reg, void *stream) {
 }
 
 int pflow_pull_lds_bytes(const TabArgs &t) {
-  return tab_lds_bytes(t, true) + (t.pairs ? (int)(sizeof(double) * t.n_s) : 0);
+  const int rb = t.rb > 1 ? t.rb : 1;
+  return tab_lds_bytes(t, true) + (t.pairs ? (int)(sizeof(double) * rb * t.n_s) : 0);
 }
 
 // Dynamic LDS beyond 64 KiB (gfx950: 160 KiB per workgroup); a refusal where
 // no opt-in is needed is cleared so that it cannot be taken for a launch error.
-template <int REG, int UR, bool P>
+template <int REG, int UR, bool P, int RB>
 static void pflow_pull_t(const TabArgs &t, const PflowPull &a, int W, hipStream_t st) {
   static const bool once = [] {
-    (void)hipFuncSetAttribute((const void *)&pflow_pull_kernel<REG, UR, P>,
+    (void)hipFuncSetAttribute((const void *)&pflow_pull_kernel<REG, UR, P, RB>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     (void)hipGetLastError();
     return true;
   }();
   (void)once;
-  hipLaunchKernelGGL((pflow_pull_kernel<REG, UR, P>), dim3((unsigned)(t.n_rows * t.n_pb)),
+  const int64_t groups = (t.n_rows + RB - 1) / RB;
+  hipLaunchKernelGGL((pflow_pull_kernel<REG, UR, P, RB>), dim3((unsigned)(groups * t.n_pb)),
                      dim3(kWave * W), pflow_pull_lds_bytes(t), st, t, a);
+}
+
+template <int REG, int RB>
+static void pflow_pull_rows(const TabArgs &t, const PflowPull &a, int W, hipStream_t st) {
+  const bool regs = t.U <= 4;
+  if (t.pairs)
+    regs ? pflow_pull_t<REG, 4, true, RB>(t, a, W, st) : pflow_pull_t<REG, 0, true, RB>(t, a, W, st);
+  else
+    regs ? pflow_pull_t<REG, 4, false, RB>(t, a, W, st) : pflow_pull_t<REG, 0, false, RB>(t, a, W, st);
 }
 
 template <int REG>
 static void pflow_pull_reg(const TabArgs &t, const PflowPull &a, int W, hipStream_t st) {
-  const bool regs = t.U <= 4;
-  if (t.pairs)
-    regs ? pflow_pull_t<REG, 4, true>(t, a, W, st) : pflow_pull_t<REG, 0, true>(t, a, W, st);
+  if (t.rb == 4)
+    pflow_pull_rows<REG, 4>(t, a, W, st);
+  else if (t.rb == 2)
+    pflow_pull_rows<REG, 2>(t, a, W, st);
   else
-    regs ? pflow_pull_t<REG, 4, false>(t, a, W, st) : pflow_pull_t<REG, 0, false>(t, a, W, st);
+    pflow_pull_rows<REG, 1>(t, a, W, st);
 }
 
 int launch_pflow_pull(const TabArgs &t, const PflowPull &a, int reg, int W, void *stream) {
   if (t.n_p <= 0 || t.n_rows <= 0) return 0;
-  // one row per workgroup of at most 256 threads (the kernel's launch bounds)
-  if (W < 1 || W * kWave > 256 || t.rb > 1) return (int)hipErrorInvalidValue;
+  // RB rows per workgroup of at most 256 threads (one row) or 1024 (several),
+  // the kernel's launch bounds
+  const int rb = t.rb > 1 ? t.rb : 1;
+  if (rb != 1 && rb != 2 && rb != 4) return (int)hipErrorInvalidValue;
+  if (W < 1 || W * kWave > (rb > 1 ? 1024 : 256)) return (int)hipErrorInvalidValue;
   hipStream_t st = (hipStream_t)stream;
   if (reg == kExp)
     pflow_pull_reg<kExp>(t, a, W, st);

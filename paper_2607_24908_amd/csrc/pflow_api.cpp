@@ -117,7 +117,7 @@ int Ctx::pflow_device(const frg_pflow &pf, int64_t n, const double *lam3, const 
   bool lds_rows = false;
   int W = 1;
   int64_t sblocks = 0;
-  rc = tab_config(tb, lds_rows, W, sblocks, false);
+  rc = tab_config(tb, lds_rows, W, sblocks, true);
   const bool pull = tune.pflow_fused && lds_rows && pflow_pull_lds_bytes(tb) <= 150 * 1024;
   auto set_scale = [&](double t, double tn) {
     a.k = pf.lambda * std::exp(t);

@@ -200,10 +200,10 @@ LDS_EDGE = [(3, EXP, 24, 40, 64, 9.0), (3, EXP, 32, 8, 6000, 50.0), (3, LIT, 512
 def test_fused_and_two_launch_stages_same_bits(ctx, case):
     """One launch per stage (every workgroup of a row redoes the previous
     stage's RK4 update and the prep for its row, state buffers alternating
-    between launches), a diagram and a stage launch per stage, and rows
-    streamed from memory instead of LDS (two launches): the same bits, for
-    solves with flows that stop at the domain boundary and for one
-    right-hand side."""
+    between launches), a diagram and a stage launch per stage, rows streamed
+    from memory instead of LDS (two launches), and one, two (the default) or
+    four flows per workgroup: the same bits, for solves with flows that stop
+    at the domain boundary and for one right-hand side."""
     rng = np.random.Generator(np.random.PCG64(100 + case))
     steps = 12
     if case < len(SHAPES):
@@ -224,14 +224,18 @@ def test_fused_and_two_launch_stages_same_bits(ctx, case):
     S0 = initial(rng, n_flows, n_s, s_max)
     S0[0] -= 2.0        # outside the domain at t = 0
     lam3[1] = 4.0       # driven towards the pole
-    keys = ("pflow_fused", "tab_lds_nodes")
+    keys = ("pflow_fused", "tab_lds_nodes", "tab_rb")
     default = {k: frg.frg_tune_get(ctx, k) for k in keys}
     outs = []
+    nodes = default["tab_lds_nodes"]
     try:
-        for fused, lds_nodes in ((1, default["tab_lds_nodes"]), (0, default["tab_lds_nodes"]),
-                                 (1, 2)):
+        # fused with the default rows per workgroup, two launches, streamed
+        # rows, fused with one and with four flows per workgroup
+        for fused, lds_nodes, rb in ((1, nodes, 0), (0, nodes, 0), (1, 2, 0), (1, nodes, 1),
+                                     (1, nodes, 4)):
             frg.frg_tune_set(ctx, "pflow_fused", fused)
             frg.frg_tune_set(ctx, "tab_lds_nodes", lds_nodes)
+            frg.frg_tune_set(ctx, "tab_rb", rb)
             S, tr = gpu_solve(ctx, pf, lam3, lam4, -0.1 * steps, steps, S0)
             r = np.empty_like(S0)
             frg.frg_pflow_rhs(ctx, pf, lam3, lam4, -0.3, S0, r, mem=frg.FRG_MEM_HOST,
