@@ -1,12 +1,13 @@
 // Tabulated-propagator flow diagram (gfx950): the propagator comes from a
 // caller's table (one row per field value, piecewise-linear in s = q^2), the
 // regulator insertion d_tR from the quadrature table.  A workgroup owns one
-// table row and W * pw momenta; each wave evaluates its momenta one after
-// another with the 64 lanes over the quadrature nodes (up to 8 angular lanes
-// per radial node, so that neighbouring lanes read neighbouring table
-// entries) and stores them together.  Rows of up to tab_lds_max_nodes nodes are staged in LDS;
+// table row (or, with rows in LDS, RB rows that share every coordinate) and
+// W * pw momenta; each wave evaluates its momenta one after another with the
+// 64 lanes over the quadrature nodes (up to 8 angular lanes per radial node,
+// so that neighbouring lanes read neighbouring table entries) and stores
+// them together.  Rows of up to tab_lds_max_nodes nodes are staged in LDS;
 // longer rows are read through the caches, with the workgroups of one row
-// placed on one XCD.  Both forms do the same arithmetic in the same order.
+// placed on one XCD.  All forms do the same arithmetic in the same order.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -24,7 +25,8 @@ namespace {
 
 using namespace dev;
 
-// LDS_ROW: one workgroup per (row, momentum block), the row staged in LDS.
+// LDS_ROW: one workgroup per (group of RB rows, momentum block), the rows
+// staged in LDS.
 // Otherwise a fixed grid of 8 * slots workgroups: workgroup b runs on XCD
 // b mod 8 (round-robin dispatch) and works through the rows of that XCD one
 // after another, taking momentum blocks slot, slot + slots, ... of each, so
