@@ -147,10 +147,10 @@ __global__ __launch_bounds__(256) void pflow_stage_kernel(PflowArgs a) {
 
 // ---- one launch per stage -------------------------------------------------
 // Launch m of a solve evaluates the diagram of RK4 stage m.  Each of its
-// workgroups (row r, momentum block pb) first redoes, for the whole row, the
-// update that the stage kernel would do after stage m - 1 (from J, T, the
+// workgroups (RB rows, momentum block pb) first redoes, for each whole row,
+// the update that the stage kernel would do after stage m - 1 (from J, T, the
 // accumulator and the step-start state of the previous launch), then the prep
-// of stage m, with the propagator row built in LDS.  Every workgroup of a row
+// of stage m, with the propagator rows built in LDS.  Every workgroup of a row
 // computes the same values; only the one with pb = 0 stores the new state,
 // tadpole and flags, into buffers that no workgroup of the launch reads
 // (read and written state alternate between launches), so a launch needs no
