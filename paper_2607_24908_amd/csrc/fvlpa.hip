@@ -123,6 +123,16 @@ __device__ __forceinline__ FvIface fv_prep(const FvArgs &a, const FvScale &sc, c
 // FP64 range there); term by term outside it.  Every term and coefficient is
 // positive and x > 0, so neither form cancels.
 constexpr double kFvXMin = 1e-20, kFvXMax = 1e20;
+
+// fma(a, b, c) with c wave-uniform, taken from a scalar register: written out
+// so that the compiler does not copy c into a vector register first (its
+// two-address form wants the addend there), which cost two moves per
+// coefficient.
+__device__ __forceinline__ double fma_su(double a, double b, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+  return r;
+}
 __device__ __forceinline__ void fv_radial(const FvArgs &a, const double *tab,
                                           const double *__restrict__ cf, double x, double &s1,
                                           double &s2) {
@@ -134,13 +144,13 @@ __device__ __forceinline__ void fv_radial(const FvArgs &a, const double *tab,
       const double *c = cf + kFvCoef * g;
       double P = x + c[7];
 #pragma unroll
-      for (int k = 6; k >= 0; --k) P = __builtin_fma(P, x, c[k]);
+      for (int k = 6; k >= 0; --k) P = fma_su(P, x, c[k]);
       double N = c[15];
 #pragma unroll
-      for (int k = 14; k >= 8; --k) N = __builtin_fma(N, x, c[k]);
+      for (int k = 14; k >= 8; --k) N = fma_su(N, x, c[k]);
       double M = c[30];
 #pragma unroll
-      for (int k = 29; k >= 16; --k) M = __builtin_fma(M, x, c[k]);
+      for (int k = 29; k >= 16; --k) M = fma_su(M, x, c[k]);
       const double r = rcp64(P);
       s1 = __builtin_fma(N, r, s1);
       s2 = __builtin_fma(M * r, r, s2);
