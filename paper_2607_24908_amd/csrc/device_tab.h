@@ -65,17 +65,23 @@ struct PairRow {
   __device__ __forceinline__ double2 fetch(int k) const { return p[k]; }
 };
 
+// Radial slots of the lane split: lane rho takes i = rho + R t (t < T), so
+// q_i and A_i are staged for R T slots, the ones past n_r holding zeros (the
+// values a guarded read would give), and the loop reads them unguarded.
+__host__ __device__ __forceinline__ int tab_radial_slots(const TabArgs &a) { return a.R * a.T; }
+
 // RB rows and one momentum block of work: A_i of the rows, then W * pw
 // momenta.  rows[r] (r < nrb) are the rows (the others alias one of them and
-// are not stored); lA holds A_i of row r at lA[r * n_r + i]; lq / lo / lm are
-// staged.  The rows share the lane's coordinates and node indices; the sum
-// of every row is that of the row alone (same lanes, same order).
+// are not stored); lA holds A_i of row r at lA[r * tab_radial_slots + i];
+// lq / lo / lm are staged.  The rows share the lane's coordinates and node
+// indices; the sum of every row is that of the row alone (same lanes, same
+// order).
 template <int UR, int RB, class Row>
 __device__ __forceinline__ void tab_block_rows(const TabArgs &a, const Row *rows, int nrb,
                                                const double *lq, const double *lA,
                                                const double *lo, const double *lm, int64_t r0,
                                                int64_t pb, int W, int wave, int lane) {
-  const int n_a = a.n_a, n_r = a.n_r;
+  const int n_a = a.n_a, n_rp = tab_radial_slots(a);
   const int k_last = (int)a.n_s - 2;
   const int rho = lane & (a.R - 1);
   const int iota = lane / a.R;
@@ -103,12 +109,11 @@ __device__ __forceinline__ void tab_block_rows(const TabArgs &a, const Row *rows
     for (int r = 0; r < RB; ++r) total_l[r] = 0.0;
     if (p >= 0.0) {
       for (int t = 0; t < a.T; ++t) {
-        const int i = rho + a.R * t;
-        const bool vi = i < n_r;
-        const double q = vi ? lq[i] : 0.0;
+        const int i = rho + a.R * t;  // < R T: slots past n_r hold q = A = 0
+        const double q = lq[i];
         double A[RB];
 #pragma unroll
-        for (int r = 0; r < RB; ++r) A[r] = vi ? lA[r * n_r + i] : 0.0;
+        for (int r = 0; r < RB; ++r) A[r] = lA[r * n_rp + i];
         const double qm = q - p;
         const double ah = (qm * qm) * a.inv_h;
         const double bh = ((2.0 * q) * p) * a.inv_h;
@@ -183,23 +188,30 @@ __device__ __forceinline__ void tab_stage_A(const TabArgs &a, const Row row, dou
 }
 
 
-// LDS of the table kernels: q_i | A_i | 1 + x_j | mu_j | the row (rows
-// staged in LDS: values, or (value, slope) pairs).  tab_lds also stages
-// 1 + x_j and mu_j (all threads of the workgroup).
+// LDS of the table kernels: q_i | A_i of rb rows | 1 + x_j | mu_j | the row
+// (rows staged in LDS: values, or (value, slope) pairs); q_i and each row's
+// A_i take tab_radial_slots entries.  tab_lds also stages 1 + x_j and mu_j and
+// zeroes the slots past n_r (all threads of the workgroup), which the staging
+// of q_i and A_i never writes.
 struct TabLds {
   double *lq, *lA, *lo, *lm, *lg;
 };
 __device__ __forceinline__ TabLds tab_lds(const TabArgs &a, double *lds, int rb = 1) {
-  const int n_r = a.n_r, n_a = a.n_a;
+  const int n_r = a.n_r, n_a = a.n_a, n_rp = tab_radial_slots(a);
   TabLds l;
   l.lq = lds;
-  l.lA = l.lq + n_r;
-  l.lo = l.lA + rb * n_r;
+  l.lA = l.lq + n_rp;
+  l.lo = l.lA + rb * n_rp;
   l.lm = l.lo + n_a;
   l.lg = l.lm + n_a;
   for (int j = threadIdx.x; j < n_a; j += blockDim.x) {
     l.lo[j] = a.tab[3 * n_r + j];
     l.lm[j] = a.tab[3 * n_r + n_a + j];
+  }
+  const int pad = n_rp - n_r;
+  for (int x = threadIdx.x; x < (1 + rb) * pad; x += blockDim.x) {
+    const int r = x / pad;  // 0: q, 1 + r': A of row r'
+    l.lq[r * n_rp + n_r + (x - r * pad)] = 0.0;
   }
   return l;
 }
@@ -254,7 +266,7 @@ __device__ __forceinline__ void tab_rows_block(const TabArgs &a, const TabLds &l
     else
       G = PlainRow{src}((q * q) * a.inv_h, a.t_last, n_s - 2);
     if (r == 0) l.lq[i] = q;
-    l.lA[r * n_r + i] = (a.tab[n_r + i] * G) * G;
+    l.lA[r * tab_radial_slots(a) + i] = (a.tab[n_r + i] * G) * G;
   }
   __syncthreads();
   tab_block_rows<UR, RB>(a, rows, nrb, l.lq, l.lA, l.lo, l.lm, r0, pb, W, wave, lane);

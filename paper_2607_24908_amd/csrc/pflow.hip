@@ -277,7 +277,7 @@ __global__ __launch_bounds__(RB > 1 ? 1024 : 256) void pflow_pull_kernel(TabArgs
     else
       G = PlainRow{src}((q * q) * t.inv_h, t.t_last, n_s - 2);
     if (rr == 0) l.lq[i] = q;
-    l.lA[rr * n_r + i] = ((a.kd2 * a.base[n_r + i]) * G) * G;
+    l.lA[rr * tab_radial_slots(t) + i] = ((a.kd2 * a.base[n_r + i]) * G) * G;
   }
   __syncthreads();
   tab_block_rows<UR, RB>(t, rows, nrb, l.lq, l.lA, l.lo, l.lm, r0, pb, W, wave, lane);

@@ -74,7 +74,9 @@ void tab_lane_split(int n_r, int n_a, int *R, int *J, int *T, int *U) {
 int tab_lds_bytes(const TabArgs &t, bool lds_rows) {
   const int rb = lds_rows && t.rb > 1 ? t.rb : 1;
   const int row = !lds_rows ? 0 : t.pairs ? (int)(2 * t.n_s) : (int)t.n_s;
-  return (int)(sizeof(double) * ((1 + rb) * t.n_r + 2 * t.n_a + rb * row));
+  int R, J, T, U;
+  tab_lane_split(t.n_r, t.n_a, &R, &J, &T, &U);
+  return (int)(sizeof(double) * ((1 + rb) * R * T + 2 * t.n_a + rb * row));
 }
 
 // Dynamic LDS beyond 64 KiB (gfx950: 160 KiB per workgroup); a refusal where
