@@ -65,23 +65,37 @@ struct PairRow {
   __device__ __forceinline__ double2 fetch(int k) const { return p[k]; }
 };
 
+// Pair k of a staged row: g_k and g_{k+1} - g_k, the last node
+// (g_{n_s-2} + (g_{n_s-1} - g_{n_s-2}), 0); g is the row's plain values.
+__device__ __forceinline__ double2 row_pair(const double *g, int k, int n_s) {
+  if (k + 1 < n_s) {
+    const double g0 = g[k];
+    return make_double2(g0, g[k + 1] - g0);
+  }
+  const double g0 = g[n_s - 2];
+  return make_double2(__builtin_fma(1.0, g[n_s - 1] - g0, g0), 0.0);
+}
+
 // Radial slots of the lane split: lane rho takes i = rho + R t (t < T), so
 // q_i and A_i are staged for R T slots, the ones past n_r holding zeros (the
-// values a guarded read would give), and the loop reads them unguarded.
+// values a guarded read would give), and the loop reads them unguarded.  A
+// slot holds q_i then A_i of each of the rb rows staged together (stride
+// 1 + rb doubles), so one address serves all of them.
 __host__ __device__ __forceinline__ int tab_radial_slots(const TabArgs &a) { return a.R * a.T; }
 
 // RB rows and one momentum block of work: A_i of the rows, then W * pw
 // momenta.  rows[r] (r < nrb) are the rows (the others alias one of them and
-// are not stored); lA holds A_i of row r at lA[r * tab_radial_slots + i];
-// lq / lo / lm are staged.  The rows share the lane's coordinates and node
+// are not stored); lrad holds the radial slots (q_i, then
+// A_i of rows 0 .. RB - 1); lo / lm are staged.  The rows share the lane's coordinates and node
 // indices; the sum of every row is that of the row alone (same lanes, same
 // order).
 template <int UR, int RB, class Row>
 __device__ __forceinline__ void tab_block_rows(const TabArgs &a, const Row *rows, int nrb,
-                                               const double *lq, const double *lA,
+                                               const double *lrad,
                                                const double *lo, const double *lm, int64_t r0,
                                                int64_t pb, int W, int wave, int lane) {
-  const int n_a = a.n_a, n_rp = tab_radial_slots(a);
+  constexpr int S = 1 + RB;  // doubles of a radial slot
+  const int n_a = a.n_a;
   const int k_last = (int)a.n_s - 2;
   const int rho = lane & (a.R - 1);
   const int iota = lane / a.R;
@@ -110,10 +124,11 @@ __device__ __forceinline__ void tab_block_rows(const TabArgs &a, const Row *rows
     if (p >= 0.0) {
       for (int t = 0; t < a.T; ++t) {
         const int i = rho + a.R * t;  // < R T: slots past n_r hold q = A = 0
-        const double q = lq[i];
+        const double *slot = lrad + i * S;
+        const double q = slot[0];
         double A[RB];
 #pragma unroll
-        for (int r = 0; r < RB; ++r) A[r] = lA[r * n_rp + i];
+        for (int r = 0; r < RB; ++r) A[r] = slot[1 + r];
         const double qm = q - p;
         const double ah = (qm * qm) * a.inv_h;
         const double bh = ((2.0 * q) * p) * a.inv_h;
@@ -169,50 +184,45 @@ __device__ __forceinline__ void tab_block_rows(const TabArgs &a, const Row *rows
 
 // One (row, momentum block) of work: tab_block_rows with one row.
 template <int UR, class Row>
-__device__ __forceinline__ void tab_block(const TabArgs &a, const Row row, const double *lq,
-                                          const double *lA, const double *lo, const double *lm,
+__device__ __forceinline__ void tab_block(const TabArgs &a, const Row row, const double *lrad,
+                                          const double *lo, const double *lm,
                                           int64_t r, int64_t pb, int W, int wave, int lane) {
-  tab_block_rows<UR, 1>(a, &row, 1, lq, lA, lo, lm, r, pb, W, wave, lane);
+  tab_block_rows<UR, 1>(a, &row, 1, lrad, lo, lm, r, pb, W, wave, lane);
 }
 
-// Stage the row-dependent factors A_i = c_i G_r(q_i^2)^2 (and q_i).
+// Stage the row-dependent factors A_i = c_i G_r(q_i^2)^2 and q_i of one row
+// (radial slots of two doubles).
 template <class Row>
-__device__ __forceinline__ void tab_stage_A(const TabArgs &a, const Row row, double *lq,
-                                            double *lA) {
+__device__ __forceinline__ void tab_stage_A(const TabArgs &a, const Row row, double *lrad) {
   for (int i = threadIdx.x; i < a.n_r; i += blockDim.x) {
     const double q = a.tab[i];
     const double G = row((q * q) * a.inv_h, a.t_last, (int)a.n_s - 2);
-    lq[i] = q;
-    lA[i] = (a.tab[a.n_r + i] * G) * G;
+    lrad[2 * i] = q;
+    lrad[2 * i + 1] = (a.tab[a.n_r + i] * G) * G;
   }
 }
 
 
-// LDS of the table kernels: q_i | A_i of rb rows | 1 + x_j | mu_j | the row
-// (rows staged in LDS: values, or (value, slope) pairs); q_i and each row's
-// A_i take tab_radial_slots entries.  tab_lds also stages 1 + x_j and mu_j and
-// zeroes the slots past n_r (all threads of the workgroup), which the staging
-// of q_i and A_i never writes.
+// LDS of the table kernels: radial slots (q_i, A_i of rb rows) | 1 + x_j |
+// mu_j | the rows (rows staged in LDS: values, or (value, slope) pairs).  tab_lds also stages 1 + x_j and mu_j and zeroes the slots past n_r
+// (all threads of the workgroup), which the staging of q_i and A_i never
+// writes.
 struct TabLds {
-  double *lq, *lA, *lo, *lm, *lg;
+  double *lrad, *lo, *lm, *lg;
 };
 __device__ __forceinline__ TabLds tab_lds(const TabArgs &a, double *lds, int rb = 1) {
   const int n_r = a.n_r, n_a = a.n_a, n_rp = tab_radial_slots(a);
   TabLds l;
-  l.lq = lds;
-  l.lA = l.lq + n_rp;
-  l.lo = l.lA + rb * n_rp;
+  l.lrad = lds;
+  l.lo = l.lrad + (1 + rb) * n_rp;
   l.lm = l.lo + n_a;
   l.lg = l.lm + n_a;
   for (int j = threadIdx.x; j < n_a; j += blockDim.x) {
     l.lo[j] = a.tab[3 * n_r + j];
     l.lm[j] = a.tab[3 * n_r + n_a + j];
   }
-  const int pad = n_rp - n_r;
-  for (int x = threadIdx.x; x < (1 + rb) * pad; x += blockDim.x) {
-    const int r = x / pad;  // 0: q, 1 + r': A of row r'
-    l.lq[r * n_rp + n_r + (x - r * pad)] = 0.0;
-  }
+  for (int x = (1 + rb) * n_r + threadIdx.x; x < (1 + rb) * n_rp; x += blockDim.x)
+    l.lrad[x] = 0.0;
   return l;
 }
 
@@ -225,22 +235,14 @@ __device__ __forceinline__ void tab_rows_block(const TabArgs &a, const TabLds &l
   const int64_t r0 = rg * RB;
   const int nrb = (int)min<int64_t>(RB, a.n_rows - r0);
   const int n_s = (int)a.n_s, n_r = a.n_r;
-  const int len = PAIRS ? 2 * n_s : n_s;  // doubles of one staged row
+  // the rows one after another (pairs: n_s double2 each)
+  double2 *lp = reinterpret_cast<double2 *>(l.lg);
   for (int r = 0; r < nrb; ++r) {
     const double *grow = a.g + (r0 + r) * a.n_s;
-    double *dst = l.lg + r * len;
     if constexpr (PAIRS) {
-      double2 *lp = reinterpret_cast<double2 *>(dst);
-      for (int k = threadIdx.x; k < n_s; k += blockDim.x) {
-        if (k + 1 < n_s) {
-          const double g0 = grow[k];
-          lp[k] = make_double2(g0, grow[k + 1] - g0);
-        } else {
-          const double g0 = grow[n_s - 2];
-          lp[k] = make_double2(__builtin_fma(1.0, grow[n_s - 1] - g0, g0), 0.0);
-        }
-      }
+      for (int k = threadIdx.x; k < n_s; k += blockDim.x) lp[r * n_s + k] = row_pair(grow, k, n_s);
     } else {
+      double *dst = l.lg + r * n_s;
       for (int k = threadIdx.x; k < n_s; k += blockDim.x) dst[k] = grow[k];
     }
   }
@@ -249,27 +251,26 @@ __device__ __forceinline__ void tab_rows_block(const TabArgs &a, const TabLds &l
   Row rows[RB];
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
-    double *src = l.lg + (r < nrb ? r : nrb - 1) * len;
+    const int rs = r < nrb ? r : nrb - 1;
     if constexpr (PAIRS)
-      rows[r] = PairRow{reinterpret_cast<const double2 *>(src)};
+      rows[r] = PairRow{lp + rs * n_s};
     else
-      rows[r] = PlainRow{src};
+      rows[r] = PlainRow{l.lg + rs * n_s};
   }
   // A_i = c_i G_r(q_i^2)^2 of each row (and q_i)
   for (int x = threadIdx.x; x < nrb * n_r; x += blockDim.x) {
     const int r = x / n_r, i = x - r * n_r;
     const double q = a.tab[i];
-    const double *src = l.lg + r * len;
     double G;
     if constexpr (PAIRS)
-      G = PairRow{reinterpret_cast<const double2 *>(src)}((q * q) * a.inv_h, a.t_last, n_s - 2);
+      G = PairRow{lp + r * n_s}((q * q) * a.inv_h, a.t_last, n_s - 2);
     else
-      G = PlainRow{src}((q * q) * a.inv_h, a.t_last, n_s - 2);
-    if (r == 0) l.lq[i] = q;
-    l.lA[r * tab_radial_slots(a) + i] = (a.tab[n_r + i] * G) * G;
+      G = PlainRow{l.lg + r * n_s}((q * q) * a.inv_h, a.t_last, n_s - 2);
+    if (r == 0) l.lrad[i * (1 + RB)] = q;
+    l.lrad[i * (1 + RB) + 1 + r] = (a.tab[n_r + i] * G) * G;
   }
   __syncthreads();
-  tab_block_rows<UR, RB>(a, rows, nrb, l.lq, l.lA, l.lo, l.lm, r0, pb, W, wave, lane);
+  tab_block_rows<UR, RB>(a, rows, nrb, l.lrad, l.lo, l.lm, r0, pb, W, wave, lane);
 }
 
 }  // namespace dev

@@ -243,44 +243,36 @@ __global__ __launch_bounds__(RB > 1 ? 1024 : 256) void pflow_pull_kernel(TabArgs
     if (writer && threadIdx.x == 0) a.aliven[r] = alive && !bad;
     // the diagram's row as tab_rows_block stages it
     if constexpr (PAIRS) {
-      double2 *lp = reinterpret_cast<double2 *>(l.lg + rr * len);
-      for (int k = threadIdx.x; k < n_s; k += blockDim.x) {
-        if (k + 1 < n_s) {
-          const double g0 = lv[k];
-          lp[k] = make_double2(g0, lv[k + 1] - g0);
-        } else {
-          const double g0 = lv[n_s - 2];
-          lp[k] = make_double2(__builtin_fma(1.0, lv[n_s - 1] - g0, g0), 0.0);
-        }
-      }
+      double2 *lp = reinterpret_cast<double2 *>(l.lg) + rr * n_s;
+      for (int k = threadIdx.x; k < n_s; k += blockDim.x) lp[k] = row_pair(lv, k, n_s);
     }
   }
   __syncthreads();
   using Row = typename std::conditional<PAIRS, PairRow, PlainRow>::type;
+  const double2 *lp = reinterpret_cast<const double2 *>(l.lg);
   Row rows[RB];
 #pragma unroll
   for (int rr = 0; rr < RB; ++rr) {
-    const double *src = l.lg + (rr < nrb ? rr : nrb - 1) * len;
+    const int rs = rr < nrb ? rr : nrb - 1;
     if constexpr (PAIRS)
-      rows[rr] = PairRow{reinterpret_cast<const double2 *>(src)};
+      rows[rr] = PairRow{lp + rs * n_s};
     else
-      rows[rr] = PlainRow{src};
+      rows[rr] = PlainRow{l.lg + rs * n_s};
   }
   // q_i and A_i of each row at scale k
   for (int x = threadIdx.x; x < nrb * n_r; x += blockDim.x) {
     const int rr = x / n_r, i = x - rr * n_r;
     const double q = a.k * a.base[i];
-    const double *src = l.lg + rr * len;
     double G;
     if constexpr (PAIRS)
-      G = PairRow{reinterpret_cast<const double2 *>(src)}((q * q) * t.inv_h, t.t_last, n_s - 2);
+      G = PairRow{lp + rr * n_s}((q * q) * t.inv_h, t.t_last, n_s - 2);
     else
-      G = PlainRow{src}((q * q) * t.inv_h, t.t_last, n_s - 2);
-    if (rr == 0) l.lq[i] = q;
-    l.lA[rr * tab_radial_slots(t) + i] = ((a.kd2 * a.base[n_r + i]) * G) * G;
+      G = PlainRow{l.lg + rr * n_s}((q * q) * t.inv_h, t.t_last, n_s - 2);
+    if (rr == 0) l.lrad[i * (1 + RB)] = q;
+    l.lrad[i * (1 + RB) + 1 + rr] = ((a.kd2 * a.base[n_r + i]) * G) * G;
   }
   __syncthreads();
-  tab_block_rows<UR, RB>(t, rows, nrb, l.lq, l.lA, l.lo, l.lm, r0, pb, W, wave, lane);
+  tab_block_rows<UR, RB>(t, rows, nrb, l.lrad, l.lo, l.lm, r0, pb, W, wave, lane);
   // tadpole of this stage of each flow, as prep_row (wave 0 of the storing
   // workgroup)
   if (writer && threadIdx.x < kWave) {

@@ -52,10 +52,10 @@ __global__ __launch_bounds__(RB > 1 ? 1024 : 256) void tab_kernel(TabArgs a) {
     for (int64_t r = x; r < a.n_rows; r += 8) {
       const PlainRow grow{a.g + r * a.n_s};
       __syncthreads();  // the previous row's A_i are no longer read
-      tab_stage_A(a, grow, l.lq, l.lA);
+      tab_stage_A(a, grow, l.lrad);
       __syncthreads();
       for (int64_t pb = slot; pb < a.n_pb; pb += slots)
-        tab_block<UR>(a, grow, l.lq, l.lA, l.lo, l.lm, r, pb, W, wave, lane);
+        tab_block<UR>(a, grow, l.lrad, l.lo, l.lm, r, pb, W, wave, lane);
     }
   }
 }
