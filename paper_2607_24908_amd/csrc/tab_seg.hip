@@ -235,18 +235,19 @@ __global__ __launch_bounds__(kNT) void tab_seg_kernel(TabArgs a, const unsigned 
   const int n_r = a.n_r, n_a = a.n_a;
   const int tid = threadIdx.x;
   double *lg0 = lds;                      // two segment buffers [kRB][kRowLds]
-  double *lq = lg0 + 2 * kBufD;           // q_i
-  double *lA = lq + n_r;                  // [kRB][n_r]
-  double *lo = lA + kRB * n_r;            // 1 + x_j
-  double *lm = lo + n_a;                  // mu_j
-  int *ns = reinterpret_cast<int *>(lm + n_a);  // splits per superchunk
+  // radial slots [n_r][1 + kRB]: q_i, then A_i of the batch's rows; angular
+  // slots [n_a][2]: 1 + x_j, mu_j (one address per node)
+  constexpr int kRS = 1 + kRB;
+  double *lrad = lg0 + 2 * kBufD;
+  double *lang = lrad + kRS * n_r;
+  int *ns = reinterpret_cast<int *>(lang + 2 * n_a);  // splits per superchunk
   int *ord = ns + n_super;                       // superchunks, costliest first
   long long *pre = reinterpret_cast<long long *>(ord + n_super);  // item prefix (8-byte aligned)
   int *claim = reinterpret_cast<int *>(pre + n_super + 1);
-  for (int i = tid; i < n_r; i += kNT) lq[i] = a.tab[i];
+  for (int i = tid; i < n_r; i += kNT) lrad[i * kRS] = a.tab[i];
   for (int j = tid; j < n_a; j += kNT) {
-    lo[j] = a.tab[3 * n_r + j];
-    lm[j] = a.tab[3 * n_r + n_a + j];
+    lang[2 * j] = a.tab[3 * n_r + j];
+    lang[2 * j + 1] = a.tab[3 * n_r + n_a + j];
   }
   // the plan (the same in every workgroup)
   const int smin = (int)((a.n_p + kItemMax - 1) / kItemMax);
@@ -307,7 +308,7 @@ __global__ __launch_bounds__(kNT) void tab_seg_kernel(TabArgs a, const unsigned 
       double A = 0.0;
       if (r < nrb) {
         const double *row = a.g + (r0 + r) * a.n_s;
-        const double q = lq[i];
+        const double q = lrad[i * kRS];
         const double t = fmin((q * q) * a.inv_h, a.t_last);
         int k = (int)t;
         k = k < k_last ? k : k_last;
@@ -316,7 +317,7 @@ __global__ __launch_bounds__(kNT) void tab_seg_kernel(TabArgs a, const unsigned 
         const double G = __builtin_fma(f, g1 - g0, g0);
         A = (a.tab[n_r + i] * G) * G;
       }
-      lA[x] = A;
+      lrad[i * kRS + 1 + r] = A;
     }
     // this lane's momentum
     const int64_t my = p_lo + wave + (int64_t)kWaves * lane;
@@ -379,15 +380,16 @@ __global__ __launch_bounds__(kNT) void tab_seg_kernel(TabArgs a, const unsigned 
           // away from a multiple of n_a)
           const int i = (int)(((float)e + 0.5f) * inv_na);
           const int j = (int)e - i * n_a;
-          const double q = lq[i];
+          const double *rad = lrad + i * kRS;
+          const double q = rad[0];
           const double qm = q - p;
           const double ah = (qm * qm) * a.inv_h;
           const double bh = ((2.0 * q) * p) * a.inv_h;
-          const double t = fmin(__builtin_fma(bh, lo[j], ah), a.t_last);
+          const double t = fmin(__builtin_fma(bh, lang[2 * j], ah), a.t_last);
           int k = (int)t;
           k = k < k_last ? k : k_last;
           const double f = t - (double)k;
-          const double mu = lm[j];
+          const double mu = lang[2 * j + 1];
           // k lies in the segment by construction; the clamp only keeps the
           // LDS index in bounds
           int x = k - T0;
@@ -395,7 +397,7 @@ __global__ __launch_bounds__(kNT) void tab_seg_kernel(TabArgs a, const unsigned 
 #pragma unroll
           for (int r = 0; r < kRB; ++r) {
             const double g0 = lg[r * kRowLds + x], g1 = lg[r * kRowLds + x + 1];
-            in[r] = __builtin_fma(lA[r * n_r + i] * mu, __builtin_fma(f, g1 - g0, g0), in[r]);
+            in[r] = __builtin_fma(rad[1 + r] * mu, __builtin_fma(f, g1 - g0, g0), in[r]);
           }
         }
         // lane groups of 16 end with the sums of rows 0..3
