@@ -133,27 +133,49 @@ __device__ __forceinline__ double fma_su(double a, double b, double c) {
   asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
   return r;
 }
+__device__ __forceinline__ double fma_vu(double a, double b, double c) {
+  return __builtin_fma(a, b, c);
+}
+
+// One coefficient group c at x: N, r = 1/P and M r, whose terms enter the
+// sums as s1 = fma(N, r, s1), s2 = fma(M r, r, s2).  UNIFORM: c is the same
+// in every lane (scalar operands); else per lane (the same operations).
+template <bool UNIFORM>
+__device__ __forceinline__ void fv_group(double x, const double *c, double &N, double &r,
+                                         double &Mr) {
+  auto fm = [](double u, double v, double w) {
+    if constexpr (UNIFORM)
+      return fma_su(u, v, w);
+    else
+      return fma_vu(u, v, w);
+  };
+  double P = x + c[7];
+#pragma unroll
+  for (int k = 6; k >= 0; --k) P = fm(P, x, c[k]);
+  N = c[15];
+#pragma unroll
+  for (int k = 14; k >= 8; --k) N = fm(N, x, c[k]);
+  double M = c[30];
+#pragma unroll
+  for (int k = 29; k >= 16; --k) M = fm(M, x, c[k]);
+  r = rcp64(P);
+  Mr = M * r;
+}
+
+__device__ __forceinline__ bool fv_coef_range(double x) { return x >= kFvXMin && x <= kFvXMax; }
+
 __device__ __forceinline__ void fv_radial(const FvArgs &a, const double *tab,
                                           const double *__restrict__ cf, double x, double &s1,
                                           double &s2) {
   s1 = 0.0;
   s2 = 0.0;
-  if (x >= kFvXMin && x <= kFvXMax) {
+  if (fv_coef_range(x)) {
     const int ng = (a.n_r + kFvGroup - 1) / kFvGroup;
     for (int g = 0; g < ng; ++g) {
-      const double *c = cf + kFvCoef * g;
-      double P = x + c[7];
-#pragma unroll
-      for (int k = 6; k >= 0; --k) P = fma_su(P, x, c[k]);
-      double N = c[15];
-#pragma unroll
-      for (int k = 14; k >= 8; --k) N = fma_su(N, x, c[k]);
-      double M = c[30];
-#pragma unroll
-      for (int k = 29; k >= 16; --k) M = fma_su(M, x, c[k]);
-      const double r = rcp64(P);
+      double N, r, Mr;
+      fv_group<true>(x, cf + kFvCoef * g, N, r, Mr);
       s1 = __builtin_fma(N, r, s1);
-      s2 = __builtin_fma(M * r, r, s2);
+      s2 = __builtin_fma(Mr, r, s2);
     }
   } else {
     for (int i = 0; i < a.n_r; ++i) {
@@ -165,14 +187,20 @@ __device__ __forceinline__ void fv_radial(const FvArgs &a, const double *tab,
   }
 }
 
-// F_1 = C_d k^d s1 and F_2 = C_d k^(d-2) s2 at dh = x.
+// F_1 = C_d k^d s1 and F_2 = C_d k^(d-2) s2 from the radial sums.
+__device__ __forceinline__ void fv_scale_sums(const FvArgs &a, const FvScale &sc, double s1,
+                                              double s2, double &F1, double &F2) {
+  F1 = a.Cd * sc.kd * s1;
+  F2 = a.Cd * sc.kdm2 * s2;
+}
+
+// F_1 and F_2 at dh = x.
 __device__ __forceinline__ void fv_mass(const FvArgs &a, const FvScale &sc, const double *tab,
                                         const double *__restrict__ cf, double x, double &F1,
                                         double &F2) {
   double s1, s2;
   fv_radial(a, tab, cf, x, s1, s2);
-  F1 = a.Cd * sc.kd * s1;
-  F2 = a.Cd * sc.kdm2 * s2;
+  fv_scale_sums(a, sc, s1, s2, F1, F2);
 }
 
 // Flux Q and the local bound lam of the step estimate at interface j from
@@ -313,6 +341,7 @@ __global__ __launch_bounds__(1024) void fv_solve_kernel(FvArgs a, const double *
   if (tid == 0) *bad_flag = 0;
   __syncthreads();
   const double cs[3] = {0.0, 1.0, 0.5};
+  const int ng = (a.n_r + kFvGroup - 1) / kFvGroup;  // coefficient groups
   for (int64_t st = 0; st < n_st; ++st) {
     const double tn = (double)(s0 + st) * a.h;
     for (int s = 0; s < 3; ++s) {
@@ -342,11 +371,45 @@ __global__ __launch_bounds__(1024) void fv_solve_kernel(FvArgs a, const double *
         for (int i = tid; i < n; i += bs) a.y0[r * n + i] = y0[i];
         return;
       }
-      for (int t = tid; t < 3 * nq; t += bs) {
+      // radial sums, one lane per (interface, mass) task.  When the tasks
+      // leave a few in a last wave (3 (n + 1) = 64 w + tail), that wave
+      // splits each of its tail tasks over the coefficient groups, one lane
+      // per group, and the task's first lane folds the groups' terms in
+      // order: the operations of one lane alone (the same bits), in the time
+      // of one group instead of all of them, so the SIMD that holds that wave
+      // is not left with one more whole radial sum than the others.
+      const int T = 3 * nq, tail = T % kWave, t_full = T - tail;
+      const bool split = tail > 0 && T <= bs && tail * ng <= kWave;  // workgroup-uniform
+      for (int t = tid; t < (split ? t_full : T); t += bs) {
         const int j = t / 3, m = t - 3 * j;
         if (m < lN[j]) {
           double F1, F2;
           fv_mass(a, sc, tab, cf, lP[6 * j + m], F1, F2);
+          lP[6 * j + m] = F1;
+          lF2[3 * j + m] = F2;
+        }
+      }
+      if (split && tid >= t_full && tid < t_full + kWave) {  // wave-uniform: the last wave
+        const int l = tid - t_full;
+        const int k = l / ng, g = l - k * ng;  // tail task k, group g
+        const int tk = t_full + (k < tail ? k : 0);
+        const int j = tk / 3, m = tk - 3 * j;
+        const bool real = k < tail && m < lN[j];
+        const double x = real ? lP[6 * j + m] : 1.0;
+        double Nv = 0.0, rv = 0.0, Mr = 0.0;
+        if (real && fv_coef_range(x)) fv_group<false>(x, cf + kFvCoef * g, Nv, rv, Mr);
+        double s1 = 0.0, s2 = 0.0;
+        for (int gg = 0; gg < ng; ++gg) {  // every lane of the wave takes part
+          const int src = min(k * ng + gg, kWave - 1);
+          const double n_ = __shfl(Nv, src, kWave), r_ = __shfl(rv, src, kWave);
+          const double m_ = __shfl(Mr, src, kWave);
+          s1 = __builtin_fma(n_, r_, s1);
+          s2 = __builtin_fma(m_, r_, s2);
+        }
+        if (real && g == 0) {
+          if (!fv_coef_range(x)) fv_radial(a, tab, cf, x, s1, s2);  // term by term
+          double F1, F2;
+          fv_scale_sums(a, sc, s1, s2, F1, F2);
           lP[6 * j + m] = F1;
           lF2[3 * j + m] = F2;
         }
