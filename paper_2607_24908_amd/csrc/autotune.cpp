@@ -187,6 +187,7 @@ using namespace frg;
 extern "C" {
 
 int frg_autotune(frg_ctx *ctx, int32_t mode, const char *cache_path) {
+  frg::TraceRange trace_("frg_autotune");
   if (!ctx) return fail(FRG_E_INVAL, "ctx is NULL");
   if (mode != 0 && mode != 1) return fail(FRG_E_INVAL, "mode must be 0 or 1");
   std::lock_guard<std::mutex> lk(ctx->mu);

@@ -875,6 +875,7 @@ void frg_destroy(frg_ctx *ctx) { delete ctx; }
 
 int frg_integrate(frg_ctx *ctx, const frg_set *sets, int32_t n_sets, int32_t mem, int32_t flags,
                   void *hip_stream) {
+  frg::TraceRange trace_("frg_integrate");
   if (!ctx) return fail(FRG_E_INVAL, "ctx is NULL");
   if (n_sets < 0 || (n_sets > 0 && !sets)) return fail(FRG_E_INVAL, "bad set array");
   if (mem != FRG_MEM_HOST && mem != FRG_MEM_DEVICE) return fail(FRG_E_INVAL, "mem must be FRG_MEM_HOST or FRG_MEM_DEVICE");
@@ -905,6 +906,7 @@ int frg_integrate(frg_ctx *ctx, const frg_set *sets, int32_t n_sets, int32_t mem
 int frg_integrate_grid(frg_ctx *ctx, const frg_quad *quad, int64_t n_p, const double *p,
                        int64_t n_m, const double *m2, double *out, double *err_est,
                        uint8_t *used_fp64, int32_t mem, void *hip_stream) {
+  frg::TraceRange trace_("frg_integrate_grid");
   if (!ctx || !quad) return fail(FRG_E_INVAL, "NULL argument");
   int rc = check_quad(*quad);
   if (rc) return rc;
@@ -952,6 +954,7 @@ int frg_integrate_grid(frg_ctx *ctx, const frg_quad *quad, int64_t n_p, const do
 
 int frg_integrate_tab(frg_ctx *ctx, const frg_quad *quad, const frg_gtab *tab, int64_t n_p,
                       const double *p, double *out, int32_t mem, void *hip_stream) {
+  frg::TraceRange trace_("frg_integrate_tab");
   if (!ctx || !quad || !tab) return fail(FRG_E_INVAL, "NULL argument");
   int rc = check_quad(*quad);
   if (rc) return rc;
@@ -998,6 +1001,7 @@ int frg_integrate_tab(frg_ctx *ctx, const frg_quad *quad, const frg_gtab *tab, i
 
 int frg_flow_rhs(frg_ctx *ctx, const frg_lpa *lpa, double t, const double *U, double *dUdt,
                  double *jac_bands, int32_t mem, void *hip_stream) {
+  frg::TraceRange trace_("frg_flow_rhs");
   if (!ctx || !lpa || !U || !dUdt) return fail(FRG_E_INVAL, "NULL argument");
   int rc = check_lpa(*lpa);
   if (rc) return rc;
@@ -1045,6 +1049,7 @@ int frg_flow_rhs(frg_ctx *ctx, const frg_lpa *lpa, double t, const double *U, do
 int frg_flow_rhs_batch(frg_ctx *ctx, int32_t n_flows, const frg_lpa *lpa, const double *t,
                        const double *const *U, double *const *dUdt, double *const *jac_bands,
                        void *hip_stream) {
+  frg::TraceRange trace_("frg_flow_rhs_batch");
   if (!ctx || n_flows < 0) return fail(FRG_E_INVAL, "bad arguments");
   if (n_flows == 0) return FRG_OK;
   if (!lpa || !t || !U || !dUdt) return fail(FRG_E_INVAL, "NULL argument");

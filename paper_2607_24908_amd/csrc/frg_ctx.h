@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <atomic>
 #include <map>
@@ -14,6 +15,15 @@
 #include "frg_internal.h"
 
 namespace frg {
+
+// A named roctx range over a scope (entry points, server batches): shown by
+// rocprofv3 --marker-trace, a few nanoseconds when no tool is attached.
+struct TraceRange {
+  explicit TraceRange(const char *name) { roctxRangePush(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange &) = delete;
+  TraceRange &operator=(const TraceRange &) = delete;
+};
 
 int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);

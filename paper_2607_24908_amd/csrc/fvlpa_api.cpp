@@ -127,6 +127,7 @@ extern "C" {
 
 int frg_fvlpa_rhs(frg_ctx *ctx, const frg_fvlpa *fv, int64_t n_flows, double t, const double *u,
                   double *dudt, double *dt_est, int32_t mem, void *hip_stream) {
+  frg::TraceRange trace_("frg_fvlpa_rhs");
   if (!ctx || !fv) return fail(FRG_E_INVAL, "NULL argument");
   int rc = check_fvlpa(*fv, n_flows);
   if (rc) return rc;
@@ -172,6 +173,7 @@ int frg_fvlpa_rhs(frg_ctx *ctx, const frg_fvlpa *fv, int64_t n_flows, double t, 
 
 int frg_fvlpa_solve(frg_ctx *ctx, const frg_fvlpa *fv, int64_t n_flows, double t_end,
                     int64_t n_steps, double *u, double *t_reached, int32_t mem, void *hip_stream) {
+  frg::TraceRange trace_("frg_fvlpa_solve");
   if (!ctx || !fv) return fail(FRG_E_INVAL, "NULL argument");
   int rc = check_fvlpa(*fv, n_flows);
   if (rc) return rc;

@@ -257,6 +257,7 @@ extern "C" {
 int frg_pflow_rhs(frg_ctx *ctx, const frg_pflow *pf, int64_t n_flows, const double *lam3,
                   const double *lam4, double t, const double *sigma, double *dsdt, int32_t mem,
                   void *hip_stream) {
+  frg::TraceRange trace_("frg_pflow_rhs");
   if (!ctx || !pf) return fail(FRG_E_INVAL, "NULL argument");
   int rc = check_pflow(*pf, n_flows);
   if (rc) return rc;
@@ -304,6 +305,7 @@ int frg_pflow_rhs(frg_ctx *ctx, const frg_pflow *pf, int64_t n_flows, const doub
 int frg_pflow_solve(frg_ctx *ctx, const frg_pflow *pf, int64_t n_flows, const double *lam3,
                     const double *lam4, double t_end, int64_t n_steps, double *sigma,
                     double *t_reached, int32_t mem, void *hip_stream) {
+  frg::TraceRange trace_("frg_pflow_solve");
   if (!ctx || !pf) return fail(FRG_E_INVAL, "NULL argument");
   int rc = check_pflow(*pf, n_flows);
   if (rc) return rc;

@@ -183,6 +183,7 @@ void Server::admit_locked() {
 }
 
 int Server::rhs_cb(void *user, double t, const double *U, int64_t n, double *dUdt, double *jac) {
+  TraceRange trace_("frg_server_rhs");  // a flow thread's right-hand side, queued to its answer
   Flow *f = static_cast<Flow *>(user);
   Server *s = f->srv;
   if (n != f->n) return FRG_E_INVAL;
@@ -246,6 +247,7 @@ void Server::dispatch_loop() {
       batch.swap(pending);
       n_pending.store(0, std::memory_order_relaxed);
     }
+    TraceRange trace_("frg_server_batch");  // staging, one launch, its synchronisation
     const int nb = (int)batch.size();
     lpas.resize(nb);
     ts.resize(nb);
@@ -353,6 +355,7 @@ using namespace frg;
 extern "C" {
 
 int frg_submit(frg_ctx *ctx, const frg_request *req, uint64_t *ticket) {
+  frg::TraceRange trace_("frg_submit");
   if (!ctx || !req || !ticket) return fail(FRG_E_INVAL, "NULL argument");
   int rc = check_lpa(req->lpa);
   if (rc) return rc;

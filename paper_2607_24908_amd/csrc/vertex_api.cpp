@@ -88,6 +88,7 @@ extern "C" {
 int frg_integrate_vertex(frg_ctx *ctx, const frg_quad *quad, int32_t n_azimuth, int64_t n_c,
                          const double *p1, const double *p2, const double *cos12, int64_t n_m,
                          const double *m2, double *out, int32_t mem, void *hip_stream) {
+  frg::TraceRange trace_("frg_integrate_vertex");
   if (!ctx || !quad) return fail(FRG_E_INVAL, "NULL argument");
   int rc = check_quad(*quad);
   if (rc) return rc;
