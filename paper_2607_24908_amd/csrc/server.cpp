@@ -66,13 +66,30 @@ struct Flow {
   std::thread th;
 };
 
+// One staging buffer: the batch's descriptors, inputs, flags and outputs.
+struct Stage {
+  char *h = nullptr;   // pinned, mapped, coherent
+  char *hd = nullptr;  // its device address
+  char *d = nullptr;   // device mirror (copy mode)
+  size_t cap = 0;
+  hipEvent_t done = nullptr;  // recorded after the batch's last operation
+};
+
+// A launched batch, until its outputs are handed back.
+struct Batch {
+  std::vector<Flow *> flows;
+  std::vector<size_t> o_o;  // each flow's outputs in the staging buffer
+  size_t o_flags = 0;
+  int slot = 0;
+  int rc = FRG_OK;
+};
+
 struct Server {
   Context *ctx = nullptr;
   hipStream_t stream = nullptr;
-  char *h_stage = nullptr;   // pinned, mapped, coherent
-  char *hd_stage = nullptr;  // its device address
-  char *d_stage = nullptr;   // device mirror (copy mode)
-  size_t stage_cap = 0;
+  // two staging buffers: the next batch is staged and enqueued while the
+  // previous one runs (at most two batches in flight, handed back in order)
+  Stage stg[2];
   std::mutex m;
   std::condition_variable cv_disp;
   std::deque<Flow *> queue;
@@ -95,7 +112,9 @@ struct Server {
   void admit_locked();
   static int rhs_cb(void *user, double t, const double *U, int64_t n, double *dUdt, double *jac);
   void run_flow(Flow *f);
-  bool grow_stage(size_t bytes);
+  bool grow_stage(Stage &g, size_t bytes);
+  void launch_batch(Batch &b);
+  void finish_batch(Batch &b);
 };
 
 // A right-hand side comes back, and the next call arrives, within tens of
@@ -118,6 +137,9 @@ static bool spin_until(Cond cond) {
 int Server::start() {
   if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess)
     return fail(FRG_E_DEVICE, "server stream");
+  for (Stage &g : stg)
+    if (hipEventCreateWithFlags(&g.done, hipEventDisableTiming) != hipSuccess)
+      return fail(FRG_E_DEVICE, "server event");
   if (const char *e = std::getenv("FRG_SERVER_SLOTS")) max_active = std::max(1, std::atoi(e));
   disp = std::thread([this] { dispatch_loop(); });
   return FRG_OK;
@@ -140,30 +162,34 @@ void Server::shutdown() {
   }
   flows.clear();
   queue.clear();
-  if (d_stage) hipFree(d_stage);
-  if (h_stage) hipHostFree(h_stage);
-  if (stream) hipStreamDestroy(stream);
+  if (stream) (void)hipStreamSynchronize(stream);
+  for (Stage &g : stg) {
+    if (g.d) (void)hipFree(g.d);
+    if (g.h) (void)hipHostFree(g.h);
+    if (g.done) (void)hipEventDestroy(g.done);
+  }
+  if (stream) (void)hipStreamDestroy(stream);
 }
 
-// Dispatcher thread only (no batch in flight): make the staging buffer hold
-// `bytes`.
-bool Server::grow_stage(size_t bytes) {
-  if (bytes <= stage_cap) return true;
-  const size_t cap = std::max(bytes, 2 * stage_cap);
-  if (d_stage) hipFree(d_stage);
-  if (h_stage) hipHostFree(h_stage);
-  d_stage = h_stage = hd_stage = nullptr;
-  stage_cap = 0;
-  if (hipMalloc((void **)&d_stage, cap) != hipSuccess) return false;
-  if (hipHostMalloc((void **)&h_stage, cap, hipHostMallocMapped | hipHostMallocCoherent) !=
+// Dispatcher thread only (no batch of this buffer in flight): make the
+// staging buffer hold `bytes`.
+bool Server::grow_stage(Stage &g, size_t bytes) {
+  if (bytes <= g.cap) return true;
+  const size_t cap = std::max(bytes, 2 * g.cap);
+  if (g.d) (void)hipFree(g.d);
+  if (g.h) (void)hipHostFree(g.h);
+  g.d = g.h = g.hd = nullptr;
+  g.cap = 0;
+  if (hipMalloc((void **)&g.d, cap) != hipSuccess) return false;
+  if (hipHostMalloc((void **)&g.h, cap, hipHostMallocMapped | hipHostMallocCoherent) !=
           hipSuccess ||
-      hipHostGetDevicePointer((void **)&hd_stage, h_stage, 0) != hipSuccess) {
-    if (h_stage) hipHostFree(h_stage);
-    hipFree(d_stage);
-    d_stage = h_stage = hd_stage = nullptr;
+      hipHostGetDevicePointer((void **)&g.hd, g.h, 0) != hipSuccess) {
+    if (g.h) (void)hipHostFree(g.h);
+    (void)hipFree(g.d);
+    g.d = g.h = g.hd = nullptr;
     return false;
   }
-  stage_cap = cap;
+  g.cap = cap;
   return true;
 }
 
@@ -226,117 +252,151 @@ void Server::run_flow(Flow *f) {
   admit_locked();
 }
 
-void Server::dispatch_loop() {
-  std::vector<Flow *> batch;
-  std::vector<frg_lpa> lpas;
-  std::vector<double> ts;
-  std::vector<const double *> Us;
-  std::vector<double *> Ds, Js;
-  std::vector<LpaJob> jobs;
-  std::vector<int64_t> start;
-  std::vector<size_t> o_u, o_o;
+// Stage the batch's right-hand sides into its buffer and enqueue it on the
+// server stream: the buffer's layout is jobs | start | U of each flow | flags
+// | outputs of each flow (dU/dt, then the 7 bands when asked); [0, o_out)
+// goes up and [o_flags, end) comes back (copy mode), or the kernel reads and
+// writes the pinned buffer in place (zero copy).  Records the buffer's event.
+void Server::launch_batch(Batch &b) {
+  TraceRange trace_("frg_server_batch");  // staging and enqueueing one launch
   auto up8 = [](size_t x) { return (x + 7) & ~(size_t)7; };
-  hipSetDevice(ctx->device);
+  const int nb = (int)b.flows.size();
+  std::vector<frg_lpa> lpas(nb);
+  std::vector<double> ts(nb);
+  std::vector<const double *> Us(nb);
+  std::vector<double *> Ds(nb), Js(nb);
+  std::vector<LpaJob> jobs(nb);
+  std::vector<int64_t> start(nb + 1);
+  std::vector<size_t> o_u(nb);
+  b.o_o.resize(nb);
+  const size_t o_start = up8(nb * sizeof(LpaJob));
+  const size_t o_U = up8(o_start + (nb + 1) * sizeof(int64_t));
+  size_t cu = o_U;
+  for (int i = 0; i < nb; ++i) {
+    o_u[i] = cu;
+    cu += b.flows[i]->n * sizeof(double);
+  }
+  b.o_flags = cu;
+  size_t co = up8(b.o_flags + nb * sizeof(int));
+  const size_t o_out = co;
+  for (int i = 0; i < nb; ++i) {
+    b.o_o[i] = co;
+    co += (b.flows[i]->want_jac ? 8 : 1) * b.flows[i]->n * sizeof(double);
+  }
+  const size_t end = co;
+  Stage &g = stg[b.slot];
+  if (!grow_stage(g, end)) {
+    b.rc = FRG_E_NOMEM;
+    return;
+  }
+  bool zero_copy;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    zero_copy = ctx->tune.server_zero_copy != 0;
+  }
+  char *dev = zero_copy ? g.hd : g.d;  // where the kernel finds the buffer
+  for (int i = 0; i < nb; ++i) {
+    Flow *f = b.flows[i];
+    lpas[i] = f->req.lpa;
+    ts[i] = f->t;
+    std::memcpy(g.h + o_u[i], f->U_src, f->n * sizeof(double));
+    Us[i] = (const double *)(dev + o_u[i]);
+    Ds[i] = (double *)(dev + b.o_o[i]);
+    Js[i] = f->want_jac ? Ds[i] + f->n : nullptr;
+  }
+  std::memset(g.h + b.o_flags, 0, o_out - b.o_flags);
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    b.rc = ctx->lpa_job_table(nb, lpas.data(), ts.data(), Us.data(), Ds.data(), Js.data(),
+                              (int *)(dev + b.o_flags), jobs.data(), start.data());
+  }
+  if (b.rc != FRG_OK) return;
+  std::memcpy(g.h, jobs.data(), nb * sizeof(LpaJob));
+  std::memcpy(g.h + o_start, start.data(), (nb + 1) * sizeof(int64_t));
+  bool ok;
+  if (zero_copy) {
+    ok = launch_lpa((const LpaJob *)dev, (const int64_t *)(dev + o_start), nb, start[nb],
+                    stream) == 0;
+  } else {
+    ok = hipMemcpyAsync(g.d, g.h, o_out, hipMemcpyHostToDevice, stream) == hipSuccess &&
+         launch_lpa((const LpaJob *)dev, (const int64_t *)(dev + o_start), nb, start[nb],
+                    stream) == 0 &&
+         hipMemcpyAsync(g.h + b.o_flags, g.d + b.o_flags, end - b.o_flags,
+                        hipMemcpyDeviceToHost, stream) == hipSuccess;
+  }
+  ok = ok && hipEventRecord(g.done, stream) == hipSuccess;
+  if (!ok) b.rc = FRG_E_DEVICE;
+}
+
+// Wait for a launched batch and hand its outputs back to its flows.
+void Server::finish_batch(Batch &b) {
+  Stage &g = stg[b.slot];
+  if (b.rc == FRG_OK && hipEventSynchronize(g.done) != hipSuccess) b.rc = FRG_E_DEVICE;
+  const int nb = (int)b.flows.size();
+  if (b.rc == FRG_OK) {
+    for (int i = 0; i < nb; ++i) {
+      Flow *f = b.flows[i];
+      const double *o = (const double *)(g.h + b.o_o[i]);
+      std::memcpy(f->dUdt_dst, o, f->n * sizeof(double));
+      if (f->want_jac) std::memcpy(f->jac_dst, o + f->n, 7 * f->n * sizeof(double));
+    }
+  }
+  const int *flags = b.rc == FRG_OK ? (const int *)(g.h + b.o_flags) : nullptr;
+  std::lock_guard<std::mutex> lk(m);
+  ++launches;
+  batched += nb;
+  for (int i = 0; i < nb; ++i) {
+    Flow *f = b.flows[i];
+    f->rc = b.rc != FRG_OK ? b.rc : (flags[i] ? FRG_E_DOMAIN : FRG_OK);
+    f->ready = true;
+    f->ready_a.store(true, std::memory_order_release);
+    f->cv.notify_one();
+  }
+}
+
+// Batches of the pending right-hand sides.  With no batch in flight the
+// dispatcher waits for work; with one in flight it takes whatever is pending
+// right away, stages and enqueues it (behind the running one, into the other
+// buffer), and only then waits for the running one and hands it back.
+void Server::dispatch_loop() {
+  (void)hipSetDevice(ctx->device);
+  Batch inflight;
+  bool busy = false;
   for (;;) {
-    batch.clear();
-    spin_until([&] { return n_pending.load(std::memory_order_acquire) > 0; });
-    {
+    Batch next;
+    bool stopping = false;
+    if (!busy) {
+      spin_until([&] { return n_pending.load(std::memory_order_acquire) > 0; });
       std::unique_lock<std::mutex> lk(m);
       cv_disp.wait(lk, [&] { return !pending.empty() || stop; });
-      if (stop) return;
-      batch.swap(pending);
-      n_pending.store(0, std::memory_order_relaxed);
-    }
-    TraceRange trace_("frg_server_batch");  // staging, one launch, its synchronisation
-    const int nb = (int)batch.size();
-    lpas.resize(nb);
-    ts.resize(nb);
-    Us.resize(nb);
-    Ds.resize(nb);
-    Js.resize(nb);
-    jobs.resize(nb);
-    start.resize(nb + 1);
-    o_u.resize(nb);
-    o_o.resize(nb);
-    // staging layout: jobs | start | U of each flow | flags | outputs of each
-    // flow (dU/dt, then the 7 bands when asked); [0, o_out) goes up,
-    // [o_flags, end) comes back
-    const size_t o_start = up8(nb * sizeof(LpaJob));
-    const size_t o_U = up8(o_start + (nb + 1) * sizeof(int64_t));
-    size_t cu = o_U;
-    for (int i = 0; i < nb; ++i) {
-      o_u[i] = cu;
-      cu += batch[i]->n * sizeof(double);
-    }
-    const size_t o_flags = cu;
-    size_t co = up8(o_flags + nb * sizeof(int));
-    const size_t o_out = co;
-    for (int i = 0; i < nb; ++i) {
-      o_o[i] = co;
-      co += (batch[i]->want_jac ? 8 : 1) * batch[i]->n * sizeof(double);
-    }
-    const size_t end = co;
-    bool ok = grow_stage(end);
-    int rc = ok ? FRG_OK : FRG_E_NOMEM;
-    bool zero_copy = false;
-    if (ok) {
-      {
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        zero_copy = ctx->tune.server_zero_copy != 0;
+      stopping = stop;
+      if (!stopping) {
+        next.flows.swap(pending);
+        n_pending.store(0, std::memory_order_relaxed);
       }
-      char *dev = zero_copy ? hd_stage : d_stage;  // where the kernel finds the buffer
-      for (int i = 0; i < nb; ++i) {
-        Flow *f = batch[i];
-        lpas[i] = f->req.lpa;
-        ts[i] = f->t;
-        std::memcpy(h_stage + o_u[i], f->U_src, f->n * sizeof(double));
-        Us[i] = (const double *)(dev + o_u[i]);
-        Ds[i] = (double *)(dev + o_o[i]);
-        Js[i] = f->want_jac ? Ds[i] + f->n : nullptr;
-      }
-      std::memset(h_stage + o_flags, 0, o_out - o_flags);
-      {
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        rc = ctx->lpa_job_table(nb, lpas.data(), ts.data(), Us.data(), Ds.data(), Js.data(),
-                                (int *)(dev + o_flags), jobs.data(), start.data());
-      }
-      ok = rc == FRG_OK;
-      if (ok) {
-        std::memcpy(h_stage, jobs.data(), nb * sizeof(LpaJob));
-        std::memcpy(h_stage + o_start, start.data(), (nb + 1) * sizeof(int64_t));
-        if (zero_copy) {
-          ok = launch_lpa((const LpaJob *)dev, (const int64_t *)(dev + o_start), nb, start[nb],
-                          stream) == 0;
-        } else {
-          ok = hipMemcpyAsync(d_stage, h_stage, o_out, hipMemcpyHostToDevice, stream) ==
-                   hipSuccess &&
-               launch_lpa((const LpaJob *)dev, (const int64_t *)(dev + o_start), nb, start[nb],
-                          stream) == 0 &&
-               hipMemcpyAsync(h_stage + o_flags, d_stage + o_flags, end - o_flags,
-                              hipMemcpyDeviceToHost, stream) == hipSuccess;
-        }
-        ok = hipStreamSynchronize(stream) == hipSuccess && ok;
-        if (!ok) rc = FRG_E_DEVICE;
+    } else if (n_pending.load(std::memory_order_acquire) > 0) {  // a stop is seen once idle
+      std::lock_guard<std::mutex> lk(m);
+      stopping = stop;
+      if (!stopping) {
+        next.flows.swap(pending);
+        n_pending.store(0, std::memory_order_relaxed);
       }
     }
-    if (ok) {
-      for (int i = 0; i < nb; ++i) {
-        Flow *f = batch[i];
-        const double *o = (const double *)(h_stage + o_o[i]);
-        std::memcpy(f->dUdt_dst, o, f->n * sizeof(double));
-        if (f->want_jac) std::memcpy(f->jac_dst, o + f->n, 7 * f->n * sizeof(double));
-      }
+    if (stopping) {
+      if (busy) finish_batch(inflight);
+      return;
     }
-    const int *flags = ok ? (const int *)(h_stage + o_flags) : nullptr;
-    std::lock_guard<std::mutex> lk(m);
-    ++launches;
-    batched += nb;
-    for (int i = 0; i < nb; ++i) {
-      Flow *f = batch[i];
-      f->rc = !ok ? rc : (flags[i] ? FRG_E_DOMAIN : FRG_OK);
-      f->ready = true;
-      f->ready_a.store(true, std::memory_order_release);
-      f->cv.notify_one();
+    if (!next.flows.empty()) {
+      next.slot = busy ? 1 - inflight.slot : 0;
+      launch_batch(next);
+    }
+    if (busy) {
+      finish_batch(inflight);
+      busy = false;
+    }
+    if (!next.flows.empty()) {
+      inflight = std::move(next);
+      busy = true;
     }
   }
 }
@@ -370,7 +430,7 @@ int frg_submit(frg_ctx *ctx, const frg_request *req, uint64_t *ticket) {
       auto *ns = new Server();
       ns->ctx = ctx;
       ns->budget = ctx->hbm_budget;
-      hipSetDevice(ctx->device);
+      (void)hipSetDevice(ctx->device);
       rc = ns->start();
       if (rc) {
         delete ns;
