@@ -1,9 +1,10 @@
 // Flow server behind frg_submit / frg_poll.
 //
 // Admission: a submitted flow waits in a FIFO queue until a slot is free
-// and its device footprint (its share of the staging buffer: U, dU/dt and
-// the 7 Jacobian bands of one call) fits the context's HBM budget, so the
-// staging buffer of any batch stays within the budget.
+// and its device footprint (its share of a staging buffer: U, dU/dt and the
+// 7 Jacobian bands of one call) fits the context's HBM budget, so the
+// batches in flight, which never share a flow, stay within the budget
+// together.
 //
 // Execution: every admitted flow runs the FP64 host stepper in its own
 // thread.  Its right-hand-side calls are handed to one dispatcher thread,
@@ -18,10 +19,12 @@
 // Round trip of a batch: descriptors, the U of every flow and zeroed domain
 // flags are packed into one pinned host buffer; the kernel reads them there
 // and writes the flags and every flow's outputs back into it (zero copy, one
-// launch and one synchronisation per batch; knob server_zero_copy), or the
-// packed head goes up in one copy and the flags and outputs come back in
-// one (a device mirror of the buffer).  The outputs are then written into
-// the waiting flows' own buffers.
+// launch and one event per batch; knob server_zero_copy), or the packed head
+// goes up in one copy and the flags and outputs come back in one (a device
+// mirror of the buffer).  The outputs are then written into the waiting
+// flows' own buffers.  There are two such buffers: while one batch runs, the
+// dispatcher stages and enqueues the next into the other, then waits for the
+// running one and hands it back.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
