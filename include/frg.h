@@ -448,7 +448,8 @@ int frg_autotune(frg_ctx *ctx, int32_t mode, const char *cache_path);
  * default 12; above 8 only for the matrix-core form with groups of up to 16
  * azimuthal terms, else 8), "server_zero_copy" (flow server, 1: the LPA kernel reads
  * and writes the pinned batch buffer in place, the default; 0: one upload and
- * one download per batch; the same bits), "grid_lds_rows" (8..96), "plain_tile" (points per
+ * one download per batch; the same bits; two batch buffers, the next batch
+ * staged while one runs), "grid_lds_rows" (8..96), "plain_tile" (points per
  * tile of a plain launch, 1..64), "persist_tile" (work of a tile of the persistent list, in
  * units of 1024 evaluations: 1..64 points of one set), "persist_wpc" (1..64), and of the
  * tabulated variant "tab_W" (1..4),
