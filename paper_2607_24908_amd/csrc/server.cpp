@@ -125,6 +125,10 @@ struct Server {
 // that long before they sleep on their condition variables (a wake-up
 // through the kernel costs about as much as the call itself).
 constexpr double kSpinSeconds = 200e-6;
+// With more running flows than this, the steppers sleep on their condition
+// variables at once: a spinning thread per flow would take the cores that
+// the others' steppers need.
+constexpr int kSpinFlows = 8;
 
 template <class Cond>
 static bool spin_until(Cond cond) {
@@ -216,9 +220,11 @@ int Server::rhs_cb(void *user, double t, const double *U, int64_t n, double *dUd
   Flow *f = static_cast<Flow *>(user);
   Server *s = f->srv;
   if (n != f->n) return FRG_E_INVAL;
+  bool spin;
   {
     std::lock_guard<std::mutex> lk(s->m);
     if (s->stop) return FRG_E_DEVICE;
+    spin = s->active <= kSpinFlows;
     f->t = t;
     f->U_src = U;
     f->dUdt_dst = dUdt;
@@ -230,7 +236,7 @@ int Server::rhs_cb(void *user, double t, const double *U, int64_t n, double *dUd
     s->n_pending.fetch_add(1, std::memory_order_release);
   }
   s->cv_disp.notify_one();
-  if (!spin_until([&] { return f->ready_a.load(std::memory_order_acquire); })) {
+  if (!spin || !spin_until([&] { return f->ready_a.load(std::memory_order_acquire); })) {
     std::unique_lock<std::mutex> lk(s->m);
     f->cv.wait(lk, [&] { return f->ready || s->stop; });
     if (!f->ready) return FRG_E_DEVICE;
