@@ -87,6 +87,12 @@ struct Batch {
   int rc = FRG_OK;
 };
 
+// With more running flows than spin_flows (environment FRG_SERVER_SPIN_FLOWS,
+// default kSpinFlows), the steppers sleep on their condition variables at
+// once: a spinning thread per flow would take the cores that the others'
+// steppers need.
+constexpr int kSpinFlows = 12;
+
 struct Server {
   Context *ctx = nullptr;
   hipStream_t stream = nullptr;
@@ -102,6 +108,7 @@ struct Server {
   uint64_t next_ticket = 1;
   int active = 0;
   int max_active = 64;
+  int spin_flows = kSpinFlows;
   size_t max_queue = 65536;
   uint64_t budget = 0;
   uint64_t used = 0;
@@ -125,10 +132,6 @@ struct Server {
 // that long before they sleep on their condition variables (a wake-up
 // through the kernel costs about as much as the call itself).
 constexpr double kSpinSeconds = 200e-6;
-// With more running flows than this, the steppers sleep on their condition
-// variables at once: a spinning thread per flow would take the cores that
-// the others' steppers need.
-constexpr int kSpinFlows = 8;
 
 template <class Cond>
 static bool spin_until(Cond cond) {
@@ -148,6 +151,7 @@ int Server::start() {
     if (hipEventCreateWithFlags(&g.done, hipEventDisableTiming) != hipSuccess)
       return fail(FRG_E_DEVICE, "server event");
   if (const char *e = std::getenv("FRG_SERVER_SLOTS")) max_active = std::max(1, std::atoi(e));
+  if (const char *e = std::getenv("FRG_SERVER_SPIN_FLOWS")) spin_flows = std::max(0, std::atoi(e));
   disp = std::thread([this] { dispatch_loop(); });
   return FRG_OK;
 }
@@ -224,7 +228,7 @@ int Server::rhs_cb(void *user, double t, const double *U, int64_t n, double *dUd
   {
     std::lock_guard<std::mutex> lk(s->m);
     if (s->stop) return FRG_E_DEVICE;
-    spin = s->active <= kSpinFlows;
+    spin = s->active <= s->spin_flows;
     f->t = t;
     f->U_src = U;
     f->dUdt_dst = dUdt;
