@@ -403,7 +403,10 @@ int frg_flow_solve(const frg_request *req, frg_rhs_fn rhs, void *user, frg_resul
  * a flow when a slot is free and its device footprint fits the HBM budget,
  * and batches the right-hand-side evaluations of all running flows into
  * shared launches (continuous batching), each reading and writing one packed
- * pinned buffer.  FRG_E_AGAIN if the queue is full. */
+ * pinned buffer.  FRG_E_AGAIN if the queue is full.  Environment, read when
+ * the server starts: FRG_SERVER_SLOTS (flows run at once, default 64) and
+ * FRG_SERVER_SPIN_FLOWS (while at most this many run, a flow's stepper polls
+ * briefly for each answer before it sleeps; default 12). */
 int frg_submit(frg_ctx *ctx, const frg_request *req, uint64_t *ticket);
 
 /* FRG_PENDING until the flow finishes; then the result (status inside) and
