@@ -135,6 +135,11 @@ int solve_flow(const frg_request &rq, frg_rhs_fn rhs, void *user, frg_result *re
   double th[3] = {0.0, 0.0, 0.0};
   int nhist = 1;
   double hprev = 0.0, hprev2 = 0.0;
+  // contraction rate of the Newton iteration, carried from step to step: an
+  // iterate whose correction times this rate is below the convergence bar
+  // is accepted (the next correction would be that small), which usually
+  // saves the second right-hand side of a step
+  double crate = 1.0;
 
   auto call = [&](double t, const std::vector<double> &u, bool want_jac) -> int {
     res->rhs_calls++;
@@ -185,11 +190,14 @@ int solve_flow(const frg_request &rq, frg_rhs_fn rhs, void *user, frg_result *re
         ynew[i] = (nhist >= 2) ? y0[i] + (h / hprev) * (y0[i] - yh[1][i]) : y0[i] + h * f0[i];
       }
     }
-    // --- Newton
-    bool conv = false, domain = false;
+    // --- Newton: the Jacobian bands and their factorisation at the first
+    // iterate, reused by the later ones (a fresh pair only when the
+    // iterates stop contracting)
+    bool conv = false, domain = false, have_lu = false;
     double prev_norm = 0.0;
     for (int it = 0; it < 8; ++it) {
-      rc = call(t + h, ynew, true);
+      const bool fresh = !have_lu;
+      rc = call(t + h, ynew, fresh);
       if (rc == FRG_E_DOMAIN) {
         domain = true;
         break;
@@ -199,8 +207,11 @@ int solve_flow(const frg_request &rq, frg_rhs_fn rhs, void *user, frg_result *re
         return rc;
       }
       for (int64_t i = 0; i < n; ++i) dy[i] = -(ynew[i] - g[i] - gamma * f[i]);
-      lu.assemble(n, gamma, jac.data());
-      if (!lu.factor()) break;
+      if (fresh) {
+        lu.assemble(n, gamma, jac.data());
+        if (!lu.factor()) break;
+        have_lu = true;
+      }
       lu.solve(dy.data());
       bool finite = true;
       for (int64_t i = 0; i < n; ++i) {
@@ -209,18 +220,28 @@ int solve_flow(const frg_request &rq, frg_rhs_fn rhs, void *user, frg_result *re
       }
       if (!finite) break;
       const double nrm = wrms(dy, y0, ynew, rtol, atol);
-      if (dbg) std::fprintf(stderr, "t=%.17g h=%.3e ord=%d it=%d nrm=%.3e\n", t, h, order, it, nrm);
-      if (nrm < 1e-3 || (it > 0 && nrm < 0.05 && nrm < 0.2 * prev_norm)) {
+      if (it > 0 && prev_norm > 0.0) crate = std::max(0.3 * crate, nrm / prev_norm);
+      if (dbg)
+        std::fprintf(stderr, "t=%.17g h=%.3e ord=%d it=%d nrm=%.3e crate=%.3e\n", t, h, order, it,
+                     nrm, crate);
+      if (nrm < 1e-3 || nrm * std::min(1.0, crate) < 1e-3 ||
+          (it > 0 && nrm < 0.05 && nrm < 0.2 * prev_norm)) {
         conv = true;
         break;
       }
-      if (it > 1 && nrm > 0.9 * prev_norm) break;
+      if (it > 0 && nrm > 0.5 * prev_norm) {
+        if (!fresh)
+          have_lu = false;  // reused bands contract slowly: fresh ones next
+        else if (it > 1 && nrm > 0.9 * prev_norm)
+          break;  // fresh bands and still no contraction
+      }
       prev_norm = nrm;
     }
     if (!conv) {
       if (dbg) std::fprintf(stderr, "reject newton t=%.17g h=%.3e domain=%d\n", t, h, (int)domain);
       res->rejected++;
       h *= domain ? 0.25 : 0.3;
+      crate = 1.0;  // the rate no longer describes the iteration
       // a flow whose steps collapse on pole crossings has reached the
       // singularity m^2 = -k^2 of the propagator: it ends there
       const double floor = domain ? hmin_pole : hmin;
@@ -260,6 +281,7 @@ int solve_flow(const frg_request &rq, frg_rhs_fn rhs, void *user, frg_result *re
     if (en > 1.0) {
       res->rejected++;
       h *= std::max(0.2, std::min(0.9, fac));
+      crate = 1.0;  // after a rejection every iterate is checked again
       if (std::fabs(h) < hmin) {
         res->status = FRG_E_STEP;
         return FRG_E_STEP;
