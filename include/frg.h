@@ -357,7 +357,10 @@ int frg_flow_rhs_batch(frg_ctx *ctx, int32_t n_flows, const frg_lpa *lpa, const 
 /* ---- flow integration on the host ------------------------------------------ */
 /* One LPA flow request: U(t=0) = (lambda/8)(rho - rho0)^2, integrated from
  * t = 0 to t_end < 0 by the implicit variable-step BDF(1,2) stepper in FP64
- * (Newton with the banded Jacobian, local error control with rtol/atol).
+ * (Newton with the banded Jacobian, formed and factorised at a step's first
+ * iterate and reused by its later ones; an iterate is accepted when its
+ * correction times the contraction rate seen on the previous steps is below
+ * the bar; local error control with rtol/atol).
  * U_out (host, n_grid float64) receives U(t_end); it must stay valid until
  * frg_poll reports completion. */
 typedef struct {
