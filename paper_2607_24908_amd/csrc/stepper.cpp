@@ -138,8 +138,11 @@ int solve_flow(const frg_request &rq, frg_rhs_fn rhs, void *user, frg_result *re
   // contraction rate of the Newton iteration, carried from step to step: an
   // iterate whose correction times this rate is below the convergence bar
   // is accepted (the next correction would be that small), which usually
-  // saves the second right-hand side of a step
+  // saves the second right-hand side of a step.  Every kRateCheck steps so
+  // accepted, a step iterates twice again so that the rate is measured anew.
   double crate = 1.0;
+  constexpr int kRateCheck = 16;
+  int unchecked = 0;
 
   auto call = [&](double t, const std::vector<double> &u, bool want_jac) -> int {
     res->rhs_calls++;
@@ -220,12 +223,16 @@ int solve_flow(const frg_request &rq, frg_rhs_fn rhs, void *user, frg_result *re
       }
       if (!finite) break;
       const double nrm = wrms(dy, y0, ynew, rtol, atol);
-      if (it > 0 && prev_norm > 0.0) crate = std::max(0.3 * crate, nrm / prev_norm);
+      if (it > 0 && prev_norm > 0.0) {
+        crate = std::max(0.3 * crate, nrm / prev_norm);
+        unchecked = 0;
+      }
       if (dbg)
         std::fprintf(stderr, "t=%.17g h=%.3e ord=%d it=%d nrm=%.3e crate=%.3e\n", t, h, order, it,
                      nrm, crate);
-      if (nrm < 1e-3 || nrm * std::min(1.0, crate) < 1e-3 ||
-          (it > 0 && nrm < 0.05 && nrm < 0.2 * prev_norm)) {
+      const bool by_rate = it == 0 && unchecked < kRateCheck && nrm * std::min(1.0, crate) < 1e-3;
+      if (nrm < 1e-3 || by_rate || (it > 0 && nrm < 0.05 && nrm < 0.2 * prev_norm)) {
+        if (by_rate && !(nrm < 1e-3)) ++unchecked;
         conv = true;
         break;
       }
