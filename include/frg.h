@@ -360,7 +360,8 @@ int frg_flow_rhs_batch(frg_ctx *ctx, int32_t n_flows, const frg_lpa *lpa, const 
  * (Newton with the banded Jacobian, formed and factorised at a step's first
  * iterate and reused by its later ones; an iterate is accepted when its
  * correction times the contraction rate seen on the previous steps is below
- * the bar; local error control with rtol/atol).
+ * the bar, the rate being measured again every 16 such steps; local error
+ * control with rtol/atol).
  * U_out (host, n_grid float64) receives U(t_end); it must stay valid until
  * frg_poll reports completion. */
 typedef struct {
