@@ -54,6 +54,13 @@ __device__ __forceinline__ int node_of(double t, double t_last, int k_last) {
   return k < k_last ? k : k_last;
 }
 
+// A term e = (i, j) is stored as (i << 8) | j when both node counts fit a
+// byte, else as i n_a + j; either way the terms of a segment keep the order
+// (i, j), so the sums do not depend on the encoding.
+__host__ __device__ __forceinline__ bool term_packed(const TabArgs &a) {
+  return a.n_r <= 256 && a.n_a <= 256;
+}
+
 // Lane l's value of v (l wave-uniform).
 __device__ __forceinline__ double readlane_d(double v, int l) {
   const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
@@ -200,7 +207,7 @@ __global__ __launch_bounds__(kSortW * kWave) void tab_seg_sort_kernel(TabArgs a,
         }
         base = __shfl(base, hl, kWave);
         const int j = jb + lane;
-        if (j < n_a) pt[base + (lane - hl)] = (uint16_t)(i * n_a + j);
+        if (j < n_a) pt[base + (lane - hl)] = (uint16_t)(term_packed(a) ? (i << 8) | j : i * n_a + j);
       }
     }
   }
@@ -226,6 +233,7 @@ __device__ __forceinline__ double super_nodes(const TabArgs &a, int c, int n_seg
 // segment a wave takes the non-empty runs of its momenta one after another,
 // all 64 lanes on one run (lane l: positions o + l, o + l + 64, ...), and the
 // four row sums of the run are folded over the wave and added by the owner.
+template <bool PACKED>
 __global__ __launch_bounds__(kNT) void tab_seg_kernel(TabArgs a, const unsigned *hist,
                                                       const uint16_t *__restrict__ terms,
                                                       const int *__restrict__ offs, int *counter,
@@ -376,10 +384,16 @@ __global__ __launch_bounds__(kNT) void tab_seg_kernel(TabArgs a, const unsigned 
         for (int r = 0; r < kRB; ++r) in[r] = 0.0;
         for (int pos = ra0 + lane; pos < ra1; pos += kWave) {
           const unsigned e = pt[pos];
-          // e = i n_a + j (exact: e < 2^16, and e + 1/2 is at least 1/(2 n_a)
-          // away from a multiple of n_a)
-          const int i = (int)(((float)e + 0.5f) * inv_na);
-          const int j = (int)e - i * n_a;
+          int i, j;
+          if constexpr (PACKED) {
+            i = (int)(e >> 8);
+            j = (int)(e & 255u);
+          } else {
+            // e = i n_a + j (exact: e < 2^16, and e + 1/2 is at least
+            // 1/(2 n_a) away from a multiple of n_a)
+            i = (int)(((float)e + 0.5f) * inv_na);
+            j = (int)e - i * n_a;
+          }
           const double *rad = lrad + i * kRS;
           const double q = rad[0];
           const double qm = q - p;
@@ -462,7 +476,9 @@ int launch_tab_seg(const TabArgs &t, const TabSegShape &s, const TabSegBufs &b, 
   if (t.n_p <= 0 || t.n_rows <= 0) return 0;
   hipStream_t st = (hipStream_t)stream;
   static const bool once =
-      ((void)hipFuncSetAttribute((const void *)&tab_seg_kernel,
+      ((void)hipFuncSetAttribute((const void *)&tab_seg_kernel<true>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024),
+       (void)hipFuncSetAttribute((const void *)&tab_seg_kernel<false>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024),
        (void)hipFuncSetAttribute((const void *)&tab_seg_sort_kernel,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024),
@@ -471,9 +487,15 @@ int launch_tab_seg(const TabArgs &t, const TabSegShape &s, const TabSegBufs &b, 
   hipLaunchKernelGGL(tab_seg_zero_kernel, dim3(1), dim3(256), 0, st, b.hist, s.n_super, b.counter);
   hipLaunchKernelGGL(tab_seg_sort_kernel, dim3((unsigned)t.n_p), dim3(kSortW * kWave),
                      sizeof(int) * kSortW * s.n_seg, st, t, b.terms, b.offs, b.hist, s.n_seg);
-  hipLaunchKernelGGL(tab_seg_kernel, dim3((unsigned)n_cu), dim3(kNT), (size_t)s.lds, st, t,
-                     (const unsigned *)b.hist, (const uint16_t *)b.terms, (const int *)b.offs,
-                     b.counter, b.part, s.n_seg, s.n_super, s.n_batch, s.target);
+  if (term_packed(t))
+    hipLaunchKernelGGL(tab_seg_kernel<true>, dim3((unsigned)n_cu), dim3(kNT), (size_t)s.lds, st, t,
+                       (const unsigned *)b.hist, (const uint16_t *)b.terms, (const int *)b.offs,
+                       b.counter, b.part, s.n_seg, s.n_super, s.n_batch, s.target);
+  else
+    hipLaunchKernelGGL(tab_seg_kernel<false>, dim3((unsigned)n_cu), dim3(kNT), (size_t)s.lds, st,
+                       t, (const unsigned *)b.hist, (const uint16_t *)b.terms,
+                       (const int *)b.offs, b.counter, b.part, s.n_seg, s.n_super, s.n_batch,
+                       s.target);
   const int64_t n = t.n_p * t.n_rows;
   hipLaunchKernelGGL(tab_seg_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, t,
                      (const double *)b.part, s.n_super);

@@ -90,14 +90,16 @@ def test_tab_matches_oracle_and_forms_agree(ctx, d, reg, n_r, n_a):
 
 
 @pytest.mark.parametrize("d,reg,n_r,n_a", [(3, 0, 1, 130), (4, 1, 3, 65), (3, 0, 5, 256),
-                                           (5, 0, 70, 200), (3, 1, 9, 64), (4, 0, 300, 256)])
+                                           (5, 0, 70, 200), (3, 1, 9, 64), (4, 1, 260, 64),
+                                           (4, 0, 300, 256)])
 def test_tab_segmented_sort_shapes(ctx, d, reg, n_r, n_a):
     """The segmented form's term sort over rules whose angular nodes span one
     to four blocks of 64 lanes and whose radial nodes are fewer than, equal
     to or more than its four waves, on rows of 11 segments (the last one
     ragged): against the oracle, and within 1e-13 of the cache-streamed form.
-    300 x 256 terms exceed its 16-bit term index: the call takes the
-    cache-streamed form (the same bits)."""
+    Terms are stored as byte pairs (i, j) up to 256 nodes each way, else as
+    i n_a + j (260 radial nodes).  300 x 256 terms exceed its 16-bit term
+    index: the call takes the cache-streamed form (the same bits)."""
     print(f"[case] segmented sort d={d} reg={reg} {n_r}x{n_a}", flush=True)
     q = workloads.Quad(d, reg, 0.9, 5.4, n_r, n_a)
     rng = np.random.Generator(np.random.PCG64(7 * n_r + n_a))
