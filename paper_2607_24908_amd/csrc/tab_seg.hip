@@ -417,11 +417,12 @@ __global__ __launch_bounds__(kNT) void tab_seg_kernel(TabArgs a, const unsigned 
         // lane groups of 16 end with the sums of rows 0..3
         const double rs = wave_sum_fold<kRB>(in, lane);
         if ((lane & 15) == (l & 15)) {
-          const int k = l >> 4;  // wave-uniform
-          acc[0] = k == 0 ? acc[0] + rs : acc[0];
-          acc[1] = k == 1 ? acc[1] + rs : acc[1];
-          acc[2] = k == 2 ? acc[2] + rs : acc[2];
-          acc[3] = k == 3 ? acc[3] + rs : acc[3];
+          switch (l >> 4) {  // wave-uniform: one add, not four selected ones
+            case 0: acc[0] += rs; break;
+            case 1: acc[1] += rs; break;
+            case 2: acc[2] += rs; break;
+            default: acc[3] += rs; break;
+          }
         }
       }
       o_cur = o_nxt;
