@@ -230,8 +230,8 @@ def oracle_checks(oracle, checks, workloads, cores):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(integral sets and flows shard across GPUs with no exchange; see DESIGN.md)",
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(integral sets and flows would shard across GPUs with no exchange)",
               file=sys.stderr)
         sys.exit(2)
     if args.only in ("pflow", "vertex", "fvlpa"):
