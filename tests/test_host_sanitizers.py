@@ -1,13 +1,13 @@
 """Host code under AddressSanitizer and UndefinedBehaviorSanitizer (CPU only).
 
-Two small drivers in tests/sanitize/ are built with gcc/g++ and
+Two small programs in tests/sanitize/ are built with gcc/g++ and
 -fsanitize=address,undefined (no recovery: the first report aborts):
   * host_check.cpp with the library's pure host translation units
     (csrc/tables.cpp: Gauss-Legendre and the packed tables; csrc/stepper.cpp:
     the BDF(1,2) flow stepper behind frg_flow_solve);
   * oracle_check.c with the oracle (oracle/frg_oracle.c), every entry point on
     small and edge-case inputs.
-A run passes when the driver exits 0 and prints its "... checks ok" line.  The
+A run passes when the program exits 0 and prints its "... checks ok" line.  The
 flow server's threads need a HIP device and are covered by the GPU tests'
 bitwise alone-versus-batched checks instead of ThreadSanitizer.
 """
